@@ -1,0 +1,96 @@
+/* Plain, slow, single-threaded CPU oracle of the tracking correspondence search.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this code; only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  It shares no code, header, table or constant with the
+ * device path.
+ *
+ * What it computes (the paper's problem statements, Section II-B to II-D and
+ * Section IV-C/IV-E of FastTrack, arXiv 2509.10757):
+ *   - stereo matching: for each left keypoint, the most similar right keypoint
+ *     (pinhole: restricted to the epipolar row band, then refined among nearby
+ *     pixels; fisheye: brute force over the overlap region);
+ *   - search by projection: for each local map point, its correspondence among
+ *     the frame's keypoints, each map point independent of the others.
+ * Every search is an exhaustive scan over the candidate set that the
+ * predicates define (no row index, no grid: those are accelerators of the
+ * device path).  Ties go to the smaller candidate index; two queries that
+ * claim one target are resolved in favour of the smaller (distance, query
+ * index) key and the loser becomes unmatched.
+ *
+ * Arithmetic: binary32 for pinhole and projection steps, binary64 for the
+ * Kannala-Brandt model and triangulation; every expression is evaluated left
+ * to right as written, built with -ffp-contract=off (no fused multiply-add).
+ *
+ * Parity pinning: see the header comment of each function; functions whose
+ * result has no independent pin say "parity unpinned".
+ */
+#ifndef FT_ORACLE_H
+#define FT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+int oracle_hamming(const uint8_t *a, const uint8_t *b);
+
+/* Rectified pinhole stereo.  i-params: th_orb, half_win, half_range,
+ * level_window, median_num, median_den.  stats (int64[8]): hamming evals,
+ * refine attempts, refined ok, after conflict, median, final matches. */
+void oracle_stereo_pinhole(
+    int nL, const float *xL, const float *yL, const uint8_t *oL, const uint8_t *dL,
+    int nR, const float *xR, const float *yR, const uint8_t *oR, const uint8_t *dR,
+    const uint8_t *pyrL, const uint8_t *pyrR, const int64_t *lv_off,
+    const int32_t *lv_w, const int32_t *lv_h, const float *sf, const float *inv_sf,
+    float bf, float b, int rows, const int32_t *ip, float band,
+    int32_t *out_j, int32_t *out_h, float *out_ur, float *out_depth, int32_t *out_sad,
+    int64_t *stats);
+
+/* Fisheye (Kannala-Brandt) stereo.  kb = {fx, fy, cx, cy, k1, k2, k3, k4}.
+ * ip = {ratio_num, ratio_den, newton_iters}; dp = {cos_parallax_max, chi2,
+ * max_theta_rad, newton_tol}.  out_h2 (nullable): second-nearest distance of
+ * every overlap query (-1 elsewhere).  stats: |Q|, |T|, ratio ok, tri ok, final. */
+void oracle_stereo_fisheye(
+    int nL, const float *xL, const float *yL, const uint8_t *oL, const uint8_t *dL,
+    int nR, const float *xR, const float *yR, const uint8_t *oR, const uint8_t *dR,
+    const float *kbL, const float *kbR, const float *R_lr, const float *t_lr,
+    const float *ovl, const float *ovr, const float *sigma2,
+    const int32_t *ip, const double *dp,
+    int32_t *out_j, int32_t *out_h, float *out_depth, float *out_xyz, int32_t *out_h2,
+    int64_t *stats);
+
+/* Local-map search by projection for one camera.
+ * cam = {fx, fy, cx, cy, k1, k2, k3, k4, bf}; model 0 = pinhole, 1 = KB.
+ * fp = {th, view_cos_limit, view_cos_narrow, r_narrow, r_wide, dist_lo, dist_hi}
+ * ip = {level_lo, level_hi, th_high, ratio_num, ratio_den, same_level_only}
+ * stats: visible, candidates, accepted before conflict, matches. */
+void oracle_search_local_points(
+    int nM, const float *pos, const float *normal, const float *dmin, const float *dmax,
+    const uint8_t *mdesc,
+    int nK, const float *kx, const float *ky, const uint8_t *ko, const uint8_t *kdesc,
+    const float *u_right, const uint8_t *preassigned,
+    int model, const float *cam, const float *R, const float *t, const float *O,
+    const float *bounds, const float *sf, int n_levels,
+    const float *fp, const int32_t *ip,
+    int32_t *mp_match, int32_t *mp_dist, int32_t *kp_match, int64_t *stats);
+
+/* Stage helpers of the pinhole refinement and of the level prediction,
+ * exported so tests can pin each stage on its own. */
+int oracle_sad_window(const uint8_t *IL, const uint8_t *IR, int Wl, int Hl,
+                      int su, int sv, int su0, int w, int L, int *sad);
+int oracle_subpixel(const int *sad, int L, int *kbest, int *sad_best, float *delta);
+int oracle_median_keep(int n, const int32_t *sad, int num, int den, uint8_t *keep);
+int oracle_predict_level(float ratio, const float *sf, int n_levels);
+
+/* Kannala-Brandt helpers, exposed so tests can pin them (round trips). */
+int oracle_kb_unproject(const float *kb, float u, float v, int iters, double tol,
+                        double max_theta, double *ray);
+void oracle_kb_project(const float *kb, const double *X, double *uv);
+int oracle_triangulate(const double *r1, const double *r2, const float *R_lr,
+                       const float *t_lr, double *X);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,70 @@
+"""The five seeded workloads (plus tiny variants for brute-force checks).
+
+Config k uses master seed 10757000 + k; sub-seeds come from SeedSequence.spawn.
+  1  one pinhole stereo frame, 752x480, 1200 kp/image, 3000 map points, 64x48 grid
+  2  one fisheye stereo frame, 512x512, 1500 kp/image, 5000 map points
+  3  local-map search only: 20000 clustered map points, 3000 kp, 96x64 grid
+  4  64 frames, 32 pinhole + 32 fisheye in seeded order, kp ~ U{300..3000},
+     map ~ U{1000..20000}
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .clustered import clustered_frame
+from .common import MASTER_SEED
+from .fisheye import fisheye_frame
+from .pinhole import pinhole_camera, pinhole_frame
+
+
+def seed_of(k: int) -> np.random.SeedSequence:
+    return np.random.SeedSequence(MASTER_SEED + k)
+
+
+def config1(seed=None):
+    return [pinhole_frame(seed if seed is not None else seed_of(1))]
+
+
+def config2(seed=None):
+    return [fisheye_frame(seed if seed is not None else seed_of(2))]
+
+
+def config3(seed=None):
+    return [clustered_frame(seed if seed is not None else seed_of(3))]
+
+
+def config4(seed=None, n_frames: int = 64):
+    ss = seed if seed is not None else seed_of(4)
+    ctl_ss, *frame_ss = ss.spawn(n_frames + 1)
+    rng = np.random.default_rng(ctl_ss)
+    kinds = np.array(["pinhole"] * (n_frames // 2) + ["fisheye"] * (n_frames - n_frames // 2))
+    rng.shuffle(kinds)
+    n_kp = rng.integers(300, 3001, n_frames)
+    n_map = rng.integers(1000, 20001, n_frames)
+    frames = []
+    for i in range(n_frames):
+        if kinds[i] == "pinhole":
+            frames.append(pinhole_frame(frame_ss[i], n_kp=int(n_kp[i]), n_map=int(n_map[i])))
+        else:
+            frames.append(fisheye_frame(frame_ss[i], n_kp=int(n_kp[i]), n_map=int(n_map[i])))
+    return frames
+
+
+def tiny_pinhole(seed, n_kp: int = 80, n_map: int = 120, grid=(12, 8)):
+    cam = pinhole_camera(W=240, H=160, fx=140.0, cx=120.0, cy=80.0, b=0.11)
+    return pinhole_frame(seed, n_kp=n_kp, n_map=n_map, grid=grid, cam=cam)
+
+
+def tiny_fisheye(seed, n_kp: int = 80, n_map: int = 120, grid=(12, 8)):
+    return fisheye_frame(seed, n_kp=n_kp, n_map=n_map, grid=grid)
+
+
+def tiny_clustered(seed, n_map: int = 400, n_kp: int = 120, grid=(16, 12)):
+    return clustered_frame(seed, n_map=n_map, n_kp=n_kp, n_blobs=4, grid=grid)
+
+
+CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+
+
+def config(k: int):
+    return CONFIGS[k]()

@@ -1,0 +1,112 @@
+"""Planted mistakes: each mutation below edits a copy of the oracle's C source
+(on the CPU only), rebuilds it, and requires that at least one pin of
+test_oracle_pins.py fails against the mutant.  This checks that the pins are
+strong enough to catch a dropped term, a wrong sign, index or operand."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+import oracle
+import synth
+from tests import test_oracle_pins as pins
+
+HERE = os.path.dirname(os.path.abspath(oracle.__file__))
+
+MUTANTS = {
+    "hamming_and": ("a[q] ^ b[q]", "a[q] & b[q]"),
+    "sad_no_centre": ("(int)IL[(size_t)(sv + dy) * Wl + su + dx] - cL", "(int)IL[(size_t)(sv + dy) * Wl + su + dx]"),
+    "sad_shift_sign": ("su0 + k + dx]", "su0 - k + dx]"),
+    "subpixel_sign": ("(float)(a - e)", "(float)(e - a)"),
+    "subpixel_den": ("2 * (a + e - 2 * c)", "(a + e - 2 * c)"),
+    "median_index": ("v[n / 2]", "v[(n - 1) / 2]"),
+    "median_ratio": ("(int64_t)den * sad[i] < (int64_t)num * m", "(int64_t)num * sad[i] < (int64_t)den * m"),
+    "pinhole_level_window": ("oj < oi - lw ||", "oj < oi - lw - 1 ||"),
+    "pinhole_disp_sign": ("float disp = xL[i] - uR;", "float disp = uR - xL[i];"),
+    "pinhole_band": ("floorf(yR[j] - r)", "floorf(yR[j] + r)"),
+    "pinhole_th_orb": ("!(best_h < th_orb)", "!(best_h <= th_orb)"),
+    "pinhole_depth": ("cd[i] = bf / disp;", "cd[i] = disp / bf;"),
+    "kb_distort_term": ("return th * ((((1.0 + k1 * t2) + k2 * t4)", "return th * ((((1.0 + k1 * t2) + k2 * t2)"),
+    "kb_unproject_tan": ("tan(th) / thd", "sin(th) / thd"),
+    "kb_newton_deriv": ("(1.0 + 3.0 * k1 * t2)", "(1.0 + 2.0 * k1 * t2)"),
+    "tri_transpose": ("Rrl[r][c] = (double)R_lr[3 * c + r];", "Rrl[r][c] = (double)R_lr[3 * r + c];"),
+    "tri_t_sign": ("trl[r] = -(((Rrl", "trl[r] = (((Rrl"),
+    "fish_ratio": ("ratio_den * h1 < ratio_num * h2", "ratio_num * h1 < ratio_den * h2"),
+    "fish_second": ("if (h < h1) { h2 = h1; h1 = h; j1 = j; }", "if (h < h1) { h1 = h; j1 = j; }"),
+    "search_R_transpose": ("((R[0] * X + R[1] * Y) + R[2] * Z)", "((R[0] * X + R[3] * Y) + R[6] * Z)"),
+    "search_radius_swap": ("(vcos > cos_narrow ? r_narrow : r_wide)", "(vcos > cos_narrow ? r_wide : r_narrow)"),
+    "search_uR_sign": ("uR = u - bf * (1.0f / zc)", "uR = u + bf * (1.0f / zc)"),
+    "search_preassigned_ignored": ("if (preassigned && preassigned[k]) continue;", ""),
+    "search_level_hi": ("ok > pred + lv_hi", "ok > pred + lv_hi + 1"),
+    "search_second_level": ("else if (h < b2) { b2 = h; l2 = ok; }", "else if (h < b2) { b2 = h; }"),
+    "search_window_y": ("fabsf(ky[k] - v) < Rm", "fabsf(ky[k] - u) < Rm"),
+    "search_dist_hi": ("dist <= hi", "dist <= lo"),
+    "predict_level_off_by_one": ("if (sf[l] >= ratio) return l;", "if (sf[l] >= ratio) return l + 1 < n_levels ? l + 1 : l;"),
+    "conflict_tie": ("int64_t key = ((int64_t)dist[i] << 32) | (int64_t)i;\n        if (key < best",
+                     "int64_t key = ((int64_t)dist[i] << 32) | (int64_t)(nQ - i);\n        if (key < best"),
+}
+
+
+@pytest.fixture(scope="module")
+def frames():
+    return {1: synth.config1()[0], 2: synth.config2()[0], 3: synth.config3()[0]}
+
+
+def _pins(frames):
+    tests = [pins.test_hamming_three_routes_agree, pins.test_hamming_special_cases,
+             pins.test_sad_window_matches_sliced_bruteforce,
+             pins.test_sad_exact_integer_shift_is_zero_at_true_shift,
+             pins.test_sad_constant_offset_is_invisible,
+             pins.test_subpixel_recovers_vertex_of_exact_parabola,
+             pins.test_subpixel_border_and_tie_rules,
+             pins.test_predicted_level_matches_log_reading,
+             pins.test_kb_projection_matches_generator_and_equidistant_closed_form,
+             pins.test_kb_round_trips,
+             pins.test_triangulation_exact_on_noise_free_rays_and_equals_lstsq,
+             pins.test_fisheye_zero_baseline_rejects_everything]
+    for vals, m, keep in [([0, 0, 3], 0, [False] * 3), ([1, 2, 3, 4, 100], 3, [True] * 4 + [False]),
+                          ([4, 3, 2, 1], 3, [True] * 4), ([10, 21, 22, 10, 10], 10, [True, False, False, True, True])]:
+        tests.append(lambda v=vals, mm=m, k=keep: pins.test_median_keep_hand_lists(v, mm, k))
+    for s in (21, 22, 23):
+        tests.append(lambda s=s: pins.test_stereo_pinhole_equals_bruteforce(s))
+    for s in (31, 32):
+        tests.append(lambda s=s: pins.test_fisheye_knn_ratio_equals_bruteforce(s))
+    for s in (41, 42, 43):
+        tests.append(lambda s=s: pins.test_search_pinhole_equals_bruteforce(s))
+    tests.append(lambda: pins.test_search_clustered_equals_bruteforce(51))
+    tests.append(pins.test_conflict_hand_built_scene)
+    tests.append(pins.test_pinhole_distance_threshold_is_strict)
+    tests.append(pins.test_search_ratio_applies_only_to_same_level_second)
+
+    def with_frames():
+        c1 = (frames[1], oracle.run_frame(frames[1]))
+        c2 = (frames[2], oracle.run_frame(frames[2]))
+        c3 = (frames[3], oracle.run_frame(frames[3]))
+        pins.test_pinhole_stereo_invariants_and_ground_truth(c1)
+        pins.test_search_invariants_and_ground_truth(c1, c3)
+        pins.test_fisheye_stereo_invariants_and_ground_truth(c2)
+        pins.test_fisheye_search_invariants_and_ground_truth(c2)
+    tests.append(with_frames)
+    return tests
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, frames, tmp_path):
+    src = open(os.path.join(HERE, "ft_oracle.c")).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, f"mutation anchor not found: {name}"
+    mutated = src.replace(old, new, 1)
+    (tmp_path / "ft_oracle.c").write_text(mutated)
+    shutil.copy(os.path.join(HERE, "ft_oracle.h"), tmp_path / "ft_oracle.h")
+    so = str(tmp_path / "libmut.so")
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", so, str(tmp_path / "ft_oracle.c"), "-lm"])
+    caught = None
+    with oracle.using_library(so):
+        for t in _pins(frames):
+            try:
+                t()
+            except (AssertionError, TypeError, IndexError, ValueError) as e:
+                caught = e
+                break
+    assert caught is not None, f"no pin caught mutation {name}"
