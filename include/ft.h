@@ -1,0 +1,324 @@
+/* ft.h -- C ABI of the MI355X tracking correspondence search.
+ *
+ * The library implements the two GPU-resident steps of visual tracking that
+ * FastTrack (arXiv 2509.10757) moves off the CPU:
+ *   - stereo matching: each left keypoint gets its most similar right keypoint
+ *     (Section II-B; Section IV-C "Stereo Matching"), rectified pinhole pairs by
+ *     an epipolar row-band search refined among nearby pixels, fisheye pairs by
+ *     a brute-force search of the overlap region;
+ *   - search by projection: each local map point gets its correspondence among
+ *     the current frame's keypoints, each map point independently of the others
+ *     (Section II-D "Track Local Map"; Section IV-E "Search Local Points").
+ * Memory is allocated once when a context is created and reused for every
+ * frame (Section IV-B: allocate at start, release at shutdown), so no call
+ * after ft_context_create allocates device memory.
+ *
+ * Conventions for every entry point:
+ *   - Pointers inside ft_keypoints, ft_pyramid, ft_map_points and the *_out
+ *     structs are DEVICE pointers; the structs themselves, the scale tables,
+ *     cameras, grids and parameters are HOST values copied during the call.
+ *   - Descriptors are 256-bit ORB descriptors stored as uint8_t[n][32],
+ *     16-byte aligned; bit t of byte q is descriptor bit 8q+t.
+ *   - Coordinates are level-0 pixels; `octave` is the pyramid level (0..7).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is only
+ *     enqueued: outputs are valid once the stream (or the batch ticket) has
+ *     completed.  All calls on one context must be ordered on one stream (or
+ *     ordered by the caller), because they share the context's workspace.
+ *   - The caller owns every buffer.  The library neither frees nor keeps any
+ *     caller pointer past the completion of that call's device work; inputs
+ *     must stay alive and unchanged until then.
+ *   - Every output element is written (-1 marks "no match"), so outputs need
+ *     no pre-fill.
+ *   - Arguments are validated synchronously.  A call that returns an error has
+ *     enqueued nothing.  FT_ERR_DEVICE is sticky: once a HIP call fails the
+ *     context reports it from every later call.
+ *   - A context is not thread safe; use one context per submitting thread.
+ *   - Ties between equal distances go to the smaller candidate index; two
+ *     queries that claim one target are resolved in favour of the smaller
+ *     (distance, query index) pair and the other becomes unmatched.  Results
+ *     are therefore bit-identical run to run and independent of batching.
+ */
+#ifndef FT_H
+#define FT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ft_status;
+#define FT_OK 0
+#define FT_ERR_INVALID_ARGUMENT 1 /* null/misaligned pointer, bad size or parameter */
+#define FT_ERR_CAPACITY 2         /* input exceeds the context's ft_limits */
+#define FT_ERR_DEVICE 3           /* a HIP call failed (sticky) */
+#define FT_ERR_UNSUPPORTED 4      /* feature or device not supported */
+
+#define FT_LEVELS 8               /* pyramid levels (ORB scale pyramid) */
+#define FT_DESC_BYTES 32          /* 256-bit descriptor */
+
+typedef struct ft_context ft_context;
+
+/* Capacity of a context, fixed at creation; the workspace is sized from it. */
+typedef struct ft_limits {
+    int32_t max_kp_per_image;  /* keypoints per image, <= 65535 */
+    int32_t max_map_points;    /* map points per search, <= 8388607 */
+    int32_t max_rows;          /* level-0 image rows of a pinhole pair, <= 4096 */
+    int32_t max_grid_cells;    /* grid cols * rows, <= 8192 */
+    int32_t max_batch_frames;  /* frames per ft_batch_submit */
+    int32_t max_inflight;      /* batch tickets in flight at once */
+} ft_limits;
+
+/* One image's keypoints (structure of arrays, device memory). */
+typedef struct ft_keypoints {
+    int32_t n;
+    const float *x;            /* [n] level-0 column */
+    const float *y;            /* [n] level-0 row */
+    const uint8_t *octave;     /* [n] pyramid level */
+    const uint8_t *desc;       /* [n][32] descriptor bytes, 16-byte aligned */
+} ft_keypoints;
+
+/* Image pyramid kept on the device (Section IV-B: the pyramid built by the
+ * feature extractor stays in GPU memory for stereo matching). */
+typedef struct ft_pyramid {
+    const uint8_t *data;       /* device: every level, row-major, pitch = width */
+    int64_t offset[FT_LEVELS]; /* byte offset of each level in data */
+    int32_t width[FT_LEVELS];
+    int32_t height[FT_LEVELS];
+} ft_pyramid;
+
+/* Scale tables of the pyramid (host values). */
+typedef struct ft_scales {
+    int32_t n_levels;          /* must be FT_LEVELS */
+    float sf[FT_LEVELS];       /* scale of level l (sf[0] = 1, increasing) */
+    float inv_sf[FT_LEVELS];   /* 1 / sf[l] */
+    float sigma2[FT_LEVELS];   /* sf[l]^2 */
+} ft_scales;
+
+/* ------------------------------------------------------------------------ */
+/* Rectified pinhole stereo (Section II-B: matches lie on epipolar lines, so  */
+/* the search is restricted to a region along them; Section IV-C: a best-    */
+/* match kernel, then a refinement among nearby pixels in shared memory).    */
+/* ------------------------------------------------------------------------ */
+typedef struct ft_pinhole_stereo {
+    float fx;                  /* focal length in pixels */
+    float bf;                  /* baseline * fx; disparity range is [0, bf/b) */
+    float b;                   /* baseline in metres */
+    int32_t rows;              /* level-0 image height (rows of the row index) */
+} ft_pinhole_stereo;
+
+typedef struct ft_pinhole_params {
+    int32_t th_orb;            /* accept the best match when distance < th_orb (75) */
+    int32_t half_win;          /* patch half size w (5): (2w+1)^2 pixels */
+    int32_t half_range;        /* shifts -L..L searched by the refinement (5) */
+    int32_t level_window;      /* right level within +-level_window of the left (1) */
+    int32_t median_num;        /* reject when median_den*SAD >= median_num*median */
+    int32_t median_den;        /*   (21 / 10) */
+    float band;                /* right keypoint j covers rows y_j +- band*sf[o_j] (2) */
+} ft_pinhole_params;
+
+typedef struct ft_pinhole_out {
+    int32_t *right_idx;        /* [nL] matched right keypoint or -1 */
+    int32_t *dist;             /* [nL] Hamming distance or -1 */
+    float *u_right;            /* [nL] sub-pixel right column or -1 */
+    float *depth;              /* [nL] bf / disparity or -1 */
+    int32_t *sad;              /* [nL] SAD at the best shift or -1 */
+    int32_t *n_matches;        /* [1] number of matched left keypoints */
+} ft_pinhole_out;
+
+/* Matches every left keypoint of a rectified pinhole pair: candidates are the
+ * right keypoints whose row band covers the left row, at most level_window
+ * levels apart, with disparity in [0, bf/b]; the nearest by Hamming distance
+ * is refined by a centre-subtracted SAD over shifts -L..L at the left
+ * keypoint's pyramid level with a parabola through the best three shifts;
+ * duplicates are resolved; outliers above 2.1x the median SAD are dropped.
+ * Requirements: L->n, R->n <= max_kp_per_image; cam->rows <= max_rows;
+ * scales->n_levels == 8; pyramids hold the level images in bounds.  Errors:
+ * FT_ERR_INVALID_ARGUMENT, FT_ERR_CAPACITY, FT_ERR_DEVICE. */
+ft_status ft_stereo_match_pinhole(ft_context *ctx, void *stream,
+                                  const ft_keypoints *left, const ft_keypoints *right,
+                                  const ft_pyramid *pyr_left, const ft_pyramid *pyr_right,
+                                  const ft_scales *scales, const ft_pinhole_stereo *cam,
+                                  const ft_pinhole_params *params, const ft_pinhole_out *out);
+
+/* ------------------------------------------------------------------------ */
+/* Fisheye stereo (Section II-B: for fisheye cameras every right keypoint is  */
+/* searched for each left keypoint; Section IV-C: one kernel, no refinement). */
+/* ------------------------------------------------------------------------ */
+typedef struct ft_kb_intrinsics {
+    float fx, fy, cx, cy;      /* Kannala-Brandt: r = f * theta*(1+k1 t^2+k2 t^4+k3 t^6+k4 t^8) */
+    float k[4];
+} ft_kb_intrinsics;
+
+typedef struct ft_fisheye_stereo {
+    ft_kb_intrinsics left, right;
+    float R_lr[9];             /* row-major; X_left = R_lr * X_right + t_lr */
+    float t_lr[3];
+    float overlap_left[2];     /* [a, b]: left keypoints with a <= x <= b are queries */
+    float overlap_right[2];    /* [a, b]: right keypoints with a <= x <= b are targets */
+} ft_fisheye_stereo;
+
+typedef struct ft_fisheye_params {
+    int32_t ratio_num;         /* accept when ratio_den*d1 < ratio_num*d2 (7 / 10) */
+    int32_t ratio_den;
+    int32_t newton_iters;      /* unprojection Newton iterations (10) */
+    int32_t pad_;
+    double cos_parallax_max;   /* reject rays more parallel than this (0.9998) */
+    double chi2;               /* reprojection gate chi2 * sigma2[level] (5.991) */
+    double max_theta;          /* reject unprojected rays at or beyond (rad) */
+    double newton_tol;         /* Newton step tolerance (1e-12) */
+} ft_fisheye_params;
+
+typedef struct ft_fisheye_out {
+    int32_t *right_idx;        /* [nL] matched right keypoint or -1 */
+    int32_t *dist;             /* [nL] Hamming distance or -1 */
+    float *depth;              /* [nL] left-camera depth or -1 */
+    float *xyz;                /* [nL][3] left-camera point, 0 when unmatched */
+    int32_t *n_matches;        /* [1] */
+} ft_fisheye_out;
+
+/* Two nearest right keypoints (overlap region) of every overlap left keypoint
+ * by Hamming distance, computed exactly as an int8 +-1 dot product on the
+ * matrix cores; a ratio test; a parallax, triangulation (linear least
+ * squares, float64), positive-depth and reprojection check; duplicates
+ * resolved.  Errors as for ft_stereo_match_pinhole. */
+ft_status ft_stereo_match_fisheye(ft_context *ctx, void *stream,
+                                  const ft_keypoints *left, const ft_keypoints *right,
+                                  const ft_scales *scales, const ft_fisheye_stereo *cam,
+                                  const ft_fisheye_params *params, const ft_fisheye_out *out);
+
+/* ------------------------------------------------------------------------ */
+/* Search by projection (Section II-D; Section IV-E: one map point per        */
+/* thread-level task, the map split into fine-grained structures).           */
+/* ------------------------------------------------------------------------ */
+typedef struct ft_map_points {
+    int32_t n;
+    const float *pos;          /* [n][3] world position */
+    const float *normal;       /* [n][3] mean viewing direction (unit) */
+    const float *dmin;         /* [n] scale-invariance distance bounds */
+    const float *dmax;         /* [n] */
+    const uint8_t *desc;       /* [n][32] representative descriptor, 16-byte aligned */
+} ft_map_points;
+
+#define FT_CAMERA_PINHOLE 0
+#define FT_CAMERA_KB 1
+
+typedef struct ft_search_camera {
+    int32_t model;             /* FT_CAMERA_PINHOLE or FT_CAMERA_KB */
+    float fx, fy, cx, cy;
+    float k[4];                /* KB coefficients (ignored for pinhole) */
+    float bf;                  /* pinhole stereo: baseline*fx for the right coordinate */
+    float R[9];                /* row-major world-to-camera rotation */
+    float t[3];                /* world-to-camera translation */
+    float O[3];                /* camera centre in the world */
+    float min_x, max_x, min_y, max_y; /* image bounds of a valid projection */
+} ft_search_camera;
+
+typedef struct ft_grid {
+    int32_t cols, rows;        /* keypoint grid over the image bounds */
+} ft_grid;
+
+typedef struct ft_search_params {
+    float th;                  /* window multiplier (2) */
+    float view_cos_limit;      /* reject when viewing cosine < this (0.5) */
+    float view_cos_narrow;     /* cosine above which the narrow radius applies (0.998) */
+    float r_narrow, r_wide;    /* base radii (2.5, 4.0) */
+    float dist_lo, dist_hi;    /* distance gate [dist_lo*dmin, dist_hi*dmax] (0.8, 1.2) */
+    int32_t level_lo;          /* keypoint level in [pred-level_lo, pred+level_hi] (1, 1) */
+    int32_t level_hi;
+    int32_t th_high;           /* accept when distance <= th_high (100) */
+    int32_t ratio_num;         /* reject when ratio_den*d1 > ratio_num*d2 (4 / 5) */
+    int32_t ratio_den;
+    int32_t ratio_same_level_only; /* apply the ratio test only if both share a level */
+} ft_search_params;
+
+typedef struct ft_search_out {
+    int32_t *mp_match;         /* [n_map] matched keypoint or -1 */
+    int32_t *mp_dist;          /* [n_map] Hamming distance or -1 */
+    int32_t *kp_match;         /* [n_kp] matched map point or -1 */
+    int32_t *n_matches;        /* [1] */
+} ft_search_out;
+
+/* Projects every map point with the camera pose, keeps those in the image at
+ * a distance inside their scale-invariance range and seen within the viewing
+ * angle, predicts the pyramid level, and takes the best and second best
+ * keypoints (by Hamming distance) inside a level- and angle-dependent window;
+ * keypoints flagged in `preassigned` (device, nullable) are skipped, and when
+ * `u_right` (device, nullable) is given, keypoints with u_right > 0 must agree
+ * with the projected right coordinate.  Requirements: map->n <=
+ * max_map_points, kps->n <= max_kp_per_image, grid cols*rows <=
+ * max_grid_cells.  Errors as above. */
+ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_points *map,
+                                 const ft_search_camera *cam, const ft_keypoints *kps,
+                                 const float *u_right, const uint8_t *preassigned,
+                                 const ft_grid *grid, const ft_scales *scales,
+                                 const ft_search_params *params, const ft_search_out *out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched frames: many frames of uneven size in one submission.             */
+/* ------------------------------------------------------------------------ */
+#define FT_JOB_PINHOLE 1       /* pinhole stereo + left-view search */
+#define FT_JOB_FISHEYE 2       /* fisheye stereo + left- and right-view search */
+#define FT_JOB_SEARCH 3        /* search only (views as given) */
+
+typedef struct ft_frame_job {
+    int32_t kind;              /* FT_JOB_* */
+    int32_t n_views;           /* search views: 1 (left) or 2 (left, right) */
+    ft_keypoints left, right;
+    ft_scales scales;
+    /* pinhole stereo */
+    ft_pyramid pyr_left, pyr_right;
+    ft_pinhole_stereo pinhole;
+    ft_pinhole_params pinhole_params;
+    ft_pinhole_out pinhole_out;
+    int32_t use_u_right;       /* pinhole: gate the left view with the stereo u_right */
+    /* fisheye stereo */
+    ft_fisheye_stereo fisheye;
+    ft_fisheye_params fisheye_params;
+    ft_fisheye_out fisheye_out;
+    /* search by projection (view 0 uses `left`, view 1 uses `right`) */
+    ft_map_points map;
+    ft_search_camera cam[2];
+    ft_grid grid[2];
+    const uint8_t *preassigned[2];
+    ft_search_params search_params;
+    ft_search_out search_out[2];
+} ft_frame_job;
+
+/* Enqueues every job on `stream` as one batch and returns a ticket.  Results
+ * are bit-identical to running each job through the single-frame calls.
+ * Requires n <= max_batch_frames and a free in-flight slot (else
+ * FT_ERR_CAPACITY).  The job array is copied during the call. */
+ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *jobs,
+                          int32_t n, uint64_t *ticket);
+/* Non-blocking: *done = 1 when the ticket's work has completed. */
+ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done);
+/* Blocks until the ticket's work has completed. */
+ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket);
+
+/* ------------------------------------------------------------------------ */
+ft_status ft_context_create(const ft_limits *limits, int32_t device, ft_context **out);
+ft_status ft_context_destroy(ft_context *ctx);
+/* Device bytes held by the context's preallocated workspace. */
+ft_status ft_context_workspace_bytes(const ft_context *ctx, int64_t *bytes);
+const char *ft_status_string(ft_status status);
+const char *ft_last_error(const ft_context *ctx);
+/* Per-phase kernel timing (for measurement tools).  When enabled, every
+ * submission records HIP events on its own stream around each phase kernel:
+ * 0 setup (row index / overlap lists / grids), 1 stereo best match (pinhole
+ * row band or fisheye all-pairs), 2 stereo refine / triangulation, 3 stereo
+ * resolve + outputs, 4 search by projection, 5 search resolve + outputs.
+ * ft_context_read_timing waits for the recorded work, returns the summed
+ * milliseconds and launch counts per phase (arrays of FT_PHASES), and resets
+ * them.  Enabling timing adds event records between kernels. */
+#define FT_PHASES 6
+ft_status ft_context_enable_timing(ft_context *ctx, int32_t enable);
+ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t ft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FT_H */

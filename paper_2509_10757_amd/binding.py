@@ -1,0 +1,470 @@
+"""Python binding of libfasttrack (include/ft.h): argument marshalling only.
+
+ctypes mirrors of the C structs, a `Context` whose methods carry the C entry
+point names, and `DeviceFrame`, which places one synthetic frame's arrays in
+device memory (torch tensors) and hands out the structs that point at them.
+Every step of the hot path runs in the HIP library; if the library is not
+built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+from . import build as _build
+
+LEVELS = 8
+FT_OK, FT_ERR_INVALID_ARGUMENT, FT_ERR_CAPACITY, FT_ERR_DEVICE, FT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+FT_CAMERA_PINHOLE, FT_CAMERA_KB = 0, 1
+FT_JOB_PINHOLE, FT_JOB_FISHEYE, FT_JOB_SEARCH = 1, 2, 3
+
+P = ct.c_void_p
+F8 = ct.c_float * LEVELS
+
+
+class ft_limits(ct.Structure):
+    _fields_ = [("max_kp_per_image", ct.c_int32), ("max_map_points", ct.c_int32),
+                ("max_rows", ct.c_int32), ("max_grid_cells", ct.c_int32),
+                ("max_batch_frames", ct.c_int32), ("max_inflight", ct.c_int32)]
+
+
+class ft_keypoints(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("x", P), ("y", P), ("octave", P), ("desc", P)]
+
+
+class ft_pyramid(ct.Structure):
+    _fields_ = [("data", P), ("offset", ct.c_int64 * LEVELS), ("width", ct.c_int32 * LEVELS),
+                ("height", ct.c_int32 * LEVELS)]
+
+
+class ft_scales(ct.Structure):
+    _fields_ = [("n_levels", ct.c_int32), ("sf", F8), ("inv_sf", F8), ("sigma2", F8)]
+
+
+class ft_pinhole_stereo(ct.Structure):
+    _fields_ = [("fx", ct.c_float), ("bf", ct.c_float), ("b", ct.c_float), ("rows", ct.c_int32)]
+
+
+class ft_pinhole_params(ct.Structure):
+    _fields_ = [("th_orb", ct.c_int32), ("half_win", ct.c_int32), ("half_range", ct.c_int32),
+                ("level_window", ct.c_int32), ("median_num", ct.c_int32),
+                ("median_den", ct.c_int32), ("band", ct.c_float)]
+
+
+class ft_pinhole_out(ct.Structure):
+    _fields_ = [("right_idx", P), ("dist", P), ("u_right", P), ("depth", P), ("sad", P),
+                ("n_matches", P)]
+
+
+class ft_kb_intrinsics(ct.Structure):
+    _fields_ = [("fx", ct.c_float), ("fy", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float),
+                ("k", ct.c_float * 4)]
+
+
+class ft_fisheye_stereo(ct.Structure):
+    _fields_ = [("left", ft_kb_intrinsics), ("right", ft_kb_intrinsics), ("R_lr", ct.c_float * 9),
+                ("t_lr", ct.c_float * 3), ("overlap_left", ct.c_float * 2),
+                ("overlap_right", ct.c_float * 2)]
+
+
+class ft_fisheye_params(ct.Structure):
+    _fields_ = [("ratio_num", ct.c_int32), ("ratio_den", ct.c_int32), ("newton_iters", ct.c_int32),
+                ("pad_", ct.c_int32), ("cos_parallax_max", ct.c_double), ("chi2", ct.c_double),
+                ("max_theta", ct.c_double), ("newton_tol", ct.c_double)]
+
+
+class ft_fisheye_out(ct.Structure):
+    _fields_ = [("right_idx", P), ("dist", P), ("depth", P), ("xyz", P), ("n_matches", P)]
+
+
+class ft_map_points(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("pos", P), ("normal", P), ("dmin", P), ("dmax", P),
+                ("desc", P)]
+
+
+class ft_search_camera(ct.Structure):
+    _fields_ = [("model", ct.c_int32), ("fx", ct.c_float), ("fy", ct.c_float), ("cx", ct.c_float),
+                ("cy", ct.c_float), ("k", ct.c_float * 4), ("bf", ct.c_float),
+                ("R", ct.c_float * 9), ("t", ct.c_float * 3), ("O", ct.c_float * 3),
+                ("min_x", ct.c_float), ("max_x", ct.c_float), ("min_y", ct.c_float),
+                ("max_y", ct.c_float)]
+
+
+class ft_grid(ct.Structure):
+    _fields_ = [("cols", ct.c_int32), ("rows", ct.c_int32)]
+
+
+class ft_search_params(ct.Structure):
+    _fields_ = [("th", ct.c_float), ("view_cos_limit", ct.c_float), ("view_cos_narrow", ct.c_float),
+                ("r_narrow", ct.c_float), ("r_wide", ct.c_float), ("dist_lo", ct.c_float),
+                ("dist_hi", ct.c_float), ("level_lo", ct.c_int32), ("level_hi", ct.c_int32),
+                ("th_high", ct.c_int32), ("ratio_num", ct.c_int32), ("ratio_den", ct.c_int32),
+                ("ratio_same_level_only", ct.c_int32)]
+
+
+class ft_search_out(ct.Structure):
+    _fields_ = [("mp_match", P), ("mp_dist", P), ("kp_match", P), ("n_matches", P)]
+
+
+class ft_frame_job(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("n_views", ct.c_int32),
+                ("left", ft_keypoints), ("right", ft_keypoints), ("scales", ft_scales),
+                ("pyr_left", ft_pyramid), ("pyr_right", ft_pyramid),
+                ("pinhole", ft_pinhole_stereo), ("pinhole_params", ft_pinhole_params),
+                ("pinhole_out", ft_pinhole_out), ("use_u_right", ct.c_int32),
+                ("fisheye", ft_fisheye_stereo), ("fisheye_params", ft_fisheye_params),
+                ("fisheye_out", ft_fisheye_out), ("map", ft_map_points),
+                ("cam", ft_search_camera * 2), ("grid", ft_grid * 2), ("preassigned", P * 2),
+                ("search_params", ft_search_params), ("search_out", ft_search_out * 2)]
+
+
+EXPORTS = {
+    "ft_context_create": [ct.POINTER(ft_limits), ct.c_int32, ct.POINTER(P)],
+    "ft_context_destroy": [P],
+    "ft_context_workspace_bytes": [P, ct.POINTER(ct.c_int64)],
+    "ft_stereo_match_pinhole": [P, P, ct.POINTER(ft_keypoints), ct.POINTER(ft_keypoints),
+                                ct.POINTER(ft_pyramid), ct.POINTER(ft_pyramid), ct.POINTER(ft_scales),
+                                ct.POINTER(ft_pinhole_stereo), ct.POINTER(ft_pinhole_params),
+                                ct.POINTER(ft_pinhole_out)],
+    "ft_stereo_match_fisheye": [P, P, ct.POINTER(ft_keypoints), ct.POINTER(ft_keypoints),
+                                ct.POINTER(ft_scales), ct.POINTER(ft_fisheye_stereo),
+                                ct.POINTER(ft_fisheye_params), ct.POINTER(ft_fisheye_out)],
+    "ft_search_local_points": [P, P, ct.POINTER(ft_map_points), ct.POINTER(ft_search_camera),
+                               ct.POINTER(ft_keypoints), P, P, ct.POINTER(ft_grid),
+                               ct.POINTER(ft_scales), ct.POINTER(ft_search_params),
+                               ct.POINTER(ft_search_out)],
+    "ft_batch_submit": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.POINTER(ct.c_uint64)],
+    "ft_batch_poll": [P, ct.c_uint64, ct.POINTER(ct.c_int32)],
+    "ft_batch_wait": [P, ct.c_uint64],
+    "ft_context_enable_timing": [P, ct.c_int32],
+    "ft_context_read_timing": [P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)],
+    "ft_status_string": [ct.c_int32],
+    "ft_last_error": [P],
+    "ft_version": [],
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load():
+    """Load libfasttrack.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it first (python -m paper_2509_10757_amd.build)")
+        lib = ct.CDLL(path)
+        for name, argtypes in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = argtypes
+            fn.restype = ct.c_int32
+        lib.ft_status_string.restype = ct.c_char_p
+        lib.ft_last_error.restype = ct.c_char_p
+        _lib = lib
+    return _lib
+
+
+class FtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def default_limits(**kw) -> ft_limits:
+    v = dict(max_kp_per_image=4096, max_map_points=65536, max_rows=1024, max_grid_cells=8192,
+             max_batch_frames=64, max_inflight=2)
+    v.update(kw)
+    return ft_limits(**v)
+
+
+def _stream(stream) -> P:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return P(stream.cuda_stream)
+
+
+class Context:
+    """Owns an ft_context; methods carry the C entry point names."""
+
+    def __init__(self, limits: ft_limits | None = None, device: int = 0):
+        self.lib = load()
+        self.limits = limits or default_limits()
+        h = P()
+        st = self.lib.ft_context_create(ct.byref(self.limits), device, ct.byref(h))
+        if st != FT_OK:
+            raise FtError(st, f"ft_context_create failed: {self.lib.ft_status_string(st).decode()}")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ft_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != FT_OK:
+            raise FtError(st, f"{what}: {self.lib.ft_last_error(self.h).decode()}")
+
+    def workspace_bytes(self) -> int:
+        v = ct.c_int64()
+        self._check(self.lib.ft_context_workspace_bytes(self.h, ct.byref(v)), "workspace_bytes")
+        return v.value
+
+    PHASES = ("setup", "stereo_best", "stereo_refine", "stereo_resolve", "search", "search_resolve")
+
+    def ft_context_enable_timing(self, enable: bool = True):
+        self._check(self.lib.ft_context_enable_timing(self.h, int(enable)), "enable_timing")
+
+    def ft_context_read_timing(self) -> dict:
+        ms = (ct.c_double * 6)()
+        n = (ct.c_int64 * 6)()
+        self._check(self.lib.ft_context_read_timing(self.h, ms, n), "read_timing")
+        return {p: (ms[i], n[i]) for i, p in enumerate(self.PHASES)}
+
+    def ft_stereo_match_pinhole(self, left, right, pyr_left, pyr_right, scales, cam, params, out,
+                                stream=None, check=True):
+        st = self.lib.ft_stereo_match_pinhole(self.h, _stream(stream), ct.byref(left), ct.byref(right),
+                                              ct.byref(pyr_left), ct.byref(pyr_right), ct.byref(scales),
+                                              ct.byref(cam), ct.byref(params), ct.byref(out))
+        if check:
+            self._check(st, "ft_stereo_match_pinhole")
+        return st
+
+    def ft_stereo_match_fisheye(self, left, right, scales, cam, params, out, stream=None, check=True):
+        st = self.lib.ft_stereo_match_fisheye(self.h, _stream(stream), ct.byref(left), ct.byref(right),
+                                              ct.byref(scales), ct.byref(cam), ct.byref(params),
+                                              ct.byref(out))
+        if check:
+            self._check(st, "ft_stereo_match_fisheye")
+        return st
+
+    def ft_search_local_points(self, map_points, cam, kps, u_right, preassigned, grid, scales,
+                               params, out, stream=None, check=True):
+        st = self.lib.ft_search_local_points(self.h, _stream(stream), ct.byref(map_points),
+                                             ct.byref(cam), ct.byref(kps), P(u_right or None),
+                                             P(preassigned or None), ct.byref(grid), ct.byref(scales),
+                                             ct.byref(params), ct.byref(out))
+        if check:
+            self._check(st, "ft_search_local_points")
+        return st
+
+    def ft_batch_submit(self, jobs, stream=None) -> int:
+        arr = (ft_frame_job * len(jobs))(*jobs)
+        t = ct.c_uint64()
+        self._check(self.lib.ft_batch_submit(self.h, _stream(stream), arr, len(jobs), ct.byref(t)),
+                    "ft_batch_submit")
+        return t.value
+
+    def ft_batch_poll(self, ticket: int) -> bool:
+        d = ct.c_int32()
+        self._check(self.lib.ft_batch_poll(self.h, ct.c_uint64(ticket), ct.byref(d)), "ft_batch_poll")
+        return bool(d.value)
+
+    def ft_batch_wait(self, ticket: int):
+        self._check(self.lib.ft_batch_wait(self.h, ct.c_uint64(ticket)), "ft_batch_wait")
+
+
+# --------------------------------------------------------------------------
+# Device placement of one synthetic frame
+# --------------------------------------------------------------------------
+def _dev(a, dtype=None, device="cuda"):
+    t = torch.from_numpy(np.ascontiguousarray(a if dtype is None else a.astype(dtype)))
+    return t.to(device)
+
+
+def _ptr(t):
+    return t.data_ptr() if t is not None and t.numel() > 0 else None
+
+
+def _scales(sc) -> ft_scales:
+    s = ft_scales()
+    s.n_levels = LEVELS
+    s.sf[:] = [float(v) for v in sc["sf"]]
+    s.inv_sf[:] = [float(v) for v in sc["inv_sf"]]
+    s.sigma2[:] = [float(v) for v in sc["sigma2"]]
+    return s
+
+
+class DeviceKeypoints:
+    def __init__(self, kp, device):
+        self.n = len(kp["x"])
+        self.x = _dev(kp["x"], np.float32, device)
+        self.y = _dev(kp["y"], np.float32, device)
+        self.octave = _dev(kp["octave"], np.uint8, device)
+        self.desc = _dev(kp["desc"], np.uint8, device)
+
+    def struct(self) -> ft_keypoints:
+        return ft_keypoints(self.n, _ptr(self.x), _ptr(self.y), _ptr(self.octave), _ptr(self.desc))
+
+
+def _pyramid(pyr, device):
+    t = _dev(pyr["data"], np.uint8, device)
+    s = ft_pyramid()
+    s.data = _ptr(t)
+    s.offset[:] = [int(v) for v in pyr["offset"]]
+    s.width[:] = [int(v) for v in pyr["width"]]
+    s.height[:] = [int(v) for v in pyr["height"]]
+    return t, s
+
+
+def _kb(c) -> ft_kb_intrinsics:
+    k = ft_kb_intrinsics(float(c["fx"]), float(c["fy"]), float(c["cx"]), float(c["cy"]))
+    k.k[:] = [float(v) for v in c["k"]]
+    return k
+
+
+def search_camera_struct(cam) -> ft_search_camera:
+    s = ft_search_camera()
+    s.model = int(cam["model"])
+    s.fx, s.fy, s.cx, s.cy = (float(cam[k]) for k in ("fx", "fy", "cx", "cy"))
+    s.k[:] = [float(v) for v in cam["k"]]
+    s.bf = float(cam["bf"])
+    s.R[:] = [float(v) for v in np.asarray(cam["R"], np.float32).reshape(-1)]
+    s.t[:] = [float(v) for v in cam["t"]]
+    s.O[:] = [float(v) for v in cam["O"]]
+    s.min_x, s.max_x, s.min_y, s.max_y = (float(v) for v in cam["bounds"])
+    return s
+
+
+def search_params_struct(sp) -> ft_search_params:
+    return ft_search_params(sp["th"], sp["view_cos_limit"], sp["view_cos_narrow"], sp["r_narrow"],
+                            sp["r_wide"], sp["dist_lo"], sp["dist_hi"], sp["level_lo"], sp["level_hi"],
+                            sp["th_high"], sp["ratio_num"], sp["ratio_den"], sp["ratio_same_level_only"])
+
+
+class DeviceFrame:
+    """One synthetic frame resident in device memory, with output buffers."""
+
+    def __init__(self, frame: dict, device="cuda"):
+        self.frame = frame
+        self.kind = frame["kind"]
+        self.device = device
+        self.left = DeviceKeypoints(frame["left"], device)
+        self.right = DeviceKeypoints(frame["right"], device) if "right" in frame else None
+        self.scales = _scales(frame["scales"])
+        nL = self.left.n
+        i32 = dict(dtype=torch.int32, device=device)
+        f32 = dict(dtype=torch.float32, device=device)
+        if self.kind == "pinhole":
+            self.pyr_left_t, self.pyr_left = _pyramid(frame["pyr_left"], device)
+            self.pyr_right_t, self.pyr_right = _pyramid(frame["pyr_right"], device)
+            c, sp = frame["stereo_cam"], frame["stereo_params"]
+            self.stereo_cam = ft_pinhole_stereo(float(c["fx"]), float(c["bf"]), float(c["b"]), int(c["rows"]))
+            self.stereo_params = ft_pinhole_params(sp["th_orb"], sp["half_win"], sp["half_range"],
+                                                   sp["level_window"], sp["median_num"],
+                                                   sp["median_den"], sp["band"])
+            self.o = {"right_idx": torch.empty(nL, **i32), "dist": torch.empty(nL, **i32),
+                      "u_right": torch.empty(nL, **f32), "depth": torch.empty(nL, **f32),
+                      "sad": torch.empty(nL, **i32), "n_matches": torch.empty(1, **i32)}
+            o = self.o
+            self.stereo_out = ft_pinhole_out(_ptr(o["right_idx"]), _ptr(o["dist"]), _ptr(o["u_right"]),
+                                             _ptr(o["depth"]), _ptr(o["sad"]), _ptr(o["n_matches"]))
+        elif self.kind == "fisheye":
+            c, sp = frame["stereo_cam"], frame["stereo_params"]
+            fs = ft_fisheye_stereo()
+            fs.left, fs.right = _kb(c["left"]), _kb(c["right"])
+            fs.R_lr[:] = [float(v) for v in np.asarray(c["R_lr"], np.float32).reshape(-1)]
+            fs.t_lr[:] = [float(v) for v in c["t_lr"]]
+            fs.overlap_left[:] = [float(v) for v in c["overlap_left"]]
+            fs.overlap_right[:] = [float(v) for v in c["overlap_right"]]
+            self.stereo_cam = fs
+            self.stereo_params = ft_fisheye_params(sp["ratio_num"], sp["ratio_den"], sp["newton_iters"], 0,
+                                                   sp["cos_parallax_max"], sp["chi2"],
+                                                   float(np.deg2rad(sp["max_theta_deg"])), sp["newton_tol"])
+            self.o = {"right_idx": torch.empty(nL, **i32), "dist": torch.empty(nL, **i32),
+                      "depth": torch.empty(nL, **f32), "xyz": torch.empty((nL, 3), **f32),
+                      "n_matches": torch.empty(1, **i32)}
+            o = self.o
+            self.stereo_out = ft_fisheye_out(_ptr(o["right_idx"]), _ptr(o["dist"]), _ptr(o["depth"]),
+                                             _ptr(o["xyz"]), _ptr(o["n_matches"]))
+        mp = frame["map"]
+        self.nM = len(mp["dmin"])
+        self.map_t = {"pos": _dev(mp["pos"], np.float32, device), "normal": _dev(mp["normal"], np.float32, device),
+                      "dmin": _dev(mp["dmin"], np.float32, device), "dmax": _dev(mp["dmax"], np.float32, device),
+                      "desc": _dev(mp["desc"], np.uint8, device)}
+        m = self.map_t
+        self.map = ft_map_points(self.nM, _ptr(m["pos"]), _ptr(m["normal"]), _ptr(m["dmin"]),
+                                 _ptr(m["dmax"]), _ptr(m["desc"]))
+        self.search_params = search_params_struct(frame["search_params"])
+        self.views = []
+        for spec in frame["search"]:
+            kps = self.left if spec["image"] == "left" else self.right
+            pre = spec.get("preassigned")
+            pre_t = _dev(pre, np.uint8, device) if pre is not None else None
+            out = {"mp_match": torch.empty(self.nM, **i32), "mp_dist": torch.empty(self.nM, **i32),
+                   "kp_match": torch.empty(kps.n, **i32), "n_matches": torch.empty(1, **i32)}
+            self.views.append({
+                "kps": kps, "cam": search_camera_struct(spec["cam"]),
+                "grid": ft_grid(*spec["grid"]), "pre_t": pre_t, "out_t": out,
+                "out": ft_search_out(_ptr(out["mp_match"]), _ptr(out["mp_dist"]), _ptr(out["kp_match"]),
+                                     _ptr(out["n_matches"])),
+                "use_u_right": bool(spec.get("use_u_right")) and self.kind == "pinhole",
+            })
+
+    # -- the per-frame path: one C call per step, in order on one stream
+    def run(self, ctx: Context, stream=None, u_right=None):
+        if self.kind == "pinhole":
+            ctx.ft_stereo_match_pinhole(self.left.struct(), self.right.struct(), self.pyr_left,
+                                        self.pyr_right, self.scales, self.stereo_cam, self.stereo_params,
+                                        self.stereo_out, stream=stream)
+        elif self.kind == "fisheye":
+            ctx.ft_stereo_match_fisheye(self.left.struct(), self.right.struct(), self.scales,
+                                        self.stereo_cam, self.stereo_params, self.stereo_out, stream=stream)
+        for v in self.views:
+            ur = None
+            if v["use_u_right"]:
+                ur = _ptr(self.o["u_right"])
+            elif u_right is not None:
+                ur = _ptr(u_right)
+            ctx.ft_search_local_points(self.map, v["cam"], v["kps"].struct(), ur, _ptr(v["pre_t"]),
+                                       v["grid"], self.scales, self.search_params, v["out"], stream=stream)
+
+    def job(self) -> ft_frame_job:
+        j = ft_frame_job()
+        j.kind = {"pinhole": FT_JOB_PINHOLE, "fisheye": FT_JOB_FISHEYE}.get(self.kind, FT_JOB_SEARCH)
+        j.n_views = len(self.views)
+        j.left = self.left.struct()
+        if self.right is not None:
+            j.right = self.right.struct()
+        j.scales = self.scales
+        if self.kind == "pinhole":
+            j.pyr_left, j.pyr_right = self.pyr_left, self.pyr_right
+            j.pinhole, j.pinhole_params, j.pinhole_out = self.stereo_cam, self.stereo_params, self.stereo_out
+            j.use_u_right = int(self.views[0]["use_u_right"]) if self.views else 0
+        elif self.kind == "fisheye":
+            j.fisheye, j.fisheye_params, j.fisheye_out = self.stereo_cam, self.stereo_params, self.stereo_out
+        j.map = self.map
+        for i, v in enumerate(self.views):
+            j.cam[i] = v["cam"]
+            j.grid[i] = v["grid"]
+            j.preassigned[i] = _ptr(v["pre_t"])
+            j.search_out[i] = v["out"]
+        j.search_params = self.search_params
+        return j
+
+    def results(self) -> dict:
+        """Copy every output to host numpy arrays (synchronises)."""
+        res = {"kind": self.kind}
+        if self.kind in ("pinhole", "fisheye"):
+            st = {k: v.cpu().numpy() for k, v in self.o.items()}
+            st["n_matches"] = int(st["n_matches"][0])
+            res["stereo"] = st
+        res["search"] = []
+        for v in self.views:
+            s = {k: t.cpu().numpy() for k, t in v["out_t"].items()}
+            s["n_matches"] = int(s["n_matches"][0])
+            res["search"].append(s)
+        return res

@@ -1,0 +1,765 @@
+// Host side of the C ABI declared in include/ft.h: context and preallocated
+// workspace, synchronous argument validation, job descriptors, batch tickets.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ft_internal.h"
+
+using namespace ft;
+
+namespace {
+
+struct Slot {  // workspace of one frame
+    int32_t *row_off, *row_items, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    float *uR, *depth, *xyz;
+    uint32_t *claimR;
+    struct {
+        int32_t *cell_off, *cell_items, *mp_k, *mp_h;
+        uint32_t *claim;
+    } view[2];
+};
+
+struct Lane {  // one batch in flight
+    std::vector<Slot> slots;
+    DevJob *d_jobs = nullptr;
+    DevJob *h_jobs = nullptr;   // pinned staging of the job table
+    hipEvent_t done = nullptr;
+    uint64_t ticket = 0;
+    bool used = false;
+};
+
+}  // namespace
+
+struct ft_context {
+    int device = 0;
+    ft_limits lim{};
+    char *base = nullptr;
+    size_t bytes = 0;
+    Slot direct{};
+    std::vector<Lane> lanes;
+    ft_status sticky = FT_OK;
+    std::string err;
+    uint64_t next_ticket = 1;
+    int rows_cap_entries = 0;
+    // per-phase timing: a ring of event sets, drained when it wraps or on read
+    bool timing = false;
+    std::vector<std::vector<hipEvent_t>> ev_sets;
+    std::vector<uint8_t> ev_pending;
+    std::vector<uint8_t> ev_phase_mask;
+    size_t ev_next = 0;
+    double phase_ms[kPhases] = {};
+    int64_t phase_n[kPhases] = {};
+};
+
+namespace {
+
+ft_status fail(ft_context *ctx, ft_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+        if (st == FT_ERR_DEVICE) ctx->sticky = FT_ERR_DEVICE;
+    }
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, FT_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Bump {
+    size_t off = 0;
+    template <class T>
+    T *take(char *base, size_t count)
+    {
+        off = align_up(off, 256);
+        T *p = reinterpret_cast<T *>(base + off);
+        off += sizeof(T) * (count ? count : 1);
+        return p;
+    }
+};
+
+void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
+{
+    const size_t kp = (size_t)L.max_kp_per_image, mp = (size_t)L.max_map_points;
+    s.row_off = b.take<int32_t>(base, (size_t)L.max_rows + 1);
+    s.row_items = b.take<int32_t>(base, kp * kRowsPerKpCap);
+    s.best_j = b.take<int32_t>(base, kp);
+    s.best_h = b.take<int32_t>(base, kp);
+    s.h2 = b.take<int32_t>(base, kp);
+    s.sad = b.take<int32_t>(base, kp);
+    s.flag = b.take<int32_t>(base, kp);
+    s.qlist = b.take<int32_t>(base, kp);
+    s.tlist = b.take<int32_t>(base, kp);
+    s.counts = b.take<int32_t>(base, 16);
+    s.uR = b.take<float>(base, kp);
+    s.depth = b.take<float>(base, kp);
+    s.xyz = b.take<float>(base, 3 * kp);
+    s.claimR = b.take<uint32_t>(base, kp);
+    for (int v = 0; v < 2; ++v) {
+        s.view[v].cell_off = b.take<int32_t>(base, (size_t)L.max_grid_cells + 1);
+        s.view[v].cell_items = b.take<int32_t>(base, kp);
+        s.view[v].mp_k = b.take<int32_t>(base, mp);
+        s.view[v].mp_h = b.take<int32_t>(base, mp);
+        s.view[v].claim = b.take<uint32_t>(base, kp);
+    }
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+ft_status check_kps(ft_context *ctx, const ft_keypoints *k, const char *what)
+{
+    if (!k) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: null keypoints", what);
+    if (k->n < 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: n < 0", what);
+    if (k->n > ctx->lim.max_kp_per_image)
+        return fail(ctx, FT_ERR_CAPACITY, "%s: %d keypoints exceed max_kp_per_image %d", what, k->n,
+                    ctx->lim.max_kp_per_image);
+    if (k->n > 0) {
+        if (!k->x || !k->y || !k->octave || !k->desc)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: null array", what);
+        if (!aligned(k->x, 4) || !aligned(k->y, 4) || !aligned(k->desc, 16))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: misaligned array", what);
+    }
+    return FT_OK;
+}
+
+ft_status check_scales(ft_context *ctx, const ft_scales *s)
+{
+    if (!s) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "null scales");
+    if (s->n_levels != kLevels)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "scales: n_levels must be %d", kLevels);
+    for (int l = 0; l < kLevels; ++l) {
+        if (!(s->sf[l] > 0.0f) || !(s->inv_sf[l] > 0.0f) || !std::isfinite(s->sf[l]))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "scales: non-positive scale at level %d", l);
+        if (l > 0 && !(s->sf[l] >= s->sf[l - 1]))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "scales: sf must be non-decreasing");
+    }
+    return FT_OK;
+}
+
+void fill_scales(DevJob &J, const ft_scales *s)
+{
+    for (int l = 0; l < kLevels; ++l) {
+        J.sf[l] = s->sf[l];
+        J.inv_sf[l] = s->inv_sf[l];
+        J.sigma2[l] = s->sigma2[l];
+    }
+}
+
+DevKps dev_kps(const ft_keypoints *k)
+{
+    DevKps d{};
+    d.n = k->n;
+    d.x = k->x;
+    d.y = k->y;
+    d.oct = k->octave;
+    d.desc = k->desc;
+    return d;
+}
+
+void bind_stereo_ws(DevJob &J, const Slot &s, int row_cap)
+{
+    J.row_off = s.row_off;
+    J.row_items = s.row_items;
+    J.best_j = s.best_j;
+    J.best_h = s.best_h;
+    J.h2 = s.h2;
+    J.sad = s.sad;
+    J.flag = s.flag;
+    J.qlist = s.qlist;
+    J.tlist = s.tlist;
+    J.counts = s.counts;
+    J.uR = s.uR;
+    J.depth = s.depth;
+    J.xyz = s.xyz;
+    J.claimR = s.claimR;
+    J.row_items_cap = row_cap;
+}
+
+ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const ft_keypoints *R,
+                        const ft_pyramid *pl, const ft_pyramid *pr, const ft_scales *sc,
+                        const ft_pinhole_stereo *cam, const ft_pinhole_params *p,
+                        const ft_pinhole_out *o, const Slot &slot)
+{
+    ft_status st;
+    if ((st = check_kps(ctx, L, "left")) || (st = check_kps(ctx, R, "right")) ||
+        (st = check_scales(ctx, sc)))
+        return st;
+    if (!pl || !pr || !cam || !p || !o)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: null argument");
+    if (!o->n_matches ||
+        (L->n > 0 && (!o->right_idx || !o->dist || !o->u_right || !o->depth || !o->sad)))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: null output");
+    if (!pl->data || !pr->data) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: null pyramid");
+    if (cam->rows <= 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: rows <= 0");
+    if (cam->rows > ctx->lim.max_rows)
+        return fail(ctx, FT_ERR_CAPACITY, "pinhole: %d rows exceed max_rows %d", cam->rows,
+                    ctx->lim.max_rows);
+    if (!(cam->b > 0.0f) || !(cam->bf > 0.0f))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: baseline and bf must be > 0");
+    if (p->half_win < 0 || p->half_win > 5)  /* (2w+1)^2 * 510 must stay below 2^16 */
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: half_win must be in [0, 5]");
+    if (p->half_range < 1 || 2 * p->half_range + 1 > 64)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: half_range must be in [1, 31]");
+    if (p->level_window < 0 || p->median_den <= 0 || p->median_num <= 0 || p->th_orb < 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: bad thresholds");
+    const float maxr = p->band * sc->sf[kLevels - 1];
+    if (!(p->band >= 0.0f) || !(2.0f * maxr + 4.0f <= (float)kRowsPerKpCap))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: band too wide for the row index");
+    for (int l = 0; l < kLevels; ++l) {
+        if (pl->width[l] != pr->width[l] || pl->height[l] != pr->height[l] || pl->width[l] <= 0 ||
+            pl->height[l] <= 0 || pl->offset[l] < 0 || pr->offset[l] < 0)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: pyramid level %d mismatch", l);
+    }
+    J.flags |= JOB_STEREO_PINHOLE;
+    J.L = dev_kps(L);
+    J.R = dev_kps(R);
+    fill_scales(J, sc);
+    J.pyrL = pl->data;
+    J.pyrR = pr->data;
+    for (int l = 0; l < kLevels; ++l) {
+        J.lv_off[l] = pl->offset[l];
+        J.lv_w[l] = pl->width[l];
+        J.lv_h[l] = pl->height[l];
+        if (pl->offset[l] != pr->offset[l])
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: pyramids must share level offsets");
+    }
+    J.bf = cam->bf;
+    J.maxD = cam->bf / cam->b;
+    J.band = p->band;
+    J.rows = cam->rows;
+    J.th_orb = p->th_orb;
+    J.half_win = p->half_win;
+    J.half_range = p->half_range;
+    J.level_window = p->level_window;
+    J.med_num = p->median_num;
+    J.med_den = p->median_den;
+    J.o_right_idx = o->right_idx;
+    J.o_dist = o->dist;
+    J.o_uR = o->u_right;
+    J.o_depth = o->depth;
+    J.o_sad = o->sad;
+    J.o_nmatch = o->n_matches;
+    bind_stereo_ws(J, slot, ctx->rows_cap_entries);
+    return FT_OK;
+}
+
+void kb8(float *dst, const ft_kb_intrinsics &k)
+{
+    dst[0] = k.fx; dst[1] = k.fy; dst[2] = k.cx; dst[3] = k.cy;
+    for (int i = 0; i < 4; ++i) dst[4 + i] = k.k[i];
+}
+
+ft_status build_fisheye(ft_context *ctx, DevJob &J, const ft_keypoints *L, const ft_keypoints *R,
+                        const ft_scales *sc, const ft_fisheye_stereo *cam,
+                        const ft_fisheye_params *p, const ft_fisheye_out *o, const Slot &slot)
+{
+    ft_status st;
+    if ((st = check_kps(ctx, L, "left")) || (st = check_kps(ctx, R, "right")) ||
+        (st = check_scales(ctx, sc)))
+        return st;
+    if (!cam || !p || !o) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "fisheye: null argument");
+    if (!o->n_matches || (L->n > 0 && (!o->right_idx || !o->dist || !o->depth || !o->xyz)))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "fisheye: null output");
+    if (!(cam->overlap_left[0] <= cam->overlap_left[1]) || !(cam->overlap_right[0] <= cam->overlap_right[1]))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "fisheye: bad overlap range");
+    if (p->ratio_den <= 0 || p->ratio_num <= 0 || p->newton_iters < 0 || p->newton_iters > 100)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "fisheye: bad parameters");
+    if (!(cam->left.fx > 0.0f) || !(cam->left.fy > 0.0f) || !(cam->right.fx > 0.0f) || !(cam->right.fy > 0.0f))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "fisheye: focal lengths must be > 0");
+    J.flags |= JOB_STEREO_FISHEYE;
+    J.L = dev_kps(L);
+    J.R = dev_kps(R);
+    fill_scales(J, sc);
+    kb8(J.kbL, cam->left);
+    kb8(J.kbR, cam->right);
+    memcpy(J.R_lr, cam->R_lr, sizeof J.R_lr);
+    memcpy(J.t_lr, cam->t_lr, sizeof J.t_lr);
+    J.ovl[0] = cam->overlap_left[0];
+    J.ovl[1] = cam->overlap_left[1];
+    J.ovr[0] = cam->overlap_right[0];
+    J.ovr[1] = cam->overlap_right[1];
+    J.ratio_num = p->ratio_num;
+    J.ratio_den = p->ratio_den;
+    J.newton_iters = p->newton_iters;
+    J.cos_max = p->cos_parallax_max;
+    J.chi2 = p->chi2;
+    J.max_theta = p->max_theta;
+    J.newton_tol = p->newton_tol;
+    J.o_right_idx = o->right_idx;
+    J.o_dist = o->dist;
+    J.o_depth = o->depth;
+    J.o_xyz = o->xyz;
+    J.o_nmatch = o->n_matches;
+    bind_stereo_ws(J, slot, ctx->rows_cap_entries);
+    return FT_OK;
+}
+
+ft_status check_search_common(ft_context *ctx, const ft_map_points *map, const ft_search_params *p)
+{
+    if (!map || !p) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: null argument");
+    if (map->n < 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: map n < 0");
+    if (map->n > ctx->lim.max_map_points)
+        return fail(ctx, FT_ERR_CAPACITY, "search: %d map points exceed max_map_points %d", map->n,
+                    ctx->lim.max_map_points);
+    if (map->n > 0) {
+        if (!map->pos || !map->normal || !map->dmin || !map->dmax || !map->desc)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: null map array");
+        if (!aligned(map->pos, 4) || !aligned(map->normal, 4) || !aligned(map->desc, 16))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: misaligned map array");
+    }
+    if (p->th_high < 0 || p->th_high > 256 || p->ratio_den <= 0 || p->ratio_num < 0 ||
+        p->level_lo < 0 || p->level_hi < 0 || !(p->th > 0.0f))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: bad parameters");
+    return FT_OK;
+}
+
+void fill_search_common(DevJob &J, const ft_map_points *map, const ft_search_params *p)
+{
+    J.nM = map->n;
+    J.pos = map->pos;
+    J.normal = map->normal;
+    J.dmin = map->dmin;
+    J.dmax = map->dmax;
+    J.mdesc = map->desc;
+    J.th = p->th;
+    J.cos_lim = p->view_cos_limit;
+    J.cos_narrow = p->view_cos_narrow;
+    J.r_narrow = p->r_narrow;
+    J.r_wide = p->r_wide;
+    J.dist_lo = p->dist_lo;
+    J.dist_hi = p->dist_hi;
+    J.lv_lo = p->level_lo;
+    J.lv_hi = p->level_hi;
+    J.th_high = p->th_high;
+    J.s_ratio_num = p->ratio_num;
+    J.s_ratio_den = p->ratio_den;
+    J.same_level_only = p->ratio_same_level_only;
+}
+
+ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_search_camera *cam,
+                     const ft_keypoints *kps, const float *u_right, const uint8_t *pre,
+                     const ft_grid *grid, const ft_search_out *o, const Slot &slot)
+{
+    ft_status st;
+    if ((st = check_kps(ctx, kps, "search keypoints"))) return st;
+    if (!cam || !grid || !o) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: null argument");
+    if (!o->n_matches || (J.nM > 0 && (!o->mp_match || !o->mp_dist)) || (kps->n > 0 && !o->kp_match))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: null output");
+    if (cam->model != FT_CAMERA_PINHOLE && cam->model != FT_CAMERA_KB)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: unknown camera model %d", cam->model);
+    if (grid->cols <= 0 || grid->rows <= 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: grid must be positive");
+    if ((int64_t)grid->cols * grid->rows > ctx->lim.max_grid_cells)
+        return fail(ctx, FT_ERR_CAPACITY, "search: grid %dx%d exceeds max_grid_cells %d", grid->cols,
+                    grid->rows, ctx->lim.max_grid_cells);
+    if (!(cam->max_x > cam->min_x) || !(cam->max_y > cam->min_y))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: empty image bounds");
+    DevView &V = J.view[v];
+    V.model = cam->model;
+    V.cols = grid->cols;
+    V.rows = grid->rows;
+    V.fx = cam->fx; V.fy = cam->fy; V.cx = cam->cx; V.cy = cam->cy; V.bf = cam->bf;
+    for (int i = 0; i < 4; ++i) V.k[i] = cam->k[i];
+    memcpy(V.R, cam->R, sizeof V.R);
+    memcpy(V.t, cam->t, sizeof V.t);
+    memcpy(V.O, cam->O, sizeof V.O);
+    V.min_x = cam->min_x; V.max_x = cam->max_x; V.min_y = cam->min_y; V.max_y = cam->max_y;
+    V.inv_cw = (float)grid->cols / (cam->max_x - cam->min_x);
+    V.inv_ch = (float)grid->rows / (cam->max_y - cam->min_y);
+    V.side = side;
+    V.preassigned = pre;
+    V.u_right = u_right;
+    V.mp_match = o->mp_match;
+    V.mp_dist = o->mp_dist;
+    V.kp_match = o->kp_match;
+    V.n_matches = o->n_matches;
+    V.cell_off = slot.view[v].cell_off;
+    V.cell_items = slot.view[v].cell_items;
+    V.mp_k = slot.view[v].mp_k;
+    V.mp_h = slot.view[v].mp_h;
+    V.claim = slot.view[v].claim;
+    J.flags |= (JOB_SEARCH0 << v);
+    if (side) J.R = dev_kps(kps);
+    else J.L = dev_kps(kps);
+    return FT_OK;
+}
+
+int tiles(int n, int per) { return (n + per - 1) / per; }
+
+void accumulate_dims(LaunchDims &d, const DevJob &J)
+{
+    const int nL = J.L.n;
+    if (J.flags & JOB_STEREO_PINHOLE) {
+        d.tiles_stereo_a = std::max(d.tiles_stereo_a, tiles(nL, kWG));
+        d.tiles_stereo_b = std::max(d.tiles_stereo_b, tiles(nL, kRefinePerWG));
+        d.tiles_stereo_c = std::max(d.tiles_stereo_c, 1);
+    }
+    if (J.flags & JOB_STEREO_FISHEYE) {
+        d.tiles_stereo_a = std::max(d.tiles_stereo_a, tiles(nL, kKnnQueriesPerWG));
+        d.tiles_stereo_b = std::max(d.tiles_stereo_b, tiles(nL, kWG));
+        d.tiles_stereo_c = std::max(d.tiles_stereo_c, tiles(nL, kWG));
+    }
+    for (int v = 0; v < 2; ++v) {
+        if (!(J.flags & (JOB_SEARCH0 << v))) continue;
+        const int nK = v == 0 ? J.L.n : (J.view[v].side ? J.R.n : J.L.n);
+        d.tiles_search = std::max(d.tiles_search, tiles(J.nM, kWG));
+        d.tiles_search_fin = std::max(d.tiles_search_fin, tiles(std::max(J.nM, nK), kWG));
+        d.setup_x = std::max(d.setup_x, 2 + v);
+    }
+}
+
+constexpr size_t kEventSets = 64;
+
+void drain_set(ft_context *ctx, size_t k)
+{
+    if (!ctx->ev_pending[k]) return;
+    auto &ev = ctx->ev_sets[k];
+    hipEventSynchronize(ev[kPhases]);
+    for (int p = 0; p < kPhases; ++p) {
+        if (!(ctx->ev_phase_mask[k] & (1u << p))) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[p], ev[p + 1]) == hipSuccess) {
+            ctx->phase_ms[p] += ms;
+            ctx->phase_n[p] += 1;
+        }
+    }
+    ctx->ev_pending[k] = 0;
+}
+
+// Event set for the next launch (nullptr when timing is off).
+hipEvent_t *next_events(ft_context *ctx, bool stereo, bool search)
+{
+    if (!ctx->timing) return nullptr;
+    const size_t k = ctx->ev_next;
+    ctx->ev_next = (k + 1) % kEventSets;
+    drain_set(ctx, k);
+    ctx->ev_pending[k] = 1;
+    ctx->ev_phase_mask[k] = (uint8_t)(1u | (stereo ? 0xEu : 0u) | (search ? 0x30u : 0u));
+    return ctx->ev_sets[k].data();
+}
+
+ft_status enter(ft_context *ctx)
+{
+    if (!ctx) return FT_ERR_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    if (hipSetDevice(ctx->device) != hipSuccess)
+        return fail(ctx, FT_ERR_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+    return FT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ft_version(void) { return 100; }
+
+const char *ft_status_string(ft_status s)
+{
+    switch (s) {
+    case FT_OK: return "ok";
+    case FT_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case FT_ERR_CAPACITY: return "capacity exceeded";
+    case FT_ERR_DEVICE: return "device error";
+    case FT_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *ft_last_error(const ft_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **out)
+{
+    if (!lim || !out) return FT_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (lim->max_kp_per_image < 1 || lim->max_kp_per_image > kMaxKp || lim->max_map_points < 1 ||
+        lim->max_map_points > kMaxMap || lim->max_rows < 1 || lim->max_rows > kMaxRows ||
+        lim->max_grid_cells < 1 || lim->max_grid_cells > kMaxCells || lim->max_batch_frames < 1 ||
+        lim->max_batch_frames > 4096 || lim->max_inflight < 1 || lim->max_inflight > 64)
+        return FT_ERR_INVALID_ARGUMENT;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FT_ERR_DEVICE;
+    if (device < 0 || device >= ndev) return FT_ERR_INVALID_ARGUMENT;
+    if (hipSetDevice(device) != hipSuccess) return FT_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return FT_ERR_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return FT_ERR_UNSUPPORTED;
+
+    ft_context *ctx = new ft_context();
+    ctx->device = device;
+    ctx->lim = *lim;
+    ctx->rows_cap_entries = lim->max_kp_per_image * kRowsPerKpCap;
+    // size the arena with a dry run of the carving
+    Bump b;
+    Slot tmp;
+    carve_slot(tmp, nullptr, b, *lim);
+    const size_t slot_bytes = align_up(b.off, 256);
+    const size_t table_bytes = align_up(sizeof(DevJob) * (size_t)lim->max_batch_frames, 256);
+    const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
+    ctx->bytes = slot_bytes * n_slots + table_bytes * lim->max_inflight;
+    if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
+        delete ctx;
+        return FT_ERR_DEVICE;
+    }
+    size_t off = 0;
+    auto carve_at = [&](Slot &s) {
+        Bump bb;
+        carve_slot(s, ctx->base + off, bb, *lim);
+        off += slot_bytes;
+    };
+    carve_at(ctx->direct);
+    ctx->lanes.resize(lim->max_inflight);
+    for (auto &ln : ctx->lanes) {
+        ln.slots.resize(lim->max_batch_frames);
+        for (auto &s : ln.slots) carve_at(s);
+        ln.d_jobs = reinterpret_cast<DevJob *>(ctx->base + off);
+        off += table_bytes;
+        if (hipHostMalloc((void **)&ln.h_jobs, sizeof(DevJob) * lim->max_batch_frames,
+                          hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
+            ft_context_destroy(ctx);
+            return FT_ERR_DEVICE;
+        }
+    }
+    *out = ctx;
+    return FT_OK;
+}
+
+ft_status ft_context_enable_timing(ft_context *ctx, int32_t enable)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (enable && ctx->ev_sets.empty()) {
+        ctx->ev_sets.assign(kEventSets, std::vector<hipEvent_t>(kPhases + 1, nullptr));
+        ctx->ev_pending.assign(kEventSets, 0);
+        ctx->ev_phase_mask.assign(kEventSets, 0);
+        for (auto &set : ctx->ev_sets)
+            for (auto &e : set) HIP_TRY(ctx, hipEventCreate(&e));
+    }
+    ctx->timing = enable != 0;
+    return FT_OK;
+}
+
+ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!ms || !launches) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "read_timing: null output");
+    for (size_t k = 0; k < ctx->ev_sets.size(); ++k) drain_set(ctx, k);
+    for (int p = 0; p < kPhases; ++p) {
+        ms[p] = ctx->phase_ms[p];
+        launches[p] = ctx->phase_n[p];
+        ctx->phase_ms[p] = 0.0;
+        ctx->phase_n[p] = 0;
+    }
+    return FT_OK;
+}
+
+ft_status ft_context_destroy(ft_context *ctx)
+{
+    if (!ctx) return FT_ERR_INVALID_ARGUMENT;
+    hipSetDevice(ctx->device);
+    for (auto &set : ctx->ev_sets)
+        for (auto &e : set)
+            if (e) hipEventDestroy(e);
+    for (auto &ln : ctx->lanes) {
+        if (ln.done) {
+            hipEventSynchronize(ln.done);
+            hipEventDestroy(ln.done);
+        }
+        if (ln.h_jobs) hipHostFree(ln.h_jobs);
+    }
+    if (ctx->base) {
+        hipDeviceSynchronize();
+        hipFree(ctx->base);
+    }
+    delete ctx;
+    return FT_OK;
+}
+
+ft_status ft_context_workspace_bytes(const ft_context *ctx, int64_t *bytes)
+{
+    if (!ctx || !bytes) return FT_ERR_INVALID_ARGUMENT;
+    *bytes = (int64_t)ctx->bytes;
+    return FT_OK;
+}
+
+ft_status ft_stereo_match_pinhole(ft_context *ctx, void *stream, const ft_keypoints *left,
+                                  const ft_keypoints *right, const ft_pyramid *pyr_left,
+                                  const ft_pyramid *pyr_right, const ft_scales *scales,
+                                  const ft_pinhole_stereo *cam, const ft_pinhole_params *params,
+                                  const ft_pinhole_out *out)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    DevJob J{};
+    if ((st = build_pinhole(ctx, J, left, right, pyr_left, pyr_right, scales, cam, params, out,
+                            ctx->direct)))
+        return st;
+    LaunchDims d{};
+    d.n_jobs = 1;
+    d.setup_x = 1;
+    accumulate_dims(d, J);
+    HIP_TRY(ctx, launch_pipeline(nullptr, J, d, (hipStream_t)stream, true, false,
+                                 next_events(ctx, true, false)));
+    return FT_OK;
+}
+
+ft_status ft_stereo_match_fisheye(ft_context *ctx, void *stream, const ft_keypoints *left,
+                                  const ft_keypoints *right, const ft_scales *scales,
+                                  const ft_fisheye_stereo *cam, const ft_fisheye_params *params,
+                                  const ft_fisheye_out *out)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    DevJob J{};
+    if ((st = build_fisheye(ctx, J, left, right, scales, cam, params, out, ctx->direct))) return st;
+    LaunchDims d{};
+    d.n_jobs = 1;
+    d.setup_x = 1;
+    accumulate_dims(d, J);
+    HIP_TRY(ctx, launch_pipeline(nullptr, J, d, (hipStream_t)stream, true, false,
+                                 next_events(ctx, true, false)));
+    return FT_OK;
+}
+
+ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_points *map,
+                                 const ft_search_camera *cam, const ft_keypoints *kps,
+                                 const float *u_right, const uint8_t *preassigned,
+                                 const ft_grid *grid, const ft_scales *scales,
+                                 const ft_search_params *params, const ft_search_out *out)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if ((st = check_scales(ctx, scales)) || (st = check_search_common(ctx, map, params))) return st;
+    if (u_right && !aligned(u_right, 4)) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "misaligned u_right");
+    DevJob J{};
+    fill_scales(J, scales);
+    fill_search_common(J, map, params);
+    if ((st = build_view(ctx, J, 0, 0, cam, kps, u_right, preassigned, grid, out, ctx->direct))) return st;
+    LaunchDims d{};
+    d.n_jobs = 1;
+    d.setup_x = 1;
+    accumulate_dims(d, J);
+    HIP_TRY(ctx, launch_pipeline(nullptr, J, d, (hipStream_t)stream, false, true,
+                                 next_events(ctx, false, true)));
+    return FT_OK;
+}
+
+ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
+                          uint64_t *ticket)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!jobs || !ticket || n <= 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: bad arguments");
+    if (n > ctx->lim.max_batch_frames)
+        return fail(ctx, FT_ERR_CAPACITY, "batch: %d frames exceed max_batch_frames %d", n,
+                    ctx->lim.max_batch_frames);
+    Lane *lane = nullptr;
+    int lane_id = -1;
+    for (size_t i = 0; i < ctx->lanes.size(); ++i) {
+        Lane &ln = ctx->lanes[i];
+        if (!ln.used) { lane = &ln; lane_id = (int)i; break; }
+        const hipError_t q = hipEventQuery(ln.done);
+        if (q == hipSuccess) { lane = &ln; lane_id = (int)i; break; }
+        if (q != hipErrorNotReady) return fail(ctx, FT_ERR_DEVICE, "batch: event query failed");
+    }
+    if (!lane) return fail(ctx, FT_ERR_CAPACITY, "batch: all %zu in-flight slots busy", ctx->lanes.size());
+    LaunchDims d{};
+    d.n_jobs = n;
+    d.setup_x = 1;
+    for (int f = 0; f < n; ++f) {
+        const ft_frame_job &jb = jobs[f];
+        DevJob &J = lane->h_jobs[f];
+        J = DevJob{};
+        const Slot &slot = lane->slots[f];
+        if (jb.kind == FT_JOB_PINHOLE) {
+            if ((st = build_pinhole(ctx, J, &jb.left, &jb.right, &jb.pyr_left, &jb.pyr_right, &jb.scales,
+                                    &jb.pinhole, &jb.pinhole_params, &jb.pinhole_out, slot)))
+                return st;
+        } else if (jb.kind == FT_JOB_FISHEYE) {
+            if ((st = build_fisheye(ctx, J, &jb.left, &jb.right, &jb.scales, &jb.fisheye,
+                                    &jb.fisheye_params, &jb.fisheye_out, slot)))
+                return st;
+        } else if (jb.kind == FT_JOB_SEARCH) {
+            if ((st = check_scales(ctx, &jb.scales))) return st;
+            fill_scales(J, &jb.scales);
+        } else {
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d has unknown kind %d", f, jb.kind);
+        }
+        if (jb.n_views < 0 || jb.n_views > 2)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d n_views must be 0..2", f);
+        if (jb.n_views > 0) {
+            if ((st = check_search_common(ctx, &jb.map, &jb.search_params))) return st;
+            fill_search_common(J, &jb.map, &jb.search_params);
+        }
+        for (int v = 0; v < jb.n_views; ++v) {
+            const ft_keypoints *kps = v == 0 ? &jb.left : &jb.right;
+            const float *ur = (v == 0 && jb.kind == FT_JOB_PINHOLE && jb.use_u_right)
+                                  ? jb.pinhole_out.u_right : nullptr;
+            if ((st = build_view(ctx, J, v, v, &jb.cam[v], kps, ur, jb.preassigned[v], &jb.grid[v],
+                                 &jb.search_out[v], slot)))
+                return st;
+        }
+        accumulate_dims(d, J);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, hipMemcpyAsync(lane->d_jobs, lane->h_jobs, sizeof(DevJob) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_pipeline(lane->d_jobs, lane->h_jobs[0], d, s, true, true,
+                                 next_events(ctx, true, true)));
+    HIP_TRY(ctx, hipEventRecord(lane->done, s));
+    lane->used = true;
+    lane->ticket = (ctx->next_ticket++ << 8) | (uint64_t)lane_id;
+    *ticket = lane->ticket;
+    return FT_OK;
+}
+
+ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!done) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "poll: null done");
+    const size_t lane_id = ticket & 0xFF;
+    if (lane_id >= ctx->lanes.size() || ticket == 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "poll: unknown ticket");
+    Lane &ln = ctx->lanes[lane_id];
+    if (ln.ticket != ticket) {  // the lane was reused, so this ticket completed earlier
+        *done = 1;
+        return FT_OK;
+    }
+    const hipError_t q = hipEventQuery(ln.done);
+    if (q == hipSuccess) *done = 1;
+    else if (q == hipErrorNotReady) *done = 0;
+    else return fail(ctx, FT_ERR_DEVICE, "poll: %s", hipGetErrorString(q));
+    return FT_OK;
+}
+
+ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    const size_t lane_id = ticket & 0xFF;
+    if (lane_id >= ctx->lanes.size() || ticket == 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "wait: unknown ticket");
+    Lane &ln = ctx->lanes[lane_id];
+    if (ln.ticket != ticket) return FT_OK;
+    HIP_TRY(ctx, hipEventSynchronize(ln.done));
+    return FT_OK;
+}
+
+}  // extern "C"

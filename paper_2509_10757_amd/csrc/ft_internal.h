@@ -1,0 +1,105 @@
+// Internal device-side job description shared by the host API and the kernels.
+// A DevJob is a plain struct: passed by value as a kernel argument for the
+// single-frame calls, or stored in a device job table for batches.
+#pragma once
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "ft.h"
+
+namespace ft {
+
+constexpr int kLevels = FT_LEVELS;
+constexpr int kWG = 256;              // every kernel runs 256-thread workgroups (4 wave64s)
+constexpr int kRowsPerKpCap = 48;     // row-index entries per right keypoint (band <= 6.2 px at sf 3.58)
+constexpr int kMaxRows = 4096;
+constexpr int kMaxCells = 8192;
+constexpr int kMaxKp = 65535;
+constexpr int kMaxMap = (1 << 23) - 1;
+constexpr int kKnnQueriesPerWG = 64;  // fisheye all-pairs: 4 waves x 16 query rows
+constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
+
+enum JobFlags : int32_t {
+    JOB_STEREO_PINHOLE = 1,
+    JOB_STEREO_FISHEYE = 2,
+    JOB_SEARCH0 = 4,
+    JOB_SEARCH1 = 8,
+};
+
+struct DevKps {
+    int32_t n;
+    const float *x, *y;
+    const uint8_t *oct;
+    const uint8_t *desc;
+};
+
+struct DevView {
+    int32_t model;
+    int32_t cols, rows;
+    float fx, fy, cx, cy, bf;
+    float k[4];
+    float R[9], t[3], O[3];
+    float min_x, max_x, min_y, max_y;
+    float inv_cw, inv_ch;            // cols/(max_x-min_x), rows/(max_y-min_y)
+    int32_t side;                    // keypoints of the left (0) or right (1) image
+    const uint8_t *preassigned;      // nullable
+    const float *u_right;            // nullable
+    int32_t *mp_match, *mp_dist, *kp_match, *n_matches;
+    // workspace
+    int32_t *cell_off, *cell_items, *mp_k, *mp_h;
+    uint32_t *claim;
+};
+
+struct DevJob {
+    int32_t flags;
+    int32_t nM;
+    DevKps L, R;
+    float sf[kLevels], inv_sf[kLevels], sigma2[kLevels];
+    // pinhole stereo
+    const uint8_t *pyrL, *pyrR;
+    int64_t lv_off[kLevels];
+    int32_t lv_w[kLevels], lv_h[kLevels];
+    float bf, maxD, band;
+    int32_t rows;
+    int32_t th_orb, half_win, half_range, level_window, med_num, med_den;
+    // fisheye stereo
+    float kbL[8], kbR[8], R_lr[9], t_lr[3], ovl[2], ovr[2];
+    int32_t ratio_num, ratio_den, newton_iters;
+    double cos_max, chi2, max_theta, newton_tol;
+    // stereo outputs (caller memory)
+    int32_t *o_right_idx, *o_dist, *o_sad, *o_nmatch;
+    float *o_uR, *o_depth, *o_xyz;
+    // stereo workspace
+    int32_t *row_off, *row_items, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    float *uR, *depth, *xyz;
+    uint32_t *claimR;
+    int32_t row_items_cap;
+    // search by projection
+    const float *pos, *normal, *dmin, *dmax;
+    const uint8_t *mdesc;
+    float th, cos_lim, cos_narrow, r_narrow, r_wide, dist_lo, dist_hi;
+    int32_t lv_lo, lv_hi, th_high, s_ratio_num, s_ratio_den, same_level_only;
+    DevView view[2];
+};
+
+// Launch geometry of one submission (single frame or batch).
+struct LaunchDims {
+    int n_jobs;
+    int tiles_stereo_a;   // best-match tiles (pinhole: 256 queries, fisheye: 64 queries)
+    int tiles_stereo_b;   // refine / triangulation tiles
+    int tiles_stereo_c;   // final stereo tiles
+    int tiles_search;     // map-point tiles per view
+    int tiles_search_fin; // max(map, keypoint) tiles per view
+    int setup_x;          // 1 + number of views needing a grid
+};
+
+// Optional per-phase event timing: when `ev` is non-null, ev[p] and ev[p+1]
+// bracket phase p on the launch stream (ev has kPhases + 1 events).
+constexpr int kPhases = FT_PHASES;
+
+// Launchers (ft_kernels.hip).  `table` == nullptr means: use `one` by value.
+hipError_t launch_pipeline(const DevJob *table, const DevJob &one, const LaunchDims &d,
+                           hipStream_t stream, bool do_stereo, bool do_search, hipEvent_t *ev);
+
+}  // namespace ft

@@ -1,0 +1,223 @@
+"""Device path (through the C ABI) against the CPU oracle, element by element.
+
+Sizes: tiny frames (several tiles and ragged tails) for every kind, the full
+single-frame workloads (pinhole 1200 kp / 3000 map points, fisheye 1500 kp /
+5000 map points, clustered 3000 kp / 20000 map points), the 64-frame batched
+workload as it is benchmarked, a maximum-size frame, and degenerate cases.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity import bit_equal, compare_frame
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(ft):
+    return ft.Context(ft.default_limits(max_batch_frames=64, max_map_points=65536))
+
+
+def run_device(ft, ctx, frame, batch=False):
+    df = ft.DeviceFrame(frame, "cuda")
+    if batch:
+        t = ctx.ft_batch_submit([df.job()])
+        ctx.ft_batch_wait(t)
+    else:
+        df.run(ctx)
+    torch.cuda.synchronize()
+    return df.results()
+
+
+@pytest.mark.parametrize("seed", [101, 102, 103, 104, 105])
+def test_tiny_pinhole(ft, ctx, seed):
+    f = synth.tiny_pinhole(seed, n_kp=int(60 + 37 * (seed % 5)), n_map=200 + seed)
+    say("tiny pinhole", seed)
+    compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+@pytest.mark.parametrize("seed", [201, 202, 203, 204, 205])
+def test_tiny_fisheye(ft, ctx, seed):
+    f = synth.tiny_fisheye(seed, n_kp=int(70 + 41 * (seed % 5)), n_map=150 + seed)
+    say("tiny fisheye", seed)
+    compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+@pytest.mark.parametrize("seed", [301, 302, 303])
+def test_tiny_clustered(ft, ctx, seed):
+    f = synth.tiny_clustered(seed, n_map=300 + 111 * (seed % 3), n_kp=97 + seed % 7)
+    say("tiny clustered", seed)
+    compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_config_single_frame(ft, ctx, k):
+    f = synth.config(k)[0]
+    say("config", k)
+    got = run_device(ft, ctx, f)
+    compare_frame(got, oracle.run_frame(f))
+    assert got["search"][0]["n_matches"] > 100
+
+
+def test_batched_workload_matches_oracle_and_single_frame_path(ft, ctx):
+    frames = synth.config4()
+    say("batched workload: 64 frames")
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    t = ctx.ft_batch_submit([d.job() for d in dfs])
+    ctx.ft_batch_wait(t)
+    torch.cuda.synchronize()
+    batch = [d.results() for d in dfs]
+    for f, got in zip(frames, batch):
+        compare_frame(got, oracle.run_frame(f))
+    # the same frames through the single-frame calls give identical bits
+    for f, b in zip(frames[:8], batch[:8]):
+        bit_equal(run_device(ft, ctx, f), b)
+
+
+def test_repeat_runs_are_bit_identical(ft, ctx):
+    f = synth.config3()[0]
+    first = run_device(ft, ctx, f)
+    for _ in range(4):
+        bit_equal(run_device(ft, ctx, f), first)
+    f = synth.config2()[0]
+    first = run_device(ft, ctx, f, batch=True)
+    for _ in range(3):
+        bit_equal(run_device(ft, ctx, f, batch=True), first)
+
+
+def test_maximum_size_frame(ft, ctx):
+    f = synth.pinhole.pinhole_frame(np.random.SeedSequence(4242), n_kp=4096, n_map=65536)
+    say("max size frame")
+    compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+# ------------------------------------------------------------ degenerate cases
+def _empty_kps():
+    return {"x": np.zeros(0, np.float32), "y": np.zeros(0, np.float32),
+            "octave": np.zeros(0, np.uint8), "desc": np.zeros((0, 32), np.uint8)}
+
+
+def _drop_preassigned(f, n):
+    for s in f["search"]:
+        s["preassigned"] = np.zeros(n, np.uint8)
+
+
+@pytest.mark.parametrize("maker", [synth.tiny_pinhole, synth.tiny_fisheye])
+def test_empty_left_and_right(ft, ctx, maker):
+    for side in ("left", "right"):
+        f = maker(501)
+        f[side] = _empty_kps()
+        for s in f["search"]:
+            if s["image"] == side:
+                s["preassigned"] = np.zeros(0, np.uint8)
+        say("empty", side, f["kind"])
+        compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+def test_empty_map(ft, ctx):
+    for maker in (synth.tiny_pinhole, synth.tiny_fisheye, synth.tiny_clustered):
+        f = maker(502)
+        f["map"] = {k: v[:0] for k, v in f["map"].items()}
+        compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+def test_fisheye_fewer_than_two_targets(ft, ctx):
+    f = synth.tiny_fisheye(503, n_kp=100)
+    xs = np.sort(f["right"]["x"])
+    f["stereo_cam"]["overlap_right"] = np.array([xs[0], xs[0]], np.float32)  # exactly one target
+    want = oracle.run_frame(f)
+    assert want["stereo"]["stats"]["T"] == 1 and want["stereo"]["n_matches"] == 0
+    compare_frame(run_device(ft, ctx, f), want)
+
+
+def test_grid_shapes_and_far_keypoints(ft, ctx):
+    base = synth.tiny_clustered(504)
+    for grid in [(1, 1), (3, 97), (128, 64)]:
+        f = copy.deepcopy(base)
+        f["search"][0]["grid"] = grid
+        f["left"]["x"][::17] = np.float32(1e6)       # far outside the image
+        f["left"]["y"][::23] = np.float32(-50.0)
+        say("grid", grid)
+        compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
+
+
+def test_all_preassigned_and_no_u_right_gate(ft, ctx):
+    f = synth.tiny_pinhole(505)
+    f["search"][0]["preassigned"][:] = 1
+    got = run_device(ft, ctx, f)
+    want = oracle.run_frame(f)
+    compare_frame(got, want)
+    assert want["search"][0]["n_matches"] == 0
+    f = synth.tiny_pinhole(506)
+    f["search"][0]["use_u_right"] = False
+    compare_frame(run_device(ft, ctx, f),
+                  {"kind": "pinhole", "stereo": oracle.stereo_pinhole(f),
+                   "search": [oracle.search_local_points(f, 0)]})
+
+
+def test_all_keypoints_identical_descriptor_ties(ft, ctx):
+    """Every descriptor equal: all distances tie, so indices alone decide."""
+    f = synth.tiny_clustered(507)
+    f["left"]["desc"][:] = f["left"]["desc"][0]
+    f["map"]["desc"][:] = f["left"]["desc"][0]
+    f2 = synth.tiny_fisheye(508)
+    f2["left"]["desc"][:] = f2["left"]["desc"][0]
+    f2["right"]["desc"][:] = f2["left"]["desc"][0]
+    for fr in (f, f2):
+        compare_frame(run_device(ft, ctx, fr), oracle.run_frame(fr))
+
+
+# ------------------------------------------------------------------ errors
+def test_invalid_arguments_enqueue_nothing(ft, ctx):
+    f = synth.tiny_pinhole(601)
+    df = ft.DeviceFrame(f, "cuda")
+    df.o["right_idx"].fill_(12345)
+    bad = ft.ft_scales.from_buffer_copy(df.scales)
+    bad.n_levels = 7
+    st = ctx.ft_stereo_match_pinhole(df.left.struct(), df.right.struct(), df.pyr_left, df.pyr_right,
+                                     bad, df.stereo_cam, df.stereo_params, df.stereo_out, check=False)
+    assert st == ft.FT_ERR_INVALID_ARGUMENT
+    params = ft.ft_pinhole_params.from_buffer_copy(df.stereo_params)
+    params.band = 50.0
+    st = ctx.ft_stereo_match_pinhole(df.left.struct(), df.right.struct(), df.pyr_left, df.pyr_right,
+                                     df.scales, df.stereo_cam, params, df.stereo_out, check=False)
+    assert st == ft.FT_ERR_INVALID_ARGUMENT
+    big = df.left.struct()
+    big.n = ctx.limits.max_kp_per_image + 1
+    st = ctx.ft_stereo_match_pinhole(big, df.right.struct(), df.pyr_left, df.pyr_right, df.scales,
+                                     df.stereo_cam, df.stereo_params, df.stereo_out, check=False)
+    assert st == ft.FT_ERR_CAPACITY
+    grid = ft.ft_grid(200, 100)
+    v = df.views[0]
+    st = ctx.ft_search_local_points(df.map, v["cam"], v["kps"].struct(), None, None, grid, df.scales,
+                                    df.search_params, v["out"], check=False)
+    assert st == ft.FT_ERR_CAPACITY
+    torch.cuda.synchronize()
+    assert bool((df.o["right_idx"] == 12345).all())
+    # the context is still usable after rejected calls
+    df.run(ctx)
+    torch.cuda.synchronize()
+    compare_frame(df.results(), oracle.run_frame(f))
+
+
+def test_batch_tickets_poll_and_wait(ft, ctx):
+    frames = [synth.tiny_pinhole(700 + i) for i in range(3)] + [synth.tiny_fisheye(710 + i) for i in range(3)]
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    t1 = ctx.ft_batch_submit([d.job() for d in dfs[:3]])
+    t2 = ctx.ft_batch_submit([d.job() for d in dfs[3:]])
+    assert t1 != t2
+    ctx.ft_batch_wait(t2)
+    assert ctx.ft_batch_poll(t1) and ctx.ft_batch_poll(t2)
+    for f, d in zip(frames, dfs):
+        compare_frame(d.results(), oracle.run_frame(f))
