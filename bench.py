@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: the hot path is a single-GPU "
@@ -84,6 +86,15 @@ def main():
     from paper_2509_10757_amd import binding as ft
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": 5}))
+        return
     log("generating the 64-frame workload")
     frames = synth.config4()
     n_frames = len(frames)
@@ -92,23 +103,31 @@ def main():
     jobs = [d.job() for d in dfs]
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
+    log("autotune")
+    shapes = ctx.ft_autotune(jobs, stream=stream)
+    torch.cuda.synchronize()
 
     def step():
         return ctx.ft_batch_submit(jobs, stream)
 
+    pending = []
+
+    def submit_bounded():
+        # keep at most max_inflight submissions outstanding (one ticket per slot)
+        if len(pending) >= ctx.limits.max_inflight:
+            ctx.ft_batch_wait(pending.pop(0))
+        pending.append(step())
+
     log("warmup", args.warmup)
     for _ in range(args.warmup):
-        step()
+        submit_bounded()
     torch.cuda.synchronize()
 
     # ---- timed region: K back-to-back batch submissions on one stream
     log("timed", args.steps)
-    pending = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        if len(pending) >= ctx.limits.max_inflight:
-            ctx.ft_batch_wait(pending.pop(0))
-        pending.append(step())
+        submit_bounded()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
@@ -116,6 +135,7 @@ def main():
 
     # ---- latency of one submission (submit -> completion seen by the host)
     lat = []
+    pending.clear()
     for _ in range(max(50, args.steps // 4)):
         s0 = time.perf_counter()
         ctx.ft_batch_wait(step())
@@ -140,9 +160,7 @@ def main():
     if not args.no_timing:
         ctx.ft_context_enable_timing(True)
         for _ in range(args.steps):
-            if len(pending) >= ctx.limits.max_inflight:
-                ctx.ft_batch_wait(pending.pop(0))
-            pending.append(step())
+            submit_bounded()
         torch.cuda.synchronize()
         tm = ctx.ft_context_read_timing()
         ctx.ft_context_enable_timing(False)
@@ -169,6 +187,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "frames_per_step": n_frames,
+                   "shapes": {"best_lanes": shapes[0], "search_lanes": shapes[1]},
                    "pinhole_frames": sum(f["kind"] == "pinhole" for f in frames),
                    "fisheye_frames": sum(f["kind"] == "fisheye" for f in frames)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),

@@ -297,6 +297,27 @@ ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done);
 /* Blocks until the ticket's work has completed. */
 ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket);
 
+/* Launch shapes of the search kernels: how many lanes of a wave cooperate on
+ * one query.  Results never depend on them, only the time does. */
+typedef struct ft_shapes {
+    int32_t best_lanes;        /* lanes per pinhole left keypoint: 1, 2, 4, 8 or 16 */
+    int32_t search_lanes;      /* lanes per map point: 1, 2, 4, 8 or 16 */
+} ft_shapes;
+
+ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *shapes);
+ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *shapes);
+
+/* Autotuner: runs the given batch once per candidate shape (outputs are
+ * overwritten; the call synchronizes `stream`), times the affected kernels
+ * with HIP events and keeps the fastest shapes in the context.  When
+ * `cache_path` is non-null it is a JSON file keyed by device and workload
+ * class (frame count and mean keypoint / map sizes in powers of two): a cached
+ * entry is used without timing, a new one is appended.  `chosen` (nullable)
+ * receives the shapes in use.  Errors as for ft_batch_submit, plus
+ * FT_ERR_INVALID_ARGUMENT for an unreadable or unwritable cache. */
+ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
+                      const char *cache_path, ft_shapes *chosen);
+
 /* ------------------------------------------------------------------------ */
 ft_status ft_context_create(const ft_limits *limits, int32_t device, ft_context **out);
 ft_status ft_context_destroy(ft_context *ctx);

@@ -121,6 +121,10 @@ class ft_frame_job(ct.Structure):
                 ("search_params", ft_search_params), ("search_out", ft_search_out * 2)]
 
 
+class ft_shapes(ct.Structure):
+    _fields_ = [("best_lanes", ct.c_int32), ("search_lanes", ct.c_int32)]
+
+
 EXPORTS = {
     "ft_context_create": [ct.POINTER(ft_limits), ct.c_int32, ct.POINTER(P)],
     "ft_context_destroy": [P],
@@ -141,6 +145,9 @@ EXPORTS = {
     "ft_batch_wait": [P, ct.c_uint64],
     "ft_context_enable_timing": [P, ct.c_int32],
     "ft_context_read_timing": [P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)],
+    "ft_set_shapes": [P, ct.POINTER(ft_shapes)],
+    "ft_get_shapes": [P, ct.POINTER(ft_shapes)],
+    "ft_autotune": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.c_char_p, ct.POINTER(ft_shapes)],
     "ft_status_string": [ct.c_int32],
     "ft_last_error": [P],
     "ft_version": [],
@@ -267,6 +274,23 @@ class Context:
         self._check(self.lib.ft_batch_submit(self.h, _stream(stream), arr, len(jobs), ct.byref(t)),
                     "ft_batch_submit")
         return t.value
+
+    def ft_set_shapes(self, best_lanes: int, search_lanes: int):
+        self._check(self.lib.ft_set_shapes(self.h, ct.byref(ft_shapes(best_lanes, search_lanes))),
+                    "ft_set_shapes")
+
+    def ft_get_shapes(self) -> tuple:
+        s = ft_shapes()
+        self._check(self.lib.ft_get_shapes(self.h, ct.byref(s)), "ft_get_shapes")
+        return s.best_lanes, s.search_lanes
+
+    def ft_autotune(self, jobs, cache_path=None, stream=None) -> tuple:
+        arr = (ft_frame_job * len(jobs))(*jobs)
+        s = ft_shapes()
+        cp = cache_path.encode() if cache_path else None
+        self._check(self.lib.ft_autotune(self.h, _stream(stream), arr, len(jobs), cp, ct.byref(s)),
+                    "ft_autotune")
+        return s.best_lanes, s.search_lanes
 
     def ft_batch_poll(self, ticket: int) -> bool:
         d = ct.c_int32()

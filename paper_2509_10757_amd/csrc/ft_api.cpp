@@ -1,11 +1,15 @@
 // Host side of the C ABI declared in include/ft.h: context and preallocated
-// workspace, synchronous argument validation, job descriptors, batch tickets.
+// workspace, synchronous argument validation, job descriptors, batch tickets,
+// per-phase timing and the launch-shape autotuner.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -16,19 +20,38 @@ using namespace ft;
 namespace {
 
 struct Slot {  // workspace of one frame
-    int32_t *row_off, *row_items, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    int32_t *row_start, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    RowRec *rrec;
+    uint8_t *tdesc;
     float *uR, *depth, *xyz;
     uint32_t *claimR;
     struct {
-        int32_t *cell_off, *cell_items, *mp_k, *mp_h;
+        int32_t *cell_off, *mp_k, *mp_h;
+        CellRec *crec;
+        uint8_t *cdesc;
         uint32_t *claim;
     } view[2];
 };
 
+// Layout of one batch's upload: the job table followed by the tile prefixes.
+struct TableLayout {
+    size_t jobs_bytes, prefix_off, total;
+};
+
+TableLayout table_layout(int max_frames)
+{
+    TableLayout t;
+    t.jobs_bytes = sizeof(DevJob) * (size_t)max_frames;
+    t.prefix_off = (t.jobs_bytes + 255) / 256 * 256;
+    t.total = t.prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1);
+    t.total = (t.total + 255) / 256 * 256;
+    return t;
+}
+
 struct Lane {  // one batch in flight
     std::vector<Slot> slots;
-    DevJob *d_jobs = nullptr;
-    DevJob *h_jobs = nullptr;   // pinned staging of the job table
+    char *d_table = nullptr;   // device: DevJob[n] | prefixes
+    char *h_table = nullptr;   // pinned staging of the same bytes
     hipEvent_t done = nullptr;
     uint64_t ticket = 0;
     bool used = false;
@@ -43,15 +66,15 @@ struct ft_context {
     size_t bytes = 0;
     Slot direct{};
     std::vector<Lane> lanes;
+    TableLayout layout{};
     ft_status sticky = FT_OK;
     std::string err;
     uint64_t next_ticket = 1;
-    int rows_cap_entries = 0;
+    Shapes shapes;
     // per-phase timing: a ring of event sets, drained when it wraps or on read
     bool timing = false;
     std::vector<std::vector<hipEvent_t>> ev_sets;
     std::vector<uint8_t> ev_pending;
-    std::vector<uint8_t> ev_phase_mask;
     size_t ev_next = 0;
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
@@ -97,8 +120,9 @@ struct Bump {
 void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
 {
     const size_t kp = (size_t)L.max_kp_per_image, mp = (size_t)L.max_map_points;
-    s.row_off = b.take<int32_t>(base, (size_t)L.max_rows + 1);
-    s.row_items = b.take<int32_t>(base, kp * kRowsPerKpCap);
+    s.row_start = b.take<int32_t>(base, (size_t)L.max_rows + 1);
+    s.rrec = b.take<RowRec>(base, kp);
+    s.tdesc = b.take<uint8_t>(base, 32 * kp);
     s.best_j = b.take<int32_t>(base, kp);
     s.best_h = b.take<int32_t>(base, kp);
     s.h2 = b.take<int32_t>(base, kp);
@@ -113,7 +137,8 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     s.claimR = b.take<uint32_t>(base, kp);
     for (int v = 0; v < 2; ++v) {
         s.view[v].cell_off = b.take<int32_t>(base, (size_t)L.max_grid_cells + 1);
-        s.view[v].cell_items = b.take<int32_t>(base, kp);
+        s.view[v].crec = b.take<CellRec>(base, kp);
+        s.view[v].cdesc = b.take<uint8_t>(base, 32 * kp);
         s.view[v].mp_k = b.take<int32_t>(base, mp);
         s.view[v].mp_h = b.take<int32_t>(base, mp);
         s.view[v].claim = b.take<uint32_t>(base, kp);
@@ -121,6 +146,8 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool valid_lanes(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
 
 ft_status check_kps(ft_context *ctx, const ft_keypoints *k, const char *what)
 {
@@ -172,10 +199,11 @@ DevKps dev_kps(const ft_keypoints *k)
     return d;
 }
 
-void bind_stereo_ws(DevJob &J, const Slot &s, int row_cap)
+void bind_stereo_ws(DevJob &J, const Slot &s)
 {
-    J.row_off = s.row_off;
-    J.row_items = s.row_items;
+    J.row_start = s.row_start;
+    J.rrec = s.rrec;
+    J.tdesc = s.tdesc;
     J.best_j = s.best_j;
     J.best_h = s.best_h;
     J.h2 = s.h2;
@@ -188,7 +216,6 @@ void bind_stereo_ws(DevJob &J, const Slot &s, int row_cap)
     J.depth = s.depth;
     J.xyz = s.xyz;
     J.claimR = s.claimR;
-    J.row_items_cap = row_cap;
 }
 
 ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const ft_keypoints *R,
@@ -214,16 +241,15 @@ ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: baseline and bf must be > 0");
     if (p->half_win < 0 || p->half_win > 5)  /* (2w+1)^2 * 510 must stay below 2^16 */
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: half_win must be in [0, 5]");
-    if (p->half_range < 1 || 2 * p->half_range + 1 > 64)
+    if (p->half_range < 1 || p->half_range > 31)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: half_range must be in [1, 31]");
     if (p->level_window < 0 || p->median_den <= 0 || p->median_num <= 0 || p->th_orb < 0)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: bad thresholds");
-    const float maxr = p->band * sc->sf[kLevels - 1];
-    if (!(p->band >= 0.0f) || !(2.0f * maxr + 4.0f <= (float)kRowsPerKpCap))
-        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: band too wide for the row index");
+    if (!(p->band >= 0.0f) || !(p->band <= 64.0f))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: band must be in [0, 64]");
     for (int l = 0; l < kLevels; ++l) {
         if (pl->width[l] != pr->width[l] || pl->height[l] != pr->height[l] || pl->width[l] <= 0 ||
-            pl->height[l] <= 0 || pl->offset[l] < 0 || pr->offset[l] < 0)
+            pl->height[l] <= 0 || pl->offset[l] < 0 || pl->offset[l] != pr->offset[l])
             return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: pyramid level %d mismatch", l);
     }
     J.flags |= JOB_STEREO_PINHOLE;
@@ -236,13 +262,14 @@ ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const
         J.lv_off[l] = pl->offset[l];
         J.lv_w[l] = pl->width[l];
         J.lv_h[l] = pl->height[l];
-        if (pl->offset[l] != pr->offset[l])
-            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "pinhole: pyramids must share level offsets");
     }
     J.bf = cam->bf;
     J.maxD = cam->bf / cam->b;
     J.band = p->band;
     J.rows = cam->rows;
+    // a right keypoint whose band covers row r has its integer row within
+    // ceil(band * sf_max) + 1 of r; one more bin absorbs the float rounding
+    J.row_reach = (int)std::ceil(p->band * sc->sf[kLevels - 1]) + 2;
     J.th_orb = p->th_orb;
     J.half_win = p->half_win;
     J.half_range = p->half_range;
@@ -255,7 +282,7 @@ ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const
     J.o_depth = o->depth;
     J.o_sad = o->sad;
     J.o_nmatch = o->n_matches;
-    bind_stereo_ws(J, slot, ctx->rows_cap_entries);
+    bind_stereo_ws(J, slot);
     return FT_OK;
 }
 
@@ -306,7 +333,7 @@ ft_status build_fisheye(ft_context *ctx, DevJob &J, const ft_keypoints *L, const
     J.o_depth = o->depth;
     J.o_xyz = o->xyz;
     J.o_nmatch = o->n_matches;
-    bind_stereo_ws(J, slot, ctx->rows_cap_entries);
+    bind_stereo_ws(J, slot);
     return FT_OK;
 }
 
@@ -370,6 +397,7 @@ ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_searc
                     grid->rows, ctx->lim.max_grid_cells);
     if (!(cam->max_x > cam->min_x) || !(cam->max_y > cam->min_y))
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "search: empty image bounds");
+    if (u_right && !aligned(u_right, 4)) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "misaligned u_right");
     DevView &V = J.view[v];
     V.model = cam->model;
     V.cols = grid->cols;
@@ -390,40 +418,19 @@ ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_searc
     V.kp_match = o->kp_match;
     V.n_matches = o->n_matches;
     V.cell_off = slot.view[v].cell_off;
-    V.cell_items = slot.view[v].cell_items;
+    V.crec = slot.view[v].crec;
+    V.cdesc = slot.view[v].cdesc;
     V.mp_k = slot.view[v].mp_k;
     V.mp_h = slot.view[v].mp_h;
     V.claim = slot.view[v].claim;
     J.flags |= (JOB_SEARCH0 << v);
+    J.n_views = std::max(J.n_views, v + 1);
     if (side) J.R = dev_kps(kps);
     else J.L = dev_kps(kps);
     return FT_OK;
 }
 
-int tiles(int n, int per) { return (n + per - 1) / per; }
-
-void accumulate_dims(LaunchDims &d, const DevJob &J)
-{
-    const int nL = J.L.n;
-    if (J.flags & JOB_STEREO_PINHOLE) {
-        d.tiles_stereo_a = std::max(d.tiles_stereo_a, tiles(nL, kWG));
-        d.tiles_stereo_b = std::max(d.tiles_stereo_b, tiles(nL, kRefinePerWG));
-        d.tiles_stereo_c = std::max(d.tiles_stereo_c, 1);
-    }
-    if (J.flags & JOB_STEREO_FISHEYE) {
-        d.tiles_stereo_a = std::max(d.tiles_stereo_a, tiles(nL, kKnnQueriesPerWG));
-        d.tiles_stereo_b = std::max(d.tiles_stereo_b, tiles(nL, kWG));
-        d.tiles_stereo_c = std::max(d.tiles_stereo_c, tiles(nL, kWG));
-    }
-    for (int v = 0; v < 2; ++v) {
-        if (!(J.flags & (JOB_SEARCH0 << v))) continue;
-        const int nK = v == 0 ? J.L.n : (J.view[v].side ? J.R.n : J.L.n);
-        d.tiles_search = std::max(d.tiles_search, tiles(J.nM, kWG));
-        d.tiles_search_fin = std::max(d.tiles_search_fin, tiles(std::max(J.nM, nK), kWG));
-        d.setup_x = std::max(d.setup_x, 2 + v);
-    }
-}
-
+// ---------------------------------------------------------------- timing
 constexpr size_t kEventSets = 64;
 
 void drain_set(ft_context *ctx, size_t k)
@@ -432,9 +439,8 @@ void drain_set(ft_context *ctx, size_t k)
     auto &ev = ctx->ev_sets[k];
     hipEventSynchronize(ev[kPhases]);
     for (int p = 0; p < kPhases; ++p) {
-        if (!(ctx->ev_phase_mask[k] & (1u << p))) continue;
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev[p], ev[p + 1]) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, ev[p], ev[p + 1]) == hipSuccess && ms > 0.0f) {
             ctx->phase_ms[p] += ms;
             ctx->phase_n[p] += 1;
         }
@@ -443,15 +449,37 @@ void drain_set(ft_context *ctx, size_t k)
 }
 
 // Event set for the next launch (nullptr when timing is off).
-hipEvent_t *next_events(ft_context *ctx, bool stereo, bool search)
+hipEvent_t *next_events(ft_context *ctx)
 {
     if (!ctx->timing) return nullptr;
     const size_t k = ctx->ev_next;
     ctx->ev_next = (k + 1) % kEventSets;
     drain_set(ctx, k);
     ctx->ev_pending[k] = 1;
-    ctx->ev_phase_mask[k] = (uint8_t)(1u | (stereo ? 0xEu : 0u) | (search ? 0x30u : 0u));
     return ctx->ev_sets[k].data();
+}
+
+ft_status set_timing(ft_context *ctx, bool enable)
+{
+    if (enable && ctx->ev_sets.empty()) {
+        ctx->ev_sets.assign(kEventSets, std::vector<hipEvent_t>(kPhases + 1, nullptr));
+        ctx->ev_pending.assign(kEventSets, 0);
+        for (auto &set : ctx->ev_sets)
+            for (auto &e : set) HIP_TRY(ctx, hipEventCreate(&e));
+    }
+    ctx->timing = enable;
+    return FT_OK;
+}
+
+void read_timing(ft_context *ctx, double *ms, int64_t *n)
+{
+    for (size_t k = 0; k < ctx->ev_sets.size(); ++k) drain_set(ctx, k);
+    for (int p = 0; p < kPhases; ++p) {
+        ms[p] = ctx->phase_ms[p];
+        n[p] = ctx->phase_n[p];
+        ctx->phase_ms[p] = 0.0;
+        ctx->phase_n[p] = 0;
+    }
 }
 
 ft_status enter(ft_context *ctx)
@@ -463,11 +491,160 @@ ft_status enter(ft_context *ctx)
     return FT_OK;
 }
 
+ft_status launch_one(ft_context *ctx, const DevJob &J, hipStream_t s, bool stereo, bool search)
+{
+    int32_t tot[PH_COUNT];
+    job_tiles(J, ctx->shapes, stereo, search, tot);
+    TileMap none{0, nullptr};
+    HIP_TRY(ctx, launch_pipeline(nullptr, none, tot, J, ctx->shapes, s, stereo, search, next_events(ctx)));
+    return FT_OK;
+}
+
+// Validates every job of a batch into the lane's staging table.
+ft_status build_batch(ft_context *ctx, Lane &lane, const ft_frame_job *jobs, int32_t n)
+{
+    ft_status st;
+    DevJob *table = reinterpret_cast<DevJob *>(lane.h_table);
+    for (int f = 0; f < n; ++f) {
+        const ft_frame_job &jb = jobs[f];
+        DevJob &J = table[f];
+        J = DevJob{};
+        const Slot &slot = lane.slots[f];
+        if (jb.kind == FT_JOB_PINHOLE) {
+            if ((st = build_pinhole(ctx, J, &jb.left, &jb.right, &jb.pyr_left, &jb.pyr_right, &jb.scales,
+                                    &jb.pinhole, &jb.pinhole_params, &jb.pinhole_out, slot)))
+                return st;
+        } else if (jb.kind == FT_JOB_FISHEYE) {
+            if ((st = build_fisheye(ctx, J, &jb.left, &jb.right, &jb.scales, &jb.fisheye,
+                                    &jb.fisheye_params, &jb.fisheye_out, slot)))
+                return st;
+        } else if (jb.kind == FT_JOB_SEARCH) {
+            if ((st = check_scales(ctx, &jb.scales))) return st;
+            fill_scales(J, &jb.scales);
+        } else {
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d has unknown kind %d", f, jb.kind);
+        }
+        if (jb.n_views < 0 || jb.n_views > 2)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d n_views must be 0..2", f);
+        if (jb.n_views > 0) {
+            if ((st = check_search_common(ctx, &jb.map, &jb.search_params))) return st;
+            fill_search_common(J, &jb.map, &jb.search_params);
+        }
+        for (int v = 0; v < jb.n_views; ++v) {
+            const ft_keypoints *kps = v == 0 ? &jb.left : &jb.right;
+            const float *ur = (v == 0 && jb.kind == FT_JOB_PINHOLE && jb.use_u_right)
+                                  ? jb.pinhole_out.u_right : nullptr;
+            if ((st = build_view(ctx, J, v, v, &jb.cam[v], kps, ur, jb.preassigned[v], &jb.grid[v],
+                                 &jb.search_out[v], slot)))
+                return st;
+        }
+    }
+    return FT_OK;
+}
+
+// Tile prefixes of every phase into the staging table; returns the totals.
+void plan_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, int32_t totals[PH_COUNT])
+{
+    const DevJob *table = reinterpret_cast<const DevJob *>(lane.h_table);
+    int32_t *pre = reinterpret_cast<int32_t *>(lane.h_table + ctx->layout.prefix_off);
+    for (int p = 0; p < PH_COUNT; ++p) {
+        pre[p * (n + 1)] = 0;
+        totals[p] = 0;
+    }
+    for (int f = 0; f < n; ++f) {
+        int32_t t[PH_COUNT];
+        job_tiles(table[f], sh, true, true, t);
+        for (int p = 0; p < PH_COUNT; ++p) {
+            totals[p] += t[p];
+            pre[p * (n + 1) + f + 1] = totals[p];
+        }
+    }
+}
+
+Lane *free_lane(ft_context *ctx, int *id, ft_status *st)
+{
+    *st = FT_OK;
+    for (size_t i = 0; i < ctx->lanes.size(); ++i) {
+        Lane &ln = ctx->lanes[i];
+        if (!ln.used) { *id = (int)i; return &ln; }
+        const hipError_t q = hipEventQuery(ln.done);
+        if (q == hipSuccess) { *id = (int)i; return &ln; }
+        if (q != hipErrorNotReady) {
+            *st = fail(ctx, FT_ERR_DEVICE, "batch: event query failed: %s", hipGetErrorString(q));
+            return nullptr;
+        }
+    }
+    *st = fail(ctx, FT_ERR_CAPACITY, "batch: all %zu in-flight slots busy", ctx->lanes.size());
+    return nullptr;
+}
+
+// Uploads the staged table and launches every phase over the batch.
+ft_status launch_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, hipStream_t s,
+                       const int32_t totals[PH_COUNT], hipEvent_t *ev)
+{
+    const size_t bytes = ctx->layout.prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(n + 1);
+    HIP_TRY(ctx, hipMemcpyAsync(lane.d_table, lane.h_table, bytes, hipMemcpyHostToDevice, s));
+    TileMap map{n, reinterpret_cast<const int32_t *>(lane.d_table + ctx->layout.prefix_off)};
+    const DevJob *table = reinterpret_cast<const DevJob *>(lane.d_table);
+    const DevJob *staged = reinterpret_cast<const DevJob *>(lane.h_table);
+    HIP_TRY(ctx, launch_pipeline(table, map, totals, staged[0], sh, s, true, true, ev));
+    return FT_OK;
+}
+
+// ---------------------------------------------------------------- autotune
+std::string workload_key(const ft_frame_job *jobs, int32_t n, const char *arch)
+{
+    double kp = 0, mp = 0;
+    int pin = 0, fish = 0;
+    for (int f = 0; f < n; ++f) {
+        kp += jobs[f].left.n;
+        mp += jobs[f].map.n;
+        pin += jobs[f].kind == FT_JOB_PINHOLE;
+        fish += jobs[f].kind == FT_JOB_FISHEYE;
+    }
+    auto p2 = [](double v) { return v <= 1 ? 0 : (int)std::lround(std::log2(v)); };
+    std::ostringstream os;
+    os << arch << ":frames=" << n << ":pinhole=" << pin << ":fisheye=" << fish
+       << ":kp2=" << p2(kp / std::max(n, 1)) << ":map2=" << p2(mp / std::max(n, 1));
+    return os.str();
+}
+
+bool cache_lookup(const std::string &path, const std::string &key, Shapes &out)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    const std::string tag = "\"key\": \"" + key + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(tag) == std::string::npos) continue;
+        const size_t pb = line.find("\"best_lanes\": "), ps = line.find("\"search_lanes\": ");
+        if (pb == std::string::npos || ps == std::string::npos) continue;
+        const int b = std::atoi(line.c_str() + pb + 14);
+        const int s = std::atoi(line.c_str() + ps + 16);
+        if (valid_lanes(b) && valid_lanes(s)) {
+            out.best_lanes = b;
+            out.search_lanes = s;
+            return true;
+        }
+    }
+    return false;
+}
+
+bool cache_append(const std::string &path, const std::string &key, const Shapes &sh, double us)
+{
+    // one JSON object per line, so entries can be appended and grepped
+    std::ofstream f(path, std::ios::app);
+    if (!f) return false;
+    f << "{\"key\": \"" << key << "\", \"best_lanes\": " << sh.best_lanes
+      << ", \"search_lanes\": " << sh.search_lanes << ", \"us\": " << us << "}\n";
+    return (bool)f;
+}
+
 }  // namespace
 
 extern "C" {
 
-int32_t ft_version(void) { return 100; }
+int32_t ft_version(void) { return 200; }
 
 const char *ft_status_string(ft_status s)
 {
@@ -503,15 +680,13 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     ft_context *ctx = new ft_context();
     ctx->device = device;
     ctx->lim = *lim;
-    ctx->rows_cap_entries = lim->max_kp_per_image * kRowsPerKpCap;
-    // size the arena with a dry run of the carving
+    ctx->layout = table_layout(lim->max_batch_frames);
     Bump b;
     Slot tmp;
     carve_slot(tmp, nullptr, b, *lim);
     const size_t slot_bytes = align_up(b.off, 256);
-    const size_t table_bytes = align_up(sizeof(DevJob) * (size_t)lim->max_batch_frames, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
-    ctx->bytes = slot_bytes * n_slots + table_bytes * lim->max_inflight;
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -527,10 +702,9 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     for (auto &ln : ctx->lanes) {
         ln.slots.resize(lim->max_batch_frames);
         for (auto &s : ln.slots) carve_at(s);
-        ln.d_jobs = reinterpret_cast<DevJob *>(ctx->base + off);
-        off += table_bytes;
-        if (hipHostMalloc((void **)&ln.h_jobs, sizeof(DevJob) * lim->max_batch_frames,
-                          hipHostMallocDefault) != hipSuccess ||
+        ln.d_table = ctx->base + off;
+        off += ctx->layout.total;
+        if (hipHostMalloc((void **)&ln.h_table, ctx->layout.total, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
             ft_context_destroy(ctx);
             return FT_ERR_DEVICE;
@@ -544,15 +718,7 @@ ft_status ft_context_enable_timing(ft_context *ctx, int32_t enable)
 {
     ft_status st = enter(ctx);
     if (st) return st;
-    if (enable && ctx->ev_sets.empty()) {
-        ctx->ev_sets.assign(kEventSets, std::vector<hipEvent_t>(kPhases + 1, nullptr));
-        ctx->ev_pending.assign(kEventSets, 0);
-        ctx->ev_phase_mask.assign(kEventSets, 0);
-        for (auto &set : ctx->ev_sets)
-            for (auto &e : set) HIP_TRY(ctx, hipEventCreate(&e));
-    }
-    ctx->timing = enable != 0;
-    return FT_OK;
+    return set_timing(ctx, enable != 0);
 }
 
 ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches)
@@ -560,13 +726,7 @@ ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches)
     ft_status st = enter(ctx);
     if (st) return st;
     if (!ms || !launches) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "read_timing: null output");
-    for (size_t k = 0; k < ctx->ev_sets.size(); ++k) drain_set(ctx, k);
-    for (int p = 0; p < kPhases; ++p) {
-        ms[p] = ctx->phase_ms[p];
-        launches[p] = ctx->phase_n[p];
-        ctx->phase_ms[p] = 0.0;
-        ctx->phase_n[p] = 0;
-    }
+    read_timing(ctx, ms, launches);
     return FT_OK;
 }
 
@@ -582,7 +742,7 @@ ft_status ft_context_destroy(ft_context *ctx)
             hipEventSynchronize(ln.done);
             hipEventDestroy(ln.done);
         }
-        if (ln.h_jobs) hipHostFree(ln.h_jobs);
+        if (ln.h_table) hipHostFree(ln.h_table);
     }
     if (ctx->base) {
         hipDeviceSynchronize();
@@ -599,6 +759,24 @@ ft_status ft_context_workspace_bytes(const ft_context *ctx, int64_t *bytes)
     return FT_OK;
 }
 
+ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *s)
+{
+    if (!ctx || !s) return FT_ERR_INVALID_ARGUMENT;
+    if (!valid_lanes(s->best_lanes) || !valid_lanes(s->search_lanes))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: lanes must be 1, 2, 4, 8 or 16");
+    ctx->shapes.best_lanes = s->best_lanes;
+    ctx->shapes.search_lanes = s->search_lanes;
+    return FT_OK;
+}
+
+ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *s)
+{
+    if (!ctx || !s) return FT_ERR_INVALID_ARGUMENT;
+    s->best_lanes = ctx->shapes.best_lanes;
+    s->search_lanes = ctx->shapes.search_lanes;
+    return FT_OK;
+}
+
 ft_status ft_stereo_match_pinhole(ft_context *ctx, void *stream, const ft_keypoints *left,
                                   const ft_keypoints *right, const ft_pyramid *pyr_left,
                                   const ft_pyramid *pyr_right, const ft_scales *scales,
@@ -611,13 +789,7 @@ ft_status ft_stereo_match_pinhole(ft_context *ctx, void *stream, const ft_keypoi
     if ((st = build_pinhole(ctx, J, left, right, pyr_left, pyr_right, scales, cam, params, out,
                             ctx->direct)))
         return st;
-    LaunchDims d{};
-    d.n_jobs = 1;
-    d.setup_x = 1;
-    accumulate_dims(d, J);
-    HIP_TRY(ctx, launch_pipeline(nullptr, J, d, (hipStream_t)stream, true, false,
-                                 next_events(ctx, true, false)));
-    return FT_OK;
+    return launch_one(ctx, J, (hipStream_t)stream, true, false);
 }
 
 ft_status ft_stereo_match_fisheye(ft_context *ctx, void *stream, const ft_keypoints *left,
@@ -629,13 +801,7 @@ ft_status ft_stereo_match_fisheye(ft_context *ctx, void *stream, const ft_keypoi
     if (st) return st;
     DevJob J{};
     if ((st = build_fisheye(ctx, J, left, right, scales, cam, params, out, ctx->direct))) return st;
-    LaunchDims d{};
-    d.n_jobs = 1;
-    d.setup_x = 1;
-    accumulate_dims(d, J);
-    HIP_TRY(ctx, launch_pipeline(nullptr, J, d, (hipStream_t)stream, true, false,
-                                 next_events(ctx, true, false)));
-    return FT_OK;
+    return launch_one(ctx, J, (hipStream_t)stream, true, false);
 }
 
 ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_points *map,
@@ -647,18 +813,11 @@ ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_poi
     ft_status st = enter(ctx);
     if (st) return st;
     if ((st = check_scales(ctx, scales)) || (st = check_search_common(ctx, map, params))) return st;
-    if (u_right && !aligned(u_right, 4)) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "misaligned u_right");
     DevJob J{};
     fill_scales(J, scales);
     fill_search_common(J, map, params);
     if ((st = build_view(ctx, J, 0, 0, cam, kps, u_right, preassigned, grid, out, ctx->direct))) return st;
-    LaunchDims d{};
-    d.n_jobs = 1;
-    d.setup_x = 1;
-    accumulate_dims(d, J);
-    HIP_TRY(ctx, launch_pipeline(nullptr, J, d, (hipStream_t)stream, false, true,
-                                 next_events(ctx, false, true)));
-    return FT_OK;
+    return launch_one(ctx, J, (hipStream_t)stream, false, true);
 }
 
 ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
@@ -670,58 +829,14 @@ ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *job
     if (n > ctx->lim.max_batch_frames)
         return fail(ctx, FT_ERR_CAPACITY, "batch: %d frames exceed max_batch_frames %d", n,
                     ctx->lim.max_batch_frames);
-    Lane *lane = nullptr;
     int lane_id = -1;
-    for (size_t i = 0; i < ctx->lanes.size(); ++i) {
-        Lane &ln = ctx->lanes[i];
-        if (!ln.used) { lane = &ln; lane_id = (int)i; break; }
-        const hipError_t q = hipEventQuery(ln.done);
-        if (q == hipSuccess) { lane = &ln; lane_id = (int)i; break; }
-        if (q != hipErrorNotReady) return fail(ctx, FT_ERR_DEVICE, "batch: event query failed");
-    }
-    if (!lane) return fail(ctx, FT_ERR_CAPACITY, "batch: all %zu in-flight slots busy", ctx->lanes.size());
-    LaunchDims d{};
-    d.n_jobs = n;
-    d.setup_x = 1;
-    for (int f = 0; f < n; ++f) {
-        const ft_frame_job &jb = jobs[f];
-        DevJob &J = lane->h_jobs[f];
-        J = DevJob{};
-        const Slot &slot = lane->slots[f];
-        if (jb.kind == FT_JOB_PINHOLE) {
-            if ((st = build_pinhole(ctx, J, &jb.left, &jb.right, &jb.pyr_left, &jb.pyr_right, &jb.scales,
-                                    &jb.pinhole, &jb.pinhole_params, &jb.pinhole_out, slot)))
-                return st;
-        } else if (jb.kind == FT_JOB_FISHEYE) {
-            if ((st = build_fisheye(ctx, J, &jb.left, &jb.right, &jb.scales, &jb.fisheye,
-                                    &jb.fisheye_params, &jb.fisheye_out, slot)))
-                return st;
-        } else if (jb.kind == FT_JOB_SEARCH) {
-            if ((st = check_scales(ctx, &jb.scales))) return st;
-            fill_scales(J, &jb.scales);
-        } else {
-            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d has unknown kind %d", f, jb.kind);
-        }
-        if (jb.n_views < 0 || jb.n_views > 2)
-            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d n_views must be 0..2", f);
-        if (jb.n_views > 0) {
-            if ((st = check_search_common(ctx, &jb.map, &jb.search_params))) return st;
-            fill_search_common(J, &jb.map, &jb.search_params);
-        }
-        for (int v = 0; v < jb.n_views; ++v) {
-            const ft_keypoints *kps = v == 0 ? &jb.left : &jb.right;
-            const float *ur = (v == 0 && jb.kind == FT_JOB_PINHOLE && jb.use_u_right)
-                                  ? jb.pinhole_out.u_right : nullptr;
-            if ((st = build_view(ctx, J, v, v, &jb.cam[v], kps, ur, jb.preassigned[v], &jb.grid[v],
-                                 &jb.search_out[v], slot)))
-                return st;
-        }
-        accumulate_dims(d, J);
-    }
+    Lane *lane = free_lane(ctx, &lane_id, &st);
+    if (!lane) return st;
+    if ((st = build_batch(ctx, *lane, jobs, n))) return st;
+    int32_t totals[PH_COUNT];
+    plan_batch(ctx, *lane, n, ctx->shapes, totals);
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(ctx, hipMemcpyAsync(lane->d_jobs, lane->h_jobs, sizeof(DevJob) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(ctx, launch_pipeline(lane->d_jobs, lane->h_jobs[0], d, s, true, true,
-                                 next_events(ctx, true, true)));
+    if ((st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx)))) return st;
     HIP_TRY(ctx, hipEventRecord(lane->done, s));
     lane->used = true;
     lane->ticket = (ctx->next_ticket++ << 8) | (uint64_t)lane_id;
@@ -735,7 +850,7 @@ ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done)
     if (st) return st;
     if (!done) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "poll: null done");
     const size_t lane_id = ticket & 0xFF;
-    if (lane_id >= ctx->lanes.size() || ticket == 0)
+    if (lane_id >= ctx->lanes.size() || ticket == 0 || (ticket >> 8) >= ctx->next_ticket)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "poll: unknown ticket");
     Lane &ln = ctx->lanes[lane_id];
     if (ln.ticket != ticket) {  // the lane was reused, so this ticket completed earlier
@@ -754,11 +869,82 @@ ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket)
     ft_status st = enter(ctx);
     if (st) return st;
     const size_t lane_id = ticket & 0xFF;
-    if (lane_id >= ctx->lanes.size() || ticket == 0)
+    if (lane_id >= ctx->lanes.size() || ticket == 0 || (ticket >> 8) >= ctx->next_ticket)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "wait: unknown ticket");
     Lane &ln = ctx->lanes[lane_id];
     if (ln.ticket != ticket) return FT_OK;
     HIP_TRY(ctx, hipEventSynchronize(ln.done));
+    return FT_OK;
+}
+
+ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
+                      const char *cache_path, ft_shapes *chosen)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!jobs || n <= 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "autotune: bad arguments");
+    if (n > ctx->lim.max_batch_frames)
+        return fail(ctx, FT_ERR_CAPACITY, "autotune: %d frames exceed max_batch_frames %d", n,
+                    ctx->lim.max_batch_frames);
+    hipDeviceProp_t prop;
+    HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    const std::string key = workload_key(jobs, n, prop.gcnArchName);
+    Shapes best = ctx->shapes;
+    if (cache_path && cache_lookup(cache_path, key, best)) {
+        ctx->shapes = best;
+    } else {
+        hipStream_t s = (hipStream_t)stream;
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        int lane_id = -1;
+        Lane *lane = free_lane(ctx, &lane_id, &st);
+        if (!lane) return st;
+        if ((st = build_batch(ctx, *lane, jobs, n))) return st;
+        const bool was_timing = ctx->timing;
+        if ((st = set_timing(ctx, true))) return st;
+        double ms[kPhases];
+        int64_t cnt[kPhases];
+        read_timing(ctx, ms, cnt);   // start from zero
+        // one phase for one candidate: 1 warm-up + 3 timed runs, median
+        auto time_phase = [&](const Shapes &sh, int phase, double *us) -> ft_status {
+            std::vector<double> v;
+            for (int r = 0; r < 4; ++r) {
+                int32_t totals[PH_COUNT];
+                plan_batch(ctx, *lane, n, sh, totals);
+                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx));
+                if (e) return e;
+                HIP_TRY(ctx, hipStreamSynchronize(s));
+                read_timing(ctx, ms, cnt);
+                if (r > 0) v.push_back(ms[phase] * 1e3);
+            }
+            std::sort(v.begin(), v.end());
+            *us = v[v.size() / 2];
+            return FT_OK;
+        };
+        const int cands[] = {1, 2, 4, 8, 16};
+        double best_a = 1e30, best_s = 1e30;
+        for (int g : cands) {
+            Shapes sh = best;
+            sh.best_lanes = g;
+            double us;
+            if ((st = time_phase(sh, PH_STEREO_A, &us))) return st;
+            if (us < best_a) { best_a = us; best.best_lanes = g; }
+        }
+        for (int g : cands) {
+            Shapes sh = best;
+            sh.search_lanes = g;
+            double us;
+            if ((st = time_phase(sh, PH_SEARCH, &us))) return st;
+            if (us < best_s) { best_s = us; best.search_lanes = g; }
+        }
+        set_timing(ctx, was_timing);
+        ctx->shapes = best;
+        if (cache_path && !cache_append(cache_path, key, best, best_a + best_s))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "autotune: cannot write %s", cache_path);
+    }
+    if (chosen) {
+        chosen->best_lanes = ctx->shapes.best_lanes;
+        chosen->search_lanes = ctx->shapes.search_lanes;
+    }
     return FT_OK;
 }
 

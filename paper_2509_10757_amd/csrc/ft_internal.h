@@ -12,19 +12,36 @@ namespace ft {
 
 constexpr int kLevels = FT_LEVELS;
 constexpr int kWG = 256;              // every kernel runs 256-thread workgroups (4 wave64s)
-constexpr int kRowsPerKpCap = 48;     // row-index entries per right keypoint (band <= 6.2 px at sf 3.58)
 constexpr int kMaxRows = 4096;
 constexpr int kMaxCells = 8192;
 constexpr int kMaxKp = 65535;
 constexpr int kMaxMap = (1 << 23) - 1;
-constexpr int kKnnQueriesPerWG = 64;  // fisheye all-pairs: 4 waves x 16 query rows
+constexpr int kKnnQueriesPerWG = 16;  // fisheye all-pairs: one 16-row MFMA block per workgroup
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
+constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
+
+enum Phase : int { PH_SETUP = 0, PH_STEREO_A, PH_STEREO_B, PH_STEREO_C, PH_SEARCH, PH_SEARCH_FIN, PH_COUNT };
 
 enum JobFlags : int32_t {
     JOB_STEREO_PINHOLE = 1,
     JOB_STEREO_FISHEYE = 2,
     JOB_SEARCH0 = 4,
     JOB_SEARCH1 = 8,
+};
+
+// Right keypoint sorted by integer row (pinhole row index): 16 bytes.
+struct RowRec {
+    float x;
+    uint32_t band;   // rows lo | hi << 16 covered by the keypoint's band (empty: lo > hi)
+    uint32_t meta;   // octave | index << 16
+    uint32_t pad;
+};
+
+// Keypoint sorted by grid cell (search by projection): 16 bytes + descriptor.
+struct CellRec {
+    float x, y;
+    uint32_t meta;   // octave | preassigned << 8 | index << 16
+    uint32_t pad;
 };
 
 struct DevKps {
@@ -47,13 +64,17 @@ struct DevView {
     const float *u_right;            // nullable
     int32_t *mp_match, *mp_dist, *kp_match, *n_matches;
     // workspace
-    int32_t *cell_off, *cell_items, *mp_k, *mp_h;
+    int32_t *cell_off;
+    CellRec *crec;
+    uint8_t *cdesc;
+    int32_t *mp_k, *mp_h;
     uint32_t *claim;
 };
 
 struct DevJob {
     int32_t flags;
     int32_t nM;
+    int32_t n_views;
     DevKps L, R;
     float sf[kLevels], inv_sf[kLevels], sigma2[kLevels];
     // pinhole stereo
@@ -61,7 +82,7 @@ struct DevJob {
     int64_t lv_off[kLevels];
     int32_t lv_w[kLevels], lv_h[kLevels];
     float bf, maxD, band;
-    int32_t rows;
+    int32_t rows, row_reach;          // bins scanned on each side of a query row
     int32_t th_orb, half_win, half_range, level_window, med_num, med_den;
     // fisheye stereo
     float kbL[8], kbR[8], R_lr[9], t_lr[3], ovl[2], ovr[2];
@@ -71,10 +92,12 @@ struct DevJob {
     int32_t *o_right_idx, *o_dist, *o_sad, *o_nmatch;
     float *o_uR, *o_depth, *o_xyz;
     // stereo workspace
-    int32_t *row_off, *row_items, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    int32_t *row_start;               // rows + 1
+    RowRec *rrec;                     // right keypoints sorted by row
+    uint8_t *tdesc;                   // fisheye: target descriptors in overlap order
+    int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
     float *uR, *depth, *xyz;
     uint32_t *claimR;
-    int32_t row_items_cap;
     // search by projection
     const float *pos, *normal, *dmin, *dmax;
     const uint8_t *mdesc;
@@ -83,23 +106,32 @@ struct DevJob {
     DevView view[2];
 };
 
-// Launch geometry of one submission (single frame or batch).
-struct LaunchDims {
-    int n_jobs;
-    int tiles_stereo_a;   // best-match tiles (pinhole: 256 queries, fisheye: 64 queries)
-    int tiles_stereo_b;   // refine / triangulation tiles
-    int tiles_stereo_c;   // final stereo tiles
-    int tiles_search;     // map-point tiles per view
-    int tiles_search_fin; // max(map, keypoint) tiles per view
-    int setup_x;          // 1 + number of views needing a grid
+// Launch shapes of one submission (the autotuner chooses the lane groups).
+struct Shapes {
+    int best_lanes = 8;    // lanes cooperating on one pinhole left keypoint
+    int search_lanes = 4;  // lanes cooperating on one map point
 };
+
+// Tiles of each phase for each job, as prefix sums: batch launches map a flat
+// block index to (job, tile) with a binary search over them.
+struct TileMap {
+    int32_t n_jobs;
+    const int32_t *prefix;  // device [PH_COUNT][n_jobs + 1]
+};
+
+// Per-job tile counts of each phase for the given shapes.
+void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search,
+               int32_t out[PH_COUNT]);
 
 // Optional per-phase event timing: when `ev` is non-null, ev[p] and ev[p+1]
 // bracket phase p on the launch stream (ev has kPhases + 1 events).
 constexpr int kPhases = FT_PHASES;
 
-// Launchers (ft_kernels.hip).  `table` == nullptr means: use `one` by value.
-hipError_t launch_pipeline(const DevJob *table, const DevJob &one, const LaunchDims &d,
-                           hipStream_t stream, bool do_stereo, bool do_search, hipEvent_t *ev);
+// Launchers (ft_kernels.hip).  `table` == nullptr: one job passed by value;
+// otherwise a device job table whose flat tiles are described by `map`.
+// `totals` holds the number of workgroups of each phase.
+hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
+                           const DevJob &one, const Shapes &shapes, hipStream_t stream,
+                           bool do_stereo, bool do_search, hipEvent_t *ev);
 
 }  // namespace ft

@@ -7,16 +7,24 @@
 // exactly as written) with correctly rounded fp32 divide and sqrt.
 //
 // Phases per frame (Section IV-C and IV-E of the paper):
-//   setup      row index of right keypoints (pinhole) | overlap lists (fisheye)
-//              + per-view keypoint grids; clears claim tables and counters
-//   stereo_a   pinhole best match per left keypoint (row band, xor+popcount)
+//   setup      counting sort of right keypoints by row (pinhole) | overlap
+//              lists + packed target descriptors (fisheye); counting sort of
+//              each view's keypoints by grid cell into packed records; clears
+//              claim tables and counters
+//   stereo_a   pinhole best match: G lanes per left keypoint stream the
+//              row-sorted records of the rows that can hold a match
 //              | fisheye all-pairs top-2 on the matrix cores (int8 +-1 MFMA)
-//   stereo_b   pinhole SAD refinement, one wave per match
+//   stereo_b   pinhole SAD refinement, one wave per match, patches in LDS
 //              | fisheye ratio + triangulation check (float64)
 //   stereo_c   pinhole duplicate resolution + median filter + outputs
 //              | fisheye duplicate resolution + outputs
-//   search     projection + windowed best/second search, thread per map point
+//   search     projection + window search: G lanes per map point stream the
+//              cell-sorted keypoint records of the window's cells
 //   search_fin duplicate resolution + outputs
+//
+// Batched submissions flatten every phase's tiles over the jobs; the flat
+// block index is first remapped so that consecutive tiles (one frame's data)
+// land on the same XCD and share its L2.
 
 #include <hip/hip_runtime.h>
 
@@ -49,7 +57,41 @@ __device__ __forceinline__ int hamming(const Desc &u, const Desc &v)
 
 // Pyramid level of a keypoint as a table index (levels are 0..7 by contract;
 // the clamp only keeps a malformed octave byte inside the tables).
-__device__ __forceinline__ int lvl(uint8_t o) { return o < kLevels ? (int)o : kLevels - 1; }
+__device__ __forceinline__ int lvl(uint32_t o) { return o < (uint32_t)kLevels ? (int)o : kLevels - 1; }
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, m);
+    const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The two smallest keys seen so far (by value, so they stay in registers).
+template <class T>
+struct Top2 {
+    T a, b;
+};
+
+template <class T>
+__device__ __forceinline__ Top2<T> top2_insert(Top2<T> t, T key)
+{
+    const bool lt1 = key < t.a, lt2 = key < t.b;
+    Top2<T> r;
+    r.b = lt1 ? t.a : (lt2 ? key : t.b);
+    r.a = lt1 ? key : t.a;
+    return r;
+}
+
+template <class T>
+__device__ __forceinline__ Top2<T> top2_merge(Top2<T> t, T o1, T o2)
+{
+    Top2<T> r;
+    const T hi = t.a < o1 ? o1 : t.a;
+    const T m2 = t.b < o2 ? t.b : o2;
+    r.a = t.a < o1 ? t.a : o1;
+    r.b = hi < m2 ? hi : m2;
+    return r;
+}
 
 // Workgroup-wide exclusive scan of a[0..n) in LDS; returns the total.
 __device__ int wg_exclusive_scan(int *a, int n, int *tmp)
@@ -78,19 +120,6 @@ __device__ int wg_exclusive_scan(int *a, int n, int *tmp)
     return total;
 }
 
-// Rows [lo, hi] of the row index covered by a right keypoint; false if none.
-__device__ __forceinline__ bool band_rows(const DevJob &J, int j, int &lo, int &hi)
-{
-    const float y = J.R.y[j];
-    const float r = J.band * J.sf[lvl(J.R.oct[j])];
-    const float flo = floorf(y - r);
-    const float fhi = ceilf(y + r);
-    if (!(fhi >= 0.0f) || !(flo <= (float)(J.rows - 1))) return false;
-    lo = flo < 0.0f ? 0 : (int)flo;
-    hi = fhi > (float)(J.rows - 1) ? J.rows - 1 : (int)fhi;
-    return lo <= hi;
-}
-
 __device__ __forceinline__ int cell_coord(float v, float lo, float inv, int n)
 {
     const float f = (v - lo) * inv;
@@ -99,31 +128,51 @@ __device__ __forceinline__ int cell_coord(float v, float lo, float inv, int n)
     return (int)f;
 }
 
-// ------------------------------------------------ setup: row index (pinhole)
-__device__ void ph_rowband(const DevJob &J, int *cnt, int *tmp)
+// ------------------------------------------------ setup: rows (pinhole)
+// Row bin of a right keypoint (clamped; non-finite rows go to bin 0).
+__device__ __forceinline__ int row_bin(float y, int rows)
+{
+    if (!(y >= 0.0f)) return 0;
+    if (!(y < (float)rows)) return rows - 1;
+    return (int)y;
+}
+
+// Packed rows [lo, hi] of the epipolar band of a right keypoint, or an empty
+// range (lo > hi).
+__device__ __forceinline__ uint32_t band_rows(const DevJob &J, float y, int oct)
+{
+    const float r = J.band * J.sf[lvl(oct)];
+    const float flo = floorf(y - r);
+    const float fhi = ceilf(y + r);
+    if (!(fhi >= 0.0f) || !(flo <= (float)(J.rows - 1))) return 0xFFFFu;  // lo = 65535 > hi = 0
+    const int lo = flo < 0.0f ? 0 : (int)flo;
+    const int hi = fhi > (float)(J.rows - 1) ? J.rows - 1 : (int)fhi;
+    return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
+__device__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
     const int rows = J.rows, nR = J.R.n;
     for (int r = tid; r < rows; r += kWG) cnt[r] = 0;
     for (int j = tid; j < nR; j += kWG) J.claimR[j] = 0xFFFFFFFFu;
     __syncthreads();
-    for (int j = tid; j < nR; j += kWG) {
-        int lo, hi;
-        if (!band_rows(J, j, lo, hi)) continue;
-        for (int r = lo; r <= hi; ++r) atomicAdd(&cnt[r], 1);
-    }
+    for (int j = tid; j < nR; j += kWG) atomicAdd(&cnt[row_bin(J.R.y[j], rows)], 1);
     __syncthreads();
     const int total = wg_exclusive_scan(cnt, rows, tmp);
-    for (int r = tid; r < rows; r += kWG) J.row_off[r] = cnt[r];
-    if (tid == 0) J.row_off[rows] = min(total, J.row_items_cap);
+    for (int r = tid; r < rows; r += kWG) J.row_start[r] = cnt[r];
+    if (tid == 0) J.row_start[rows] = total;
     __syncthreads();
     for (int j = tid; j < nR; j += kWG) {
-        int lo, hi;
-        if (!band_rows(J, j, lo, hi)) continue;
-        for (int r = lo; r <= hi; ++r) {
-            const int pos = atomicAdd(&cnt[r], 1);
-            if (pos < J.row_items_cap) J.row_items[pos] = j;
-        }
+        const float y = J.R.y[j];
+        const int oct = J.R.oct[j];
+        const int pos = atomicAdd(&cnt[row_bin(y, rows)], 1);
+        RowRec rec;
+        rec.x = J.R.x[j];
+        rec.band = band_rows(J, y, oct);
+        rec.meta = (uint32_t)oct | ((uint32_t)j << 16);
+        rec.pad = 0;
+        J.rrec[pos] = rec;
     }
 }
 
@@ -156,6 +205,10 @@ __device__ void ph_overlap(const DevJob &J, int *wsum)
     for (int i = tid; i < J.L.n; i += kWG) J.flag[i] = 0;
     const int nQ = compact_range(J.L.x, J.L.n, J.ovl[0], J.ovl[1], J.qlist, wsum);
     const int nT = compact_range(J.R.x, J.R.n, J.ovr[0], J.ovr[1], J.tlist, wsum);
+    // targets' descriptors in overlap order: one 16-byte half per thread step
+    const uint4 *src = reinterpret_cast<const uint4 *>(J.R.desc);
+    uint4 *dst = reinterpret_cast<uint4 *>(J.tdesc);
+    for (int h = tid; h < 2 * nT; h += kWG) dst[h] = src[2 * J.tlist[h >> 1] + (h & 1)];
     if (tid == 0) {
         J.counts[0] = nQ;
         J.counts[1] = nT;
@@ -164,7 +217,7 @@ __device__ void ph_overlap(const DevJob &J, int *wsum)
 }
 
 // ------------------------------------------------ setup: keypoint grid
-__device__ void ph_grid(const DevView &V, const DevKps &K, int *cnt, int *tmp)
+__device__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
     const int cells = V.cols * V.rows;
@@ -182,190 +235,213 @@ __device__ void ph_grid(const DevView &V, const DevKps &K, int *cnt, int *tmp)
     for (int c = tid; c < cells; c += kWG) V.cell_off[c] = cnt[c];
     if (tid == 0) V.cell_off[cells] = total;
     __syncthreads();
+    const uint4 *dsrc = reinterpret_cast<const uint4 *>(K.desc);
+    uint4 *ddst = reinterpret_cast<uint4 *>(V.cdesc);
     for (int k = tid; k < K.n; k += kWG) {
-        const int cx = cell_coord(K.x[k], V.min_x, V.inv_cw, V.cols);
-        const int cy = cell_coord(K.y[k], V.min_y, V.inv_ch, V.rows);
+        const float x = K.x[k], y = K.y[k];
+        const int cx = cell_coord(x, V.min_x, V.inv_cw, V.cols);
+        const int cy = cell_coord(y, V.min_y, V.inv_ch, V.rows);
         const int pos = atomicAdd(&cnt[cy * V.cols + cx], 1);
-        V.cell_items[pos] = k;
+        const uint32_t pre = (V.preassigned && V.preassigned[k]) ? 1u : 0u;
+        CellRec rec;
+        rec.x = x;
+        rec.y = y;
+        rec.meta = (uint32_t)K.oct[k] | (pre << 8) | ((uint32_t)k << 16);
+        rec.pad = 0;
+        V.crec[pos] = rec;
+        ddst[2 * pos] = dsrc[2 * k];
+        ddst[2 * pos + 1] = dsrc[2 * k + 1];
     }
 }
 
 // ------------------------------------- stereo_a (pinhole): row-band best match
+// G lanes per left keypoint.  The candidates of row r are the right keypoints
+// whose band covers r; their integer rows lie within J.row_reach of r, so the
+// lanes stream the row-sorted records of those bins and test the band exactly.
+template <int G>
 __device__ void ph_best(const DevJob &J, int tile)
 {
-    const int i = tile * kWG + threadIdx.x;
-    if (i >= J.L.n) return;
-    int bj = -1, bh = 1 << 20;
-    const float y = J.L.y[i];
-    const float x = J.L.x[i];
-    const float minU = x - J.maxD;
-    const float maxU = x - 0.0f;
-    if (y > -1.0f && y < (float)J.rows && !(maxU < 0.0f)) {
-        const int row = (int)y;
-        const int oi = J.L.oct[i];
-        const Desc di = load_desc(J.L.desc, i);
-        const int e = min(J.row_off[row + 1], J.row_items_cap);
-        for (int idx = J.row_off[row]; idx < e; ++idx) {
-            const int j = J.row_items[idx];
-            const int oj = J.R.oct[j];
-            if (oj < oi - J.level_window || oj > oi + J.level_window) continue;
-            const float xj = J.R.x[j];
-            if (!(xj >= minU && xj <= maxU)) continue;
-            const int h = hamming(di, load_desc(J.R.desc, j));
-            if (h < bh || (h == bh && j < bj)) {
-                bh = h;
-                bj = j;
+    const int sub = threadIdx.x % G;
+    const int i = tile * (kWG / G) + threadIdx.x / G;
+    uint32_t best = 0xFFFFFFFFu;   // Hamming << 16 | right index
+    if (i < J.L.n) {
+        const float y = J.L.y[i];
+        const float x = J.L.x[i];
+        const float minU = x - J.maxD;
+        const float maxU = x - 0.0f;
+        if (y > -1.0f && y < (float)J.rows && !(maxU < 0.0f)) {
+            const int row = (int)y;
+            const int oi = J.L.oct[i];
+            const Desc di = load_desc(J.L.desc, i);
+            const int b0 = max(row - J.row_reach, 0);
+            const int b1 = min(row + J.row_reach, J.rows - 1);
+            const int p1 = J.row_start[b1 + 1];
+            for (int p = J.row_start[b0] + sub; p < p1; p += G) {
+                const RowRec rec = J.rrec[p];
+                const int lo = (int)(rec.band & 0xFFFFu), hi = (int)(rec.band >> 16);
+                if (row < lo || row > hi) continue;
+                const int oj = (int)(rec.meta & 0xFFu);
+                if (oj < oi - J.level_window || oj > oi + J.level_window) continue;
+                if (!(rec.x >= minU && rec.x <= maxU)) continue;
+                const uint32_t j = rec.meta >> 16;
+                const uint32_t key = ((uint32_t)hamming(di, load_desc(J.R.desc, (int)j)) << 16) | j;
+                best = key < best ? key : best;
             }
         }
     }
-    const bool ok = bj >= 0 && bh < J.th_orb;
-    J.best_j[i] = ok ? bj : -1;
-    J.best_h[i] = ok ? bh : -1;
+    for (int m = 1; m < G; m <<= 1) {
+        const uint32_t o = __shfl_xor(best, m);
+        best = o < best ? o : best;
+    }
+    if (sub == 0 && i < J.L.n) {
+        const int h = (int)(best >> 16);
+        const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
+        J.best_j[i] = ok ? (int)(best & 0xFFFFu) : -1;
+        J.best_h[i] = ok ? h : -1;
+    }
 }
 
 // ----------------------------- stereo_a (fisheye): all-pairs top-2 on MFMA
-// Expand one descriptor byte to eight signed bytes: bit t -> byte t, 1 -> +1,
-// 0 -> -1.  Then H(a, b) = (256 - <a, b>) / 2 exactly for the +-1 vectors.
-__device__ __forceinline__ uint64_t pm1_bytes(uint32_t b)
+// H(a, b) = (256 - <a, b>) / 2 for the +-1 expansions of two descriptors.
+// A workgroup owns 16 queries (one MFMA row block); its four waves take every
+// fourth 16-target tile; partial top-2 lists are merged in LDS.  Each lane
+// group g (lanes 16g..16g+15) supplies descriptor bytes 8g..8g+7 over the four
+// K-steps of v_mfma_i32_16x16x64_i8 (two bytes = sixteen int8 per step); the A
+// and B operands use the same byte-to-K assignment, so the dot product is the
+// full 256-term sum whatever order the hardware sums K in.
+__device__ void ph_knn(const DevJob &J, int tile, uint64_t *tab, uint32_t *part)
 {
-    uint64_t x = (uint64_t)(b & 0xFFu) * 0x0101010101010101ull;
-    x &= 0x8040201008040201ull;
-    x = ((x + 0x7F7F7F7F7F7F7F7Full) >> 7) & 0x0101010101010101ull;
-    return ~(x * 0xFEull);
-}
-
-// Operand of K-step s for lane group g: descriptor bytes 8s + 2g and 8s + 2g + 1.
-// Any assignment of descriptor bits to (lane group, byte) works as long as the
-// A and B operands use the same one, because the dot product sums over K.
-__device__ __forceinline__ v4i pm1_operand(const Desc &d, int s, int g)
-{
-    const uint32_t w[8] = {d.a.x, d.a.y, d.a.z, d.a.w, d.b.x, d.b.y, d.b.z, d.b.w};
-    const int byte0 = 8 * s + 2 * g;
-    const uint32_t word = w[byte0 >> 2];
-    const int sh = (byte0 & 3) * 8;
-    const uint64_t lo = pm1_bytes(word >> sh);
-    const uint64_t hi = pm1_bytes(word >> (sh + 8));
-    v4i r;
-    r.x = (int)(uint32_t)lo;
-    r.y = (int)(uint32_t)(lo >> 32);
-    r.z = (int)(uint32_t)hi;
-    r.w = (int)(uint32_t)(hi >> 32);
-    return r;
-}
-
-__device__ __forceinline__ void top2_insert(uint32_t key, uint32_t &k1, uint32_t &k2)
-{
-    if (key < k1) {
-        k2 = k1;
-        k1 = key;
-    } else if (key < k2) {
-        k2 = key;
+    const int tid = threadIdx.x;
+    // +-1 expansion of every byte value: bit t -> byte t, 1 -> +1, 0 -> -1
+    {
+        uint64_t e = 0;
+        for (int t = 0; t < 8; ++t) e |= (uint64_t)(((tid >> t) & 1) ? 0x01u : 0xFFu) << (8 * t);
+        tab[tid] = e;
     }
-}
-
-__device__ void ph_knn(const DevJob &J, int tile)
-{
+    __syncthreads();
     const int nQ = J.counts[0], nT = J.counts[1];
-    const int q0 = tile * kKnnQueriesPerWG + (threadIdx.x >> 6) * 16;
-    if (q0 >= nQ || nT < 2) return;
-    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-    const int qa = q0 + c;
+    const int q0 = tile * kKnnQueriesPerWG;
+    if (q0 >= nQ || nT < 2) return;   // uniform over the workgroup
+    const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
     v4i A[4];
-    if (qa < nQ) {
-        const Desc dq = load_desc(J.L.desc, J.qlist[qa]);
-        for (int s = 0; s < 4; ++s) A[s] = pm1_operand(dq, s, g);
-    } else {
-        for (int s = 0; s < 4; ++s) A[s] = v4i{0, 0, 0, 0};
+    {
+        const int qa = q0 + c;
+        uint2 w = make_uint2(0, 0);
+        if (qa < nQ) w = *reinterpret_cast<const uint2 *>(J.L.desc + 32 * (size_t)J.qlist[qa] + 8 * g);
+        _Pragma("unroll") for (int s = 0; s < 4; ++s) {
+            const uint32_t word = s < 2 ? w.x : w.y;
+            const uint64_t lo = tab[(word >> (16 * (s & 1))) & 0xFF];
+            const uint64_t hi = tab[(word >> (16 * (s & 1) + 8)) & 0xFF];
+            A[s] = qa < nQ ? v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
+                                 (int)(uint32_t)(hi >> 32)}
+                           : v4i{0, 0, 0, 0};
+        }
     }
-    uint32_t k1[4], k2[4];
-    for (int r = 0; r < 4; ++r) k1[r] = k2[r] = 0xFFFFFFFFu;
-    for (int t0 = 0; t0 < nT; t0 += 16) {
-        const int tj = t0 + c;
+    Top2<uint32_t> t0 = {0xFFFFFFFFu, 0xFFFFFFFFu}, t1 = t0, t2 = t0, t3 = t0;
+    const int n_tiles = (nT + 15) >> 4;
+    for (int t = wave; t < n_tiles; t += 4) {
+        const int tj = (t << 4) + c;
         const bool tv = tj < nT;
-        const int j = tv ? J.tlist[tj] : 0;
-        v4i B[4];
-        if (tv) {
-            const Desc dt = load_desc(J.R.desc, j);
-            for (int s = 0; s < 4; ++s) B[s] = pm1_operand(dt, s, g);
-        } else {
-            for (int s = 0; s < 4; ++s) B[s] = v4i{0, 0, 0, 0};
-        }
+        uint2 w = make_uint2(0, 0);
+        if (tv) w = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)tj + 8 * g);
         v4i acc = {0, 0, 0, 0};
-        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[s], B[s], acc, 0, 0, 0);
-        // acc[r] = dot(query row 4g + r, target column c)
+        _Pragma("unroll") for (int s = 0; s < 4; ++s) {
+            const uint32_t word = s < 2 ? w.x : w.y;
+            const uint64_t lo = tab[(word >> (16 * (s & 1))) & 0xFF];
+            const uint64_t hi = tab[(word >> (16 * (s & 1) + 8)) & 0xFF];
+            const v4i B = tv ? v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
+                                   (int)(uint32_t)(hi >> 32)}
+                             : v4i{0, 0, 0, 0};
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[s], B, acc, 0, 0, 0);
+        }
+        // acc[r] = dot(query row 4g + r, target column c); targets are in index order
         if (tv) {
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t h = (uint32_t)((256 - acc[r]) >> 1);
-                top2_insert((h << 16) | (uint32_t)j, k1[r], k2[r]);
-            }
+            const uint32_t col = (uint32_t)tj;
+            t0 = top2_insert(t0, ((uint32_t)((256 - acc[0]) >> 1) << 16) | col);
+            t1 = top2_insert(t1, ((uint32_t)((256 - acc[1]) >> 1) << 16) | col);
+            t2 = top2_insert(t2, ((uint32_t)((256 - acc[2]) >> 1) << 16) | col);
+            t3 = top2_insert(t3, ((uint32_t)((256 - acc[3]) >> 1) << 16) | col);
         }
     }
-    for (int r = 0; r < 4; ++r) {
-        for (int m = 1; m < 16; m <<= 1) {
-            const uint32_t o1 = __shfl_xor(k1[r], m);
-            const uint32_t o2 = __shfl_xor(k2[r], m);
-            const uint32_t lo = min(k1[r], o1), hi = max(k1[r], o1);
-            k2[r] = min(hi, min(k2[r], o2));
-            k1[r] = lo;
-        }
+    _Pragma("unroll") for (int m = 1; m < 16; m <<= 1) {
+        t0 = top2_merge(t0, __shfl_xor(t0.a, m), __shfl_xor(t0.b, m));
+        t1 = top2_merge(t1, __shfl_xor(t1.a, m), __shfl_xor(t1.b, m));
+        t2 = top2_merge(t2, __shfl_xor(t2.a, m), __shfl_xor(t2.b, m));
+        t3 = top2_merge(t3, __shfl_xor(t3.a, m), __shfl_xor(t3.b, m));
     }
     if (c == 0) {
-        for (int r = 0; r < 4; ++r) {
-            const int q = q0 + 4 * g + r;
-            if (q >= nQ) continue;
-            const int i = J.qlist[q];
-            J.best_j[i] = (int)(k1[r] & 0xFFFFu);
-            J.best_h[i] = (int)(k1[r] >> 16);
-            J.h2[i] = (int)(k2[r] >> 16);
-        }
+        uint32_t *pw = part + (wave * 16 + 4 * g) * 2;
+        pw[0] = t0.a; pw[1] = t0.b; pw[2] = t1.a; pw[3] = t1.b;
+        pw[4] = t2.a; pw[5] = t2.b; pw[6] = t3.a; pw[7] = t3.b;
+    }
+    __syncthreads();
+    if (tid < 16 && q0 + tid < nQ) {
+        Top2<uint32_t> t = {part[tid * 2], part[tid * 2 + 1]};
+        for (int w = 1; w < 4; ++w) t = top2_merge(t, part[(w * 16 + tid) * 2], part[(w * 16 + tid) * 2 + 1]);
+        const int i = J.qlist[q0 + tid];
+        J.best_j[i] = J.tlist[t.a & 0xFFFFu];
+        J.best_h[i] = (int)(t.a >> 16);
+        J.h2[i] = (int)(t.b >> 16);
     }
 }
 
 // ------------------------------------- stereo_b (pinhole): SAD refinement
-__device__ void ph_refine(const DevJob &J, int tile)
+// One wave per match.  The wave stages the left patch and the right strip of
+// the left keypoint's level in LDS, then 64 lanes split the (shift, row) sums.
+__device__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
 {
-    const int lane = threadIdx.x & 63;
-    const int i = tile * kRefinePerWG + (threadIdx.x >> 6);
-    if (i >= J.L.n) return;
-    const int j = J.best_j[i];
-    if (j < 0) {
-        if (lane == 0) J.flag[i] = 0;
-        return;
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = tile * kRefinePerWG + wave;
     const int w = J.half_win, L = J.half_range;
-    const int l = lvl(J.L.oct[i]);
-    const float s = J.inv_sf[l];
-    const int su = (int)roundf(J.L.x[i] * s);
-    const int sv = (int)roundf(J.L.y[i] * s);
-    const int su0 = (int)roundf(J.R.x[j] * s);
-    const int Wl = J.lv_w[l], Hl = J.lv_h[l];
-    if (su - w < 0 || su + w >= Wl || sv - w < 0 || sv + w >= Hl || su0 - L - w < 0 ||
-        su0 + L + w >= Wl) {
-        if (lane == 0) J.flag[i] = 0;
-        return;
+    const int side = 2 * w + 1, strip = 2 * (L + w) + 1, nS = 2 * L + 1;
+    int j = -1, l = 0, su = 0, sv = 0, su0 = 0, Wl = 0;
+    bool act = false;
+    if (i < J.L.n) {
+        j = J.best_j[i];
+        if (j >= 0) {
+            l = lvl(J.L.oct[i]);
+            const float s = J.inv_sf[l];
+            su = (int)roundf(J.L.x[i] * s);
+            sv = (int)roundf(J.L.y[i] * s);
+            su0 = (int)roundf(J.R.x[j] * s);
+            Wl = J.lv_w[l];
+            const int Hl = J.lv_h[l];
+            act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
+                  su0 + L + w < Wl;
+        }
     }
-    const uint8_t *IL = J.pyrL + J.lv_off[l];
-    const uint8_t *IR = J.pyrR + J.lv_off[l];
-    const int nS = 2 * L + 1;          // shifts
-    const int parts = 64 / nS;         // lanes per shift
-    const int side = 2 * w + 1;
+    uint8_t *P = lds + wave * kRefineLds;          // left patch [side][side]
+    uint8_t *S = P + side * side;                  // right strip [side][strip]
+    if (act) {
+        const uint8_t *IL = J.pyrL + J.lv_off[l];
+        const uint8_t *IR = J.pyrR + J.lv_off[l];
+        const int nP = side * side, n = nP + side * strip;
+        for (int e = lane; e < n; e += 64) {
+            if (e < nP) {
+                const int r = e / side, c = e - r * side;
+                P[e] = IL[(size_t)(sv - w + r) * Wl + su - w + c];
+            } else {
+                const int e2 = e - nP, r = e2 / strip, c = e2 - r * strip;
+                P[e] = IR[(size_t)(sv - w + r) * Wl + su0 - L - w + c];
+            }
+        }
+    }
+    __syncthreads();
+    const int parts = 64 / nS;
     const int k_idx = lane / parts, part = lane - k_idx * parts;
     int acc = 0;
-    if (k_idx < nS) {
-        const int k = k_idx - L;
-        const int cL = IL[(size_t)sv * Wl + su];
-        const int cR = IR[(size_t)sv * Wl + su0 + k];
-        for (int dyi = part; dyi < side; dyi += parts) {
-            const uint8_t *pl = IL + (size_t)(sv + dyi - w) * Wl + su - w;
-            const uint8_t *pr = IR + (size_t)(sv + dyi - w) * Wl + su0 + k - w;
+    if (act && k_idx < nS) {
+        const int cL = P[w * side + w];
+        const int cR = S[w * strip + k_idx + w];
+        for (int r = part; r < side; r += parts) {
+            const uint8_t *pl = P + r * side;
+            const uint8_t *pr = S + r * strip + k_idx;
             for (int dx = 0; dx < side; ++dx) acc += abs(((int)pl[dx] - cL) - ((int)pr[dx] - cR));
         }
     }
-    // sum the `parts` partial sums of each shift into the first lane of its group
     int tot = acc;
     for (int p = 1; p < parts; ++p) tot += __shfl(acc, min(lane + p, 63));
-    // gather the profile in every lane (all lanes take part in the shuffles);
-    // ties go to the smaller shift; lane 0 then decides
+    // every lane takes part in the shuffles; ties go to the smaller shift
     int best = 0x7FFFFFFF, kb = -L;
     for (int kk = 0; kk < nS; ++kk) {
         const int v = __shfl(tot, kk * parts);
@@ -376,12 +452,12 @@ __device__ void ph_refine(const DevJob &J, int tile)
     }
     const int a = __shfl(tot, max(kb + L - 1, 0) * parts);
     const int e = __shfl(tot, min(kb + L + 1, nS - 1) * parts);
-    const int c = best;
-    if (lane != 0) return;
-    if (kb == -L || kb == L) {
+    if (lane != 0 || i >= J.L.n) return;
+    if (!act || kb == -L || kb == L) {
         J.flag[i] = 0;
         return;
     }
+    const int c = best;
     const float num = (float)(a - e);
     const float den = (float)(2 * (a + e - 2 * c));
     const float delta = num / den;
@@ -408,14 +484,14 @@ __device__ void ph_refine(const DevJob &J, int tile)
 }
 
 // ------------------------------- stereo_b (fisheye): ratio + triangulation
-__device__ double kb_distort(const float *kb, double th)
+__device__ __forceinline__ double kb_distort(const float *kb, double th)
 {
     const double k1 = kb[4], k2 = kb[5], k3 = kb[6], k4 = kb[7];
     const double t2 = th * th, t4 = t2 * t2, t6 = t4 * t2, t8 = t4 * t4;
     return th * ((((1.0 + k1 * t2) + k2 * t4) + k3 * t6) + k4 * t8);
 }
 
-__device__ void kb_project(const float *kb, const double X[3], double uv[2])
+__device__ __forceinline__ void kb_project(const float *kb, const double X[3], double uv[2])
 {
     const double fx = kb[0], fy = kb[1], cx = kb[2], cy = kb[3];
     const double rho = sqrt(X[0] * X[0] + X[1] * X[1]);
@@ -430,7 +506,7 @@ __device__ void kb_project(const float *kb, const double X[3], double uv[2])
     uv[1] = fy * ((thd * X[1]) / rho) + cy;
 }
 
-__device__ bool kb_unproject(const float *kb, float u, float v, int iters, double tol,
+__device__ __forceinline__ bool kb_unproject(const float *kb, float u, float v, int iters, double tol,
                              double max_theta, double ray[3])
 {
     const double fx = kb[0], fy = kb[1], cx = kb[2], cy = kb[3];
@@ -463,7 +539,7 @@ __device__ bool kb_unproject(const float *kb, float u, float v, int iters, doubl
     return true;
 }
 
-__device__ double det3(const double m[3][3])
+__device__ __forceinline__ double det3(const double m[3][3])
 {
     return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
            m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
@@ -472,7 +548,7 @@ __device__ double det3(const double m[3][3])
 
 // Linear least-squares triangulation with the homogeneous coordinate fixed to
 // one; 3x3 normal equations solved by Cramer's rule (float64).
-__device__ bool triangulate(const double r1[3], const double r2[3], const float *R_lr,
+__device__ __forceinline__ bool triangulate(const double r1[3], const double r2[3], const float *R_lr,
                             const float *t_lr, double X[3])
 {
     double Rrl[3][3], trl[3];
@@ -559,60 +635,67 @@ __device__ void ph_tri(const DevJob &J, int tile)
 }
 
 // ---------------------- stereo_c (pinhole): conflicts + median + outputs
-__device__ __forceinline__ bool pinhole_survivor(const DevJob &J, int i)
+// The median is the value at rank n/2 of the survivors' 16-bit SADs, found by
+// a two-pass 8-bit radix select with a parallel prefix over the 256 bins.
+__device__ int select_bin(int *hist, int *tmp, int target, int *out_rank, int *found)
 {
-    if (!J.flag[i]) return false;
-    const int j = J.best_j[i];
-    return J.claimR[j] == (((uint32_t)J.best_h[i] << 23) | (uint32_t)i);
+    const int tid = threadIdx.x;
+    const int h = hist[tid];
+    wg_exclusive_scan(hist, 256, tmp);   // hist now holds exclusive prefixes
+    if (h > 0 && hist[tid] <= target && target < hist[tid] + h) {
+        found[0] = tid;
+        found[1] = target - hist[tid];
+    }
+    __syncthreads();
+    *out_rank = found[1];
+    const int b = found[0];
+    __syncthreads();
+    return b;
 }
 
-// Value at rank `target` (0-based, ascending) of the 16-bit SAD of survivors,
-// by a two-pass 8-bit radix select in LDS.
-__device__ void ph_median(const DevJob &J, int *hist, int *sh)
+__device__ __forceinline__ bool bit(const uint32_t *b, int i) { return (b[i >> 5] >> (i & 31)) & 1u; }
+
+__device__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, int *sh)
 {
     const int tid = threadIdx.x, nL = J.L.n;
-    if (tid < 256) hist[tid] = 0;
+    hist[tid] = 0;
     if (tid == 0) sh[0] = 0;
+    for (int w = tid; w < (nL + 31) / 32; w += kWG) surv[w] = 0;
     __syncthreads();
+    int my_n = 0;
     for (int i = tid; i < nL; i += kWG) {
-        if (pinhole_survivor(J, i)) {
-            atomicAdd(&sh[0], 1);
+        bool s = false;
+        if (J.flag[i]) {
+            const int j = J.best_j[i];
+            s = J.claimR[j] == (((uint32_t)J.best_h[i] << 23) | (uint32_t)i);
+        }
+        if (s) {
+            atomicOr(&surv[i >> 5], 1u << (i & 31));
+            ++my_n;
             atomicAdd(&hist[(J.sad[i] >> 8) & 0xFF], 1);
         }
     }
+    atomicAdd(&sh[0], my_n);
     __syncthreads();
     const int n = sh[0];
-    if (tid == 0) {
-        int target = n / 2, acc = 0, bin = 0;
-        for (; bin < 256; ++bin) {
-            if (acc + hist[bin] > target) break;
-            acc += hist[bin];
-        }
-        sh[1] = bin;
-        sh[2] = target - acc;
+    int m = 0;
+    if (n > 0) {
+        int rank;
+        const int hb = select_bin(hist, tmp, n / 2, &rank, sh + 2);
+        hist[tid] = 0;
+        __syncthreads();
+        for (int i = tid; i < nL; i += kWG)
+            if (bit(surv, i) && ((J.sad[i] >> 8) & 0xFF) == hb) atomicAdd(&hist[J.sad[i] & 0xFF], 1);
+        __syncthreads();
+        int rank2;
+        const int lb = select_bin(hist, tmp, rank, &rank2, sh + 2);
+        m = (hb << 8) | lb;
     }
+    if (tid == 0) sh[1] = 0;
     __syncthreads();
-    const int hb = sh[1];
-    if (tid < 256) hist[tid] = 0;
-    __syncthreads();
-    for (int i = tid; i < nL; i += kWG)
-        if (pinhole_survivor(J, i) && ((J.sad[i] >> 8) & 0xFF) == hb) atomicAdd(&hist[J.sad[i] & 0xFF], 1);
-    __syncthreads();
-    if (tid == 0) {
-        int target = sh[2], acc = 0, bin = 0;
-        for (; bin < 256; ++bin) {
-            if (acc + hist[bin] > target) break;
-            acc += hist[bin];
-        }
-        sh[3] = (hb << 8) | bin;
-        sh[4] = 0;
-    }
-    __syncthreads();
-    const long long m = sh[3];
     int kept = 0;
     for (int i = tid; i < nL; i += kWG) {
-        const bool keep = n > 0 && pinhole_survivor(J, i) &&
-                          (long long)J.med_den * J.sad[i] < (long long)J.med_num * m;
+        const bool keep = bit(surv, i) && (long long)J.med_den * J.sad[i] < (long long)J.med_num * m;
         if (keep) {
             J.o_right_idx[i] = J.best_j[i];
             J.o_dist[i] = J.best_h[i];
@@ -628,9 +711,9 @@ __device__ void ph_median(const DevJob &J, int *hist, int *sh)
             J.o_sad[i] = -1;
         }
     }
-    atomicAdd(&sh[4], kept);
+    atomicAdd(&sh[1], kept);
     __syncthreads();
-    if (tid == 0) *J.o_nmatch = sh[4];
+    if (tid == 0) *J.o_nmatch = sh[1];
 }
 
 // ---------------------- stereo_c (fisheye): conflicts + outputs
@@ -662,101 +745,108 @@ __device__ void ph_fish_final(const DevJob &J, int tile)
 }
 
 // ------------------------------------------------ search by projection
-__device__ void ph_search(const DevJob &J, const DevView &V, const DevKps &K, int tile)
+// G lanes per map point.  Every lane of the group evaluates the projection and
+// the visibility tests (identical results), then the group streams the
+// cell-sorted records of the window's cells (one cell of margin on each side
+// covers the rounding of the cell arithmetic) and merges its top-2 lists.
+// Keys order candidates by (distance, keypoint index): distance << 40 |
+// index << 8 | level.
+template <int G>
+__device__ void ph_search(const DevJob &J, const DevView &V, int tile)
 {
-    const int m = tile * kWG + threadIdx.x;
-    if (m >= J.nM) return;
-    int k1 = -1;
-    int b1 = 1 << 20;
-    const float X = J.pos[3 * m], Y = J.pos[3 * m + 1], Z = J.pos[3 * m + 2];
-    const float xc = ((V.R[0] * X + V.R[1] * Y) + V.R[2] * Z) + V.t[0];
-    const float yc = ((V.R[3] * X + V.R[4] * Y) + V.R[5] * Z) + V.t[1];
-    const float zc = ((V.R[6] * X + V.R[7] * Y) + V.R[8] * Z) + V.t[2];
-    do {
-        if (!(zc > 0.0f)) break;
-        float u, v;
-        if (V.model == FT_CAMERA_PINHOLE) {
-            u = ((V.fx * xc) / zc) + V.cx;
-            v = ((V.fy * yc) / zc) + V.cy;
-        } else {
-            const float kb[8] = {V.fx, V.fy, V.cx, V.cy, V.k[0], V.k[1], V.k[2], V.k[3]};
-            const double Pc[3] = {(double)xc, (double)yc, (double)zc};
-            double uv[2];
-            kb_project(kb, Pc, uv);
-            u = (float)uv[0];
-            v = (float)uv[1];
-        }
-        if (!(u >= V.min_x && u <= V.max_x && v >= V.min_y && v <= V.max_y)) break;
-        const float pox = X - V.O[0], poy = Y - V.O[1], poz = Z - V.O[2];
-        const float dist = sqrtf((pox * pox + poy * poy) + poz * poz);
-        const float dmin = J.dmin[m], dmax = J.dmax[m];
-        const float lo = J.dist_lo * dmin, hi = J.dist_hi * dmax;
-        if (!(dist >= lo && dist <= hi)) break;
-        const float vcos =
-            ((pox * J.normal[3 * m] + poy * J.normal[3 * m + 1]) + poz * J.normal[3 * m + 2]) / dist;
-        if (!(vcos >= J.cos_lim)) break;
-        const float ratio = dmax / dist;
-        int pred = kLevels - 1;
-        for (int l = 0; l < kLevels; ++l)
-            if (J.sf[l] >= ratio) {
-                pred = l;
-                break;
+    const int sub = threadIdx.x % G;
+    const int m = tile * (kWG / G) + threadIdx.x / G;
+    Top2<uint64_t> top = {~0ull, ~0ull};
+    if (m < J.nM) {
+        const float X = J.pos[3 * m], Y = J.pos[3 * m + 1], Z = J.pos[3 * m + 2];
+        const float xc = ((V.R[0] * X + V.R[1] * Y) + V.R[2] * Z) + V.t[0];
+        const float yc = ((V.R[3] * X + V.R[4] * Y) + V.R[5] * Z) + V.t[1];
+        const float zc = ((V.R[6] * X + V.R[7] * Y) + V.R[8] * Z) + V.t[2];
+        float u = 0.0f, v = 0.0f;
+        bool vis = false;
+        if (zc > 0.0f) {
+            if (V.model == FT_CAMERA_PINHOLE) {
+                u = ((V.fx * xc) / zc) + V.cx;
+                v = ((V.fy * yc) / zc) + V.cy;
+            } else {
+                const float kb[8] = {V.fx, V.fy, V.cx, V.cy, V.k[0], V.k[1], V.k[2], V.k[3]};
+                const double Pc[3] = {(double)xc, (double)yc, (double)zc};
+                double uv[2];
+                kb_project(kb, Pc, uv);
+                u = (float)uv[0];
+                v = (float)uv[1];
             }
-        const float rbase = (vcos > J.cos_narrow ? J.r_narrow : J.r_wide) * J.th;
-        const float Rm = rbase * J.sf[pred];
-        float uR = 0.0f;
-        if (V.u_right) uR = u - V.bf * (1.0f / zc);
-        // cells covering the window, one cell of margin on each side for rounding
-        const int cx0 = max(cell_coord(u - Rm, V.min_x, V.inv_cw, V.cols) - 1, 0);
-        const int cx1 = min(cell_coord(u + Rm, V.min_x, V.inv_cw, V.cols) + 1, V.cols - 1);
-        const int cy0 = max(cell_coord(v - Rm, V.min_y, V.inv_ch, V.rows) - 1, 0);
-        const int cy1 = min(cell_coord(v + Rm, V.min_y, V.inv_ch, V.rows) + 1, V.rows - 1);
-        const Desc dm = load_desc(J.mdesc, m);
-        int kk2 = -1, b2 = 1 << 20, l1 = -1, l2 = -1;
-        const int plo = pred - J.lv_lo, phi = pred + J.lv_hi;
-        for (int cy = cy0; cy <= cy1; ++cy) {
-            const int c0 = V.cell_off[cy * V.cols + cx0];
-            const int c1 = V.cell_off[cy * V.cols + cx1 + 1];
-            for (int idx = c0; idx < c1; ++idx) {
-                const int k = V.cell_items[idx];
-                const int ok = K.oct[k];
-                if (ok < plo || ok > phi) continue;
-                if (!(fabsf(K.x[k] - u) < Rm && fabsf(K.y[k] - v) < Rm)) continue;
-                if (V.preassigned && V.preassigned[k]) continue;
-                if (V.u_right) {
-                    const float ur = V.u_right[k];
-                    if (ur > 0.0f && !(fabsf(uR - ur) <= Rm)) continue;
-                }
-                const int h = hamming(dm, load_desc(K.desc, k));
-                if (h < b1 || (h == b1 && k < k1)) {
-                    b2 = b1; kk2 = k1; l2 = l1;
-                    b1 = h; k1 = k; l1 = ok;
-                } else if (h < b2 || (h == b2 && k < kk2)) {
-                    b2 = h; kk2 = k; l2 = ok;
-                }
+            vis = u >= V.min_x && u <= V.max_x && v >= V.min_y && v <= V.max_y;
+        }
+        float dist = 0.0f, vcos = 0.0f, dmax = 0.0f;
+        if (vis) {
+            const float pox = X - V.O[0], poy = Y - V.O[1], poz = Z - V.O[2];
+            dist = sqrtf((pox * pox + poy * poy) + poz * poz);
+            dmax = J.dmax[m];
+            const float lo = J.dist_lo * J.dmin[m], hi = J.dist_hi * dmax;
+            vis = dist >= lo && dist <= hi;
+            if (vis) {
+                vcos = ((pox * J.normal[3 * m] + poy * J.normal[3 * m + 1]) + poz * J.normal[3 * m + 2]) / dist;
+                vis = vcos >= J.cos_lim;
             }
         }
-        if (k1 < 0) break;
-        if (kk2 < 0) {
-            b2 = 256;
-            l2 = -1;
+        if (vis) {
+            const float ratio = dmax / dist;
+            int pred = kLevels - 1;
+            for (int l = 0; l < kLevels; ++l)
+                if (J.sf[l] >= ratio) {
+                    pred = l;
+                    break;
+                }
+            const float rbase = (vcos > J.cos_narrow ? J.r_narrow : J.r_wide) * J.th;
+            const float Rm = rbase * J.sf[pred];
+            const bool gate = V.u_right != nullptr;
+            const float uR = gate ? u - V.bf * (1.0f / zc) : 0.0f;
+            const int cx0 = max(cell_coord(u - Rm, V.min_x, V.inv_cw, V.cols) - 1, 0);
+            const int cx1 = min(cell_coord(u + Rm, V.min_x, V.inv_cw, V.cols) + 1, V.cols - 1);
+            const int cy0 = max(cell_coord(v - Rm, V.min_y, V.inv_ch, V.rows) - 1, 0);
+            const int cy1 = min(cell_coord(v + Rm, V.min_y, V.inv_ch, V.rows) + 1, V.rows - 1);
+            const Desc dm = load_desc(J.mdesc, m);
+            const int plo = pred - J.lv_lo, phi = pred + J.lv_hi;
+            for (int cy = cy0; cy <= cy1; ++cy) {
+                const int c1 = V.cell_off[cy * V.cols + cx1 + 1];
+                for (int p = V.cell_off[cy * V.cols + cx0] + sub; p < c1; p += G) {
+                    const CellRec rec = V.crec[p];
+                    const int ok = (int)(rec.meta & 0xFFu);
+                    if (ok < plo || ok > phi) continue;
+                    if (!(fabsf(rec.x - u) < Rm && fabsf(rec.y - v) < Rm)) continue;
+                    if (rec.meta & 0x100u) continue;
+                    const uint32_t k = rec.meta >> 16;
+                    if (gate) {
+                        const float ur = V.u_right[k];
+                        if (ur > 0.0f && !(fabsf(uR - ur) <= Rm)) continue;
+                    }
+                    const uint64_t h = (uint64_t)hamming(dm, load_desc(V.cdesc, p));
+                    top = top2_insert(top, (h << 40) | ((uint64_t)k << 8) | (uint64_t)(rec.meta & 0xFFu));
+                }
+            }
         }
-        if (!(b1 <= J.th_high)) {
-            k1 = -1;
-            break;
+    }
+    for (int o = 1; o < G; o <<= 1) top = top2_merge(top, shfl_xor64(top.a, o), shfl_xor64(top.b, o));
+    if (sub != 0 || m >= J.nM) return;
+    const uint64_t k1 = top.a, k2 = top.b;
+    int kk1 = -1, b1 = -1;
+    if (k1 != ~0ull) {
+        const int h1 = (int)(k1 >> 40), l1 = (int)(k1 & 0xFFu);
+        const int h2 = k2 != ~0ull ? (int)(k2 >> 40) : 256;
+        const int l2 = k2 != ~0ull ? (int)(k2 & 0xFFu) : -1;
+        const bool fails = J.s_ratio_den * h1 > J.s_ratio_num * h2;
+        if (h1 <= J.th_high && !(J.same_level_only ? (l1 == l2 && fails) : fails)) {
+            kk1 = (int)((k1 >> 8) & 0xFFFFu);
+            b1 = h1;
         }
-        const bool fails = J.s_ratio_den * b1 > J.s_ratio_num * b2;
-        if (J.same_level_only ? (l1 == l2 && fails) : fails) {
-            k1 = -1;
-            break;
-        }
-    } while (false);
-    V.mp_k[m] = k1;
-    V.mp_h[m] = k1 >= 0 ? b1 : -1;
-    if (k1 >= 0) atomicMin(&V.claim[k1], ((uint32_t)b1 << 23) | (uint32_t)m);
+    }
+    V.mp_k[m] = kk1;
+    V.mp_h[m] = b1;
+    if (kk1 >= 0) atomicMin(&V.claim[kk1], ((uint32_t)b1 << 23) | (uint32_t)m);
 }
 
-__device__ void ph_search_final(const DevJob &J, const DevView &V, const DevKps &K, int tile)
+__device__ void ph_search_final(const DevJob &J, const DevView &V, int nK, int tile)
 {
     const int idx = tile * kWG + threadIdx.x;
     if (idx < J.nM) {
@@ -766,133 +856,232 @@ __device__ void ph_search_final(const DevJob &J, const DevView &V, const DevKps 
         V.mp_dist[idx] = keep ? V.mp_h[idx] : -1;
     }
     bool has = false;
-    if (idx < K.n) {
+    if (idx < nK) {
         const uint32_t c = V.claim[idx];
         has = c != 0xFFFFFFFFu;
         V.kp_match[idx] = has ? (int)(c & 0x7FFFFFu) : -1;
     }
-    const unsigned long long m = __ballot(has);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(V.n_matches, (int)__popcll(m));
+    const unsigned long long mk = __ballot(has);
+    if ((threadIdx.x & 63) == 0 && mk) atomicAdd(V.n_matches, (int)__popcll(mk));
 }
 
-// ------------------------------------------------------------------ kernels
-struct OneJob {
-    DevJob j;
-    __device__ __forceinline__ const DevJob &operator()(int) const { return j; }
-};
-struct JobTable {
-    const DevJob *p;
-    __device__ __forceinline__ const DevJob &operator()(int i) const { return p[i]; }
-};
+// ------------------------------------------------------- tile bookkeeping
+__host__ __device__ inline int div_up(int n, int d) { return (n + d - 1) / d; }
 
-__device__ __forceinline__ const DevKps &view_kps(const DevJob &J, int v)
+__host__ __device__ inline int view_kp(const DevJob &J, int v) { return J.view[v].side ? J.R.n : J.L.n; }
+
+__host__ __device__ inline int search_tiles_per_view(const DevJob &J, int lanes)
 {
-    return J.view[v].side ? J.R : J.L;
+    return div_up(J.nM, kWG / lanes);
 }
 
-template <class Src>
-__global__ __launch_bounds__(kWG) void k_setup(Src src, int do_stereo, int do_search)
+__host__ __device__ inline int final_tiles_view(const DevJob &J, int v)
 {
-    __shared__ int lds[kMaxCells + 8];
-    __shared__ int tmp[kWG];
-    const DevJob &J = src(blockIdx.y);
-    const int part = blockIdx.x;
-    if (part == 0) {
-        if (!do_stereo) return;
-        if (J.flags & JOB_STEREO_PINHOLE) ph_rowband(J, lds, tmp);
-        else if (J.flags & JOB_STEREO_FISHEYE) ph_overlap(J, tmp);
-    } else {
-        const int v = part - 1;
-        if (!do_search || !(J.flags & (JOB_SEARCH0 << v))) return;
-        ph_grid(J.view[v], view_kps(J, v), lds, tmp);
+    const int nK = view_kp(J, v);
+    return div_up(J.nM > nK ? J.nM : nK, kWG);
+}
+
+void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search, int32_t out[PH_COUNT])
+{
+    for (int p = 0; p < PH_COUNT; ++p) out[p] = 0;
+    const int nL = J.L.n;
+    const bool pin = do_stereo && (J.flags & JOB_STEREO_PINHOLE);
+    const bool fish = do_stereo && (J.flags & JOB_STEREO_FISHEYE);
+    const int nv = do_search ? J.n_views : 0;
+    out[PH_SETUP] = (pin || fish ? 1 : 0) + nv;
+    if (pin) {
+        out[PH_STEREO_A] = div_up(nL, kWG / s.best_lanes);
+        out[PH_STEREO_B] = div_up(nL, kRefinePerWG);
+        out[PH_STEREO_C] = 1;
+    } else if (fish) {
+        out[PH_STEREO_A] = div_up(nL, kKnnQueriesPerWG);
+        out[PH_STEREO_B] = div_up(nL, kWG);
+        out[PH_STEREO_C] = div_up(nL, kWG);
+    }
+    for (int v = 0; v < nv; ++v) {
+        out[PH_SEARCH] += search_tiles_per_view(J, s.search_lanes);
+        out[PH_SEARCH_FIN] += final_tiles_view(J, v);
     }
 }
 
+// ------------------------------------------------------------------ kernels
+// Consecutive logical tiles on one XCD: workgroups are dealt round-robin over
+// the 8 XCDs, so block b runs on XCD b % 8; map it to a contiguous chunk.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int per = n >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+struct OneJob {
+    DevJob j;
+    __device__ __forceinline__ const DevJob &operator()(int) const { return j; }
+    __device__ __forceinline__ bool locate(int, int &job, int &tile) const
+    {
+        job = 0;
+        tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+        return true;
+    }
+};
+
+struct JobTable {
+    const DevJob *p;
+    TileMap map;
+    __device__ __forceinline__ const DevJob &operator()(int i) const { return p[i]; }
+    __device__ __forceinline__ bool locate(int ph, int &job, int &tile) const
+    {
+        const int32_t *pre = map.prefix + ph * (map.n_jobs + 1);
+        const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+        int lo = 0, hi = map.n_jobs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= b) lo = mid;
+            else hi = mid;
+        }
+        job = lo;
+        tile = b - pre[lo];
+        return tile < pre[lo + 1] - pre[lo];
+    }
+};
+
 template <class Src>
+__global__ __launch_bounds__(kWG) void k_setup(Src src)
+{
+    __shared__ int lds[kMaxCells + 8];
+    __shared__ int tmp[kWG];
+    int job, tile;
+    if (!src.locate(PH_SETUP, job, tile)) return;
+    const DevJob &J = src(job);
+    const bool stereo = J.flags & (JOB_STEREO_PINHOLE | JOB_STEREO_FISHEYE);
+    if (stereo && tile == 0) {
+        if (J.flags & JOB_STEREO_PINHOLE) ph_rowsort(J, lds, tmp);
+        else ph_overlap(J, tmp);
+        return;
+    }
+    const int v = tile - (stereo ? 1 : 0);
+    const DevView &V = J.view[v];
+    ph_cellsort(V, V.side ? J.R : J.L, lds, tmp);
+}
+
+template <class Src, int G>
 __global__ __launch_bounds__(kWG) void k_stereo_a(Src src)
 {
-    const DevJob &J = src(blockIdx.y);
-    if (J.flags & JOB_STEREO_PINHOLE) ph_best(J, blockIdx.x);
-    else if (J.flags & JOB_STEREO_FISHEYE) ph_knn(J, blockIdx.x);
+    __shared__ uint64_t tab[256];
+    __shared__ uint32_t part[4 * 16 * 2];
+    int job, tile;
+    if (!src.locate(PH_STEREO_A, job, tile)) return;
+    const DevJob &J = src(job);
+    if (J.flags & JOB_STEREO_PINHOLE) ph_best<G>(J, tile);
+    else ph_knn(J, tile, tab, part);
 }
 
 template <class Src>
 __global__ __launch_bounds__(kWG) void k_stereo_b(Src src)
 {
-    const DevJob &J = src(blockIdx.y);
-    if (J.flags & JOB_STEREO_PINHOLE) ph_refine(J, blockIdx.x);
-    else if (J.flags & JOB_STEREO_FISHEYE) ph_tri(J, blockIdx.x);
+    __shared__ uint8_t lds[kRefinePerWG * kRefineLds];
+    int job, tile;
+    if (!src.locate(PH_STEREO_B, job, tile)) return;
+    const DevJob &J = src(job);
+    if (J.flags & JOB_STEREO_PINHOLE) ph_refine(J, tile, lds);
+    else ph_tri(J, tile);
 }
 
 template <class Src>
 __global__ __launch_bounds__(kWG) void k_stereo_c(Src src)
 {
     __shared__ int hist[256];
-    __shared__ int sh[8];
-    const DevJob &J = src(blockIdx.y);
-    if (J.flags & JOB_STEREO_PINHOLE) {
-        if (blockIdx.x == 0) ph_median(J, hist, sh);
-    } else if (J.flags & JOB_STEREO_FISHEYE) {
-        ph_fish_final(J, blockIdx.x);
-    }
+    __shared__ int tmp[kWG];
+    __shared__ uint32_t surv[(kMaxKp + 32) / 32];
+    __shared__ int sh[4];
+    int job, tile;
+    if (!src.locate(PH_STEREO_C, job, tile)) return;
+    const DevJob &J = src(job);
+    if (J.flags & JOB_STEREO_PINHOLE) ph_median(J, hist, tmp, surv, sh);
+    else ph_fish_final(J, tile);
 }
 
-template <class Src>
+template <class Src, int G>
 __global__ __launch_bounds__(kWG) void k_search(Src src)
 {
-    const DevJob &J = src(blockIdx.y);
-    const int v = blockIdx.z;
-    if (!(J.flags & (JOB_SEARCH0 << v))) return;
-    ph_search(J, J.view[v], view_kps(J, v), blockIdx.x);
+    int job, tile;
+    if (!src.locate(PH_SEARCH, job, tile)) return;
+    const DevJob &J = src(job);
+    const int tpv = search_tiles_per_view(J, G);
+    const int v = tile / tpv;
+    ph_search<G>(J, J.view[v], tile - v * tpv);
 }
 
 template <class Src>
 __global__ __launch_bounds__(kWG) void k_search_final(Src src)
 {
-    const DevJob &J = src(blockIdx.y);
-    const int v = blockIdx.z;
-    if (!(J.flags & (JOB_SEARCH0 << v))) return;
-    ph_search_final(J, J.view[v], view_kps(J, v), blockIdx.x);
+    int job, tile;
+    if (!src.locate(PH_SEARCH_FIN, job, tile)) return;
+    const DevJob &J = src(job);
+    const int t0 = final_tiles_view(J, 0);
+    const int v = tile < t0 ? 0 : 1;
+    ph_search_final(J, J.view[v], view_kp(J, v), tile - (v ? t0 : 0));
 }
 
 template <class Src>
-static hipError_t run(Src src, const LaunchDims &d, hipStream_t s, bool do_stereo, bool do_search,
-                      hipEvent_t *ev)
+static void launch_best(Src src, int lanes, int blocks, hipStream_t s)
 {
     const dim3 blk(kWG);
-    const int nj = d.n_jobs;
+    switch (lanes) {
+    case 1: hipLaunchKernelGGL((k_stereo_a<Src, 1>), dim3(blocks), blk, 0, s, src); break;
+    case 2: hipLaunchKernelGGL((k_stereo_a<Src, 2>), dim3(blocks), blk, 0, s, src); break;
+    case 4: hipLaunchKernelGGL((k_stereo_a<Src, 4>), dim3(blocks), blk, 0, s, src); break;
+    case 16: hipLaunchKernelGGL((k_stereo_a<Src, 16>), dim3(blocks), blk, 0, s, src); break;
+    default: hipLaunchKernelGGL((k_stereo_a<Src, 8>), dim3(blocks), blk, 0, s, src); break;
+    }
+}
+
+template <class Src>
+static void launch_search(Src src, int lanes, int blocks, hipStream_t s)
+{
+    const dim3 blk(kWG);
+    switch (lanes) {
+    case 1: hipLaunchKernelGGL((k_search<Src, 1>), dim3(blocks), blk, 0, s, src); break;
+    case 2: hipLaunchKernelGGL((k_search<Src, 2>), dim3(blocks), blk, 0, s, src); break;
+    case 8: hipLaunchKernelGGL((k_search<Src, 8>), dim3(blocks), blk, 0, s, src); break;
+    case 16: hipLaunchKernelGGL((k_search<Src, 16>), dim3(blocks), blk, 0, s, src); break;
+    default: hipLaunchKernelGGL((k_search<Src, 4>), dim3(blocks), blk, 0, s, src); break;
+    }
+}
+
+template <class Src>
+static hipError_t run(Src src, const int32_t *tot, const Shapes &sh, hipStream_t s, bool do_stereo,
+                      bool do_search, hipEvent_t *ev)
+{
+    const dim3 blk(kWG);
     auto mark = [&](int p) {
         if (ev) (void)hipEventRecord(ev[p], s);
     };
     mark(0);
-    hipLaunchKernelGGL(k_setup<Src>, dim3(d.setup_x, nj), blk, 0, s, src, (int)do_stereo, (int)do_search);
+    if (tot[PH_SETUP] > 0) hipLaunchKernelGGL(k_setup<Src>, dim3(tot[PH_SETUP]), blk, 0, s, src);
     mark(1);
-    if (do_stereo) {
-        hipLaunchKernelGGL(k_stereo_a<Src>, dim3(max(d.tiles_stereo_a, 1), nj), blk, 0, s, src);
-        mark(2);
-        hipLaunchKernelGGL(k_stereo_b<Src>, dim3(max(d.tiles_stereo_b, 1), nj), blk, 0, s, src);
-        mark(3);
-        hipLaunchKernelGGL(k_stereo_c<Src>, dim3(max(d.tiles_stereo_c, 1), nj), blk, 0, s, src);
-        mark(4);
-    } else {
-        mark(2); mark(3); mark(4);
-    }
-    if (do_search) {
-        hipLaunchKernelGGL(k_search<Src>, dim3(max(d.tiles_search, 1), nj, 2), blk, 0, s, src);
-        mark(5);
-        hipLaunchKernelGGL(k_search_final<Src>, dim3(max(d.tiles_search_fin, 1), nj, 2), blk, 0, s, src);
-        mark(6);
-    } else {
-        mark(5); mark(6);
-    }
+    if (do_stereo && tot[PH_STEREO_A] > 0) launch_best(src, sh.best_lanes, tot[PH_STEREO_A], s);
+    mark(2);
+    if (do_stereo && tot[PH_STEREO_B] > 0)
+        hipLaunchKernelGGL(k_stereo_b<Src>, dim3(tot[PH_STEREO_B]), blk, 0, s, src);
+    mark(3);
+    if (do_stereo && tot[PH_STEREO_C] > 0)
+        hipLaunchKernelGGL(k_stereo_c<Src>, dim3(tot[PH_STEREO_C]), blk, 0, s, src);
+    mark(4);
+    if (do_search && tot[PH_SEARCH] > 0) launch_search(src, sh.search_lanes, tot[PH_SEARCH], s);
+    mark(5);
+    if (do_search && tot[PH_SEARCH_FIN] > 0)
+        hipLaunchKernelGGL(k_search_final<Src>, dim3(tot[PH_SEARCH_FIN]), blk, 0, s, src);
+    mark(6);
     return hipGetLastError();
 }
 
-hipError_t launch_pipeline(const DevJob *table, const DevJob &one, const LaunchDims &d,
-                           hipStream_t stream, bool do_stereo, bool do_search, hipEvent_t *ev)
+hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
+                           const DevJob &one, const Shapes &shapes, hipStream_t stream,
+                           bool do_stereo, bool do_search, hipEvent_t *ev)
 {
-    if (table) return run(JobTable{table}, d, stream, do_stereo, do_search, ev);
-    return run(OneJob{one}, d, stream, do_stereo, do_search, ev);
+    if (table) return run(JobTable{table, map}, totals, shapes, stream, do_stereo, do_search, ev);
+    return run(OneJob{one}, totals, shapes, stream, do_stereo, do_search, ev);
 }
 
 }  // namespace ft

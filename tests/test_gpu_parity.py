@@ -189,7 +189,7 @@ def test_invalid_arguments_enqueue_nothing(ft, ctx):
                                      bad, df.stereo_cam, df.stereo_params, df.stereo_out, check=False)
     assert st == ft.FT_ERR_INVALID_ARGUMENT
     params = ft.ft_pinhole_params.from_buffer_copy(df.stereo_params)
-    params.band = 50.0
+    params.band = 100.0
     st = ctx.ft_stereo_match_pinhole(df.left.struct(), df.right.struct(), df.pyr_left, df.pyr_right,
                                      df.scales, df.stereo_cam, params, df.stereo_out, check=False)
     assert st == ft.FT_ERR_INVALID_ARGUMENT
@@ -221,3 +221,48 @@ def test_batch_tickets_poll_and_wait(ft, ctx):
     assert ctx.ft_batch_poll(t1) and ctx.ft_batch_poll(t2)
     for f, d in zip(frames, dfs):
         compare_frame(d.results(), oracle.run_frame(f))
+
+
+# ------------------------------------------------------- launch shapes / tuner
+def test_lane_groups_do_not_change_results(ft, ctx):
+    frames = synth.config4(n_frames=8)
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    jobs = [d.job() for d in dfs]
+    ref = None
+    try:
+        for gb, gs in [(1, 1), (2, 16), (4, 8), (8, 4), (16, 2)]:
+            ctx.ft_set_shapes(gb, gs)
+            say("shapes", gb, gs)
+            ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+            torch.cuda.synchronize()
+            res = [d.results() for d in dfs]
+            if ref is None:
+                ref = res
+                for f, r in zip(frames, res):
+                    compare_frame(r, oracle.run_frame(f))
+            else:
+                for a, b in zip(res, ref):
+                    bit_equal(a, b)
+    finally:
+        ctx.ft_set_shapes(8, 4)
+
+
+def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
+    frames = synth.config4(n_frames=6)
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    jobs = [d.job() for d in dfs]
+    cache = str(tmp_path / "shapes.jsonl")
+    try:
+        chosen = ctx.ft_autotune(jobs, cache)
+        assert chosen[0] in (1, 2, 4, 8, 16) and chosen[1] in (1, 2, 4, 8, 16)
+        text = open(cache).read()
+        assert '"best_lanes": %d' % chosen[0] in text
+        ctx.ft_set_shapes(1, 1)
+        assert ctx.ft_autotune(jobs, cache) == chosen        # served from the cache
+        assert open(cache).read() == text
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+        torch.cuda.synchronize()
+        for f, d in zip(frames, dfs):
+            compare_frame(d.results(), oracle.run_frame(f))
+    finally:
+        ctx.ft_set_shapes(8, 4)
