@@ -51,6 +51,27 @@ def algorithmic_search_bytes(frames, results):
     return total
 
 
+def algorithmic_path_bytes(frames, results):
+    """Compulsory bytes of the whole path (stereo + search) for one step.
+
+    Stereo, per image keypoint: x 4 + y 4 + level 1 + descriptor 32 read.
+    Pinhole: per left keypoint 20 B of outputs (right index, distance, right
+    coordinate, depth, SAD), and per final match the two SAD windows of the
+    refinement, 11x11 left + 11x21 right = 352 B (final matches only, so a
+    lower bound).  Fisheye: per left keypoint 24 B of outputs (right index,
+    distance, depth, point).  Search: as `algorithmic_search_bytes`.
+    """
+    total = algorithmic_search_bytes(frames, results)
+    for f, r in zip(frames, results):
+        nL, nR = len(f["left"]["x"]), len(f["right"]["x"])
+        total += 41 * (nL + nR)
+        if f["kind"] == "pinhole":
+            total += 20 * nL + 352 * int((r["stereo"]["right_idx"] >= 0).sum())
+        else:
+            total += 24 * nL
+    return total
+
+
 def cpu_baseline(frames, budget_s=12.0):
     import oracle
     done = 0
@@ -64,13 +85,46 @@ def cpu_baseline(frames, budget_s=12.0):
                       f"single-threaded plain C oracle, {dt:.1f} s"}
 
 
+def serving_sweep(duration_s, speedups):
+    """Config-5 serving: 32 streams, both the per-frame path and continuous
+    batching over the same Poisson arrivals, compressed in time by `speedups`."""
+    from paper_2509_10757_amd import serve
+    from synth.serving import make_streams
+    log("generating the 32-stream serving workload")
+    streams = make_streams()
+    ex = serve.DeviceExecutor(streams, max_batch=64, max_inflight=4)
+    rows = []
+    for mode in ("per_frame", "batched"):
+        for a in speedups:
+            r = serve.serve(streams, duration_s, speedup=a, mode=mode, executor=ex)
+            log(mode, a, {k: round(v, 3) if isinstance(v, float) else v for k, v in r.items()
+                          if k in ("frames_per_s", "p50_ms", "p99_ms", "offered_fps", "mean_batch")})
+            rows.append({k: r[k] for k in ("mode", "speedup", "offered_fps", "frames_per_s",
+                                           "p50_ms", "p99_ms", "mean_batch", "failed")})
+    # knee of the per-frame path: the highest load it still keeps up with
+    pf = [r for r in rows if r["mode"] == "per_frame" and r["frames_per_s"] >= 0.95 * r["offered_fps"]]
+    knee = max(pf, key=lambda r: r["offered_fps"]) if pf else min(
+        (r for r in rows if r["mode"] == "per_frame"), key=lambda r: r["offered_fps"])
+    bound = knee["p99_ms"]
+    ok = [r for r in rows if r["mode"] == "batched" and r["p99_ms"] <= bound]
+    best = max(ok, key=lambda r: r["frames_per_s"]) if ok else None
+    return {"streams": len(streams), "duration_s": duration_s, "runs": rows,
+            "p99_bound_ms": round(bound, 3), "per_frame_fps_at_bound": round(knee["frames_per_s"], 1),
+            "batched_fps_at_bound": round(best["frames_per_s"], 1) if best else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shapes", type=str, default="", help="best,search lanes instead of autotuning")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--exec", choices=["auto", "graph", "persistent", "eager"], default="auto",
+                    help="batch execution mode; auto times graph and persistent briefly and keeps the faster")
+    ap.add_argument("--serving", type=float, default=0.0, metavar="SECONDS",
+                    help="also run the 32-stream serving sweep, SECONDS per run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -103,8 +157,12 @@ def main():
     jobs = [d.job() for d in dfs]
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    log("autotune")
-    shapes = ctx.ft_autotune(jobs, stream=stream)
+    if args.shapes:
+        shapes = tuple(int(v) for v in args.shapes.split(","))
+        ctx.ft_set_shapes(*shapes)
+    else:
+        log("autotune")
+        shapes = ctx.ft_autotune(jobs, stream=stream)
     torch.cuda.synchronize()
 
     def step():
@@ -118,24 +176,57 @@ def main():
             ctx.ft_batch_wait(pending.pop(0))
         pending.append(step())
 
+    def drain():
+        while pending:
+            ctx.ft_batch_wait(pending.pop(0))
+        torch.cuda.synchronize()
+
+    modes = {"graph": ft.FT_EXEC_GRAPH, "persistent": ft.FT_EXEC_PERSISTENT, "eager": ft.FT_EXEC_EAGER}
+    trial = {}
+    if args.exec == "auto":
+        for name in ("graph", "persistent"):
+            ctx.ft_set_exec_mode(modes[name])
+            for _ in range(10):
+                submit_bounded()
+            drain()
+            q0 = time.perf_counter()
+            for _ in range(50):
+                submit_bounded()
+            drain()
+            trial[name] = round(n_frames * 50 / (time.perf_counter() - q0), 1)
+            log("trial", name, trial[name])
+        exec_mode = max(trial, key=trial.get)
+    else:
+        exec_mode = args.exec
+    ctx.ft_set_exec_mode(modes[exec_mode])
+    persistent = exec_mode == "persistent"
+
     log("warmup", args.warmup)
     for _ in range(args.warmup):
         submit_bounded()
     torch.cuda.synchronize()
 
-    # ---- timed region: K back-to-back batch submissions on one stream
-    log("timed", args.steps)
+    # ---- timed region: K back-to-back batch submissions on one stream.  A
+    # persistent batch is one kernel, bracketed by HIP events on this stream.
+    log("timed", args.steps, exec_mode)
+    if persistent:
+        ctx.ft_context_enable_timing(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         submit_bounded()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    drain()
+    kernel_us = None
+    if persistent:
+        ms, n = ctx.ft_context_read_timing()["persistent_batch"]
+        ctx.ft_context_enable_timing(False)
+        kernel_us = ms / n * 1e3 if n else None
     ms_per_step = dt * 1e3 / args.steps
     value = n_frames * args.steps / dt
 
     # ---- latency of one submission (submit -> completion seen by the host)
     lat = []
-    pending.clear()
     for _ in range(max(50, args.steps // 4)):
         s0 = time.perf_counter()
         ctx.ft_batch_wait(step())
@@ -157,24 +248,45 @@ def main():
     # ---- per-kernel timing with HIP events on the launch stream
     roofline = None
     phases = None
+    res = [d.results() for d in dfs]
+    if persistent and kernel_us:
+        pbytes = algorithmic_path_bytes(frames, res)
+        achieved = pbytes / (kernel_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_persistent (whole batch: stereo + search)",
+                    "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                    "algorithmic_bytes_per_launch": pbytes, "avg_launch_us": round(kernel_us, 3),
+                    "timed": "HIP events around every launch of the timed region"}
     if not args.no_timing:
+        # per-phase breakdown: the same batches as one kernel per phase
+        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
         ctx.ft_context_enable_timing(True)
         for _ in range(args.steps):
             submit_bounded()
-        torch.cuda.synchronize()
+        drain()
         tm = ctx.ft_context_read_timing()
         ctx.ft_context_enable_timing(False)
-        phases = {k: {"avg_us": (ms / n * 1e3) if n else None, "launches": n} for k, (ms, n) in tm.items()}
+        ctx.ft_set_exec_mode(modes[exec_mode])
+        phases = {k: {"avg_us": (ms / n * 1e3) if n else None, "launches": n}
+                  for k, (ms, n) in tm.items() if n}
         dom = max(phases, key=lambda k: phases[k]["avg_us"] or 0)
-        res = [d.results() for d in dfs]
         sbytes = algorithmic_search_bytes(frames, res)
         s_us = phases["search"]["avg_us"]
         achieved = sbytes / (s_us * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_search (search by projection)",
-                    "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                    "algorithmic_bytes_per_launch": sbytes, "avg_launch_us": round(s_us, 3),
-                    "dominant_phase": dom}
+        search_roof = {"bound": "hbm", "kernel": "k_search (search by projection)",
+                       "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                       "algorithmic_bytes_per_launch": sbytes, "avg_launch_us": round(s_us, 3),
+                       "timed": "HIP events around each phase kernel, eager per-phase pass",
+                       "dominant_phase": dom}
+        if roofline is None:
+            roofline = search_roof
+        else:
+            phases["search_roofline"] = search_roof
+
+    serving = None
+    if args.serving > 0:
+        serving = serving_sweep(args.serving, [1, 8, 32, 64, 128, 256])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,6 +300,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "frames_per_step": n_frames,
                    "shapes": {"best_lanes": shapes[0], "search_lanes": shapes[1]},
+                   "exec": exec_mode, "exec_trial_fps": trial or None,
                    "pinhole_frames": sum(f["kind"] == "pinhole" for f in frames),
                    "fisheye_frames": sum(f["kind"] == "fisheye" for f in frames)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
@@ -196,6 +309,7 @@ def main():
         "phases": phases,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out))
 

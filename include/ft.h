@@ -22,8 +22,10 @@
  *   - Coordinates are level-0 pixels; `octave` is the pyramid level (0..7).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is only
  *     enqueued: outputs are valid once the stream (or the batch ticket) has
- *     completed.  All calls on one context must be ordered on one stream (or
- *     ordered by the caller), because they share the context's workspace.
+ *     completed.  The single-frame calls of one context share one workspace,
+ *     so they must be ordered on one stream (or by the caller).  Each batch in
+ *     flight owns a workspace lane of its own, so batches may run on
+ *     different streams at the same time.
  *   - The caller owns every buffer.  The library neither frees nor keeps any
  *     caller pointer past the completion of that call's device work; inputs
  *     must stay alive and unchanged until then.
@@ -54,6 +56,7 @@ typedef int32_t ft_status;
 #define FT_ERR_CAPACITY 2         /* input exceeds the context's ft_limits */
 #define FT_ERR_DEVICE 3           /* a HIP call failed (sticky) */
 #define FT_ERR_UNSUPPORTED 4      /* feature or device not supported */
+#define FT_ERR_ABORTED 5          /* a persistent batch gave up waiting; its outputs are invalid (not sticky) */
 
 #define FT_LEVELS 8               /* pyramid levels (ORB scale pyramid) */
 #define FT_DESC_BYTES 32          /* 256-bit descriptor */
@@ -297,6 +300,39 @@ ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done);
 /* Blocks until the ticket's work has completed. */
 ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket);
 
+/* How a batch is executed on the device:
+ *   FT_EXEC_EAGER       the table upload and one kernel per phase, launched on
+ *                       the stream one by one;
+ *   FT_EXEC_GRAPH       the same work as one HIP graph launch; each in-flight
+ *                       lane keeps the instantiated graph of every batch shape
+ *                       it has seen (frame count, tiles per phase, lane
+ *                       groups), so a repeated shape is relaunched without
+ *                       capture (the default);
+ *   FT_EXEC_PERSISTENT  one persistent kernel per batch: workgroups take tasks
+ *                       (phase, frame, tile) from a queue in phase order and
+ *                       wait, with a bounded spin, until the earlier phases of
+ *                       the task's frame are complete, so phases of different
+ *                       frames overlap; one kernel launch after the table
+ *                       upload, followed by a 4-byte copy of its status.
+ * Results are identical in every mode.  While per-phase timing is enabled,
+ * graph batches run eagerly so that each phase can be bracketed by events;
+ * persistent batches are timed as a whole.
+ * Returns FT_ERR_INVALID_ARGUMENT for an unknown mode. */
+#define FT_EXEC_EAGER 0
+#define FT_EXEC_GRAPH 1
+#define FT_EXEC_PERSISTENT 2
+ft_status ft_set_exec_mode(ft_context *ctx, int32_t mode);
+ft_status ft_get_exec_mode(const ft_context *ctx, int32_t *mode);
+
+/* Settings of FT_EXEC_PERSISTENT.  `blocks`: workgroups of the persistent
+ * kernel, 0 = as many as fit on the device at once (the default; the grid is
+ * never larger than the batch's task count).  `spin_limit`: sleeps one
+ * dependency wait may take before the kernel gives up, 0 = the default (about
+ * a second).  A batch that gave up skips its remaining tasks; ft_batch_poll /
+ * ft_batch_wait of its ticket then return FT_ERR_ABORTED and its outputs are
+ * invalid; the context stays usable.  Negative values: FT_ERR_INVALID_ARGUMENT. */
+ft_status ft_set_persistent(ft_context *ctx, int32_t blocks, int32_t spin_limit);
+
 /* Launch shapes of the search kernels: how many lanes of a wave cooperate on
  * one query.  Results never depend on them, only the time does. */
 typedef struct ft_shapes {
@@ -328,12 +364,14 @@ const char *ft_last_error(const ft_context *ctx);
 /* Per-phase kernel timing (for measurement tools).  When enabled, every
  * submission records HIP events on its own stream around each phase kernel:
  * 0 setup (row index / overlap lists / grids), 1 stereo best match (pinhole
- * row band or fisheye all-pairs), 2 stereo refine / triangulation, 3 stereo
- * resolve + outputs, 4 search by projection, 5 search resolve + outputs.
+ * row band or fisheye all-pairs), 2 pinhole refinement, 3 fisheye
+ * triangulation check, 4 stereo resolve + outputs, 5 search by projection,
+ * 6 search resolve + outputs, 7 a whole FT_EXEC_PERSISTENT batch (its one
+ * kernel; in that mode phases 0-6 are not timed separately).
  * ft_context_read_timing waits for the recorded work, returns the summed
  * milliseconds and launch counts per phase (arrays of FT_PHASES), and resets
  * them.  Enabling timing adds event records between kernels. */
-#define FT_PHASES 6
+#define FT_PHASES 8
 ft_status ft_context_enable_timing(ft_context *ctx, int32_t enable);
 ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches);
 /* Library version as major*10000 + minor*100 + patch. */

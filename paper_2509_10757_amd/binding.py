@@ -18,8 +18,10 @@ from . import build as _build
 
 LEVELS = 8
 FT_OK, FT_ERR_INVALID_ARGUMENT, FT_ERR_CAPACITY, FT_ERR_DEVICE, FT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+FT_ERR_ABORTED = 5
 FT_CAMERA_PINHOLE, FT_CAMERA_KB = 0, 1
 FT_JOB_PINHOLE, FT_JOB_FISHEYE, FT_JOB_SEARCH = 1, 2, 3
+FT_EXEC_EAGER, FT_EXEC_GRAPH, FT_EXEC_PERSISTENT = 0, 1, 2
 
 P = ct.c_void_p
 F8 = ct.c_float * LEVELS
@@ -145,6 +147,9 @@ EXPORTS = {
     "ft_batch_wait": [P, ct.c_uint64],
     "ft_context_enable_timing": [P, ct.c_int32],
     "ft_context_read_timing": [P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)],
+    "ft_set_exec_mode": [P, ct.c_int32],
+    "ft_get_exec_mode": [P, ct.POINTER(ct.c_int32)],
+    "ft_set_persistent": [P, ct.c_int32, ct.c_int32],
     "ft_set_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_get_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_autotune": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.c_char_p, ct.POINTER(ft_shapes)],
@@ -230,14 +235,15 @@ class Context:
         self._check(self.lib.ft_context_workspace_bytes(self.h, ct.byref(v)), "workspace_bytes")
         return v.value
 
-    PHASES = ("setup", "stereo_best", "stereo_refine", "stereo_resolve", "search", "search_resolve")
+    PHASES = ("setup", "stereo_best", "pinhole_refine", "fisheye_triangulate", "stereo_resolve",
+              "search", "search_resolve", "persistent_batch")
 
     def ft_context_enable_timing(self, enable: bool = True):
         self._check(self.lib.ft_context_enable_timing(self.h, int(enable)), "enable_timing")
 
     def ft_context_read_timing(self) -> dict:
-        ms = (ct.c_double * 6)()
-        n = (ct.c_int64 * 6)()
+        ms = (ct.c_double * 7)()
+        n = (ct.c_int64 * 7)()
         self._check(self.lib.ft_context_read_timing(self.h, ms, n), "read_timing")
         return {p: (ms[i], n[i]) for i, p in enumerate(self.PHASES)}
 
@@ -274,6 +280,17 @@ class Context:
         self._check(self.lib.ft_batch_submit(self.h, _stream(stream), arr, len(jobs), ct.byref(t)),
                     "ft_batch_submit")
         return t.value
+
+    def ft_set_exec_mode(self, mode: int):
+        self._check(self.lib.ft_set_exec_mode(self.h, mode), "ft_set_exec_mode")
+
+    def ft_set_persistent(self, blocks: int = 0, spin_limit: int = 0):
+        self._check(self.lib.ft_set_persistent(self.h, blocks, spin_limit), "ft_set_persistent")
+
+    def ft_get_exec_mode(self) -> int:
+        m = ct.c_int32()
+        self._check(self.lib.ft_get_exec_mode(self.h, ct.byref(m)), "ft_get_exec_mode")
+        return m.value
 
     def ft_set_shapes(self, best_lanes: int, search_lanes: int):
         self._check(self.lib.ft_set_shapes(self.h, ct.byref(ft_shapes(best_lanes, search_lanes))),

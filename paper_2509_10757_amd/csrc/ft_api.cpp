@@ -33,9 +33,16 @@ struct Slot {  // workspace of one frame
     } view[2];
 };
 
-// Layout of one batch's upload: the job table followed by the tile prefixes.
+// Layout of one batch's upload: the job table, the tile prefixes, then the
+// persistent kernel's state (always zero in the staging copy, so the upload
+// itself resets it).
 struct TableLayout {
-    size_t jobs_bytes, prefix_off, total;
+    size_t jobs_bytes, prefix_off, state_off, total;
+    size_t upload_bytes(int n, bool persistent) const
+    {
+        if (persistent) return state_off + sizeof(int32_t) * (kPersistHdrInts + PH_COUNT * (size_t)n);
+        return prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(n + 1);
+    }
 };
 
 TableLayout table_layout(int max_frames)
@@ -43,18 +50,31 @@ TableLayout table_layout(int max_frames)
     TableLayout t;
     t.jobs_bytes = sizeof(DevJob) * (size_t)max_frames;
     t.prefix_off = (t.jobs_bytes + 255) / 256 * 256;
-    t.total = t.prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1);
+    t.state_off = t.prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1);
+    t.state_off = (t.state_off + 255) / 256 * 256;
+    t.total = t.state_off + sizeof(int32_t) * (kPersistHdrInts + PH_COUNT * (size_t)max_frames);
     t.total = (t.total + 255) / 256 * 256;
     return t;
 }
 
+struct GraphEntry {  // an instantiated batch graph and the shape it was built for
+    int32_t n = 0;
+    int32_t totals[PH_COUNT] = {};
+    Shapes shapes;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
 struct Lane {  // one batch in flight
     std::vector<Slot> slots;
-    char *d_table = nullptr;   // device: DevJob[n] | prefixes
+    std::vector<GraphEntry> graphs;
+    char *d_table = nullptr;   // device: DevJob[n] | prefixes | persistent state
     char *h_table = nullptr;   // pinned staging of the same bytes
+    int32_t *h_abort = nullptr;   // pinned: the persistent kernel's abort flag after the batch
     hipEvent_t done = nullptr;
     uint64_t ticket = 0;
     bool used = false;
+    bool persistent = false;   // the batch in flight ran as one persistent kernel
 };
 
 }  // namespace
@@ -71,10 +91,15 @@ struct ft_context {
     std::string err;
     uint64_t next_ticket = 1;
     Shapes shapes;
+    int32_t exec_mode = FT_EXEC_GRAPH;
+    hipStream_t cap_stream = nullptr;   // graphs are captured here, launched on the caller's stream
+    int32_t persist_blocks = 0;         // 0: as many workgroups as fit on the device
+    int32_t persist_spin = kPersistSpinLimit;
+    uint64_t use_clock = 0;
     // per-phase timing: a ring of event sets, drained when it wraps or on read
     bool timing = false;
     std::vector<std::vector<hipEvent_t>> ev_sets;
-    std::vector<uint8_t> ev_pending;
+    std::vector<uint8_t> ev_pending;   // 0 free, 1 per-phase marks, 2 persistent batch
     size_t ev_next = 0;
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
@@ -437,8 +462,18 @@ void drain_set(ft_context *ctx, size_t k)
 {
     if (!ctx->ev_pending[k]) return;
     auto &ev = ctx->ev_sets[k];
-    hipEventSynchronize(ev[kPhases]);
-    for (int p = 0; p < kPhases; ++p) {
+    if (ctx->ev_pending[k] == 2) {
+        hipEventSynchronize(ev[1]);
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) {
+            ctx->phase_ms[kPersistSlot] += ms;
+            ctx->phase_n[kPersistSlot] += 1;
+        }
+        ctx->ev_pending[k] = 0;
+        return;
+    }
+    hipEventSynchronize(ev[PH_COUNT]);
+    for (int p = 0; p < PH_COUNT; ++p) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[p], ev[p + 1]) == hipSuccess && ms > 0.0f) {
             ctx->phase_ms[p] += ms;
@@ -449,13 +484,13 @@ void drain_set(ft_context *ctx, size_t k)
 }
 
 // Event set for the next launch (nullptr when timing is off).
-hipEvent_t *next_events(ft_context *ctx)
+hipEvent_t *next_events(ft_context *ctx, bool persistent = false)
 {
     if (!ctx->timing) return nullptr;
     const size_t k = ctx->ev_next;
     ctx->ev_next = (k + 1) % kEventSets;
     drain_set(ctx, k);
-    ctx->ev_pending[k] = 1;
+    ctx->ev_pending[k] = persistent ? 2 : 1;
     return ctx->ev_sets[k].data();
 }
 
@@ -578,16 +613,84 @@ Lane *free_lane(ft_context *ctx, int *id, ft_status *st)
     return nullptr;
 }
 
-// Uploads the staged table and launches every phase over the batch.
+// Uploads the staged table and launches the batch: one kernel per phase, or
+// one persistent kernel whose abort flag is copied back afterwards.
 ft_status launch_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, hipStream_t s,
-                       const int32_t totals[PH_COUNT], hipEvent_t *ev)
+                       const int32_t totals[PH_COUNT], hipEvent_t *ev, bool persistent)
 {
-    const size_t bytes = ctx->layout.prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(n + 1);
+    const size_t bytes = ctx->layout.upload_bytes(n, persistent);
     HIP_TRY(ctx, hipMemcpyAsync(lane.d_table, lane.h_table, bytes, hipMemcpyHostToDevice, s));
     TileMap map{n, reinterpret_cast<const int32_t *>(lane.d_table + ctx->layout.prefix_off)};
     const DevJob *table = reinterpret_cast<const DevJob *>(lane.d_table);
+    if (persistent) {
+        int32_t *state = reinterpret_cast<int32_t *>(lane.d_table + ctx->layout.state_off);
+        int blocks = ctx->persist_blocks;
+        if (blocks <= 0 && (blocks = persistent_blocks(sh)) <= 0)
+            return fail(ctx, FT_ERR_DEVICE, "persistent kernel: occupancy query failed");
+        if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], s));
+        HIP_TRY(ctx, launch_persistent(table, map, totals, state, sh, blocks, ctx->persist_spin, s));
+        if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], s));
+        HIP_TRY(ctx, hipMemcpyAsync(lane.h_abort, state + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        return FT_OK;
+    }
     const DevJob *staged = reinterpret_cast<const DevJob *>(lane.h_table);
     HIP_TRY(ctx, launch_pipeline(table, map, totals, staged[0], sh, s, true, true, ev));
+    return FT_OK;
+}
+
+// Result of a finished batch on `lane`.
+ft_status finished(ft_context *ctx, const Lane &lane)
+{
+    if (lane.persistent && *lane.h_abort)
+        return fail(ctx, FT_ERR_ABORTED,
+                    "persistent batch aborted: a dependency wait exceeded %d sleeps; its outputs are invalid",
+                    ctx->persist_spin);
+    return FT_OK;
+}
+
+constexpr size_t kGraphsPerLane = 8;
+
+// Relaunches the lane's graph for this batch shape, capturing it first if new.
+ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, hipStream_t s,
+                             const int32_t totals[PH_COUNT])
+{
+    GraphEntry *hit = nullptr;
+    for (auto &g : lane.graphs) {
+        if (g.n == n && g.shapes.best_lanes == sh.best_lanes &&
+            g.shapes.search_lanes == sh.search_lanes &&
+            std::equal(totals, totals + PH_COUNT, g.totals)) {
+            hit = &g;
+            break;
+        }
+    }
+    if (!hit) {
+        if (lane.graphs.size() >= kGraphsPerLane) {
+            auto old = std::min_element(lane.graphs.begin(), lane.graphs.end(),
+                                        [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
+            hipGraphExecDestroy(old->exec);
+            lane.graphs.erase(old);
+        }
+        GraphEntry g;
+        g.n = n;
+        g.shapes = sh;
+        std::copy(totals, totals + PH_COUNT, g.totals);
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const ft_status st = launch_batch(ctx, lane, n, sh, ctx->cap_stream, totals, nullptr, false);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+        if (st) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(ctx, FT_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(ctx, FT_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+        lane.graphs.push_back(g);
+        hit = &lane.graphs.back();
+    }
+    hit->last_use = ++ctx->use_clock;
+    HIP_TRY(ctx, hipGraphLaunch(hit->exec, s));
     return FT_OK;
 }
 
@@ -654,6 +757,7 @@ const char *ft_status_string(ft_status s)
     case FT_ERR_CAPACITY: return "capacity exceeded";
     case FT_ERR_DEVICE: return "device error";
     case FT_ERR_UNSUPPORTED: return "unsupported";
+    case FT_ERR_ABORTED: return "batch aborted";
     default: return "unknown status";
     }
 }
@@ -698,6 +802,11 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         off += slot_bytes;
     };
     carve_at(ctx->direct);
+    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipFree(ctx->base);
+        delete ctx;
+        return FT_ERR_DEVICE;
+    }
     ctx->lanes.resize(lim->max_inflight);
     for (auto &ln : ctx->lanes) {
         ln.slots.resize(lim->max_batch_frames);
@@ -705,10 +814,13 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         ln.d_table = ctx->base + off;
         off += ctx->layout.total;
         if (hipHostMalloc((void **)&ln.h_table, ctx->layout.total, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void **)&ln.h_abort, 256, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
             ft_context_destroy(ctx);
             return FT_ERR_DEVICE;
         }
+        memset(ln.h_table, 0, ctx->layout.total);   // the persistent state part stays zero
+        *ln.h_abort = 0;
     }
     *out = ctx;
     return FT_OK;
@@ -742,8 +854,11 @@ ft_status ft_context_destroy(ft_context *ctx)
             hipEventSynchronize(ln.done);
             hipEventDestroy(ln.done);
         }
+        for (auto &g : ln.graphs) hipGraphExecDestroy(g.exec);
         if (ln.h_table) hipHostFree(ln.h_table);
+        if (ln.h_abort) hipHostFree(ln.h_abort);
     }
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     if (ctx->base) {
         hipDeviceSynchronize();
         hipFree(ctx->base);
@@ -766,6 +881,34 @@ ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *s)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: lanes must be 1, 2, 4, 8 or 16");
     ctx->shapes.best_lanes = s->best_lanes;
     ctx->shapes.search_lanes = s->search_lanes;
+    return FT_OK;
+}
+
+ft_status ft_set_exec_mode(ft_context *ctx, int32_t mode)
+{
+    if (!ctx) return FT_ERR_INVALID_ARGUMENT;
+    if (mode != FT_EXEC_EAGER && mode != FT_EXEC_GRAPH && mode != FT_EXEC_PERSISTENT)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "exec mode %d unknown", mode);
+    ctx->exec_mode = mode;
+    return FT_OK;
+}
+
+ft_status ft_set_persistent(ft_context *ctx, int32_t blocks, int32_t spin_limit)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (blocks < 0 || spin_limit < 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "persistent: negative blocks %d or spin limit %d", blocks,
+                    spin_limit);
+    ctx->persist_blocks = blocks;
+    ctx->persist_spin = spin_limit ? spin_limit : kPersistSpinLimit;
+    return FT_OK;
+}
+
+ft_status ft_get_exec_mode(const ft_context *ctx, int32_t *mode)
+{
+    if (!ctx || !mode) return FT_ERR_INVALID_ARGUMENT;
+    *mode = ctx->exec_mode;
     return FT_OK;
 }
 
@@ -833,12 +976,21 @@ ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *job
     Lane *lane = free_lane(ctx, &lane_id, &st);
     if (!lane) return st;
     if ((st = build_batch(ctx, *lane, jobs, n))) return st;
+    const bool persistent = ctx->exec_mode == FT_EXEC_PERSISTENT;
+    const Shapes sh = persistent ? persistent_shapes(ctx->shapes) : ctx->shapes;
     int32_t totals[PH_COUNT];
-    plan_batch(ctx, *lane, n, ctx->shapes, totals);
+    plan_batch(ctx, *lane, n, sh, totals);
     hipStream_t s = (hipStream_t)stream;
-    if ((st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx)))) return st;
+    if (persistent)
+        st = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx, true), true);
+    else if (ctx->exec_mode == FT_EXEC_EAGER || ctx->timing)
+        st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx), false);
+    else
+        st = launch_batch_graph(ctx, *lane, n, ctx->shapes, s, totals);
+    if (st) return st;
     HIP_TRY(ctx, hipEventRecord(lane->done, s));
     lane->used = true;
+    lane->persistent = persistent;
     lane->ticket = (ctx->next_ticket++ << 8) | (uint64_t)lane_id;
     *ticket = lane->ticket;
     return FT_OK;
@@ -858,8 +1010,11 @@ ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done)
         return FT_OK;
     }
     const hipError_t q = hipEventQuery(ln.done);
-    if (q == hipSuccess) *done = 1;
-    else if (q == hipErrorNotReady) *done = 0;
+    if (q == hipSuccess) {
+        *done = 1;
+        return finished(ctx, ln);
+    }
+    if (q == hipErrorNotReady) *done = 0;
     else return fail(ctx, FT_ERR_DEVICE, "poll: %s", hipGetErrorString(q));
     return FT_OK;
 }
@@ -874,7 +1029,7 @@ ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket)
     Lane &ln = ctx->lanes[lane_id];
     if (ln.ticket != ticket) return FT_OK;
     HIP_TRY(ctx, hipEventSynchronize(ln.done));
-    return FT_OK;
+    return finished(ctx, ln);
 }
 
 ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
@@ -910,7 +1065,7 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
             for (int r = 0; r < 4; ++r) {
                 int32_t totals[PH_COUNT];
                 plan_batch(ctx, *lane, n, sh, totals);
-                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx));
+                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx), false);
                 if (e) return e;
                 HIP_TRY(ctx, hipStreamSynchronize(s));
                 read_timing(ctx, ms, cnt);

@@ -20,7 +20,16 @@ constexpr int kKnnQueriesPerWG = 16;  // fisheye all-pairs: one 16-row MFMA bloc
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
 
-enum Phase : int { PH_SETUP = 0, PH_STEREO_A, PH_STEREO_B, PH_STEREO_C, PH_SEARCH, PH_SEARCH_FIN, PH_COUNT };
+enum Phase : int {
+    PH_SETUP = 0,    // row sort / overlap lists / cell sort
+    PH_STEREO_A,     // pinhole best match | fisheye all-pairs top-2
+    PH_REFINE,       // pinhole SAD refinement
+    PH_TRI,          // fisheye ratio + triangulation check
+    PH_STEREO_C,     // stereo resolve + outputs
+    PH_SEARCH,       // search by projection
+    PH_SEARCH_FIN,   // search resolve + outputs
+    PH_COUNT
+};
 
 enum JobFlags : int32_t {
     JOB_STEREO_PINHOLE = 1,
@@ -123,9 +132,26 @@ struct TileMap {
 void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search,
                int32_t out[PH_COUNT]);
 
+// Persistent batches: device state = [kPersistHdrInts header ints: task
+// ticket, abort flag] + done[n_jobs][PH_COUNT] completion counters.  The table
+// upload zeroes it before every launch.
+constexpr int kPersistHdrInts = 64;
+constexpr int kPersistSpinLimit = 1 << 22;   // sleeps of one dependency wait before aborting
+
+hipError_t launch_persistent(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
+                             int32_t *state, const Shapes &shapes, int blocks, int spin_limit,
+                             hipStream_t stream);
+// Lane groups the persistent kernel is built for nearest to `s`; a persistent
+// batch is planned and launched with these.
+Shapes persistent_shapes(const Shapes &s);
+// Workgroups of the persistent kernel that fit on the device at once.
+int persistent_blocks(const Shapes &shapes);
+
 // Optional per-phase event timing: when `ev` is non-null, ev[p] and ev[p+1]
 // bracket phase p on the launch stream (ev has kPhases + 1 events).
 constexpr int kPhases = FT_PHASES;
+constexpr int kPersistSlot = FT_PHASES - 1;   // timing slot of a whole persistent batch
+static_assert(kPersistSlot == PH_COUNT, "one timing slot per phase plus the persistent batch");
 
 // Launchers (ft_kernels.hip).  `table` == nullptr: one job passed by value;
 // otherwise a device job table whose flat tiles are described by `map`.

@@ -14,8 +14,10 @@
 //   stereo_a   pinhole best match: G lanes per left keypoint stream the
 //              row-sorted records of the rows that can hold a match
 //              | fisheye all-pairs top-2 on the matrix cores (int8 +-1 MFMA)
-//   stereo_b   pinhole SAD refinement, one wave per match, patches in LDS
-//              | fisheye ratio + triangulation check (float64)
+//   refine     pinhole SAD refinement, one wave per match, patches in LDS
+//   tri        fisheye ratio + triangulation check (float64; its own kernel
+//              so that its register demand does not cap the refinement's
+//              occupancy)
 //   stereo_c   pinhole duplicate resolution + median filter + outputs
 //              | fisheye duplicate resolution + outputs
 //   search     projection + window search: G lanes per map point stream the
@@ -27,6 +29,8 @@
 // land on the same XCD and share its L2.
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "ft_internal.h"
 
@@ -758,7 +762,11 @@ __device__ void ph_search(const DevJob &J, const DevView &V, int tile)
     const int m = tile * (kWG / G) + threadIdx.x / G;
     Top2<uint64_t> top = {~0ull, ~0ull};
     if (m < J.nM) {
+        // every field of the map point record is issued up front (one round trip)
         const float X = J.pos[3 * m], Y = J.pos[3 * m + 1], Z = J.pos[3 * m + 2];
+        const float nx = J.normal[3 * m], ny = J.normal[3 * m + 1], nz = J.normal[3 * m + 2];
+        const float dmin = J.dmin[m], dmax = J.dmax[m];
+        const Desc dm = load_desc(J.mdesc, m);
         const float xc = ((V.R[0] * X + V.R[1] * Y) + V.R[2] * Z) + V.t[0];
         const float yc = ((V.R[3] * X + V.R[4] * Y) + V.R[5] * Z) + V.t[1];
         const float zc = ((V.R[6] * X + V.R[7] * Y) + V.R[8] * Z) + V.t[2];
@@ -778,18 +786,11 @@ __device__ void ph_search(const DevJob &J, const DevView &V, int tile)
             }
             vis = u >= V.min_x && u <= V.max_x && v >= V.min_y && v <= V.max_y;
         }
-        float dist = 0.0f, vcos = 0.0f, dmax = 0.0f;
-        if (vis) {
-            const float pox = X - V.O[0], poy = Y - V.O[1], poz = Z - V.O[2];
-            dist = sqrtf((pox * pox + poy * poy) + poz * poz);
-            dmax = J.dmax[m];
-            const float lo = J.dist_lo * J.dmin[m], hi = J.dist_hi * dmax;
-            vis = dist >= lo && dist <= hi;
-            if (vis) {
-                vcos = ((pox * J.normal[3 * m] + poy * J.normal[3 * m + 1]) + poz * J.normal[3 * m + 2]) / dist;
-                vis = vcos >= J.cos_lim;
-            }
-        }
+        const float pox = X - V.O[0], poy = Y - V.O[1], poz = Z - V.O[2];
+        const float dist = sqrtf((pox * pox + poy * poy) + poz * poz);
+        vis = vis && dist >= J.dist_lo * dmin && dist <= J.dist_hi * dmax;
+        const float vcos = ((pox * nx + poy * ny) + poz * nz) / dist;
+        vis = vis && vcos >= J.cos_lim;
         if (vis) {
             const float ratio = dmax / dist;
             int pred = kLevels - 1;
@@ -802,11 +803,14 @@ __device__ void ph_search(const DevJob &J, const DevView &V, int tile)
             const float Rm = rbase * J.sf[pred];
             const bool gate = V.u_right != nullptr;
             const float uR = gate ? u - V.bf * (1.0f / zc) : 0.0f;
-            const int cx0 = max(cell_coord(u - Rm, V.min_x, V.inv_cw, V.cols) - 1, 0);
-            const int cx1 = min(cell_coord(u + Rm, V.min_x, V.inv_cw, V.cols) + 1, V.cols - 1);
-            const int cy0 = max(cell_coord(v - Rm, V.min_y, V.inv_ch, V.rows) - 1, 0);
-            const int cy1 = min(cell_coord(v + Rm, V.min_y, V.inv_ch, V.rows) + 1, V.rows - 1);
-            const Desc dm = load_desc(J.mdesc, m);
+            // A candidate has |x - u| < Rm up to one rounding of the subtraction,
+            // so x lies within Rm + 0.01 px of u; cell_coord is monotone, so the
+            // cells of u -+ (Rm + 0.01) bracket the cells of every candidate.
+            const float Rc = Rm + 0.01f;
+            const int cx0 = cell_coord(u - Rc, V.min_x, V.inv_cw, V.cols);
+            const int cx1 = cell_coord(u + Rc, V.min_x, V.inv_cw, V.cols);
+            const int cy0 = cell_coord(v - Rc, V.min_y, V.inv_ch, V.rows);
+            const int cy1 = cell_coord(v + Rc, V.min_y, V.inv_ch, V.rows);
             const int plo = pred - J.lv_lo, phi = pred + J.lv_hi;
             for (int cy = cy0; cy <= cy1; ++cy) {
                 const int c1 = V.cell_off[cy * V.cols + cx1 + 1];
@@ -891,11 +895,11 @@ void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search,
     out[PH_SETUP] = (pin || fish ? 1 : 0) + nv;
     if (pin) {
         out[PH_STEREO_A] = div_up(nL, kWG / s.best_lanes);
-        out[PH_STEREO_B] = div_up(nL, kRefinePerWG);
+        out[PH_REFINE] = div_up(nL, kRefinePerWG);
         out[PH_STEREO_C] = 1;
     } else if (fish) {
         out[PH_STEREO_A] = div_up(nL, kKnnQueriesPerWG);
-        out[PH_STEREO_B] = div_up(nL, kWG);
+        out[PH_TRI] = div_up(nL, kWG);
         out[PH_STEREO_C] = div_up(nL, kWG);
     }
     for (int v = 0; v < nv; ++v) {
@@ -945,14 +949,16 @@ struct JobTable {
     }
 };
 
-template <class Src>
-__global__ __launch_bounds__(kWG) void k_setup(Src src)
+// ------------------------------------------------------------ phase tasks
+// One task = one tile of one phase of one frame, run by a whole workgroup.
+// The per-phase kernels and the persistent kernel call the same functions.
+// `smem` is the workgroup's LDS scratch (kTaskLds bytes, 16-byte aligned).
+constexpr int kTaskLds = (kMaxCells + 8 + kWG) * 4;
+
+__device__ void task_setup(const DevJob &J, int tile, unsigned char *smem)
 {
-    __shared__ int lds[kMaxCells + 8];
-    __shared__ int tmp[kWG];
-    int job, tile;
-    if (!src.locate(PH_SETUP, job, tile)) return;
-    const DevJob &J = src(job);
+    int *lds = reinterpret_cast<int *>(smem);
+    int *tmp = lds + kMaxCells + 8;
     const bool stereo = J.flags & (JOB_STEREO_PINHOLE | JOB_STEREO_FISHEYE);
     if (stereo && tile == 0) {
         if (J.flags & JOB_STEREO_PINHOLE) ph_rowsort(J, lds, tmp);
@@ -964,41 +970,89 @@ __global__ __launch_bounds__(kWG) void k_setup(Src src)
     ph_cellsort(V, V.side ? J.R : J.L, lds, tmp);
 }
 
-template <class Src, int G>
-__global__ __launch_bounds__(kWG) void k_stereo_a(Src src)
+template <int G>
+__device__ void task_stereo_a(const DevJob &J, int tile, unsigned char *smem)
 {
-    __shared__ uint64_t tab[256];
-    __shared__ uint32_t part[4 * 16 * 2];
-    int job, tile;
-    if (!src.locate(PH_STEREO_A, job, tile)) return;
-    const DevJob &J = src(job);
+    uint64_t *tab = reinterpret_cast<uint64_t *>(smem);
+    uint32_t *part = reinterpret_cast<uint32_t *>(smem + 256 * sizeof(uint64_t));
     if (J.flags & JOB_STEREO_PINHOLE) ph_best<G>(J, tile);
     else ph_knn(J, tile, tab, part);
 }
 
-template <class Src>
-__global__ __launch_bounds__(kWG) void k_stereo_b(Src src)
+__device__ void task_stereo_c(const DevJob &J, int tile, unsigned char *smem)
 {
-    __shared__ uint8_t lds[kRefinePerWG * kRefineLds];
+    int *hist = reinterpret_cast<int *>(smem);
+    int *tmp = hist + 256;
+    int *sh = tmp + kWG;
+    uint32_t *surv = reinterpret_cast<uint32_t *>(sh + 8);
+    if (J.flags & JOB_STEREO_PINHOLE) ph_median(J, hist, tmp, surv, sh);
+    else ph_fish_final(J, tile);
+}
+
+template <int G>
+__device__ void task_search(const DevJob &J, int tile)
+{
+    const int tpv = search_tiles_per_view(J, G);
+    const int v = tile / tpv;
+    if (v >= J.n_views) return;
+    ph_search<G>(J, J.view[v], tile - v * tpv);
+}
+
+__device__ void task_search_final(const DevJob &J, int tile)
+{
+    const int t0 = final_tiles_view(J, 0);
+    const int v = tile < t0 ? 0 : 1;
+    if (v >= J.n_views) return;
+    ph_search_final(J, J.view[v], view_kp(J, v), tile - (v ? t0 : 0));
+}
+
+static_assert(256 * 8 + 4 * 16 * 2 * 4 <= kTaskLds, "stereo_a LDS");
+static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
+static_assert((256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4 <= kTaskLds, "median LDS");
+
+// ------------------------------------------------------- per-phase kernels
+template <class Src>
+__global__ __launch_bounds__(kWG) void k_setup(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[kTaskLds];
     int job, tile;
-    if (!src.locate(PH_STEREO_B, job, tile)) return;
-    const DevJob &J = src(job);
-    if (J.flags & JOB_STEREO_PINHOLE) ph_refine(J, tile, lds);
-    else ph_tri(J, tile);
+    if (!src.locate(PH_SETUP, job, tile)) return;
+    task_setup(src(job), tile, smem);
+}
+
+template <class Src, int G>
+__global__ __launch_bounds__(kWG) void k_stereo_a(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[256 * 8 + 4 * 16 * 2 * 4];
+    int job, tile;
+    if (!src.locate(PH_STEREO_A, job, tile)) return;
+    task_stereo_a<G>(src(job), tile, smem);
+}
+
+template <class Src>
+__global__ __launch_bounds__(kWG) void k_refine(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[kRefinePerWG * kRefineLds];
+    int job, tile;
+    if (!src.locate(PH_REFINE, job, tile)) return;
+    ph_refine(src(job), tile, smem);
+}
+
+template <class Src>
+__global__ __launch_bounds__(kWG) void k_tri(Src src)
+{
+    int job, tile;
+    if (!src.locate(PH_TRI, job, tile)) return;
+    ph_tri(src(job), tile);
 }
 
 template <class Src>
 __global__ __launch_bounds__(kWG) void k_stereo_c(Src src)
 {
-    __shared__ int hist[256];
-    __shared__ int tmp[kWG];
-    __shared__ uint32_t surv[(kMaxKp + 32) / 32];
-    __shared__ int sh[4];
+    __shared__ __align__(16) unsigned char smem[(256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4];
     int job, tile;
     if (!src.locate(PH_STEREO_C, job, tile)) return;
-    const DevJob &J = src(job);
-    if (J.flags & JOB_STEREO_PINHOLE) ph_median(J, hist, tmp, surv, sh);
-    else ph_fish_final(J, tile);
+    task_stereo_c(src(job), tile, smem);
 }
 
 template <class Src, int G>
@@ -1006,10 +1060,7 @@ __global__ __launch_bounds__(kWG) void k_search(Src src)
 {
     int job, tile;
     if (!src.locate(PH_SEARCH, job, tile)) return;
-    const DevJob &J = src(job);
-    const int tpv = search_tiles_per_view(J, G);
-    const int v = tile / tpv;
-    ph_search<G>(J, J.view[v], tile - v * tpv);
+    task_search<G>(src(job), tile);
 }
 
 template <class Src>
@@ -1017,10 +1068,182 @@ __global__ __launch_bounds__(kWG) void k_search_final(Src src)
 {
     int job, tile;
     if (!src.locate(PH_SEARCH_FIN, job, tile)) return;
-    const DevJob &J = src(job);
-    const int t0 = final_tiles_view(J, 0);
-    const int v = tile < t0 ? 0 : 1;
-    ph_search_final(J, J.view[v], view_kp(J, v), tile - (v ? t0 : 0));
+    task_search_final(src(job), tile);
+}
+
+// ------------------------------------------------------- persistent kernel
+// One launch runs every task of a batch.  Tasks (phase, frame, tile) are
+// numbered phase by phase; a workgroup takes the next ticket, waits until the
+// frame's prerequisite phases have completed, runs the task and counts it as
+// done.  A task only ever waits for tasks with smaller tickets, which running
+// workgroups already hold, so the waits always end; a wait longer than
+// kPersistSpinLimit sleeps raises the abort flag and every workgroup leaves.
+struct PersistArgs {
+    const DevJob *jobs;
+    TileMap map;
+    int32_t task_off[PH_COUNT + 1];
+    int32_t *hdr;    // [0] next ticket, [1] abort
+    int32_t *done;   // [n_jobs][PH_COUNT]
+    int32_t spin_limit;
+};
+
+__device__ __forceinline__ int phase_tiles(const TileMap &m, int p, int j)
+{
+    const int32_t *pre = m.prefix + p * (m.n_jobs + 1);
+    return pre[j + 1] - pre[j];
+}
+
+__device__ __forceinline__ bool phase_done(const PersistArgs &a, int j, int p)
+{
+    const int c = __hip_atomic_load(&a.done[j * PH_COUNT + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return c >= phase_tiles(a.map, p, j);
+}
+
+// A task of phase p waits for every earlier phase of its frame (refinement
+// and triangulation do not wait for each other).  Checking all of them, not
+// only the direct predecessors, keeps the order right when a phase has no
+// tiles for the frame.
+__device__ bool deps_ready(const PersistArgs &a, int j, int p)
+{
+    for (int q = 0; q < p; ++q) {
+        if (p == PH_TRI && q == PH_REFINE) continue;
+        if (!phase_done(a, j, q)) return false;
+    }
+    return true;
+}
+
+// Every branch between two barriers of the task loop is wave-uniform and known
+// to be so (wave index and LDS values pass through readfirstlane; the atomics
+// are issued by all lanes of wave 0, lanes other than 0 adding nothing).  A
+// lane-divergent guard there (say, "thread 0 takes the ticket") lets the
+// compiler run the other lanes of wave 0 round the loop to the next barrier
+// with lane 0 parked, so the workgroup would pass the barrier before the next
+// task is published.
+template <int GB, int GS>
+__global__ __launch_bounds__(kWG) void k_persistent(PersistArgs a)
+{
+    __shared__ __align__(16) unsigned char smem[kTaskLds];
+    __shared__ int s_ctl[4];   // job, phase, tile, stop
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int one = (threadIdx.x & 63) == 0 ? 1 : 0;
+    const int total = a.task_off[PH_COUNT];
+    for (;;) {
+        if (wave == 0) {
+            const int t = __builtin_amdgcn_readfirstlane(atomicAdd(&a.hdr[0], one));
+            int stop = t >= total, job = 0, p = 0, tile = 0;
+            if (!stop) {
+                while (t >= a.task_off[p + 1]) ++p;
+                const int b = t - a.task_off[p];
+                const int32_t *pre = a.map.prefix + p * (a.map.n_jobs + 1);
+                int lo = 0, hi = a.map.n_jobs;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (__builtin_amdgcn_readfirstlane(pre[mid]) <= b) lo = mid;
+                    else hi = mid;
+                }
+                job = lo;
+                tile = b - __builtin_amdgcn_readfirstlane(pre[lo]);
+                int spins = 0;
+                while (!__builtin_amdgcn_readfirstlane((int)deps_ready(a, job, p))) {
+                    const int abort_now = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(&a.hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (abort_now) {
+                        stop = 1;
+                        break;
+                    }
+                    if (++spins > a.spin_limit) {
+                        atomicExch(&a.hdr[1], 1);
+                        stop = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            s_ctl[0] = job;   // every lane of wave 0 stores the same values
+            s_ctl[1] = p;
+            s_ctl[2] = tile;
+            s_ctl[3] = stop;
+        }
+        __syncthreads();
+        if (__builtin_amdgcn_readfirstlane(s_ctl[3])) break;
+        const int job = __builtin_amdgcn_readfirstlane(s_ctl[0]);
+        const int p = __builtin_amdgcn_readfirstlane(s_ctl[1]);
+        const int tile = __builtin_amdgcn_readfirstlane(s_ctl[2]);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the prerequisite phases' writes
+        const DevJob &J = a.jobs[job];
+        switch (p) {
+        case PH_SETUP: task_setup(J, tile, smem); break;
+        case PH_STEREO_A: task_stereo_a<GB>(J, tile, smem); break;
+        case PH_REFINE: ph_refine(J, tile, smem); break;
+        case PH_TRI: ph_tri(J, tile); break;
+        case PH_STEREO_C: task_stereo_c(J, tile, smem); break;
+        case PH_SEARCH: task_search<GS>(J, tile); break;
+        default: task_search_final(J, tile); break;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // publish this task's writes
+        __syncthreads();
+        if (wave == 0)
+            __hip_atomic_fetch_add(&a.done[job * PH_COUNT + p], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int GB, int GS>
+static void *persistent_fn()
+{
+    return reinterpret_cast<void *>(&k_persistent<GB, GS>);
+}
+
+Shapes persistent_shapes(const Shapes &s)
+{
+    Shapes r = s;
+    r.best_lanes = s.best_lanes <= 4 ? 4 : (s.best_lanes >= 16 ? 16 : 8);
+    r.search_lanes = s.search_lanes <= 1 ? 1 : (s.search_lanes >= 4 ? 4 : 2);
+    return r;
+}
+
+// The instantiation for exactly these lane groups, or null.
+static void *pick_persistent(const Shapes &s)
+{
+    const int gb = s.best_lanes, gs = s.search_lanes;
+    if (gb == 4 && gs == 1) return persistent_fn<4, 1>();
+    if (gb == 4 && gs == 2) return persistent_fn<4, 2>();
+    if (gb == 4 && gs == 4) return persistent_fn<4, 4>();
+    if (gb == 8 && gs == 1) return persistent_fn<8, 1>();
+    if (gb == 8 && gs == 2) return persistent_fn<8, 2>();
+    if (gb == 8 && gs == 4) return persistent_fn<8, 4>();
+    if (gb == 16 && gs == 1) return persistent_fn<16, 1>();
+    if (gb == 16 && gs == 2) return persistent_fn<16, 2>();
+    if (gb == 16 && gs == 4) return persistent_fn<16, 4>();
+    return nullptr;
+}
+
+int persistent_blocks(const Shapes &shapes)
+{
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    void *fn = pick_persistent(shapes);
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWG, 0) != hipSuccess) return 0;
+    return per_cu * prop.multiProcessorCount;
+}
+
+hipError_t launch_persistent(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
+                             int32_t *state, const Shapes &shapes, int blocks, int spin_limit,
+                             hipStream_t stream)
+{
+    PersistArgs a;
+    a.spin_limit = spin_limit;
+    a.jobs = table;
+    a.map = map;
+    a.task_off[0] = 0;
+    for (int p = 0; p < PH_COUNT; ++p) a.task_off[p + 1] = a.task_off[p] + totals[p];
+    a.hdr = state;
+    a.done = state + kPersistHdrInts;
+    void *args[] = {&a};
+    const int grid = std::max(1, std::min(blocks, a.task_off[PH_COUNT]));
+    void *fn = pick_persistent(shapes);
+    if (!fn) return hipErrorInvalidValue;   // tiles were planned for other lane groups
+    return hipLaunchKernel(fn, dim3(grid), dim3(kWG), args, 0, stream);
 }
 
 template <class Src>
@@ -1062,17 +1285,19 @@ static hipError_t run(Src src, const int32_t *tot, const Shapes &sh, hipStream_t
     mark(1);
     if (do_stereo && tot[PH_STEREO_A] > 0) launch_best(src, sh.best_lanes, tot[PH_STEREO_A], s);
     mark(2);
-    if (do_stereo && tot[PH_STEREO_B] > 0)
-        hipLaunchKernelGGL(k_stereo_b<Src>, dim3(tot[PH_STEREO_B]), blk, 0, s, src);
+    if (do_stereo && tot[PH_REFINE] > 0)
+        hipLaunchKernelGGL(k_refine<Src>, dim3(tot[PH_REFINE]), blk, 0, s, src);
     mark(3);
+    if (do_stereo && tot[PH_TRI] > 0) hipLaunchKernelGGL(k_tri<Src>, dim3(tot[PH_TRI]), blk, 0, s, src);
+    mark(4);
     if (do_stereo && tot[PH_STEREO_C] > 0)
         hipLaunchKernelGGL(k_stereo_c<Src>, dim3(tot[PH_STEREO_C]), blk, 0, s, src);
-    mark(4);
-    if (do_search && tot[PH_SEARCH] > 0) launch_search(src, sh.search_lanes, tot[PH_SEARCH], s);
     mark(5);
+    if (do_search && tot[PH_SEARCH] > 0) launch_search(src, sh.search_lanes, tot[PH_SEARCH], s);
+    mark(6);
     if (do_search && tot[PH_SEARCH_FIN] > 0)
         hipLaunchKernelGGL(k_search_final<Src>, dim3(tot[PH_SEARCH_FIN]), blk, 0, s, src);
-    mark(6);
+    mark(7);
     return hipGetLastError();
 }
 

@@ -1,0 +1,440 @@
+"""Continuous-batching serving loop for many camera streams.
+
+Frames from many streams arrive over time.  Each frame is one stereo pair
+matched plus search by projection against its stream's local map (the map is
+device-resident from admission on, Section IV-E's "transfer only what is
+needed").  The scheduler
+
+  * admits streams while their device footprint fits the HBM budget,
+  * queues arriving frames (FIFO),
+  * whenever an in-flight slot frees up, coalesces the pending frames into one
+    batch (up to `max_batch`) and submits it, so work that arrives while other
+    batches run is admitted as soon as capacity frees up; up to `max_inflight`
+    batches run concurrently on separate HIP streams,
+  * stamps each frame's latency from its arrival time to the moment the host
+    sees its batch complete (frame upload included).
+
+`mode="per_frame"` serves the same arrivals through the single-frame calls,
+one frame at a time as it arrives (the plain per-frame GPU path), for the
+comparison at equal p99 latency.
+
+The scheduler only talks to an executor (`launch`, `done`, `release`), so its
+logic is tested on the CPU with a fake executor.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes as ct
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Frame:
+    stream: int
+    seq: int
+    arrival: float          # seconds since the start of the run
+    done: float = -1.0
+    failed: bool = False
+
+
+@dataclass
+class Stats:
+    completed: int = 0
+    failed: int = 0
+    rejected_streams: list = field(default_factory=list)
+    dropped_frames: int = 0
+    batches: int = 0
+    latencies_ms: list = field(default_factory=list)
+    wall_s: float = 0.0
+
+    def summary(self) -> dict:
+        lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
+        return {"frames": self.completed, "failed": self.failed,
+                "dropped_frames": self.dropped_frames, "rejected_streams": self.rejected_streams,
+                "batches": self.batches,
+                "frames_per_s": self.completed / self.wall_s if self.wall_s > 0 else 0.0,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_batch": self.completed / max(self.batches, 1)}
+
+
+class Scheduler:
+    """Stream registry, admission, FIFO coalescing and latency accounting."""
+
+    def __init__(self, executor, hbm_budget: int, max_batch: int = 64, max_inflight: int = 4,
+                 mode: str = "batched", clock=time.perf_counter, timeout_s: float = 10.0):
+        assert mode in ("batched", "per_frame")
+        self.ex = executor
+        self.budget = hbm_budget
+        self.used = 0
+        self.max_batch = max_batch if mode == "batched" else 1
+        self.max_inflight = max_inflight
+        self.mode = mode
+        self.clock = clock
+        self.timeout_s = timeout_s
+        self.streams = {}
+        self.pending = collections.deque()
+        self.inflight = []           # (handle, frames, launch time)
+        self.stats = Stats()
+        self.t0 = None
+
+    # -- admission ---------------------------------------------------------
+    def register_stream(self, sid: int, footprint: int) -> bool:
+        if self.used + footprint > self.budget:
+            self.stats.rejected_streams.append(sid)
+            return False
+        self.ex.admit(sid)
+        self.streams[sid] = footprint
+        self.used += footprint
+        return True
+
+    def remove_stream(self, sid: int):
+        """Drop a stream: its queued frames are dropped, its in-flight frames
+        finish (their results are simply not used)."""
+        if sid not in self.streams:
+            return
+        kept = collections.deque(f for f in self.pending if f.stream != sid)
+        self.stats.dropped_frames += len(self.pending) - len(kept)
+        self.pending = kept
+        self.used -= self.streams.pop(sid)
+        self.ex.evict(sid)
+
+    def arrive(self, frame: Frame):
+        if frame.stream in self.streams:
+            self.pending.append(frame)
+        else:
+            self.stats.dropped_frames += 1
+
+    # -- one scheduling step ------------------------------------------------
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def poll(self):
+        still = []
+        for h, frames, t_launch in self.inflight:
+            try:
+                ok = self.ex.done(h)
+            except Exception:
+                ok, err = True, True
+            else:
+                err = False
+            if not ok and self.now() - t_launch > self.timeout_s:
+                ok, err = True, True
+            if ok:
+                t = self.now()
+                for f in frames:
+                    f.done = t
+                    if err:
+                        f.failed = True
+                        self.stats.failed += 1
+                    else:
+                        self.stats.completed += 1
+                        self.stats.latencies_ms.append((t - f.arrival) * 1e3)
+                self.ex.release(h)
+            else:
+                still.append((h, frames, t_launch))
+        self.inflight = still
+
+    def launch(self) -> bool:
+        if not self.pending or len(self.inflight) >= self.max_inflight:
+            return False
+        n = min(self.max_batch, len(self.pending), self.ex.free_slots())
+        if n <= 0:
+            return False
+        frames = [self.pending.popleft() for _ in range(n)]
+        try:
+            h = self.ex.launch(frames, per_frame=self.mode == "per_frame")
+        except Exception:
+            for f in frames:
+                f.failed = True
+                self.stats.failed += 1
+            return True
+        self.inflight.append((h, frames, self.now()))
+        self.stats.batches += 1
+        return True
+
+    def run(self, arrivals, drain_s: float = 2.0) -> Stats:
+        """Serve `arrivals` = [(time_s, stream, seq)] in real time."""
+        self.t0 = self.clock()
+        i, n = 0, len(arrivals)
+        end = arrivals[-1][0] if n else 0.0
+        while True:
+            now = self.now()
+            while i < n and arrivals[i][0] <= now:
+                t, s, q = arrivals[i]
+                self.arrive(Frame(s, q, t))
+                i += 1
+            self.poll()
+            while self.launch():
+                pass
+            if i >= n and not self.pending and not self.inflight:
+                break
+            if now > end + drain_s + self.timeout_s:
+                for _, frames, _ in self.inflight:
+                    for f in frames:
+                        f.failed = True
+                        self.stats.failed += 1
+                self.inflight = []
+                break
+        self.stats.wall_s = max(self.now(), end)
+        return self.stats
+
+
+# --------------------------------------------------------------------------
+# Device executor
+# --------------------------------------------------------------------------
+class _Packed:
+    """One frame's keypoint data in a single buffer of 256-byte aligned parts."""
+
+    FIELDS = ("Lx", "Ly", "Rx", "Ry", "Ldesc", "Rdesc", "Loct", "Roct", "pre0", "pre1")
+
+    @staticmethod
+    def layout(n_max: int):
+        sizes = {"Lx": 4 * n_max, "Ly": 4 * n_max, "Rx": 4 * n_max, "Ry": 4 * n_max,
+                 "Ldesc": 32 * n_max, "Rdesc": 32 * n_max, "Loct": n_max, "Roct": n_max,
+                 "pre0": n_max, "pre1": n_max}
+        off, out = 0, {}
+        for k in _Packed.FIELDS:
+            out[k] = off
+            off += (sizes[k] + 255) // 256 * 256
+        return out, off
+
+
+class DeviceExecutor:
+    """Runs batches through the HIP library with stream maps resident on the
+    device and one upload (pinned host -> device slot) per frame."""
+
+    def __init__(self, streams, max_batch: int = 64, max_inflight: int = 4, max_kp: int = 4096,
+                 device: str = "cuda"):
+        import torch
+
+        from . import binding as ft
+        self.torch, self.ft = torch, ft
+        self.streams = {s["id"]: s for s in streams}
+        self.max_batch, self.max_inflight = max_batch, max_inflight
+        n_map = max(s["n_map"] for s in streams)
+        self.ctx = ft.Context(ft.default_limits(max_kp_per_image=max_kp, max_map_points=max(n_map, 1),
+                                                max_batch_frames=max_batch, max_inflight=max_inflight))
+        self.hip_streams = [torch.cuda.Stream(device=device) for _ in range(max_inflight)]
+        self.layout, self.slot_bytes = _Packed.layout(max_kp)
+        n_slots = max_batch * max_inflight
+        self.dev = torch.empty((n_slots, self.slot_bytes), dtype=torch.uint8, device=device)
+        self.free = list(range(n_slots))
+        self.maps = {}
+        self.pinned = {}       # (stream, pool index) -> pinned packed frame
+        self.pyr = {}          # id(pyramid dict) -> device tensor
+        self.outs = [self._alloc_outputs(max_kp, n_map, device) for _ in range(n_slots)]
+        self.device = device
+        self.handles = {}
+        self.next_h = 0
+
+    # -- residency -----------------------------------------------------------
+    def admit(self, sid):
+        if sid in self.maps:
+            return
+        torch = self.torch
+        s = self.streams[sid]
+        mp = s["frames"][0]["map"]
+        self.maps[sid] = {k: torch.from_numpy(np.ascontiguousarray(v)).to(self.device) for k, v in mp.items()}
+        for q, f in enumerate(s["frames"]):
+            self.pinned[(sid, q)] = self._pack(f)
+            for key in ("pyr_left", "pyr_right"):
+                if key in f and id(f[key]) not in self.pyr:
+                    self.pyr[id(f[key])] = torch.from_numpy(f[key]["data"]).to(self.device)
+
+    def evict(self, sid):
+        self.maps.pop(sid, None)
+        for k in [k for k in self.pinned if k[0] == sid]:
+            del self.pinned[k]
+
+    def footprint(self, sid) -> int:
+        """Device bytes a stream holds while admitted: its map (64 bytes per
+        point) and, for pinhole streams, one pyramid pair per pooled frame."""
+        s = self.streams[sid]
+        pyr = 0
+        if s["kind"] == "pinhole":
+            pyr = sum(f["pyr_left"]["data"].size + f["pyr_right"]["data"].size for f in s["frames"])
+        return s["map_bytes"] + pyr
+
+    def _pack(self, f):
+        torch = self.torch
+        buf = torch.zeros(self.slot_bytes, dtype=torch.uint8).pin_memory()
+        a = buf.numpy()
+        L, R = f["left"], f["right"]
+        n = len(L["x"])
+        lay = self.layout
+
+        def put(key, arr):
+            b = np.ascontiguousarray(arr).view(np.uint8).reshape(-1)
+            a[lay[key]:lay[key] + b.size] = b
+        put("Lx", L["x"].astype(np.float32)); put("Ly", L["y"].astype(np.float32))
+        put("Rx", R["x"].astype(np.float32)); put("Ry", R["y"].astype(np.float32))
+        put("Ldesc", L["desc"]); put("Rdesc", R["desc"])
+        put("Loct", L["octave"]); put("Roct", R["octave"])
+        for v, spec in enumerate(f["search"]):
+            put("pre%d" % v, spec["preassigned"].astype(np.uint8))
+        return buf, n
+
+    def _alloc_outputs(self, kp, nm, device):
+        torch = self.torch
+        i32 = dict(dtype=torch.int32, device=device)
+        f32 = dict(dtype=torch.float32, device=device)
+        return {"right_idx": torch.empty(kp, **i32), "dist": torch.empty(kp, **i32),
+                "u_right": torch.empty(kp, **f32), "depth": torch.empty(kp, **f32),
+                "sad": torch.empty(kp, **i32), "xyz": torch.empty((kp, 3), **f32),
+                "n_stereo": torch.empty(1, **i32),
+                "mp_match": torch.empty((2, max(nm, 1)), **i32), "mp_dist": torch.empty((2, max(nm, 1)), **i32),
+                "kp_match": torch.empty((2, kp), **i32), "n_search": torch.empty(2, **i32)}
+
+    # -- jobs ------------------------------------------------------------------
+    def _job(self, f, n, slot):
+        ft = self.ft
+        base = self.dev[slot].data_ptr()
+        lay = self.layout
+        o = self.outs[slot]
+        sc = f["scales"]
+        j = ft.ft_frame_job()
+        j.left = ft.ft_keypoints(n, base + lay["Lx"], base + lay["Ly"], base + lay["Loct"], base + lay["Ldesc"])
+        j.right = ft.ft_keypoints(n, base + lay["Rx"], base + lay["Ry"], base + lay["Roct"], base + lay["Rdesc"])
+        j.scales = ft._scales(sc)
+        if f["kind"] == "pinhole":
+            j.kind = ft.FT_JOB_PINHOLE
+            for key, dst in (("pyr_left", "pyr_left"), ("pyr_right", "pyr_right")):
+                p = f[key]
+                s = ft.ft_pyramid()
+                s.data = self.pyr[id(p)].data_ptr()
+                s.offset[:] = [int(v) for v in p["offset"]]
+                s.width[:] = [int(v) for v in p["width"]]
+                s.height[:] = [int(v) for v in p["height"]]
+                setattr(j, dst, s)
+            c, sp = f["stereo_cam"], f["stereo_params"]
+            j.pinhole = ft.ft_pinhole_stereo(float(c["fx"]), float(c["bf"]), float(c["b"]), int(c["rows"]))
+            j.pinhole_params = ft.ft_pinhole_params(sp["th_orb"], sp["half_win"], sp["half_range"],
+                                                    sp["level_window"], sp["median_num"], sp["median_den"],
+                                                    sp["band"])
+            j.pinhole_out = ft.ft_pinhole_out(o["right_idx"].data_ptr(), o["dist"].data_ptr(),
+                                              o["u_right"].data_ptr(), o["depth"].data_ptr(),
+                                              o["sad"].data_ptr(), o["n_stereo"].data_ptr())
+            j.use_u_right = 1
+        else:
+            j.kind = ft.FT_JOB_FISHEYE
+            c, sp = f["stereo_cam"], f["stereo_params"]
+            fs = ft.ft_fisheye_stereo()
+            fs.left, fs.right = ft._kb(c["left"]), ft._kb(c["right"])
+            fs.R_lr[:] = [float(v) for v in np.asarray(c["R_lr"], np.float32).reshape(-1)]
+            fs.t_lr[:] = [float(v) for v in c["t_lr"]]
+            fs.overlap_left[:] = [float(v) for v in c["overlap_left"]]
+            fs.overlap_right[:] = [float(v) for v in c["overlap_right"]]
+            j.fisheye = fs
+            j.fisheye_params = ft.ft_fisheye_params(sp["ratio_num"], sp["ratio_den"], sp["newton_iters"], 0,
+                                                    sp["cos_parallax_max"], sp["chi2"],
+                                                    float(np.deg2rad(sp["max_theta_deg"])), sp["newton_tol"])
+            j.fisheye_out = ft.ft_fisheye_out(o["right_idx"].data_ptr(), o["dist"].data_ptr(),
+                                              o["depth"].data_ptr(), o["xyz"].data_ptr(),
+                                              o["n_stereo"].data_ptr())
+        m = self.maps[f["_stream"]]
+        j.map = ft.ft_map_points(len(f["map"]["dmin"]), m["pos"].data_ptr(), m["normal"].data_ptr(),
+                                 m["dmin"].data_ptr(), m["dmax"].data_ptr(), m["desc"].data_ptr())
+        j.search_params = ft.search_params_struct(f["search_params"])
+        j.n_views = len(f["search"])
+        for v, spec in enumerate(f["search"]):
+            j.cam[v] = ft.search_camera_struct(spec["cam"])
+            j.grid[v] = ft.ft_grid(*spec["grid"])
+            j.preassigned[v] = base + lay["pre%d" % v]
+            j.search_out[v] = ft.ft_search_out(o["mp_match"][v].data_ptr(), o["mp_dist"][v].data_ptr(),
+                                               o["kp_match"][v].data_ptr(), o["n_search"][v:v + 1].data_ptr())
+        return j
+
+    # -- executor protocol -----------------------------------------------------
+    def free_slots(self) -> int:
+        return len(self.free)
+
+    def launch(self, frames, per_frame=False):
+        torch = self.torch
+        # single-frame calls share the context's one workspace: keep them on one
+        # stream; each in-flight batch owns its own workspace lane
+        lane = 0 if per_frame else self.next_h % self.max_inflight
+        hs = self.hip_streams[lane]
+        slots = [self.free.pop() for _ in frames]
+        jobs = []
+        with torch.cuda.stream(hs):
+            for fr, slot in zip(frames, slots):
+                s = self.streams[fr.stream]
+                q = fr.seq % len(s["frames"])
+                buf, n = self.pinned[(fr.stream, q)]
+                self.dev[slot].copy_(buf, non_blocking=True)
+                f = s["frames"][q]
+                f["_stream"] = fr.stream
+                jobs.append(self._job(f, n, slot))
+        if per_frame:
+            self._run_single(jobs[0], hs)
+            ev = torch.cuda.Event()
+            ev.record(hs)
+            token = ("event", ev)
+        else:
+            token = ("ticket", self.ctx.ft_batch_submit(jobs, hs))
+        h = self.next_h
+        self.next_h += 1
+        self.handles[h] = (token, slots, frames)
+        return h
+
+    def _run_single(self, j, hs):
+        ctx, ft = self.ctx, self.ft
+        if j.kind == ft.FT_JOB_PINHOLE:
+            ctx.ft_stereo_match_pinhole(j.left, j.right, j.pyr_left, j.pyr_right, j.scales, j.pinhole,
+                                        j.pinhole_params, j.pinhole_out, stream=hs)
+        else:
+            ctx.ft_stereo_match_fisheye(j.left, j.right, j.scales, j.fisheye, j.fisheye_params,
+                                        j.fisheye_out, stream=hs)
+        for v in range(j.n_views):
+            kps = j.left if v == 0 else j.right
+            ur = j.pinhole_out.u_right if (v == 0 and j.kind == ft.FT_JOB_PINHOLE and j.use_u_right) else None
+            ctx.ft_search_local_points(j.map, j.cam[v], kps, ur, j.preassigned[v], j.grid[v], j.scales,
+                                       j.search_params, j.search_out[v], stream=hs)
+
+    def done(self, h) -> bool:
+        token = self.handles[h][0]
+        if token[0] == "event":
+            return token[1].query()
+        return self.ctx.ft_batch_poll(token[1])
+
+    def release(self, h):
+        _, slots, _ = self.handles.pop(h)
+        self.free.extend(slots)
+
+    def results(self, slot: int, kind: str, n: int, n_map: int, n_views: int) -> dict:
+        """Copy one slot's outputs to the host (synchronises)."""
+        o = self.outs[slot]
+        self.torch.cuda.synchronize()
+        st = {"right_idx": o["right_idx"][:n].cpu().numpy(), "dist": o["dist"][:n].cpu().numpy(),
+              "n_matches": int(o["n_stereo"][0])}
+        if kind == "pinhole":
+            st.update(u_right=o["u_right"][:n].cpu().numpy(), depth=o["depth"][:n].cpu().numpy(),
+                      sad=o["sad"][:n].cpu().numpy())
+        else:
+            st.update(depth=o["depth"][:n].cpu().numpy(), xyz=o["xyz"][:n].cpu().numpy())
+        search = [{"mp_match": o["mp_match"][v][:n_map].cpu().numpy(),
+                   "mp_dist": o["mp_dist"][v][:n_map].cpu().numpy(),
+                   "kp_match": o["kp_match"][v][:n].cpu().numpy(),
+                   "n_matches": int(o["n_search"][v])} for v in range(n_views)]
+        return {"kind": kind, "stereo": st, "search": search}
+
+
+def serve(streams, duration_s: float, speedup: float = 1.0, mode: str = "batched",
+          max_batch: int = 64, max_inflight: int = 4, hbm_budget: int = 8 << 30, seed: int = 0,
+          executor=None) -> dict:
+    """Serve Poisson arrivals of every stream for `duration_s` seconds."""
+    from synth.serving import poisson_arrivals
+    ex = executor or DeviceExecutor(streams, max_batch=max_batch, max_inflight=max_inflight)
+    sch = Scheduler(ex, hbm_budget, max_batch=max_batch, max_inflight=max_inflight, mode=mode)
+    for s in streams:
+        sch.register_stream(s["id"], ex.footprint(s["id"]))
+    arr = poisson_arrivals(np.random.default_rng(seed), streams, duration_s, speedup)
+    arr = [a for a in arr if a[1] in sch.streams] + [a for a in arr if a[1] not in sch.streams]
+    arr.sort()
+    st = sch.run(arr)
+    out = st.summary()
+    out.update(mode=mode, speedup=speedup, offered_fps=len(arr) / duration_s, streams=len(streams))
+    return out

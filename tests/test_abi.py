@@ -42,6 +42,7 @@ def test_status_strings_without_device(lib):
     lib.ft_status_string.restype = ct.c_char_p
     assert lib.ft_status_string(0) == b"ok"
     assert lib.ft_status_string(2) == b"capacity exceeded"
+    assert lib.ft_status_string(5) == b"batch aborted"
     lib.ft_version.restype = ct.c_int32
     assert lib.ft_version() >= 100
 

@@ -266,3 +266,111 @@ def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
             compare_frame(d.results(), oracle.run_frame(f))
     finally:
         ctx.ft_set_shapes(8, 4)
+
+
+def test_graph_replays_match_eager(ft, ctx):
+    frames = synth.config4(n_frames=8)
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    jobs = [d.job() for d in dfs]
+    try:
+        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+        torch.cuda.synchronize()
+        ref = [d.results() for d in dfs]
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs[:5]))
+        torch.cuda.synchronize()
+        ref5 = [d.results() for d in dfs[:5]]
+        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
+        for rep in range(4):
+            for d in dfs:                                   # eager work between replays
+                for t in d.o.values():
+                    t.fill_(-7)
+                for v in d.views:
+                    for t in v["out_t"].values():
+                        t.fill_(-9)
+            torch.cuda.synchronize()
+            sub = jobs if rep % 2 == 0 else jobs[:5]
+            ctx.ft_batch_wait(ctx.ft_batch_submit(sub))
+            torch.cuda.synchronize()
+            want = ref if rep % 2 == 0 else ref5
+            for d, w in zip(dfs, want):
+                bit_equal(d.results(), w)
+    finally:
+        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
+
+
+def _clobber(dfs):
+    for d in dfs:
+        for t in d.o.values():
+            t.fill_(-7)
+        for v in d.views:
+            for t in v["out_t"].values():
+                t.fill_(-9)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n_frames,blocks", [(64, 0), (16, 1), (16, 37)])
+def test_persistent_matches_eager(ft, ctx, n_frames, blocks):
+    frames = synth.config4(n_frames=n_frames)
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    jobs = [d.job() for d in dfs]
+    say("persistent", n_frames, "frames, blocks", blocks)
+    try:
+        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+        torch.cuda.synchronize()
+        ref = [d.results() for d in dfs]
+        ctx.ft_set_exec_mode(ft.FT_EXEC_PERSISTENT)
+        ctx.ft_set_persistent(blocks, 0)
+        for rep in range(3):
+            _clobber(dfs)
+            ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+            torch.cuda.synchronize()
+            for d, w in zip(dfs, ref):
+                bit_equal(d.results(), w)
+    finally:
+        ctx.ft_set_persistent(0, 0)
+        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
+    if n_frames == 64:
+        for d, f in list(zip(dfs, frames))[:6]:
+            compare_frame(d.results(), oracle.run_frame(f))
+
+
+def test_persistent_gives_up_cleanly_and_recovers(ft, ctx):
+    """A one-sleep spin limit makes dependency waits give up: the batch is then
+    reported as failed (or, if no task had to wait, is correct), and the next
+    batch with the default limit is correct again."""
+    frames = synth.config4(n_frames=32)
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    jobs = [d.job() for d in dfs]
+    with pytest.raises(ft.FtError):
+        ctx.ft_set_persistent(-1, 0)
+    try:
+        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+        torch.cuda.synchronize()
+        ref = [d.results() for d in dfs]
+        ctx.ft_set_exec_mode(ft.FT_EXEC_PERSISTENT)
+        ctx.ft_set_persistent(0, 1)
+        _clobber(dfs)
+        t = ctx.ft_batch_submit(jobs)
+        try:
+            ctx.ft_batch_wait(t)
+            aborted = False
+        except ft.FtError as e:
+            assert e.status == ft.FT_ERR_ABORTED and "aborted" in str(e)
+            aborted = True
+        torch.cuda.synchronize()
+        say("gave up" if aborted else "finished without waiting")
+        if not aborted:
+            for d, w in zip(dfs, ref):
+                bit_equal(d.results(), w)
+        ctx.ft_set_persistent(0, 0)
+        _clobber(dfs)
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+        torch.cuda.synchronize()
+        for d, w in zip(dfs, ref):
+            bit_equal(d.results(), w)
+    finally:
+        ctx.ft_set_persistent(0, 0)
+        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
