@@ -72,6 +72,29 @@ def algorithmic_path_bytes(frames, results):
     return total
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_10757_amd", "csrc", "ft_kernels.hip")
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what
+    the counter reads for a plain copy of known size), or None when there is no
+    summary for it or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*pmc*.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("kernel_key") != kernel_key or rec.get("source_sha256") != digest:
+            continue
+        return round(rec["fetch_kib"] * rec["fetch_scale"] * 1024 + rec["write_kib"] * rec["write_scale"] * 1024)
+    return None
+
+
 def cpu_baseline(frames, budget_s=12.0):
     import oracle
     done = 0
@@ -86,7 +109,7 @@ def cpu_baseline(frames, budget_s=12.0):
 
 
 def serving_sweep(duration_s, speedups):
-    """Config-5 serving: 32 streams, both the per-frame path and continuous
+    """Serving 32 camera streams (20-30 Hz, resident maps of 2k-40k points): the per-frame path and continuous
     batching over the same Poisson arrivals, compressed in time by `speedups`."""
     from paper_2509_10757_amd import serve
     from synth.serving import make_streams
@@ -122,7 +145,8 @@ def main():
     ap.add_argument("--shapes", type=str, default="", help="best,search lanes instead of autotuning")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--exec", choices=["auto", "graph", "persistent", "eager"], default="auto",
-                    help="batch execution mode; auto times graph and persistent briefly and keeps the faster")
+                    help="batch execution mode; auto times the modes and submission splits briefly and keeps the fastest")
+    ap.add_argument("--parts", type=int, default=1, help="submission split (with an explicit --exec)")
     ap.add_argument("--serving", type=float, default=0.0, metavar="SECONDS",
                     help="also run the 32-stream serving sweep, SECONDS per run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -150,7 +174,7 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": 5}))
         return
     log("generating the 64-frame workload")
-    frames = synth.config4()
+    frames = synth.mixed_batch()
     n_frames = len(frames)
     ctx = ft.Context(ft.default_limits(max_batch_frames=n_frames, max_map_points=32768, max_inflight=4))
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
@@ -184,8 +208,10 @@ def main():
     modes = {"graph": ft.FT_EXEC_GRAPH, "persistent": ft.FT_EXEC_PERSISTENT, "eager": ft.FT_EXEC_EAGER}
     trial = {}
     if args.exec == "auto":
-        for name in ("graph", "persistent"):
+        # execution mode and submission split: a short timed trial of each
+        for name, parts in (("graph", 1), ("graph", 2), ("graph", 3), ("graph", 4), ("persistent", 1)):
             ctx.ft_set_exec_mode(modes[name])
+            ctx.ft_set_batch_parts(parts)
             for _ in range(10):
                 submit_bounded()
             drain()
@@ -193,12 +219,14 @@ def main():
             for _ in range(50):
                 submit_bounded()
             drain()
-            trial[name] = round(n_frames * 50 / (time.perf_counter() - q0), 1)
-            log("trial", name, trial[name])
-        exec_mode = max(trial, key=trial.get)
+            trial[f"{name}/{parts}"] = round(n_frames * 50 / (time.perf_counter() - q0), 1)
+            log("trial", name, parts, trial[f"{name}/{parts}"])
+        best = max(trial, key=trial.get)
+        exec_mode, n_parts = best.split("/")[0], int(best.split("/")[1])
     else:
-        exec_mode = args.exec
+        exec_mode, n_parts = args.exec, args.parts
     ctx.ft_set_exec_mode(modes[exec_mode])
+    ctx.ft_set_batch_parts(n_parts)
     persistent = exec_mode == "persistent"
 
     log("warmup", args.warmup)
@@ -275,7 +303,8 @@ def main():
         achieved = sbytes / (s_us * 1e-6) / 1e9
         search_roof = {"bound": "hbm", "kernel": "k_search (search by projection)",
                        "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                       "frac": round(achieved / HBM_PEAK_GBS, 5),
+                       "traffic": measured_traffic("k_search<JobTable>"),
                        "algorithmic_bytes_per_launch": sbytes, "avg_launch_us": round(s_us, 3),
                        "timed": "HIP events around each phase kernel, eager per-phase pass",
                        "dominant_phase": dom}
@@ -300,7 +329,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "frames_per_step": n_frames,
                    "shapes": {"best_lanes": shapes[0], "search_lanes": shapes[1]},
-                   "exec": exec_mode, "exec_trial_fps": trial or None,
+                   "exec": exec_mode, "batch_parts": n_parts, "exec_trial_fps": trial or None,
                    "pinhole_frames": sum(f["kind"] == "pinhole" for f in frames),
                    "fisheye_frames": sum(f["kind"] == "fisheye" for f in frames)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),

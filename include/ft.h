@@ -324,6 +324,18 @@ ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket);
 ft_status ft_set_exec_mode(ft_context *ctx, int32_t mode);
 ft_status ft_get_exec_mode(const ft_context *ctx, int32_t *mode);
 
+/* Split every batch submission into `parts` (1..4; default 1) runs of
+ * consecutive frames with about equal work.  Each run is launched (eagerly or
+ * as its own graph) on an internal stream of the context that first waits for
+ * the caller's stream; the caller's stream then waits for all of them, so
+ * completion, ft_batch_poll and ft_batch_wait behave as for one launch.  The
+ * runs overlap on the device: one run's latency-bound phases (sorts, median)
+ * share the GPU with another's search.  Results are identical for every value.
+ * Persistent batches and timed batches (per-phase timing enabled) are not
+ * split.  Out of range: FT_ERR_INVALID_ARGUMENT. */
+ft_status ft_set_batch_parts(ft_context *ctx, int32_t parts);
+ft_status ft_get_batch_parts(const ft_context *ctx, int32_t *parts);
+
 /* Settings of FT_EXEC_PERSISTENT.  `blocks`: workgroups of the persistent
  * kernel, 0 = as many as fit on the device at once (the default; the grid is
  * never larger than the batch's task count).  `spin_limit`: sleeps one

@@ -19,6 +19,7 @@ from . import build as _build
 LEVELS = 8
 FT_OK, FT_ERR_INVALID_ARGUMENT, FT_ERR_CAPACITY, FT_ERR_DEVICE, FT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 FT_ERR_ABORTED = 5
+FT_PHASES = 8
 FT_CAMERA_PINHOLE, FT_CAMERA_KB = 0, 1
 FT_JOB_PINHOLE, FT_JOB_FISHEYE, FT_JOB_SEARCH = 1, 2, 3
 FT_EXEC_EAGER, FT_EXEC_GRAPH, FT_EXEC_PERSISTENT = 0, 1, 2
@@ -150,6 +151,8 @@ EXPORTS = {
     "ft_set_exec_mode": [P, ct.c_int32],
     "ft_get_exec_mode": [P, ct.POINTER(ct.c_int32)],
     "ft_set_persistent": [P, ct.c_int32, ct.c_int32],
+    "ft_set_batch_parts": [P, ct.c_int32],
+    "ft_get_batch_parts": [P, ct.POINTER(ct.c_int32)],
     "ft_set_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_get_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_autotune": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.c_char_p, ct.POINTER(ft_shapes)],
@@ -242,8 +245,8 @@ class Context:
         self._check(self.lib.ft_context_enable_timing(self.h, int(enable)), "enable_timing")
 
     def ft_context_read_timing(self) -> dict:
-        ms = (ct.c_double * 7)()
-        n = (ct.c_int64 * 7)()
+        ms = (ct.c_double * FT_PHASES)()
+        n = (ct.c_int64 * FT_PHASES)()
         self._check(self.lib.ft_context_read_timing(self.h, ms, n), "read_timing")
         return {p: (ms[i], n[i]) for i, p in enumerate(self.PHASES)}
 
@@ -283,6 +286,14 @@ class Context:
 
     def ft_set_exec_mode(self, mode: int):
         self._check(self.lib.ft_set_exec_mode(self.h, mode), "ft_set_exec_mode")
+
+    def ft_set_batch_parts(self, parts: int):
+        self._check(self.lib.ft_set_batch_parts(self.h, parts), "ft_set_batch_parts")
+
+    def ft_get_batch_parts(self) -> int:
+        v = ct.c_int32()
+        self._check(self.lib.ft_get_batch_parts(self.h, ct.byref(v)), "ft_get_batch_parts")
+        return v.value
 
     def ft_set_persistent(self, blocks: int = 0, spin_limit: int = 0):
         self._check(self.lib.ft_set_persistent(self.h, blocks, spin_limit), "ft_set_persistent")

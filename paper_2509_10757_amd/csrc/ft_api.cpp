@@ -23,7 +23,7 @@ struct Slot {  // workspace of one frame
     int32_t *row_start, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
     RowRec *rrec;
     uint8_t *tdesc;
-    float *uR, *depth, *xyz;
+    float *uR, *depth, *xyz, *best_x;
     uint32_t *claimR;
     struct {
         int32_t *cell_off, *mp_k, *mp_h;
@@ -33,31 +33,33 @@ struct Slot {  // workspace of one frame
     } view[2];
 };
 
-// Layout of one batch's upload: the job table, the tile prefixes, then the
-// persistent kernel's state (always zero in the staging copy, so the upload
-// itself resets it).
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Layout of one batch table (one per part of a submission): the tile prefix
+// sums, the persistent kernel's state (always zero in the staging copy, so the
+// upload itself resets it), then the job descriptors.  One upload of the first
+// upload_bytes(n) bytes moves everything a launch reads.
 struct TableLayout {
-    size_t jobs_bytes, prefix_off, state_off, total;
-    size_t upload_bytes(int n, bool persistent) const
-    {
-        if (persistent) return state_off + sizeof(int32_t) * (kPersistHdrInts + PH_COUNT * (size_t)n);
-        return prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(n + 1);
-    }
+    size_t prefix_off = 0, state_off = 0, jobs_off = 0, total = 0;
+    size_t upload_bytes(int n) const { return jobs_off + sizeof(DevJob) * (size_t)n; }
 };
 
 TableLayout table_layout(int max_frames)
 {
     TableLayout t;
-    t.jobs_bytes = sizeof(DevJob) * (size_t)max_frames;
-    t.prefix_off = (t.jobs_bytes + 255) / 256 * 256;
-    t.state_off = t.prefix_off + sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1);
-    t.state_off = (t.state_off + 255) / 256 * 256;
-    t.total = t.state_off + sizeof(int32_t) * (kPersistHdrInts + PH_COUNT * (size_t)max_frames);
-    t.total = (t.total + 255) / 256 * 256;
+    t.state_off = align_up(sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1), 256);
+    t.jobs_off = align_up(t.state_off + sizeof(int32_t) * (kPersistHdrInts + PH_COUNT * (size_t)max_frames), 256);
+    t.total = align_up(t.jobs_off + sizeof(DevJob) * (size_t)max_frames, 256);
     return t;
 }
 
+// A batch submission runs as up to kMaxParts parts of consecutive frames, each
+// on its own internal stream, so that the latency-bound phases of one part
+// overlap the others.
+constexpr int kMaxParts = 4;
+
 struct GraphEntry {  // an instantiated batch graph and the shape it was built for
+    int32_t part = 0;
     int32_t n = 0;
     int32_t totals[PH_COUNT] = {};
     Shapes shapes;
@@ -68,8 +70,9 @@ struct GraphEntry {  // an instantiated batch graph and the shape it was built f
 struct Lane {  // one batch in flight
     std::vector<Slot> slots;
     std::vector<GraphEntry> graphs;
-    char *d_table = nullptr;   // device: DevJob[n] | prefixes | persistent state
+    char *d_table = nullptr;   // device: kMaxParts tables (prefixes | persistent state | jobs)
     char *h_table = nullptr;   // pinned staging of the same bytes
+    hipEvent_t fork = nullptr, join[kMaxParts] = {};   // split submissions
     int32_t *h_abort = nullptr;   // pinned: the persistent kernel's abort flag after the batch
     hipEvent_t done = nullptr;
     uint64_t ticket = 0;
@@ -78,6 +81,10 @@ struct Lane {  // one batch in flight
 };
 
 }  // namespace
+
+struct ft_context;
+static char *h_part(const ft_context *ctx, const Lane &l, int part);
+static char *d_part(const ft_context *ctx, const Lane &l, int part);
 
 struct ft_context {
     int device = 0;
@@ -93,6 +100,8 @@ struct ft_context {
     Shapes shapes;
     int32_t exec_mode = FT_EXEC_GRAPH;
     hipStream_t cap_stream = nullptr;   // graphs are captured here, launched on the caller's stream
+    hipStream_t part_streams[kMaxParts] = {};   // parts of a split submission run here
+    int32_t n_parts = 1;
     int32_t persist_blocks = 0;         // 0: as many workgroups as fit on the device
     int32_t persist_spin = kPersistSpinLimit;
     uint64_t use_clock = 0;
@@ -104,6 +113,16 @@ struct ft_context {
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
 };
+
+static char *h_part(const ft_context *ctx, const Lane &l, int part)
+{
+    return l.h_table + (size_t)part * ctx->layout.total;
+}
+
+static char *d_part(const ft_context *ctx, const Lane &l, int part)
+{
+    return l.d_table + (size_t)part * ctx->layout.total;
+}
 
 namespace {
 
@@ -128,7 +147,6 @@ ft_status fail(ft_context *ctx, ft_status st, const char *fmt, ...)
             return fail(ctx, FT_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Bump {
     size_t off = 0;
@@ -150,6 +168,7 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     s.tdesc = b.take<uint8_t>(base, 32 * kp);
     s.best_j = b.take<int32_t>(base, kp);
     s.best_h = b.take<int32_t>(base, kp);
+    s.best_x = b.take<float>(base, kp);
     s.h2 = b.take<int32_t>(base, kp);
     s.sad = b.take<int32_t>(base, kp);
     s.flag = b.take<int32_t>(base, kp);
@@ -231,6 +250,7 @@ void bind_stereo_ws(DevJob &J, const Slot &s)
     J.tdesc = s.tdesc;
     J.best_j = s.best_j;
     J.best_h = s.best_h;
+    J.best_x = s.best_x;
     J.h2 = s.h2;
     J.sad = s.sad;
     J.flag = s.flag;
@@ -539,7 +559,7 @@ ft_status launch_one(ft_context *ctx, const DevJob &J, hipStream_t s, bool stere
 ft_status build_batch(ft_context *ctx, Lane &lane, const ft_frame_job *jobs, int32_t n)
 {
     ft_status st;
-    DevJob *table = reinterpret_cast<DevJob *>(lane.h_table);
+    DevJob *table = reinterpret_cast<DevJob *>(h_part(ctx, lane, 0) + ctx->layout.jobs_off);
     for (int f = 0; f < n; ++f) {
         const ft_frame_job &jb = jobs[f];
         DevJob &J = table[f];
@@ -577,11 +597,12 @@ ft_status build_batch(ft_context *ctx, Lane &lane, const ft_frame_job *jobs, int
     return FT_OK;
 }
 
-// Tile prefixes of every phase into the staging table; returns the totals.
-void plan_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, int32_t totals[PH_COUNT])
+// Tile prefixes of every phase into a part's staging table; returns the totals.
+void plan_batch(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &sh, int32_t totals[PH_COUNT])
 {
-    const DevJob *table = reinterpret_cast<const DevJob *>(lane.h_table);
-    int32_t *pre = reinterpret_cast<int32_t *>(lane.h_table + ctx->layout.prefix_off);
+    char *tab = h_part(ctx, lane, part);
+    const DevJob *table = reinterpret_cast<const DevJob *>(tab + ctx->layout.jobs_off);
+    int32_t *pre = reinterpret_cast<int32_t *>(tab + ctx->layout.prefix_off);
     for (int p = 0; p < PH_COUNT; ++p) {
         pre[p * (n + 1)] = 0;
         totals[p] = 0;
@@ -594,6 +615,30 @@ void plan_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, int32_
             pre[p * (n + 1) + f + 1] = totals[p];
         }
     }
+}
+
+// Splits the n jobs staged in part 0 into `parts` runs of consecutive frames
+// with about equal work and moves runs 1.. into their own part tables.
+// bound[k]..bound[k+1] are the frames of part k; every part gets a frame.
+void split_batch(ft_context *ctx, Lane &lane, int32_t n, int parts, int32_t bound[kMaxParts + 1])
+{
+    const DevJob *table = reinterpret_cast<const DevJob *>(h_part(ctx, lane, 0) + ctx->layout.jobs_off);
+    std::vector<double> cum(n + 1, 0.0);
+    for (int f = 0; f < n; ++f) {
+        const DevJob &J = table[f];
+        const double work = 64.0 + 2.0 * ((double)J.L.n + J.R.n) + (double)J.nM * J.n_views;
+        cum[f + 1] = cum[f] + work;
+    }
+    bound[0] = 0;
+    for (int k = 1; k < parts; ++k) {
+        int f = bound[k - 1] + 1;
+        while (f < n - (parts - k) && cum[f] < cum[n] * k / parts) ++f;
+        bound[k] = f;
+    }
+    bound[parts] = n;
+    for (int k = 1; k < parts; ++k)
+        memcpy(h_part(ctx, lane, k) + ctx->layout.jobs_off, table + bound[k],
+               sizeof(DevJob) * (size_t)(bound[k + 1] - bound[k]));
 }
 
 Lane *free_lane(ft_context *ctx, int *id, ft_status *st)
@@ -613,17 +658,18 @@ Lane *free_lane(ft_context *ctx, int *id, ft_status *st)
     return nullptr;
 }
 
-// Uploads the staged table and launches the batch: one kernel per phase, or
-// one persistent kernel whose abort flag is copied back afterwards.
-ft_status launch_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, hipStream_t s,
+// Uploads a part's staged table and launches it: one kernel per phase, or one
+// persistent kernel whose abort flag is copied back afterwards.
+ft_status launch_batch(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &sh, hipStream_t s,
                        const int32_t totals[PH_COUNT], hipEvent_t *ev, bool persistent)
 {
-    const size_t bytes = ctx->layout.upload_bytes(n, persistent);
-    HIP_TRY(ctx, hipMemcpyAsync(lane.d_table, lane.h_table, bytes, hipMemcpyHostToDevice, s));
-    TileMap map{n, reinterpret_cast<const int32_t *>(lane.d_table + ctx->layout.prefix_off)};
-    const DevJob *table = reinterpret_cast<const DevJob *>(lane.d_table);
+    char *dtab = d_part(ctx, lane, part);
+    const char *htab = h_part(ctx, lane, part);
+    HIP_TRY(ctx, hipMemcpyAsync(dtab, htab, ctx->layout.upload_bytes(n), hipMemcpyHostToDevice, s));
+    TileMap map{n, reinterpret_cast<const int32_t *>(dtab + ctx->layout.prefix_off)};
+    const DevJob *table = reinterpret_cast<const DevJob *>(dtab + ctx->layout.jobs_off);
     if (persistent) {
-        int32_t *state = reinterpret_cast<int32_t *>(lane.d_table + ctx->layout.state_off);
+        int32_t *state = reinterpret_cast<int32_t *>(dtab + ctx->layout.state_off);
         int blocks = ctx->persist_blocks;
         if (blocks <= 0 && (blocks = persistent_blocks(sh)) <= 0)
             return fail(ctx, FT_ERR_DEVICE, "persistent kernel: occupancy query failed");
@@ -633,7 +679,7 @@ ft_status launch_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh,
         HIP_TRY(ctx, hipMemcpyAsync(lane.h_abort, state + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         return FT_OK;
     }
-    const DevJob *staged = reinterpret_cast<const DevJob *>(lane.h_table);
+    const DevJob *staged = reinterpret_cast<const DevJob *>(htab + ctx->layout.jobs_off);
     HIP_TRY(ctx, launch_pipeline(table, map, totals, staged[0], sh, s, true, true, ev));
     return FT_OK;
 }
@@ -648,15 +694,15 @@ ft_status finished(ft_context *ctx, const Lane &lane)
     return FT_OK;
 }
 
-constexpr size_t kGraphsPerLane = 8;
+constexpr size_t kGraphsPerLane = 8 * kMaxParts;
 
 // Relaunches the lane's graph for this batch shape, capturing it first if new.
-ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, hipStream_t s,
-                             const int32_t totals[PH_COUNT])
+ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &sh,
+                             hipStream_t s, const int32_t totals[PH_COUNT])
 {
     GraphEntry *hit = nullptr;
     for (auto &g : lane.graphs) {
-        if (g.n == n && g.shapes.best_lanes == sh.best_lanes &&
+        if (g.part == part && g.n == n && g.shapes.best_lanes == sh.best_lanes &&
             g.shapes.search_lanes == sh.search_lanes &&
             std::equal(totals, totals + PH_COUNT, g.totals)) {
             hit = &g;
@@ -671,11 +717,12 @@ ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, const Shape
             lane.graphs.erase(old);
         }
         GraphEntry g;
+        g.part = part;
         g.n = n;
         g.shapes = sh;
         std::copy(totals, totals + PH_COUNT, g.totals);
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        const ft_status st = launch_batch(ctx, lane, n, sh, ctx->cap_stream, totals, nullptr, false);
+        const ft_status st = launch_batch(ctx, lane, part, n, sh, ctx->cap_stream, totals, nullptr, false);
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
         if (st) {
@@ -790,7 +837,7 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     carve_slot(tmp, nullptr, b, *lim);
     const size_t slot_bytes = align_up(b.off, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
-    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight;
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * kMaxParts * lim->max_inflight;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -802,7 +849,12 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         off += slot_bytes;
     };
     carve_at(ctx->direct);
-    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    bool streams_ok = true;
+    for (auto &ps : ctx->part_streams)
+        streams_ok = streams_ok && hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
+    if (!streams_ok || hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        for (auto &ps : ctx->part_streams)
+            if (ps) hipStreamDestroy(ps);
         hipFree(ctx->base);
         delete ctx;
         return FT_ERR_DEVICE;
@@ -812,14 +864,17 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         ln.slots.resize(lim->max_batch_frames);
         for (auto &s : ln.slots) carve_at(s);
         ln.d_table = ctx->base + off;
-        off += ctx->layout.total;
-        if (hipHostMalloc((void **)&ln.h_table, ctx->layout.total, hipHostMallocDefault) != hipSuccess ||
+        off += ctx->layout.total * kMaxParts;
+        bool ev_ok = hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming) == hipSuccess;
+        for (auto &e : ln.join) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (!ev_ok ||
+            hipHostMalloc((void **)&ln.h_table, ctx->layout.total * kMaxParts, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void **)&ln.h_abort, 256, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
             ft_context_destroy(ctx);
             return FT_ERR_DEVICE;
         }
-        memset(ln.h_table, 0, ctx->layout.total);   // the persistent state part stays zero
+        memset(ln.h_table, 0, ctx->layout.total * kMaxParts);   // the persistent state stays zero
         *ln.h_abort = 0;
     }
     *out = ctx;
@@ -855,10 +910,15 @@ ft_status ft_context_destroy(ft_context *ctx)
             hipEventDestroy(ln.done);
         }
         for (auto &g : ln.graphs) hipGraphExecDestroy(g.exec);
+        if (ln.fork) hipEventDestroy(ln.fork);
+        for (auto &e : ln.join)
+            if (e) hipEventDestroy(e);
         if (ln.h_table) hipHostFree(ln.h_table);
         if (ln.h_abort) hipHostFree(ln.h_abort);
     }
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    for (auto &ps : ctx->part_streams)
+        if (ps) hipStreamDestroy(ps);
     if (ctx->base) {
         hipDeviceSynchronize();
         hipFree(ctx->base);
@@ -890,6 +950,23 @@ ft_status ft_set_exec_mode(ft_context *ctx, int32_t mode)
     if (mode != FT_EXEC_EAGER && mode != FT_EXEC_GRAPH && mode != FT_EXEC_PERSISTENT)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "exec mode %d unknown", mode);
     ctx->exec_mode = mode;
+    return FT_OK;
+}
+
+ft_status ft_set_batch_parts(ft_context *ctx, int32_t parts)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (parts < 1 || parts > kMaxParts)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch parts %d outside 1..%d", parts, kMaxParts);
+    ctx->n_parts = parts;
+    return FT_OK;
+}
+
+ft_status ft_get_batch_parts(const ft_context *ctx, int32_t *parts)
+{
+    if (!ctx || !parts) return FT_ERR_INVALID_ARGUMENT;
+    *parts = ctx->n_parts;
     return FT_OK;
 }
 
@@ -977,17 +1054,37 @@ ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *job
     if (!lane) return st;
     if ((st = build_batch(ctx, *lane, jobs, n))) return st;
     const bool persistent = ctx->exec_mode == FT_EXEC_PERSISTENT;
+    const bool eager = ctx->exec_mode == FT_EXEC_EAGER || ctx->timing;
     const Shapes sh = persistent ? persistent_shapes(ctx->shapes) : ctx->shapes;
-    int32_t totals[PH_COUNT];
-    plan_batch(ctx, *lane, n, sh, totals);
     hipStream_t s = (hipStream_t)stream;
-    if (persistent)
-        st = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx, true), true);
-    else if (ctx->exec_mode == FT_EXEC_EAGER || ctx->timing)
-        st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx), false);
-    else
-        st = launch_batch_graph(ctx, *lane, n, ctx->shapes, s, totals);
-    if (st) return st;
+    const int parts = (persistent || ctx->timing) ? 1 : std::min<int>(ctx->n_parts, n);
+    if (parts == 1) {
+        int32_t totals[PH_COUNT];
+        plan_batch(ctx, *lane, 0, n, sh, totals);
+        if (persistent)
+            st = launch_batch(ctx, *lane, 0, n, sh, s, totals, next_events(ctx, true), true);
+        else if (eager)
+            st = launch_batch(ctx, *lane, 0, n, sh, s, totals, next_events(ctx), false);
+        else
+            st = launch_batch_graph(ctx, *lane, 0, n, sh, s, totals);
+        if (st) return st;
+    } else {
+        int32_t bound[kMaxParts + 1];
+        split_batch(ctx, *lane, n, parts, bound);
+        HIP_TRY(ctx, hipEventRecord(lane->fork, s));
+        for (int k = 0; k < parts; ++k) {
+            const int32_t nk = bound[k + 1] - bound[k];
+            int32_t totals[PH_COUNT];
+            plan_batch(ctx, *lane, k, nk, sh, totals);
+            hipStream_t ps = ctx->part_streams[k];
+            HIP_TRY(ctx, hipStreamWaitEvent(ps, lane->fork, 0));
+            st = eager ? launch_batch(ctx, *lane, k, nk, sh, ps, totals, nullptr, false)
+                       : launch_batch_graph(ctx, *lane, k, nk, sh, ps, totals);
+            if (st) return st;
+            HIP_TRY(ctx, hipEventRecord(lane->join[k], ps));
+            HIP_TRY(ctx, hipStreamWaitEvent(s, lane->join[k], 0));
+        }
+    }
     HIP_TRY(ctx, hipEventRecord(lane->done, s));
     lane->used = true;
     lane->persistent = persistent;
@@ -1064,8 +1161,8 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
             std::vector<double> v;
             for (int r = 0; r < 4; ++r) {
                 int32_t totals[PH_COUNT];
-                plan_batch(ctx, *lane, n, sh, totals);
-                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx), false);
+                plan_batch(ctx, *lane, 0, n, sh, totals);
+                ft_status e = launch_batch(ctx, *lane, 0, n, sh, s, totals, next_events(ctx), false);
                 if (e) return e;
                 HIP_TRY(ctx, hipStreamSynchronize(s));
                 read_timing(ctx, ms, cnt);

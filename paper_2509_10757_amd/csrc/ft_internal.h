@@ -103,8 +103,9 @@ struct DevJob {
     // stereo workspace
     int32_t *row_start;               // rows + 1
     RowRec *rrec;                     // right keypoints sorted by row
-    uint8_t *tdesc;                   // fisheye: target descriptors in overlap order
+    uint8_t *tdesc;                   // right descriptors: row order (pinhole) / overlap order (fisheye)
     int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    float *best_x;                    // pinhole: x of the best right keypoint
     float *uR, *depth, *xyz;
     uint32_t *claimR;
     // search by projection

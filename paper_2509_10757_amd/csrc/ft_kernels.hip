@@ -43,6 +43,18 @@ struct Desc {
     uint4 a, b;
 };
 
+// 16-byte vector for copying descriptor halves through registers (a native
+// vector type: arrays of it stay in registers, unlike arrays of uint4).
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+// Keypoints per thread whose loads are issued together in the setup sorts and
+// the median pass (a strided loop body unrolled; surplus entries masked).
+constexpr int kSortUnroll = 4;
+
+// Candidates whose loads are issued together in the best-match and search scans.
+constexpr int kBestUnroll = 2;
+constexpr int kSearchUnroll = 2;
+
 __device__ __forceinline__ Desc load_desc(const uint8_t *base, int idx)
 {
     const uint4 *p = reinterpret_cast<const uint4 *>(base + 32 * (size_t)idx);
@@ -57,6 +69,18 @@ __device__ __forceinline__ int hamming(const Desc &u, const Desc &v)
     return __popc(u.a.x ^ v.a.x) + __popc(u.a.y ^ v.a.y) + __popc(u.a.z ^ v.a.z) +
            __popc(u.a.w ^ v.a.w) + __popc(u.b.x ^ v.b.x) + __popc(u.b.y ^ v.b.y) +
            __popc(u.b.z ^ v.b.z) + __popc(u.b.w ^ v.b.w);
+}
+
+// Entry l of a per-level table, selected from values loaded for every level
+// (the loads do not wait for l; a select chain instead of a dependent load).
+template <class T>
+__device__ __forceinline__ T pick_level(const T (&t)[kLevels], int l)
+{
+    T v[kLevels];
+    _Pragma("unroll") for (int k = 0; k < kLevels; ++k) v[k] = t[k];
+    T r = v[0];
+    _Pragma("unroll") for (int k = 1; k < kLevels; ++k) r = l == k ? v[k] : r;
+    return r;
 }
 
 // Pyramid level of a keypoint as a table index (levels are 0..7 by contract;
@@ -98,7 +122,7 @@ __device__ __forceinline__ Top2<T> top2_merge(Top2<T> t, T o1, T o2)
 }
 
 // Workgroup-wide exclusive scan of a[0..n) in LDS; returns the total.
-__device__ int wg_exclusive_scan(int *a, int n, int *tmp)
+__device__ __forceinline__ int wg_exclusive_scan(int *a, int n, int *tmp)
 {
     const int tid = threadIdx.x;
     const int per = (n + kWG - 1) / kWG;
@@ -154,34 +178,59 @@ __device__ __forceinline__ uint32_t band_rows(const DevJob &J, float y, int oct)
     return (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
-__device__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
+__device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
     const int rows = J.rows, nR = J.R.n;
     for (int r = tid; r < rows; r += kWG) cnt[r] = 0;
     for (int j = tid; j < nR; j += kWG) J.claimR[j] = 0xFFFFFFFFu;
     __syncthreads();
-    for (int j = tid; j < nR; j += kWG) atomicAdd(&cnt[row_bin(J.R.y[j], rows)], 1);
+    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * kWG) {
+        float y[kSortUnroll];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) y[e] = J.R.y[min(j0 + e * kWG, nR - 1)];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+            if (j0 + e * kWG < nR) atomicAdd(&cnt[row_bin(y[e], rows)], 1);
+    }
     __syncthreads();
     const int total = wg_exclusive_scan(cnt, rows, tmp);
     for (int r = tid; r < rows; r += kWG) J.row_start[r] = cnt[r];
     if (tid == 0) J.row_start[rows] = total;
     __syncthreads();
-    for (int j = tid; j < nR; j += kWG) {
-        const float y = J.R.y[j];
-        const int oct = J.R.oct[j];
-        const int pos = atomicAdd(&cnt[row_bin(y, rows)], 1);
-        RowRec rec;
-        rec.x = J.R.x[j];
-        rec.band = band_rows(J, y, oct);
-        rec.meta = (uint32_t)oct | ((uint32_t)j << 16);
-        rec.pad = 0;
-        J.rrec[pos] = rec;
+    const v4u *src = reinterpret_cast<const v4u *>(J.R.desc);
+    v4u *dst = reinterpret_cast<v4u *>(J.tdesc);
+    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * kWG) {
+        float x[kSortUnroll], y[kSortUnroll];
+        int oct[kSortUnroll];
+        v4u da[kSortUnroll], db[kSortUnroll];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int j = min(j0 + e * kWG, nR - 1);
+            x[e] = J.R.x[j];
+            y[e] = J.R.y[j];
+            oct[e] = J.R.oct[j];
+            da[e] = src[2 * j];
+            db[e] = src[2 * j + 1];
+        }
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int j = j0 + e * kWG;
+            if (j < nR) {
+                const int pos = atomicAdd(&cnt[row_bin(y[e], rows)], 1);
+                RowRec rec;
+                rec.x = x[e];
+                rec.band = band_rows(J, y[e], oct[e]);
+                rec.meta = (uint32_t)oct[e] | ((uint32_t)j << 16);
+                rec.pad = 0;
+                J.rrec[pos] = rec;
+                dst[2 * pos] = da[e];
+                dst[2 * pos + 1] = db[e];
+            }
+        }
     }
 }
 
 // ------------------------------------------- setup: overlap lists (fisheye)
-__device__ int compact_range(const float *x, int n, float a, float b, int32_t *out, int *wsum)
+__device__ __forceinline__ int compact_range(const float *x, int n, float a, float b, int32_t *out, int *wsum)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int base = 0;
@@ -202,7 +251,7 @@ __device__ int compact_range(const float *x, int n, float a, float b, int32_t *o
     return base;
 }
 
-__device__ void ph_overlap(const DevJob &J, int *wsum)
+__device__ __forceinline__ void ph_overlap(const DevJob &J, int *wsum)
 {
     const int tid = threadIdx.x;
     for (int j = tid; j < J.R.n; j += kWG) J.claimR[j] = 0xFFFFFFFFu;
@@ -221,7 +270,7 @@ __device__ void ph_overlap(const DevJob &J, int *wsum)
 }
 
 // ------------------------------------------------ setup: keypoint grid
-__device__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tmp)
+__device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
     const int cells = V.cols * V.rows;
@@ -229,32 +278,60 @@ __device__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tm
     for (int k = tid; k < K.n; k += kWG) V.claim[k] = 0xFFFFFFFFu;
     if (tid == 0) *V.n_matches = 0;
     __syncthreads();
-    for (int k = tid; k < K.n; k += kWG) {
-        const int cx = cell_coord(K.x[k], V.min_x, V.inv_cw, V.cols);
-        const int cy = cell_coord(K.y[k], V.min_y, V.inv_ch, V.rows);
-        atomicAdd(&cnt[cy * V.cols + cx], 1);
+    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * kWG) {
+        float x[kSortUnroll], y[kSortUnroll];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int k = min(k0 + e * kWG, K.n - 1);
+            x[e] = K.x[k];
+            y[e] = K.y[k];
+        }
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            if (k0 + e * kWG < K.n) {
+                const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
+                const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
+                atomicAdd(&cnt[cy * V.cols + cx], 1);
+            }
+        }
     }
     __syncthreads();
     const int total = wg_exclusive_scan(cnt, cells, tmp);
     for (int c = tid; c < cells; c += kWG) V.cell_off[c] = cnt[c];
     if (tid == 0) V.cell_off[cells] = total;
     __syncthreads();
-    const uint4 *dsrc = reinterpret_cast<const uint4 *>(K.desc);
-    uint4 *ddst = reinterpret_cast<uint4 *>(V.cdesc);
-    for (int k = tid; k < K.n; k += kWG) {
-        const float x = K.x[k], y = K.y[k];
-        const int cx = cell_coord(x, V.min_x, V.inv_cw, V.cols);
-        const int cy = cell_coord(y, V.min_y, V.inv_ch, V.rows);
-        const int pos = atomicAdd(&cnt[cy * V.cols + cx], 1);
-        const uint32_t pre = (V.preassigned && V.preassigned[k]) ? 1u : 0u;
-        CellRec rec;
-        rec.x = x;
-        rec.y = y;
-        rec.meta = (uint32_t)K.oct[k] | (pre << 8) | ((uint32_t)k << 16);
-        rec.pad = 0;
-        V.crec[pos] = rec;
-        ddst[2 * pos] = dsrc[2 * k];
-        ddst[2 * pos + 1] = dsrc[2 * k + 1];
+    const v4u *dsrc = reinterpret_cast<const v4u *>(K.desc);
+    v4u *ddst = reinterpret_cast<v4u *>(V.cdesc);
+    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * kWG) {
+        float x[kSortUnroll], y[kSortUnroll];
+        uint32_t meta[kSortUnroll];
+        v4u da[kSortUnroll], db[kSortUnroll];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int k = min(k0 + e * kWG, K.n - 1);
+            x[e] = K.x[k];
+            y[e] = K.y[k];
+            const uint32_t pre = (V.preassigned && V.preassigned[k]) ? 1u : 0u;
+            meta[e] = (uint32_t)K.oct[k] | (pre << 8) | ((uint32_t)k << 16);
+            da[e] = dsrc[2 * k];
+            db[e] = dsrc[2 * k + 1];
+        }
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            if (k0 + e * kWG < K.n) {
+                const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
+                const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
+                const int pos = atomicAdd(&cnt[cy * V.cols + cx], 1);
+                CellRec rec;
+                rec.x = x[e];
+                rec.y = y[e];
+                rec.meta = meta[e];
+                rec.pad = 0;
+                V.crec[pos] = rec;
+                ddst[2 * pos] = da[e];
+                ddst[2 * pos + 1] = db[e];
+            }
+        }
     }
 }
 
@@ -263,11 +340,12 @@ __device__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tm
 // whose band covers r; their integer rows lie within J.row_reach of r, so the
 // lanes stream the row-sorted records of those bins and test the band exactly.
 template <int G>
-__device__ void ph_best(const DevJob &J, int tile)
+__device__ __forceinline__ void ph_best(const DevJob &J, int tile)
 {
     const int sub = threadIdx.x % G;
     const int i = tile * (kWG / G) + threadIdx.x / G;
     uint32_t best = 0xFFFFFFFFu;   // Hamming << 16 | right index
+    float bx = 0.0f;               // x of that right keypoint (for the refinement)
     if (i < J.L.n) {
         const float y = J.L.y[i];
         const float x = J.L.x[i];
@@ -280,28 +358,49 @@ __device__ void ph_best(const DevJob &J, int tile)
             const int b0 = max(row - J.row_reach, 0);
             const int b1 = min(row + J.row_reach, J.rows - 1);
             const int p1 = J.row_start[b1 + 1];
-            for (int p = J.row_start[b0] + sub; p < p1; p += G) {
-                const RowRec rec = J.rrec[p];
-                const int lo = (int)(rec.band & 0xFFFFu), hi = (int)(rec.band >> 16);
-                if (row < lo || row > hi) continue;
-                const int oj = (int)(rec.meta & 0xFFu);
-                if (oj < oi - J.level_window || oj > oi + J.level_window) continue;
-                if (!(rec.x >= minU && rec.x <= maxU)) continue;
-                const uint32_t j = rec.meta >> 16;
-                const uint32_t key = ((uint32_t)hamming(di, load_desc(J.R.desc, (int)j)) << 16) | j;
-                best = key < best ? key : best;
+            // kBestUnroll records per step are loaded together (indices
+            // clamped into the range, surplus entries masked); then the
+            // row-ordered descriptors of the candidates among them.
+            for (int p0 = J.row_start[b0] + sub; p0 < p1; p0 += kBestUnroll * G) {
+                RowRec rec[kBestUnroll];
+                bool cand[kBestUnroll];
+                Desc d[kBestUnroll];
+                _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) rec[u] = J.rrec[min(p0 + u * G, p1 - 1)];
+                _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
+                {
+                    const int lo = (int)(rec[u].band & 0xFFFFu), hi = (int)(rec[u].band >> 16);
+                    const int oj = (int)(rec[u].meta & 0xFFu);
+                    cand[u] = p0 + u * G < p1 && row >= lo && row <= hi && oj >= oi - J.level_window &&
+                              oj <= oi + J.level_window && rec[u].x >= minU && rec[u].x <= maxU;
+                    if (cand[u]) d[u] = load_desc(J.tdesc, p0 + u * G);
+                }
+                _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
+                {
+                    if (cand[u]) {
+                        const uint32_t key = ((uint32_t)hamming(di, d[u]) << 16) | (rec[u].meta >> 16);
+                        if (key < best) {
+                            best = key;
+                            bx = rec[u].x;
+                        }
+                    }
+                }
             }
         }
     }
     for (int m = 1; m < G; m <<= 1) {
         const uint32_t o = __shfl_xor(best, m);
-        best = o < best ? o : best;
+        const float ox = __shfl_xor(bx, m);
+        if (o < best) {
+            best = o;
+            bx = ox;
+        }
     }
     if (sub == 0 && i < J.L.n) {
         const int h = (int)(best >> 16);
         const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
         J.best_j[i] = ok ? (int)(best & 0xFFFFu) : -1;
         J.best_h[i] = ok ? h : -1;
+        J.best_x[i] = bx;
     }
 }
 
@@ -313,7 +412,7 @@ __device__ void ph_best(const DevJob &J, int tile)
 // K-steps of v_mfma_i32_16x16x64_i8 (two bytes = sixteen int8 per step); the A
 // and B operands use the same byte-to-K assignment, so the dot product is the
 // full 256-term sum whatever order the hardware sums K in.
-__device__ void ph_knn(const DevJob &J, int tile, uint64_t *tab, uint32_t *part)
+__device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab, uint32_t *part)
 {
     const int tid = threadIdx.x;
     // +-1 expansion of every byte value: bit t -> byte t, 1 -> +1, 0 -> -1
@@ -392,24 +491,33 @@ __device__ void ph_knn(const DevJob &J, int tile, uint64_t *tab, uint32_t *part)
 // ------------------------------------- stereo_b (pinhole): SAD refinement
 // One wave per match.  The wave stages the left patch and the right strip of
 // the left keypoint's level in LDS, then 64 lanes split the (shift, row) sums.
-__device__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
+__device__ __forceinline__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = tile * kRefinePerWG + wave;
     const int w = J.half_win, L = J.half_range;
     const int side = 2 * w + 1, strip = 2 * (L + w) + 1, nS = 2 * L + 1;
-    int j = -1, l = 0, su = 0, sv = 0, su0 = 0, Wl = 0;
+    int j = -1, l = 0, su = 0, sv = 0, su0 = 0, Wl = 0, bh = 0;
+    float xi = 0.0f, sfl = 0.0f;
+    int64_t off = 0;
     bool act = false;
     if (i < J.L.n) {
+        // everything the match needs is indexed by i: one round of loads
         j = J.best_j[i];
+        bh = J.best_h[i];
+        const float xj = J.best_x[i];
+        xi = J.L.x[i];
+        const float yi = J.L.y[i];
+        l = lvl(J.L.oct[i]);
         if (j >= 0) {
-            l = lvl(J.L.oct[i]);
-            const float s = J.inv_sf[l];
-            su = (int)roundf(J.L.x[i] * s);
-            sv = (int)roundf(J.L.y[i] * s);
-            su0 = (int)roundf(J.R.x[j] * s);
-            Wl = J.lv_w[l];
-            const int Hl = J.lv_h[l];
+            const float s = pick_level(J.inv_sf, l);
+            sfl = pick_level(J.sf, l);
+            su = (int)roundf(xi * s);
+            sv = (int)roundf(yi * s);
+            su0 = (int)roundf(xj * s);
+            Wl = pick_level(J.lv_w, l);
+            const int Hl = pick_level(J.lv_h, l);
+            off = pick_level(J.lv_off, l);
             act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
                   su0 + L + w < Wl;
         }
@@ -417,8 +525,8 @@ __device__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
     uint8_t *P = lds + wave * kRefineLds;          // left patch [side][side]
     uint8_t *S = P + side * side;                  // right strip [side][strip]
     if (act) {
-        const uint8_t *IL = J.pyrL + J.lv_off[l];
-        const uint8_t *IR = J.pyrR + J.lv_off[l];
+        const uint8_t *IL = J.pyrL + off;
+        const uint8_t *IR = J.pyrR + off;
         const int nP = side * side, n = nP + side * strip;
         for (int e = lane; e < n; e += 64) {
             if (e < nP) {
@@ -469,8 +577,7 @@ __device__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
         J.flag[i] = 0;
         return;
     }
-    const float xi = J.L.x[i];
-    float uR = J.sf[l] * (((float)su0 + (float)kb) + delta);
+    float uR = sfl * (((float)su0 + (float)kb) + delta);
     float disp = xi - uR;
     if (!(disp >= 0.0f && disp < J.maxD)) {
         J.flag[i] = 0;
@@ -484,7 +591,7 @@ __device__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
     J.uR[i] = uR;
     J.depth[i] = J.bf / disp;
     J.flag[i] = 1;
-    atomicMin(&J.claimR[j], ((uint32_t)J.best_h[i] << 23) | (uint32_t)i);
+    atomicMin(&J.claimR[j], ((uint32_t)bh << 23) | (uint32_t)i);
 }
 
 // ------------------------------- stereo_b (fisheye): ratio + triangulation
@@ -594,7 +701,7 @@ __device__ __forceinline__ bool triangulate(const double r1[3], const double r2[
     return true;
 }
 
-__device__ void ph_tri(const DevJob &J, int tile)
+__device__ __forceinline__ void ph_tri(const DevJob &J, int tile)
 {
     const int nQ = J.counts[0], nT = J.counts[1];
     const int q = tile * kWG + threadIdx.x;
@@ -641,7 +748,7 @@ __device__ void ph_tri(const DevJob &J, int tile)
 // ---------------------- stereo_c (pinhole): conflicts + median + outputs
 // The median is the value at rank n/2 of the survivors' 16-bit SADs, found by
 // a two-pass 8-bit radix select with a parallel prefix over the 256 bins.
-__device__ int select_bin(int *hist, int *tmp, int target, int *out_rank, int *found)
+__device__ __forceinline__ int select_bin(int *hist, int *tmp, int target, int *out_rank, int *found)
 {
     const int tid = threadIdx.x;
     const int h = hist[tid];
@@ -659,7 +766,7 @@ __device__ int select_bin(int *hist, int *tmp, int target, int *out_rank, int *f
 
 __device__ __forceinline__ bool bit(const uint32_t *b, int i) { return (b[i >> 5] >> (i & 31)) & 1u; }
 
-__device__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, int *sh)
+__device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, int *sh)
 {
     const int tid = threadIdx.x, nL = J.L.n;
     hist[tid] = 0;
@@ -667,16 +774,28 @@ __device__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, 
     for (int w = tid; w < (nL + 31) / 32; w += kWG) surv[w] = 0;
     __syncthreads();
     int my_n = 0;
-    for (int i = tid; i < nL; i += kWG) {
-        bool s = false;
-        if (J.flag[i]) {
-            const int j = J.best_j[i];
-            s = J.claimR[j] == (((uint32_t)J.best_h[i] << 23) | (uint32_t)i);
+    for (int i0 = tid; i0 < nL; i0 += kSortUnroll * kWG) {
+        int fl[kSortUnroll], bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
+        uint32_t cl[kSortUnroll];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int i = min(i0 + e * kWG, nL - 1);
+            fl[e] = J.flag[i];
+            bj[e] = J.best_j[i];
+            bh[e] = J.best_h[i];
+            sd[e] = J.sad[i];
         }
-        if (s) {
-            atomicOr(&surv[i >> 5], 1u << (i & 31));
-            ++my_n;
-            atomicAdd(&hist[(J.sad[i] >> 8) & 0xFF], 1);
+        // a flagged keypoint has a valid right index; others read index 0
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) cl[e] = J.claimR[fl[e] ? bj[e] : 0];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int i = i0 + e * kWG;
+            const bool s = i < nL && fl[e] && cl[e] == (((uint32_t)bh[e] << 23) | (uint32_t)i);
+            if (s) {
+                atomicOr(&surv[i >> 5], 1u << (i & 31));
+                ++my_n;
+                atomicAdd(&hist[(sd[e] >> 8) & 0xFF], 1);
+            }
         }
     }
     atomicAdd(&sh[0], my_n);
@@ -698,21 +817,29 @@ __device__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, 
     if (tid == 0) sh[1] = 0;
     __syncthreads();
     int kept = 0;
-    for (int i = tid; i < nL; i += kWG) {
-        const bool keep = bit(surv, i) && (long long)J.med_den * J.sad[i] < (long long)J.med_num * m;
-        if (keep) {
-            J.o_right_idx[i] = J.best_j[i];
-            J.o_dist[i] = J.best_h[i];
-            J.o_uR[i] = J.uR[i];
-            J.o_depth[i] = J.depth[i];
-            J.o_sad[i] = J.sad[i];
-            ++kept;
-        } else {
-            J.o_right_idx[i] = -1;
-            J.o_dist[i] = -1;
-            J.o_uR[i] = -1.0f;
-            J.o_depth[i] = -1.0f;
-            J.o_sad[i] = -1;
+    for (int i0 = tid; i0 < nL; i0 += kSortUnroll * kWG) {
+        int bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
+        float ur[kSortUnroll], dp[kSortUnroll];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int i = min(i0 + e * kWG, nL - 1);
+            bj[e] = J.best_j[i];
+            bh[e] = J.best_h[i];
+            sd[e] = J.sad[i];
+            ur[e] = J.uR[i];
+            dp[e] = J.depth[i];
+        }
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int i = i0 + e * kWG;
+            if (i >= nL) continue;
+            const bool keep = bit(surv, i) && (long long)J.med_den * sd[e] < (long long)J.med_num * m;
+            J.o_right_idx[i] = keep ? bj[e] : -1;
+            J.o_dist[i] = keep ? bh[e] : -1;
+            J.o_uR[i] = keep ? ur[e] : -1.0f;
+            J.o_depth[i] = keep ? dp[e] : -1.0f;
+            J.o_sad[i] = keep ? sd[e] : -1;
+            kept += keep ? 1 : 0;
         }
     }
     atomicAdd(&sh[1], kept);
@@ -721,7 +848,7 @@ __device__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, 
 }
 
 // ---------------------- stereo_c (fisheye): conflicts + outputs
-__device__ void ph_fish_final(const DevJob &J, int tile)
+__device__ __forceinline__ void ph_fish_final(const DevJob &J, int tile)
 {
     const int i = tile * kWG + threadIdx.x;
     bool keep = false;
@@ -756,7 +883,7 @@ __device__ void ph_fish_final(const DevJob &J, int tile)
 // Keys order candidates by (distance, keypoint index): distance << 40 |
 // index << 8 | level.
 template <int G>
-__device__ void ph_search(const DevJob &J, const DevView &V, int tile)
+__device__ __forceinline__ void ph_search(const DevJob &J, const DevView &V, int tile)
 {
     const int sub = threadIdx.x % G;
     const int m = tile * (kWG / G) + threadIdx.x / G;
@@ -812,22 +939,49 @@ __device__ void ph_search(const DevJob &J, const DevView &V, int tile)
             const int cy0 = cell_coord(v - Rc, V.min_y, V.inv_ch, V.rows);
             const int cy1 = cell_coord(v + Rc, V.min_y, V.inv_ch, V.rows);
             const int plo = pred - J.lv_lo, phi = pred + J.lv_hi;
+            // One record range per window row; the next row's bounds are
+            // loaded before the current row is scanned, and kSearchUnroll
+            // candidates' records and descriptors are loaded together
+            // (indices clamped into the range, surplus entries masked).
+            int c0 = V.cell_off[cy0 * V.cols + cx0];
+            int c1 = V.cell_off[cy0 * V.cols + cx1 + 1];
             for (int cy = cy0; cy <= cy1; ++cy) {
-                const int c1 = V.cell_off[cy * V.cols + cx1 + 1];
-                for (int p = V.cell_off[cy * V.cols + cx0] + sub; p < c1; p += G) {
-                    const CellRec rec = V.crec[p];
-                    const int ok = (int)(rec.meta & 0xFFu);
-                    if (ok < plo || ok > phi) continue;
-                    if (!(fabsf(rec.x - u) < Rm && fabsf(rec.y - v) < Rm)) continue;
-                    if (rec.meta & 0x100u) continue;
-                    const uint32_t k = rec.meta >> 16;
-                    if (gate) {
-                        const float ur = V.u_right[k];
-                        if (ur > 0.0f && !(fabsf(uR - ur) <= Rm)) continue;
-                    }
-                    const uint64_t h = (uint64_t)hamming(dm, load_desc(V.cdesc, p));
-                    top = top2_insert(top, (h << 40) | ((uint64_t)k << 8) | (uint64_t)(rec.meta & 0xFFu));
+                int n0 = 0, n1 = 0;
+                if (cy < cy1) {
+                    n0 = V.cell_off[(cy + 1) * V.cols + cx0];
+                    n1 = V.cell_off[(cy + 1) * V.cols + cx1 + 1];
                 }
+                for (int p0 = c0 + sub; p0 < c1; p0 += kSearchUnroll * G) {
+                    CellRec rec[kSearchUnroll];
+                    bool cand[kSearchUnroll];
+                    Desc d[kSearchUnroll];
+                    float ur[kSearchUnroll];
+                    _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e) rec[e] = V.crec[min(p0 + e * G, c1 - 1)];
+                    // descriptors (and right coordinates) only for the records
+                    // that pass the position, level and preassignment tests
+                    _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
+                    {
+                        const int ok = (int)(rec[e].meta & 0xFFu);
+                        cand[e] = p0 + e * G < c1 && ok >= plo && ok <= phi && fabsf(rec[e].x - u) < Rm &&
+                                  fabsf(rec[e].y - v) < Rm && !(rec[e].meta & 0x100u);
+                        ur[e] = 0.0f;
+                        if (cand[e]) {
+                            d[e] = load_desc(V.cdesc, p0 + e * G);
+                            if (gate) ur[e] = V.u_right[rec[e].meta >> 16];
+                        }
+                    }
+                    _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
+                    {
+                        if (gate && ur[e] > 0.0f && !(fabsf(uR - ur[e]) <= Rm)) cand[e] = false;
+                        if (cand[e]) {
+                            const uint64_t h = (uint64_t)hamming(dm, d[e]);
+                            top = top2_insert(top, (h << 40) | ((uint64_t)(rec[e].meta >> 16) << 8) |
+                                                       (uint64_t)(rec[e].meta & 0xFFu));
+                        }
+                    }
+                }
+                c0 = n0;
+                c1 = n1;
             }
         }
     }
@@ -850,7 +1004,7 @@ __device__ void ph_search(const DevJob &J, const DevView &V, int tile)
     if (kk1 >= 0) atomicMin(&V.claim[kk1], ((uint32_t)b1 << 23) | (uint32_t)m);
 }
 
-__device__ void ph_search_final(const DevJob &J, const DevView &V, int nK, int tile)
+__device__ __forceinline__ void ph_search_final(const DevJob &J, const DevView &V, int nK, int tile)
 {
     const int idx = tile * kWG + threadIdx.x;
     if (idx < J.nM) {
@@ -955,7 +1109,7 @@ struct JobTable {
 // `smem` is the workgroup's LDS scratch (kTaskLds bytes, 16-byte aligned).
 constexpr int kTaskLds = (kMaxCells + 8 + kWG) * 4;
 
-__device__ void task_setup(const DevJob &J, int tile, unsigned char *smem)
+__device__ __forceinline__ void task_setup(const DevJob &J, int tile, unsigned char *smem)
 {
     int *lds = reinterpret_cast<int *>(smem);
     int *tmp = lds + kMaxCells + 8;
@@ -971,7 +1125,7 @@ __device__ void task_setup(const DevJob &J, int tile, unsigned char *smem)
 }
 
 template <int G>
-__device__ void task_stereo_a(const DevJob &J, int tile, unsigned char *smem)
+__device__ __forceinline__ void task_stereo_a(const DevJob &J, int tile, unsigned char *smem)
 {
     uint64_t *tab = reinterpret_cast<uint64_t *>(smem);
     uint32_t *part = reinterpret_cast<uint32_t *>(smem + 256 * sizeof(uint64_t));
@@ -979,7 +1133,7 @@ __device__ void task_stereo_a(const DevJob &J, int tile, unsigned char *smem)
     else ph_knn(J, tile, tab, part);
 }
 
-__device__ void task_stereo_c(const DevJob &J, int tile, unsigned char *smem)
+__device__ __forceinline__ void task_stereo_c(const DevJob &J, int tile, unsigned char *smem)
 {
     int *hist = reinterpret_cast<int *>(smem);
     int *tmp = hist + 256;
@@ -990,7 +1144,7 @@ __device__ void task_stereo_c(const DevJob &J, int tile, unsigned char *smem)
 }
 
 template <int G>
-__device__ void task_search(const DevJob &J, int tile)
+__device__ __forceinline__ void task_search(const DevJob &J, int tile)
 {
     const int tpv = search_tiles_per_view(J, G);
     const int v = tile / tpv;
@@ -998,7 +1152,7 @@ __device__ void task_search(const DevJob &J, int tile)
     ph_search<G>(J, J.view[v], tile - v * tpv);
 }
 
-__device__ void task_search_final(const DevJob &J, int tile)
+__device__ __forceinline__ void task_search_final(const DevJob &J, int tile)
 {
     const int t0 = final_tiles_view(J, 0);
     const int v = tile < t0 ? 0 : 1;
@@ -1103,7 +1257,7 @@ __device__ __forceinline__ bool phase_done(const PersistArgs &a, int j, int p)
 // and triangulation do not wait for each other).  Checking all of them, not
 // only the direct predecessors, keeps the order right when a phase has no
 // tiles for the frame.
-__device__ bool deps_ready(const PersistArgs &a, int j, int p)
+__device__ __forceinline__ bool deps_ready(const PersistArgs &a, int j, int p)
 {
     for (int q = 0; q < p; ++q) {
         if (p == PH_TRI && q == PH_REFINE) continue;

@@ -1,11 +1,15 @@
-"""The five seeded workloads (plus tiny variants for brute-force checks).
+"""The seeded workloads (plus tiny variants for brute-force checks).
 
-Config k uses master seed 10757000 + k; sub-seeds come from SeedSequence.spawn.
-  1  one pinhole stereo frame, 752x480, 1200 kp/image, 3000 map points, 64x48 grid
-  2  one fisheye stereo frame, 512x512, 1500 kp/image, 5000 map points
-  3  local-map search only: 20000 clustered map points, 3000 kp, 96x64 grid
-  4  64 frames, 32 pinhole + 32 fisheye in seeded order, kp ~ U{300..3000},
-     map ~ U{1000..20000}
+Each workload has its own master seed, 10757000 + a fixed offset; sub-seeds come
+from SeedSequence.spawn.
+  pinhole_frame_1200      one pinhole stereo frame, 752x480, 1200 kp/image,
+                          3000 map points, 64x48 grid (offset 1)
+  fisheye_frame_1500      one fisheye stereo frame, 512x512, 1500 kp/image,
+                          5000 map points (offset 2)
+  clustered_search_20000  local-map search only: 20000 clustered map points,
+                          3000 kp, 96x64 grid (offset 3)
+  mixed_batch             64 frames, 32 pinhole + 32 fisheye in seeded order,
+                          kp ~ U{300..3000}, map ~ U{1000..20000} (offset 4)
 """
 from __future__ import annotations
 
@@ -17,23 +21,23 @@ from .fisheye import fisheye_frame
 from .pinhole import pinhole_camera, pinhole_frame
 
 
-def seed_of(k: int) -> np.random.SeedSequence:
-    return np.random.SeedSequence(MASTER_SEED + k)
+def seed_of(offset: int) -> np.random.SeedSequence:
+    return np.random.SeedSequence(MASTER_SEED + offset)
 
 
-def config1(seed=None):
+def pinhole_frame_1200(seed=None):
     return [pinhole_frame(seed if seed is not None else seed_of(1))]
 
 
-def config2(seed=None):
+def fisheye_frame_1500(seed=None):
     return [fisheye_frame(seed if seed is not None else seed_of(2))]
 
 
-def config3(seed=None):
+def clustered_search_20000(seed=None):
     return [clustered_frame(seed if seed is not None else seed_of(3))]
 
 
-def config4(seed=None, n_frames: int = 64):
+def mixed_batch(seed=None, n_frames: int = 64):
     ss = seed if seed is not None else seed_of(4)
     ctl_ss, *frame_ss = ss.spawn(n_frames + 1)
     rng = np.random.default_rng(ctl_ss)
@@ -63,8 +67,9 @@ def tiny_clustered(seed, n_map: int = 400, n_kp: int = 120, grid=(16, 12)):
     return clustered_frame(seed, n_map=n_map, n_kp=n_kp, n_blobs=4, grid=grid)
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+SINGLE_FRAME = {"pinhole_frame_1200": pinhole_frame_1200, "fisheye_frame_1500": fisheye_frame_1500,
+                "clustered_search_20000": clustered_search_20000}
 
 
-def config(k: int):
-    return CONFIGS[k]()
+def workload(name: str):
+    return SINGLE_FRAME[name]()

@@ -75,3 +75,15 @@ def test_ctypes_layout_matches_c_compiler(tmp_path):
             assert getattr(getattr(binding, s), f).offset == int(val), key
         else:
             assert ct.sizeof(getattr(binding, key)) == int(val), key
+
+
+def test_binding_constants_match_header():
+    """Every #define of the header that the binding mirrors has the same value
+    (the timing arrays are sized by FT_PHASES, so a mismatch overruns them)."""
+    from paper_2509_10757_amd import binding
+    defs = dict(re.findall(r"#define\s+(FT_[A-Z_0-9]+)\s+(-?\d+)", open(HEADER).read()))
+    mirrored = [k for k in defs if hasattr(binding, k)]
+    assert {"FT_PHASES", "FT_ERR_ABORTED", "FT_EXEC_PERSISTENT"} <= set(mirrored)
+    for k in mirrored:
+        assert getattr(binding, k) == int(defs[k]), k
+    assert len(binding.Context.PHASES) == int(defs["FT_PHASES"])

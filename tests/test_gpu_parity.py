@@ -61,17 +61,17 @@ def test_tiny_clustered(ft, ctx, seed):
     compare_frame(run_device(ft, ctx, f), oracle.run_frame(f))
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_config_single_frame(ft, ctx, k):
-    f = synth.config(k)[0]
-    say("config", k)
+@pytest.mark.parametrize("name", sorted(synth.SINGLE_FRAME))
+def test_full_size_single_frame(ft, ctx, name):
+    f = synth.workload(name)[0]
+    say("workload", name)
     got = run_device(ft, ctx, f)
     compare_frame(got, oracle.run_frame(f))
     assert got["search"][0]["n_matches"] > 100
 
 
 def test_batched_workload_matches_oracle_and_single_frame_path(ft, ctx):
-    frames = synth.config4()
+    frames = synth.mixed_batch()
     say("batched workload: 64 frames")
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     t = ctx.ft_batch_submit([d.job() for d in dfs])
@@ -86,11 +86,11 @@ def test_batched_workload_matches_oracle_and_single_frame_path(ft, ctx):
 
 
 def test_repeat_runs_are_bit_identical(ft, ctx):
-    f = synth.config3()[0]
+    f = synth.clustered_search_20000()[0]
     first = run_device(ft, ctx, f)
     for _ in range(4):
         bit_equal(run_device(ft, ctx, f), first)
-    f = synth.config2()[0]
+    f = synth.fisheye_frame_1500()[0]
     first = run_device(ft, ctx, f, batch=True)
     for _ in range(3):
         bit_equal(run_device(ft, ctx, f, batch=True), first)
@@ -225,7 +225,7 @@ def test_batch_tickets_poll_and_wait(ft, ctx):
 
 # ------------------------------------------------------- launch shapes / tuner
 def test_lane_groups_do_not_change_results(ft, ctx):
-    frames = synth.config4(n_frames=8)
+    frames = synth.mixed_batch(n_frames=8)
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     jobs = [d.job() for d in dfs]
     ref = None
@@ -248,7 +248,7 @@ def test_lane_groups_do_not_change_results(ft, ctx):
 
 
 def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
-    frames = synth.config4(n_frames=6)
+    frames = synth.mixed_batch(n_frames=6)
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     jobs = [d.job() for d in dfs]
     cache = str(tmp_path / "shapes.jsonl")
@@ -269,7 +269,7 @@ def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
 
 
 def test_graph_replays_match_eager(ft, ctx):
-    frames = synth.config4(n_frames=8)
+    frames = synth.mixed_batch(n_frames=8)
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     jobs = [d.job() for d in dfs]
     try:
@@ -311,7 +311,7 @@ def _clobber(dfs):
 
 @pytest.mark.parametrize("n_frames,blocks", [(64, 0), (16, 1), (16, 37)])
 def test_persistent_matches_eager(ft, ctx, n_frames, blocks):
-    frames = synth.config4(n_frames=n_frames)
+    frames = synth.mixed_batch(n_frames=n_frames)
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     jobs = [d.job() for d in dfs]
     say("persistent", n_frames, "frames, blocks", blocks)
@@ -340,7 +340,7 @@ def test_persistent_gives_up_cleanly_and_recovers(ft, ctx):
     """A one-sleep spin limit makes dependency waits give up: the batch is then
     reported as failed (or, if no task had to wait, is correct), and the next
     batch with the default limit is correct again."""
-    frames = synth.config4(n_frames=32)
+    frames = synth.mixed_batch(n_frames=32)
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     jobs = [d.job() for d in dfs]
     with pytest.raises(ft.FtError):
@@ -373,4 +373,42 @@ def test_persistent_gives_up_cleanly_and_recovers(ft, ctx):
             bit_equal(d.results(), w)
     finally:
         ctx.ft_set_persistent(0, 0)
+        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
+
+
+def test_split_submissions_match_one_launch(ft, ctx):
+    """A submission split into 2-4 parts on the context's internal streams gives
+    the results of one launch, in eager and graph mode, also when there are
+    fewer frames than parts."""
+    frames = synth.mixed_batch(n_frames=24)
+    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
+    jobs = [d.job() for d in dfs]
+    for bad in (0, 5):
+        with pytest.raises(ft.FtError):
+            ctx.ft_set_batch_parts(bad)
+    try:
+        ctx.ft_set_batch_parts(1)
+        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+        torch.cuda.synchronize()
+        ref = [d.results() for d in dfs]
+        for mode in (ft.FT_EXEC_EAGER, ft.FT_EXEC_GRAPH):
+            ctx.ft_set_exec_mode(mode)
+            for parts in (2, 3, 4):
+                ctx.ft_set_batch_parts(parts)
+                assert ctx.ft_get_batch_parts() == parts
+                say("mode", mode, "parts", parts)
+                for rep in range(2):
+                    _clobber(dfs)
+                    ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
+                    torch.cuda.synchronize()
+                    for d, w in zip(dfs, ref):
+                        bit_equal(d.results(), w)
+                _clobber(dfs[:3])
+                ctx.ft_batch_wait(ctx.ft_batch_submit(jobs[:3]))
+                torch.cuda.synchronize()
+                for d, w in zip(dfs[:3], ref[:3]):
+                    bit_equal(d.results(), w)
+    finally:
+        ctx.ft_set_batch_parts(1)
         ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)

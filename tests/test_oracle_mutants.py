@@ -50,7 +50,7 @@ MUTANTS = {
 
 @pytest.fixture(scope="module")
 def frames():
-    return {1: synth.config1()[0], 2: synth.config2()[0], 3: synth.config3()[0]}
+    return {1: synth.pinhole_frame_1200()[0], 2: synth.fisheye_frame_1500()[0], 3: synth.clustered_search_20000()[0]}
 
 
 def _pins(frames):

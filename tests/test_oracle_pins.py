@@ -281,19 +281,19 @@ def test_search_clustered_equals_bruteforce(seed):
 # -------------------------------------------- invariants + ground truth ----
 @pytest.fixture(scope="module")
 def c1():
-    f = synth.config1()[0]
+    f = synth.pinhole_frame_1200()[0]
     return f, oracle.run_frame(f)
 
 
 @pytest.fixture(scope="module")
 def c2():
-    f = synth.config2()[0]
+    f = synth.fisheye_frame_1500()[0]
     return f, oracle.run_frame(f)
 
 
 @pytest.fixture(scope="module")
 def c3():
-    f = synth.config3()[0]
+    f = synth.clustered_search_20000()[0]
     return f, oracle.run_frame(f)
 
 
