@@ -142,7 +142,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--shapes", type=str, default="", help="best,search lanes instead of autotuning")
+    ap.add_argument("--shapes", type=str, default="",
+                    help="best_lanes,search_lanes[,search_block,best_block,aux_block] instead of autotuning")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--exec", choices=["auto", "graph", "persistent", "eager"], default="auto",
                     help="batch execution mode; auto times the modes and submission splits briefly and keeps the fastest")
@@ -182,8 +183,8 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     if args.shapes:
-        shapes = tuple(int(v) for v in args.shapes.split(","))
-        ctx.ft_set_shapes(*shapes)
+        ctx.ft_set_shapes(*(int(v) for v in args.shapes.split(",")))
+        shapes = ctx.ft_get_shapes()
     else:
         log("autotune")
         shapes = ctx.ft_autotune(jobs, stream=stream)
@@ -328,7 +329,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "frames_per_step": n_frames,
-                   "shapes": {"best_lanes": shapes[0], "search_lanes": shapes[1]},
+                   "shapes": dict(zip(("best_lanes", "search_lanes", "search_block", "best_block",
+                                       "aux_block"), shapes)),
                    "exec": exec_mode, "batch_parts": n_parts, "exec_trial_fps": trial or None,
                    "pinhole_frames": sum(f["kind"] == "pinhole" for f in frames),
                    "fisheye_frames": sum(f["kind"] == "fisheye" for f in frames)},

@@ -348,8 +348,18 @@ ft_status ft_set_persistent(ft_context *ctx, int32_t blocks, int32_t spin_limit)
 /* Launch shapes of the search kernels: how many lanes of a wave cooperate on
  * one query.  Results never depend on them, only the time does. */
 typedef struct ft_shapes {
-    int32_t best_lanes;        /* lanes per pinhole left keypoint: 1, 2, 4, 8 or 16 */
-    int32_t search_lanes;      /* lanes per map point: 1, 2, 4, 8 or 16 */
+    int32_t best_lanes;        /* lanes per pinhole left keypoint of the 256-thread best match:
+                                  1, 2, 4, 8 or 16 */
+    int32_t search_lanes;      /* lanes per map point of the 256-thread search: 1, 2, 4, 8 or 16 */
+    int32_t search_block;      /* threads per search workgroup: 1024 = one lane per map point,
+                                  the view's grid staged in LDS (views whose grid exceeds 64 KiB
+                                  scan global memory); 256 = global-memory scan with
+                                  search_lanes lanes per map point */
+    int32_t best_block;        /* threads per stereo best-match workgroup: 1024 = the frame's row
+                                  records staged in LDS, 8 lanes per left keypoint, fisheye kNN
+                                  in four 16-query subgroups; 256 = global scan with best_lanes */
+    int32_t aux_block;         /* threads per workgroup of the setup sorts and the stereo
+                                  resolve: 256 or 1024 */
 } ft_shapes;
 
 ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *shapes);

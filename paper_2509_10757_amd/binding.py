@@ -125,7 +125,8 @@ class ft_frame_job(ct.Structure):
 
 
 class ft_shapes(ct.Structure):
-    _fields_ = [("best_lanes", ct.c_int32), ("search_lanes", ct.c_int32)]
+    _fields_ = [("best_lanes", ct.c_int32), ("search_lanes", ct.c_int32), ("search_block", ct.c_int32),
+                ("best_block", ct.c_int32), ("aux_block", ct.c_int32)]
 
 
 EXPORTS = {
@@ -303,14 +304,15 @@ class Context:
         self._check(self.lib.ft_get_exec_mode(self.h, ct.byref(m)), "ft_get_exec_mode")
         return m.value
 
-    def ft_set_shapes(self, best_lanes: int, search_lanes: int):
-        self._check(self.lib.ft_set_shapes(self.h, ct.byref(ft_shapes(best_lanes, search_lanes))),
-                    "ft_set_shapes")
+    def ft_set_shapes(self, best_lanes: int, search_lanes: int, search_block: int = 256,
+                      best_block: int = 256, aux_block: int = 256):
+        sh = ft_shapes(best_lanes, search_lanes, search_block, best_block, aux_block)
+        self._check(self.lib.ft_set_shapes(self.h, ct.byref(sh)), "ft_set_shapes")
 
     def ft_get_shapes(self) -> tuple:
         s = ft_shapes()
         self._check(self.lib.ft_get_shapes(self.h, ct.byref(s)), "ft_get_shapes")
-        return s.best_lanes, s.search_lanes
+        return s.best_lanes, s.search_lanes, s.search_block, s.best_block, s.aux_block
 
     def ft_autotune(self, jobs, cache_path=None, stream=None) -> tuple:
         arr = (ft_frame_job * len(jobs))(*jobs)
@@ -318,7 +320,7 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         self._check(self.lib.ft_autotune(self.h, _stream(stream), arr, len(jobs), cp, ct.byref(s)),
                     "ft_autotune")
-        return s.best_lanes, s.search_lanes
+        return s.best_lanes, s.search_lanes, s.search_block, s.best_block, s.aux_block
 
     def ft_batch_poll(self, ticket: int) -> bool:
         d = ct.c_int32()

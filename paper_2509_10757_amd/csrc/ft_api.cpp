@@ -768,12 +768,23 @@ bool cache_lookup(const std::string &path, const std::string &key, Shapes &out)
     while (std::getline(f, line)) {
         if (line.find(tag) == std::string::npos) continue;
         const size_t pb = line.find("\"best_lanes\": "), ps = line.find("\"search_lanes\": ");
-        if (pb == std::string::npos || ps == std::string::npos) continue;
+        const size_t pk = line.find("\"search_block\": "), pbb = line.find("\"best_block\": ");
+        const size_t pa = line.find("\"aux_block\": ");
+        if (pb == std::string::npos || ps == std::string::npos || pk == std::string::npos ||
+            pbb == std::string::npos || pa == std::string::npos)
+            continue;
         const int b = std::atoi(line.c_str() + pb + 14);
         const int s = std::atoi(line.c_str() + ps + 16);
-        if (valid_lanes(b) && valid_lanes(s)) {
+        const int k = std::atoi(line.c_str() + pk + 16);
+        const int kb = std::atoi(line.c_str() + pbb + 14);
+        const int ka = std::atoi(line.c_str() + pa + 13);
+        auto blk = [](int v) { return v == kWG || v == kSearchWG; };
+        if (valid_lanes(b) && valid_lanes(s) && blk(k) && blk(kb) && blk(ka)) {
             out.best_lanes = b;
             out.search_lanes = s;
+            out.search_wide = k == kSearchWG;
+            out.best_wide = kb == kSearchWG;
+            out.wide_misc = ka == kSearchWG;
             return true;
         }
     }
@@ -786,7 +797,9 @@ bool cache_append(const std::string &path, const std::string &key, const Shapes 
     std::ofstream f(path, std::ios::app);
     if (!f) return false;
     f << "{\"key\": \"" << key << "\", \"best_lanes\": " << sh.best_lanes
-      << ", \"search_lanes\": " << sh.search_lanes << ", \"us\": " << us << "}\n";
+      << ", \"search_lanes\": " << sh.search_lanes << ", \"search_block\": "
+      << (sh.search_wide ? kSearchWG : kWG) << ", \"best_block\": " << (sh.best_wide ? kSearchWG : kWG)
+      << ", \"aux_block\": " << (sh.wide_misc ? kSearchWG : kWG) << ", \"us\": " << us << "}\n";
     return (bool)f;
 }
 
@@ -939,8 +952,14 @@ ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *s)
     if (!ctx || !s) return FT_ERR_INVALID_ARGUMENT;
     if (!valid_lanes(s->best_lanes) || !valid_lanes(s->search_lanes))
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: lanes must be 1, 2, 4, 8 or 16");
+    auto block_ok = [](int b) { return b == kWG || b == kSearchWG; };
+    if (!block_ok(s->search_block) || !block_ok(s->best_block) || !block_ok(s->aux_block))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: blocks must be %d or %d", kWG, kSearchWG);
     ctx->shapes.best_lanes = s->best_lanes;
     ctx->shapes.search_lanes = s->search_lanes;
+    ctx->shapes.search_wide = s->search_block == kSearchWG;
+    ctx->shapes.best_wide = s->best_block == kSearchWG;
+    ctx->shapes.wide_misc = s->aux_block == kSearchWG;
     return FT_OK;
 }
 
@@ -994,6 +1013,9 @@ ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *s)
     if (!ctx || !s) return FT_ERR_INVALID_ARGUMENT;
     s->best_lanes = ctx->shapes.best_lanes;
     s->search_lanes = ctx->shapes.search_lanes;
+    s->search_block = ctx->shapes.search_wide ? kSearchWG : kWG;
+    s->best_block = ctx->shapes.best_wide ? kSearchWG : kWG;
+    s->aux_block = ctx->shapes.wide_misc ? kSearchWG : kWG;
     return FT_OK;
 }
 
@@ -1176,17 +1198,53 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
         double best_a = 1e30, best_s = 1e30;
         for (int g : cands) {
             Shapes sh = best;
+            sh.best_wide = false;
             sh.best_lanes = g;
             double us;
             if ((st = time_phase(sh, PH_STEREO_A, &us))) return st;
-            if (us < best_a) { best_a = us; best.best_lanes = g; }
+            if (us < best_a) {
+                best_a = us;
+                best.best_wide = false;
+                best.best_lanes = g;
+            }
+        }
+        {
+            Shapes sh = best;
+            sh.best_wide = true;
+            double us;
+            if ((st = time_phase(sh, PH_STEREO_A, &us))) return st;
+            if (us < best_a) {
+                best_a = us;
+                best.best_wide = true;
+            }
+        }
+        {   // setup sorts + stereo resolve: 256 or 1024 threads
+            double t[2][2];
+            for (int w = 0; w < 2; ++w) {
+                Shapes sh = best;
+                sh.wide_misc = w == 1;
+                if ((st = time_phase(sh, PH_SETUP, &t[w][0]))) return st;
+                if ((st = time_phase(sh, PH_STEREO_C, &t[w][1]))) return st;
+            }
+            best.wide_misc = t[1][0] + t[1][1] < t[0][0] + t[0][1];
+        }
+        {   // the LDS-staged search first, then the global scans by lane group
+            Shapes sh = best;
+            sh.search_wide = true;
+            if ((st = time_phase(sh, PH_SEARCH, &best_s))) return st;
+            best.search_wide = true;
         }
         for (int g : cands) {
             Shapes sh = best;
+            sh.search_wide = false;
             sh.search_lanes = g;
             double us;
             if ((st = time_phase(sh, PH_SEARCH, &us))) return st;
-            if (us < best_s) { best_s = us; best.search_lanes = g; }
+            if (us < best_s) {
+                best_s = us;
+                best.search_wide = false;
+                best.search_lanes = g;
+            }
         }
         set_timing(ctx, was_timing);
         ctx->shapes = best;
@@ -1196,6 +1254,9 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
     if (chosen) {
         chosen->best_lanes = ctx->shapes.best_lanes;
         chosen->search_lanes = ctx->shapes.search_lanes;
+        chosen->search_block = ctx->shapes.search_wide ? kSearchWG : kWG;
+        chosen->best_block = ctx->shapes.best_wide ? kSearchWG : kWG;
+        chosen->aux_block = ctx->shapes.wide_misc ? kSearchWG : kWG;
     }
     return FT_OK;
 }

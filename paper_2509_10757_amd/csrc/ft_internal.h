@@ -19,6 +19,8 @@ constexpr int kMaxMap = (1 << 23) - 1;
 constexpr int kKnnQueriesPerWG = 16;  // fisheye all-pairs: one 16-row MFMA block per workgroup
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
+constexpr int kRefineQPerWG = 16;     // ... 11x11 window, +-5 shifts: four matches per wave
+constexpr int kRefineQLds = 368;      // bytes of LDS per match (121 + 231, rounded to 16)
 
 enum Phase : int {
     PH_SETUP = 0,    // row sort / overlap lists / cell sort
@@ -118,9 +120,19 @@ struct DevJob {
 
 // Launch shapes of one submission (the autotuner chooses the lane groups).
 struct Shapes {
-    int best_lanes = 8;    // lanes cooperating on one pinhole left keypoint
-    int search_lanes = 4;  // lanes cooperating on one map point
+    int best_lanes = 8;        // lanes cooperating on one pinhole left keypoint
+    int search_lanes = 4;      // lanes cooperating on one map point (kWG-thread search)
+    bool search_wide = false;  // search in kSearchWG-thread tiles with the view staged in LDS
+    bool best_wide = false;    // stereo best match in kSearchWG-thread tiles (pinhole rows in LDS)
+    bool wide_misc = false;    // setup sorts and stereo resolve in kSearchWG-thread workgroups
 };
+
+// Wide search: threads per workgroup and LDS staging bytes.
+constexpr int kSearchWG = 1024;
+constexpr int kSearchLds = 64 * 1024;
+// Wide pinhole best match: lanes per left keypoint and keypoints per workgroup.
+constexpr int kBestWideLanes = 8;
+constexpr int kBestWideQ = 1024 / kBestWideLanes;
 
 // Tiles of each phase for each job, as prefix sums: batch launches map a flat
 // block index to (job, tile) with a binary search over them.

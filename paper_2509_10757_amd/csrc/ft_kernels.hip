@@ -51,6 +51,9 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 // the median pass (a strided loop body unrolled; surplus entries masked).
 constexpr int kSortUnroll = 4;
 
+// Candidates of a scan whose descriptors are read in one round.
+constexpr int kCandBatch = 3;
+
 // Candidates whose loads are issued together in the best-match and search scans.
 constexpr int kBestUnroll = 2;
 constexpr int kSearchUnroll = 2;
@@ -69,6 +72,28 @@ __device__ __forceinline__ int hamming(const Desc &u, const Desc &v)
     return __popc(u.a.x ^ v.a.x) + __popc(u.a.y ^ v.a.y) + __popc(u.a.z ^ v.a.z) +
            __popc(u.a.w ^ v.a.w) + __popc(u.b.x ^ v.b.x) + __popc(u.b.y ^ v.b.y) +
            __popc(u.b.z ^ v.b.z) + __popc(u.b.w ^ v.b.w);
+}
+
+__host__ __device__ inline int div_up(int n, int d) { return (n + d - 1) / d; }
+
+// The refinement runs four matches per wave for the 11x11 window and +-5 shifts.
+__host__ __device__ inline bool refine_quarter(const DevJob &J) { return J.half_win == 5 && J.half_range == 5; }
+
+__host__ __device__ inline int view_kp(const DevJob &J, int v) { return J.view[v].side ? J.R.n : J.L.n; }
+// LDS staging of the wide search: cell offsets, then 16-byte records.
+__host__ __device__ inline int lds_rec_offset(int cells) { return ((cells + 1) * 4 + 15) / 16 * 16; }
+
+__host__ __device__ inline bool search_in_lds(int cells, int nK)
+{
+    return lds_rec_offset(cells) + 16 * nK <= kSearchLds;
+}
+
+// LDS staging of the wide best match: row offsets, then 16-byte row records.
+__host__ __device__ inline int rows_lds_offset(int rows) { return ((rows + 1) * 4 + 15) / 16 * 16; }
+
+__host__ __device__ inline bool best_in_lds(int rows, int nR)
+{
+    return rows_lds_offset(rows) + 16 * nR <= kSearchLds;
 }
 
 // Entry l of a per-level table, selected from values loaded for every level
@@ -122,23 +147,24 @@ __device__ __forceinline__ Top2<T> top2_merge(Top2<T> t, T o1, T o2)
 }
 
 // Workgroup-wide exclusive scan of a[0..n) in LDS; returns the total.
+template <int NT>
 __device__ __forceinline__ int wg_exclusive_scan(int *a, int n, int *tmp)
 {
     const int tid = threadIdx.x;
-    const int per = (n + kWG - 1) / kWG;
+    const int per = (n + NT - 1) / NT;
     const int beg = min(tid * per, n), end = min(beg + per, n);
     int s = 0;
     for (int i = beg; i < end; ++i) s += a[i];
     tmp[tid] = s;
     __syncthreads();
-    for (int off = 1; off < kWG; off <<= 1) {
+    for (int off = 1; off < NT; off <<= 1) {
         const int v = tid >= off ? tmp[tid - off] : 0;
         __syncthreads();
         tmp[tid] += v;
         __syncthreads();
     }
     int run = tmp[tid] - s;
-    const int total = tmp[kWG - 1];
+    const int total = tmp[NT - 1];
     for (int i = beg; i < end; ++i) {
         const int v = a[i];
         a[i] = run;
@@ -178,33 +204,34 @@ __device__ __forceinline__ uint32_t band_rows(const DevJob &J, float y, int oct)
     return (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
+template <int NT>
 __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
     const int rows = J.rows, nR = J.R.n;
-    for (int r = tid; r < rows; r += kWG) cnt[r] = 0;
-    for (int j = tid; j < nR; j += kWG) J.claimR[j] = 0xFFFFFFFFu;
+    for (int r = tid; r < rows; r += NT) cnt[r] = 0;
+    for (int j = tid; j < nR; j += NT) J.claimR[j] = 0xFFFFFFFFu;
     __syncthreads();
-    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * kWG) {
+    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
         float y[kSortUnroll];
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) y[e] = J.R.y[min(j0 + e * kWG, nR - 1)];
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) y[e] = J.R.y[min(j0 + e * NT, nR - 1)];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-            if (j0 + e * kWG < nR) atomicAdd(&cnt[row_bin(y[e], rows)], 1);
+            if (j0 + e * NT < nR) atomicAdd(&cnt[row_bin(y[e], rows)], 1);
     }
     __syncthreads();
-    const int total = wg_exclusive_scan(cnt, rows, tmp);
-    for (int r = tid; r < rows; r += kWG) J.row_start[r] = cnt[r];
+    const int total = wg_exclusive_scan<NT>(cnt, rows, tmp);
+    for (int r = tid; r < rows; r += NT) J.row_start[r] = cnt[r];
     if (tid == 0) J.row_start[rows] = total;
     __syncthreads();
     const v4u *src = reinterpret_cast<const v4u *>(J.R.desc);
     v4u *dst = reinterpret_cast<v4u *>(J.tdesc);
-    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * kWG) {
+    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
         int oct[kSortUnroll];
         v4u da[kSortUnroll], db[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int j = min(j0 + e * kWG, nR - 1);
+            const int j = min(j0 + e * NT, nR - 1);
             x[e] = J.R.x[j];
             y[e] = J.R.y[j];
             oct[e] = J.R.oct[j];
@@ -213,7 +240,7 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int j = j0 + e * kWG;
+            const int j = j0 + e * NT;
             if (j < nR) {
                 const int pos = atomicAdd(&cnt[row_bin(y[e], rows)], 1);
                 RowRec rec;
@@ -230,11 +257,12 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
 }
 
 // ------------------------------------------- setup: overlap lists (fisheye)
+template <int NT>
 __device__ __forceinline__ int compact_range(const float *x, int n, float a, float b, int32_t *out, int *wsum)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int base = 0;
-    for (int s = 0; s < n; s += kWG) {
+    for (int s = 0; s < n; s += NT) {
         const int i = s + tid;
         const bool p = i < n && x[i] >= a && x[i] <= b;
         const unsigned long long m = __ballot(p);
@@ -244,24 +272,26 @@ __device__ __forceinline__ int compact_range(const float *x, int n, float a, flo
         int off = base;
         for (int w = 0; w < wave; ++w) off += wsum[w];
         if (p) out[off + rank] = i;
-        const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        int tot = 0;
+        for (int w = 0; w < NT / 64; ++w) tot += wsum[w];
         __syncthreads();
         base += tot;
     }
     return base;
 }
 
+template <int NT>
 __device__ __forceinline__ void ph_overlap(const DevJob &J, int *wsum)
 {
     const int tid = threadIdx.x;
-    for (int j = tid; j < J.R.n; j += kWG) J.claimR[j] = 0xFFFFFFFFu;
-    for (int i = tid; i < J.L.n; i += kWG) J.flag[i] = 0;
-    const int nQ = compact_range(J.L.x, J.L.n, J.ovl[0], J.ovl[1], J.qlist, wsum);
-    const int nT = compact_range(J.R.x, J.R.n, J.ovr[0], J.ovr[1], J.tlist, wsum);
+    for (int j = tid; j < J.R.n; j += NT) J.claimR[j] = 0xFFFFFFFFu;
+    for (int i = tid; i < J.L.n; i += NT) J.flag[i] = 0;
+    const int nQ = compact_range<NT>(J.L.x, J.L.n, J.ovl[0], J.ovl[1], J.qlist, wsum);
+    const int nT = compact_range<NT>(J.R.x, J.R.n, J.ovr[0], J.ovr[1], J.tlist, wsum);
     // targets' descriptors in overlap order: one 16-byte half per thread step
     const uint4 *src = reinterpret_cast<const uint4 *>(J.R.desc);
     uint4 *dst = reinterpret_cast<uint4 *>(J.tdesc);
-    for (int h = tid; h < 2 * nT; h += kWG) dst[h] = src[2 * J.tlist[h >> 1] + (h & 1)];
+    for (int h = tid; h < 2 * nT; h += NT) dst[h] = src[2 * J.tlist[h >> 1] + (h & 1)];
     if (tid == 0) {
         J.counts[0] = nQ;
         J.counts[1] = nT;
@@ -270,25 +300,26 @@ __device__ __forceinline__ void ph_overlap(const DevJob &J, int *wsum)
 }
 
 // ------------------------------------------------ setup: keypoint grid
+template <int NT>
 __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
     const int cells = V.cols * V.rows;
-    for (int c = tid; c < cells; c += kWG) cnt[c] = 0;
-    for (int k = tid; k < K.n; k += kWG) V.claim[k] = 0xFFFFFFFFu;
+    for (int c = tid; c < cells; c += NT) cnt[c] = 0;
+    for (int k = tid; k < K.n; k += NT) V.claim[k] = 0xFFFFFFFFu;
     if (tid == 0) *V.n_matches = 0;
     __syncthreads();
-    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * kWG) {
+    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int k = min(k0 + e * kWG, K.n - 1);
+            const int k = min(k0 + e * NT, K.n - 1);
             x[e] = K.x[k];
             y[e] = K.y[k];
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            if (k0 + e * kWG < K.n) {
+            if (k0 + e * NT < K.n) {
                 const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
                 const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
                 atomicAdd(&cnt[cy * V.cols + cx], 1);
@@ -296,19 +327,19 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
         }
     }
     __syncthreads();
-    const int total = wg_exclusive_scan(cnt, cells, tmp);
-    for (int c = tid; c < cells; c += kWG) V.cell_off[c] = cnt[c];
+    const int total = wg_exclusive_scan<NT>(cnt, cells, tmp);
+    for (int c = tid; c < cells; c += NT) V.cell_off[c] = cnt[c];
     if (tid == 0) V.cell_off[cells] = total;
     __syncthreads();
     const v4u *dsrc = reinterpret_cast<const v4u *>(K.desc);
     v4u *ddst = reinterpret_cast<v4u *>(V.cdesc);
-    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * kWG) {
+    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
         uint32_t meta[kSortUnroll];
         v4u da[kSortUnroll], db[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int k = min(k0 + e * kWG, K.n - 1);
+            const int k = min(k0 + e * NT, K.n - 1);
             x[e] = K.x[k];
             y[e] = K.y[k];
             const uint32_t pre = (V.preassigned && V.preassigned[k]) ? 1u : 0u;
@@ -318,7 +349,7 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            if (k0 + e * kWG < K.n) {
+            if (k0 + e * NT < K.n) {
                 const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
                 const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
                 const int pos = atomicAdd(&cnt[cy * V.cols + cx], 1);
@@ -404,6 +435,105 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
     }
 }
 
+// Row-band scan of one pinhole left keypoint over staged (LDS) or global row
+// records: lane `sub` of G takes every G-th record of the bins row +- reach;
+// the candidates are collected first (kCandBatch at a time) and their
+// row-ordered descriptors then read together (as in the wide search).
+template <int G>
+__device__ __forceinline__ void best_scan(const DevJob &J, const int *rs, const RowRec *rr, int row, int oi,
+                                          float minU, float maxU, const Desc &di, int sub, uint32_t &best,
+                                          float &bx)
+{
+    const int b0 = max(row - J.row_reach, 0);
+    const int b1 = min(row + J.row_reach, J.rows - 1);
+    const int p0 = rs[b0], p1 = rs[b1 + 1];
+    int done = 0;
+    for (;;) {
+        int n = 0, seen = 0;
+        int cp[kCandBatch];
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cp[e] = 0;
+        for (int p = p0 + sub; p < p1; p += G) {
+            const RowRec rec = rr[p];
+            const int lo = (int)(rec.band & 0xFFFFu), hi = (int)(rec.band >> 16);
+            const int oj = (int)(rec.meta & 0xFFu);
+            if (row < lo || row > hi || oj < oi - J.level_window || oj > oi + J.level_window ||
+                !(rec.x >= minU && rec.x <= maxU))
+                continue;
+            if (seen >= done && n < kCandBatch) {
+                _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (n == e) cp[e] = p;
+                ++n;
+            }
+            ++seen;
+        }
+        Desc d[kCandBatch];
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (e < n) d[e] = load_desc(J.tdesc, cp[e]);
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+        {
+            if (e < n) {
+                const RowRec rec = rr[cp[e]];
+                const uint32_t key = ((uint32_t)hamming(di, d[e]) << 16) | (rec.meta >> 16);
+                if (key < best) {
+                    best = key;
+                    bx = rec.x;
+                }
+            }
+        }
+        done += n;
+        if (done >= seen) break;
+    }
+}
+
+// Pinhole best match in kSearchWG-thread tiles (kBestWideQ left keypoints,
+// kBestWideLanes lanes each).  The workgroup stages the frame's row offsets
+// and row records in LDS when they fit (best_in_lds), else scans global memory.
+__device__ __forceinline__ void ph_best_wide(const DevJob &J, int tile, unsigned char *smem)
+{
+    constexpr int G = kBestWideLanes;
+    const int sub = threadIdx.x % G;
+    const int i = tile * kBestWideQ + (int)threadIdx.x / G;
+    // the query's own loads first: they overlap the staging
+    bool q = false;
+    float x = 0.0f, y = 0.0f;
+    int oi = 0;
+    Desc di = {};
+    if (i < J.L.n) {
+        y = J.L.y[i];
+        x = J.L.x[i];
+        oi = J.L.oct[i];
+        di = load_desc(J.L.desc, i);
+    }
+    const float minU = x - J.maxD, maxU = x - 0.0f;
+    q = i < J.L.n && y > -1.0f && y < (float)J.rows && !(maxU < 0.0f);
+    const int row = q ? (int)y : 0;
+    uint32_t best = 0xFFFFFFFFu;   // Hamming << 16 | right index
+    float bx = 0.0f;               // x of that right keypoint (for the refinement)
+    if (best_in_lds(J.rows, J.R.n)) {
+        int *srs = reinterpret_cast<int *>(smem);
+        RowRec *srr = reinterpret_cast<RowRec *>(smem + rows_lds_offset(J.rows));
+        for (int r = threadIdx.x; r <= J.rows; r += kSearchWG) srs[r] = J.row_start[r];
+        for (int p = threadIdx.x; p < J.R.n; p += kSearchWG) srr[p] = J.rrec[p];
+        __syncthreads();
+        if (q) best_scan<G>(J, srs, srr, row, oi, minU, maxU, di, sub, best, bx);
+    } else if (q) {
+        best_scan<G>(J, J.row_start, J.rrec, row, oi, minU, maxU, di, sub, best, bx);
+    }
+    for (int m = 1; m < G; m <<= 1) {
+        const uint32_t o = __shfl_xor(best, m);
+        const float ox = __shfl_xor(bx, m);
+        if (o < best) {
+            best = o;
+            bx = ox;
+        }
+    }
+    if (sub == 0 && i < J.L.n) {
+        const int h = (int)(best >> 16);
+        const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
+        J.best_j[i] = ok ? (int)(best & 0xFFFFu) : -1;
+        J.best_h[i] = ok ? h : -1;
+        J.best_x[i] = bx;
+    }
+}
+
 // ----------------------------- stereo_a (fisheye): all-pairs top-2 on MFMA
 // H(a, b) = (256 - <a, b>) / 2 for the +-1 expansions of two descriptors.
 // A workgroup owns 16 queries (one MFMA row block); its four waves take every
@@ -412,20 +542,26 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
 // K-steps of v_mfma_i32_16x16x64_i8 (two bytes = sixteen int8 per step); the A
 // and B operands use the same byte-to-K assignment, so the dot product is the
 // full 256-term sum whatever order the hardware sums K in.
+// NT threads = NT / 256 independent subgroups of four waves; subgroup k of
+// tile t owns queries (t * NT / 256 + k) * 16 ... + 15.  `part` holds 128
+// words per subgroup.  Every thread reaches both barriers.
+template <int NT>
 __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab, uint32_t *part)
 {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, ltid = tid & 255, sg = tid >> 8;
     // +-1 expansion of every byte value: bit t -> byte t, 1 -> +1, 0 -> -1
-    {
+    if (tid < 256) {
         uint64_t e = 0;
         for (int t = 0; t < 8; ++t) e |= (uint64_t)(((tid >> t) & 1) ? 0x01u : 0xFFu) << (8 * t);
         tab[tid] = e;
     }
     __syncthreads();
     const int nQ = J.counts[0], nT = J.counts[1];
-    const int q0 = tile * kKnnQueriesPerWG;
-    if (q0 >= nQ || nT < 2) return;   // uniform over the workgroup
-    const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int q0 = (tile * (NT / 256) + sg) * kKnnQueriesPerWG;
+    part += sg * 128;
+    const bool active = q0 < nQ && nT >= 2;   // uniform over the subgroup
+    const int lane = ltid & 63, wave = ltid >> 6, g = lane >> 4, c = lane & 15;
+    if (active) {
     v4i A[4];
     {
         const int qa = q0 + c;
@@ -477,11 +613,12 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
         pw[0] = t0.a; pw[1] = t0.b; pw[2] = t1.a; pw[3] = t1.b;
         pw[4] = t2.a; pw[5] = t2.b; pw[6] = t3.a; pw[7] = t3.b;
     }
+    }
     __syncthreads();
-    if (tid < 16 && q0 + tid < nQ) {
-        Top2<uint32_t> t = {part[tid * 2], part[tid * 2 + 1]};
-        for (int w = 1; w < 4; ++w) t = top2_merge(t, part[(w * 16 + tid) * 2], part[(w * 16 + tid) * 2 + 1]);
-        const int i = J.qlist[q0 + tid];
+    if (active && ltid < 16 && q0 + ltid < nQ) {
+        Top2<uint32_t> t = {part[ltid * 2], part[ltid * 2 + 1]};
+        for (int w = 1; w < 4; ++w) t = top2_merge(t, part[(w * 16 + ltid) * 2], part[(w * 16 + ltid) * 2 + 1]);
+        const int i = J.qlist[q0 + ltid];
         J.best_j[i] = J.tlist[t.a & 0xFFFFu];
         J.best_h[i] = (int)(t.a >> 16);
         J.h2[i] = (int)(t.b >> 16);
@@ -491,7 +628,8 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
 // ------------------------------------- stereo_b (pinhole): SAD refinement
 // One wave per match.  The wave stages the left patch and the right strip of
 // the left keypoint's level in LDS, then 64 lanes split the (shift, row) sums.
-__device__ __forceinline__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
+// General window sizes: one wave per match, lanes split the (shift, row) sums.
+__device__ __forceinline__ void ph_refine_wave(const DevJob &J, int tile, uint8_t *lds)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = tile * kRefinePerWG + wave;
@@ -592,6 +730,117 @@ __device__ __forceinline__ void ph_refine(const DevJob &J, int tile, uint8_t *ld
     J.depth[i] = J.bf / disp;
     J.flag[i] = 1;
     atomicMin(&J.claimR[j], ((uint32_t)bh << 23) | (uint32_t)i);
+}
+
+// The usual 11x11 window and +-5 shifts: four matches per wave, sixteen lanes
+// each; lane k of a match stages its share of the windows and computes SAD of
+// shift k - 5 alone, so the argmin is a 16-lane shuffle reduction.  A quarter
+// of the waves of the general path, the same dependent round trips.
+__device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uint8_t *lds)
+{
+    constexpr int w = 5, L = 5, side = 2 * w + 1, strip = 2 * (L + w) + 1, nS = 2 * L + 1;
+    constexpr int nP = side * side, nT = nP + side * strip;
+    static_assert(nT <= kRefineQLds, "refine windows");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ql = lane & 15, slot = wave * 4 + (lane >> 4);
+    const int i = tile * kRefineQPerWG + slot;
+    int j = -1, l = 0, su = 0, sv = 0, su0 = 0, Wl = 0, bh = 0;
+    float xi = 0.0f, sfl = 0.0f;
+    int64_t off = 0;
+    bool act = false;
+    if (i < J.L.n) {
+        // everything the match needs is indexed by i: one round of loads
+        j = J.best_j[i];
+        bh = J.best_h[i];
+        const float xj = J.best_x[i];
+        xi = J.L.x[i];
+        const float yi = J.L.y[i];
+        l = lvl(J.L.oct[i]);
+        if (j >= 0) {
+            const float s = pick_level(J.inv_sf, l);
+            sfl = pick_level(J.sf, l);
+            su = (int)roundf(xi * s);
+            sv = (int)roundf(yi * s);
+            su0 = (int)roundf(xj * s);
+            Wl = pick_level(J.lv_w, l);
+            const int Hl = pick_level(J.lv_h, l);
+            off = pick_level(J.lv_off, l);
+            act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
+                  su0 + L + w < Wl;
+        }
+    }
+    uint8_t *P = lds + slot * kRefineQLds;   // left patch [side][side]
+    uint8_t *S = P + nP;                     // right strip [side][strip]
+    if (act) {
+        const uint8_t *IL = J.pyrL + off;
+        const uint8_t *IR = J.pyrR + off;
+        _Pragma("unroll") for (int e0 = 0; e0 < nT; e0 += 16)
+        {
+            const int e = e0 + ql;
+            if (e < nP) {
+                const int r = e / side, c = e - r * side;
+                P[e] = IL[(size_t)(sv - w + r) * Wl + su - w + c];
+            } else if (e < nT) {
+                const int e2 = e - nP, r = e2 / strip, c = e2 - r * strip;
+                P[e] = IR[(size_t)(sv - w + r) * Wl + su0 - L - w + c];
+            }
+        }
+    }
+    __syncthreads();
+    int sad = 0;
+    uint32_t key = 0xFFFFFFFFu;   // SAD << 4 | lane: ties go to the smaller shift
+    if (act && ql < nS) {
+        const int cL = P[w * side + w];
+        const int cR = S[w * strip + ql + w];
+        _Pragma("unroll 1") for (int r = 0; r < side; ++r)
+        {
+            _Pragma("unroll") for (int dx = 0; dx < side; ++dx)
+                sad += abs(((int)P[r * side + dx] - cL) - ((int)S[r * strip + ql + dx] - cR));
+        }
+        key = ((uint32_t)sad << 4) | (uint32_t)ql;
+    }
+    for (int m = 8; m >= 1; m >>= 1) {
+        const uint32_t o = __shfl_xor(key, m);
+        key = o < key ? o : key;
+    }
+    const int kb = (int)(key & 15u) - L;
+    const int base = lane & ~15;
+    const int a = __shfl(sad, base + max(kb + L - 1, 0));
+    const int e = __shfl(sad, base + min(kb + L + 1, nS - 1));
+    if (ql != 0 || i >= J.L.n) return;
+    if (!act || kb == -L || kb == L) {
+        J.flag[i] = 0;
+        return;
+    }
+    const int c = (int)(key >> 4);
+    const float num = (float)(a - e);
+    const float den = (float)(2 * (a + e - 2 * c));
+    const float delta = num / den;
+    if (delta < -1.0f || delta > 1.0f) {
+        J.flag[i] = 0;
+        return;
+    }
+    float uR = sfl * (((float)su0 + (float)kb) + delta);
+    float disp = xi - uR;
+    if (!(disp >= 0.0f && disp < J.maxD)) {
+        J.flag[i] = 0;
+        return;
+    }
+    if (disp <= 0.0f) {
+        disp = 0.01f;
+        uR = (float)((double)xi - 0.01);
+    }
+    J.sad[i] = c;
+    J.uR[i] = uR;
+    J.depth[i] = J.bf / disp;
+    J.flag[i] = 1;
+    atomicMin(&J.claimR[j], ((uint32_t)bh << 23) | (uint32_t)i);
+}
+
+__device__ __forceinline__ void ph_refine(const DevJob &J, int tile, uint8_t *lds)
+{
+    if (refine_quarter(J)) ph_refine_quarter(J, tile, lds);
+    else ph_refine_wave(J, tile, lds);
 }
 
 // ------------------------------- stereo_b (fisheye): ratio + triangulation
@@ -748,12 +997,13 @@ __device__ __forceinline__ void ph_tri(const DevJob &J, int tile)
 // ---------------------- stereo_c (pinhole): conflicts + median + outputs
 // The median is the value at rank n/2 of the survivors' 16-bit SADs, found by
 // a two-pass 8-bit radix select with a parallel prefix over the 256 bins.
+template <int NT>
 __device__ __forceinline__ int select_bin(int *hist, int *tmp, int target, int *out_rank, int *found)
 {
     const int tid = threadIdx.x;
-    const int h = hist[tid];
-    wg_exclusive_scan(hist, 256, tmp);   // hist now holds exclusive prefixes
-    if (h > 0 && hist[tid] <= target && target < hist[tid] + h) {
+    const int h = tid < 256 ? hist[tid] : 0;
+    wg_exclusive_scan<NT>(hist, 256, tmp);   // hist now holds exclusive prefixes
+    if (tid < 256 && h > 0 && hist[tid] <= target && target < hist[tid] + h) {
         found[0] = tid;
         found[1] = target - hist[tid];
     }
@@ -766,20 +1016,21 @@ __device__ __forceinline__ int select_bin(int *hist, int *tmp, int target, int *
 
 __device__ __forceinline__ bool bit(const uint32_t *b, int i) { return (b[i >> 5] >> (i & 31)) & 1u; }
 
+template <int NT>
 __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, int *sh)
 {
     const int tid = threadIdx.x, nL = J.L.n;
-    hist[tid] = 0;
+    if (tid < 256) hist[tid] = 0;
     if (tid == 0) sh[0] = 0;
-    for (int w = tid; w < (nL + 31) / 32; w += kWG) surv[w] = 0;
+    for (int w = tid; w < (nL + 31) / 32; w += NT) surv[w] = 0;
     __syncthreads();
     int my_n = 0;
-    for (int i0 = tid; i0 < nL; i0 += kSortUnroll * kWG) {
+    for (int i0 = tid; i0 < nL; i0 += kSortUnroll * NT) {
         int fl[kSortUnroll], bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
         uint32_t cl[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int i = min(i0 + e * kWG, nL - 1);
+            const int i = min(i0 + e * NT, nL - 1);
             fl[e] = J.flag[i];
             bj[e] = J.best_j[i];
             bh[e] = J.best_h[i];
@@ -789,7 +1040,7 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) cl[e] = J.claimR[fl[e] ? bj[e] : 0];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int i = i0 + e * kWG;
+            const int i = i0 + e * NT;
             const bool s = i < nL && fl[e] && cl[e] == (((uint32_t)bh[e] << 23) | (uint32_t)i);
             if (s) {
                 atomicOr(&surv[i >> 5], 1u << (i & 31));
@@ -804,25 +1055,25 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
     int m = 0;
     if (n > 0) {
         int rank;
-        const int hb = select_bin(hist, tmp, n / 2, &rank, sh + 2);
-        hist[tid] = 0;
+        const int hb = select_bin<NT>(hist, tmp, n / 2, &rank, sh + 2);
+        if (tid < 256) hist[tid] = 0;
         __syncthreads();
-        for (int i = tid; i < nL; i += kWG)
+        for (int i = tid; i < nL; i += NT)
             if (bit(surv, i) && ((J.sad[i] >> 8) & 0xFF) == hb) atomicAdd(&hist[J.sad[i] & 0xFF], 1);
         __syncthreads();
         int rank2;
-        const int lb = select_bin(hist, tmp, rank, &rank2, sh + 2);
+        const int lb = select_bin<NT>(hist, tmp, rank, &rank2, sh + 2);
         m = (hb << 8) | lb;
     }
     if (tid == 0) sh[1] = 0;
     __syncthreads();
     int kept = 0;
-    for (int i0 = tid; i0 < nL; i0 += kSortUnroll * kWG) {
+    for (int i0 = tid; i0 < nL; i0 += kSortUnroll * NT) {
         int bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
         float ur[kSortUnroll], dp[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int i = min(i0 + e * kWG, nL - 1);
+            const int i = min(i0 + e * NT, nL - 1);
             bj[e] = J.best_j[i];
             bh[e] = J.best_h[i];
             sd[e] = J.sad[i];
@@ -831,7 +1082,7 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
-            const int i = i0 + e * kWG;
+            const int i = i0 + e * NT;
             if (i >= nL) continue;
             const bool keep = bit(surv, i) && (long long)J.med_den * sd[e] < (long long)J.med_num * m;
             J.o_right_idx[i] = keep ? bj[e] : -1;
@@ -848,9 +1099,10 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
 }
 
 // ---------------------- stereo_c (fisheye): conflicts + outputs
+template <int NT>
 __device__ __forceinline__ void ph_fish_final(const DevJob &J, int tile)
 {
-    const int i = tile * kWG + threadIdx.x;
+    const int i = tile * NT + threadIdx.x;
     bool keep = false;
     if (i < J.L.n) {
         keep = J.flag[i] &&
@@ -882,109 +1134,143 @@ __device__ __forceinline__ void ph_fish_final(const DevJob &J, int tile)
 // covers the rounding of the cell arithmetic) and merges its top-2 lists.
 // Keys order candidates by (distance, keypoint index): distance << 40 |
 // index << 8 | level.
-template <int G>
-__device__ __forceinline__ void ph_search(const DevJob &J, const DevView &V, int tile)
+// What one map point looks for in one view: its projection, the search
+// window (radius, levels, cells) and its descriptor.
+struct Query {
+    bool vis;
+    bool gate;          // stereo right-coordinate gate applies
+    float u, v, Rm, uR;
+    int cx0, cx1, cy0, cy1, plo, phi;
+    Desc dm;
+};
+
+__device__ __forceinline__ Query make_query(const DevJob &J, const DevView &V, int m)
 {
-    const int sub = threadIdx.x % G;
-    const int m = tile * (kWG / G) + threadIdx.x / G;
-    Top2<uint64_t> top = {~0ull, ~0ull};
-    if (m < J.nM) {
-        // every field of the map point record is issued up front (one round trip)
-        const float X = J.pos[3 * m], Y = J.pos[3 * m + 1], Z = J.pos[3 * m + 2];
-        const float nx = J.normal[3 * m], ny = J.normal[3 * m + 1], nz = J.normal[3 * m + 2];
-        const float dmin = J.dmin[m], dmax = J.dmax[m];
-        const Desc dm = load_desc(J.mdesc, m);
-        const float xc = ((V.R[0] * X + V.R[1] * Y) + V.R[2] * Z) + V.t[0];
-        const float yc = ((V.R[3] * X + V.R[4] * Y) + V.R[5] * Z) + V.t[1];
-        const float zc = ((V.R[6] * X + V.R[7] * Y) + V.R[8] * Z) + V.t[2];
-        float u = 0.0f, v = 0.0f;
-        bool vis = false;
-        if (zc > 0.0f) {
-            if (V.model == FT_CAMERA_PINHOLE) {
-                u = ((V.fx * xc) / zc) + V.cx;
-                v = ((V.fy * yc) / zc) + V.cy;
-            } else {
-                const float kb[8] = {V.fx, V.fy, V.cx, V.cy, V.k[0], V.k[1], V.k[2], V.k[3]};
-                const double Pc[3] = {(double)xc, (double)yc, (double)zc};
-                double uv[2];
-                kb_project(kb, Pc, uv);
-                u = (float)uv[0];
-                v = (float)uv[1];
-            }
-            vis = u >= V.min_x && u <= V.max_x && v >= V.min_y && v <= V.max_y;
+    Query q;
+    // every field of the map point record is issued up front (one round trip)
+    const float X = J.pos[3 * m], Y = J.pos[3 * m + 1], Z = J.pos[3 * m + 2];
+    const float nx = J.normal[3 * m], ny = J.normal[3 * m + 1], nz = J.normal[3 * m + 2];
+    const float dmin = J.dmin[m], dmax = J.dmax[m];
+    q.dm = load_desc(J.mdesc, m);
+    const float xc = ((V.R[0] * X + V.R[1] * Y) + V.R[2] * Z) + V.t[0];
+    const float yc = ((V.R[3] * X + V.R[4] * Y) + V.R[5] * Z) + V.t[1];
+    const float zc = ((V.R[6] * X + V.R[7] * Y) + V.R[8] * Z) + V.t[2];
+    float u = 0.0f, v = 0.0f;
+    bool vis = false;
+    if (zc > 0.0f) {
+        if (V.model == FT_CAMERA_PINHOLE) {
+            u = ((V.fx * xc) / zc) + V.cx;
+            v = ((V.fy * yc) / zc) + V.cy;
+        } else {
+            const float kb[8] = {V.fx, V.fy, V.cx, V.cy, V.k[0], V.k[1], V.k[2], V.k[3]};
+            const double Pc[3] = {(double)xc, (double)yc, (double)zc};
+            double uv[2];
+            kb_project(kb, Pc, uv);
+            u = (float)uv[0];
+            v = (float)uv[1];
         }
-        const float pox = X - V.O[0], poy = Y - V.O[1], poz = Z - V.O[2];
-        const float dist = sqrtf((pox * pox + poy * poy) + poz * poz);
-        vis = vis && dist >= J.dist_lo * dmin && dist <= J.dist_hi * dmax;
-        const float vcos = ((pox * nx + poy * ny) + poz * nz) / dist;
-        vis = vis && vcos >= J.cos_lim;
-        if (vis) {
-            const float ratio = dmax / dist;
-            int pred = kLevels - 1;
-            for (int l = 0; l < kLevels; ++l)
-                if (J.sf[l] >= ratio) {
-                    pred = l;
-                    break;
-                }
-            const float rbase = (vcos > J.cos_narrow ? J.r_narrow : J.r_wide) * J.th;
-            const float Rm = rbase * J.sf[pred];
-            const bool gate = V.u_right != nullptr;
-            const float uR = gate ? u - V.bf * (1.0f / zc) : 0.0f;
-            // A candidate has |x - u| < Rm up to one rounding of the subtraction,
-            // so x lies within Rm + 0.01 px of u; cell_coord is monotone, so the
-            // cells of u -+ (Rm + 0.01) bracket the cells of every candidate.
-            const float Rc = Rm + 0.01f;
-            const int cx0 = cell_coord(u - Rc, V.min_x, V.inv_cw, V.cols);
-            const int cx1 = cell_coord(u + Rc, V.min_x, V.inv_cw, V.cols);
-            const int cy0 = cell_coord(v - Rc, V.min_y, V.inv_ch, V.rows);
-            const int cy1 = cell_coord(v + Rc, V.min_y, V.inv_ch, V.rows);
-            const int plo = pred - J.lv_lo, phi = pred + J.lv_hi;
-            // One record range per window row; the next row's bounds are
-            // loaded before the current row is scanned, and kSearchUnroll
-            // candidates' records and descriptors are loaded together
-            // (indices clamped into the range, surplus entries masked).
-            int c0 = V.cell_off[cy0 * V.cols + cx0];
-            int c1 = V.cell_off[cy0 * V.cols + cx1 + 1];
-            for (int cy = cy0; cy <= cy1; ++cy) {
-                int n0 = 0, n1 = 0;
-                if (cy < cy1) {
-                    n0 = V.cell_off[(cy + 1) * V.cols + cx0];
-                    n1 = V.cell_off[(cy + 1) * V.cols + cx1 + 1];
-                }
-                for (int p0 = c0 + sub; p0 < c1; p0 += kSearchUnroll * G) {
-                    CellRec rec[kSearchUnroll];
-                    bool cand[kSearchUnroll];
-                    Desc d[kSearchUnroll];
-                    float ur[kSearchUnroll];
-                    _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e) rec[e] = V.crec[min(p0 + e * G, c1 - 1)];
-                    // descriptors (and right coordinates) only for the records
-                    // that pass the position, level and preassignment tests
-                    _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
-                    {
-                        const int ok = (int)(rec[e].meta & 0xFFu);
-                        cand[e] = p0 + e * G < c1 && ok >= plo && ok <= phi && fabsf(rec[e].x - u) < Rm &&
-                                  fabsf(rec[e].y - v) < Rm && !(rec[e].meta & 0x100u);
-                        ur[e] = 0.0f;
-                        if (cand[e]) {
-                            d[e] = load_desc(V.cdesc, p0 + e * G);
-                            if (gate) ur[e] = V.u_right[rec[e].meta >> 16];
-                        }
-                    }
-                    _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
-                    {
-                        if (gate && ur[e] > 0.0f && !(fabsf(uR - ur[e]) <= Rm)) cand[e] = false;
-                        if (cand[e]) {
-                            const uint64_t h = (uint64_t)hamming(dm, d[e]);
-                            top = top2_insert(top, (h << 40) | ((uint64_t)(rec[e].meta >> 16) << 8) |
-                                                       (uint64_t)(rec[e].meta & 0xFFu));
-                        }
-                    }
-                }
-                c0 = n0;
-                c1 = n1;
-            }
-        }
+        vis = u >= V.min_x && u <= V.max_x && v >= V.min_y && v <= V.max_y;
     }
+    const float pox = X - V.O[0], poy = Y - V.O[1], poz = Z - V.O[2];
+    const float dist = sqrtf((pox * pox + poy * poy) + poz * poz);
+    vis = vis && dist >= J.dist_lo * dmin && dist <= J.dist_hi * dmax;
+    const float vcos = ((pox * nx + poy * ny) + poz * nz) / dist;
+    q.vis = vis && vcos >= J.cos_lim;
+    q.u = u;
+    q.v = v;
+    if (!q.vis) return q;
+    const float ratio = dmax / dist;
+    int pred = kLevels - 1;
+    for (int l = 0; l < kLevels; ++l)
+        if (J.sf[l] >= ratio) {
+            pred = l;
+            break;
+        }
+    const float rbase = (vcos > J.cos_narrow ? J.r_narrow : J.r_wide) * J.th;
+    q.Rm = rbase * J.sf[pred];
+    q.gate = V.u_right != nullptr;
+    q.uR = q.gate ? u - V.bf * (1.0f / zc) : 0.0f;
+    // A candidate has |x - u| < Rm up to one rounding of the subtraction, so x
+    // lies within Rm + 0.01 px of u; cell_coord is monotone, so the cells of
+    // u -+ (Rm + 0.01) bracket the cells of every candidate.
+    const float Rc = q.Rm + 0.01f;
+    q.cx0 = cell_coord(u - Rc, V.min_x, V.inv_cw, V.cols);
+    q.cx1 = cell_coord(u + Rc, V.min_x, V.inv_cw, V.cols);
+    q.cy0 = cell_coord(v - Rc, V.min_y, V.inv_ch, V.rows);
+    q.cy1 = cell_coord(v + Rc, V.min_y, V.inv_ch, V.rows);
+    q.plo = pred - J.lv_lo;
+    q.phi = pred + J.lv_hi;
+    return q;
+}
+
+// A keypoint record (level, position) is a candidate of the query, before the
+// stereo gate.
+__device__ __forceinline__ bool in_window(const Query &q, float x, float y, uint32_t meta)
+{
+    const int ok = (int)(meta & 0xFFu);
+    return ok >= q.plo && ok <= q.phi && fabsf(x - q.u) < q.Rm && fabsf(y - q.v) < q.Rm && !(meta & 0x100u);
+}
+
+__device__ __forceinline__ bool gate_rejects(const Query &q, float ur)
+{
+    return q.gate && ur > 0.0f && !(fabsf(q.uR - ur) <= q.Rm);
+}
+
+__device__ __forceinline__ uint64_t cand_key(int h, uint32_t meta)
+{
+    return ((uint64_t)h << 40) | ((uint64_t)(meta >> 16) << 8) | (uint64_t)(meta & 0xFFu);
+}
+
+// Scan of the window over the sorted records in global memory; lane `sub` of
+// G takes every G-th record.  One record range per window row; the next row's
+// bounds are loaded before the current row is scanned, and kSearchUnroll
+// records are loaded together (indices clamped into the range, surplus
+// entries masked), then the descriptors of the candidates among them.
+template <int G>
+__device__ __forceinline__ Top2<uint64_t> scan_global(const DevView &V, const Query &q, int sub)
+{
+    Top2<uint64_t> top = {~0ull, ~0ull};
+    int c0 = V.cell_off[q.cy0 * V.cols + q.cx0];
+    int c1 = V.cell_off[q.cy0 * V.cols + q.cx1 + 1];
+    for (int cy = q.cy0; cy <= q.cy1; ++cy) {
+        int n0 = 0, n1 = 0;
+        if (cy < q.cy1) {
+            n0 = V.cell_off[(cy + 1) * V.cols + q.cx0];
+            n1 = V.cell_off[(cy + 1) * V.cols + q.cx1 + 1];
+        }
+        for (int p0 = c0 + sub; p0 < c1; p0 += kSearchUnroll * G) {
+            CellRec rec[kSearchUnroll];
+            bool cand[kSearchUnroll];
+            Desc d[kSearchUnroll];
+            float ur[kSearchUnroll];
+            _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e) rec[e] = V.crec[min(p0 + e * G, c1 - 1)];
+            _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
+            {
+                cand[e] = p0 + e * G < c1 && in_window(q, rec[e].x, rec[e].y, rec[e].meta);
+                ur[e] = 0.0f;
+                if (cand[e]) {
+                    d[e] = load_desc(V.cdesc, p0 + e * G);
+                    if (q.gate) ur[e] = V.u_right[rec[e].meta >> 16];
+                }
+            }
+            _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
+            {
+                if (cand[e] && !gate_rejects(q, ur[e]))
+                    top = top2_insert(top, cand_key(hamming(q.dm, d[e]), rec[e].meta));
+            }
+        }
+        c0 = n0;
+        c1 = n1;
+    }
+    return top;
+}
+
+// Merge of the G lanes' lists, acceptance, outputs and the claim on the
+// matched keypoint.  Every lane of the wave calls it (shuffles).
+template <int G>
+__device__ __forceinline__ void finish_query(const DevJob &J, const DevView &V, int m, int sub,
+                                             Top2<uint64_t> top)
+{
     for (int o = 1; o < G; o <<= 1) top = top2_merge(top, shfl_xor64(top.a, o), shfl_xor64(top.b, o));
     if (sub != 0 || m >= J.nM) return;
     const uint64_t k1 = top.a, k2 = top.b;
@@ -1002,6 +1288,107 @@ __device__ __forceinline__ void ph_search(const DevJob &J, const DevView &V, int
     V.mp_k[m] = kk1;
     V.mp_h[m] = b1;
     if (kk1 >= 0) atomicMin(&V.claim[kk1], ((uint32_t)b1 << 23) | (uint32_t)m);
+}
+
+// Search by projection, kWG-thread tiles, G lanes per map point, records read
+// from global memory.
+template <int G>
+__device__ __forceinline__ void ph_search(const DevJob &J, const DevView &V, int tile)
+{
+    const int sub = threadIdx.x % G;
+    const int m = tile * (kWG / G) + threadIdx.x / G;
+    Top2<uint64_t> top = {~0ull, ~0ull};
+    if (m < J.nM) {
+        const Query q = make_query(J, V, m);
+        if (q.vis) top = scan_global<G>(V, q, sub);
+    }
+    finish_query<G>(J, V, m, sub, top);
+}
+
+// Search by projection, kSearchWG-thread tiles of one view, one lane per map
+// point.  The workgroup first stages the view's cell offsets and records (with
+// the right coordinate of the stereo gate) in LDS, so that a map point reads
+// only its own record and its candidates' descriptors from global memory.
+// Views whose grid does not fit (search_in_lds) scan global memory instead.
+struct LRec {
+    float x, y;
+    uint32_t meta;   // octave | preassigned << 8 | index << 16
+    float ur;        // right coordinate of the keypoint (stereo gate), or 0
+};
+
+
+// The window is scanned in LDS and its candidates are collected first (the
+// first kCandBatch not yet handled, in registers); their descriptors are then
+// read together.  A lane's candidates turn up at different iterations of the
+// scan than its neighbours', so reading each one as it is found would cost the
+// whole wave a global round trip at almost every iteration.  A lane with more
+// candidates rescans the window (LDS only) for the next batch.
+__device__ __forceinline__ Top2<uint64_t> scan_lds(const DevView &V, const Query &q, const int *soff,
+                                                   const LRec *srec)
+{
+    Top2<uint64_t> top = {~0ull, ~0ull};
+    int done = 0;
+    for (;;) {
+        int n = 0, seen = 0;
+        int cp[kCandBatch];   // record positions (their meta is re-read from LDS)
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cp[e] = 0;
+        for (int cy = q.cy0; cy <= q.cy1; ++cy) {
+            const int a = soff[cy * V.cols + q.cx0], b = soff[cy * V.cols + q.cx1 + 1];
+            for (int p = a; p < b; ++p) {
+                const LRec r = srec[p];
+                if (!in_window(q, r.x, r.y, r.meta) || gate_rejects(q, r.ur)) continue;
+                if (seen >= done && n < kCandBatch) {
+                    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (n == e) cp[e] = p;
+                    ++n;
+                }
+                ++seen;
+            }
+        }
+        Desc d[kCandBatch];
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (e < n) d[e] = load_desc(V.cdesc, cp[e]);
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+        {
+            if (e < n) top = top2_insert(top, cand_key(hamming(q.dm, d[e]), srec[cp[e]].meta));
+        }
+        done += n;
+        if (done >= seen) break;
+    }
+    return top;
+}
+
+__device__ __forceinline__ void ph_search_wide(const DevJob &J, int tile, unsigned char *smem)
+{
+    const int tpv = div_up(J.nM, kSearchWG);
+    const int v = tile / tpv;
+    if (v >= J.n_views) return;
+    const DevView &V = J.view[v];
+    const int nK = view_kp(J, v);
+    const int cells = V.cols * V.rows;
+    const int m = (tile - v * tpv) * kSearchWG + (int)threadIdx.x;
+    Top2<uint64_t> top = {~0ull, ~0ull};
+    if (search_in_lds(cells, nK)) {
+        Query q;
+        q.vis = false;
+        if (m < J.nM) q = make_query(J, V, m);   // its loads overlap the staging below
+        int *soff = reinterpret_cast<int *>(smem);
+        LRec *srec = reinterpret_cast<LRec *>(smem + lds_rec_offset(cells));
+        for (int c = threadIdx.x; c <= cells; c += kSearchWG) soff[c] = V.cell_off[c];
+        for (int p = threadIdx.x; p < nK; p += kSearchWG) {
+            const CellRec r = V.crec[p];
+            LRec l;
+            l.x = r.x;
+            l.y = r.y;
+            l.meta = r.meta;
+            l.ur = V.u_right ? V.u_right[r.meta >> 16] : 0.0f;
+            srec[p] = l;
+        }
+        __syncthreads();
+        if (q.vis) top = scan_lds(V, q, soff, srec);
+    } else if (m < J.nM) {
+        const Query q = make_query(J, V, m);
+        if (q.vis) top = scan_global<1>(V, q, 0);
+    }
+    finish_query<1>(J, V, m, 0, top);
 }
 
 __device__ __forceinline__ void ph_search_final(const DevJob &J, const DevView &V, int nK, int tile)
@@ -1024,14 +1411,12 @@ __device__ __forceinline__ void ph_search_final(const DevJob &J, const DevView &
 }
 
 // ------------------------------------------------------- tile bookkeeping
-__host__ __device__ inline int div_up(int n, int d) { return (n + d - 1) / d; }
-
-__host__ __device__ inline int view_kp(const DevJob &J, int v) { return J.view[v].side ? J.R.n : J.L.n; }
 
 __host__ __device__ inline int search_tiles_per_view(const DevJob &J, int lanes)
 {
     return div_up(J.nM, kWG / lanes);
 }
+
 
 __host__ __device__ inline int final_tiles_view(const DevJob &J, int v)
 {
@@ -1048,16 +1433,16 @@ void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search,
     const int nv = do_search ? J.n_views : 0;
     out[PH_SETUP] = (pin || fish ? 1 : 0) + nv;
     if (pin) {
-        out[PH_STEREO_A] = div_up(nL, kWG / s.best_lanes);
-        out[PH_REFINE] = div_up(nL, kRefinePerWG);
+        out[PH_STEREO_A] = s.best_wide ? div_up(nL, kBestWideQ) : div_up(nL, kWG / s.best_lanes);
+        out[PH_REFINE] = div_up(nL, refine_quarter(J) ? kRefineQPerWG : kRefinePerWG);
         out[PH_STEREO_C] = 1;
     } else if (fish) {
-        out[PH_STEREO_A] = div_up(nL, kKnnQueriesPerWG);
+        out[PH_STEREO_A] = div_up(nL, s.best_wide ? kKnnQueriesPerWG * (kSearchWG / kWG) : kKnnQueriesPerWG);
         out[PH_TRI] = div_up(nL, kWG);
-        out[PH_STEREO_C] = div_up(nL, kWG);
+        out[PH_STEREO_C] = div_up(nL, s.wide_misc ? kSearchWG : kWG);
     }
     for (int v = 0; v < nv; ++v) {
-        out[PH_SEARCH] += search_tiles_per_view(J, s.search_lanes);
+        out[PH_SEARCH] += s.search_wide ? div_up(J.nM, kSearchWG) : search_tiles_per_view(J, s.search_lanes);
         out[PH_SEARCH_FIN] += final_tiles_view(J, v);
     }
 }
@@ -1109,19 +1494,20 @@ struct JobTable {
 // `smem` is the workgroup's LDS scratch (kTaskLds bytes, 16-byte aligned).
 constexpr int kTaskLds = (kMaxCells + 8 + kWG) * 4;
 
+template <int NT>
 __device__ __forceinline__ void task_setup(const DevJob &J, int tile, unsigned char *smem)
 {
     int *lds = reinterpret_cast<int *>(smem);
     int *tmp = lds + kMaxCells + 8;
     const bool stereo = J.flags & (JOB_STEREO_PINHOLE | JOB_STEREO_FISHEYE);
     if (stereo && tile == 0) {
-        if (J.flags & JOB_STEREO_PINHOLE) ph_rowsort(J, lds, tmp);
-        else ph_overlap(J, tmp);
+        if (J.flags & JOB_STEREO_PINHOLE) ph_rowsort<NT>(J, lds, tmp);
+        else ph_overlap<NT>(J, tmp);
         return;
     }
     const int v = tile - (stereo ? 1 : 0);
     const DevView &V = J.view[v];
-    ph_cellsort(V, V.side ? J.R : J.L, lds, tmp);
+    ph_cellsort<NT>(V, V.side ? J.R : J.L, lds, tmp);
 }
 
 template <int G>
@@ -1130,17 +1516,31 @@ __device__ __forceinline__ void task_stereo_a(const DevJob &J, int tile, unsigne
     uint64_t *tab = reinterpret_cast<uint64_t *>(smem);
     uint32_t *part = reinterpret_cast<uint32_t *>(smem + 256 * sizeof(uint64_t));
     if (J.flags & JOB_STEREO_PINHOLE) ph_best<G>(J, tile);
-    else ph_knn(J, tile, tab, part);
+    else ph_knn<kWG>(J, tile, tab, part);
 }
 
+// Stereo best match in kSearchWG-thread tiles: pinhole frames take the wide
+// row-band scan, fisheye frames four kNN subgroups per workgroup.
+__device__ __forceinline__ void task_stereo_a_wide(const DevJob &J, int tile, unsigned char *smem)
+{
+    if (J.flags & JOB_STEREO_PINHOLE) {
+        ph_best_wide(J, tile, smem);
+    } else {
+        uint64_t *tab = reinterpret_cast<uint64_t *>(smem);
+        uint32_t *part = reinterpret_cast<uint32_t *>(smem + 256 * sizeof(uint64_t));
+        ph_knn<kSearchWG>(J, tile, tab, part);
+    }
+}
+
+template <int NT>
 __device__ __forceinline__ void task_stereo_c(const DevJob &J, int tile, unsigned char *smem)
 {
     int *hist = reinterpret_cast<int *>(smem);
     int *tmp = hist + 256;
-    int *sh = tmp + kWG;
+    int *sh = tmp + NT;
     uint32_t *surv = reinterpret_cast<uint32_t *>(sh + 8);
-    if (J.flags & JOB_STEREO_PINHOLE) ph_median(J, hist, tmp, surv, sh);
-    else ph_fish_final(J, tile);
+    if (J.flags & JOB_STEREO_PINHOLE) ph_median<NT>(J, hist, tmp, surv, sh);
+    else ph_fish_final<NT>(J, tile);
 }
 
 template <int G>
@@ -1161,17 +1561,19 @@ __device__ __forceinline__ void task_search_final(const DevJob &J, int tile)
 }
 
 static_assert(256 * 8 + 4 * 16 * 2 * 4 <= kTaskLds, "stereo_a LDS");
+static_assert(256 * 8 + (kSearchWG / 256) * 128 * 4 <= kSearchLds, "stereo_a LDS (wide)");
 static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
+static_assert(kRefineQPerWG * kRefineQLds <= kTaskLds, "refine LDS (quarter waves)");
 static_assert((256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4 <= kTaskLds, "median LDS");
 
 // ------------------------------------------------------- per-phase kernels
-template <class Src>
-__global__ __launch_bounds__(kWG) void k_setup(Src src)
+template <class Src, int NT>
+__global__ __launch_bounds__(NT) void k_setup(Src src)
 {
-    __shared__ __align__(16) unsigned char smem[kTaskLds];
+    __shared__ __align__(16) unsigned char smem[(kMaxCells + 8 + NT) * 4];
     int job, tile;
     if (!src.locate(PH_SETUP, job, tile)) return;
-    task_setup(src(job), tile, smem);
+    task_setup<NT>(src(job), tile, smem);
 }
 
 template <class Src, int G>
@@ -1186,7 +1588,9 @@ __global__ __launch_bounds__(kWG) void k_stereo_a(Src src)
 template <class Src>
 __global__ __launch_bounds__(kWG) void k_refine(Src src)
 {
-    __shared__ __align__(16) unsigned char smem[kRefinePerWG * kRefineLds];
+    __shared__ __align__(16) unsigned char smem[kRefineQPerWG * kRefineQLds > kRefinePerWG * kRefineLds
+                                                    ? kRefineQPerWG * kRefineQLds
+                                                    : kRefinePerWG * kRefineLds];
     int job, tile;
     if (!src.locate(PH_REFINE, job, tile)) return;
     ph_refine(src(job), tile, smem);
@@ -1200,13 +1604,13 @@ __global__ __launch_bounds__(kWG) void k_tri(Src src)
     ph_tri(src(job), tile);
 }
 
-template <class Src>
-__global__ __launch_bounds__(kWG) void k_stereo_c(Src src)
+template <class Src, int NT>
+__global__ __launch_bounds__(NT) void k_stereo_c(Src src)
 {
-    __shared__ __align__(16) unsigned char smem[(256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4];
+    __shared__ __align__(16) unsigned char smem[(256 + NT + 8) * 4 + (kMaxKp + 32) / 32 * 4];
     int job, tile;
     if (!src.locate(PH_STEREO_C, job, tile)) return;
-    task_stereo_c(src(job), tile, smem);
+    task_stereo_c<NT>(src(job), tile, smem);
 }
 
 template <class Src, int G>
@@ -1215,6 +1619,26 @@ __global__ __launch_bounds__(kWG) void k_search(Src src)
     int job, tile;
     if (!src.locate(PH_SEARCH, job, tile)) return;
     task_search<G>(src(job), tile);
+}
+
+// Two workgroups per CU (LDS) need 8 waves per SIMD: at most 64 VGPRs.
+template <class Src>
+__global__ __launch_bounds__(kSearchWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_stereo_a_wide(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[kSearchLds];
+    int job, tile;
+    if (!src.locate(PH_STEREO_A, job, tile)) return;
+    task_stereo_a_wide(src(job), tile, smem);
+}
+
+// Two workgroups per CU (LDS) need 8 waves per SIMD: at most 64 VGPRs.
+template <class Src>
+__global__ __launch_bounds__(kSearchWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_wide(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[kSearchLds];
+    int job, tile;
+    if (!src.locate(PH_SEARCH, job, tile)) return;
+    ph_search_wide(src(job), tile, smem);
 }
 
 template <class Src>
@@ -1326,11 +1750,11 @@ __global__ __launch_bounds__(kWG) void k_persistent(PersistArgs a)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the prerequisite phases' writes
         const DevJob &J = a.jobs[job];
         switch (p) {
-        case PH_SETUP: task_setup(J, tile, smem); break;
+        case PH_SETUP: task_setup<kWG>(J, tile, smem); break;
         case PH_STEREO_A: task_stereo_a<GB>(J, tile, smem); break;
         case PH_REFINE: ph_refine(J, tile, smem); break;
         case PH_TRI: ph_tri(J, tile); break;
-        case PH_STEREO_C: task_stereo_c(J, tile, smem); break;
+        case PH_STEREO_C: task_stereo_c<kWG>(J, tile, smem); break;
         case PH_SEARCH: task_search<GS>(J, tile); break;
         default: task_search_final(J, tile); break;
         }
@@ -1350,6 +1774,9 @@ static void *persistent_fn()
 Shapes persistent_shapes(const Shapes &s)
 {
     Shapes r = s;
+    r.search_wide = false;   // the persistent kernel's workgroups have kWG threads
+    r.best_wide = false;
+    r.wide_misc = false;
     r.best_lanes = s.best_lanes <= 4 ? 4 : (s.best_lanes >= 16 ? 16 : 8);
     r.search_lanes = s.search_lanes <= 1 ? 1 : (s.search_lanes >= 4 ? 4 : 2);
     return r;
@@ -1435,19 +1862,38 @@ static hipError_t run(Src src, const int32_t *tot, const Shapes &sh, hipStream_t
         if (ev) (void)hipEventRecord(ev[p], s);
     };
     mark(0);
-    if (tot[PH_SETUP] > 0) hipLaunchKernelGGL(k_setup<Src>, dim3(tot[PH_SETUP]), blk, 0, s, src);
+    if (tot[PH_SETUP] > 0) {
+        if (sh.wide_misc)
+            hipLaunchKernelGGL((k_setup<Src, kSearchWG>), dim3(tot[PH_SETUP]), dim3(kSearchWG), 0, s, src);
+        else
+            hipLaunchKernelGGL((k_setup<Src, kWG>), dim3(tot[PH_SETUP]), blk, 0, s, src);
+    }
     mark(1);
-    if (do_stereo && tot[PH_STEREO_A] > 0) launch_best(src, sh.best_lanes, tot[PH_STEREO_A], s);
+    if (do_stereo && tot[PH_STEREO_A] > 0) {
+        if (sh.best_wide)
+            hipLaunchKernelGGL(k_stereo_a_wide<Src>, dim3(tot[PH_STEREO_A]), dim3(kSearchWG), 0, s, src);
+        else
+            launch_best(src, sh.best_lanes, tot[PH_STEREO_A], s);
+    }
     mark(2);
     if (do_stereo && tot[PH_REFINE] > 0)
         hipLaunchKernelGGL(k_refine<Src>, dim3(tot[PH_REFINE]), blk, 0, s, src);
     mark(3);
     if (do_stereo && tot[PH_TRI] > 0) hipLaunchKernelGGL(k_tri<Src>, dim3(tot[PH_TRI]), blk, 0, s, src);
     mark(4);
-    if (do_stereo && tot[PH_STEREO_C] > 0)
-        hipLaunchKernelGGL(k_stereo_c<Src>, dim3(tot[PH_STEREO_C]), blk, 0, s, src);
+    if (do_stereo && tot[PH_STEREO_C] > 0) {
+        if (sh.wide_misc)
+            hipLaunchKernelGGL((k_stereo_c<Src, kSearchWG>), dim3(tot[PH_STEREO_C]), dim3(kSearchWG), 0, s, src);
+        else
+            hipLaunchKernelGGL((k_stereo_c<Src, kWG>), dim3(tot[PH_STEREO_C]), blk, 0, s, src);
+    }
     mark(5);
-    if (do_search && tot[PH_SEARCH] > 0) launch_search(src, sh.search_lanes, tot[PH_SEARCH], s);
+    if (do_search && tot[PH_SEARCH] > 0) {
+        if (sh.search_wide)
+            hipLaunchKernelGGL(k_search_wide<Src>, dim3(tot[PH_SEARCH]), dim3(kSearchWG), 0, s, src);
+        else
+            launch_search(src, sh.search_lanes, tot[PH_SEARCH], s);
+    }
     mark(6);
     if (do_search && tot[PH_SEARCH_FIN] > 0)
         hipLaunchKernelGGL(k_search_final<Src>, dim3(tot[PH_SEARCH_FIN]), blk, 0, s, src);

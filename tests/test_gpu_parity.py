@@ -230,9 +230,10 @@ def test_lane_groups_do_not_change_results(ft, ctx):
     jobs = [d.job() for d in dfs]
     ref = None
     try:
-        for gb, gs in [(1, 1), (2, 16), (4, 8), (8, 4), (16, 2)]:
-            ctx.ft_set_shapes(gb, gs)
-            say("shapes", gb, gs)
+        for shape in [(1, 1, 1024, 1024, 1024), (2, 16, 256, 256, 256), (4, 8, 256, 1024, 256),
+                      (8, 4, 1024, 256, 1024), (16, 2, 256, 256, 1024), (8, 1, 256, 1024, 256)]:
+            ctx.ft_set_shapes(*shape)
+            say("shapes", shape)
             ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
             torch.cuda.synchronize()
             res = [d.results() for d in dfs]
@@ -244,7 +245,7 @@ def test_lane_groups_do_not_change_results(ft, ctx):
                 for a, b in zip(res, ref):
                     bit_equal(a, b)
     finally:
-        ctx.ft_set_shapes(8, 4)
+        ctx.ft_set_shapes(8, 1, 256)
 
 
 def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
@@ -255,17 +256,19 @@ def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
     try:
         chosen = ctx.ft_autotune(jobs, cache)
         assert chosen[0] in (1, 2, 4, 8, 16) and chosen[1] in (1, 2, 4, 8, 16)
+        assert all(b in (256, 1024) for b in chosen[2:])
         text = open(cache).read()
         assert '"best_lanes": %d' % chosen[0] in text
-        ctx.ft_set_shapes(1, 1)
+        ctx.ft_set_shapes(1, 1, 1024, 1024, 1024)
         assert ctx.ft_autotune(jobs, cache) == chosen        # served from the cache
+        assert ctx.ft_get_shapes() == chosen
         assert open(cache).read() == text
         ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
         torch.cuda.synchronize()
         for f, d in zip(frames, dfs):
             compare_frame(d.results(), oracle.run_frame(f))
     finally:
-        ctx.ft_set_shapes(8, 4)
+        ctx.ft_set_shapes(8, 1, 256)
 
 
 def test_graph_replays_match_eager(ft, ctx):
@@ -412,3 +415,15 @@ def test_split_submissions_match_one_launch(ft, ctx):
     finally:
         ctx.ft_set_batch_parts(1)
         ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
+
+
+@pytest.mark.parametrize("half_win,half_range", [(3, 7), (5, 9), (2, 2)])
+def test_refinement_window_sizes(ft, ctx, half_win, half_range):
+    """Windows other than 11x11 / +-5 take the one-wave-per-match refinement;
+    single-frame and batched results equal the oracle."""
+    f = synth.pinhole_frame_1200()[0]
+    f["stereo_params"] = dict(f["stereo_params"], half_win=half_win, half_range=half_range)
+    say("refinement window", half_win, half_range)
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, ctx, f), want)
+    compare_frame(run_device(ft, ctx, f, batch=True), want)
