@@ -1290,6 +1290,161 @@ __device__ __forceinline__ void finish_query(const DevJob &J, const DevView &V, 
     if (kk1 >= 0) atomicMin(&V.claim[kk1], ((uint32_t)b1 << 23) | (uint32_t)m);
 }
 
+// Balanced search (one lane per map point).  A lane projects its map point; the
+// wave then splits the work of all its windows into items of one window row
+// (about 2.5 records each) and deals the items round-robin to its lanes, so
+// a map point with a large window does not hold its whole wave.  Candidates are
+// batched per lane (kCandBatch) for their descriptor reads, and each map
+// point's best two keys are kept in LDS by 64-bit atomic minima: a key goes to
+// the best slot, and whichever of it and the displaced best is larger goes to
+// the second slot, which leaves the two smallest distinct keys.
+constexpr int kFlatRowsPerPass = 4;                  // window rows per lane and pass
+constexpr int kFlatItems = 64 * kFlatRowsPerPass;    // items per wave and pass
+constexpr int kFlatRecs = 3;                         // records of an item loaded together
+constexpr int kFlatLdsPerWave = kFlatItems * 8 + 64 * 4 * 6 + 128 * 8 + 64 * 32;
+
+// Orders one wave's LDS accesses (its lanes read what other lanes wrote); the
+// balanced search syncs only within a wave, whose pass count is wave-uniform
+// but may differ between the waves of a workgroup.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct FlatCand {
+    int p;    // record position
+    int ml;   // lane of the map point
+};
+
+__device__ __forceinline__ void flat_flush(const DevView &V, const FlatCand *c, int nc, const float *quR,
+                                           const float *qR, const Desc *qd, unsigned long long *tb)
+{
+    Desc d[kCandBatch];
+    float ur[kCandBatch];
+    uint32_t meta[kCandBatch];
+    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+    {
+        if (e < nc) {
+            d[e] = load_desc(V.cdesc, c[e].p);
+            meta[e] = V.crec[c[e].p].meta;
+        }
+    }
+    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+    {
+        ur[e] = 0.0f;
+        if (e < nc && V.u_right) ur[e] = V.u_right[meta[e] >> 16];
+    }
+    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+    {
+        if (e < nc) {
+            const int ml = c[e].ml;
+            const bool rej = V.u_right && ur[e] > 0.0f && !(fabsf(quR[ml] - ur[e]) <= qR[ml]);
+            if (!rej) {
+                const unsigned long long key = cand_key(hamming(qd[ml], d[e]), meta[e]);
+                const unsigned long long old = atomicMin(&tb[ml], key);
+                atomicMin(&tb[64 + ml], key < old ? old : key);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void ph_search_flat(const DevJob &J, const DevView &V, int tile, unsigned char *smem)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = tile * kWG + wave * 64;   // map point of lane 0 of this wave
+    const int m = m0 + lane;
+    unsigned char *base = smem + wave * kFlatLdsPerWave;
+    int2 *items = reinterpret_cast<int2 *>(base);
+    float *qu = reinterpret_cast<float *>(base + kFlatItems * 8);
+    float *qv = qu + 64, *qR = qv + 64, *quR = qR + 64;
+    int *qlo = reinterpret_cast<int *>(quR + 64), *qhi = qlo + 64;
+    unsigned long long *tb = reinterpret_cast<unsigned long long *>(qhi + 64);   // best[64], second[64]
+    Desc *qd = reinterpret_cast<Desc *>(tb + 128);                                // map point descriptors
+
+    Query q;
+    q.vis = false;
+    if (m < J.nM) q = make_query(J, V, m);
+    const int cx0 = q.vis ? q.cx0 : 0, cx1 = q.vis ? q.cx1 : 0;
+    const int cy0 = q.vis ? q.cy0 : 0, cy1 = q.vis ? q.cy1 : -1;
+    qu[lane] = q.u;
+    qv[lane] = q.v;
+    qR[lane] = q.vis ? q.Rm : 0.0f;
+    quR[lane] = q.vis ? q.uR : 0.0f;
+    qlo[lane] = q.vis ? q.plo : 0;
+    qhi[lane] = q.vis ? q.phi : -1;
+    tb[lane] = ~0ull;
+    tb[64 + lane] = ~0ull;
+    qd[lane] = q.dm;
+    int passes = (cy1 - cy0 + 1 + kFlatRowsPerPass - 1) / kFlatRowsPerPass;
+    for (int o = 32; o >= 1; o >>= 1) passes = max(passes, __shfl_xor(passes, o));
+    wave_lds_sync();
+    for (int pass = 0; pass < passes; ++pass) {
+        // this lane's rows of the pass: their record ranges, one round of loads
+        const int r0 = cy0 + pass * kFlatRowsPerPass;
+        int ra[kFlatRowsPerPass], rn[kFlatRowsPerPass];
+        _Pragma("unroll") for (int e = 0; e < kFlatRowsPerPass; ++e)
+        {
+            const bool in = r0 + e <= cy1;
+            const int row = in ? r0 + e : 0;
+            const int a = V.cell_off[row * V.cols + cx0];
+            const int b = V.cell_off[row * V.cols + cx1 + 1];
+            ra[e] = a;
+            rn[e] = in ? b - a : 0;
+        }
+        int cnt = 0;
+        _Pragma("unroll") for (int e = 0; e < kFlatRowsPerPass; ++e) cnt += rn[e] > 0 ? 1 : 0;
+        int incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int total = __shfl(incl, 63);
+        int k = incl - cnt;
+        _Pragma("unroll") for (int e = 0; e < kFlatRowsPerPass; ++e)
+        {
+            if (rn[e] > 0) {
+                items[k] = make_int2(ra[e], rn[e] | (lane << 16));
+                ++k;
+            }
+        }
+        wave_lds_sync();
+        FlatCand cand[kCandBatch];
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cand[e] = FlatCand{0, 0};
+        int nc = 0;
+        for (int it = lane; it < total; it += 64) {
+            const int2 item = items[it];
+            const int a = item.x, n = item.y & 0xFFFF, ml = item.y >> 16;
+            Query iq;
+            iq.u = qu[ml];
+            iq.v = qv[ml];
+            iq.Rm = qR[ml];
+            iq.plo = qlo[ml];
+            iq.phi = qhi[ml];
+            for (int p0 = a; p0 < a + n; p0 += kFlatRecs) {
+                CellRec rec[kFlatRecs];
+                _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e) rec[e] = V.crec[min(p0 + e, a + n - 1)];
+                _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e)
+                {
+                    if (p0 + e < a + n && in_window(iq, rec[e].x, rec[e].y, rec[e].meta)) {
+                        if (nc == kCandBatch) {   // rare: a full batch before the end
+                            flat_flush(V, cand, nc, quR, qR, qd, tb);
+                            nc = 0;
+                        }
+                        _Pragma("unroll") for (int f = 0; f < kCandBatch; ++f) if (nc == f) cand[f] = FlatCand{p0 + e, ml};
+                        ++nc;
+                    }
+                }
+            }
+        }
+        flat_flush(V, cand, nc, quR, qR, qd, tb);
+        wave_lds_sync();   // atomics done; items free for the next pass
+    }
+    Top2<uint64_t> top = {tb[lane], tb[64 + lane]};
+    finish_query<1>(J, V, m, 0, top);
+}
+
 // Search by projection, kWG-thread tiles, G lanes per map point, records read
 // from global memory.
 template <int G>
@@ -1544,12 +1699,13 @@ __device__ __forceinline__ void task_stereo_c(const DevJob &J, int tile, unsigne
 }
 
 template <int G>
-__device__ __forceinline__ void task_search(const DevJob &J, int tile)
+__device__ __forceinline__ void task_search(const DevJob &J, int tile, unsigned char *smem)
 {
     const int tpv = search_tiles_per_view(J, G);
     const int v = tile / tpv;
     if (v >= J.n_views) return;
-    ph_search<G>(J, J.view[v], tile - v * tpv);
+    if constexpr (G == 1) ph_search_flat(J, J.view[v], tile - v * tpv, smem);
+    else ph_search<G>(J, J.view[v], tile - v * tpv);
 }
 
 __device__ __forceinline__ void task_search_final(const DevJob &J, int tile)
@@ -1564,6 +1720,7 @@ static_assert(256 * 8 + 4 * 16 * 2 * 4 <= kTaskLds, "stereo_a LDS");
 static_assert(256 * 8 + (kSearchWG / 256) * 128 * 4 <= kSearchLds, "stereo_a LDS (wide)");
 static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
 static_assert(kRefineQPerWG * kRefineQLds <= kTaskLds, "refine LDS (quarter waves)");
+static_assert(4 * kFlatLdsPerWave <= kTaskLds, "balanced search LDS");
 static_assert((256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4 <= kTaskLds, "median LDS");
 
 // ------------------------------------------------------- per-phase kernels
@@ -1616,9 +1773,10 @@ __global__ __launch_bounds__(NT) void k_stereo_c(Src src)
 template <class Src, int G>
 __global__ __launch_bounds__(kWG) void k_search(Src src)
 {
+    __shared__ __align__(16) unsigned char smem[G == 1 ? 4 * kFlatLdsPerWave : 16];
     int job, tile;
     if (!src.locate(PH_SEARCH, job, tile)) return;
-    task_search<G>(src(job), tile);
+    task_search<G>(src(job), tile, smem);
 }
 
 // Two workgroups per CU (LDS) need 8 waves per SIMD: at most 64 VGPRs.
@@ -1755,7 +1913,7 @@ __global__ __launch_bounds__(kWG) void k_persistent(PersistArgs a)
         case PH_REFINE: ph_refine(J, tile, smem); break;
         case PH_TRI: ph_tri(J, tile); break;
         case PH_STEREO_C: task_stereo_c<kWG>(J, tile, smem); break;
-        case PH_SEARCH: task_search<GS>(J, tile); break;
+        case PH_SEARCH: task_search<GS>(J, tile, smem); break;
         default: task_search_final(J, tile); break;
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // publish this task's writes
