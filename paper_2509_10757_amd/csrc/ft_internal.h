@@ -20,7 +20,7 @@ constexpr int kKnnQueriesPerWG = 16;  // fisheye all-pairs: one 16-row MFMA bloc
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
 constexpr int kRefineQPerWG = 16;     // ... 11x11 window, +-5 shifts: four matches per wave
-constexpr int kRefineQLds = 368;      // bytes of LDS per match (121 + 231, rounded to 16)
+constexpr int kRefineQLds = 800;      // bytes of LDS per match (11 x 12 + 11 x 24 16-bit values)
 
 enum Phase : int {
     PH_SETUP = 0,    // row sort / overlap lists / cell sort

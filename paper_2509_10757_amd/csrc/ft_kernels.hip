@@ -466,7 +466,10 @@ __device__ __forceinline__ void best_scan(const DevJob &J, const int *rs, const 
             ++seen;
         }
         Desc d[kCandBatch];
-        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (e < n) d[e] = load_desc(J.tdesc, cp[e]);
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+        {
+            if (e < n) d[e] = load_desc(J.tdesc, cp[e]);
+        }
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
         {
             if (e < n) {
@@ -578,11 +581,16 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
     }
     Top2<uint32_t> t0 = {0xFFFFFFFFu, 0xFFFFFFFFu}, t1 = t0, t2 = t0, t3 = t0;
     const int n_tiles = (nT + 15) >> 4;
+    // the next tile's descriptor bytes are loaded while this tile is processed
+    uint2 wn = make_uint2(0, 0);
+    if (wave < n_tiles && (wave << 4) + c < nT)
+        wn = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)((wave << 4) + c) + 8 * g);
     for (int t = wave; t < n_tiles; t += 4) {
         const int tj = (t << 4) + c;
         const bool tv = tj < nT;
-        uint2 w = make_uint2(0, 0);
-        if (tv) w = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)tj + 8 * g);
+        const uint2 w = wn;
+        const int tn = ((t + 4) << 4) + c;
+        if (t + 4 < n_tiles && tn < nT) wn = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)tn + 8 * g);
         v4i acc = {0, 0, 0, 0};
         _Pragma("unroll") for (int s = 0; s < 4; ++s) {
             const uint32_t word = s < 2 ? w.x : w.y;
@@ -740,7 +748,7 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
 {
     constexpr int w = 5, L = 5, side = 2 * w + 1, strip = 2 * (L + w) + 1, nS = 2 * L + 1;
     constexpr int nP = side * side, nT = nP + side * strip;
-    static_assert(nT <= kRefineQLds, "refine windows");
+    static_assert((side * 12 + side * 24) * 2 <= kRefineQLds, "refine windows");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ql = lane & 15, slot = wave * 4 + (lane >> 4);
     const int i = tile * kRefineQPerWG + slot;
@@ -769,8 +777,14 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
                   su0 + L + w < Wl;
         }
     }
-    uint8_t *P = lds + slot * kRefineQLds;   // left patch [side][side]
-    uint8_t *S = P + nP;                     // right strip [side][strip]
+    // Windows in LDS as 16-bit values, rows padded to whole dwords: the left
+    // patch holds P + 255, the right strip holds S.  For shift k (lane k) the
+    // centre-subtracted difference |(P - cL) - (S - cR)| equals
+    // |(P + 255) - (S + off)| with off = cL - cR + 255 in [0, 510]; both
+    // terms lie in [0, 765], so v_sad_u16 sums two pixels per instruction.
+    constexpr int pS = 12, sS = 24;   // row strides (u16) of patch and strip
+    uint16_t *P = reinterpret_cast<uint16_t *>(lds + slot * kRefineQLds);
+    uint16_t *S = P + side * pS;
     if (act) {
         const uint8_t *IL = J.pyrL + off;
         const uint8_t *IR = J.pyrR + off;
@@ -779,10 +793,10 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
             const int e = e0 + ql;
             if (e < nP) {
                 const int r = e / side, c = e - r * side;
-                P[e] = IL[(size_t)(sv - w + r) * Wl + su - w + c];
+                P[r * pS + c] = (uint16_t)(IL[(size_t)(sv - w + r) * Wl + su - w + c] + 255);
             } else if (e < nT) {
                 const int e2 = e - nP, r = e2 / strip, c = e2 - r * strip;
-                P[e] = IR[(size_t)(sv - w + r) * Wl + su0 - L - w + c];
+                S[r * sS + c] = IR[(size_t)(sv - w + r) * Wl + su0 - L - w + c];
             }
         }
     }
@@ -790,13 +804,25 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
     int sad = 0;
     uint32_t key = 0xFFFFFFFFu;   // SAD << 4 | lane: ties go to the smaller shift
     if (act && ql < nS) {
-        const int cL = P[w * side + w];
-        const int cR = S[w * strip + ql + w];
+        const int cL = (int)P[w * pS + w] - 255;
+        const int cR = S[w * sS + ql + w];
+        const uint32_t off1 = (uint32_t)(cL - cR + 255);
+        const uint32_t off2 = off1 | (off1 << 16);
+        const int b0 = ql & ~1;                   // first u16 of the strip pairs read
+        const uint32_t sh = (uint32_t)(ql & 1) * 2;   // byte shift realigning them to pixel ql
+        uint32_t acc = 0;
         _Pragma("unroll 1") for (int r = 0; r < side; ++r)
         {
-            _Pragma("unroll") for (int dx = 0; dx < side; ++dx)
-                sad += abs(((int)P[r * side + dx] - cL) - ((int)S[r * strip + ql + dx] - cR));
+            const uint32_t *pa = reinterpret_cast<const uint32_t *>(P + r * pS);
+            const uint32_t *pb = reinterpret_cast<const uint32_t *>(S + r * sS + b0);
+            uint32_t db[6];
+            _Pragma("unroll") for (int t = 0; t < 6; ++t) db[t] = pb[t];
+            _Pragma("unroll") for (int t = 0; t < 5; ++t)
+                acc = __builtin_amdgcn_sad_u16(pa[t], __builtin_amdgcn_alignbyte(db[t + 1], db[t], sh) + off2, acc);
+            const int d10 = (int)P[r * pS + 10] - ((int)S[r * sS + ql + 10] + (int)off1);
+            acc += (uint32_t)abs(d10);
         }
+        sad = (int)acc;
         key = ((uint32_t)sad << 4) | (uint32_t)ql;
     }
     for (int m = 8; m >= 1; m >>= 1) {
@@ -1298,10 +1324,24 @@ __device__ __forceinline__ void finish_query(const DevJob &J, const DevView &V, 
 // point's best two keys are kept in LDS by 64-bit atomic minima: a key goes to
 // the best slot, and whichever of it and the displaced best is larger goes to
 // the second slot, which leaves the two smallest distinct keys.
-constexpr int kFlatRowsPerPass = 4;                  // window rows per lane and pass
+constexpr int kFlatRowsPerPass = 2;                  // window rows per lane and pass
 constexpr int kFlatItems = 64 * kFlatRowsPerPass;    // items per wave and pass
 constexpr int kFlatRecs = 3;                         // records of an item loaded together
-constexpr int kFlatLdsPerWave = kFlatItems * 8 + 64 * 4 * 6 + 128 * 8 + 64 * 32;
+constexpr int kFlatCand = 4;                         // candidates per descriptor batch
+constexpr int kFlatLdsPerWave = kFlatItems * 8 + 64 * 4 * 5 + 128 * 4 + 64 * 32;
+
+// Candidate key of the balanced search in 32 bits: distance (9 bits), keypoint
+// (16), level (4; octaves are 0..7 by contract); the same order as cand_key.
+__device__ __forceinline__ uint32_t cand_key32(int h, uint32_t meta)
+{
+    return ((uint32_t)h << 20) | ((meta >> 16) << 4) | (meta & 15u);
+}
+
+__device__ __forceinline__ uint64_t key32_to_64(uint32_t k)
+{
+    if (k == 0xFFFFFFFFu) return ~0ull;
+    return ((uint64_t)(k >> 20) << 40) | ((uint64_t)((k >> 4) & 0xFFFFu) << 8) | (uint64_t)(k & 15u);
+}
 
 // Orders one wave's LDS accesses (its lanes read what other lanes wrote); the
 // balanced search syncs only within a wave, whose pass count is wave-uniform
@@ -1319,31 +1359,31 @@ struct FlatCand {
 };
 
 __device__ __forceinline__ void flat_flush(const DevView &V, const FlatCand *c, int nc, const float *quR,
-                                           const float *qR, const Desc *qd, unsigned long long *tb)
+                                           const float *qR, const Desc *qd, uint32_t *tb)
 {
-    Desc d[kCandBatch];
-    float ur[kCandBatch];
-    uint32_t meta[kCandBatch];
-    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+    Desc d[kFlatCand];
+    float ur[kFlatCand];
+    uint32_t meta[kFlatCand];
+    _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e)
     {
         if (e < nc) {
             d[e] = load_desc(V.cdesc, c[e].p);
             meta[e] = V.crec[c[e].p].meta;
         }
     }
-    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+    _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e)
     {
         ur[e] = 0.0f;
         if (e < nc && V.u_right) ur[e] = V.u_right[meta[e] >> 16];
     }
-    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
+    _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e)
     {
         if (e < nc) {
             const int ml = c[e].ml;
             const bool rej = V.u_right && ur[e] > 0.0f && !(fabsf(quR[ml] - ur[e]) <= qR[ml]);
             if (!rej) {
-                const unsigned long long key = cand_key(hamming(qd[ml], d[e]), meta[e]);
-                const unsigned long long old = atomicMin(&tb[ml], key);
+                const uint32_t key = cand_key32(hamming(qd[ml], d[e]), meta[e]);
+                const uint32_t old = atomicMin(&tb[ml], key);
                 atomicMin(&tb[64 + ml], key < old ? old : key);
             }
         }
@@ -1359,9 +1399,9 @@ __device__ __forceinline__ void ph_search_flat(const DevJob &J, const DevView &V
     int2 *items = reinterpret_cast<int2 *>(base);
     float *qu = reinterpret_cast<float *>(base + kFlatItems * 8);
     float *qv = qu + 64, *qR = qv + 64, *quR = qR + 64;
-    int *qlo = reinterpret_cast<int *>(quR + 64), *qhi = qlo + 64;
-    unsigned long long *tb = reinterpret_cast<unsigned long long *>(qhi + 64);   // best[64], second[64]
-    Desc *qd = reinterpret_cast<Desc *>(tb + 128);                                // map point descriptors
+    int *qlv = reinterpret_cast<int *>(quR + 64);               // level window: lo + 16 | (hi + 16) << 8
+    uint32_t *tb = reinterpret_cast<uint32_t *>(qlv + 64);       // best[64], second[64] (32-bit keys)
+    Desc *qd = reinterpret_cast<Desc *>(tb + 128);               // map point descriptors
 
     Query q;
     q.vis = false;
@@ -1372,10 +1412,9 @@ __device__ __forceinline__ void ph_search_flat(const DevJob &J, const DevView &V
     qv[lane] = q.v;
     qR[lane] = q.vis ? q.Rm : 0.0f;
     quR[lane] = q.vis ? q.uR : 0.0f;
-    qlo[lane] = q.vis ? q.plo : 0;
-    qhi[lane] = q.vis ? q.phi : -1;
-    tb[lane] = ~0ull;
-    tb[64 + lane] = ~0ull;
+    qlv[lane] = q.vis ? ((q.plo + 16) | ((q.phi + 16) << 8)) : (16 | (15 << 8));
+    tb[lane] = 0xFFFFFFFFu;
+    tb[64 + lane] = 0xFFFFFFFFu;
     qd[lane] = q.dm;
     int passes = (cy1 - cy0 + 1 + kFlatRowsPerPass - 1) / kFlatRowsPerPass;
     for (int o = 32; o >= 1; o >>= 1) passes = max(passes, __shfl_xor(passes, o));
@@ -1410,38 +1449,45 @@ __device__ __forceinline__ void ph_search_flat(const DevJob &J, const DevView &V
             }
         }
         wave_lds_sync();
-        FlatCand cand[kCandBatch];
-        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cand[e] = FlatCand{0, 0};
-        int nc = 0;
-        for (int it = lane; it < total; it += 64) {
-            const int2 item = items[it];
-            const int a = item.x, n = item.y & 0xFFFF, ml = item.y >> 16;
-            Query iq;
-            iq.u = qu[ml];
-            iq.v = qv[ml];
-            iq.Rm = qR[ml];
-            iq.plo = qlo[ml];
-            iq.phi = qhi[ml];
-            for (int p0 = a; p0 < a + n; p0 += kFlatRecs) {
-                CellRec rec[kFlatRecs];
-                _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e) rec[e] = V.crec[min(p0 + e, a + n - 1)];
-                _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e)
-                {
-                    if (p0 + e < a + n && in_window(iq, rec[e].x, rec[e].y, rec[e].meta)) {
-                        if (nc == kCandBatch) {   // rare: a full batch before the end
-                            flat_flush(V, cand, nc, quR, qR, qd, tb);
-                            nc = 0;
+        // a lane's candidates are collected kFlatCand at a time (the first
+        // `done` skipped) and flushed; only lanes with more rescan
+        int done = 0;
+        for (;;) {
+            FlatCand cand[kFlatCand];
+            _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e) cand[e] = FlatCand{0, 0};
+            int nc = 0, seen = 0;
+            for (int it = lane; it < total; it += 64) {
+                const int2 item = items[it];
+                const int a = item.x, n = item.y & 0xFFFF, ml = item.y >> 16;
+                Query iq;
+                iq.u = qu[ml];
+                iq.v = qv[ml];
+                iq.Rm = qR[ml];
+                const int lv = qlv[ml];
+                iq.plo = (lv & 0xFF) - 16;
+                iq.phi = ((lv >> 8) & 0xFF) - 16;
+                for (int p0 = a; p0 < a + n; p0 += kFlatRecs) {
+                    CellRec rec[kFlatRecs];
+                    _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e) rec[e] = V.crec[min(p0 + e, a + n - 1)];
+                    _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e)
+                    {
+                        if (p0 + e < a + n && in_window(iq, rec[e].x, rec[e].y, rec[e].meta)) {
+                            if (seen >= done && nc < kFlatCand) {
+                                _Pragma("unroll") for (int f = 0; f < kFlatCand; ++f) if (nc == f) cand[f] = FlatCand{p0 + e, ml};
+                                ++nc;
+                            }
+                            ++seen;
                         }
-                        _Pragma("unroll") for (int f = 0; f < kCandBatch; ++f) if (nc == f) cand[f] = FlatCand{p0 + e, ml};
-                        ++nc;
                     }
                 }
             }
+            flat_flush(V, cand, nc, quR, qR, qd, tb);
+            done += nc;
+            if (done >= seen) break;
         }
-        flat_flush(V, cand, nc, quR, qR, qd, tb);
         wave_lds_sync();   // atomics done; items free for the next pass
     }
-    Top2<uint64_t> top = {tb[lane], tb[64 + lane]};
+    Top2<uint64_t> top = {key32_to_64(tb[lane]), key32_to_64(tb[64 + lane])};
     finish_query<1>(J, V, m, 0, top);
 }
 

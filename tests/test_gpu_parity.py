@@ -427,3 +427,21 @@ def test_refinement_window_sizes(ft, ctx, half_win, half_range):
     want = oracle.run_frame(f)
     compare_frame(run_device(ft, ctx, f), want)
     compare_frame(run_device(ft, ctx, f, batch=True), want)
+
+
+@pytest.mark.parametrize("band", [0.5, 8.0])
+def test_epipolar_band_widths(ft, ctx, band):
+    """Narrow and wide epipolar bands (the row index scans row_reach bins on
+    each side): single-frame and batched results, both best-match blocks,
+    equal the oracle."""
+    f = synth.pinhole_frame_1200()[0]
+    f["stereo_params"] = dict(f["stereo_params"], band=band)
+    say("epipolar band", band)
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, ctx, f), want)
+    try:
+        for blk in (256, 1024):
+            ctx.ft_set_shapes(4, 1, 256, blk, 1024)
+            compare_frame(run_device(ft, ctx, f, batch=True), want)
+    finally:
+        ctx.ft_set_shapes(8, 1, 256)
