@@ -376,6 +376,39 @@ ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *shapes);
 ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
                       const char *cache_path, ft_shapes *chosen);
 
+/* ------------------------------------------------------------ frame upload
+ * A tracker hands each frame's keypoints to the GPU once (Section IV-E: move
+ * only the data the kernels need).  When many camera streams are served, the
+ * frames of one batch sit in separate host buffers, and one copy command per
+ * frame costs a command submission each; ft_upload moves a whole gather list
+ * with one kernel that reads pinned host memory directly over the bus.
+ *
+ * ft_host_alloc returns `bytes` of pinned (page-locked, device-mapped) host
+ * memory owned by the context; it stays valid until ft_host_free or
+ * ft_context_destroy.  It is the only memory an ft_upload source may lie in,
+ * so the library can check every source range.  Allocate at set-up: like
+ * ft_context_create it allocates, no other call does.  bytes <= 0 or a null
+ * ptr: FT_ERR_INVALID_ARGUMENT; allocation failure: FT_ERR_DEVICE.
+ * ft_host_free of a pointer that ft_host_alloc did not return, or that was
+ * freed already: FT_ERR_INVALID_ARGUMENT.  The caller must not free memory
+ * that an enqueued upload still reads. */
+typedef struct ft_segment {
+    const void *src;           /* pinned host memory from ft_host_alloc, 16-byte aligned */
+    void *dst;                 /* device memory, 16-byte aligned */
+    int64_t bytes;             /* >= 0; [src, src + bytes) inside one ft_host_alloc block */
+} ft_segment;
+
+ft_status ft_host_alloc(ft_context *ctx, int64_t bytes, void **ptr);
+ft_status ft_host_free(ft_context *ctx, void *ptr);
+/* Enqueues the copy of every segment on `stream` (one kernel per 64
+ * segments); the segments list itself is read during the call.  The
+ * destinations must not overlap each other; the sources must stay unchanged
+ * until the stream has passed the copy.  n == 0 enqueues nothing.  A null
+ * list with n > 0, n < 0, a misaligned pointer, a negative size or a source
+ * range outside every ft_host_alloc block: FT_ERR_INVALID_ARGUMENT, and
+ * nothing is enqueued. */
+ft_status ft_upload(ft_context *ctx, void *stream, const ft_segment *segs, int32_t n);
+
 /* ------------------------------------------------------------------------ */
 ft_status ft_context_create(const ft_limits *limits, int32_t device, ft_context **out);
 ft_status ft_context_destroy(ft_context *ctx);

@@ -124,6 +124,10 @@ class ft_frame_job(ct.Structure):
                 ("search_params", ft_search_params), ("search_out", ft_search_out * 2)]
 
 
+class ft_segment(ct.Structure):
+    _fields_ = [("src", P), ("dst", P), ("bytes", ct.c_int64)]
+
+
 class ft_shapes(ct.Structure):
     _fields_ = [("best_lanes", ct.c_int32), ("search_lanes", ct.c_int32), ("search_block", ct.c_int32),
                 ("best_block", ct.c_int32), ("aux_block", ct.c_int32)]
@@ -157,6 +161,9 @@ EXPORTS = {
     "ft_set_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_get_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_autotune": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.c_char_p, ct.POINTER(ft_shapes)],
+    "ft_host_alloc": [P, ct.c_int64, ct.POINTER(P)],
+    "ft_host_free": [P, P],
+    "ft_upload": [P, P, ct.POINTER(ft_segment), ct.c_int32],
     "ft_status_string": [ct.c_int32],
     "ft_last_error": [P],
     "ft_version": [],
@@ -284,6 +291,32 @@ class Context:
         self._check(self.lib.ft_batch_submit(self.h, _stream(stream), arr, len(jobs), ct.byref(t)),
                     "ft_batch_submit")
         return t.value
+
+    def ft_batch_submit_raw(self, addr: int, n: int, stream=None) -> int:
+        """Submit `n` jobs already laid out as ft_frame_job structs at host
+        address `addr` (e.g. a NumPy buffer)."""
+        t = ct.c_uint64()
+        arr = ct.cast(P(addr), ct.POINTER(ft_frame_job))
+        self._check(self.lib.ft_batch_submit(self.h, _stream(stream), arr, n, ct.byref(t)), "ft_batch_submit")
+        return t.value
+
+    def ft_host_alloc(self, nbytes: int) -> int:
+        p = P()
+        self._check(self.lib.ft_host_alloc(self.h, nbytes, ct.byref(p)), "ft_host_alloc")
+        return p.value
+
+    def ft_host_free(self, addr: int):
+        self._check(self.lib.ft_host_free(self.h, P(addr)), "ft_host_free")
+
+    def ft_upload(self, segs, stream=None, check=True):
+        """`segs`: a C-contiguous int64 array of shape (n, 3) holding (src,
+        dst, bytes) rows, or a sequence of such triples."""
+        a = np.ascontiguousarray(np.asarray(segs, dtype=np.int64).reshape(-1, 3))
+        st = self.lib.ft_upload(self.h, _stream(stream), ct.cast(P(a.ctypes.data), ct.POINTER(ft_segment)),
+                                len(a))
+        if check:
+            self._check(st, "ft_upload")
+        return st
 
     def ft_set_exec_mode(self, mode: int):
         self._check(self.lib.ft_set_exec_mode(self.h, mode), "ft_set_exec_mode")

@@ -112,6 +112,7 @@ struct ft_context {
     size_t ev_next = 0;
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
+    std::vector<std::pair<char *, size_t>> host_blocks;   // ft_host_alloc blocks (upload sources)
 };
 
 static char *h_part(const ft_context *ctx, const Lane &l, int part)
@@ -932,11 +933,81 @@ ft_status ft_context_destroy(ft_context *ctx)
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     for (auto &ps : ctx->part_streams)
         if (ps) hipStreamDestroy(ps);
-    if (ctx->base) {
-        hipDeviceSynchronize();
-        hipFree(ctx->base);
-    }
+    if (ctx->base || !ctx->host_blocks.empty()) hipDeviceSynchronize();
+    for (auto &hb : ctx->host_blocks) hipHostFree(hb.first);
+    if (ctx->base) hipFree(ctx->base);
     delete ctx;
+    return FT_OK;
+}
+
+ft_status ft_host_alloc(ft_context *ctx, int64_t bytes, void **ptr)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!ptr || bytes <= 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "host_alloc: null ptr or size %lld", (long long)bytes);
+    *ptr = nullptr;
+    char *p = nullptr;
+    HIP_TRY(ctx, hipHostMalloc((void **)&p, (size_t)bytes, hipHostMallocDefault));
+    ctx->host_blocks.emplace_back(p, (size_t)bytes);
+    *ptr = p;
+    return FT_OK;
+}
+
+ft_status ft_host_free(ft_context *ctx, void *ptr)
+{
+    if (!ctx) return FT_ERR_INVALID_ARGUMENT;
+    for (size_t i = 0; i < ctx->host_blocks.size(); ++i) {
+        if (ctx->host_blocks[i].first != ptr) continue;
+        hipSetDevice(ctx->device);
+        HIP_TRY(ctx, hipHostFree(ptr));
+        ctx->host_blocks.erase(ctx->host_blocks.begin() + (ptrdiff_t)i);
+        return FT_OK;
+    }
+    return fail(ctx, FT_ERR_INVALID_ARGUMENT, "host_free: %p is not a live ft_host_alloc block", ptr);
+}
+
+// Largest segment: keeps a launch's workgroup count (<= kUploadSegs segments)
+// far below the grid limit.
+constexpr int64_t kMaxUploadBytes = int64_t(1) << 36;
+
+ft_status ft_upload(ft_context *ctx, void *stream, const ft_segment *segs, int32_t n)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (n < 0 || (n > 0 && !segs)) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "upload: %d segments, list %p", n, (const void *)segs);
+    // validate everything before enqueueing anything
+    for (int32_t i = 0; i < n; ++i) {
+        const ft_segment &g = segs[i];
+        const uintptr_t src = (uintptr_t)g.src, dst = (uintptr_t)g.dst;
+        if (g.bytes < 0 || g.bytes > kMaxUploadBytes || !g.src || !g.dst || (src & 15) || (dst & 15))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "upload: segment %d null, misaligned or of size %lld", i,
+                        (long long)g.bytes);
+        bool inside = false;
+        for (const auto &hb : ctx->host_blocks) {
+            const uintptr_t b0 = (uintptr_t)hb.first;
+            if (src >= b0 && src - b0 <= hb.second && (uint64_t)g.bytes <= hb.second - (src - b0)) {
+                inside = true;
+                break;
+            }
+        }
+        if (!inside) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "upload: segment %d source outside every ft_host_alloc block", i);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t g0 = 0; g0 < n; g0 += kUploadSegs) {
+        UploadArgs a{};
+        a.n = std::min(kUploadSegs, n - g0);
+        int64_t blocks = 0;
+        for (int k = 0; k < a.n; ++k) {
+            const ft_segment &g = segs[g0 + k];
+            a.first[k] = (int32_t)blocks;
+            a.src[k] = static_cast<const char *>(g.src);
+            a.dst[k] = static_cast<char *>(g.dst);
+            a.bytes[k] = g.bytes;
+            blocks += (g.bytes + kUploadChunk - 1) / kUploadChunk;
+        }
+        a.first[a.n] = (int32_t)blocks;
+        HIP_TRY(ctx, launch_upload(a, s));
+    }
     return FT_OK;
 }
 

@@ -173,4 +173,18 @@ hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_
                            const DevJob &one, const Shapes &shapes, hipStream_t stream,
                            bool do_stereo, bool do_search, hipEvent_t *ev);
 
+// Gather-list copy (ft_upload.hip): up to kUploadSegs segments per launch,
+// passed by value; each workgroup copies one kUploadChunk-byte chunk of one
+// segment.  `first[s]` is the first workgroup of segment s, first[n] the grid.
+constexpr int kUploadSegs = 64;
+constexpr int kUploadChunk = 32768;
+struct UploadArgs {
+    int32_t n;
+    int32_t first[kUploadSegs + 1];
+    const char *src[kUploadSegs];
+    char *dst[kUploadSegs];
+    int64_t bytes[kUploadSegs];
+};
+hipError_t launch_upload(const UploadArgs &a, hipStream_t stream);
+
 }  // namespace ft

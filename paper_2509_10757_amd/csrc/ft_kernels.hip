@@ -146,25 +146,41 @@ __device__ __forceinline__ Top2<T> top2_merge(Top2<T> t, T o1, T o2)
     return r;
 }
 
-// Workgroup-wide exclusive scan of a[0..n) in LDS; returns the total.
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+    _Pragma("unroll") for (int o = 1; o < 64; o <<= 1)
+    {
+        const int t = __shfl_up(v, o, 64);
+        v += lane >= o ? t : 0;
+    }
+    return v;
+}
+
+// Workgroup-wide exclusive scan of a[0..n) in LDS; returns the total.  Each
+// thread owns a contiguous run of a[], the runs' sums are scanned inside each
+// wave with lane shuffles, and the waves' totals (tmp[0..NT/64)) are combined
+// after one barrier.
 template <int NT>
 __device__ __forceinline__ int wg_exclusive_scan(int *a, int n, int *tmp)
 {
-    const int tid = threadIdx.x;
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int per = (n + NT - 1) / NT;
     const int beg = min(tid * per, n), end = min(beg + per, n);
     int s = 0;
     for (int i = beg; i < end; ++i) s += a[i];
-    tmp[tid] = s;
+    const int inc = wave_inclusive_scan(s);
+    if (lane == 63) tmp[wave] = inc;
     __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        const int v = tid >= off ? tmp[tid - off] : 0;
-        __syncthreads();
-        tmp[tid] += v;
-        __syncthreads();
+    int run = inc - s, total = 0;
+    _Pragma("unroll") for (int w = 0; w < NW; ++w)
+    {
+        const int t = tmp[w];
+        run += w < wave ? t : 0;
+        total += t;
     }
-    int run = tmp[tid] - s;
-    const int total = tmp[NT - 1];
     for (int i = beg; i < end; ++i) {
         const int v = a[i];
         a[i] = run;
@@ -1046,13 +1062,19 @@ template <int NT>
 __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, uint32_t *surv, int *sh)
 {
     const int tid = threadIdx.x, nL = J.L.n;
+    // Up to kSortUnroll * NT keypoints, every field a thread needs stays in
+    // its registers from the first pass to the outputs; larger frames re-read.
+    const bool held = nL <= kSortUnroll * NT;
     if (tid < 256) hist[tid] = 0;
     if (tid == 0) sh[0] = 0;
     for (int w = tid; w < (nL + 31) / 32; w += NT) surv[w] = 0;
     __syncthreads();
     int my_n = 0;
+    int bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
+    float ur[kSortUnroll], dp[kSortUnroll];
+    bool sv[kSortUnroll] = {};
     for (int i0 = tid; i0 < nL; i0 += kSortUnroll * NT) {
-        int fl[kSortUnroll], bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
+        int fl[kSortUnroll];
         uint32_t cl[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
@@ -1061,14 +1083,16 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
             bj[e] = J.best_j[i];
             bh[e] = J.best_h[i];
             sd[e] = J.sad[i];
+            ur[e] = J.uR[i];
+            dp[e] = J.depth[i];
         }
         // a flagged keypoint has a valid right index; others read index 0
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) cl[e] = J.claimR[fl[e] ? bj[e] : 0];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int i = i0 + e * NT;
-            const bool s = i < nL && fl[e] && cl[e] == (((uint32_t)bh[e] << 23) | (uint32_t)i);
-            if (s) {
+            sv[e] = i < nL && fl[e] && cl[e] == (((uint32_t)bh[e] << 23) | (uint32_t)i);
+            if (sv[e]) {
                 atomicOr(&surv[i >> 5], 1u << (i & 31));
                 ++my_n;
                 atomicAdd(&hist[(sd[e] >> 8) & 0xFF], 1);
@@ -1084,8 +1108,13 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
         const int hb = select_bin<NT>(hist, tmp, n / 2, &rank, sh + 2);
         if (tid < 256) hist[tid] = 0;
         __syncthreads();
-        for (int i = tid; i < nL; i += NT)
-            if (bit(surv, i) && ((J.sad[i] >> 8) & 0xFF) == hb) atomicAdd(&hist[J.sad[i] & 0xFF], 1);
+        if (held) {
+            _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+                if (tid + e * NT < nL && sv[e] && ((sd[e] >> 8) & 0xFF) == hb) atomicAdd(&hist[sd[e] & 0xFF], 1);
+        } else {
+            for (int i = tid; i < nL; i += NT)
+                if (bit(surv, i) && ((J.sad[i] >> 8) & 0xFF) == hb) atomicAdd(&hist[J.sad[i] & 0xFF], 1);
+        }
         __syncthreads();
         int rank2;
         const int lb = select_bin<NT>(hist, tmp, rank, &rank2, sh + 2);
@@ -1095,22 +1124,23 @@ __device__ __forceinline__ void ph_median(const DevJob &J, int *hist, int *tmp, 
     __syncthreads();
     int kept = 0;
     for (int i0 = tid; i0 < nL; i0 += kSortUnroll * NT) {
-        int bj[kSortUnroll], bh[kSortUnroll], sd[kSortUnroll];
-        float ur[kSortUnroll], dp[kSortUnroll];
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-        {
-            const int i = min(i0 + e * NT, nL - 1);
-            bj[e] = J.best_j[i];
-            bh[e] = J.best_h[i];
-            sd[e] = J.sad[i];
-            ur[e] = J.uR[i];
-            dp[e] = J.depth[i];
+        if (!held) {
+            _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+            {
+                const int i = min(i0 + e * NT, nL - 1);
+                bj[e] = J.best_j[i];
+                bh[e] = J.best_h[i];
+                sd[e] = J.sad[i];
+                ur[e] = J.uR[i];
+                dp[e] = J.depth[i];
+                sv[e] = bit(surv, i);
+            }
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int i = i0 + e * NT;
             if (i >= nL) continue;
-            const bool keep = bit(surv, i) && (long long)J.med_den * sd[e] < (long long)J.med_num * m;
+            const bool keep = sv[e] && (long long)J.med_den * sd[e] < (long long)J.med_num * m;
             J.o_right_idx[i] = keep ? bj[e] : -1;
             J.o_dist[i] = keep ? bh[e] : -1;
             J.o_uR[i] = keep ? ur[e] : -1.0f;

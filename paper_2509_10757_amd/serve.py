@@ -185,26 +185,39 @@ class Scheduler:
 # --------------------------------------------------------------------------
 # Device executor
 # --------------------------------------------------------------------------
-class _Packed:
-    """One frame's keypoint data in a single buffer of 256-byte aligned parts."""
+def _carve(sizes):
+    """Offsets of consecutive 256-byte aligned parts; returns (offsets, total)."""
+    off, out = 0, {}
+    for k, n in sizes:
+        out[k] = off
+        off += (n + 255) // 256 * 256
+    return out, off
 
-    FIELDS = ("Lx", "Ly", "Rx", "Ry", "Ldesc", "Rdesc", "Loct", "Roct", "pre0", "pre1")
 
-    @staticmethod
-    def layout(n_max: int):
-        sizes = {"Lx": 4 * n_max, "Ly": 4 * n_max, "Rx": 4 * n_max, "Ry": 4 * n_max,
-                 "Ldesc": 32 * n_max, "Rdesc": 32 * n_max, "Loct": n_max, "Roct": n_max,
-                 "pre0": n_max, "pre1": n_max}
-        off, out = 0, {}
-        for k in _Packed.FIELDS:
-            out[k] = off
-            off += (sizes[k] + 255) // 256 * 256
-        return out, off
+def _input_layout(n: int):
+    """One frame's keypoint inputs for `n` keypoints per image, packed."""
+    return _carve([("Lx", 4 * n), ("Ly", 4 * n), ("Rx", 4 * n), ("Ry", 4 * n),
+                   ("Ldesc", 32 * n), ("Rdesc", 32 * n), ("Loct", n), ("Roct", n),
+                   ("pre0", n), ("pre1", n)])
+
+
+def _output_layout(kp: int, nm: int):
+    return _carve([("right_idx", 4 * kp), ("dist", 4 * kp), ("u_right", 4 * kp), ("depth", 4 * kp),
+                   ("sad", 4 * kp), ("xyz", 12 * kp), ("n_stereo", 4), ("mp_match", 8 * nm),
+                   ("mp_dist", 8 * nm), ("kp_match", 8 * kp), ("n_search", 8)])
 
 
 class DeviceExecutor:
     """Runs batches through the HIP library with stream maps resident on the
-    device and one upload (pinned host -> device slot) per frame."""
+    device.
+
+    Every in-flight frame slot owns one device region: the frame's packed
+    inputs followed by its outputs.  Each pooled frame of an admitted stream
+    is packed once into a pinned host arena (ft_host_alloc), as a frame
+    producer would write it.  A launch uploads its frames with one gather
+    copy (ft_upload) and submits job descriptors patched from per-frame
+    templates: a template is built once per pooled frame for slot 0, and the
+    words that hold slot addresses are shifted by the slot's offset."""
 
     def __init__(self, streams, max_batch: int = 64, max_inflight: int = 4, max_kp: int = 4096,
                  device: str = "cuda"):
@@ -214,21 +227,50 @@ class DeviceExecutor:
         self.torch, self.ft = torch, ft
         self.streams = {s["id"]: s for s in streams}
         self.max_batch, self.max_inflight = max_batch, max_inflight
-        n_map = max(s["n_map"] for s in streams)
-        self.ctx = ft.Context(ft.default_limits(max_kp_per_image=max_kp, max_map_points=max(n_map, 1),
+        n_map = max(max(s["n_map"] for s in streams), 1)
+        self.ctx = ft.Context(ft.default_limits(max_kp_per_image=max_kp, max_map_points=n_map,
                                                 max_batch_frames=max_batch, max_inflight=max_inflight))
         self.hip_streams = [torch.cuda.Stream(device=device) for _ in range(max_inflight)]
-        self.layout, self.slot_bytes = _Packed.layout(max_kp)
+        self.in_max = _input_layout(max_kp)[1]
+        self.out_off, out_bytes = _output_layout(max_kp, n_map)
+        self.slot_bytes = self.in_max + out_bytes
         n_slots = max_batch * max_inflight
         self.dev = torch.empty((n_slots, self.slot_bytes), dtype=torch.uint8, device=device)
+        self.dev_base = self.dev.data_ptr()
         self.free = list(range(n_slots))
+        self.outs = [self._out_views(k, max_kp, n_map) for k in range(n_slots)]
+        # host arena: every pooled frame of every stream, packed
+        self.arena_off = {}
+        off = 0
+        for s in streams:
+            for q, f in enumerate(s["frames"]):
+                self.arena_off[(s["id"], q)] = off
+                off += _input_layout(len(f["left"]["x"]))[1]
+        self.arena_bytes = max(off, 256)
+        self.arena = self.ctx.ft_host_alloc(self.arena_bytes)
+        self.arena_np = np.ctypeslib.as_array((ct.c_uint8 * self.arena_bytes).from_address(self.arena))
         self.maps = {}
-        self.pinned = {}       # (stream, pool index) -> pinned packed frame
         self.pyr = {}          # id(pyramid dict) -> device tensor
-        self.outs = [self._alloc_outputs(max_kp, n_map, device) for _ in range(n_slots)]
+        self.tmpl = {}         # (stream, pool index) -> (template words, slot mask, packed bytes)
+        self.packed = {}       # (stream, pool index) -> packed bytes in the arena
         self.device = device
         self.handles = {}
         self.next_h = 0
+
+    def _out_views(self, slot, kp, nm):
+        torch = self.torch
+        row = self.dev[slot]
+
+        def part(key, nbytes, dtype, shape):
+            o = self.in_max + self.out_off[key]
+            return row[o:o + nbytes].view(dtype).view(shape)
+        i32, f32 = torch.int32, torch.float32
+        return {"right_idx": part("right_idx", 4 * kp, i32, (kp,)), "dist": part("dist", 4 * kp, i32, (kp,)),
+                "u_right": part("u_right", 4 * kp, f32, (kp,)), "depth": part("depth", 4 * kp, f32, (kp,)),
+                "sad": part("sad", 4 * kp, i32, (kp,)), "xyz": part("xyz", 12 * kp, f32, (kp, 3)),
+                "n_stereo": part("n_stereo", 4, i32, (1,)),
+                "mp_match": part("mp_match", 8 * nm, i32, (2, nm)), "mp_dist": part("mp_dist", 8 * nm, i32, (2, nm)),
+                "kp_match": part("kp_match", 8 * kp, i32, (2, kp)), "n_search": part("n_search", 8, i32, (2,))}
 
     # -- residency -----------------------------------------------------------
     def admit(self, sid):
@@ -239,15 +281,17 @@ class DeviceExecutor:
         mp = s["frames"][0]["map"]
         self.maps[sid] = {k: torch.from_numpy(np.ascontiguousarray(v)).to(self.device) for k, v in mp.items()}
         for q, f in enumerate(s["frames"]):
-            self.pinned[(sid, q)] = self._pack(f)
             for key in ("pyr_left", "pyr_right"):
                 if key in f and id(f[key]) not in self.pyr:
                     self.pyr[id(f[key])] = torch.from_numpy(f[key]["data"]).to(self.device)
+            if (sid, q) not in self.packed:   # packed once: an upload may still read it
+                self.packed[(sid, q)] = self._pack(f, self.arena_off[(sid, q)])
+            self.tmpl[(sid, q)] = self._template(sid, f) + (self.packed[(sid, q)],)
 
     def evict(self, sid):
         self.maps.pop(sid, None)
-        for k in [k for k in self.pinned if k[0] == sid]:
-            del self.pinned[k]
+        for k in [k for k in self.tmpl if k[0] == sid]:
+            del self.tmpl[k]
 
     def footprint(self, sid) -> int:
         """Device bytes a stream holds while admitted: its map (64 bytes per
@@ -258,13 +302,12 @@ class DeviceExecutor:
             pyr = sum(f["pyr_left"]["data"].size + f["pyr_right"]["data"].size for f in s["frames"])
         return s["map_bytes"] + pyr
 
-    def _pack(self, f):
-        torch = self.torch
-        buf = torch.zeros(self.slot_bytes, dtype=torch.uint8).pin_memory()
-        a = buf.numpy()
+    def _pack(self, f, at):
         L, R = f["left"], f["right"]
         n = len(L["x"])
-        lay = self.layout
+        lay, total = _input_layout(n)
+        a = self.arena_np[at:at + total]
+        a[:] = 0
 
         def put(key, arr):
             b = np.ascontiguousarray(arr).view(np.uint8).reshape(-1)
@@ -275,24 +318,23 @@ class DeviceExecutor:
         put("Loct", L["octave"]); put("Roct", R["octave"])
         for v, spec in enumerate(f["search"]):
             put("pre%d" % v, spec["preassigned"].astype(np.uint8))
-        return buf, n
-
-    def _alloc_outputs(self, kp, nm, device):
-        torch = self.torch
-        i32 = dict(dtype=torch.int32, device=device)
-        f32 = dict(dtype=torch.float32, device=device)
-        return {"right_idx": torch.empty(kp, **i32), "dist": torch.empty(kp, **i32),
-                "u_right": torch.empty(kp, **f32), "depth": torch.empty(kp, **f32),
-                "sad": torch.empty(kp, **i32), "xyz": torch.empty((kp, 3), **f32),
-                "n_stereo": torch.empty(1, **i32),
-                "mp_match": torch.empty((2, max(nm, 1)), **i32), "mp_dist": torch.empty((2, max(nm, 1)), **i32),
-                "kp_match": torch.empty((2, kp), **i32), "n_search": torch.empty(2, **i32)}
+        return total
 
     # -- jobs ------------------------------------------------------------------
-    def _job(self, f, n, slot):
+    def _template(self, sid, f):
+        """Job words for slot 0 and the mask of words holding slot addresses
+        (found by building the job for slots 0 and 1 and comparing)."""
+        w0 = np.frombuffer(bytes(self._job(sid, f, 0)), dtype=np.uint64)
+        w1 = np.frombuffer(bytes(self._job(sid, f, 1)), dtype=np.uint64)
+        mask = (w0 != w1).astype(np.uint64)
+        assert np.all((w1 - w0)[mask == 1] == np.uint64(self.slot_bytes)), "job words move with the slot"
+        return w0.copy(), mask
+
+    def _job(self, sid, f, slot):
         ft = self.ft
-        base = self.dev[slot].data_ptr()
-        lay = self.layout
+        n = len(f["left"]["x"])
+        base = self.dev_base + slot * self.slot_bytes
+        lay = _input_layout(n)[0]
         o = self.outs[slot]
         sc = f["scales"]
         j = ft.ft_frame_job()
@@ -334,7 +376,7 @@ class DeviceExecutor:
             j.fisheye_out = ft.ft_fisheye_out(o["right_idx"].data_ptr(), o["dist"].data_ptr(),
                                               o["depth"].data_ptr(), o["xyz"].data_ptr(),
                                               o["n_stereo"].data_ptr())
-        m = self.maps[f["_stream"]]
+        m = self.maps[sid]
         j.map = ft.ft_map_points(len(f["map"]["dmin"]), m["pos"].data_ptr(), m["normal"].data_ptr(),
                                  m["dmin"].data_ptr(), m["dmax"].data_ptr(), m["desc"].data_ptr())
         j.search_params = ft.search_params_struct(f["search_params"])
@@ -352,29 +394,28 @@ class DeviceExecutor:
         return len(self.free)
 
     def launch(self, frames, per_frame=False):
-        torch = self.torch
         # single-frame calls share the context's one workspace: keep them on one
         # stream; each in-flight batch owns its own workspace lane
         lane = 0 if per_frame else self.next_h % self.max_inflight
         hs = self.hip_streams[lane]
-        slots = [self.free.pop() for _ in frames]
-        jobs = []
-        with torch.cuda.stream(hs):
-            for fr, slot in zip(frames, slots):
-                s = self.streams[fr.stream]
-                q = fr.seq % len(s["frames"])
-                buf, n = self.pinned[(fr.stream, q)]
-                self.dev[slot].copy_(buf, non_blocking=True)
-                f = s["frames"][q]
-                f["_stream"] = fr.stream
-                jobs.append(self._job(f, n, slot))
+        n = len(frames)
+        slots = [self.free.pop() for _ in range(n)]
+        keys = [(fr.stream, fr.seq % len(self.streams[fr.stream]["frames"])) for fr in frames]
+        t = [self.tmpl[k] for k in keys]
+        shift = np.array(slots, dtype=np.uint64) * np.uint64(self.slot_bytes)
+        jobs = np.stack([w for w, _, _ in t]) + np.stack([m for _, m, _ in t]) * shift[:, None]
+        segs = np.empty((n, 3), dtype=np.int64)
+        segs[:, 0] = [self.arena + self.arena_off[k] for k in keys]
+        segs[:, 1] = self.dev_base + np.array(slots, dtype=np.int64) * self.slot_bytes
+        segs[:, 2] = [b for _, _, b in t]
+        self.ctx.ft_upload(segs, hs)
         if per_frame:
-            self._run_single(jobs[0], hs)
-            ev = torch.cuda.Event()
+            self._run_single(self.ft.ft_frame_job.from_buffer_copy(jobs[0].tobytes()), hs)
+            ev = self.torch.cuda.Event()
             ev.record(hs)
             token = ("event", ev)
         else:
-            token = ("ticket", self.ctx.ft_batch_submit(jobs, hs))
+            token = ("ticket", self.ctx.ft_batch_submit_raw(jobs.ctypes.data, n, hs))
         h = self.next_h
         self.next_h += 1
         self.handles[h] = (token, slots, frames)

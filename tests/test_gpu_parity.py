@@ -445,3 +445,36 @@ def test_epipolar_band_widths(ft, ctx, band):
             compare_frame(run_device(ft, ctx, f, batch=True), want)
     finally:
         ctx.ft_set_shapes(8, 1, 256)
+
+
+def test_concurrent_batches_on_streams_match(ft):
+    """Batches in flight on four streams at once (each its own copy of the
+    frames, each its own in-flight lane) give the single-stream results, in
+    graph and eager mode."""
+    ctx4 = ft.Context(ft.default_limits(max_batch_frames=16, max_map_points=65536, max_inflight=4))
+    frames = synth.mixed_batch(n_frames=16)
+    copies = [[ft.DeviceFrame(f, "cuda") for f in frames] for _ in range(4)]
+    jobs = [[d.job() for d in c] for c in copies]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    ctx4.ft_set_exec_mode(ft.FT_EXEC_EAGER)
+    ctx4.ft_batch_wait(ctx4.ft_batch_submit(jobs[0]))
+    torch.cuda.synchronize()
+    ref = [d.results() for d in copies[0]]
+    for mode in (ft.FT_EXEC_GRAPH, ft.FT_EXEC_EAGER):
+        ctx4.ft_set_exec_mode(mode)
+        say("mode", mode)
+        for c in copies:
+            _clobber(c)
+        pending = []
+        for rep in range(3):
+            for k in range(4):
+                if len(pending) >= 4:
+                    ctx4.ft_batch_wait(pending.pop(0))
+                pending.append(ctx4.ft_batch_submit(jobs[k], streams[k]))
+        while pending:
+            ctx4.ft_batch_wait(pending.pop(0))
+        torch.cuda.synchronize()
+        for c in copies:
+            for d, w in zip(c, ref):
+                bit_equal(d.results(), w)
+    ctx4.close()
