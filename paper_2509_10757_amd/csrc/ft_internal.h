@@ -16,7 +16,7 @@ constexpr int kMaxRows = 4096;
 constexpr int kMaxCells = 8192;
 constexpr int kMaxKp = 65535;
 constexpr int kMaxMap = (1 << 23) - 1;
-constexpr int kKnnQueriesPerWG = 16;  // fisheye all-pairs: one 16-row MFMA block per workgroup
+constexpr int kKnnQueriesPerWG = 32;  // fisheye all-pairs: queries per 256-thread subgroup (16-row MFMA blocks)
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
 constexpr int kRefineQPerWG = 16;     // ... 11x11 window, +-5 shifts: four matches per wave

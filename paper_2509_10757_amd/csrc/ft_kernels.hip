@@ -564,9 +564,30 @@ __device__ __forceinline__ void ph_best_wide(const DevJob &J, int tile, unsigned
 // NT threads = NT / 256 independent subgroups of four waves; subgroup k of
 // tile t owns queries (t * NT / 256 + k) * 16 ... + 15.  `part` holds 128
 // words per subgroup.  Every thread reaches both barriers.
+// Top-2 of 32-bit keys by value: the new best is min(a, key), the new second
+// min(b, max(a, key)) (keys are distinct: they carry the target index).
+__device__ __forceinline__ void top2_push(uint32_t &a, uint32_t &b, uint32_t key)
+{
+    b = min(b, max(a, key));
+    a = min(a, key);
+}
+
+// +-1 bytes of 16 descriptor bits (two table entries per byte pair).
+__device__ __forceinline__ v4i expand16(const uint64_t *tab, uint32_t word, int half)
+{
+    const uint64_t lo = tab[(word >> (16 * half)) & 0xFF];
+    const uint64_t hi = tab[(word >> (16 * half + 8)) & 0xFF];
+    return v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi, (int)(uint32_t)(hi >> 32)};
+}
+
+// Fisheye all-pairs top-2 on the matrix cores.  A workgroup subgroup (256
+// threads) owns kKnnQueriesPerWG queries; its four waves split the target
+// tiles.  Each wave holds the +-1 expansion of all its queries (QB blocks of
+// 16) and expands every 16-target tile once for all QB blocks.
 template <int NT>
 __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab, uint32_t *part)
 {
+    constexpr int QB = kKnnQueriesPerWG / 16;
     const int tid = threadIdx.x, ltid = tid & 255, sg = tid >> 8;
     // +-1 expansion of every byte value: bit t -> byte t, 1 -> +1, 0 -> -1
     if (tid < 256) {
@@ -577,25 +598,22 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
     __syncthreads();
     const int nQ = J.counts[0], nT = J.counts[1];
     const int q0 = (tile * (NT / 256) + sg) * kKnnQueriesPerWG;
-    part += sg * 128;
+    part += sg * (4 * kKnnQueriesPerWG * 2);
     const bool active = q0 < nQ && nT >= 2;   // uniform over the subgroup
     const int lane = ltid & 63, wave = ltid >> 6, g = lane >> 4, c = lane & 15;
     if (active) {
-    v4i A[4];
+    v4i A[QB][4];
+    _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
     {
-        const int qa = q0 + c;
+        const int qa = q0 + 16 * qb + c;
         uint2 w = make_uint2(0, 0);
         if (qa < nQ) w = *reinterpret_cast<const uint2 *>(J.L.desc + 32 * (size_t)J.qlist[qa] + 8 * g);
-        _Pragma("unroll") for (int s = 0; s < 4; ++s) {
-            const uint32_t word = s < 2 ? w.x : w.y;
-            const uint64_t lo = tab[(word >> (16 * (s & 1))) & 0xFF];
-            const uint64_t hi = tab[(word >> (16 * (s & 1) + 8)) & 0xFF];
-            A[s] = qa < nQ ? v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
-                                 (int)(uint32_t)(hi >> 32)}
-                           : v4i{0, 0, 0, 0};
-        }
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)
+            A[qb][s] = qa < nQ ? expand16(tab, s < 2 ? w.x : w.y, s & 1) : v4i{0, 0, 0, 0};
     }
-    Top2<uint32_t> t0 = {0xFFFFFFFFu, 0xFFFFFFFFu}, t1 = t0, t2 = t0, t3 = t0;
+    uint32_t ta[QB][4], tb[QB][4];
+    _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
+        _Pragma("unroll") for (int r = 0; r < 4; ++r) ta[qb][r] = tb[qb][r] = 0xFFFFFFFFu;
     const int n_tiles = (nT + 15) >> 4;
     // the next tile's descriptor bytes are loaded while this tile is processed
     uint2 wn = make_uint2(0, 0);
@@ -607,41 +625,41 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
         const uint2 w = wn;
         const int tn = ((t + 4) << 4) + c;
         if (t + 4 < n_tiles && tn < nT) wn = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)tn + 8 * g);
-        v4i acc = {0, 0, 0, 0};
-        _Pragma("unroll") for (int s = 0; s < 4; ++s) {
-            const uint32_t word = s < 2 ? w.x : w.y;
-            const uint64_t lo = tab[(word >> (16 * (s & 1))) & 0xFF];
-            const uint64_t hi = tab[(word >> (16 * (s & 1) + 8)) & 0xFF];
-            const v4i B = tv ? v4i{(int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
-                                   (int)(uint32_t)(hi >> 32)}
-                             : v4i{0, 0, 0, 0};
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[s], B, acc, 0, 0, 0);
-        }
-        // acc[r] = dot(query row 4g + r, target column c); targets are in index order
-        if (tv) {
-            const uint32_t col = (uint32_t)tj;
-            t0 = top2_insert(t0, ((uint32_t)((256 - acc[0]) >> 1) << 16) | col);
-            t1 = top2_insert(t1, ((uint32_t)((256 - acc[1]) >> 1) << 16) | col);
-            t2 = top2_insert(t2, ((uint32_t)((256 - acc[2]) >> 1) << 16) | col);
-            t3 = top2_insert(t3, ((uint32_t)((256 - acc[3]) >> 1) << 16) | col);
+        v4i B[4];
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)
+            B[s] = tv ? expand16(tab, s < 2 ? w.x : w.y, s & 1) : v4i{0, 0, 0, 0};
+        // acc[r] = dot(query row 4g + r of block qb, target column c); the key
+        // (256 - dot) << 15 | index = Hamming << 16 | index (dot = 256 - 2 H)
+        const uint32_t kbase = (256u << 15) | (uint32_t)tj;
+        _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
+        {
+            v4i acc = {0, 0, 0, 0};
+            _Pragma("unroll") for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qb][s], B[s], acc, 0, 0, 0);
+            if (tv) {
+                _Pragma("unroll") for (int r = 0; r < 4; ++r)
+                    top2_push(ta[qb][r], tb[qb][r], kbase - ((uint32_t)acc[r] << 15));
+            }
         }
     }
-    _Pragma("unroll") for (int m = 1; m < 16; m <<= 1) {
-        t0 = top2_merge(t0, __shfl_xor(t0.a, m), __shfl_xor(t0.b, m));
-        t1 = top2_merge(t1, __shfl_xor(t1.a, m), __shfl_xor(t1.b, m));
-        t2 = top2_merge(t2, __shfl_xor(t2.a, m), __shfl_xor(t2.b, m));
-        t3 = top2_merge(t3, __shfl_xor(t3.a, m), __shfl_xor(t3.b, m));
-    }
-    if (c == 0) {
-        uint32_t *pw = part + (wave * 16 + 4 * g) * 2;
-        pw[0] = t0.a; pw[1] = t0.b; pw[2] = t1.a; pw[3] = t1.b;
-        pw[4] = t2.a; pw[5] = t2.b; pw[6] = t3.a; pw[7] = t3.b;
+    _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
+    {
+        _Pragma("unroll") for (int r = 0; r < 4; ++r)
+        {
+            Top2<uint32_t> t = {ta[qb][r], tb[qb][r]};
+            _Pragma("unroll") for (int m = 1; m < 16; m <<= 1) t = top2_merge(t, __shfl_xor(t.a, m), __shfl_xor(t.b, m));
+            if (c == 0) {
+                uint32_t *pw = part + (wave * kKnnQueriesPerWG + 16 * qb + 4 * g + r) * 2;
+                pw[0] = t.a;
+                pw[1] = t.b;
+            }
+        }
     }
     }
     __syncthreads();
-    if (active && ltid < 16 && q0 + ltid < nQ) {
+    if (active && ltid < kKnnQueriesPerWG && q0 + ltid < nQ) {
         Top2<uint32_t> t = {part[ltid * 2], part[ltid * 2 + 1]};
-        for (int w = 1; w < 4; ++w) t = top2_merge(t, part[(w * 16 + ltid) * 2], part[(w * 16 + ltid) * 2 + 1]);
+        for (int w = 1; w < 4; ++w)
+            t = top2_merge(t, part[(w * kKnnQueriesPerWG + ltid) * 2], part[(w * kKnnQueriesPerWG + ltid) * 2 + 1]);
         const int i = J.qlist[q0 + ltid];
         J.best_j[i] = J.tlist[t.a & 0xFFFFu];
         J.best_h[i] = (int)(t.a >> 16);
@@ -1792,8 +1810,8 @@ __device__ __forceinline__ void task_search_final(const DevJob &J, int tile)
     ph_search_final(J, J.view[v], view_kp(J, v), tile - (v ? t0 : 0));
 }
 
-static_assert(256 * 8 + 4 * 16 * 2 * 4 <= kTaskLds, "stereo_a LDS");
-static_assert(256 * 8 + (kSearchWG / 256) * 128 * 4 <= kSearchLds, "stereo_a LDS (wide)");
+static_assert(256 * 8 + 4 * kKnnQueriesPerWG * 2 * 4 <= kTaskLds, "stereo_a LDS");
+static_assert(256 * 8 + (kSearchWG / 256) * 4 * kKnnQueriesPerWG * 2 * 4 <= kSearchLds, "stereo_a LDS (wide)");
 static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
 static_assert(kRefineQPerWG * kRefineQLds <= kTaskLds, "refine LDS (quarter waves)");
 static_assert(4 * kFlatLdsPerWave <= kTaskLds, "balanced search LDS");
@@ -1812,7 +1830,7 @@ __global__ __launch_bounds__(NT) void k_setup(Src src)
 template <class Src, int G>
 __global__ __launch_bounds__(kWG) void k_stereo_a(Src src)
 {
-    __shared__ __align__(16) unsigned char smem[256 * 8 + 4 * 16 * 2 * 4];
+    __shared__ __align__(16) unsigned char smem[256 * 8 + 4 * kKnnQueriesPerWG * 2 * 4];
     int job, tile;
     if (!src.locate(PH_STEREO_A, job, tile)) return;
     task_stereo_a<G>(src(job), tile, smem);
