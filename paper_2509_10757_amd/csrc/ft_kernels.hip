@@ -1364,27 +1364,11 @@ __device__ __forceinline__ void finish_query(const DevJob &J, const DevView &V, 
     if (kk1 >= 0) atomicMin(&V.claim[kk1], ((uint32_t)b1 << 23) | (uint32_t)m);
 }
 
-// Balanced search (one lane per map point).  A lane projects its map point; the
-// wave then splits the work of all its windows into items of one window row
-// (about 2.5 records each) and deals the items round-robin to its lanes, so
-// a map point with a large window does not hold its whole wave.  Candidates are
-// batched per lane (kCandBatch) for their descriptor reads, and each map
-// point's best two keys are kept in LDS by 64-bit atomic minima: a key goes to
-// the best slot, and whichever of it and the displaced best is larger goes to
-// the second slot, which leaves the two smallest distinct keys.
-constexpr int kFlatRowsPerPass = 2;                  // window rows per lane and pass
-constexpr int kFlatItems = 64 * kFlatRowsPerPass;    // items per wave and pass
-constexpr int kFlatRecs = 3;                         // records of an item loaded together
-constexpr int kFlatCand = 4;                         // candidates per descriptor batch
-constexpr int kFlatLdsPerWave = kFlatItems * 8 + 64 * 4 * 5 + 128 * 4 + 64 * 32;
-
-// Candidate key of the balanced search in 32 bits: distance (9 bits), keypoint
-// (16), level (4; octaves are 0..7 by contract); the same order as cand_key.
-__device__ __forceinline__ uint32_t cand_key32(int h, uint32_t meta)
-{
-    return ((uint32_t)h << 20) | ((meta >> 16) << 4) | (meta & 15u);
-}
-
+// Candidate keys of the record-dealt search are 32 bits: distance (9 bits),
+// keypoint (16), level (4; octaves are 0..7 by contract), in the same order as
+// cand_key; each map point's best two keys are kept in LDS by atomic minima: a
+// key goes to the best slot, and whichever of it and the displaced best is
+// larger goes to the second slot, which leaves the two smallest distinct keys.
 __device__ __forceinline__ uint64_t key32_to_64(uint32_t k)
 {
     if (k == 0xFFFFFFFFu) return ~0ull;
@@ -1392,8 +1376,8 @@ __device__ __forceinline__ uint64_t key32_to_64(uint32_t k)
 }
 
 // Orders one wave's LDS accesses (its lanes read what other lanes wrote); the
-// balanced search syncs only within a wave, whose pass count is wave-uniform
-// but may differ between the waves of a workgroup.
+// record-dealt search syncs only within a wave, whose chunk and round counts
+// are wave-uniform but may differ between the waves of a workgroup.
 __device__ __forceinline__ void wave_lds_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1401,140 +1385,178 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-struct FlatCand {
-    int p;    // record position
-    int ml;   // lane of the map point
-};
+// Record-dealt search (one lane per map point).  Every lane projects its map
+// point and loads the record ranges of up to kDealRows window rows at once;
+// the wave then lays the records of all 64 windows end to end and deals them
+// in contiguous runs of at most kDealRecs per lane, so every lane issues all
+// its record loads together whatever the window sizes.  Records that pass the
+// window test become candidates in one wave-wide list, which is again dealt
+// evenly for the descriptor reads; each map point's best two keys are kept in
+// LDS by 32-bit atomic minima.
+constexpr int kDealRows = 4;    // window rows per lane and chunk
+constexpr int kDealRecs = 6;    // records per lane and round
+constexpr int kDealFlush = 1;   // candidates per lane and descriptor batch
+constexpr int kDealQp = 0;                                // float4 u, v, Rm, level window [64]
+constexpr int kDealUr = kDealQp + 64 * 16;                // float uR [64]
+constexpr int kDealQd = kDealUr + 64 * 4;                 // Desc [64]
+constexpr int kDealTb = kDealQd + 64 * 32;                // best [64], second [64]
+constexpr int kDealSeg = kDealTb + 128 * 4;               // row segments [64][kDealRows]: start | count << 16
+constexpr int kDealBase = kDealSeg + 64 * kDealRows * 4;  // record prefix per lane [65]
+constexpr int kDealCands = kDealBase + 80 * 4;            // candidate list [64 * kDealRecs]
+constexpr int kDealLdsPerWave = kDealCands + 64 * kDealRecs * 4;
 
-__device__ __forceinline__ void flat_flush(const DevView &V, const FlatCand *c, int nc, const float *quR,
-                                           const float *qR, const Desc *qd, uint32_t *tb)
-{
-    Desc d[kFlatCand];
-    float ur[kFlatCand];
-    uint32_t meta[kFlatCand];
-    _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e)
-    {
-        if (e < nc) {
-            d[e] = load_desc(V.cdesc, c[e].p);
-            meta[e] = V.crec[c[e].p].meta;
-        }
-    }
-    _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e)
-    {
-        ur[e] = 0.0f;
-        if (e < nc && V.u_right) ur[e] = V.u_right[meta[e] >> 16];
-    }
-    _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e)
-    {
-        if (e < nc) {
-            const int ml = c[e].ml;
-            const bool rej = V.u_right && ur[e] > 0.0f && !(fabsf(quR[ml] - ur[e]) <= qR[ml]);
-            if (!rej) {
-                const uint32_t key = cand_key32(hamming(qd[ml], d[e]), meta[e]);
-                const uint32_t old = atomicMin(&tb[ml], key);
-                atomicMin(&tb[64 + ml], key < old ? old : key);
-            }
-        }
-    }
-}
-
-__device__ __forceinline__ void ph_search_flat(const DevJob &J, const DevView &V, int tile, unsigned char *smem)
+__device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, const DevKps &K, int tile,
+                                               unsigned char *smem)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = tile * kWG + wave * 64;   // map point of lane 0 of this wave
-    const int m = m0 + lane;
-    unsigned char *base = smem + wave * kFlatLdsPerWave;
-    int2 *items = reinterpret_cast<int2 *>(base);
-    float *qu = reinterpret_cast<float *>(base + kFlatItems * 8);
-    float *qv = qu + 64, *qR = qv + 64, *quR = qR + 64;
-    int *qlv = reinterpret_cast<int *>(quR + 64);               // level window: lo + 16 | (hi + 16) << 8
-    uint32_t *tb = reinterpret_cast<uint32_t *>(qlv + 64);       // best[64], second[64] (32-bit keys)
-    Desc *qd = reinterpret_cast<Desc *>(tb + 128);               // map point descriptors
+    const int m = tile * kWG + wave * 64 + lane;
+    unsigned char *base = smem + wave * kDealLdsPerWave;
+    float4 *qp = reinterpret_cast<float4 *>(base + kDealQp);
+    float *quR = reinterpret_cast<float *>(base + kDealUr);
+    Desc *qd = reinterpret_cast<Desc *>(base + kDealQd);
+    uint32_t *tb = reinterpret_cast<uint32_t *>(base + kDealTb);
+    uint32_t *seg = reinterpret_cast<uint32_t *>(base + kDealSeg);
+    int *lbase = reinterpret_cast<int *>(base + kDealBase);
+    uint32_t *cl = reinterpret_cast<uint32_t *>(base + kDealCands);
 
     Query q;
     q.vis = false;
     if (m < J.nM) q = make_query(J, V, m);
     const int cx0 = q.vis ? q.cx0 : 0, cx1 = q.vis ? q.cx1 : 0;
     const int cy0 = q.vis ? q.cy0 : 0, cy1 = q.vis ? q.cy1 : -1;
-    qu[lane] = q.u;
-    qv[lane] = q.v;
-    qR[lane] = q.vis ? q.Rm : 0.0f;
+    const int lv = q.vis ? ((q.plo + 16) | ((q.phi + 16) << 8)) : (16 | (15 << 8));
+    qp[lane] = make_float4(q.u, q.v, q.vis ? q.Rm : 0.0f, __int_as_float(lv));
     quR[lane] = q.vis ? q.uR : 0.0f;
-    qlv[lane] = q.vis ? ((q.plo + 16) | ((q.phi + 16) << 8)) : (16 | (15 << 8));
+    qd[lane] = q.dm;
     tb[lane] = 0xFFFFFFFFu;
     tb[64 + lane] = 0xFFFFFFFFu;
-    qd[lane] = q.dm;
-    int passes = (cy1 - cy0 + 1 + kFlatRowsPerPass - 1) / kFlatRowsPerPass;
-    for (int o = 32; o >= 1; o >>= 1) passes = max(passes, __shfl_xor(passes, o));
-    wave_lds_sync();
-    for (int pass = 0; pass < passes; ++pass) {
-        // this lane's rows of the pass: their record ranges, one round of loads
-        const int r0 = cy0 + pass * kFlatRowsPerPass;
-        int ra[kFlatRowsPerPass], rn[kFlatRowsPerPass];
-        _Pragma("unroll") for (int e = 0; e < kFlatRowsPerPass; ++e)
+    const bool gate = V.u_right != nullptr;
+    int chunks = (cy1 - cy0 + kDealRows) / kDealRows;
+    for (int o = 32; o >= 1; o >>= 1) chunks = max(chunks, __shfl_xor(chunks, o));
+    for (int ch = 0; ch < chunks; ++ch) {
+        // record ranges of this lane's rows of the chunk: one round of loads
+        const int r0 = cy0 + ch * kDealRows;
+        uint32_t sg[kDealRows];
+        int mine = 0;
+        _Pragma("unroll") for (int e = 0; e < kDealRows; ++e)
         {
             const bool in = r0 + e <= cy1;
             const int row = in ? r0 + e : 0;
             const int a = V.cell_off[row * V.cols + cx0];
             const int b = V.cell_off[row * V.cols + cx1 + 1];
-            ra[e] = a;
-            rn[e] = in ? b - a : 0;
+            const int n = in ? b - a : 0;
+            sg[e] = (uint32_t)a | ((uint32_t)n << 16);
+            mine += n;
         }
-        int cnt = 0;
-        _Pragma("unroll") for (int e = 0; e < kFlatRowsPerPass; ++e) cnt += rn[e] > 0 ? 1 : 0;
-        int incl = cnt;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
+        const int incl = wave_inclusive_scan(mine);
         const int total = __shfl(incl, 63);
-        int k = incl - cnt;
-        _Pragma("unroll") for (int e = 0; e < kFlatRowsPerPass; ++e)
-        {
-            if (rn[e] > 0) {
-                items[k] = make_int2(ra[e], rn[e] | (lane << 16));
-                ++k;
-            }
-        }
+        wave_lds_sync();   // the previous chunk's readers are done with seg / lbase
+        lbase[lane] = incl - mine;
+        if (lane == 63) lbase[64] = total;
+        _Pragma("unroll") for (int e = 0; e < kDealRows; ++e) seg[lane * kDealRows + e] = sg[e];
         wave_lds_sync();
-        // a lane's candidates are collected kFlatCand at a time (the first
-        // `done` skipped) and flushed; only lanes with more rescan
-        int done = 0;
-        for (;;) {
-            FlatCand cand[kFlatCand];
-            _Pragma("unroll") for (int e = 0; e < kFlatCand; ++e) cand[e] = FlatCand{0, 0};
-            int nc = 0, seen = 0;
-            for (int it = lane; it < total; it += 64) {
-                const int2 item = items[it];
-                const int a = item.x, n = item.y & 0xFFFF, ml = item.y >> 16;
-                Query iq;
-                iq.u = qu[ml];
-                iq.v = qv[ml];
-                iq.Rm = qR[ml];
-                const int lv = qlv[ml];
-                iq.plo = (lv & 0xFF) - 16;
-                iq.phi = ((lv >> 8) & 0xFF) - 16;
-                for (int p0 = a; p0 < a + n; p0 += kFlatRecs) {
-                    CellRec rec[kFlatRecs];
-                    _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e) rec[e] = V.crec[min(p0 + e, a + n - 1)];
-                    _Pragma("unroll") for (int e = 0; e < kFlatRecs; ++e)
-                    {
-                        if (p0 + e < a + n && in_window(iq, rec[e].x, rec[e].y, rec[e].meta)) {
-                            if (seen >= done && nc < kFlatCand) {
-                                _Pragma("unroll") for (int f = 0; f < kFlatCand; ++f) if (nc == f) cand[f] = FlatCand{p0 + e, ml};
-                                ++nc;
+        for (int g_lo = 0; g_lo < total; g_lo += 64 * kDealRecs) {
+            const int cnt = min(total - g_lo, 64 * kDealRecs);
+            const int run = (cnt + 63) >> 6;
+            const int g0 = g_lo + min(lane * run, cnt), g1 = g_lo + min(lane * run + run, cnt);
+            // the run's first record: owning lane s (last lane whose prefix is
+            // <= g0), then its row segment
+            int s = 0;
+            int e = 0, off = 0;
+            uint32_t cur = 0;
+            if (g0 < g1) {
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (lbase[mid] <= g0) lo = mid;
+                    else hi = mid - 1;
+                }
+                s = lo;
+                off = g0 - lbase[s];
+                cur = seg[s * kDealRows];
+                while (off >= (int)(cur >> 16)) {
+                    off -= (int)(cur >> 16);
+                    cur = seg[s * kDealRows + ++e];
+                }
+            }
+            // the run's records: record index | map lane << 16
+            uint32_t key[kDealRecs];
+            _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k)
+            {
+                const bool v = g0 + k < g1;
+                key[k] = v ? (((cur & 0xFFFFu) + (uint32_t)off) | ((uint32_t)s << 16)) : 0u;
+                if (v && g0 + k + 1 < g1) {
+                    if (++off == (int)(cur >> 16)) {
+                        off = 0;
+                        do {
+                            if (++e == kDealRows) {
+                                e = 0;
+                                ++s;
                             }
-                            ++seen;
-                        }
+                            cur = seg[s * kDealRows + e];
+                        } while ((cur >> 16) == 0u);
                     }
                 }
             }
-            flat_flush(V, cand, nc, quR, qR, qd, tb);
-            done += nc;
-            if (done >= seen) break;
+            CellRec rec[kDealRecs];
+            _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k) if (g0 + k < g1) rec[k] = V.crec[key[k] & 0xFFFFu];
+            // window test; candidates as keypoint | level << 16 | map lane << 20
+            uint32_t cand[kDealRecs];
+            int nc = 0;
+            _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k)
+            {
+                cand[k] = 0xFFFFFFFFu;
+                if (g0 + k < g1) {
+                    const int ml = (int)(key[k] >> 16);
+                    const float4 qq = qp[ml];
+                    const int l = __float_as_int(qq.w);
+                    Query iq;
+                    iq.u = qq.x;
+                    iq.v = qq.y;
+                    iq.Rm = qq.z;
+                    iq.plo = (l & 0xFF) - 16;
+                    iq.phi = ((l >> 8) & 0xFF) - 16;
+                    if (in_window(iq, rec[k].x, rec[k].y, rec[k].meta)) {
+                        cand[k] = (rec[k].meta >> 16) | ((rec[k].meta & 15u) << 16) | ((uint32_t)ml << 20);
+                        ++nc;
+                    }
+                }
+            }
+            const int cincl = wave_inclusive_scan(nc);
+            const int ctot = __shfl(cincl, 63);
+            int cw = cincl - nc;
+            _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k) if (cand[k] != 0xFFFFFFFFu) cl[cw++] = cand[k];
+            wave_lds_sync();
+            // candidates dealt evenly: descriptor (and right coordinate) reads together
+            for (int c0 = 0; c0 < ctot; c0 += 64 * kDealFlush) {
+                uint32_t cc[kDealFlush];
+                Desc d[kDealFlush];
+                float ur[kDealFlush];
+                _Pragma("unroll") for (int t = 0; t < kDealFlush; ++t)
+                {
+                    const int ci = c0 + t * 64 + lane;
+                    cc[t] = ci < ctot ? cl[ci] : 0xFFFFFFFFu;
+                    if (cc[t] != 0xFFFFFFFFu) d[t] = load_desc(K.desc, (int)(cc[t] & 0xFFFFu));
+                    ur[t] = 0.0f;
+                    if (cc[t] != 0xFFFFFFFFu && gate) ur[t] = V.u_right[cc[t] & 0xFFFFu];
+                }
+                _Pragma("unroll") for (int t = 0; t < kDealFlush; ++t)
+                {
+                    if (cc[t] == 0xFFFFFFFFu) continue;
+                    const int ml = (int)(cc[t] >> 20);
+                    const bool rej = gate && ur[t] > 0.0f && !(fabsf(quR[ml] - ur[t]) <= qp[ml].z);
+                    if (!rej) {
+                        const uint32_t key32 = ((uint32_t)hamming(qd[ml], d[t]) << 20) | ((cc[t] & 0xFFFFu) << 4) |
+                                               ((cc[t] >> 16) & 15u);
+                        const uint32_t old = atomicMin(&tb[ml], key32);
+                        atomicMin(&tb[64 + ml], key32 < old ? old : key32);
+                    }
+                }
+            }
+            wave_lds_sync();   // the list is free for the next round
         }
-        wave_lds_sync();   // atomics done; items free for the next pass
     }
+    wave_lds_sync();
     Top2<uint64_t> top = {key32_to_64(tb[lane]), key32_to_64(tb[64 + lane])};
     finish_query<1>(J, V, m, 0, top);
 }
@@ -1798,7 +1820,10 @@ __device__ __forceinline__ void task_search(const DevJob &J, int tile, unsigned 
     const int tpv = search_tiles_per_view(J, G);
     const int v = tile / tpv;
     if (v >= J.n_views) return;
-    if constexpr (G == 1) ph_search_flat(J, J.view[v], tile - v * tpv, smem);
+    if constexpr (G == 1) {
+        const DevView &V = J.view[v];
+        ph_search_deal(J, V, V.side ? J.R : J.L, tile - v * tpv, smem);
+    }
     else ph_search<G>(J, J.view[v], tile - v * tpv);
 }
 
@@ -1814,7 +1839,7 @@ static_assert(256 * 8 + 4 * kKnnQueriesPerWG * 2 * 4 <= kTaskLds, "stereo_a LDS"
 static_assert(256 * 8 + (kSearchWG / 256) * 4 * kKnnQueriesPerWG * 2 * 4 <= kSearchLds, "stereo_a LDS (wide)");
 static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
 static_assert(kRefineQPerWG * kRefineQLds <= kTaskLds, "refine LDS (quarter waves)");
-static_assert(4 * kFlatLdsPerWave <= kTaskLds, "balanced search LDS");
+static_assert(4 * kDealLdsPerWave <= kTaskLds, "record-dealt search LDS");
 static_assert((256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4 <= kTaskLds, "median LDS");
 
 // ------------------------------------------------------- per-phase kernels
@@ -1865,9 +1890,11 @@ __global__ __launch_bounds__(NT) void k_stereo_c(Src src)
 }
 
 template <class Src, int G>
-__global__ __launch_bounds__(kWG) void k_search(Src src)
+// Six waves per SIMD: the record-dealt search's LDS allows six workgroups per
+// CU, and registers are capped to match.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_search(Src src)
 {
-    __shared__ __align__(16) unsigned char smem[G == 1 ? 4 * kFlatLdsPerWave : 16];
+    __shared__ __align__(16) unsigned char smem[G == 1 ? 4 * kDealLdsPerWave : 16];
     int job, tile;
     if (!src.locate(PH_SEARCH, job, tile)) return;
     task_search<G>(src(job), tile, smem);
