@@ -28,7 +28,6 @@ struct Slot {  // workspace of one frame
     struct {
         int32_t *cell_off, *mp_k, *mp_h;
         CellRec *crec;
-        uint8_t *cdesc;
         uint32_t *claim;
     } view[2];
 };
@@ -183,7 +182,6 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     for (int v = 0; v < 2; ++v) {
         s.view[v].cell_off = b.take<int32_t>(base, (size_t)L.max_grid_cells + 1);
         s.view[v].crec = b.take<CellRec>(base, kp);
-        s.view[v].cdesc = b.take<uint8_t>(base, 32 * kp);
         s.view[v].mp_k = b.take<int32_t>(base, mp);
         s.view[v].mp_h = b.take<int32_t>(base, mp);
         s.view[v].claim = b.take<uint32_t>(base, kp);
@@ -459,13 +457,13 @@ ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_searc
     V.side = side;
     V.preassigned = pre;
     V.u_right = u_right;
+    V.kdesc = kps->desc;
     V.mp_match = o->mp_match;
     V.mp_dist = o->mp_dist;
     V.kp_match = o->kp_match;
     V.n_matches = o->n_matches;
     V.cell_off = slot.view[v].cell_off;
     V.crec = slot.view[v].crec;
-    V.cdesc = slot.view[v].cdesc;
     V.mp_k = slot.view[v].mp_k;
     V.mp_h = slot.view[v].mp_h;
     V.claim = slot.view[v].claim;

@@ -73,11 +73,11 @@ struct DevView {
     int32_t side;                    // keypoints of the left (0) or right (1) image
     const uint8_t *preassigned;      // nullable
     const float *u_right;            // nullable
+    const uint8_t *kdesc;            // descriptors of the view's keypoints
     int32_t *mp_match, *mp_dist, *kp_match, *n_matches;
     // workspace
     int32_t *cell_off;
     CellRec *crec;
-    uint8_t *cdesc;
     int32_t *mp_k, *mp_h;
     uint32_t *claim;
 };
@@ -105,7 +105,7 @@ struct DevJob {
     // stereo workspace
     int32_t *row_start;               // rows + 1
     RowRec *rrec;                     // right keypoints sorted by row
-    uint8_t *tdesc;                   // right descriptors: row order (pinhole) / overlap order (fisheye)
+    uint8_t *tdesc;                   // right descriptors in overlap order (fisheye)
     int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
     float *best_x;                    // pinhole: x of the best right keypoint
     float *uR, *depth, *xyz;

@@ -239,20 +239,15 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
     for (int r = tid; r < rows; r += NT) J.row_start[r] = cnt[r];
     if (tid == 0) J.row_start[rows] = total;
     __syncthreads();
-    const v4u *src = reinterpret_cast<const v4u *>(J.R.desc);
-    v4u *dst = reinterpret_cast<v4u *>(J.tdesc);
     for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
         int oct[kSortUnroll];
-        v4u da[kSortUnroll], db[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int j = min(j0 + e * NT, nR - 1);
             x[e] = J.R.x[j];
             y[e] = J.R.y[j];
             oct[e] = J.R.oct[j];
-            da[e] = src[2 * j];
-            db[e] = src[2 * j + 1];
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
@@ -265,8 +260,6 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
                 rec.meta = (uint32_t)oct[e] | ((uint32_t)j << 16);
                 rec.pad = 0;
                 J.rrec[pos] = rec;
-                dst[2 * pos] = da[e];
-                dst[2 * pos + 1] = db[e];
             }
         }
     }
@@ -347,12 +340,9 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
     for (int c = tid; c < cells; c += NT) V.cell_off[c] = cnt[c];
     if (tid == 0) V.cell_off[cells] = total;
     __syncthreads();
-    const v4u *dsrc = reinterpret_cast<const v4u *>(K.desc);
-    v4u *ddst = reinterpret_cast<v4u *>(V.cdesc);
     for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
         uint32_t meta[kSortUnroll];
-        v4u da[kSortUnroll], db[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int k = min(k0 + e * NT, K.n - 1);
@@ -360,8 +350,6 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
             y[e] = K.y[k];
             const uint32_t pre = (V.preassigned && V.preassigned[k]) ? 1u : 0u;
             meta[e] = (uint32_t)K.oct[k] | (pre << 8) | ((uint32_t)k << 16);
-            da[e] = dsrc[2 * k];
-            db[e] = dsrc[2 * k + 1];
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
@@ -375,8 +363,6 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
                 rec.meta = meta[e];
                 rec.pad = 0;
                 V.crec[pos] = rec;
-                ddst[2 * pos] = da[e];
-                ddst[2 * pos + 1] = db[e];
             }
         }
     }
@@ -419,7 +405,7 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
                     const int oj = (int)(rec[u].meta & 0xFFu);
                     cand[u] = p0 + u * G < p1 && row >= lo && row <= hi && oj >= oi - J.level_window &&
                               oj <= oi + J.level_window && rec[u].x >= minU && rec[u].x <= maxU;
-                    if (cand[u]) d[u] = load_desc(J.tdesc, p0 + u * G);
+                    if (cand[u]) d[u] = load_desc(J.R.desc, (int)(rec[u].meta >> 16));
                 }
                 _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
                 {
@@ -484,7 +470,7 @@ __device__ __forceinline__ void best_scan(const DevJob &J, const int *rs, const 
         Desc d[kCandBatch];
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
         {
-            if (e < n) d[e] = load_desc(J.tdesc, cp[e]);
+            if (e < n) d[e] = load_desc(J.R.desc, (int)(rr[cp[e]].meta >> 16));
         }
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
         {
@@ -1323,7 +1309,7 @@ __device__ __forceinline__ Top2<uint64_t> scan_global(const DevView &V, const Qu
                 cand[e] = p0 + e * G < c1 && in_window(q, rec[e].x, rec[e].y, rec[e].meta);
                 ur[e] = 0.0f;
                 if (cand[e]) {
-                    d[e] = load_desc(V.cdesc, p0 + e * G);
+                    d[e] = load_desc(V.kdesc, (int)(rec[e].meta >> 16));
                     if (q.gate) ur[e] = V.u_right[rec[e].meta >> 16];
                 }
             }
@@ -1405,8 +1391,7 @@ constexpr int kDealBase = kDealSeg + 64 * kDealRows * 4;  // record prefix per l
 constexpr int kDealCands = kDealBase + 80 * 4;            // candidate list [64 * kDealRecs]
 constexpr int kDealLdsPerWave = kDealCands + 64 * kDealRecs * 4;
 
-__device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, const DevKps &K, int tile,
-                                               unsigned char *smem)
+__device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, int tile, unsigned char *smem)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = tile * kWG + wave * 64 + lane;
@@ -1536,7 +1521,7 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
                 {
                     const int ci = c0 + t * 64 + lane;
                     cc[t] = ci < ctot ? cl[ci] : 0xFFFFFFFFu;
-                    if (cc[t] != 0xFFFFFFFFu) d[t] = load_desc(K.desc, (int)(cc[t] & 0xFFFFu));
+                    if (cc[t] != 0xFFFFFFFFu) d[t] = load_desc(V.kdesc, (int)(cc[t] & 0xFFFFu));
                     ur[t] = 0.0f;
                     if (cc[t] != 0xFFFFFFFFu && gate) ur[t] = V.u_right[cc[t] & 0xFFFFu];
                 }
@@ -1616,7 +1601,7 @@ __device__ __forceinline__ Top2<uint64_t> scan_lds(const DevView &V, const Query
             }
         }
         Desc d[kCandBatch];
-        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (e < n) d[e] = load_desc(V.cdesc, cp[e]);
+        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (e < n) d[e] = load_desc(V.kdesc, (int)(srec[cp[e]].meta >> 16));
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
         {
             if (e < n) top = top2_insert(top, cand_key(hamming(q.dm, d[e]), srec[cp[e]].meta));
@@ -1820,10 +1805,7 @@ __device__ __forceinline__ void task_search(const DevJob &J, int tile, unsigned 
     const int tpv = search_tiles_per_view(J, G);
     const int v = tile / tpv;
     if (v >= J.n_views) return;
-    if constexpr (G == 1) {
-        const DevView &V = J.view[v];
-        ph_search_deal(J, V, V.side ? J.R : J.L, tile - v * tpv, smem);
-    }
+    if constexpr (G == 1) ph_search_deal(J, J.view[v], tile - v * tpv, smem);
     else ph_search<G>(J, J.view[v], tile - v * tpv);
 }
 
