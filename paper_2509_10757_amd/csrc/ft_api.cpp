@@ -702,7 +702,8 @@ ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int part, int32_t n, c
     GraphEntry *hit = nullptr;
     for (auto &g : lane.graphs) {
         if (g.part == part && g.n == n && g.shapes.best_lanes == sh.best_lanes &&
-            g.shapes.search_lanes == sh.search_lanes &&
+            g.shapes.search_lanes == sh.search_lanes && g.shapes.search_wide == sh.search_wide &&
+            g.shapes.best_wide == sh.best_wide && g.shapes.wide_misc == sh.wide_misc &&
             std::equal(totals, totals + PH_COUNT, g.totals)) {
             hit = &g;
             break;
