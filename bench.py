@@ -117,6 +117,9 @@ def serving_sweep(duration_s, speedups):
     log("generating the 32-stream serving workload")
     streams = make_streams()
     ex = serve.DeviceExecutor(streams, max_batch=64, max_inflight=4)
+    for s in streams:
+        ex.admit(s["id"])
+    log("serving shapes", ex.autotune())
     rows = []
     for mode in ("per_frame", "batched"):
         for a in speedups:

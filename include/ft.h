@@ -362,6 +362,9 @@ typedef struct ft_shapes {
                                   resolve: 256 or 1024 */
 } ft_shapes;
 
+/* A new context starts with best_lanes 8, search_lanes 1, search_block 256,
+ * best_block 256, aux_block 1024 (the shapes the autotuner picks for mixed
+ * pinhole/fisheye batches). */
 ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *shapes);
 ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *shapes);
 

@@ -119,12 +119,13 @@ struct DevJob {
 };
 
 // Launch shapes of one submission (the autotuner chooses the lane groups).
+// Defaults: the shapes the autotuner picks for mixed pinhole/fisheye batches.
 struct Shapes {
     int best_lanes = 8;        // lanes cooperating on one pinhole left keypoint
-    int search_lanes = 4;      // lanes cooperating on one map point (kWG-thread search)
+    int search_lanes = 1;      // lanes cooperating on one map point (kWG-thread search; 1 = record-dealt)
     bool search_wide = false;  // search in kSearchWG-thread tiles with the view staged in LDS
     bool best_wide = false;    // stereo best match in kSearchWG-thread tiles (pinhole rows in LDS)
-    bool wide_misc = false;    // setup sorts and stereo resolve in kSearchWG-thread workgroups
+    bool wide_misc = true;     // setup sorts and stereo resolve in kSearchWG-thread workgroups
 };
 
 // Wide search: threads per workgroup and LDS staging bytes.

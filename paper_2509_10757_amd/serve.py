@@ -389,6 +389,23 @@ class DeviceExecutor:
                                                o["kp_match"][v].data_ptr(), o["n_search"][v:v + 1].data_ptr())
         return j
 
+    def autotune(self, n: int | None = None, cache_path: str | None = None):
+        """Pick launch shapes on a batch of up to `n` pooled frames of the
+        admitted streams (uploaded to slots 0.., then timed by ft_autotune)."""
+        ft = self.ft
+        n = min(n or self.max_batch, self.max_batch)
+        keys = [k for k in self.tmpl][:n]
+        if not keys:
+            return None
+        jobs = np.stack([self.tmpl[k][0] + self.tmpl[k][1] * np.uint64(i * self.slot_bytes)
+                         for i, k in enumerate(keys)])
+        segs = np.array([(self.arena + self.arena_off[k], self.dev_base + i * self.slot_bytes, self.tmpl[k][2])
+                         for i, k in enumerate(keys)], dtype=np.int64)
+        hs = self.hip_streams[0]
+        self.ctx.ft_upload(segs, hs)
+        structs = [ft.ft_frame_job.from_buffer_copy(row.tobytes()) for row in jobs]
+        return self.ctx.ft_autotune(structs, cache_path=cache_path, stream=hs)
+
     # -- executor protocol -----------------------------------------------------
     def free_slots(self) -> int:
         return len(self.free)
