@@ -49,6 +49,16 @@ struct RowRec {
 };
 
 // Keypoint sorted by grid cell (search by projection): 16 bytes + descriptor.
+// Pointers the kernels dereference are global-memory pointers in the kernels'
+// device code (FT_KERNELS is defined by the kernel sources), so loads and
+// stores through them are global, not flat, instructions; host code sees
+// plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(FT_KERNELS)
+#define FT_G __attribute__((address_space(1)))
+#else
+#define FT_G
+#endif
+
 struct CellRec {
     float x, y;
     uint32_t meta;   // octave | preassigned << 8 | index << 16
@@ -57,9 +67,9 @@ struct CellRec {
 
 struct DevKps {
     int32_t n;
-    const float *x, *y;
-    const uint8_t *oct;
-    const uint8_t *desc;
+    const FT_G float *x, *y;
+    const FT_G uint8_t *oct;
+    const FT_G uint8_t *desc;
 };
 
 struct DevView {
@@ -71,15 +81,15 @@ struct DevView {
     float min_x, max_x, min_y, max_y;
     float inv_cw, inv_ch;            // cols/(max_x-min_x), rows/(max_y-min_y)
     int32_t side;                    // keypoints of the left (0) or right (1) image
-    const uint8_t *preassigned;      // nullable
-    const float *u_right;            // nullable
-    const uint8_t *kdesc;            // descriptors of the view's keypoints
-    int32_t *mp_match, *mp_dist, *kp_match, *n_matches;
+    const FT_G uint8_t *preassigned;      // nullable
+    const FT_G float *u_right;            // nullable
+    const FT_G uint8_t *kdesc;            // descriptors of the view's keypoints
+    FT_G int32_t *mp_match, *mp_dist, *kp_match, *n_matches;
     // workspace
-    int32_t *cell_off;
-    CellRec *crec;
-    int32_t *mp_k, *mp_h;
-    uint32_t *claim;
+    FT_G int32_t *cell_off;
+    FT_G CellRec *crec;
+    FT_G int32_t *mp_k, *mp_h;
+    FT_G uint32_t *claim;
 };
 
 struct DevJob {
@@ -89,7 +99,7 @@ struct DevJob {
     DevKps L, R;
     float sf[kLevels], inv_sf[kLevels], sigma2[kLevels];
     // pinhole stereo
-    const uint8_t *pyrL, *pyrR;
+    const FT_G uint8_t *pyrL, *pyrR;
     int64_t lv_off[kLevels];
     int32_t lv_w[kLevels], lv_h[kLevels];
     float bf, maxD, band;
@@ -100,19 +110,19 @@ struct DevJob {
     int32_t ratio_num, ratio_den, newton_iters;
     double cos_max, chi2, max_theta, newton_tol;
     // stereo outputs (caller memory)
-    int32_t *o_right_idx, *o_dist, *o_sad, *o_nmatch;
-    float *o_uR, *o_depth, *o_xyz;
+    FT_G int32_t *o_right_idx, *o_dist, *o_sad, *o_nmatch;
+    FT_G float *o_uR, *o_depth, *o_xyz;
     // stereo workspace
-    int32_t *row_start;               // rows + 1
-    RowRec *rrec;                     // right keypoints sorted by row
-    uint8_t *tdesc;                   // right descriptors in overlap order (fisheye)
-    int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
-    float *best_x;                    // pinhole: x of the best right keypoint
-    float *uR, *depth, *xyz;
-    uint32_t *claimR;
+    FT_G int32_t *row_start;               // rows + 1
+    FT_G RowRec *rrec;                     // right keypoints sorted by row
+    FT_G uint8_t *tdesc;                   // right descriptors in overlap order (fisheye)
+    FT_G int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
+    FT_G float *best_x;                    // pinhole: x of the best right keypoint
+    FT_G float *uR, *depth, *xyz;
+    FT_G uint32_t *claimR;
     // search by projection
-    const float *pos, *normal, *dmin, *dmax;
-    const uint8_t *mdesc;
+    const FT_G float *pos, *normal, *dmin, *dmax;
+    const FT_G uint8_t *mdesc;
     float th, cos_lim, cos_narrow, r_narrow, r_wide, dist_lo, dist_hi;
     int32_t lv_lo, lv_hi, th_high, s_ratio_num, s_ratio_den, same_level_only;
     DevView view[2];
@@ -139,7 +149,7 @@ constexpr int kBestWideQ = 1024 / kBestWideLanes;
 // block index to (job, tile) with a binary search over them.
 struct TileMap {
     int32_t n_jobs;
-    const int32_t *prefix;  // device [PH_COUNT][n_jobs + 1]
+    const FT_G int32_t *prefix;  // device [PH_COUNT][n_jobs + 1]
 };
 
 // Per-job tile counts of each phase for the given shapes.

@@ -32,6 +32,7 @@
 
 #include <algorithm>
 
+#define FT_KERNELS 1
 #include "ft_internal.h"
 
 namespace ft {

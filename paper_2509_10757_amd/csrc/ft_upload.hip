@@ -2,6 +2,7 @@
 // in one kernel (the per-frame upload of a serving loop).
 #include <hip/hip_runtime.h>
 
+#define FT_KERNELS 1
 #include "ft_internal.h"
 
 namespace ft {
