@@ -163,7 +163,7 @@ struct Bump {
 void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
 {
     const size_t kp = (size_t)L.max_kp_per_image, mp = (size_t)L.max_map_points;
-    s.row_start = b.take<int32_t>(base, (size_t)L.max_rows + 1);
+    s.row_start = b.take<int32_t>(base, (size_t)kLevels * ((size_t)L.max_rows + 1));
     s.rrec = b.take<RowRec>(base, kp);
     s.tdesc = b.take<uint8_t>(base, 32 * kp);
     s.best_j = b.take<int32_t>(base, kp);
@@ -314,6 +314,12 @@ ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const
     // a right keypoint whose band covers row r has its integer row within
     // ceil(band * sf_max) + 1 of r; one more bin absorbs the float rounding
     J.row_reach = (int)std::ceil(p->band * sc->sf[kLevels - 1]) + 2;
+    // rows are binned per pyramid level when the (level, row) bins fit the
+    // sort's LDS histogram: a query then scans only the levels of its window,
+    // each over that level's own reach
+    J.n_lb = (int64_t)kLevels * cam->rows <= kMaxCells ? kLevels : 1;
+    for (int l = 0; l < kLevels; ++l)
+        J.lv_reach[l] = J.n_lb == 1 ? J.row_reach : (int)std::ceil(p->band * sc->sf[l]) + 2;
     J.th_orb = p->th_orb;
     J.half_win = p->half_win;
     J.half_range = p->half_range;

@@ -103,7 +103,10 @@ struct DevJob {
     int64_t lv_off[kLevels];
     int32_t lv_w[kLevels], lv_h[kLevels];
     float bf, maxD, band;
-    int32_t rows, row_reach;          // bins scanned on each side of a query row
+    int32_t rows, row_reach;          // bins scanned on each side of a query row (one level bin)
+    int32_t n_lb;                     // level bins of the row index: kLevels (rows binned per
+                                      // pyramid level) or 1 (one bin for every level)
+    int32_t lv_reach[kLevels];        // per level bin: rows scanned on each side of a query row
     int32_t th_orb, half_win, half_range, level_window, med_num, med_den;
     // fisheye stereo
     float kbL[8], kbR[8], R_lr[9], t_lr[3], ovl[2], ovr[2];
@@ -113,7 +116,7 @@ struct DevJob {
     FT_G int32_t *o_right_idx, *o_dist, *o_sad, *o_nmatch;
     FT_G float *o_uR, *o_depth, *o_xyz;
     // stereo workspace
-    FT_G int32_t *row_start;               // rows + 1
+    FT_G int32_t *row_start;               // [n_lb][rows + 1] record offsets of (level bin, row)
     FT_G RowRec *rrec;                     // right keypoints sorted by row
     FT_G uint8_t *tdesc;                   // right descriptors in overlap order (fisheye)
     FT_G int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;

@@ -90,11 +90,11 @@ __host__ __device__ inline bool search_in_lds(int cells, int nK)
 }
 
 // LDS staging of the wide best match: row offsets, then 16-byte row records.
-__host__ __device__ inline int rows_lds_offset(int rows) { return ((rows + 1) * 4 + 15) / 16 * 16; }
+__host__ __device__ inline int rows_lds_offset(int entries) { return (entries * 4 + 15) / 16 * 16; }
 
-__host__ __device__ inline bool best_in_lds(int rows, int nR)
+__host__ __device__ inline bool best_in_lds(int entries, int nR)
 {
-    return rows_lds_offset(rows) + 16 * nR <= kSearchLds;
+    return rows_lds_offset(entries) + 16 * nR <= kSearchLds;
 }
 
 // Entry l of a per-level table, selected from values loaded for every level
@@ -225,20 +225,31 @@ template <int NT>
 __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
 {
     const int tid = threadIdx.x;
-    const int rows = J.rows, nR = J.R.n;
-    for (int r = tid; r < rows; r += NT) cnt[r] = 0;
+    const int rows = J.rows, nR = J.R.n, nb = J.n_lb * rows;
+    const bool per_level = J.n_lb > 1;
+    for (int r = tid; r < nb; r += NT) cnt[r] = 0;
     for (int j = tid; j < nR; j += NT) J.claimR[j] = 0xFFFFFFFFu;
     __syncthreads();
     for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
         float y[kSortUnroll];
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e) y[e] = J.R.y[min(j0 + e * NT, nR - 1)];
+        int oc[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-            if (j0 + e * NT < nR) atomicAdd(&cnt[row_bin(y[e], rows)], 1);
+        {
+            const int j = min(j0 + e * NT, nR - 1);
+            y[e] = J.R.y[j];
+            oc[e] = J.R.oct[j];
+        }
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+            if (j0 + e * NT < nR) atomicAdd(&cnt[(per_level ? lvl(oc[e]) * rows : 0) + row_bin(y[e], rows)], 1);
     }
     __syncthreads();
-    const int total = wg_exclusive_scan<NT>(cnt, rows, tmp);
-    for (int r = tid; r < rows; r += NT) J.row_start[r] = cnt[r];
-    if (tid == 0) J.row_start[rows] = total;
+    const int total = wg_exclusive_scan<NT>(cnt, nb, tmp);
+    // row_start[lb][r] = first record of (lb, r); row_start[lb][rows] = end of level bin lb
+    for (int e = tid; e < J.n_lb * (rows + 1); e += NT) {
+        const int lb = e / (rows + 1), r = e - lb * (rows + 1);
+        const int bin = lb * rows + r;
+        J.row_start[e] = bin < nb ? cnt[bin] : total;
+    }
     __syncthreads();
     for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
@@ -254,7 +265,7 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
         {
             const int j = j0 + e * NT;
             if (j < nR) {
-                const int pos = atomicAdd(&cnt[row_bin(y[e], rows)], 1);
+                const int pos = atomicAdd(&cnt[(per_level ? lvl(oct[e]) * rows : 0) + row_bin(y[e], rows)], 1);
                 RowRec rec;
                 rec.x = x[e];
                 rec.band = band_rows(J, y[e], oct[e]);
@@ -370,6 +381,19 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
 }
 
 // ------------------------------------- stereo_a (pinhole): row-band best match
+// Level bins of the row index a left keypoint of octave oi scans: the bins of
+// octaves oi - level_window .. oi + level_window (clamped into the table;
+// octaves above the last level share its bin), or the one bin of all levels.
+__device__ __forceinline__ void level_bins(const DevJob &J, int oi, int &lb0, int &lb1)
+{
+    if (J.n_lb == 1) {
+        lb0 = lb1 = 0;
+        return;
+    }
+    lb0 = min(max(oi - J.level_window, 0), kLevels - 1);
+    lb1 = min(max(oi + J.level_window, 0), kLevels - 1);
+}
+
 // G lanes per left keypoint.  The candidates of row r are the right keypoints
 // whose band covers r; their integer rows lie within J.row_reach of r, so the
 // lanes stream the row-sorted records of those bins and test the band exactly.
@@ -389,13 +413,18 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
             const int row = (int)y;
             const int oi = J.L.oct[i];
             const Desc di = load_desc(J.L.desc, i);
-            const int b0 = max(row - J.row_reach, 0);
-            const int b1 = min(row + J.row_reach, J.rows - 1);
-            const int p1 = J.row_start[b1 + 1];
+            int lb0, lb1;
+            level_bins(J, oi, lb0, lb1);
+            for (int lb = lb0; lb <= lb1; ++lb) {
+            const int reach = pick_level(J.lv_reach, lb);
+            const FT_G int32_t *rs = J.row_start + lb * (J.rows + 1);
+            const int b0 = max(row - reach, 0);
+            const int b1 = min(row + reach, J.rows - 1);
+            const int p1 = rs[b1 + 1];
             // kBestUnroll records per step are loaded together (indices
             // clamped into the range, surplus entries masked); then the
-            // row-ordered descriptors of the candidates among them.
-            for (int p0 = J.row_start[b0] + sub; p0 < p1; p0 += kBestUnroll * G) {
+            // descriptors of the candidates among them.
+            for (int p0 = rs[b0] + sub; p0 < p1; p0 += kBestUnroll * G) {
                 RowRec rec[kBestUnroll];
                 bool cand[kBestUnroll];
                 Desc d[kBestUnroll];
@@ -418,6 +447,7 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
                         }
                     }
                 }
+            }
             }
         }
     }
@@ -447,15 +477,20 @@ __device__ __forceinline__ void best_scan(const DevJob &J, const int *rs, const 
                                           float minU, float maxU, const Desc &di, int sub, uint32_t &best,
                                           float &bx)
 {
-    const int b0 = max(row - J.row_reach, 0);
-    const int b1 = min(row + J.row_reach, J.rows - 1);
-    const int p0 = rs[b0], p1 = rs[b1 + 1];
+    int lb0, lb1;
+    level_bins(J, oi, lb0, lb1);
     int done = 0;
     for (;;) {
         int n = 0, seen = 0;
         int cp[kCandBatch];
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cp[e] = 0;
-        for (int p = p0 + sub; p < p1; p += G) {
+        for (int lb = lb0; lb <= lb1; ++lb) {
+        const int reach = pick_level(J.lv_reach, lb);
+        const int *rsl = rs + lb * (J.rows + 1);
+        const int b0 = max(row - reach, 0);
+        const int b1 = min(row + reach, J.rows - 1);
+        const int p1 = rsl[b1 + 1];
+        for (int p = rsl[b0] + sub; p < p1; p += G) {
             const RowRec rec = rr[p];
             const int lo = (int)(rec.band & 0xFFFFu), hi = (int)(rec.band >> 16);
             const int oj = (int)(rec.meta & 0xFFu);
@@ -467,6 +502,7 @@ __device__ __forceinline__ void best_scan(const DevJob &J, const int *rs, const 
                 ++n;
             }
             ++seen;
+        }
         }
         Desc d[kCandBatch];
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
@@ -513,10 +549,11 @@ __device__ __forceinline__ void ph_best_wide(const DevJob &J, int tile, unsigned
     const int row = q ? (int)y : 0;
     uint32_t best = 0xFFFFFFFFu;   // Hamming << 16 | right index
     float bx = 0.0f;               // x of that right keypoint (for the refinement)
-    if (best_in_lds(J.rows, J.R.n)) {
+    const int n_rs = J.n_lb * (J.rows + 1);
+    if (best_in_lds(n_rs, J.R.n)) {
         int *srs = reinterpret_cast<int *>(smem);
-        RowRec *srr = reinterpret_cast<RowRec *>(smem + rows_lds_offset(J.rows));
-        for (int r = threadIdx.x; r <= J.rows; r += kSearchWG) srs[r] = J.row_start[r];
+        RowRec *srr = reinterpret_cast<RowRec *>(smem + rows_lds_offset(n_rs));
+        for (int r = threadIdx.x; r < n_rs; r += kSearchWG) srs[r] = J.row_start[r];
         for (int p = threadIdx.x; p < J.R.n; p += kSearchWG) srr[p] = J.rrec[p];
         __syncthreads();
         if (q) best_scan<G>(J, srs, srr, row, oi, minU, maxU, di, sub, best, bx);

@@ -478,3 +478,29 @@ def test_concurrent_batches_on_streams_match(ft):
             for d, w in zip(c, ref):
                 bit_equal(d.results(), w)
     ctx4.close()
+
+
+@pytest.mark.parametrize("level_window", [0, 2, 7])
+def test_level_windows(ft, ctx, level_window):
+    """The row index is binned per pyramid level and a left keypoint scans only
+    the level bins of its window: every window width gives the oracle's
+    matches, single-frame and batched."""
+    f = synth.pinhole_frame_1200()[0]
+    f["stereo_params"] = dict(f["stereo_params"], level_window=level_window)
+    say("level window", level_window)
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, ctx, f), want)
+    compare_frame(run_device(ft, ctx, f, batch=True), want)
+
+
+def test_tall_row_index_single_level_bin(ft):
+    """More rows than the per-level (level, row) histogram holds: the row index
+    falls back to one bin for every level and still gives the oracle's matches."""
+    tall = ft.Context(ft.default_limits(max_batch_frames=4, max_map_points=65536, max_rows=2048))
+    f = synth.pinhole_frame_1200()[0]
+    f["stereo_cam"] = dict(f["stereo_cam"], rows=1100)
+    say("tall row index")
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, tall, f), want)
+    compare_frame(run_device(ft, tall, f, batch=True), want)
+    tall.close()
