@@ -338,7 +338,7 @@ class Context:
         return m.value
 
     def ft_set_shapes(self, best_lanes: int, search_lanes: int, search_block: int = 256,
-                      best_block: int = 256, aux_block: int = 256):
+                      best_block: int = 256, aux_block: int = 1024):
         sh = ft_shapes(best_lanes, search_lanes, search_block, best_block, aux_block)
         self._check(self.lib.ft_set_shapes(self.h, ct.byref(sh)), "ft_set_shapes")
 
