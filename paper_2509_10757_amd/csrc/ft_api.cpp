@@ -180,8 +180,8 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     s.xyz = b.take<float>(base, 3 * kp);
     s.claimR = b.take<uint32_t>(base, kp);
     for (int v = 0; v < 2; ++v) {
-        s.view[v].cell_off = b.take<int32_t>(base, (size_t)L.max_grid_cells + 1);
-        s.view[v].crec = b.take<CellRec>(base, kp);
+        s.view[v].cell_off = b.take<int32_t>(base, (size_t)kMaxCells + 1);
+        s.view[v].crec = b.take<CellRec>(base, (size_t)kMaxCellRep * kp);
         s.view[v].mp_k = b.take<int32_t>(base, mp);
         s.view[v].mp_h = b.take<int32_t>(base, mp);
         s.view[v].claim = b.take<uint32_t>(base, kp);
@@ -429,6 +429,27 @@ void fill_search_common(DevJob &J, const ft_map_points *map, const ft_search_par
     J.same_level_only = p->ratio_same_level_only;
 }
 
+// Grid of a view's keypoint index.  When the level window spans at most
+// kMaxCellRep octaves, the index holds one bin per predicted level with only
+// the octaves that level's map points may match (a keypoint is copied into at
+// most kMaxCellRep bins), and the caller's cells are merged by the smallest
+// factor that fits kLevels bins into kMaxCells; otherwise it is the caller's
+// grid with one bin.  The index only accelerates the search, which scans every
+// cell that can hold a candidate, so the grid never changes a match.
+void index_grid(const DevJob &J, int n, const ft_grid *grid, DevView &V)
+{
+    const int64_t rep = (int64_t)J.lv_lo + J.lv_hi + 1;
+    V.n_pb = 1;
+    V.cols = grid->cols;
+    V.rows = grid->rows;
+    if (rep > kMaxCellRep || rep * n > kMaxKp) return;
+    int f = 1;
+    while ((int64_t)kLevels * ((grid->cols + f - 1) / f) * ((grid->rows + f - 1) / f) > kMaxCells) ++f;
+    V.n_pb = kLevels;
+    V.cols = (grid->cols + f - 1) / f;
+    V.rows = (grid->rows + f - 1) / f;
+}
+
 ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_search_camera *cam,
                      const ft_keypoints *kps, const float *u_right, const uint8_t *pre,
                      const ft_grid *grid, const ft_search_out *o, const Slot &slot)
@@ -450,16 +471,15 @@ ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_searc
     if (u_right && !aligned(u_right, 4)) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "misaligned u_right");
     DevView &V = J.view[v];
     V.model = cam->model;
-    V.cols = grid->cols;
-    V.rows = grid->rows;
+    index_grid(J, kps->n, grid, V);
     V.fx = cam->fx; V.fy = cam->fy; V.cx = cam->cx; V.cy = cam->cy; V.bf = cam->bf;
     for (int i = 0; i < 4; ++i) V.k[i] = cam->k[i];
     memcpy(V.R, cam->R, sizeof V.R);
     memcpy(V.t, cam->t, sizeof V.t);
     memcpy(V.O, cam->O, sizeof V.O);
     V.min_x = cam->min_x; V.max_x = cam->max_x; V.min_y = cam->min_y; V.max_y = cam->max_y;
-    V.inv_cw = (float)grid->cols / (cam->max_x - cam->min_x);
-    V.inv_ch = (float)grid->rows / (cam->max_y - cam->min_y);
+    V.inv_cw = (float)V.cols / (cam->max_x - cam->min_x);
+    V.inv_ch = (float)V.rows / (cam->max_y - cam->min_y);
     V.side = side;
     V.preassigned = pre;
     V.u_right = u_right;

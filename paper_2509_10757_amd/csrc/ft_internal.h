@@ -15,6 +15,7 @@ constexpr int kWG = 256;              // every kernel runs 256-thread workgroups
 constexpr int kMaxRows = 4096;
 constexpr int kMaxCells = 8192;
 constexpr int kMaxKp = 65535;
+constexpr int kMaxCellRep = 3;       // copies of a keypoint in a level-binned cell index (level window <= 3 octaves)
 constexpr int kMaxMap = (1 << 23) - 1;
 constexpr int kKnnQueriesPerWG = 32;  // fisheye all-pairs: queries per 256-thread subgroup (16-row MFMA blocks)
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
@@ -74,20 +75,22 @@ struct DevKps {
 
 struct DevView {
     int32_t model;
-    int32_t cols, rows;
+    int32_t cols, rows;              // cells of the keypoint index (the caller's grid, coarser when binned)
     float fx, fy, cx, cy, bf;
     float k[4];
     float R[9], t[3], O[3];
     float min_x, max_x, min_y, max_y;
     float inv_cw, inv_ch;            // cols/(max_x-min_x), rows/(max_y-min_y)
+    int32_t n_pb;                    // level bins of the cell index: kLevels (bin p holds the
+                                     // octaves a map point predicted at level p may match) or 1
     int32_t side;                    // keypoints of the left (0) or right (1) image
     const FT_G uint8_t *preassigned;      // nullable
     const FT_G float *u_right;            // nullable
     const FT_G uint8_t *kdesc;            // descriptors of the view's keypoints
     FT_G int32_t *mp_match, *mp_dist, *kp_match, *n_matches;
     // workspace
-    FT_G int32_t *cell_off;
-    FT_G CellRec *crec;
+    FT_G int32_t *cell_off;          // [n_pb][rows][cols] + 1 record offsets
+    FT_G CellRec *crec;              // records sorted by (level bin, cell)
     FT_G int32_t *mp_k, *mp_h;
     FT_G uint32_t *claim;
 };

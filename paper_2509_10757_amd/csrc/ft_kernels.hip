@@ -321,36 +321,58 @@ __device__ __forceinline__ void ph_overlap(const DevJob &J, int *wsum)
 }
 
 // ------------------------------------------------ setup: keypoint grid
+// Level bins of the cell index that hold a keypoint of octave o: the bins p
+// whose octave window p - lv_lo .. p + lv_hi contains o, i.e. the predicted
+// levels of the map points that may match it; one bin when the index is not
+// binned.
+__device__ __forceinline__ void cell_bins(const DevView &V, int o, int lv_lo, int lv_hi, int &p0, int &p1)
+{
+    if (V.n_pb == 1) {
+        p0 = p1 = 0;
+        return;
+    }
+    p0 = max(o - lv_hi, 0);
+    p1 = min(o + lv_lo, kLevels - 1);
+}
+
+// Counting sort of the view's keypoints by (level bin, row, column) into
+// 16-byte records; a keypoint is copied into every bin that holds its octave.
 template <int NT>
-__device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, int *cnt, int *tmp)
+__device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, int lv_lo, int lv_hi, int *cnt,
+                                            int *tmp)
 {
     const int tid = threadIdx.x;
     const int cells = V.cols * V.rows;
-    for (int c = tid; c < cells; c += NT) cnt[c] = 0;
+    const int nb = V.n_pb * cells;
+    for (int c = tid; c < nb; c += NT) cnt[c] = 0;
     for (int k = tid; k < K.n; k += NT) V.claim[k] = 0xFFFFFFFFu;
     if (tid == 0) *V.n_matches = 0;
     __syncthreads();
     for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
+        int o[kSortUnroll];
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int k = min(k0 + e * NT, K.n - 1);
             x[e] = K.x[k];
             y[e] = K.y[k];
+            o[e] = K.oct[k];
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             if (k0 + e * NT < K.n) {
                 const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
                 const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
-                atomicAdd(&cnt[cy * V.cols + cx], 1);
+                int p0, p1;
+                cell_bins(V, o[e], lv_lo, lv_hi, p0, p1);
+                for (int p = p0; p <= p1; ++p) atomicAdd(&cnt[p * cells + cy * V.cols + cx], 1);
             }
         }
     }
     __syncthreads();
-    const int total = wg_exclusive_scan<NT>(cnt, cells, tmp);
-    for (int c = tid; c < cells; c += NT) V.cell_off[c] = cnt[c];
-    if (tid == 0) V.cell_off[cells] = total;
+    const int total = wg_exclusive_scan<NT>(cnt, nb, tmp);
+    for (int c = tid; c < nb; c += NT) V.cell_off[c] = cnt[c];
+    if (tid == 0) V.cell_off[nb] = total;
     __syncthreads();
     for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
@@ -368,13 +390,14 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
             if (k0 + e * NT < K.n) {
                 const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
                 const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
-                const int pos = atomicAdd(&cnt[cy * V.cols + cx], 1);
                 CellRec rec;
                 rec.x = x[e];
                 rec.y = y[e];
                 rec.meta = meta[e];
                 rec.pad = 0;
-                V.crec[pos] = rec;
+                int p0, p1;
+                cell_bins(V, (int)(meta[e] & 0xFFu), lv_lo, lv_hi, p0, p1);
+                for (int p = p0; p <= p1; ++p) V.crec[atomicAdd(&cnt[p * cells + cy * V.cols + cx], 1)] = rec;
             }
         }
     }
@@ -1239,6 +1262,7 @@ struct Query {
     bool gate;          // stereo right-coordinate gate applies
     float u, v, Rm, uR;
     int cx0, cx1, cy0, cy1, plo, phi;
+    int cb;             // first cell offset of the level bin of the predicted level
     Desc dm;
 };
 
@@ -1298,6 +1322,7 @@ __device__ __forceinline__ Query make_query(const DevJob &J, const DevView &V, i
     q.cy1 = cell_coord(v + Rc, V.min_y, V.inv_ch, V.rows);
     q.plo = pred - J.lv_lo;
     q.phi = pred + J.lv_hi;
+    q.cb = (V.n_pb > 1 ? pred : 0) * (V.cols * V.rows);
     return q;
 }
 
@@ -1328,13 +1353,14 @@ template <int G>
 __device__ __forceinline__ Top2<uint64_t> scan_global(const DevView &V, const Query &q, int sub)
 {
     Top2<uint64_t> top = {~0ull, ~0ull};
-    int c0 = V.cell_off[q.cy0 * V.cols + q.cx0];
-    int c1 = V.cell_off[q.cy0 * V.cols + q.cx1 + 1];
+    const FT_G int32_t *off = V.cell_off + q.cb;
+    int c0 = off[q.cy0 * V.cols + q.cx0];
+    int c1 = off[q.cy0 * V.cols + q.cx1 + 1];
     for (int cy = q.cy0; cy <= q.cy1; ++cy) {
         int n0 = 0, n1 = 0;
         if (cy < q.cy1) {
-            n0 = V.cell_off[(cy + 1) * V.cols + q.cx0];
-            n1 = V.cell_off[(cy + 1) * V.cols + q.cx1 + 1];
+            n0 = off[(cy + 1) * V.cols + q.cx0];
+            n1 = off[(cy + 1) * V.cols + q.cx1 + 1];
         }
         for (int p0 = c0 + sub; p0 < c1; p0 += kSearchUnroll * G) {
             CellRec rec[kSearchUnroll];
@@ -1447,6 +1473,7 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
     if (m < J.nM) q = make_query(J, V, m);
     const int cx0 = q.vis ? q.cx0 : 0, cx1 = q.vis ? q.cx1 : 0;
     const int cy0 = q.vis ? q.cy0 : 0, cy1 = q.vis ? q.cy1 : -1;
+    const FT_G int32_t *off = V.cell_off + (q.vis ? q.cb : 0);
     const int lv = q.vis ? ((q.plo + 16) | ((q.phi + 16) << 8)) : (16 | (15 << 8));
     qp[lane] = make_float4(q.u, q.v, q.vis ? q.Rm : 0.0f, __int_as_float(lv));
     quR[lane] = q.vis ? q.uR : 0.0f;
@@ -1465,8 +1492,8 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
         {
             const bool in = r0 + e <= cy1;
             const int row = in ? r0 + e : 0;
-            const int a = V.cell_off[row * V.cols + cx0];
-            const int b = V.cell_off[row * V.cols + cx1 + 1];
+            const int a = off[row * V.cols + cx0];
+            const int b = off[row * V.cols + cx1 + 1];
             const int n = in ? b - a : 0;
             sg[e] = (uint32_t)a | ((uint32_t)n << 16);
             mine += n;
@@ -1627,7 +1654,7 @@ __device__ __forceinline__ Top2<uint64_t> scan_lds(const DevView &V, const Query
         int cp[kCandBatch];   // record positions (their meta is re-read from LDS)
         _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cp[e] = 0;
         for (int cy = q.cy0; cy <= q.cy1; ++cy) {
-            const int a = soff[cy * V.cols + q.cx0], b = soff[cy * V.cols + q.cx1 + 1];
+            const int a = soff[q.cb + cy * V.cols + q.cx0], b = soff[q.cb + cy * V.cols + q.cx1 + 1];
             for (int p = a; p < b; ++p) {
                 const LRec r = srec[p];
                 if (!in_window(q, r.x, r.y, r.meta) || gate_rejects(q, r.ur)) continue;
@@ -1656,18 +1683,19 @@ __device__ __forceinline__ void ph_search_wide(const DevJob &J, int tile, unsign
     const int v = tile / tpv;
     if (v >= J.n_views) return;
     const DevView &V = J.view[v];
-    const int nK = view_kp(J, v);
-    const int cells = V.cols * V.rows;
+    const int cells = V.n_pb * V.cols * V.rows;   // cell offsets of every level bin
+    const int rep = V.n_pb > 1 ? J.lv_lo + J.lv_hi + 1 : 1;
     const int m = (tile - v * tpv) * kSearchWG + (int)threadIdx.x;
     Top2<uint64_t> top = {~0ull, ~0ull};
-    if (search_in_lds(cells, nK)) {
+    if (search_in_lds(cells, rep * view_kp(J, v))) {
         Query q;
         q.vis = false;
         if (m < J.nM) q = make_query(J, V, m);   // its loads overlap the staging below
         int *soff = reinterpret_cast<int *>(smem);
         LRec *srec = reinterpret_cast<LRec *>(smem + lds_rec_offset(cells));
         for (int c = threadIdx.x; c <= cells; c += kSearchWG) soff[c] = V.cell_off[c];
-        for (int p = threadIdx.x; p < nK; p += kSearchWG) {
+        const int nrec = V.cell_off[cells];
+        for (int p = threadIdx.x; p < nrec; p += kSearchWG) {
             const CellRec r = V.crec[p];
             LRec l;
             l.x = r.x;
@@ -1801,7 +1829,7 @@ __device__ __forceinline__ void task_setup(const DevJob &J, int tile, unsigned c
     }
     const int v = tile - (stereo ? 1 : 0);
     const DevView &V = J.view[v];
-    ph_cellsort<NT>(V, V.side ? J.R : J.L, lds, tmp);
+    ph_cellsort<NT>(V, V.side ? J.R : J.L, J.lv_lo, J.lv_hi, lds, tmp);
 }
 
 template <int G>
