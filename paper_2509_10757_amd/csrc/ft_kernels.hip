@@ -1444,7 +1444,7 @@ __device__ __forceinline__ void wave_lds_sync()
 // evenly for the descriptor reads; each map point's best two keys are kept in
 // LDS by 32-bit atomic minima.
 constexpr int kDealRows = 4;    // window rows per lane and chunk
-constexpr int kDealRecs = 6;    // records per lane and round
+constexpr int kDealRecs = 4;    // records per lane and round
 constexpr int kDealFlush = 1;   // candidates per lane and descriptor batch
 constexpr int kDealQp = 0;                                // float4 u, v, Rm, level window [64]
 constexpr int kDealUr = kDealQp + 64 * 16;                // float uR [64]
