@@ -504,3 +504,41 @@ def test_tall_row_index_single_level_bin(ft):
     compare_frame(run_device(ft, tall, f), want)
     compare_frame(run_device(ft, tall, f, batch=True), want)
     tall.close()
+
+
+@pytest.mark.parametrize("name", ["fisheye_frame_1500", "clustered_search_20000"])
+@pytest.mark.parametrize("lo,hi", [(0, 0), (0, 2), (2, 0), (1, 2)])
+def test_search_level_windows(ft, ctx, name, lo, hi):
+    """The search's keypoint index holds one bin per predicted level (with the
+    octaves of that level's window) when the window spans at most three
+    octaves, and one bin for every octave otherwise (1, 2); the fisheye grid is
+    merged 2 x 2 and the clustered 96 x 64 grid 3 x 3.  Every window gives the
+    oracle's matches, single-frame and batched."""
+    f = synth.workload(name)[0]
+    f["search_params"] = dict(f["search_params"], level_lo=lo, level_hi=hi)
+    say("search level window", name, lo, hi)
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, ctx, f), want)
+    compare_frame(run_device(ft, ctx, f, batch=True), want)
+
+
+def test_many_keypoints_single_bin_search_index(ft):
+    """24000 keypoints: three level-bin copies of each would exceed the 16-bit
+    record offsets, so the search index keeps one bin on the caller's grid and
+    still gives the oracle's matches (the keypoints are the clustered frame's
+    3000 repeated eight times, copy r with bit 0 of descriptor byte r flipped,
+    so near and equal-distance ties abound)."""
+    f = synth.clustered_search_20000()[0]
+    n, reps = f["left"]["x"].shape[0], 8
+    f["left"] = {k: np.concatenate([v] * reps) for k, v in f["left"].items()}
+    for r in range(1, reps):
+        f["left"]["desc"][r * n:(r + 1) * n, r] ^= 1
+    for s in f["search"]:
+        s["preassigned"] = np.concatenate([s["preassigned"]] * reps)
+    big = ft.Context(ft.default_limits(max_kp_per_image=n * reps, max_map_points=32768, max_batch_frames=2,
+                                       max_inflight=1))
+    say("many keypoints", n * reps)
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, big, f), want)
+    compare_frame(run_device(ft, big, f, batch=True), want)
+    big.close()
