@@ -218,8 +218,13 @@ typedef struct ft_search_camera {
     float min_x, max_x, min_y, max_y; /* image bounds of a valid projection */
 } ft_search_camera;
 
+/* Keypoint grid over the image bounds (floor + clamp cell placement).  It only
+ * accelerates the search: the matches are those of a scan over every keypoint.
+ * With a level window of at most three octaves the library indexes keypoints
+ * per predicted level on a coarser grid of its own (cells merged until eight
+ * level bins fit 8192 entries); otherwise it uses this grid as given. */
 typedef struct ft_grid {
-    int32_t cols, rows;        /* keypoint grid over the image bounds */
+    int32_t cols, rows;
 } ft_grid;
 
 typedef struct ft_search_params {
