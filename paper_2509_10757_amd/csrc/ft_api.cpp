@@ -23,7 +23,8 @@ struct Slot {  // workspace of one frame
     int32_t *row_start, *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
     RowRec *rrec;
     uint8_t *tdesc;
-    float *uR, *depth, *xyz, *best_x;
+    float *uR, *depth, *xyz;
+    MatchRec *mrec;
     uint32_t *claimR;
     struct {
         int32_t *cell_off, *mp_k, *mp_h;
@@ -168,7 +169,7 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     s.tdesc = b.take<uint8_t>(base, 32 * kp);
     s.best_j = b.take<int32_t>(base, kp);
     s.best_h = b.take<int32_t>(base, kp);
-    s.best_x = b.take<float>(base, kp);
+    s.mrec = b.take<MatchRec>(base, kp);
     s.h2 = b.take<int32_t>(base, kp);
     s.sad = b.take<int32_t>(base, kp);
     s.flag = b.take<int32_t>(base, kp);
@@ -249,7 +250,7 @@ void bind_stereo_ws(DevJob &J, const Slot &s)
     J.tdesc = s.tdesc;
     J.best_j = s.best_j;
     J.best_h = s.best_h;
-    J.best_x = s.best_x;
+    J.mrec = s.mrec;
     J.h2 = s.h2;
     J.sad = s.sad;
     J.flag = s.flag;

@@ -49,6 +49,15 @@ struct RowRec {
     uint32_t pad;
 };
 
+// An accepted pinhole best match, appended by the best-match phase so that the
+// refinement runs over matches only and reads everything it needs at once.
+struct MatchRec {
+    int32_t i, j, h;   // left keypoint, right keypoint, Hamming distance
+    float bx;          // x of the right keypoint
+    float x, y;        // left keypoint
+    int32_t oct, pad;  // left keypoint octave
+};
+
 // Keypoint sorted by grid cell (search by projection): 16 bytes + descriptor.
 // Pointers the kernels dereference are global-memory pointers in the kernels'
 // device code (FT_KERNELS is defined by the kernel sources), so loads and
@@ -123,7 +132,7 @@ struct DevJob {
     FT_G RowRec *rrec;                     // right keypoints sorted by row
     FT_G uint8_t *tdesc;                   // right descriptors in overlap order (fisheye)
     FT_G int32_t *best_j, *best_h, *h2, *sad, *flag, *qlist, *tlist, *counts;
-    FT_G float *best_x;                    // pinhole: x of the best right keypoint
+    FT_G MatchRec *mrec;                   // pinhole: accepted best matches, counts[2] of them
     FT_G float *uR, *depth, *xyz;
     FT_G uint32_t *claimR;
     // search by projection

@@ -229,6 +229,8 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
     const bool per_level = J.n_lb > 1;
     for (int r = tid; r < nb; r += NT) cnt[r] = 0;
     for (int j = tid; j < nR; j += NT) J.claimR[j] = 0xFFFFFFFFu;
+    for (int i = tid; i < J.L.n; i += NT) J.flag[i] = 0;   // the refinement flags matches only
+    if (tid == 0) J.counts[2] = 0;                          // length of the match list
     __syncthreads();
     for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
         float y[kSortUnroll];
@@ -420,6 +422,35 @@ __device__ __forceinline__ void level_bins(const DevJob &J, int oi, int &lb0, in
 // G lanes per left keypoint.  The candidates of row r are the right keypoints
 // whose band covers r; their integer rows lie within J.row_reach of r, so the
 // lanes stream the row-sorted records of those bins and test the band exactly.
+// Appends the wave's accepted pinhole matches to the frame's match list, one
+// counter update per wave; the list order does not matter (the refinement
+// writes by left keypoint).  Every lane of the wave calls it.
+__device__ __forceinline__ void append_match(const DevJob &J, bool take, const MatchRec &r)
+{
+    const unsigned long long bal = __ballot(take);
+    if (bal == 0ull) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)bal) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&J.counts[2], (int)__popcll(bal));
+    base = __shfl(base, leader);
+    if (take) J.mrec[base + (int)__popcll(bal & ((1ull << lane) - 1ull))] = r;
+}
+
+__device__ __forceinline__ MatchRec match_rec(int i, uint32_t best, float bx, float x, float y, int oi)
+{
+    MatchRec r;
+    r.i = i;
+    r.j = (int)(best & 0xFFFFu);
+    r.h = (int)(best >> 16);
+    r.bx = bx;
+    r.x = x;
+    r.y = y;
+    r.oct = oi;
+    r.pad = 0;
+    return r;
+}
+
 template <int G>
 __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
 {
@@ -427,14 +458,16 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
     const int i = tile * (kWG / G) + threadIdx.x / G;
     uint32_t best = 0xFFFFFFFFu;   // Hamming << 16 | right index
     float bx = 0.0f;               // x of that right keypoint (for the refinement)
+    float x = 0.0f, y = 0.0f;
+    int oi = 0;
     if (i < J.L.n) {
-        const float y = J.L.y[i];
-        const float x = J.L.x[i];
+        y = J.L.y[i];
+        x = J.L.x[i];
+        oi = J.L.oct[i];
         const float minU = x - J.maxD;
         const float maxU = x - 0.0f;
         if (y > -1.0f && y < (float)J.rows && !(maxU < 0.0f)) {
             const int row = (int)y;
-            const int oi = J.L.oct[i];
             const Desc di = load_desc(J.L.desc, i);
             int lb0, lb1;
             level_bins(J, oi, lb0, lb1);
@@ -482,13 +515,13 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
             bx = ox;
         }
     }
+    const int h = (int)(best >> 16);
+    const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
     if (sub == 0 && i < J.L.n) {
-        const int h = (int)(best >> 16);
-        const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
         J.best_j[i] = ok ? (int)(best & 0xFFFFu) : -1;
         J.best_h[i] = ok ? h : -1;
-        J.best_x[i] = bx;
     }
+    append_match(J, sub == 0 && i < J.L.n && ok, match_rec(i, best, bx, x, y, oi));
 }
 
 // Row-band scan of one pinhole left keypoint over staged (LDS) or global row
@@ -591,13 +624,13 @@ __device__ __forceinline__ void ph_best_wide(const DevJob &J, int tile, unsigned
             bx = ox;
         }
     }
+    const int h = (int)(best >> 16);
+    const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
     if (sub == 0 && i < J.L.n) {
-        const int h = (int)(best >> 16);
-        const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
         J.best_j[i] = ok ? (int)(best & 0xFFFFu) : -1;
         J.best_h[i] = ok ? h : -1;
-        J.best_x[i] = bx;
     }
+    append_match(J, sub == 0 && i < J.L.n && ok, match_rec(i, best, bx, x, y, oi));
 }
 
 // ----------------------------- stereo_a (fisheye): all-pairs top-2 on MFMA
@@ -721,33 +754,34 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
 __device__ __forceinline__ void ph_refine_wave(const DevJob &J, int tile, uint8_t *lds)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = tile * kRefinePerWG + wave;
+    const int idx = tile * kRefinePerWG + wave;   // position in the frame's match list
+    const bool has = idx < J.counts[2];
+    const MatchRec mr = J.mrec[min(idx, max(J.L.n - 1, 0))];   // loaded with the list length
+    const int i = mr.i;
     const int w = J.half_win, L = J.half_range;
     const int side = 2 * w + 1, strip = 2 * (L + w) + 1, nS = 2 * L + 1;
     int j = -1, l = 0, su = 0, sv = 0, su0 = 0, Wl = 0, bh = 0;
     float xi = 0.0f, sfl = 0.0f;
     int64_t off = 0;
     bool act = false;
-    if (i < J.L.n) {
-        // everything the match needs is indexed by i: one round of loads
-        j = J.best_j[i];
-        bh = J.best_h[i];
-        const float xj = J.best_x[i];
-        xi = J.L.x[i];
-        const float yi = J.L.y[i];
-        l = lvl(J.L.oct[i]);
-        if (j >= 0) {
-            const float s = pick_level(J.inv_sf, l);
-            sfl = pick_level(J.sf, l);
-            su = (int)roundf(xi * s);
-            sv = (int)roundf(yi * s);
-            su0 = (int)roundf(xj * s);
-            Wl = pick_level(J.lv_w, l);
-            const int Hl = pick_level(J.lv_h, l);
-            off = pick_level(J.lv_off, l);
-            act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
-                  su0 + L + w < Wl;
-        }
+    if (has) {
+        // everything the match needs is in its list record: one round of loads
+        j = mr.j;
+        bh = mr.h;
+        const float xj = mr.bx;
+        xi = mr.x;
+        const float yi = mr.y;
+        l = lvl(mr.oct);
+        const float s = pick_level(J.inv_sf, l);
+        sfl = pick_level(J.sf, l);
+        su = (int)roundf(xi * s);
+        sv = (int)roundf(yi * s);
+        su0 = (int)roundf(xj * s);
+        Wl = pick_level(J.lv_w, l);
+        const int Hl = pick_level(J.lv_h, l);
+        off = pick_level(J.lv_off, l);
+        act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
+              su0 + L + w < Wl;
     }
     uint8_t *P = lds + wave * kRefineLds;          // left patch [side][side]
     uint8_t *S = P + side * side;                  // right strip [side][strip]
@@ -791,7 +825,7 @@ __device__ __forceinline__ void ph_refine_wave(const DevJob &J, int tile, uint8_
     }
     const int a = __shfl(tot, max(kb + L - 1, 0) * parts);
     const int e = __shfl(tot, min(kb + L + 1, nS - 1) * parts);
-    if (lane != 0 || i >= J.L.n) return;
+    if (lane != 0 || !has) return;
     if (!act || kb == -L || kb == L) {
         J.flag[i] = 0;
         return;
@@ -832,31 +866,32 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
     static_assert((side * 12 + side * 24) * 2 <= kRefineQLds, "refine windows");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ql = lane & 15, slot = wave * 4 + (lane >> 4);
-    const int i = tile * kRefineQPerWG + slot;
+    const int idx = tile * kRefineQPerWG + slot;   // position in the frame's match list
+    const bool has = idx < J.counts[2];
+    const MatchRec mr = J.mrec[min(idx, max(J.L.n - 1, 0))];   // loaded with the list length
+    const int i = mr.i;
     int j = -1, l = 0, su = 0, sv = 0, su0 = 0, Wl = 0, bh = 0;
     float xi = 0.0f, sfl = 0.0f;
     int64_t off = 0;
     bool act = false;
-    if (i < J.L.n) {
-        // everything the match needs is indexed by i: one round of loads
-        j = J.best_j[i];
-        bh = J.best_h[i];
-        const float xj = J.best_x[i];
-        xi = J.L.x[i];
-        const float yi = J.L.y[i];
-        l = lvl(J.L.oct[i]);
-        if (j >= 0) {
-            const float s = pick_level(J.inv_sf, l);
-            sfl = pick_level(J.sf, l);
-            su = (int)roundf(xi * s);
-            sv = (int)roundf(yi * s);
-            su0 = (int)roundf(xj * s);
-            Wl = pick_level(J.lv_w, l);
-            const int Hl = pick_level(J.lv_h, l);
-            off = pick_level(J.lv_off, l);
-            act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
-                  su0 + L + w < Wl;
-        }
+    if (has) {
+        // everything the match needs is in its list record: one round of loads
+        j = mr.j;
+        bh = mr.h;
+        const float xj = mr.bx;
+        xi = mr.x;
+        const float yi = mr.y;
+        l = lvl(mr.oct);
+        const float s = pick_level(J.inv_sf, l);
+        sfl = pick_level(J.sf, l);
+        su = (int)roundf(xi * s);
+        sv = (int)roundf(yi * s);
+        su0 = (int)roundf(xj * s);
+        Wl = pick_level(J.lv_w, l);
+        const int Hl = pick_level(J.lv_h, l);
+        off = pick_level(J.lv_off, l);
+        act = su - w >= 0 && su + w < Wl && sv - w >= 0 && sv + w < Hl && su0 - L - w >= 0 &&
+              su0 + L + w < Wl;
     }
     // Windows in LDS as 16-bit values, rows padded to whole dwords: the left
     // patch holds P + 255, the right strip holds S.  For shift k (lane k) the
@@ -914,7 +949,7 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
     const int base = lane & ~15;
     const int a = __shfl(sad, base + max(kb + L - 1, 0));
     const int e = __shfl(sad, base + min(kb + L + 1, nS - 1));
-    if (ql != 0 || i >= J.L.n) return;
+    if (ql != 0 || !has) return;
     if (!act || kb == -L || kb == L) {
         J.flag[i] = 0;
         return;
