@@ -644,11 +644,14 @@ __device__ __forceinline__ void ph_best_wide(const DevJob &J, int tile, unsigned
 // NT threads = NT / 256 independent subgroups of four waves; subgroup k of
 // tile t owns queries (t * NT / 256 + k) * 16 ... + 15.  `part` holds 128
 // words per subgroup.  Every thread reaches both barriers.
-// Top-2 of 32-bit keys by value: the new best is min(a, key), the new second
-// min(b, max(a, key)) (keys are distinct: they carry the target index).
+// Top-2 of 32-bit keys by value (keys are distinct: they carry the target
+// index).  a <= b always holds, so the new second is the median of a, b and
+// the key, one v_med3_u32; the new best is min(a, key).
 __device__ __forceinline__ void top2_push(uint32_t &a, uint32_t &b, uint32_t key)
 {
-    b = min(b, max(a, key));
+    uint32_t m;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(m) : "v"(a), "v"(b), "v"(key));
+    b = m;
     a = min(a, key);
 }
 
@@ -689,7 +692,13 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
         uint2 w = make_uint2(0, 0);
         if (qa < nQ) w = *reinterpret_cast<const uint2 *>(J.L.desc + 32 * (size_t)J.qlist[qa] + 8 * g);
         _Pragma("unroll") for (int s = 0; s < 4; ++s)
-            A[qb][s] = qa < nQ ? expand16(tab, s < 2 ? w.x : w.y, s & 1) : v4i{0, 0, 0, 0};
+        {
+            // the queries' signs are flipped (x ^ 0xFE negates a +-1 byte), so
+            // the MFMA accumulates -dot
+            const v4i e = expand16(tab, s < 2 ? w.x : w.y, s & 1);
+            const int f = (int)0xFEFEFEFE;
+            A[qb][s] = qa < nQ ? v4i{e[0] ^ f, e[1] ^ f, e[2] ^ f, e[3] ^ f} : v4i{0, 0, 0, 0};
+        }
     }
     uint32_t ta[QB][4], tb[QB][4];
     _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
@@ -708,8 +717,9 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
         v4i B[4];
         _Pragma("unroll") for (int s = 0; s < 4; ++s)
             B[s] = tv ? expand16(tab, s < 2 ? w.x : w.y, s & 1) : v4i{0, 0, 0, 0};
-        // acc[r] = dot(query row 4g + r of block qb, target column c); the key
-        // (256 - dot) << 15 | index = Hamming << 16 | index (dot = 256 - 2 H)
+        // acc[r] = -dot(query row 4g + r of block qb, target column c); the key
+        // (256 - dot) << 15 | index = Hamming << 16 | index (dot = 256 - 2 H) is
+        // kbase + (acc << 15), one shift-add
         const uint32_t kbase = (256u << 15) | (uint32_t)tj;
         _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
         {
@@ -717,7 +727,7 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
             _Pragma("unroll") for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qb][s], B[s], acc, 0, 0, 0);
             if (tv) {
                 _Pragma("unroll") for (int r = 0; r < 4; ++r)
-                    top2_push(ta[qb][r], tb[qb][r], kbase - ((uint32_t)acc[r] << 15));
+                    top2_push(ta[qb][r], tb[qb][r], kbase + ((uint32_t)acc[r] << 15));
             }
         }
     }
