@@ -542,3 +542,21 @@ def test_many_keypoints_single_bin_search_index(ft):
     compare_frame(run_device(ft, big, f), want)
     compare_frame(run_device(ft, big, f, batch=True), want)
     big.close()
+
+
+@pytest.mark.parametrize("th_orb", [0, 1, 20])
+def test_refinement_list_lengths(ft, ctx, th_orb):
+    """The refinement runs over the list of accepted best matches: an empty
+    list (threshold 0 accepts nothing), a short one and a longer one give the
+    oracle's outputs, single-frame and in a batch beside an unchanged frame."""
+    f = synth.pinhole_frame_1200()[0]
+    f["stereo_params"] = dict(f["stereo_params"], th_orb=th_orb)
+    say("refinement list, th_orb", th_orb)
+    want = oracle.run_frame(f)
+    compare_frame(run_device(ft, ctx, f), want)
+    g = synth.pinhole_frame_1200()[0]
+    dfs = [ft.DeviceFrame(f, "cuda"), ft.DeviceFrame(g, "cuda")]
+    ctx.ft_batch_wait(ctx.ft_batch_submit([d.job() for d in dfs]))
+    torch.cuda.synchronize()
+    compare_frame(dfs[0].results(), want)
+    compare_frame(dfs[1].results(), oracle.run_frame(g))
