@@ -152,7 +152,8 @@ def stereo_fisheye(frame) -> dict:
         ct.c_int(nR), _p(xR), _p(yR), _p(oR), _p(dR),
         _p(kbl), _p(kbr), _p(R), _p(t), _p(ovl), _p(ovr), _p(s2), _p(ip), _p(dp),
         _p(out["right_idx"]), _p(out["dist"]), _p(out["depth"]), _p(out["xyz"]), _p(out["h2"]), _p(stats))
-    out["stats"] = dict(zip(["Q", "T", "ratio_ok", "tri_ok", "matches"], stats[:5].tolist()))
+    out["stats"] = dict(zip(["Q", "T", "ratio_ok", "tri_ok", "matches", "rej_parallax", "rej_depth",
+                             "rej_reproj"], stats.tolist()))
     out["n_matches"] = int(stats[4])
     return out
 
@@ -194,7 +195,8 @@ def search_local_points(frame, view: int = 0, u_right=None) -> dict:
         ct.c_int(int(cam["model"])), _p(camv), _p(R), _p(t), _p(O), _p(bounds), _p(sf),
         ct.c_int(len(sf)), _p(fp), _p(ip),
         _p(out["mp_match"]), _p(out["mp_dist"]), _p(out["kp_match"]), _p(stats))
-    out["stats"] = dict(zip(["visible", "candidates", "accepted", "matches"], stats[:4].tolist()))
+    out["stats"] = dict(zip(["visible", "candidates", "accepted", "matches", "rej_frame", "rej_near",
+                             "rej_far", "rej_angle"], stats.tolist()))
     out["n_matches"] = int(stats[3])
     return out
 

@@ -338,6 +338,7 @@ void oracle_stereo_fisheye(
     const int ratio_num = ip[0], ratio_den = ip[1], iters = ip[2];
     const double cos_max = dp[0], chi2 = dp[1], max_theta = dp[2], tol = dp[3];
     int64_t nQ = 0, nT = 0, n_ratio = 0, n_tri = 0;
+    int64_t n_par = 0, n_dep = 0, n_rep = 0;   /* rejections by the parallax, depth and reprojection tests */
     int32_t *cj = (int32_t *)malloc(sizeof(int32_t) * (nL > 0 ? nL : 1));
     int32_t *ch = (int32_t *)malloc(sizeof(int32_t) * (nL > 0 ? nL : 1));
     float *cdep = (float *)malloc(sizeof(float) * (nL > 0 ? nL : 1));
@@ -372,10 +373,10 @@ void oracle_stereo_fisheye(
         const double n1 = sqrt((r1[0] * r1[0] + r1[1] * r1[1]) + r1[2] * r1[2]);
         const double n2 = sqrt((r21[0] * r21[0] + r21[1] * r21[1]) + r21[2] * r21[2]);
         const double cosp = ((r1[0] * r21[0] + r1[1] * r21[1]) + r1[2] * r21[2]) / (n1 * n2);
-        if (!(cosp <= cos_max)) continue;
+        if (!(cosp <= cos_max)) { ++n_par; continue; }
         double X[3];
         if (!oracle_triangulate(r1, r2, R_lr, t_lr, X)) continue;
-        if (!(X[2] > 0.0)) continue;
+        if (!(X[2] > 0.0)) { ++n_dep; continue; }
         double X2[3];
         for (int r = 0; r < 3; ++r) {
             /* right-camera coordinates: R_lr^T (X - t_lr) */
@@ -383,14 +384,15 @@ void oracle_stereo_fisheye(
                      (double)R_lr[3 + r] * (X[1] - (double)t_lr[1])) +
                     (double)R_lr[6 + r] * (X[2] - (double)t_lr[2]);
         }
-        if (!(X2[2] > 0.0)) continue;
+        if (!(X2[2] > 0.0)) { ++n_dep; continue; }
+        /* reprojection error in each view against that keypoint's own octave */
         double uv[2];
         oracle_kb_project(kbL, X, uv);
         double ex = uv[0] - (double)xL[i], ey = uv[1] - (double)yL[i];
-        if (!(ex * ex + ey * ey <= chi2 * (double)sigma2[oL[i]])) continue;
+        if (!(ex * ex + ey * ey <= chi2 * (double)sigma2[oL[i]])) { ++n_rep; continue; }
         oracle_kb_project(kbR, X2, uv);
         ex = uv[0] - (double)xR[j1]; ey = uv[1] - (double)yR[j1];
-        if (!(ex * ex + ey * ey <= chi2 * (double)sigma2[oR[j1]])) continue;
+        if (!(ex * ex + ey * ey <= chi2 * (double)sigma2[oR[j1]])) { ++n_rep; continue; }
         ++n_tri;
         cj[i] = j1; ch[i] = h1; cdep[i] = (float)X[2];
         cx3[3 * i] = (float)X[0]; cx3[3 * i + 1] = (float)X[1]; cx3[3 * i + 2] = (float)X[2];
@@ -405,7 +407,10 @@ void oracle_stereo_fisheye(
         out_xyz[3 * i + 2] = cx3[3 * i + 2];
         ++n_final;
     }
-    if (stats) { stats[0] = nQ; stats[1] = nT; stats[2] = n_ratio; stats[3] = n_tri; stats[4] = n_final; }
+    if (stats) {
+        stats[0] = nQ; stats[1] = nT; stats[2] = n_ratio; stats[3] = n_tri; stats[4] = n_final;
+        stats[5] = n_par; stats[6] = n_dep; stats[7] = n_rep;
+    }
     free(cj); free(ch); free(cdep); free(cx3); free(alive);
 }
 
@@ -432,6 +437,7 @@ void oracle_search_local_points(
     const int ratio_num = ip[3], ratio_den = ip[4], same_level_only = ip[5];
     const float fx = cam[0], fy = cam[1], cx = cam[2], cy = cam[3], bf = cam[8];
     int64_t n_vis = 0, n_cand = 0, n_acc = 0;
+    int64_t n_out = 0, n_near = 0, n_far = 0, n_angle = 0;   /* rejections by each visibility gate */
     int32_t *cand_k = (int32_t *)malloc(sizeof(int32_t) * (nM > 0 ? nM : 1));
     int32_t *cand_h = (int32_t *)malloc(sizeof(int32_t) * (nM > 0 ? nM : 1));
     uint8_t *alive = (uint8_t *)calloc(nM > 0 ? nM : 1, 1);
@@ -443,7 +449,7 @@ void oracle_search_local_points(
         const float xc = ((R[0] * X + R[1] * Y) + R[2] * Z) + t[0];
         const float yc = ((R[3] * X + R[4] * Y) + R[5] * Z) + t[1];
         const float zc = ((R[6] * X + R[7] * Y) + R[8] * Z) + t[2];
-        if (!(zc > 0.0f)) continue;
+        if (!(zc > 0.0f)) { ++n_out; continue; }
         float u, v;
         if (model == 0) {
             u = ((fx * xc) / zc) + cx;
@@ -454,13 +460,16 @@ void oracle_search_local_points(
             u = (float)uv[0];
             v = (float)uv[1];
         }
-        if (!(u >= bounds[0] && u <= bounds[1] && v >= bounds[2] && v <= bounds[3])) continue;
+        if (!(u >= bounds[0] && u <= bounds[1] && v >= bounds[2] && v <= bounds[3])) { ++n_out; continue; }
+        /* scale invariance: the point must be seen from inside its distance range */
         const float pox = X - O[0], poy = Y - O[1], poz = Z - O[2];
         const float dist = sqrtf((pox * pox + poy * poy) + poz * poz);
         const float lo = dist_lo * dmin[m], hi = dist_hi * dmax[m];
-        if (!(dist >= lo && dist <= hi)) continue;
+        if (!(dist >= lo)) { ++n_near; continue; }
+        if (!(dist <= hi)) { ++n_far; continue; }
+        /* viewing angle: the ray from the camera must be close to the mean viewing direction */
         const float vcos = ((pox * normal[3 * m] + poy * normal[3 * m + 1]) + poz * normal[3 * m + 2]) / dist;
-        if (!(vcos >= cos_lim)) continue;
+        if (!(vcos >= cos_lim)) { ++n_angle; continue; }
         const int pred = oracle_predict_level(dmax[m] / dist, sf, n_levels);
         ++n_vis;
         const float rbase = (vcos > cos_narrow ? r_narrow : r_wide) * th;
@@ -495,6 +504,9 @@ void oracle_search_local_points(
         mp_match[m] = cand_k[m]; mp_dist[m] = cand_h[m]; kp_match[cand_k[m]] = m;
         ++n_match;
     }
-    if (stats) { stats[0] = n_vis; stats[1] = n_cand; stats[2] = n_acc; stats[3] = n_match; }
+    if (stats) {
+        stats[0] = n_vis; stats[1] = n_cand; stats[2] = n_acc; stats[3] = n_match;
+        stats[4] = n_out; stats[5] = n_near; stats[6] = n_far; stats[7] = n_angle;
+    }
     free(cand_k); free(cand_h); free(alive);
 }

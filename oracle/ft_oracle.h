@@ -50,7 +50,9 @@ void oracle_stereo_pinhole(
 /* Fisheye (Kannala-Brandt) stereo.  kb = {fx, fy, cx, cy, k1, k2, k3, k4}.
  * ip = {ratio_num, ratio_den, newton_iters}; dp = {cos_parallax_max, chi2,
  * max_theta_rad, newton_tol}.  out_h2 (nullable): second-nearest distance of
- * every overlap query (-1 elsewhere).  stats: |Q|, |T|, ratio ok, tri ok, final. */
+ * every overlap query (-1 elsewhere).  stats: |Q|, |T|, ratio ok, tri ok, final,
+ * then the queries past the ratio test rejected by the parallax test, by a
+ * depth <= 0 in either camera, and by the reprojection test of either view. */
 void oracle_stereo_fisheye(
     int nL, const float *xL, const float *yL, const uint8_t *oL, const uint8_t *dL,
     int nR, const float *xR, const float *yR, const uint8_t *oR, const uint8_t *dR,
@@ -64,7 +66,10 @@ void oracle_stereo_fisheye(
  * cam = {fx, fy, cx, cy, k1, k2, k3, k4, bf}; model 0 = pinhole, 1 = KB.
  * fp = {th, view_cos_limit, view_cos_narrow, r_narrow, r_wide, dist_lo, dist_hi}
  * ip = {level_lo, level_hi, th_high, ratio_num, ratio_den, same_level_only}
- * stats: visible, candidates, accepted before conflict, matches. */
+ * stats: visible, candidates, accepted before conflict, matches, then the
+ * map points rejected by each visibility test in order: behind the camera or
+ * outside the image bounds, nearer than dist_lo*dmin, farther than
+ * dist_hi*dmax, viewing cosine below the limit. */
 void oracle_search_local_points(
     int nM, const float *pos, const float *normal, const float *dmin, const float *dmax,
     const uint8_t *mdesc,

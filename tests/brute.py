@@ -175,9 +175,11 @@ def search_pinhole(frame, view=0, u_right=None):
         dist = np.sqrt((pox * pox + poy * poy) + poz * poz)
         vcos = ((pox * mp["normal"][:, 0] + poy * mp["normal"][:, 1]) + poz * mp["normal"][:, 2]) / dist
         ratio = mp["dmax"] / dist
-    vis = ((zc > 0) & (u >= b[0]) & (u <= b[1]) & (v >= b[2]) & (v <= b[3]) &
-           (dist >= f32(sp["dist_lo"]) * mp["dmin"]) & (dist <= f32(sp["dist_hi"]) * mp["dmax"]) &
-           (vcos >= f32(sp["view_cos_limit"])))
+    in_frame = (zc > 0) & (u >= b[0]) & (u <= b[1]) & (v >= b[2]) & (v <= b[3])
+    near_ok = dist >= f32(sp["dist_lo"]) * mp["dmin"]
+    far_ok = dist <= f32(sp["dist_hi"]) * mp["dmax"]
+    angle_ok = vcos >= f32(sp["view_cos_limit"])
+    vis = in_frame & near_ok & far_ok & angle_ok
     reach = sf[None, :] >= ratio[:, None]
     pred = np.where(reach.any(1), np.argmax(reach, axis=1), len(sf) - 1)
     rbase = np.where(vcos > f32(sp["view_cos_narrow"]), f32(sp["r_narrow"]), f32(sp["r_wide"])) * f32(sp["th"])
@@ -209,4 +211,7 @@ def search_pinhole(frame, view=0, u_right=None):
     kp_match[k1[alive]] = np.nonzero(alive)[0]
     return {"mp_match": mp_match, "mp_dist": np.where(alive, H1, -1), "kp_match": kp_match,
             "stats": {"visible": int(vis.sum()), "candidates": int(C.sum()),
-                      "accepted": int(acc.sum()), "matches": int(alive.sum())}}
+                      "accepted": int(acc.sum()), "matches": int(alive.sum()),
+                      "rej_frame": int((~in_frame).sum()), "rej_near": int((in_frame & ~near_ok).sum()),
+                      "rej_far": int((in_frame & near_ok & ~far_ok).sum()),
+                      "rej_angle": int((in_frame & near_ok & far_ok & ~angle_ok).sum())}}

@@ -43,6 +43,22 @@ MUTANTS = {
     "search_window_y": ("fabsf(ky[k] - v) < Rm", "fabsf(ky[k] - u) < Rm"),
     "search_dist_hi": ("dist <= hi", "dist <= lo"),
     "predict_level_off_by_one": ("if (sf[l] >= ratio) return l;", "if (sf[l] >= ratio) return l + 1 < n_levels ? l + 1 : l;"),
+    # visibility tests of the search (each must reject its own cases)
+    "search_dist_lo_dropped": ("if (!(dist >= lo)) { ++n_near; continue; }", ""),
+    "search_dist_lo_strict": ("if (!(dist >= lo))", "if (!(dist > lo))"),
+    "search_dist_hi_strict": ("if (!(dist <= hi))", "if (!(dist < hi))"),
+    "search_viewcos_dropped": ("if (!(vcos >= cos_lim)) { ++n_angle; continue; }", ""),
+    "search_viewcos_strict": ("if (!(vcos >= cos_lim))", "if (!(vcos > cos_lim))"),
+    "search_viewcos_no_divide": (") / dist;\n        if (!(vcos", ");\n        if (!(vcos"),
+    # triangulation check of fisheye pairs
+    "fish_parallax_dropped": ("if (!(cosp <= cos_max)) { ++n_par; continue; }", ""),
+    "fish_left_depth_dropped": ("if (!(X[2] > 0.0)) { ++n_dep; continue; }", ""),
+    "fish_right_depth_dropped": ("if (!(X2[2] > 0.0)) { ++n_dep; continue; }", ""),
+    "fish_right_reproj_left_level": ("chi2 * (double)sigma2[oR[j1]]", "chi2 * (double)sigma2[oL[i]]"),
+    "fish_right_reproj_half_bound": ("chi2 * (double)sigma2[oR[j1]]", "0.5 * chi2 * (double)sigma2[oR[j1]]"),
+    "fish_left_reproj_right_level": ("chi2 * (double)sigma2[oL[i]]", "chi2 * (double)sigma2[oR[j1]]"),
+    "fish_right_reproj_dropped": ("if (!(ex * ex + ey * ey <= chi2 * (double)sigma2[oR[j1]])) { ++n_rep; continue; }", ""),
+    "fish_one_target_enough": ("if (nT < 2) continue;", "if (nT < 1) continue;"),
     "conflict_tie": ("int64_t key = ((int64_t)dist[i] << 32) | (int64_t)i;\n        if (key < best",
                      "int64_t key = ((int64_t)dist[i] << 32) | (int64_t)(nQ - i);\n        if (key < best"),
 }
@@ -78,6 +94,13 @@ def _pins(frames):
     tests.append(pins.test_conflict_hand_built_scene)
     tests.append(pins.test_pinhole_distance_threshold_is_strict)
     tests.append(pins.test_search_ratio_applies_only_to_same_level_second)
+    for s in (81, 82):
+        tests.append(lambda s=s: pins.test_search_visibility_gates_equal_bruteforce(s))
+    tests.append(pins.test_search_visibility_boundaries_are_inclusive)
+    tests.append(pins.test_fisheye_parallax_gate_scene)
+    tests.append(pins.test_fisheye_depth_gate_scene)
+    tests.append(pins.test_fisheye_reprojection_gate_scene)
+    tests.append(pins.test_fisheye_needs_two_targets)
 
     def with_frames():
         c1 = (frames[1], oracle.run_frame(frames[1]))

@@ -502,3 +502,183 @@ def test_search_ratio_applies_only_to_same_level_second():
     kp["desc"][a], kp["desc"][b] = kp["desc"][b].copy(), kp["desc"][a].copy()
     out = oracle.search_local_points(f, 0)
     assert out["mp_match"][0] == -1
+
+
+# ------------------------------------------- visibility tests of the search ----
+def _gate_frames(seed):
+    from synth.gates import add_gate_cases
+    out = []
+    for base in (synth.tiny_pinhole(seed, n_kp=100, n_map=220), synth.tiny_clustered(seed)):
+        g, cases = add_gate_cases(base, seed, frac=0.06, n_edge=6)
+        out.append((g, cases))
+    return out
+
+
+@pytest.mark.parametrize("seed", [81, 82])
+def test_search_visibility_gates_equal_bruteforce(seed):
+    """Map points seen too near, too far and from the side, and points on the
+    exact binary32 boundary of each test: the oracle's per-test rejection
+    counts and matches equal the all-pairs brute force, and each test rejects
+    its own cases."""
+    from synth.gates import gate_outcomes
+    for g, cases in _gate_frames(seed):
+        edge = gate_outcomes(g, cases)
+        for name, ok in edge.items():
+            assert ok.all() if name.endswith("_in") else not ok.any(), name
+        st = oracle.stereo_pinhole(g) if g["kind"] == "pinhole" else None
+        for ur in ((None, st["u_right"]) if st else (None,)):
+            got = oracle.search_local_points(g, 0, ur)
+            want = brute.search_pinhole(g, 0, ur)
+            assert got["stats"] == want["stats"]
+            for k in ("mp_match", "mp_dist", "kp_match"):
+                assert (got[k] == want[k]).all(), k
+            s = got["stats"]
+            # every far-off case is rejected by its own test (some may already
+            # fall outside the image); edge cases outside their bound too
+            for name, key in (("near", "rej_near"), ("far", "rej_far"), ("angle", "rej_angle")):
+                assert s[key] >= len(cases[name]) + len(cases[name + "_out"]) - s["rej_frame"]
+                assert s[key] > 0
+
+
+def test_search_visibility_boundaries_are_inclusive():
+    """A map point whose distance equals dist_lo*dmin or dist_hi*dmax exactly,
+    or whose viewing cosine equals the limit exactly, is visible; one binary32
+    step beyond is not (the tests are >= / <= / >=)."""
+    f = synth.tiny_pinhole(83, n_kp=60, n_map=1)
+    cam = f["search"][0]["cam"]
+    cam["R"] = np.eye(3, dtype=np.float32); cam["t"] = np.zeros(3, np.float32)
+    cam["O"] = np.zeros(3, np.float32)
+    mp = f["map"]
+    P = np.array([0.5, -0.25, 4.0], np.float32)
+    mp["pos"][0] = P
+    dist = np.sqrt((P[0] * P[0] + P[1] * P[1]) + P[2] * P[2]).astype(np.float32)
+    ray = P.astype(np.float64) / np.linalg.norm(P.astype(np.float64))
+    mp["normal"][0] = ray.astype(np.float32)
+    sp = f["search_params"]
+    from synth.gates import _first_passing_max, _last_passing_min
+
+    def visible():
+        return oracle.search_local_points(f, 0)["stats"]["visible"] == 1
+    mp["dmax"][0] = np.float32(dist * 2); mp["dmin"][0] = np.float32(dist / 2)
+    assert visible()
+    d = _last_passing_min(dist, np.float32(sp["dist_lo"]))
+    mp["dmin"][0] = d
+    if np.float32(np.float32(sp["dist_lo"]) * d) == dist:
+        assert visible()
+    mp["dmin"][0] = np.nextafter(d, np.float32(np.inf))
+    assert not visible()
+    mp["dmin"][0] = np.float32(dist / 2)
+    d = _first_passing_max(dist, np.float32(sp["dist_hi"]))
+    mp["dmax"][0] = d
+    assert visible()
+    mp["dmax"][0] = np.nextafter(d, np.float32(0))
+    assert not visible()
+
+
+# ------------------------------------- triangulation check of fisheye pairs ----
+def _scene_check(f, reasons_needed):
+    from tests import fisheye_scenes as fs
+    exp = fs.expected(f)
+    out = oracle.stereo_fisheye(f)
+    got = out["right_idx"] == np.arange(len(exp))
+    n_clear = 0
+    for i, (acc, reason, clear) in enumerate(exp):
+        if clear:
+            n_clear += 1
+            assert got[i] == acc, (i, reason)
+    seen = {}
+    for acc, reason, clear in exp:
+        if clear:
+            seen[reason] = seen.get(reason, 0) + 1
+    for r in reasons_needed:
+        assert seen.get(r, 0) >= 3, (r, seen)
+    return exp, out
+
+
+def test_fisheye_parallax_gate_scene():
+    """Noise-free pairs with parallax cosines just below and just above the
+    limit: accepted below, rejected above (the depth and reprojection tests
+    pass for all of them)."""
+    from tests import fisheye_scenes as fs
+    f = fs.parallax_scene()
+    _, out = _scene_check(f, ["ok", "parallax"])
+    assert out["stats"]["rej_parallax"] >= 3
+
+
+def test_fisheye_depth_gate_scene():
+    """Lines that meet behind one camera and in front of the other are
+    rejected by the depth test of that camera, with the reprojection gate
+    opened so that nothing else could reject them."""
+    from tests import fisheye_scenes as fs
+    f = fs.depth_scene()
+    exp, out = _scene_check(f, ["ok", "depth"])
+    L = f["left"]
+    # both halves are present: behind the right camera and behind the left one
+    cam = f["stereo_cam"]
+    R, t = cam["R_lr"].astype(np.float64), cam["t_lr"].astype(np.float64)
+    behind = {"left": 0, "right": 0}
+    for i, (acc, reason, clear) in enumerate(exp):
+        if reason != "depth":
+            continue
+        r1 = fs.unproject(cam["left"], L["x"][i], L["y"][i])
+        r2 = fs.unproject(cam["right"], f["right"]["x"][i], f["right"]["y"][i])
+        X = fs.lstsq_point(r1, r2, R, t)
+        behind["left" if X[2] <= 0 else "right"] += 1
+    assert behind["left"] >= 3 and behind["right"] >= 3
+    assert out["stats"]["rej_depth"] == sum(e[1] == "depth" for e in exp)
+
+
+def test_fisheye_reprojection_gate_scene():
+    """Right keypoints moved off the exact projection, with the two keypoints
+    on levels whose gates differ 12.8x: each view is judged against its own
+    keypoint's level.  The scene holds pairs that only the right view's own
+    level rejects, pairs that pass only with the full chi2 bound (not half),
+    and the same two kinds for the left view."""
+    from tests import fisheye_scenes as fs
+    f = fs.reprojection_scene()
+    exp, _ = _scene_check(f, ["ok", "reproj"])
+    cam, sc, sp = f["stereo_cam"], f["scales"], f["stereo_params"]
+    L, Rk = f["left"], f["right"]
+    R, t = cam["R_lr"].astype(np.float64), cam["t_lr"].astype(np.float64)
+    s2 = sc["sigma2"].astype(np.float64)
+    kinds = {"right_own_level": 0, "right_full_bound": 0, "left_own_level": 0, "left_full_bound": 0}
+    for i, (acc, reason, clear) in enumerate(exp):
+        if not clear or reason not in ("ok", "reproj"):
+            continue
+        r1 = fs.unproject(cam["left"], L["x"][i], L["y"][i])
+        r2 = fs.unproject(cam["right"], Rk["x"][i], Rk["y"][i])
+        X = fs.lstsq_point(r1, r2, R, t)
+        eL = ((kb_project64(X[None], cam["left"])[0] - [L["x"][i], L["y"][i]]) ** 2).sum()
+        eR = ((kb_project64((R.T @ (X - t))[None], cam["right"])[0] - [Rk["x"][i], Rk["y"][i]]) ** 2).sum()
+        oL, oR = int(L["octave"][i]), int(Rk["octave"][i])
+        gL, gR = sp["chi2"] * s2[oL], sp["chi2"] * s2[oR]
+        if eL <= gL and gR < eR <= sp["chi2"] * s2[oL]:
+            kinds["right_own_level"] += 1
+        if eL <= gL and 0.5 * gR < eR <= gR:
+            kinds["right_full_bound"] += 1
+        if eR <= gR and gL < eL <= sp["chi2"] * s2[oR]:
+            kinds["left_own_level"] += 1
+        if eR <= gR and 0.5 * gL < eL <= gL:
+            kinds["left_full_bound"] += 1
+    assert all(v >= 2 for v in kinds.values()), kinds
+
+
+def test_fisheye_needs_two_targets():
+    """With one right keypoint in the overlap there is no second nearest
+    distance, so nothing is matched; a second target makes matches possible."""
+    from tests import fisheye_scenes as fs
+    f = fs.parallax_scene()
+    ok = [i for i, e in enumerate(fs.expected(f)) if e[0] and e[2]]
+    i = ok[0]
+    W = f["size"]["W"]
+    xr = f["right"]["x"][i]
+    f["stereo_cam"]["overlap_right"] = np.array([xr, xr], np.float32)
+    others = np.nonzero(f["right"]["x"] == xr)[0]
+    assert len(others) == 1
+    out = oracle.stereo_fisheye(f)
+    assert out["stats"]["T"] == 1 and out["n_matches"] == 0
+    j = ok[1]
+    f["right"]["x"][j] = xr
+    out = oracle.stereo_fisheye(f)
+    assert out["stats"]["T"] == 2 and out["right_idx"][i] == i
+    f["stereo_cam"]["overlap_right"] = np.array([0, W], np.float32)
