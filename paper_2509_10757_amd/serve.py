@@ -18,8 +18,16 @@ needed").  The scheduler
 one frame at a time as it arrives (the plain per-frame GPU path), for the
 comparison at equal p99 latency.
 
-The scheduler only talks to an executor (`launch`, `done`, `release`), so its
-logic is tested on the CPU with a fake executor.
+The scheduler only talks to an executor (`launch`, `done`, `release`, `admit`,
+`evict`), so its logic is tested on the CPU with a fake executor.  `done(h)`
+returns whether the batch's device work has ended; it raises `BatchFailed`
+when the work ended with an error (the batch's slots may then be reused), and
+any other exception means the device state is unknown, which stops the loop.
+A batch that outlives `timeout_s` is reported failed at once, but its slots
+stay withheld until the executor reports its work ended; if that does not
+happen within another `timeout_s`, the loop stops with an error rather than
+hand the slots to new frames.  A removed stream's map stays resident until
+its last in-flight batch has ended.
 """
 from __future__ import annotations
 
@@ -29,6 +37,15 @@ import time
 from dataclasses import dataclass, field
 
 import numpy as np
+
+
+class BatchFailed(RuntimeError):
+    """A batch's device work ended with an error; its slots may be reused."""
+
+
+class ServingStalled(RuntimeError):
+    """A timed-out batch never reported completion: its slots cannot be
+    handed to new frames, so serving stops."""
 
 
 @dataclass
@@ -47,6 +64,8 @@ class Stats:
     rejected_streams: list = field(default_factory=list)
     dropped_frames: int = 0
     batches: int = 0
+    timed_out: int = 0
+    max_overlap: int = 0         # largest number of batches in flight at once
     latencies_ms: list = field(default_factory=list)
     wall_s: float = 0.0
 
@@ -54,7 +73,7 @@ class Stats:
         lat = np.array(self.latencies_ms) if self.latencies_ms else np.zeros(1)
         return {"frames": self.completed, "failed": self.failed,
                 "dropped_frames": self.dropped_frames, "rejected_streams": self.rejected_streams,
-                "batches": self.batches,
+                "batches": self.batches, "timed_out": self.timed_out, "max_overlap": self.max_overlap,
                 "frames_per_s": self.completed / self.wall_s if self.wall_s > 0 else 0.0,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_batch": self.completed / max(self.batches, 1)}
@@ -77,6 +96,8 @@ class Scheduler:
         self.streams = {}
         self.pending = collections.deque()
         self.inflight = []           # (handle, frames, launch time)
+        self.quarantine = []         # (handle, time-out time): failed, slots still withheld
+        self.evicting = set()        # removed streams whose batches are still in flight
         self.stats = Stats()
         self.t0 = None
 
@@ -92,17 +113,28 @@ class Scheduler:
 
     def remove_stream(self, sid: int):
         """Drop a stream: its queued frames are dropped, its in-flight frames
-        finish (their results are simply not used)."""
+        finish (their results are simply not used).  Its map leaves the device,
+        and its footprint the budget, once no batch in flight reads it."""
         if sid not in self.streams:
             return
         kept = collections.deque(f for f in self.pending if f.stream != sid)
         self.stats.dropped_frames += len(self.pending) - len(kept)
         self.pending = kept
-        self.used -= self.streams.pop(sid)
-        self.ex.evict(sid)
+        self.evicting.add(sid)
+        self._finish_evictions()
+
+    def _stream_busy(self, sid) -> bool:
+        return any(f.stream == sid for _, frames, _ in self.inflight for f in frames) or \
+            any(f.stream == sid for _, frames, _ in self.quarantine for f in frames)
+
+    def _finish_evictions(self):
+        for sid in [s for s in self.evicting if not self._stream_busy(s)]:
+            self.evicting.discard(sid)
+            self.used -= self.streams.pop(sid)
+            self.ex.evict(sid)
 
     def arrive(self, frame: Frame):
-        if frame.stream in self.streams:
+        if frame.stream in self.streams and frame.stream not in self.evicting:
             self.pending.append(frame)
         else:
             self.stats.dropped_frames += 1
@@ -111,31 +143,49 @@ class Scheduler:
     def now(self) -> float:
         return self.clock() - self.t0
 
+    def _ended(self, h) -> tuple:
+        """(work ended, ended with an error) for one batch."""
+        try:
+            return bool(self.ex.done(h)), False
+        except BatchFailed:
+            return True, True
+
     def poll(self):
         still = []
         for h, frames, t_launch in self.inflight:
-            try:
-                ok = self.ex.done(h)
-            except Exception:
-                ok, err = True, True
-            else:
-                err = False
-            if not ok and self.now() - t_launch > self.timeout_s:
-                ok, err = True, True
-            if ok:
+            ended, err = self._ended(h)
+            timed_out = not ended and self.now() - t_launch > self.timeout_s
+            if ended or timed_out:
                 t = self.now()
                 for f in frames:
                     f.done = t
-                    if err:
+                    if err or timed_out:
                         f.failed = True
                         self.stats.failed += 1
                     else:
                         self.stats.completed += 1
                         self.stats.latencies_ms.append((t - f.arrival) * 1e3)
-                self.ex.release(h)
+                if ended:
+                    self.ex.release(h)
+                else:
+                    # reported failed, but its kernels may still write its
+                    # slots: they stay withheld until the work has ended
+                    self.stats.timed_out += 1
+                    self.quarantine.append((h, frames, t))
             else:
                 still.append((h, frames, t_launch))
         self.inflight = still
+        held = []
+        for h, frames, t_out in self.quarantine:
+            if self._ended(h)[0]:
+                self.ex.release(h)
+            elif self.now() - t_out > self.timeout_s:
+                raise ServingStalled(f"batch {h} has not ended {self.timeout_s} s after its time-out")
+            else:
+                held.append((h, frames, t_out))
+        self.quarantine = held
+        if self.evicting:
+            self._finish_evictions()
 
     def launch(self) -> bool:
         if not self.pending or len(self.inflight) >= self.max_inflight:
@@ -153,9 +203,10 @@ class Scheduler:
             return True
         self.inflight.append((h, frames, self.now()))
         self.stats.batches += 1
+        self.stats.max_overlap = max(self.stats.max_overlap, len(self.inflight))
         return True
 
-    def run(self, arrivals, drain_s: float = 2.0) -> Stats:
+    def run(self, arrivals) -> Stats:
         """Serve `arrivals` = [(time_s, stream, seq)] in real time."""
         self.t0 = self.clock()
         i, n = 0, len(arrivals)
@@ -169,14 +220,7 @@ class Scheduler:
             self.poll()
             while self.launch():
                 pass
-            if i >= n and not self.pending and not self.inflight:
-                break
-            if now > end + drain_s + self.timeout_s:
-                for _, frames, _ in self.inflight:
-                    for f in frames:
-                        f.failed = True
-                        self.stats.failed += 1
-                self.inflight = []
+            if i >= n and not self.pending and not self.inflight and not self.quarantine:
                 break
         self.stats.wall_s = max(self.now(), end)
         return self.stats
@@ -250,7 +294,8 @@ class DeviceExecutor:
         self.arena = self.ctx.ft_host_alloc(self.arena_bytes)
         self.arena_np = np.ctypeslib.as_array((ct.c_uint8 * self.arena_bytes).from_address(self.arena))
         self.maps = {}
-        self.pyr = {}          # id(pyramid dict) -> device tensor
+        self.pyr = {}          # (stream, id(pyramid dict)) -> device tensor, per stream
+        self.on_release = None # optional hook(handle) called before a batch's slots are freed
         self.tmpl = {}         # (stream, pool index) -> (template words, slot mask, packed bytes)
         self.packed = {}       # (stream, pool index) -> packed bytes in the arena
         self.device = device
@@ -280,27 +325,40 @@ class DeviceExecutor:
         s = self.streams[sid]
         mp = s["frames"][0]["map"]
         self.maps[sid] = {k: torch.from_numpy(np.ascontiguousarray(v)).to(self.device) for k, v in mp.items()}
+        for key, p in self._pyramids(sid).items():
+            self.pyr[key] = torch.from_numpy(p["data"]).to(self.device)
         for q, f in enumerate(s["frames"]):
-            for key in ("pyr_left", "pyr_right"):
-                if key in f and id(f[key]) not in self.pyr:
-                    self.pyr[id(f[key])] = torch.from_numpy(f[key]["data"]).to(self.device)
             if (sid, q) not in self.packed:   # packed once: an upload may still read it
                 self.packed[(sid, q)] = self._pack(f, self.arena_off[(sid, q)])
             self.tmpl[(sid, q)] = self._template(sid, f) + (self.packed[(sid, q)],)
 
     def evict(self, sid):
+        """Frees what the stream holds on the device (exactly what footprint
+        counts); the scheduler calls it once no batch in flight reads it."""
         self.maps.pop(sid, None)
         for k in [k for k in self.tmpl if k[0] == sid]:
             del self.tmpl[k]
+        for k in [k for k in self.pyr if k[0] == sid]:
+            del self.pyr[k]
+
+    def _pyramids(self, sid) -> dict:
+        """The distinct image pyramids of a stream's pooled frames."""
+        out = {}
+        for f in self.streams[sid]["frames"]:
+            for key in ("pyr_left", "pyr_right"):
+                if key in f:
+                    out[(sid, id(f[key]))] = f[key]
+        return out
 
     def footprint(self, sid) -> int:
         """Device bytes a stream holds while admitted: its map (64 bytes per
-        point) and, for pinhole streams, one pyramid pair per pooled frame."""
-        s = self.streams[sid]
-        pyr = 0
-        if s["kind"] == "pinhole":
-            pyr = sum(f["pyr_left"]["data"].size + f["pyr_right"]["data"].size for f in s["frames"])
-        return s["map_bytes"] + pyr
+        point) and its own copy of each distinct pyramid of its pooled frames."""
+        return self.streams[sid]["map_bytes"] + sum(p["data"].size for p in self._pyramids(sid).values())
+
+    def resident_bytes(self) -> int:
+        """Device bytes held for admitted streams (maps and pyramids)."""
+        return (sum(t.numel() * t.element_size() for m in self.maps.values() for t in m.values()) +
+                sum(t.numel() for t in self.pyr.values()))
 
     def _pack(self, f, at):
         L, R = f["left"], f["right"]
@@ -346,7 +404,7 @@ class DeviceExecutor:
             for key, dst in (("pyr_left", "pyr_left"), ("pyr_right", "pyr_right")):
                 p = f[key]
                 s = ft.ft_pyramid()
-                s.data = self.pyr[id(p)].data_ptr()
+                s.data = self.pyr[(sid, id(p))].data_ptr()
                 s.offset[:] = [int(v) for v in p["offset"]]
                 s.width[:] = [int(v) for v in p["width"]]
                 s.height[:] = [int(v) for v in p["height"]]
@@ -456,16 +514,25 @@ class DeviceExecutor:
         token = self.handles[h][0]
         if token[0] == "event":
             return token[1].query()
-        return self.ctx.ft_batch_poll(token[1])
+        try:
+            return self.ctx.ft_batch_poll(token[1])
+        except self.ft.FtError as e:
+            if e.status == self.ft.FT_ERR_ABORTED:   # the batch ended, its outputs are invalid
+                raise BatchFailed(str(e)) from e
+            raise
 
     def release(self, h):
+        if self.on_release is not None:
+            self.on_release(h)
         _, slots, _ = self.handles.pop(h)
         self.free.extend(slots)
 
-    def results(self, slot: int, kind: str, n: int, n_map: int, n_views: int) -> dict:
-        """Copy one slot's outputs to the host (synchronises)."""
+    def results(self, slot: int, kind: str, n: int, n_map: int, n_views: int, sync: bool = True) -> dict:
+        """Copy one slot's outputs to the host (synchronises the device unless
+        `sync` is false, for a slot whose batch is known to have ended)."""
         o = self.outs[slot]
-        self.torch.cuda.synchronize()
+        if sync:
+            self.torch.cuda.synchronize()
         st = {"right_idx": o["right_idx"][:n].cpu().numpy(), "dist": o["dist"][:n].cpu().numpy(),
               "n_matches": int(o["n_stereo"][0])}
         if kind == "pinhole":

@@ -67,16 +67,52 @@ def test_result_alone_equals_result_in_mix(streams, executor):
 
 
 def test_short_real_time_run_serves_everything(streams, executor):
+    """Continuous batching in real time with batches overlapping on the
+    device: every arrival is served, and every served frame's outputs (copied
+    when its batch ends, before its slots are reused) equal the oracle's."""
     from paper_2509_10757_amd.serve import Scheduler
     from synth.serving import poisson_arrivals
+    served = []
+
+    def keep(h):
+        _, slots, frames = executor.handles[h]
+        for slot, fr in zip(slots, frames):
+            s = streams[fr.stream]
+            f = s["frames"][fr.seq % len(s["frames"])]
+            served.append(((fr.stream, fr.seq % len(s["frames"])),
+                           executor.results(slot, f["kind"], len(f["left"]["x"]), len(f["map"]["dmin"]),
+                                            len(f["search"]), sync=False)))
     sch = Scheduler(executor, hbm_budget=1 << 32, max_batch=16, max_inflight=2)
     for s in streams:
         sch.register_stream(s["id"], executor.footprint(s["id"]))
-    arr = poisson_arrivals(np.random.default_rng(3), streams, 1.0, speedup=4.0)
-    st = sch.run(arr).summary()
-    say(st)
+    arr = poisson_arrivals(np.random.default_rng(3), streams, 1.0, speedup=16.0)
+    executor.on_release = keep
+    try:
+        st = sch.run(arr).summary()
+    finally:
+        executor.on_release = None
+    say({k: v for k, v in st.items() if k != "rejected_streams"})
     assert st["frames"] == len(arr) and st["failed"] == 0
     assert st["p99_ms"] < 1000.0
+    assert st["max_overlap"] >= 2, "no two batches were ever in flight together"
+    assert len(served) == len(arr)
+    want = {}
+    for key, got in served:
+        if key not in want:
+            sid, q = key
+            want[key] = oracle.run_frame(streams[sid]["frames"][q])
+        compare_frame(got, want[key])
+
+
+def test_evicted_stream_frees_its_device_memory(streams, executor):
+    """Eviction frees exactly the bytes the stream's footprint counts, and the
+    stream can be admitted again."""
+    sid = next(s["id"] for s in streams if s["kind"] == "pinhole")
+    before = executor.resident_bytes()
+    executor.evict(sid)
+    assert before - executor.resident_bytes() == executor.footprint(sid)
+    executor.admit(sid)
+    assert executor.resident_bytes() == before
 
 
 def test_admission_rejects_streams_beyond_budget(streams, executor):

@@ -3,7 +3,7 @@ admission by footprint, FIFO coalescing, in-flight and slot limits, latency
 accounting, injected failures, time-outs and stream removal."""
 import pytest
 
-from paper_2509_10757_amd.serve import Frame, Scheduler
+from paper_2509_10757_amd.serve import BatchFailed, Frame, Scheduler, ServingStalled
 
 
 class FakeClock:
@@ -18,12 +18,14 @@ class FakeExecutor:
     """Completes a batch `delay` seconds of fake time after launch."""
 
     def __init__(self, clock, slots=64, delay=0.002, fail_streams=(), raise_on_launch=False,
-                 hang_streams=()):
+                 hang_streams=(), hang_s=None):
         self.clock = clock
         self.slots = slots
         self.delay = delay
         self.fail_streams = set(fail_streams)
         self.hang_streams = set(hang_streams)
+        self.hang_s = hang_s          # a hung batch ends after this long (None: never)
+        self.evicted = []
         self.raise_on_launch = raise_on_launch
         self.launched = []
         self.h = {}
@@ -35,6 +37,7 @@ class FakeExecutor:
 
     def evict(self, sid):
         self.admitted.discard(sid)
+        self.evicted.append(sid)
 
     def free_slots(self):
         return self.slots
@@ -51,9 +54,9 @@ class FakeExecutor:
     def done(self, h):
         t, frames = self.h[h]
         if any(f.stream in self.hang_streams for f in frames):
-            return False
+            return self.hang_s is not None and self.clock() >= t + self.hang_s
         if any(f.stream in self.fail_streams for f in frames):
-            raise RuntimeError("kernel error")
+            raise BatchFailed("kernel error")
         return self.clock() >= t
 
     def release(self, h):
@@ -156,15 +159,41 @@ def test_launch_exception_fails_the_frames_cleanly():
     assert st.failed == 5 and st.completed == 0 and not sch.inflight
 
 
-def test_timeout_marks_hung_batch_failed():
+def test_timeout_marks_batch_failed_but_withholds_its_slots():
+    """A batch past its time-out is reported failed at once, but its slots are
+    handed out again only after the executor reports its work ended."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock, hang_streams={7}, hang_s=0.08)
+    sch = Scheduler(ex, hbm_budget=10, max_batch=1, clock=clock, timeout_s=0.05)
+    sch.register_stream(7, 1)
+    sch.register_stream(8, 1)
+    st = drive(sch, clock, [(0.0, 7, 0), (0.0, 8, 1)], horizon=0.06)
+    assert st.failed == 1 and st.completed == 1 and st.timed_out == 1
+    assert ex.slots == 63 and len(sch.quarantine) == 1    # withheld while its work may run
+    drive(sch, clock, [], horizon=0.05)
+    assert ex.slots == 64 and not sch.quarantine          # released once it ended
+    assert st.failed == 1 and st.completed == 1
+
+
+def test_batch_that_never_ends_stops_the_loop():
     clock = FakeClock()
     ex = FakeExecutor(clock, hang_streams={7})
     sch = Scheduler(ex, hbm_budget=10, max_batch=1, clock=clock, timeout_s=0.05)
     sch.register_stream(7, 1)
-    sch.register_stream(8, 1)
-    st = drive(sch, clock, [(0.0, 7, 0), (0.0, 8, 1)], horizon=0.2)
-    assert st.failed == 1 and st.completed == 1
-    assert ex.slots == 64                          # the hung batch's slots were released
+    with pytest.raises(ServingStalled):
+        drive(sch, clock, [(0.0, 7, 0)], horizon=0.5)
+    assert ex.slots == 63                                 # never handed to new frames
+
+
+def test_unknown_device_error_stops_the_loop():
+    class Lost(FakeExecutor):
+        def done(self, h):
+            raise RuntimeError("device lost")
+    clock = FakeClock()
+    sch = Scheduler(Lost(clock), hbm_budget=10, clock=clock)
+    sch.register_stream(0, 1)
+    with pytest.raises(RuntimeError, match="device lost"):
+        drive(sch, clock, [(0.0, 0, 0)], horizon=0.05)
 
 
 def test_stream_removal_drops_queued_frames_only():
@@ -179,10 +208,14 @@ def test_stream_removal_drops_queued_frames_only():
     sch.launch()                                   # frames 0, 1 in flight
     sch.remove_stream(1)                           # drops queued frames 3, 5
     assert sch.stats.dropped_frames == 2
+    # frame 1 of the removed stream is still in flight: its map stays resident
+    # and its footprint stays counted until that batch ends
+    assert 1 in ex.admitted and sch.used == 2 and ex.evicted == []
     sch.arrive(Frame(1, 99, 0.0))                  # arrives after removal: dropped
     assert sch.stats.dropped_frames == 3
     st = drive(sch, clock, [], horizon=0.5)
     assert st.completed == 4                       # 0, 1 (in flight) + 2, 4
+    assert ex.evicted == [1] and 1 not in ex.admitted and sch.used == 1
 
 
 @pytest.mark.parametrize("mode", ["batched", "per_frame"])
