@@ -6,14 +6,29 @@ pinhole 752x480 frames and 32 fisheye 512x512 frames in seeded order,
 stereo matching and search by projection in each camera view.  Inputs are
 resident in device memory before the timed region.  Prints one JSON line.
 
-Extra fields: per-step latency percentiles, the same frames through the
-single-frame calls (the plain per-frame path), the dominant kernel's roofline
-fraction from live HIP-event timing, and the CPU oracle's throughput on a
-bounded sample of the same frames.
+Beside the headline the default run also reports:
+  * latency of one 64-frame submission, and the same frames through the
+    single-frame calls (the plain per-frame GPU path);
+  * per-phase kernel times (HIP events) and the dominant kernel's roofline
+    fraction, warm and cold (the 256 MB last-level cache flushed by a 512 MB
+    write before every submission);
+  * per-frame p50/p99 latency of the three single-frame workloads (pinhole
+    1200 keypoints / 3000 map points, fisheye 1500 / 5000, clustered 3000 /
+    20000);
+  * the clustered scene over 64 seeds in one submission, with the search
+    kernel's roofline on it;
+  * a bounded serving sweep (32 camera streams, resident maps of 2k-40k
+    points): per-frame path and continuous batching over the same Poisson
+    arrivals, frames/s at equal p99, and a sample of frames served inside
+    overlapping batches checked bit for bit against the same frames alone;
+  * the CPU oracle on the same frames, one thread and on all host cores (the
+    host's CPU model and core count recorded), and on each single-frame
+    workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,13 +42,14 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "frame-pairs/s (stereo + local-map search) on 1 MI355X; p50/p99 frame latency"
 WORKLOAD = ("batched: 64 stereo frames, 32 pinhole 752x480 + 32 fisheye 512x512 (seeded order), "
             "300-3000 keypoints/image, 1k-20k local map points/frame, one submission per step")
+FLUSH_BYTES = 512 << 20     # twice the MI355X last-level cache
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_search_bytes(frames, results):
+def algorithmic_search_bytes(frames):
     """Compulsory bytes of the search-by-projection kernel for one step.
 
     Per map point and view: 64 B record (position 12, normal 12, dmin 4, dmax 4,
@@ -61,8 +77,10 @@ def algorithmic_path_bytes(frames, results):
     lower bound).  Fisheye: per left keypoint 24 B of outputs (right index,
     distance, depth, point).  Search: as `algorithmic_search_bytes`.
     """
-    total = algorithmic_search_bytes(frames, results)
+    total = algorithmic_search_bytes(frames)
     for f, r in zip(frames, results):
+        if "right" not in f:
+            continue
         nL, nR = len(f["left"]["x"]), len(f["right"]["x"])
         total += 41 * (nL + nR)
         if f["kind"] == "pinhole":
@@ -75,13 +93,13 @@ def algorithmic_path_bytes(frames, results):
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_10757_amd", "csrc", "ft_kernels.hip")
 
 
-def measured_traffic(kernel_key):
+def measured_traffic(kernel_key, workload):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what
     the counter reads for a plain copy of known size), or None when there is no
-    summary for it or the kernel source changed since the counters were taken."""
+    summary for it on this workload or the kernel source changed since the
+    counters were taken."""
     import glob
-    import hashlib
     import re
     digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*pmc*.md"))):
@@ -89,29 +107,134 @@ def measured_traffic(kernel_key):
         if not m:
             continue
         rec = json.loads(m.group(1))
-        if rec.get("kernel_key") != kernel_key or rec.get("source_sha256") != digest:
+        if (rec.get("kernel_key") != kernel_key or rec.get("source_sha256") != digest or
+                rec.get("workload", "mixed_batch64") != workload):
             continue
         return round(rec["fetch_kib"] * rec["fetch_scale"] * 1024 + rec["write_kib"] * rec["write_scale"] * 1024)
     return None
 
 
-def cpu_baseline(frames, budget_s=12.0):
+# ------------------------------------------------------------ CPU oracle ----
+def host_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+
+
+def _digest(res):
+    h = hashlib.sha256()
+    if "stereo" in res:
+        for k in ("right_idx", "dist"):
+            h.update(res["stereo"][k].tobytes())
+    for s in res["search"]:
+        for k in ("mp_match", "mp_dist", "kp_match"):
+            h.update(s[k].tobytes())
+    return h.hexdigest()[:16]
+
+
+_POOL_FRAMES = None
+
+
+def _oracle_worker(args):
+    """Runs the oracle on frames w, w + P, w + 2P, ... (wrapping) for `budget`
+    seconds; returns (frames done, digests of the first pass)."""
+    w, P, budget = args
     import oracle
-    done = 0
+    frames = _POOL_FRAMES
+    done, seen = 0, {}
+    t0 = time.perf_counter()
+    i = w
+    while time.perf_counter() - t0 < budget:
+        idx = i % len(frames)
+        r = oracle.run_frame(frames[idx])
+        if idx not in seen:
+            seen[idx] = _digest(r)
+        done += 1
+        i += P
+    return done, seen, time.perf_counter() - t0
+
+
+def cpu_baseline(frames, single, budget_s=10.0, workers=None):
+    """The oracle as it stands on the same frames: (i) one thread, in order;
+    (ii) one process per host core (at most 16, the host share of one GPU),
+    each taking every P-th frame.  Both runs hash their results; frames done
+    by both must hash the same.  Also the oracle's time on each single-frame
+    workload in `single` (name -> frame)."""
+    import multiprocessing as mp
+
+    import oracle
+    global _POOL_FRAMES
+    oracle._load()
+    per_config = {}
+    for name, f in single.items():
+        o0 = time.perf_counter()
+        oracle.run_frame(f)
+        per_config[name] = round((time.perf_counter() - o0) * 1e3, 2)
+    done, seen = 0, {}
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
-        oracle.run_frame(frames[done % len(frames)])
+        idx = done % len(frames)
+        r = oracle.run_frame(frames[idx])
+        if idx not in seen:
+            seen[idx] = _digest(r)
         done += 1
+    dt1 = time.perf_counter() - t0
+    single_run = {"value": round(done / dt1, 3), "unit": "frame-pairs/s", "cores": 1,
+                  "sample": f"{done} frames of the 64-frame workload in order, {dt1:.1f} s"}
+    info = host_info()
+    P = workers or max(1, min(16, info["nproc"]))
+    _POOL_FRAMES = frames
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        outs = pool.map(_oracle_worker, [(w, P, budget_s) for w in range(P)])
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "frame-pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} frames of the same 64-frame workload in order (wrapping), "
-                      f"single-threaded plain C oracle, {dt:.1f} s"}
+    _POOL_FRAMES = None
+    total = sum(o[0] for o in outs)
+    par_seen = {}
+    for o in outs:
+        par_seen.update(o[1])
+    common = set(seen) & set(par_seen)
+    identical = all(seen[k] == par_seen[k] for k in common)
+    return {"value": round(total / dt, 3), "unit": "frame-pairs/s", "cores": P, "kind": "oracle",
+            "sample": (f"{total} frames of the same 64-frame workload, {P} worker processes each taking "
+                       f"every {P}-th frame (wrapping) for {budget_s:.0f} s; plain C oracle, unchanged"),
+            "single_thread": single_run, "host": info, "single_frame_workloads_ms": per_config,
+            "results_identical_to_single_thread": identical, "frames_compared": len(common)}
 
 
-def serving_sweep(duration_s, speedups):
-    """Serving 32 camera streams (20-30 Hz, resident maps of 2k-40k points): the per-frame path and continuous
-    batching over the same Poisson arrivals, compressed in time by `speedups` (ascending).  Each mode stops
-    after the first rate it cannot keep up with (served < 90 % of offered)."""
+# -------------------------------------------------------------- serving ----
+def same_results(a, b) -> bool:
+    """Two device result dicts hold identical bits."""
+    import numpy as np
+    if ("stereo" in a) != ("stereo" in b) or len(a["search"]) != len(b["search"]):
+        return False
+    pairs = [(a["stereo"], b["stereo"])] if "stereo" in a else []
+    pairs += list(zip(a["search"], b["search"]))
+    for x, y in pairs:
+        for k, v in x.items():
+            if isinstance(v, np.ndarray):
+                if not np.array_equal(v.view(np.uint8), y[k].view(np.uint8)):
+                    return False
+            elif v != y[k]:
+                return False
+    return True
+
+
+def serving_sweep(duration_s, per_frame_rates, batched_rates, check_frames=24):
+    """Serving 32 camera streams (20-30 Hz, resident maps of 2k-40k points):
+    the per-frame path and continuous batching over the same Poisson arrivals,
+    compressed in time by the given factors (ascending).  Each mode stops after
+    the first rate it cannot keep up with (served < 90 % of offered).  Then a
+    batched run whose first `check_frames` served frames are copied as their
+    batches end (while other batches are in flight) and compared bit for bit
+    with the same frames served alone through the single-frame calls."""
     from paper_2509_10757_amd import serve
     from synth.serving import make_streams
     log("generating the 32-stream serving workload")
@@ -121,25 +244,87 @@ def serving_sweep(duration_s, speedups):
         ex.admit(s["id"])
     log("serving shapes", ex.autotune())
     rows = []
-    for mode in ("per_frame", "batched"):
-        for a in speedups:
+    for mode, rates in (("per_frame", per_frame_rates), ("batched", batched_rates)):
+        for a in rates:
             r = serve.serve(streams, duration_s, speedup=a, mode=mode, executor=ex)
             log(mode, a, {k: round(v, 3) if isinstance(v, float) else v for k, v in r.items()
-                          if k in ("frames_per_s", "p50_ms", "p99_ms", "offered_fps", "mean_batch")})
+                          if k in ("frames_per_s", "p50_ms", "p99_ms", "offered_fps", "mean_batch", "max_overlap")})
             rows.append({k: r[k] for k in ("mode", "speedup", "offered_fps", "frames_per_s",
-                                           "p50_ms", "p99_ms", "mean_batch", "failed")})
+                                           "p50_ms", "p99_ms", "mean_batch", "max_overlap", "failed")})
             if r["frames_per_s"] < 0.9 * r["offered_fps"]:
                 break
-    # knee of the per-frame path: the highest load it still keeps up with
     pf = [r for r in rows if r["mode"] == "per_frame" and r["frames_per_s"] >= 0.95 * r["offered_fps"]]
     knee = max(pf, key=lambda r: r["offered_fps"]) if pf else min(
         (r for r in rows if r["mode"] == "per_frame"), key=lambda r: r["offered_fps"])
     bound = knee["p99_ms"]
     ok = [r for r in rows if r["mode"] == "batched" and r["p99_ms"] <= bound]
     best = max(ok, key=lambda r: r["frames_per_s"]) if ok else None
+
+    # served results (copied before the slots are reused) against the same
+    # frames served alone
+    captured = []
+
+    def keep(h):
+        if len(captured) >= check_frames:
+            return
+        _, slots, frames = ex.handles[h]
+        for slot, fr in zip(slots, frames):
+            s = ex.streams[fr.stream]
+            q = fr.seq % len(s["frames"])
+            f = s["frames"][q]
+            captured.append((fr, f, ex.results(slot, f["kind"], len(f["left"]["x"]), len(f["map"]["dmin"]),
+                                               len(f["search"]), sync=False)))
+    ex.on_release = keep
+    try:
+        serve.serve(streams, min(duration_s, 0.3), speedup=batched_rates[len(batched_rates) // 2],
+                    mode="batched", executor=ex)
+    finally:
+        ex.on_release = None
+    bad = 0
+    for fr, f, got in captured[:check_frames]:
+        h = ex.launch([serve.Frame(fr.stream, fr.seq, 0.0)], per_frame=True)
+        while not ex.done(h):
+            pass
+        alone = ex.results(ex.handles[h][1][0], f["kind"], len(f["left"]["x"]), len(f["map"]["dmin"]),
+                           len(f["search"]), sync=False)
+        ex.release(h)
+        bad += not same_results(got, alone)
     return {"streams": len(streams), "duration_s": duration_s, "runs": rows,
             "p99_bound_ms": round(bound, 3), "per_frame_fps_at_bound": round(knee["frames_per_s"], 1),
-            "batched_fps_at_bound": round(best["frames_per_s"], 1) if best else None}
+            "batched_fps_at_bound": round(best["frames_per_s"], 1) if best else None,
+            "batched_over_per_frame_at_equal_p99": (round(best["frames_per_s"] / knee["frames_per_s"], 2)
+                                                    if best and knee["frames_per_s"] > 0 else None),
+            "served_frames_checked_against_alone": min(len(captured), check_frames),
+            "served_frames_mismatching": bad}
+
+
+# --------------------------------------------------------------- helpers ----
+def percentiles(xs):
+    import numpy as np
+    a = np.asarray(xs)
+    return {"p50": round(float(np.percentile(a, 50)), 4), "p99": round(float(np.percentile(a, 99)), 4)}
+
+
+def phase_times(ctx, ft, submit, n, flush=None):
+    """Average HIP-event time of each phase kernel over `n` eager submissions
+    on one stream (each kernel runs alone); `flush()` runs before each."""
+    ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
+    ctx.ft_context_enable_timing(True)
+    for _ in range(n):
+        if flush is not None:
+            flush()
+        submit()
+    tm = ctx.ft_context_read_timing()
+    ctx.ft_context_enable_timing(False)
+    return {k: {"avg_us": round(ms / c * 1e3, 3), "launches": c} for k, (ms, c) in tm.items() if c}
+
+
+def search_roofline(nbytes, us, traffic, note):
+    achieved = nbytes / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": "k_search (search by projection)", "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "avg_launch_us": round(us, 3),
+            "timed": note}
 
 
 def main():
@@ -148,16 +333,21 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of each oracle leg")
     ap.add_argument("--shapes", type=str, default="",
                     help="best_lanes,search_lanes[,search_block,best_block,aux_block] instead of autotuning")
-    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event passes")
     ap.add_argument("--exec", choices=["auto", "graph", "persistent", "eager"], default="auto",
-                    help="batch execution mode; auto times the modes and submission splits briefly and keeps the fastest")
+                    help="batch execution mode; auto times the modes and submission streams briefly")
     ap.add_argument("--parts", type=int, default=1, help="submission split (with an explicit --exec)")
     ap.add_argument("--streams", type=int, default=1, choices=[1, 2, 3, 4],
                     help="submission streams (with an explicit --exec)")
-    ap.add_argument("--serving", type=float, default=0.0, metavar="SECONDS",
-                    help="also run the 32-stream serving sweep, SECONDS per run")
+    ap.add_argument("--serving", type=float, default=0.6, metavar="SECONDS",
+                    help="seconds per arrival rate of the serving sweep (0: skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="headline only: skip the single-frame workloads and the clustered batch")
+    ap.add_argument("--only", choices=["mixed", "clustered"], default=None,
+                    help="profiling runs: only the timed region of one workload, no other legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -167,13 +357,11 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import synth
-    from paper_2509_10757_amd import binding as ft
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
     if args.copy_calibration:
+        import torch
         n = args.copy_calibration << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -182,19 +370,41 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n, "launches": 5}))
         return
-    log("generating the 64-frame workload")
-    frames = synth.mixed_batch()
+
+    profiling = args.only is not None
+    if args.only == "clustered":
+        log("generating the clustered scene over 64 seeds")
+        frames = synth.clustered_batch()
+    else:
+        log("generating the 64-frame workload")
+        frames = synth.mixed_batch()
     n_frames = len(frames)
+
+    single = {} if args.no_extra or profiling else {name: synth.workload(name)[0]
+                                                   for name in sorted(synth.SINGLE_FRAME)}
+    # CPU baselines first: the worker processes fork before the GPU is touched
+    cpu = None
+    if not args.no_cpu_baseline and not profiling:
+        log("cpu baseline")
+        cpu = cpu_baseline(frames, single, budget_s=args.cpu_budget)
+        log("cpu", cpu["value"], "frame-pairs/s on", cpu["cores"], "processes; one thread",
+            cpu["single_thread"]["value"])
+
+    import torch
+
+    from paper_2509_10757_amd import binding as ft
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
     max_streams = 4
     ctx = ft.Context(ft.default_limits(max_batch_frames=n_frames, max_map_points=32768, max_inflight=8))
     # one private copy of the frames (inputs, workspace-independent outputs)
     # per submission stream, so batches in flight on different streams never
     # share a buffer
-    copies = [[ft.DeviceFrame(f, "cuda") for f in frames] for _ in range(max_streams)]
+    copies = [[ft.DeviceFrame(f, "cuda") for f in frames] for _ in range(1 if profiling else max_streams)]
     dfs = copies[0]
     job_sets = [[d.job() for d in c] for c in copies]
     jobs = job_sets[0]
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(max_streams - 1)]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(len(copies) - 1)]
     stream = streams[0]
     torch.cuda.synchronize()
     if args.shapes:
@@ -204,9 +414,6 @@ def main():
         log("autotune")
         shapes = ctx.ft_autotune(jobs, stream=stream)
     torch.cuda.synchronize()
-
-    def step():
-        return ctx.ft_batch_submit(jobs, stream)
 
     pending = []
     n_streams = 1
@@ -228,10 +435,9 @@ def main():
 
     modes = {"graph": ft.FT_EXEC_GRAPH, "persistent": ft.FT_EXEC_PERSISTENT, "eager": ft.FT_EXEC_EAGER}
     trial = {}
-    if args.exec == "auto":
-        # execution mode, submission split and submission streams: a short
-        # timed trial of each
-        cands = [("graph", 1, k) for k in range(1, max_streams + 1)] + [("graph", 2, 1), ("persistent", 1, 1)]
+    if args.exec == "auto" and not profiling:
+        # execution mode and submission streams: a short timed trial of each
+        cands = [("graph", 1, k) for k in range(1, max_streams + 1)] + [("persistent", 1, 1)]
         for name, parts, ns in cands:
             ctx.ft_set_exec_mode(modes[name])
             ctx.ft_set_batch_parts(parts)
@@ -248,6 +454,8 @@ def main():
             log("trial", key, trial[key])
         best = max(trial, key=trial.get)
         exec_mode, n_parts, n_streams = best.split("/")[0], int(best.split("/")[1]), int(best.split("/s")[1])
+    elif profiling:
+        exec_mode, n_parts, n_streams = (args.exec if args.exec != "auto" else "graph"), 1, 1
     else:
         exec_mode, n_parts, n_streams = args.exec, args.parts, args.streams
     ctx.ft_set_exec_mode(modes[exec_mode])
@@ -257,7 +465,7 @@ def main():
     log("warmup", args.warmup)
     for _ in range(args.warmup):
         submit_bounded()
-    torch.cuda.synchronize()
+    drain()
 
     # ---- timed region: K back-to-back batch submissions, rotating over
     # n_streams streams (each with its own copy of the frames), so one batch's
@@ -266,12 +474,12 @@ def main():
     log("timed", args.steps, exec_mode)
     if persistent:
         ctx.ft_context_enable_timing(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         submit_bounded()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     drain()
+    dt = time.perf_counter() - t0
     kernel_us = None
     if persistent:
         ms, n = ctx.ft_context_read_timing()["persistent_batch"]
@@ -279,14 +487,17 @@ def main():
         kernel_us = ms / n * 1e3 if n else None
     ms_per_step = dt * 1e3 / args.steps
     value = n_frames * args.steps / dt
+    if profiling:
+        print(json.dumps({"workload": args.only, "value": round(value, 2), "ms_per_step": round(ms_per_step, 4),
+                          "steps": args.steps, "exec": exec_mode}))
+        return
 
     # ---- latency of one submission (submit -> completion seen by the host)
     lat = []
     for _ in range(max(50, args.steps // 4)):
         s0 = time.perf_counter()
-        ctx.ft_batch_wait(step())
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs, stream))
         lat.append((time.perf_counter() - s0) * 1e3)
-    lat = np.array(lat)
 
     # ---- plain per-frame path on the same frames (single-frame calls)
     for d in dfs:
@@ -300,9 +511,9 @@ def main():
     torch.cuda.synchronize()
     plain_fps = n_frames * n_plain / (time.perf_counter() - p0)
 
-    # ---- per-kernel timing with HIP events on the launch stream
-    roofline = None
-    phases = None
+    # ---- per-kernel timing with HIP events on the launch stream, warm and
+    # with the last-level cache flushed before every submission
+    roofline, phases, phases_cold = None, None, None
     res = [d.results() for d in dfs]
     if persistent and kernel_us:
         pbytes = algorithmic_path_bytes(frames, res)
@@ -312,46 +523,102 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                     "algorithmic_bytes_per_launch": pbytes, "avg_launch_us": round(kernel_us, 3),
                     "timed": "HIP events around every launch of the timed region"}
+    flush_buf = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device="cuda")
+
+    def flush():
+        flush_buf.fill_(counter[0] & 0xFF)
+
+    def one_submit():
+        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs, stream))
+
     if not args.no_timing:
-        # per-phase breakdown: the same batches as one kernel per phase, one
-        # stream (no overlap between batches, so each kernel runs alone)
-        n_streams_timed = n_streams
-        n_streams = 1
-        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
-        ctx.ft_context_enable_timing(True)
-        for _ in range(args.steps):
-            submit_bounded()
-        drain()
-        tm = ctx.ft_context_read_timing()
-        ctx.ft_context_enable_timing(False)
+        n_t = max(20, args.steps)
+        phases = phase_times(ctx, ft, one_submit, n_t)
+        phases_cold = phase_times(ctx, ft, one_submit, max(10, n_t // 2), flush=flush)
         ctx.ft_set_exec_mode(modes[exec_mode])
-        n_streams = n_streams_timed
-        phases = {k: {"avg_us": (ms / n * 1e3) if n else None, "launches": n}
-                  for k, (ms, n) in tm.items() if n}
         dom = max(phases, key=lambda k: phases[k]["avg_us"] or 0)
-        sbytes = algorithmic_search_bytes(frames, res)
-        s_us = phases["search"]["avg_us"]
-        achieved = sbytes / (s_us * 1e-6) / 1e9
-        search_roof = {"bound": "hbm", "kernel": "k_search (search by projection)",
-                       "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 5),
-                       "traffic": measured_traffic("k_search<JobTable>"),
-                       "algorithmic_bytes_per_launch": sbytes, "avg_launch_us": round(s_us, 3),
-                       "timed": "HIP events around each phase kernel, eager per-phase pass",
-                       "dominant_phase": dom}
+        sbytes = algorithmic_search_bytes(frames)
+        search_roof = search_roofline(sbytes, phases["search"]["avg_us"],
+                                      measured_traffic("k_search<JobTable>", "mixed_batch64"),
+                                      "HIP events around each phase kernel, eager per-phase pass, warm caches")
+        search_roof["dominant_phase"] = dom
+        cold = search_roofline(sbytes, phases_cold["search"]["avg_us"], None,
+                               "as warm, with a 512 MB write before every submission")
+        search_roof["cold"] = {k: cold[k] for k in ("achieved", "frac", "avg_launch_us", "timed")}
         if roofline is None:
             roofline = search_roof
         else:
             phases["search_roofline"] = search_roof
 
+    # ---- the three single-frame workloads: per-frame latency through the
+    # single-frame calls (host wall time from the call to the stream's end)
+    configs = None
+    clustered = None
+    if not args.no_extra:
+        configs = {}
+        reps = max(100, args.steps * 5)
+        for name, f in single.items():
+            d = ft.DeviceFrame(f, "cuda")
+            for _ in range(10):
+                d.run(ctx, stream)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                s0 = time.perf_counter()
+                d.run(ctx, stream)
+                stream.synchronize()
+                ts.append((time.perf_counter() - s0) * 1e3)
+            configs[name] = {**percentiles(ts), "frame_pairs_per_s": round(1e3 / float(np.mean(ts)), 1),
+                             "reps": reps}
+            log("single frame", name, configs[name])
+
+        # ---- the clustered scene over 64 seeds in one submission
+        log("clustered scene over 64 seeds")
+        cframes = synth.clustered_batch()
+        cdfs = [ft.DeviceFrame(f, "cuda") for f in cframes]
+        cjobs = [d.job() for d in cdfs]
+        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
+        for _ in range(5):
+            ctx.ft_batch_wait(ctx.ft_batch_submit(cjobs, stream))
+        torch.cuda.synchronize()
+        csteps = max(20, args.steps)
+        c0 = time.perf_counter()
+        tickets = []
+        for _ in range(csteps):
+            if len(tickets) >= ctx.limits.max_inflight:
+                ctx.ft_batch_wait(tickets.pop(0))
+            tickets.append(ctx.ft_batch_submit(cjobs, stream))
+        for t in tickets:
+            ctx.ft_batch_wait(t)
+        torch.cuda.synchronize()
+        cdt = time.perf_counter() - c0
+        clustered = {"workload": "clustered local map, 20000 map points in 40 blobs + 3000 keypoints, "
+                                 "752x480 pinhole, 96x64 grid, 64 seeds, one submission per step",
+                     "frame_pairs_per_s": round(len(cframes) * csteps / cdt, 1),
+                     "ms_per_step": round(cdt * 1e3 / csteps, 4), "steps": csteps}
+        if not args.no_timing:
+            def csub():
+                ctx.ft_batch_wait(ctx.ft_batch_submit(cjobs, stream))
+            cph = phase_times(ctx, ft, csub, csteps)
+            cph_cold = phase_times(ctx, ft, csub, max(10, csteps // 2), flush=flush)
+            cb = algorithmic_search_bytes(cframes)
+            croof = search_roofline(cb, cph["search"]["avg_us"],
+                                    measured_traffic("k_search<JobTable>", "clustered64"),
+                                    "HIP events around each phase kernel, eager per-phase pass, warm caches")
+            cold = search_roofline(cb, cph_cold["search"]["avg_us"], None,
+                                   "as warm, with a 512 MB write before every submission")
+            croof["cold"] = {k: cold[k] for k in ("achieved", "frac", "avg_launch_us", "timed")}
+            clustered["phases"] = cph
+            clustered["roofline"] = croof
+        log("clustered", clustered["frame_pairs_per_s"], clustered.get("roofline", {}).get("frac"))
+        ctx.ft_set_exec_mode(modes[exec_mode])
+        del cdfs
+
     serving = None
     if args.serving > 0:
-        serving = serving_sweep(args.serving, [1, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384])
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        cpu = cpu_baseline(frames)
+        del copies, dfs
+        torch.cuda.empty_cache()
+        serving = serving_sweep(args.serving, [2, 4, 8, 12, 16], [16, 64, 128, 192, 256, 384])
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "frame-pairs/s", "n_gpus": 1,
@@ -365,12 +632,14 @@ def main():
                    "submit_streams": n_streams, "exec_trial_fps": trial or None,
                    "pinhole_frames": sum(f["kind"] == "pinhole" for f in frames),
                    "fisheye_frames": sum(f["kind"] == "fisheye" for f in frames)},
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                       "p99": round(float(np.percentile(lat, 99)), 4), "per": "64-frame submission"},
+        "latency_ms": {**percentiles(lat), "per": "64-frame submission"},
         "per_frame_path_fps": round(plain_fps, 2),
         "phases": phases,
+        "phases_cold": phases_cold,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "single_frame_workloads": configs,
+        "clustered_batch64": clustered,
         "serving": serving,
     }
     print(json.dumps(out))

@@ -101,14 +101,21 @@ def perturbed_pose(rng, R_cw: np.ndarray, t_cw: np.ndarray,
 
 def rotate_within(rng, v: np.ndarray, max_deg: float) -> np.ndarray:
     """Rotate each unit row of v by a random angle in [0, max_deg] about a random
-    axis perpendicular to it."""
-    out = np.empty_like(v)
-    for i in range(v.shape[0]):
-        a = random_unit(rng)
-        a = a - np.dot(a, v[i]) * v[i]
-        a /= np.linalg.norm(a)
-        out[i] = rodrigues(a, np.deg2rad(rng.uniform(0.0, max_deg))) @ v[i]
-    return out
+    axis perpendicular to it.  The draws are taken row by row (a direction, then
+    an angle), the rotation itself is done for all rows at once."""
+    n = v.shape[0]
+    g = np.empty((n, 3))
+    ang = np.empty(n)
+    for i in range(n):
+        g[i] = rng.standard_normal(3)
+        ang[i] = rng.uniform(0.0, max_deg)
+    a = g / np.linalg.norm(g, axis=1, keepdims=True)
+    a = a - np.sum(a * v, axis=1, keepdims=True) * v
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    th = np.deg2rad(ang)[:, None]
+    av = np.cross(a, v)
+    # Rodrigues' formula for an axis perpendicular to the vector
+    return v + av * np.sin(th) + np.cross(a, av) * (1.0 - np.cos(th))
 
 
 def pose_dict(R, t, O):

@@ -10,6 +10,7 @@ from SeedSequence.spawn.
                           3000 kp, 96x64 grid (offset 3)
   mixed_batch             64 frames, 32 pinhole + 32 fisheye in seeded order,
                           kp ~ U{300..3000}, map ~ U{1000..20000} (offset 4)
+  clustered_batch         the clustered scene over 64 seeds spawned from offset 3
 """
 from __future__ import annotations
 
@@ -52,6 +53,13 @@ def mixed_batch(seed=None, n_frames: int = 64):
         else:
             frames.append(fisheye_frame(frame_ss[i], n_kp=int(n_kp[i]), n_map=int(n_map[i])))
     return frames
+
+
+def clustered_batch(seed=None, n_frames: int = 64):
+    """The clustered local-map scene (20000 map points, 3000 keypoints, 96x64
+    grid) over `n_frames` seeds, for one batched submission."""
+    ss = seed if seed is not None else seed_of(3)
+    return [clustered_frame(s) for s in ss.spawn(n_frames)]
 
 
 def tiny_pinhole(seed, n_kp: int = 80, n_map: int = 120, grid=(12, 8)):
