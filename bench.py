@@ -67,29 +67,6 @@ def algorithmic_search_bytes(frames):
     return total
 
 
-def algorithmic_path_bytes(frames, results):
-    """Compulsory bytes of the whole path (stereo + search) for one step.
-
-    Stereo, per image keypoint: x 4 + y 4 + level 1 + descriptor 32 read.
-    Pinhole: per left keypoint 20 B of outputs (right index, distance, right
-    coordinate, depth, SAD), and per final match the two SAD windows of the
-    refinement, 11x11 left + 11x21 right = 352 B (final matches only, so a
-    lower bound).  Fisheye: per left keypoint 24 B of outputs (right index,
-    distance, depth, point).  Search: as `algorithmic_search_bytes`.
-    """
-    total = algorithmic_search_bytes(frames)
-    for f, r in zip(frames, results):
-        if "right" not in f:
-            continue
-        nL, nR = len(f["left"]["x"]), len(f["right"]["x"])
-        total += 41 * (nL + nR)
-        if f["kind"] == "pinhole":
-            total += 20 * nL + 352 * int((r["stereo"]["right_idx"] >= 0).sum())
-        else:
-            total += 24 * nL
-    return total
-
-
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_10757_amd", "csrc", "ft_kernels.hip")
 
 
@@ -335,11 +312,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of each oracle leg")
     ap.add_argument("--shapes", type=str, default="",
-                    help="best_lanes,search_lanes[,search_block,best_block,aux_block] instead of autotuning")
+                    help="best_lanes,search_lanes[,aux_block] instead of autotuning")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel event passes")
-    ap.add_argument("--exec", choices=["auto", "graph", "persistent", "eager"], default="auto",
-                    help="batch execution mode; auto times the modes and submission streams briefly")
-    ap.add_argument("--parts", type=int, default=1, help="submission split (with an explicit --exec)")
+    ap.add_argument("--exec", choices=["auto", "graph", "eager"], default="auto",
+                    help="batch execution mode; auto times graph mode on 1-4 submission streams briefly")
     ap.add_argument("--streams", type=int, default=1, choices=[1, 2, 3, 4],
                     help="submission streams (with an explicit --exec)")
     ap.add_argument("--serving", type=float, default=0.6, metavar="SECONDS",
@@ -433,14 +409,12 @@ def main():
             ctx.ft_batch_wait(pending.pop(0))
         torch.cuda.synchronize()
 
-    modes = {"graph": ft.FT_EXEC_GRAPH, "persistent": ft.FT_EXEC_PERSISTENT, "eager": ft.FT_EXEC_EAGER}
+    modes = {"graph": ft.FT_EXEC_GRAPH, "eager": ft.FT_EXEC_EAGER}
     trial = {}
     if args.exec == "auto" and not profiling:
-        # execution mode and submission streams: a short timed trial of each
-        cands = [("graph", 1, k) for k in range(1, max_streams + 1)] + [("persistent", 1, 1)]
-        for name, parts, ns in cands:
-            ctx.ft_set_exec_mode(modes[name])
-            ctx.ft_set_batch_parts(parts)
+        # submission streams: a short timed trial of each count
+        for ns in range(1, max_streams + 1):
+            ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
             n_streams = ns
             for _ in range(10):
                 submit_bounded()
@@ -449,18 +423,16 @@ def main():
             for _ in range(60):
                 submit_bounded()
             drain()
-            key = f"{name}/{parts}/s{ns}"
+            key = f"graph/s{ns}"
             trial[key] = round(n_frames * 60 / (time.perf_counter() - q0), 1)
             log("trial", key, trial[key])
         best = max(trial, key=trial.get)
-        exec_mode, n_parts, n_streams = best.split("/")[0], int(best.split("/")[1]), int(best.split("/s")[1])
+        exec_mode, n_streams = "graph", int(best.split("/s")[1])
     elif profiling:
-        exec_mode, n_parts, n_streams = (args.exec if args.exec != "auto" else "graph"), 1, 1
+        exec_mode, n_streams = (args.exec if args.exec != "auto" else "graph"), 1
     else:
-        exec_mode, n_parts, n_streams = args.exec, args.parts, args.streams
+        exec_mode, n_streams = args.exec, args.streams
     ctx.ft_set_exec_mode(modes[exec_mode])
-    ctx.ft_set_batch_parts(n_parts)
-    persistent = exec_mode == "persistent"
 
     log("warmup", args.warmup)
     for _ in range(args.warmup):
@@ -469,22 +441,14 @@ def main():
 
     # ---- timed region: K back-to-back batch submissions, rotating over
     # n_streams streams (each with its own copy of the frames), so one batch's
-    # latency-bound phases overlap the next one's search.  A persistent batch
-    # is one kernel, bracketed by HIP events on its stream.
+    # latency-bound phases overlap the next one's search.
     log("timed", args.steps, exec_mode)
-    if persistent:
-        ctx.ft_context_enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         submit_bounded()
     drain()
     dt = time.perf_counter() - t0
-    kernel_us = None
-    if persistent:
-        ms, n = ctx.ft_context_read_timing()["persistent_batch"]
-        ctx.ft_context_enable_timing(False)
-        kernel_us = ms / n * 1e3 if n else None
     ms_per_step = dt * 1e3 / args.steps
     value = n_frames * args.steps / dt
     if profiling:
@@ -514,15 +478,6 @@ def main():
     # ---- per-kernel timing with HIP events on the launch stream, warm and
     # with the last-level cache flushed before every submission
     roofline, phases, phases_cold = None, None, None
-    res = [d.results() for d in dfs]
-    if persistent and kernel_us:
-        pbytes = algorithmic_path_bytes(frames, res)
-        achieved = pbytes / (kernel_us * 1e-6) / 1e9
-        roofline = {"bound": "hbm", "kernel": "k_persistent (whole batch: stereo + search)",
-                    "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                    "algorithmic_bytes_per_launch": pbytes, "avg_launch_us": round(kernel_us, 3),
-                    "timed": "HIP events around every launch of the timed region"}
     flush_buf = torch.empty(FLUSH_BYTES, dtype=torch.uint8, device="cuda")
 
     def flush():
@@ -545,10 +500,7 @@ def main():
         cold = search_roofline(sbytes, phases_cold["search"]["avg_us"], None,
                                "as warm, with a 512 MB write before every submission")
         search_roof["cold"] = {k: cold[k] for k in ("achieved", "frac", "avg_launch_us", "timed")}
-        if roofline is None:
-            roofline = search_roof
-        else:
-            phases["search_roofline"] = search_roof
+        roofline = search_roof
 
     # ---- the three single-frame workloads: per-frame latency through the
     # single-frame calls (host wall time from the call to the stream's end)
@@ -626,9 +578,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "frames_per_step": n_frames,
-                   "shapes": dict(zip(("best_lanes", "search_lanes", "search_block", "best_block",
-                                       "aux_block"), shapes)),
-                   "exec": exec_mode, "batch_parts": n_parts,
+                   "shapes": dict(zip(("best_lanes", "search_lanes", "aux_block"), shapes)),
+                   "exec": exec_mode,
                    "submit_streams": n_streams, "exec_trial_fps": trial or None,
                    "pinhole_frames": sum(f["kind"] == "pinhole" for f in frames),
                    "fisheye_frames": sum(f["kind"] == "fisheye" for f in frames)},

@@ -10,8 +10,9 @@
  *     the current frame's keypoints, each map point independently of the others
  *     (Section II-D "Track Local Map"; Section IV-E "Search Local Points").
  * Memory is allocated once when a context is created and reused for every
- * frame (Section IV-B: allocate at start, release at shutdown), so no call
- * after ft_context_create allocates device memory.
+ * frame (Section IV-A: allocate at start, release at shutdown), so no call
+ * after ft_context_create allocates device memory (ft_host_alloc, which
+ * allocates pinned host memory, is the one set-up call besides it).
  *
  * Conventions for every entry point:
  *   - Pointers inside ft_keypoints, ft_pyramid, ft_map_points and the *_out
@@ -56,7 +57,6 @@ typedef int32_t ft_status;
 #define FT_ERR_CAPACITY 2         /* input exceeds the context's ft_limits */
 #define FT_ERR_DEVICE 3           /* a HIP call failed (sticky) */
 #define FT_ERR_UNSUPPORTED 4      /* feature or device not supported */
-#define FT_ERR_ABORTED 5          /* a persistent batch gave up waiting; its outputs are invalid (not sticky) */
 
 #define FT_LEVELS 8               /* pyramid levels (ORB scale pyramid) */
 #define FT_DESC_BYTES 32          /* 256-bit descriptor */
@@ -71,6 +71,11 @@ typedef struct ft_limits {
     int32_t max_grid_cells;    /* grid cols * rows, <= 8192 */
     int32_t max_batch_frames;  /* frames per ft_batch_submit */
     int32_t max_inflight;      /* batch tickets in flight at once */
+    int32_t max_levels;        /* pyramid levels: must be FT_LEVELS (8) */
+    int32_t max_batch_kp_total;   /* keypoints (left + right) of all frames of one batch;
+                                     0 = max_batch_frames * 2 * max_kp_per_image */
+    int32_t max_batch_map_total;  /* map points of all frames of one batch;
+                                     0 = max_batch_frames * max_map_points */
 } ft_limits;
 
 /* One image's keypoints (structure of arrays, device memory). */
@@ -306,70 +311,38 @@ ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done);
 ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket);
 
 /* How a batch is executed on the device:
- *   FT_EXEC_EAGER       the table upload and one kernel per phase, launched on
- *                       the stream one by one;
- *   FT_EXEC_GRAPH       the same work as one HIP graph launch; each in-flight
- *                       lane keeps the instantiated graph of every batch shape
- *                       it has seen (frame count, tiles per phase, lane
- *                       groups), so a repeated shape is relaunched without
- *                       capture (the default);
- *   FT_EXEC_PERSISTENT  one persistent kernel per batch: workgroups take tasks
- *                       (phase, frame, tile) from a queue in phase order and
- *                       wait, with a bounded spin, until the earlier phases of
- *                       the task's frame are complete, so phases of different
- *                       frames overlap; one kernel launch after the table
- *                       upload, followed by a 4-byte copy of its status.
- * Results are identical in every mode.  While per-phase timing is enabled,
- * graph batches run eagerly so that each phase can be bracketed by events;
- * persistent batches are timed as a whole.
+ *   FT_EXEC_EAGER  the table upload and one kernel per phase, launched on the
+ *                  stream one by one;
+ *   FT_EXEC_GRAPH  the same work as one HIP graph launch (the default).  Each
+ *                  in-flight lane holds one instantiated graph, built when the
+ *                  context is created and rebuilt only by ft_set_shapes and
+ *                  ft_autotune; a submission updates the graph's nodes (table
+ *                  size, grid of every phase) in place and launches it, so
+ *                  batches of any shape run without capture or allocation.
+ * Results are identical in both modes.  While per-phase timing is enabled,
+ * graph batches run eagerly so that each phase can be bracketed by events.
  * Returns FT_ERR_INVALID_ARGUMENT for an unknown mode. */
 #define FT_EXEC_EAGER 0
 #define FT_EXEC_GRAPH 1
-#define FT_EXEC_PERSISTENT 2
 ft_status ft_set_exec_mode(ft_context *ctx, int32_t mode);
 ft_status ft_get_exec_mode(const ft_context *ctx, int32_t *mode);
 
-/* Split every batch submission into `parts` (1..4; default 1) runs of
- * consecutive frames with about equal work.  Each run is launched (eagerly or
- * as its own graph) on an internal stream of the context that first waits for
- * the caller's stream; the caller's stream then waits for all of them, so
- * completion, ft_batch_poll and ft_batch_wait behave as for one launch.  The
- * runs overlap on the device: one run's latency-bound phases (sorts, median)
- * share the GPU with another's search.  Results are identical for every value.
- * Persistent batches and timed batches (per-phase timing enabled) are not
- * split.  Out of range: FT_ERR_INVALID_ARGUMENT. */
-ft_status ft_set_batch_parts(ft_context *ctx, int32_t parts);
-ft_status ft_get_batch_parts(const ft_context *ctx, int32_t *parts);
-
-/* Settings of FT_EXEC_PERSISTENT.  `blocks`: workgroups of the persistent
- * kernel, 0 = as many as fit on the device at once (the default; the grid is
- * never larger than the batch's task count).  `spin_limit`: sleeps one
- * dependency wait may take before the kernel gives up, 0 = the default (about
- * a second).  A batch that gave up skips its remaining tasks; ft_batch_poll /
- * ft_batch_wait of its ticket then return FT_ERR_ABORTED and its outputs are
- * invalid; the context stays usable.  Negative values: FT_ERR_INVALID_ARGUMENT. */
-ft_status ft_set_persistent(ft_context *ctx, int32_t blocks, int32_t spin_limit);
-
-/* Launch shapes of the search kernels: how many lanes of a wave cooperate on
- * one query.  Results never depend on them, only the time does. */
+/* Launch shapes of the batch kernels.  Results never depend on them, only the
+ * time does. */
 typedef struct ft_shapes {
-    int32_t best_lanes;        /* lanes per pinhole left keypoint of the 256-thread best match:
+    int32_t best_lanes;        /* lanes per pinhole left keypoint of the best match:
                                   1, 2, 4, 8 or 16 */
-    int32_t search_lanes;      /* lanes per map point of the 256-thread search: 1, 2, 4, 8 or 16 */
-    int32_t search_block;      /* threads per search workgroup: 1024 = one lane per map point,
-                                  the view's grid staged in LDS (views whose grid exceeds 64 KiB
-                                  scan global memory); 256 = global-memory scan with
-                                  search_lanes lanes per map point */
-    int32_t best_block;        /* threads per stereo best-match workgroup: 1024 = the frame's row
-                                  records staged in LDS, 8 lanes per left keypoint, fisheye kNN
-                                  in four 16-query subgroups; 256 = global scan with best_lanes */
+    int32_t search_lanes;      /* lanes per map point of the search: 1 (record-dealt: a wave deals
+                                  its 64 map points' window records evenly over its lanes),
+                                  2, 4, 8 or 16 (lane groups stride each window) */
     int32_t aux_block;         /* threads per workgroup of the setup sorts and the stereo
                                   resolve: 256 or 1024 */
 } ft_shapes;
 
-/* A new context starts with best_lanes 8, search_lanes 1, search_block 256,
- * best_block 256, aux_block 1024 (the shapes the autotuner picks for mixed
- * pinhole/fisheye batches). */
+/* A new context starts with best_lanes 8, search_lanes 1, aux_block 1024 (the
+ * shapes the autotuner picks for mixed pinhole/fisheye batches).  Setting
+ * shapes rebuilds the in-flight lanes' batch graphs (a set-up call: it waits
+ * for the batches in flight, and graph instantiation may allocate). */
 ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *shapes);
 ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *shapes);
 
@@ -429,12 +402,11 @@ const char *ft_last_error(const ft_context *ctx);
  * 0 setup (row index / overlap lists / grids), 1 stereo best match (pinhole
  * row band or fisheye all-pairs), 2 pinhole refinement, 3 fisheye
  * triangulation check, 4 stereo resolve + outputs, 5 search by projection,
- * 6 search resolve + outputs, 7 a whole FT_EXEC_PERSISTENT batch (its one
- * kernel; in that mode phases 0-6 are not timed separately).
+ * 6 search resolve + outputs.
  * ft_context_read_timing waits for the recorded work, returns the summed
  * milliseconds and launch counts per phase (arrays of FT_PHASES), and resets
  * them.  Enabling timing adds event records between kernels. */
-#define FT_PHASES 8
+#define FT_PHASES 7
 ft_status ft_context_enable_timing(ft_context *ctx, int32_t enable);
 ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches);
 /* Library version as major*10000 + minor*100 + patch. */

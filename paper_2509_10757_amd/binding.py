@@ -18,11 +18,10 @@ from . import build as _build
 
 LEVELS = 8
 FT_OK, FT_ERR_INVALID_ARGUMENT, FT_ERR_CAPACITY, FT_ERR_DEVICE, FT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
-FT_ERR_ABORTED = 5
-FT_PHASES = 8
+FT_PHASES = 7
 FT_CAMERA_PINHOLE, FT_CAMERA_KB = 0, 1
 FT_JOB_PINHOLE, FT_JOB_FISHEYE, FT_JOB_SEARCH = 1, 2, 3
-FT_EXEC_EAGER, FT_EXEC_GRAPH, FT_EXEC_PERSISTENT = 0, 1, 2
+FT_EXEC_EAGER, FT_EXEC_GRAPH = 0, 1
 
 P = ct.c_void_p
 F8 = ct.c_float * LEVELS
@@ -31,7 +30,9 @@ F8 = ct.c_float * LEVELS
 class ft_limits(ct.Structure):
     _fields_ = [("max_kp_per_image", ct.c_int32), ("max_map_points", ct.c_int32),
                 ("max_rows", ct.c_int32), ("max_grid_cells", ct.c_int32),
-                ("max_batch_frames", ct.c_int32), ("max_inflight", ct.c_int32)]
+                ("max_batch_frames", ct.c_int32), ("max_inflight", ct.c_int32),
+                ("max_levels", ct.c_int32), ("max_batch_kp_total", ct.c_int32),
+                ("max_batch_map_total", ct.c_int32)]
 
 
 class ft_keypoints(ct.Structure):
@@ -129,8 +130,7 @@ class ft_segment(ct.Structure):
 
 
 class ft_shapes(ct.Structure):
-    _fields_ = [("best_lanes", ct.c_int32), ("search_lanes", ct.c_int32), ("search_block", ct.c_int32),
-                ("best_block", ct.c_int32), ("aux_block", ct.c_int32)]
+    _fields_ = [("best_lanes", ct.c_int32), ("search_lanes", ct.c_int32), ("aux_block", ct.c_int32)]
 
 
 EXPORTS = {
@@ -155,9 +155,6 @@ EXPORTS = {
     "ft_context_read_timing": [P, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)],
     "ft_set_exec_mode": [P, ct.c_int32],
     "ft_get_exec_mode": [P, ct.POINTER(ct.c_int32)],
-    "ft_set_persistent": [P, ct.c_int32, ct.c_int32],
-    "ft_set_batch_parts": [P, ct.c_int32],
-    "ft_get_batch_parts": [P, ct.POINTER(ct.c_int32)],
     "ft_set_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_get_shapes": [P, ct.POINTER(ft_shapes)],
     "ft_autotune": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.c_char_p, ct.POINTER(ft_shapes)],
@@ -202,7 +199,8 @@ class FtError(RuntimeError):
 
 def default_limits(**kw) -> ft_limits:
     v = dict(max_kp_per_image=4096, max_map_points=65536, max_rows=1024, max_grid_cells=8192,
-             max_batch_frames=64, max_inflight=2)
+             max_batch_frames=64, max_inflight=2, max_levels=LEVELS, max_batch_kp_total=0,
+             max_batch_map_total=0)
     v.update(kw)
     return ft_limits(**v)
 
@@ -247,7 +245,7 @@ class Context:
         return v.value
 
     PHASES = ("setup", "stereo_best", "pinhole_refine", "fisheye_triangulate", "stereo_resolve",
-              "search", "search_resolve", "persistent_batch")
+              "search", "search_resolve")
 
     def ft_context_enable_timing(self, enable: bool = True):
         self._check(self.lib.ft_context_enable_timing(self.h, int(enable)), "enable_timing")
@@ -321,31 +319,19 @@ class Context:
     def ft_set_exec_mode(self, mode: int):
         self._check(self.lib.ft_set_exec_mode(self.h, mode), "ft_set_exec_mode")
 
-    def ft_set_batch_parts(self, parts: int):
-        self._check(self.lib.ft_set_batch_parts(self.h, parts), "ft_set_batch_parts")
-
-    def ft_get_batch_parts(self) -> int:
-        v = ct.c_int32()
-        self._check(self.lib.ft_get_batch_parts(self.h, ct.byref(v)), "ft_get_batch_parts")
-        return v.value
-
-    def ft_set_persistent(self, blocks: int = 0, spin_limit: int = 0):
-        self._check(self.lib.ft_set_persistent(self.h, blocks, spin_limit), "ft_set_persistent")
-
     def ft_get_exec_mode(self) -> int:
         m = ct.c_int32()
         self._check(self.lib.ft_get_exec_mode(self.h, ct.byref(m)), "ft_get_exec_mode")
         return m.value
 
-    def ft_set_shapes(self, best_lanes: int, search_lanes: int, search_block: int = 256,
-                      best_block: int = 256, aux_block: int = 1024):
-        sh = ft_shapes(best_lanes, search_lanes, search_block, best_block, aux_block)
+    def ft_set_shapes(self, best_lanes: int, search_lanes: int, aux_block: int = 1024):
+        sh = ft_shapes(best_lanes, search_lanes, aux_block)
         self._check(self.lib.ft_set_shapes(self.h, ct.byref(sh)), "ft_set_shapes")
 
     def ft_get_shapes(self) -> tuple:
         s = ft_shapes()
         self._check(self.lib.ft_get_shapes(self.h, ct.byref(s)), "ft_get_shapes")
-        return s.best_lanes, s.search_lanes, s.search_block, s.best_block, s.aux_block
+        return s.best_lanes, s.search_lanes, s.aux_block
 
     def ft_autotune(self, jobs, cache_path=None, stream=None) -> tuple:
         arr = (ft_frame_job * len(jobs))(*jobs)
@@ -353,7 +339,7 @@ class Context:
         cp = cache_path.encode() if cache_path else None
         self._check(self.lib.ft_autotune(self.h, _stream(stream), arr, len(jobs), cp, ct.byref(s)),
                     "ft_autotune")
-        return s.best_lanes, s.search_lanes, s.search_block, s.best_block, s.aux_block
+        return s.best_lanes, s.search_lanes, s.aux_block
 
     def ft_batch_poll(self, ticket: int) -> bool:
         d = ct.c_int32()
@@ -519,19 +505,22 @@ class DeviceFrame:
             ctx.ft_search_local_points(self.map, v["cam"], v["kps"].struct(), ur, _ptr(v["pre_t"]),
                                        v["grid"], self.scales, self.search_params, v["out"], stream=stream)
 
-    def job(self) -> ft_frame_job:
+    def job(self, stereo: bool = True) -> ft_frame_job:
+        """The frame as a batch job; stereo=False submits its search views only
+        (a search job, for frames whose views need no stereo output)."""
         j = ft_frame_job()
-        j.kind = {"pinhole": FT_JOB_PINHOLE, "fisheye": FT_JOB_FISHEYE}.get(self.kind, FT_JOB_SEARCH)
+        kind = self.kind if stereo else "search"
+        j.kind = {"pinhole": FT_JOB_PINHOLE, "fisheye": FT_JOB_FISHEYE}.get(kind, FT_JOB_SEARCH)
         j.n_views = len(self.views)
         j.left = self.left.struct()
         if self.right is not None:
             j.right = self.right.struct()
         j.scales = self.scales
-        if self.kind == "pinhole":
+        if kind == "pinhole":
             j.pyr_left, j.pyr_right = self.pyr_left, self.pyr_right
             j.pinhole, j.pinhole_params, j.pinhole_out = self.stereo_cam, self.stereo_params, self.stereo_out
             j.use_u_right = int(self.views[0]["use_u_right"]) if self.views else 0
-        elif self.kind == "fisheye":
+        elif kind == "fisheye":
             j.fisheye, j.fisheye_params, j.fisheye_out = self.stereo_cam, self.stereo_params, self.stereo_out
         j.map = self.map
         for i, v in enumerate(self.views):

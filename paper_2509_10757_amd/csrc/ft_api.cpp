@@ -35,56 +35,47 @@ struct Slot {  // workspace of one frame
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Layout of one batch table (one per part of a submission): the tile prefix
-// sums, the persistent kernel's state (always zero in the staging copy, so the
-// upload itself resets it), then the job descriptors.  One upload of the first
-// upload_bytes(n) bytes moves everything a launch reads.
+// Layout of one batch table: the tile prefix sums, then the job descriptors.
+// One upload of the first upload_bytes(n) bytes moves everything a launch
+// reads.
 struct TableLayout {
-    size_t prefix_off = 0, state_off = 0, jobs_off = 0, total = 0;
+    size_t prefix_off = 0, jobs_off = 0, total = 0;
     size_t upload_bytes(int n) const { return jobs_off + sizeof(DevJob) * (size_t)n; }
 };
 
 TableLayout table_layout(int max_frames)
 {
     TableLayout t;
-    t.state_off = align_up(sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1), 256);
-    t.jobs_off = align_up(t.state_off + sizeof(int32_t) * (kPersistHdrInts + PH_COUNT * (size_t)max_frames), 256);
+    t.jobs_off = align_up(sizeof(int32_t) * PH_COUNT * (size_t)(max_frames + 1), 256);
     t.total = align_up(t.jobs_off + sizeof(DevJob) * (size_t)max_frames, 256);
     return t;
 }
 
-// A batch submission runs as up to kMaxParts parts of consecutive frames, each
-// on its own internal stream, so that the latency-bound phases of one part
-// overlap the others.
-constexpr int kMaxParts = 4;
-
-struct GraphEntry {  // an instantiated batch graph and the shape it was built for
-    int32_t part = 0;
-    int32_t n = 0;
-    int32_t totals[PH_COUNT] = {};
-    Shapes shapes;
+// A lane's batch graph: the table upload followed by one kernel node per
+// phase, in phase order.  Built once per shape setting; a submission sets the
+// upload size and each kernel's grid and argument in the instantiated graph.
+struct BatchGraph {
+    hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t last_use = 0;
+    hipGraphNode_t copy = nullptr;
+    hipGraphNode_t kern[PH_COUNT] = {};
+    void *fn[PH_COUNT] = {};
+    int block[PH_COUNT] = {};
+    int32_t n = -1;                  // job count of the last submission (kernel argument)
+    int32_t grid[PH_COUNT] = {};     // grids of the last submission
 };
 
 struct Lane {  // one batch in flight
     std::vector<Slot> slots;
-    std::vector<GraphEntry> graphs;
-    char *d_table = nullptr;   // device: kMaxParts tables (prefixes | persistent state | jobs)
+    BatchGraph g;
+    char *d_table = nullptr;   // device: prefixes | jobs
     char *h_table = nullptr;   // pinned staging of the same bytes
-    hipEvent_t fork = nullptr, join[kMaxParts] = {};   // split submissions
-    int32_t *h_abort = nullptr;   // pinned: the persistent kernel's abort flag after the batch
     hipEvent_t done = nullptr;
     uint64_t ticket = 0;
     bool used = false;
-    bool persistent = false;   // the batch in flight ran as one persistent kernel
 };
 
 }  // namespace
-
-struct ft_context;
-static char *h_part(const ft_context *ctx, const Lane &l, int part);
-static char *d_part(const ft_context *ctx, const Lane &l, int part);
 
 struct ft_context {
     int device = 0;
@@ -99,31 +90,16 @@ struct ft_context {
     uint64_t next_ticket = 1;
     Shapes shapes;
     int32_t exec_mode = FT_EXEC_GRAPH;
-    hipStream_t cap_stream = nullptr;   // graphs are captured here, launched on the caller's stream
-    hipStream_t part_streams[kMaxParts] = {};   // parts of a split submission run here
-    int32_t n_parts = 1;
-    int32_t persist_blocks = 0;         // 0: as many workgroups as fit on the device
-    int32_t persist_spin = kPersistSpinLimit;
-    uint64_t use_clock = 0;
+    int64_t batch_kp_cap = 0, batch_map_cap = 0;   // per-submission totals (ft_limits)
     // per-phase timing: a ring of event sets, drained when it wraps or on read
     bool timing = false;
     std::vector<std::vector<hipEvent_t>> ev_sets;
-    std::vector<uint8_t> ev_pending;   // 0 free, 1 per-phase marks, 2 persistent batch
+    std::vector<uint8_t> ev_pending;   // 0 free, 1 per-phase marks pending
     size_t ev_next = 0;
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
     std::vector<std::pair<char *, size_t>> host_blocks;   // ft_host_alloc blocks (upload sources)
 };
-
-static char *h_part(const ft_context *ctx, const Lane &l, int part)
-{
-    return l.h_table + (size_t)part * ctx->layout.total;
-}
-
-static char *d_part(const ft_context *ctx, const Lane &l, int part)
-{
-    return l.d_table + (size_t)part * ctx->layout.total;
-}
 
 namespace {
 
@@ -161,6 +137,17 @@ struct Bump {
     }
 };
 
+// Workspace of one search view: cell offsets, cell records (a keypoint in up
+// to kMaxCellRep level bins), per-map-point candidates, claim table.
+void carve_view(Slot &s, int v, char *base, Bump &b, size_t kp, size_t mp)
+{
+    s.view[v].cell_off = b.take<int32_t>(base, (size_t)kMaxCells + 1);
+    s.view[v].crec = b.take<CellRec>(base, (size_t)kMaxCellRep * kp);
+    s.view[v].mp_k = b.take<int32_t>(base, mp);
+    s.view[v].mp_h = b.take<int32_t>(base, mp);
+    s.view[v].claim = b.take<uint32_t>(base, kp);
+}
+
 void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
 {
     const size_t kp = (size_t)L.max_kp_per_image, mp = (size_t)L.max_map_points;
@@ -180,13 +167,7 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     s.depth = b.take<float>(base, kp);
     s.xyz = b.take<float>(base, 3 * kp);
     s.claimR = b.take<uint32_t>(base, kp);
-    for (int v = 0; v < 2; ++v) {
-        s.view[v].cell_off = b.take<int32_t>(base, (size_t)kMaxCells + 1);
-        s.view[v].crec = b.take<CellRec>(base, (size_t)kMaxCellRep * kp);
-        s.view[v].mp_k = b.take<int32_t>(base, mp);
-        s.view[v].mp_h = b.take<int32_t>(base, mp);
-        s.view[v].claim = b.take<uint32_t>(base, kp);
-    }
+    for (int v = 0; v < 2; ++v) carve_view(s, v, base, b, kp, mp);
 }
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -508,16 +489,6 @@ void drain_set(ft_context *ctx, size_t k)
 {
     if (!ctx->ev_pending[k]) return;
     auto &ev = ctx->ev_sets[k];
-    if (ctx->ev_pending[k] == 2) {
-        hipEventSynchronize(ev[1]);
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) {
-            ctx->phase_ms[kPersistSlot] += ms;
-            ctx->phase_n[kPersistSlot] += 1;
-        }
-        ctx->ev_pending[k] = 0;
-        return;
-    }
     hipEventSynchronize(ev[PH_COUNT]);
     for (int p = 0; p < PH_COUNT; ++p) {
         float ms = 0.0f;
@@ -530,13 +501,13 @@ void drain_set(ft_context *ctx, size_t k)
 }
 
 // Event set for the next launch (nullptr when timing is off).
-hipEvent_t *next_events(ft_context *ctx, bool persistent = false)
+hipEvent_t *next_events(ft_context *ctx)
 {
     if (!ctx->timing) return nullptr;
     const size_t k = ctx->ev_next;
     ctx->ev_next = (k + 1) % kEventSets;
     drain_set(ctx, k);
-    ctx->ev_pending[k] = persistent ? 2 : 1;
+    ctx->ev_pending[k] = 1;
     return ctx->ev_sets[k].data();
 }
 
@@ -577,7 +548,7 @@ ft_status launch_one(ft_context *ctx, const DevJob &J, hipStream_t s, bool stere
     int32_t tot[PH_COUNT];
     job_tiles(J, ctx->shapes, stereo, search, tot);
     TileMap none{0, nullptr};
-    HIP_TRY(ctx, launch_pipeline(nullptr, none, tot, J, ctx->shapes, s, stereo, search, next_events(ctx)));
+    HIP_TRY(ctx, launch_pipeline(nullptr, none, tot, J, ctx->shapes, s, next_events(ctx)));
     return FT_OK;
 }
 
@@ -585,9 +556,13 @@ ft_status launch_one(ft_context *ctx, const DevJob &J, hipStream_t s, bool stere
 ft_status build_batch(ft_context *ctx, Lane &lane, const ft_frame_job *jobs, int32_t n)
 {
     ft_status st;
-    DevJob *table = reinterpret_cast<DevJob *>(h_part(ctx, lane, 0) + ctx->layout.jobs_off);
+    DevJob *table = reinterpret_cast<DevJob *>(lane.h_table + ctx->layout.jobs_off);
+    int64_t kp_total = 0, map_total = 0;
     for (int f = 0; f < n; ++f) {
         const ft_frame_job &jb = jobs[f];
+        const bool stereo = jb.kind == FT_JOB_PINHOLE || jb.kind == FT_JOB_FISHEYE;
+        kp_total += (stereo || jb.n_views > 0 ? (int64_t)jb.left.n : 0) + (stereo || jb.n_views > 1 ? (int64_t)jb.right.n : 0);
+        map_total += jb.n_views > 0 ? (int64_t)jb.map.n : 0;
         DevJob &J = table[f];
         J = DevJob{};
         const Slot &slot = lane.slots[f];
@@ -620,15 +595,20 @@ ft_status build_batch(ft_context *ctx, Lane &lane, const ft_frame_job *jobs, int
                 return st;
         }
     }
+    if (kp_total > ctx->batch_kp_cap)
+        return fail(ctx, FT_ERR_CAPACITY, "batch: %lld keypoints exceed max_batch_kp_total %lld",
+                    (long long)kp_total, (long long)ctx->batch_kp_cap);
+    if (map_total > ctx->batch_map_cap)
+        return fail(ctx, FT_ERR_CAPACITY, "batch: %lld map points exceed max_batch_map_total %lld",
+                    (long long)map_total, (long long)ctx->batch_map_cap);
     return FT_OK;
 }
 
-// Tile prefixes of every phase into a part's staging table; returns the totals.
-void plan_batch(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &sh, int32_t totals[PH_COUNT])
+// Tile prefixes of every phase into the lane's staging table; returns the totals.
+void plan_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, int32_t totals[PH_COUNT])
 {
-    char *tab = h_part(ctx, lane, part);
-    const DevJob *table = reinterpret_cast<const DevJob *>(tab + ctx->layout.jobs_off);
-    int32_t *pre = reinterpret_cast<int32_t *>(tab + ctx->layout.prefix_off);
+    const DevJob *table = reinterpret_cast<const DevJob *>(lane.h_table + ctx->layout.jobs_off);
+    int32_t *pre = reinterpret_cast<int32_t *>(lane.h_table + ctx->layout.prefix_off);
     for (int p = 0; p < PH_COUNT; ++p) {
         pre[p * (n + 1)] = 0;
         totals[p] = 0;
@@ -641,30 +621,6 @@ void plan_batch(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &
             pre[p * (n + 1) + f + 1] = totals[p];
         }
     }
-}
-
-// Splits the n jobs staged in part 0 into `parts` runs of consecutive frames
-// with about equal work and moves runs 1.. into their own part tables.
-// bound[k]..bound[k+1] are the frames of part k; every part gets a frame.
-void split_batch(ft_context *ctx, Lane &lane, int32_t n, int parts, int32_t bound[kMaxParts + 1])
-{
-    const DevJob *table = reinterpret_cast<const DevJob *>(h_part(ctx, lane, 0) + ctx->layout.jobs_off);
-    std::vector<double> cum(n + 1, 0.0);
-    for (int f = 0; f < n; ++f) {
-        const DevJob &J = table[f];
-        const double work = 64.0 + 2.0 * ((double)J.L.n + J.R.n) + (double)J.nM * J.n_views;
-        cum[f + 1] = cum[f] + work;
-    }
-    bound[0] = 0;
-    for (int k = 1; k < parts; ++k) {
-        int f = bound[k - 1] + 1;
-        while (f < n - (parts - k) && cum[f] < cum[n] * k / parts) ++f;
-        bound[k] = f;
-    }
-    bound[parts] = n;
-    for (int k = 1; k < parts; ++k)
-        memcpy(h_part(ctx, lane, k) + ctx->layout.jobs_off, table + bound[k],
-               sizeof(DevJob) * (size_t)(bound[k + 1] - bound[k]));
 }
 
 Lane *free_lane(ft_context *ctx, int *id, ft_status *st)
@@ -684,87 +640,102 @@ Lane *free_lane(ft_context *ctx, int *id, ft_status *st)
     return nullptr;
 }
 
-// Uploads a part's staged table and launches it: one kernel per phase, or one
-// persistent kernel whose abort flag is copied back afterwards.
-ft_status launch_batch(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &sh, hipStream_t s,
-                       const int32_t totals[PH_COUNT], hipEvent_t *ev, bool persistent)
+BatchArgs batch_args(const ft_context *ctx, const Lane &lane, int32_t n)
 {
-    char *dtab = d_part(ctx, lane, part);
-    const char *htab = h_part(ctx, lane, part);
-    HIP_TRY(ctx, hipMemcpyAsync(dtab, htab, ctx->layout.upload_bytes(n), hipMemcpyHostToDevice, s));
-    TileMap map{n, reinterpret_cast<const int32_t *>(dtab + ctx->layout.prefix_off)};
-    const DevJob *table = reinterpret_cast<const DevJob *>(dtab + ctx->layout.jobs_off);
-    if (persistent) {
-        int32_t *state = reinterpret_cast<int32_t *>(dtab + ctx->layout.state_off);
-        int blocks = ctx->persist_blocks;
-        if (blocks <= 0 && (blocks = persistent_blocks(sh)) <= 0)
-            return fail(ctx, FT_ERR_DEVICE, "persistent kernel: occupancy query failed");
-        if (ev) HIP_TRY(ctx, hipEventRecord(ev[0], s));
-        HIP_TRY(ctx, launch_persistent(table, map, totals, state, sh, blocks, ctx->persist_spin, s));
-        if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], s));
-        HIP_TRY(ctx, hipMemcpyAsync(lane.h_abort, state + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        return FT_OK;
-    }
-    const DevJob *staged = reinterpret_cast<const DevJob *>(htab + ctx->layout.jobs_off);
-    HIP_TRY(ctx, launch_pipeline(table, map, totals, staged[0], sh, s, true, true, ev));
+    const char *dtab = lane.d_table;
+    return BatchArgs{reinterpret_cast<const DevJob *>(dtab + ctx->layout.jobs_off),
+                     TileMap{n, reinterpret_cast<const int32_t *>(dtab + ctx->layout.prefix_off)}};
+}
+
+// Uploads the lane's staged table and launches one kernel per phase.
+ft_status launch_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh, hipStream_t s,
+                       const int32_t totals[PH_COUNT], hipEvent_t *ev)
+{
+    HIP_TRY(ctx, hipMemcpyAsync(lane.d_table, lane.h_table, ctx->layout.upload_bytes(n), hipMemcpyHostToDevice, s));
+    const BatchArgs a = batch_args(ctx, lane, n);
+    const DevJob *staged = reinterpret_cast<const DevJob *>(lane.h_table + ctx->layout.jobs_off);
+    HIP_TRY(ctx, launch_pipeline(a.p, a.map, totals, staged[0], sh, s, ev));
     return FT_OK;
 }
 
-// Result of a finished batch on `lane`.
-ft_status finished(ft_context *ctx, const Lane &lane)
+void release_graph(BatchGraph &g)
 {
-    if (lane.persistent && *lane.h_abort)
-        return fail(ctx, FT_ERR_ABORTED,
-                    "persistent batch aborted: a dependency wait exceeded %d sleeps; its outputs are invalid",
-                    ctx->persist_spin);
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+    g = BatchGraph{};
+}
+
+// Builds and instantiates the lane's batch graph for the context's shapes:
+// table upload -> setup -> best match -> refinement -> triangulation ->
+// stereo resolve -> search -> search resolve.  The grids (one workgroup) and
+// arguments are placeholders that every submission replaces.
+ft_status build_graph(ft_context *ctx, Lane &lane)
+{
+    release_graph(lane.g);
+    BatchGraph &g = lane.g;
+    HIP_TRY(ctx, hipGraphCreate(&g.graph, 0));
+    HIP_TRY(ctx, hipGraphAddMemcpyNode1D(&g.copy, g.graph, nullptr, 0, lane.d_table, lane.h_table,
+                                         ctx->layout.upload_bytes(1), hipMemcpyHostToDevice));
+    batch_kernels(ctx->shapes, g.fn, g.block);
+    BatchArgs a = batch_args(ctx, lane, 1);
+    void *args[] = {&a};
+    hipGraphNode_t prev = g.copy;
+    for (int p = 0; p < PH_COUNT; ++p) {
+        hipKernelNodeParams kp{};
+        kp.func = g.fn[p];
+        kp.gridDim = dim3(1);
+        kp.blockDim = dim3(g.block[p]);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        HIP_TRY(ctx, hipGraphAddKernelNode(&g.kern[p], g.graph, &prev, 1, &kp));
+        prev = g.kern[p];
+    }
+    HIP_TRY(ctx, hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
     return FT_OK;
 }
 
-constexpr size_t kGraphsPerLane = 8 * kMaxParts;
-
-// Relaunches the lane's graph for this batch shape, capturing it first if new.
-ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int part, int32_t n, const Shapes &sh,
-                             hipStream_t s, const int32_t totals[PH_COUNT])
+// Builds every lane's graph for the current shapes, after the lanes' batches
+// in flight have finished.
+ft_status rebuild_graphs(ft_context *ctx)
 {
-    GraphEntry *hit = nullptr;
-    for (auto &g : lane.graphs) {
-        if (g.part == part && g.n == n && g.shapes.best_lanes == sh.best_lanes &&
-            g.shapes.search_lanes == sh.search_lanes && g.shapes.search_wide == sh.search_wide &&
-            g.shapes.best_wide == sh.best_wide && g.shapes.wide_misc == sh.wide_misc &&
-            std::equal(totals, totals + PH_COUNT, g.totals)) {
-            hit = &g;
-            break;
-        }
+    for (auto &ln : ctx->lanes)
+        if (ln.used) HIP_TRY(ctx, hipEventSynchronize(ln.done));
+    for (auto &ln : ctx->lanes) {
+        const ft_status st = build_graph(ctx, ln);
+        if (st) return st;
     }
-    if (!hit) {
-        if (lane.graphs.size() >= kGraphsPerLane) {
-            auto old = std::min_element(lane.graphs.begin(), lane.graphs.end(),
-                                        [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
-            hipGraphExecDestroy(old->exec);
-            lane.graphs.erase(old);
-        }
-        GraphEntry g;
-        g.part = part;
-        g.n = n;
-        g.shapes = sh;
-        std::copy(totals, totals + PH_COUNT, g.totals);
-        HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        const ft_status st = launch_batch(ctx, lane, part, n, sh, ctx->cap_stream, totals, nullptr, false);
-        hipGraph_t graph = nullptr;
-        const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
-        if (st) {
-            if (graph) hipGraphDestroy(graph);
-            return st;
-        }
-        if (e != hipSuccess) return fail(ctx, FT_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-        hipGraphDestroy(graph);
-        if (ie != hipSuccess) return fail(ctx, FT_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
-        lane.graphs.push_back(g);
-        hit = &lane.graphs.back();
+    return FT_OK;
+}
+
+// Launches the lane's graph for this batch: the table upload size and, for
+// every phase whose grid or job count changed, the kernel node's grid and
+// argument are set in the instantiated graph first.  A phase without tiles
+// keeps its node with one workgroup, which finds no tile and returns.
+ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, hipStream_t s,
+                             const int32_t totals[PH_COUNT])
+{
+    BatchGraph &g = lane.g;
+    if (!g.exec) return fail(ctx, FT_ERR_DEVICE, "batch graph missing");
+    HIP_TRY(ctx, hipGraphExecMemcpyNodeSetParams1D(g.exec, g.copy, lane.d_table, lane.h_table,
+                                                   ctx->layout.upload_bytes(n), hipMemcpyHostToDevice));
+    BatchArgs a = batch_args(ctx, lane, n);
+    void *args[] = {&a};
+    for (int p = 0; p < PH_COUNT; ++p) {
+        const int32_t grid = std::max<int32_t>(1, totals[p]);
+        if (grid == g.grid[p] && n == g.n) continue;
+        hipKernelNodeParams kp{};
+        kp.func = g.fn[p];
+        kp.gridDim = dim3(grid);
+        kp.blockDim = dim3(g.block[p]);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        HIP_TRY(ctx, hipGraphExecKernelNodeSetParams(g.exec, g.kern[p], &kp));
+        g.grid[p] = grid;
     }
-    hit->last_use = ++ctx->use_clock;
-    HIP_TRY(ctx, hipGraphLaunch(hit->exec, s));
+    g.n = n;
+    HIP_TRY(ctx, hipGraphLaunch(g.exec, s));
     return FT_OK;
 }
 
@@ -795,23 +766,15 @@ bool cache_lookup(const std::string &path, const std::string &key, Shapes &out)
     while (std::getline(f, line)) {
         if (line.find(tag) == std::string::npos) continue;
         const size_t pb = line.find("\"best_lanes\": "), ps = line.find("\"search_lanes\": ");
-        const size_t pk = line.find("\"search_block\": "), pbb = line.find("\"best_block\": ");
         const size_t pa = line.find("\"aux_block\": ");
-        if (pb == std::string::npos || ps == std::string::npos || pk == std::string::npos ||
-            pbb == std::string::npos || pa == std::string::npos)
-            continue;
+        if (pb == std::string::npos || ps == std::string::npos || pa == std::string::npos) continue;
         const int b = std::atoi(line.c_str() + pb + 14);
         const int s = std::atoi(line.c_str() + ps + 16);
-        const int k = std::atoi(line.c_str() + pk + 16);
-        const int kb = std::atoi(line.c_str() + pbb + 14);
         const int ka = std::atoi(line.c_str() + pa + 13);
-        auto blk = [](int v) { return v == kWG || v == kSearchWG; };
-        if (valid_lanes(b) && valid_lanes(s) && blk(k) && blk(kb) && blk(ka)) {
+        if (valid_lanes(b) && valid_lanes(s) && (ka == kWG || ka == kAuxWG)) {
             out.best_lanes = b;
             out.search_lanes = s;
-            out.search_wide = k == kSearchWG;
-            out.best_wide = kb == kSearchWG;
-            out.wide_misc = ka == kSearchWG;
+            out.aux_block = ka;
             return true;
         }
     }
@@ -824,17 +787,23 @@ bool cache_append(const std::string &path, const std::string &key, const Shapes 
     std::ofstream f(path, std::ios::app);
     if (!f) return false;
     f << "{\"key\": \"" << key << "\", \"best_lanes\": " << sh.best_lanes
-      << ", \"search_lanes\": " << sh.search_lanes << ", \"search_block\": "
-      << (sh.search_wide ? kSearchWG : kWG) << ", \"best_block\": " << (sh.best_wide ? kSearchWG : kWG)
-      << ", \"aux_block\": " << (sh.wide_misc ? kSearchWG : kWG) << ", \"us\": " << us << "}\n";
+      << ", \"search_lanes\": " << sh.search_lanes << ", \"aux_block\": " << sh.aux_block
+      << ", \"us\": " << us << "}\n";
     return (bool)f;
+}
+
+void to_public(const Shapes &sh, ft_shapes *s)
+{
+    s->best_lanes = sh.best_lanes;
+    s->search_lanes = sh.search_lanes;
+    s->aux_block = sh.aux_block;
 }
 
 }  // namespace
 
 extern "C" {
 
-int32_t ft_version(void) { return 200; }
+int32_t ft_version(void) { return 300; }
 
 const char *ft_status_string(ft_status s)
 {
@@ -844,7 +813,6 @@ const char *ft_status_string(ft_status s)
     case FT_ERR_CAPACITY: return "capacity exceeded";
     case FT_ERR_DEVICE: return "device error";
     case FT_ERR_UNSUPPORTED: return "unsupported";
-    case FT_ERR_ABORTED: return "batch aborted";
     default: return "unknown status";
     }
 }
@@ -858,7 +826,8 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     if (lim->max_kp_per_image < 1 || lim->max_kp_per_image > kMaxKp || lim->max_map_points < 1 ||
         lim->max_map_points > kMaxMap || lim->max_rows < 1 || lim->max_rows > kMaxRows ||
         lim->max_grid_cells < 1 || lim->max_grid_cells > kMaxCells || lim->max_batch_frames < 1 ||
-        lim->max_batch_frames > 4096 || lim->max_inflight < 1 || lim->max_inflight > 64)
+        lim->max_batch_frames > 4096 || lim->max_inflight < 1 || lim->max_inflight > 64 ||
+        lim->max_levels != kLevels || lim->max_batch_kp_total < 0 || lim->max_batch_map_total < 0)
         return FT_ERR_INVALID_ARGUMENT;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return FT_ERR_DEVICE;
@@ -871,13 +840,17 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     ft_context *ctx = new ft_context();
     ctx->device = device;
     ctx->lim = *lim;
+    ctx->batch_kp_cap = lim->max_batch_kp_total ? lim->max_batch_kp_total
+                                                : (int64_t)lim->max_batch_frames * 2 * lim->max_kp_per_image;
+    ctx->batch_map_cap = lim->max_batch_map_total ? lim->max_batch_map_total
+                                                  : (int64_t)lim->max_batch_frames * lim->max_map_points;
     ctx->layout = table_layout(lim->max_batch_frames);
     Bump b;
     Slot tmp;
     carve_slot(tmp, nullptr, b, *lim);
     const size_t slot_bytes = align_up(b.off, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
-    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * kMaxParts * lim->max_inflight;
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -889,33 +862,23 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         off += slot_bytes;
     };
     carve_at(ctx->direct);
-    bool streams_ok = true;
-    for (auto &ps : ctx->part_streams)
-        streams_ok = streams_ok && hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
-    if (!streams_ok || hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        for (auto &ps : ctx->part_streams)
-            if (ps) hipStreamDestroy(ps);
-        hipFree(ctx->base);
-        delete ctx;
-        return FT_ERR_DEVICE;
-    }
     ctx->lanes.resize(lim->max_inflight);
     for (auto &ln : ctx->lanes) {
         ln.slots.resize(lim->max_batch_frames);
         for (auto &s : ln.slots) carve_at(s);
         ln.d_table = ctx->base + off;
-        off += ctx->layout.total * kMaxParts;
-        bool ev_ok = hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming) == hipSuccess;
-        for (auto &e : ln.join) ev_ok = ev_ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-        if (!ev_ok ||
-            hipHostMalloc((void **)&ln.h_table, ctx->layout.total * kMaxParts, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void **)&ln.h_abort, 256, hipHostMallocDefault) != hipSuccess ||
+        off += ctx->layout.total;
+        if (hipHostMalloc((void **)&ln.h_table, ctx->layout.total, hipHostMallocDefault) != hipSuccess ||
             hipEventCreateWithFlags(&ln.done, hipEventDisableTiming) != hipSuccess) {
             ft_context_destroy(ctx);
             return FT_ERR_DEVICE;
         }
-        memset(ln.h_table, 0, ctx->layout.total * kMaxParts);   // the persistent state stays zero
-        *ln.h_abort = 0;
+        memset(ln.h_table, 0, ctx->layout.total);
+    }
+    // every lane's batch graph, so that no submission instantiates one
+    if (rebuild_graphs(ctx) != FT_OK) {
+        ft_context_destroy(ctx);
+        return FT_ERR_DEVICE;
     }
     *out = ctx;
     return FT_OK;
@@ -949,16 +912,9 @@ ft_status ft_context_destroy(ft_context *ctx)
             hipEventSynchronize(ln.done);
             hipEventDestroy(ln.done);
         }
-        for (auto &g : ln.graphs) hipGraphExecDestroy(g.exec);
-        if (ln.fork) hipEventDestroy(ln.fork);
-        for (auto &e : ln.join)
-            if (e) hipEventDestroy(e);
+        release_graph(ln.g);
         if (ln.h_table) hipHostFree(ln.h_table);
-        if (ln.h_abort) hipHostFree(ln.h_abort);
     }
-    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
-    for (auto &ps : ctx->part_streams)
-        if (ps) hipStreamDestroy(ps);
     if (ctx->base || !ctx->host_blocks.empty()) hipDeviceSynchronize();
     for (auto &hb : ctx->host_blocks) hipHostFree(hb.first);
     if (ctx->base) hipFree(ctx->base);
@@ -1046,55 +1002,28 @@ ft_status ft_context_workspace_bytes(const ft_context *ctx, int64_t *bytes)
 
 ft_status ft_set_shapes(ft_context *ctx, const ft_shapes *s)
 {
-    if (!ctx || !s) return FT_ERR_INVALID_ARGUMENT;
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!s) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: null");
     if (!valid_lanes(s->best_lanes) || !valid_lanes(s->search_lanes))
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: lanes must be 1, 2, 4, 8 or 16");
-    auto block_ok = [](int b) { return b == kWG || b == kSearchWG; };
-    if (!block_ok(s->search_block) || !block_ok(s->best_block) || !block_ok(s->aux_block))
-        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: blocks must be %d or %d", kWG, kSearchWG);
-    ctx->shapes.best_lanes = s->best_lanes;
-    ctx->shapes.search_lanes = s->search_lanes;
-    ctx->shapes.search_wide = s->search_block == kSearchWG;
-    ctx->shapes.best_wide = s->best_block == kSearchWG;
-    ctx->shapes.wide_misc = s->aux_block == kSearchWG;
-    return FT_OK;
+    if (s->aux_block != kWG && s->aux_block != kAuxWG)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "shapes: aux_block must be %d or %d", kWG, kAuxWG);
+    Shapes sh;
+    sh.best_lanes = s->best_lanes;
+    sh.search_lanes = s->search_lanes;
+    sh.aux_block = s->aux_block;
+    if (sh == ctx->shapes) return FT_OK;
+    ctx->shapes = sh;
+    return rebuild_graphs(ctx);
 }
 
 ft_status ft_set_exec_mode(ft_context *ctx, int32_t mode)
 {
     if (!ctx) return FT_ERR_INVALID_ARGUMENT;
-    if (mode != FT_EXEC_EAGER && mode != FT_EXEC_GRAPH && mode != FT_EXEC_PERSISTENT)
+    if (mode != FT_EXEC_EAGER && mode != FT_EXEC_GRAPH)
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "exec mode %d unknown", mode);
     ctx->exec_mode = mode;
-    return FT_OK;
-}
-
-ft_status ft_set_batch_parts(ft_context *ctx, int32_t parts)
-{
-    ft_status st = enter(ctx);
-    if (st) return st;
-    if (parts < 1 || parts > kMaxParts)
-        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch parts %d outside 1..%d", parts, kMaxParts);
-    ctx->n_parts = parts;
-    return FT_OK;
-}
-
-ft_status ft_get_batch_parts(const ft_context *ctx, int32_t *parts)
-{
-    if (!ctx || !parts) return FT_ERR_INVALID_ARGUMENT;
-    *parts = ctx->n_parts;
-    return FT_OK;
-}
-
-ft_status ft_set_persistent(ft_context *ctx, int32_t blocks, int32_t spin_limit)
-{
-    ft_status st = enter(ctx);
-    if (st) return st;
-    if (blocks < 0 || spin_limit < 0)
-        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "persistent: negative blocks %d or spin limit %d", blocks,
-                    spin_limit);
-    ctx->persist_blocks = blocks;
-    ctx->persist_spin = spin_limit ? spin_limit : kPersistSpinLimit;
     return FT_OK;
 }
 
@@ -1108,11 +1037,7 @@ ft_status ft_get_exec_mode(const ft_context *ctx, int32_t *mode)
 ft_status ft_get_shapes(const ft_context *ctx, ft_shapes *s)
 {
     if (!ctx || !s) return FT_ERR_INVALID_ARGUMENT;
-    s->best_lanes = ctx->shapes.best_lanes;
-    s->search_lanes = ctx->shapes.search_lanes;
-    s->search_block = ctx->shapes.search_wide ? kSearchWG : kWG;
-    s->best_block = ctx->shapes.best_wide ? kSearchWG : kWG;
-    s->aux_block = ctx->shapes.wide_misc ? kSearchWG : kWG;
+    to_public(ctx->shapes, s);
     return FT_OK;
 }
 
@@ -1172,41 +1097,16 @@ ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *job
     Lane *lane = free_lane(ctx, &lane_id, &st);
     if (!lane) return st;
     if ((st = build_batch(ctx, *lane, jobs, n))) return st;
-    const bool persistent = ctx->exec_mode == FT_EXEC_PERSISTENT;
-    const bool eager = ctx->exec_mode == FT_EXEC_EAGER || ctx->timing;
-    const Shapes sh = persistent ? persistent_shapes(ctx->shapes) : ctx->shapes;
     hipStream_t s = (hipStream_t)stream;
-    const int parts = (persistent || ctx->timing) ? 1 : std::min<int>(ctx->n_parts, n);
-    if (parts == 1) {
-        int32_t totals[PH_COUNT];
-        plan_batch(ctx, *lane, 0, n, sh, totals);
-        if (persistent)
-            st = launch_batch(ctx, *lane, 0, n, sh, s, totals, next_events(ctx, true), true);
-        else if (eager)
-            st = launch_batch(ctx, *lane, 0, n, sh, s, totals, next_events(ctx), false);
-        else
-            st = launch_batch_graph(ctx, *lane, 0, n, sh, s, totals);
-        if (st) return st;
-    } else {
-        int32_t bound[kMaxParts + 1];
-        split_batch(ctx, *lane, n, parts, bound);
-        HIP_TRY(ctx, hipEventRecord(lane->fork, s));
-        for (int k = 0; k < parts; ++k) {
-            const int32_t nk = bound[k + 1] - bound[k];
-            int32_t totals[PH_COUNT];
-            plan_batch(ctx, *lane, k, nk, sh, totals);
-            hipStream_t ps = ctx->part_streams[k];
-            HIP_TRY(ctx, hipStreamWaitEvent(ps, lane->fork, 0));
-            st = eager ? launch_batch(ctx, *lane, k, nk, sh, ps, totals, nullptr, false)
-                       : launch_batch_graph(ctx, *lane, k, nk, sh, ps, totals);
-            if (st) return st;
-            HIP_TRY(ctx, hipEventRecord(lane->join[k], ps));
-            HIP_TRY(ctx, hipStreamWaitEvent(s, lane->join[k], 0));
-        }
-    }
+    int32_t totals[PH_COUNT];
+    plan_batch(ctx, *lane, n, ctx->shapes, totals);
+    if (ctx->exec_mode == FT_EXEC_EAGER || ctx->timing)
+        st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx));
+    else
+        st = launch_batch_graph(ctx, *lane, n, s, totals);
+    if (st) return st;
     HIP_TRY(ctx, hipEventRecord(lane->done, s));
     lane->used = true;
-    lane->persistent = persistent;
     lane->ticket = (ctx->next_ticket++ << 8) | (uint64_t)lane_id;
     *ticket = lane->ticket;
     return FT_OK;
@@ -1228,7 +1128,7 @@ ft_status ft_batch_poll(ft_context *ctx, uint64_t ticket, int32_t *done)
     const hipError_t q = hipEventQuery(ln.done);
     if (q == hipSuccess) {
         *done = 1;
-        return finished(ctx, ln);
+        return FT_OK;
     }
     if (q == hipErrorNotReady) *done = 0;
     else return fail(ctx, FT_ERR_DEVICE, "poll: %s", hipGetErrorString(q));
@@ -1245,7 +1145,7 @@ ft_status ft_batch_wait(ft_context *ctx, uint64_t ticket)
     Lane &ln = ctx->lanes[lane_id];
     if (ln.ticket != ticket) return FT_OK;
     HIP_TRY(ctx, hipEventSynchronize(ln.done));
-    return finished(ctx, ln);
+    return FT_OK;
 }
 
 ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,
@@ -1261,9 +1161,7 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
     HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));
     const std::string key = workload_key(jobs, n, prop.gcnArchName);
     Shapes best = ctx->shapes;
-    if (cache_path && cache_lookup(cache_path, key, best)) {
-        ctx->shapes = best;
-    } else {
+    if (!(cache_path && cache_lookup(cache_path, key, best))) {
         hipStream_t s = (hipStream_t)stream;
         HIP_TRY(ctx, hipStreamSynchronize(s));
         int lane_id = -1;
@@ -1280,8 +1178,8 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
             std::vector<double> v;
             for (int r = 0; r < 4; ++r) {
                 int32_t totals[PH_COUNT];
-                plan_batch(ctx, *lane, 0, n, sh, totals);
-                ft_status e = launch_batch(ctx, *lane, 0, n, sh, s, totals, next_events(ctx), false);
+                plan_batch(ctx, *lane, n, sh, totals);
+                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx));
                 if (e) return e;
                 HIP_TRY(ctx, hipStreamSynchronize(s));
                 read_timing(ctx, ms, cnt);
@@ -1295,66 +1193,44 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
         double best_a = 1e30, best_s = 1e30;
         for (int g : cands) {
             Shapes sh = best;
-            sh.best_wide = false;
             sh.best_lanes = g;
             double us;
             if ((st = time_phase(sh, PH_STEREO_A, &us))) return st;
             if (us < best_a) {
                 best_a = us;
-                best.best_wide = false;
                 best.best_lanes = g;
-            }
-        }
-        {
-            Shapes sh = best;
-            sh.best_wide = true;
-            double us;
-            if ((st = time_phase(sh, PH_STEREO_A, &us))) return st;
-            if (us < best_a) {
-                best_a = us;
-                best.best_wide = true;
             }
         }
         {   // setup sorts + stereo resolve: 256 or 1024 threads
             double t[2][2];
+            const int blocks[2] = {kWG, kAuxWG};
             for (int w = 0; w < 2; ++w) {
                 Shapes sh = best;
-                sh.wide_misc = w == 1;
+                sh.aux_block = blocks[w];
                 if ((st = time_phase(sh, PH_SETUP, &t[w][0]))) return st;
                 if ((st = time_phase(sh, PH_STEREO_C, &t[w][1]))) return st;
             }
-            best.wide_misc = t[1][0] + t[1][1] < t[0][0] + t[0][1];
-        }
-        {   // the LDS-staged search first, then the global scans by lane group
-            Shapes sh = best;
-            sh.search_wide = true;
-            if ((st = time_phase(sh, PH_SEARCH, &best_s))) return st;
-            best.search_wide = true;
+            best.aux_block = t[1][0] + t[1][1] < t[0][0] + t[0][1] ? kAuxWG : kWG;
         }
         for (int g : cands) {
             Shapes sh = best;
-            sh.search_wide = false;
             sh.search_lanes = g;
             double us;
             if ((st = time_phase(sh, PH_SEARCH, &us))) return st;
             if (us < best_s) {
                 best_s = us;
-                best.search_wide = false;
                 best.search_lanes = g;
             }
         }
         set_timing(ctx, was_timing);
-        ctx->shapes = best;
         if (cache_path && !cache_append(cache_path, key, best, best_a + best_s))
             return fail(ctx, FT_ERR_INVALID_ARGUMENT, "autotune: cannot write %s", cache_path);
     }
-    if (chosen) {
-        chosen->best_lanes = ctx->shapes.best_lanes;
-        chosen->search_lanes = ctx->shapes.search_lanes;
-        chosen->search_block = ctx->shapes.search_wide ? kSearchWG : kWG;
-        chosen->best_block = ctx->shapes.best_wide ? kSearchWG : kWG;
-        chosen->aux_block = ctx->shapes.wide_misc ? kSearchWG : kWG;
+    if (!(best == ctx->shapes)) {
+        ctx->shapes = best;
+        if ((st = rebuild_graphs(ctx))) return st;
     }
+    if (chosen) to_public(ctx->shapes, chosen);
     return FT_OK;
 }
 

@@ -143,22 +143,18 @@ struct DevJob {
     DevView view[2];
 };
 
-// Launch shapes of one submission (the autotuner chooses the lane groups).
-// Defaults: the shapes the autotuner picks for mixed pinhole/fisheye batches.
+// Launch shapes of one submission (the autotuner chooses them).  Defaults:
+// the shapes the autotuner picks for mixed pinhole/fisheye batches.
+constexpr int kAuxWG = 1024;          // the wide option for the setup sorts and the stereo resolve
 struct Shapes {
     int best_lanes = 8;        // lanes cooperating on one pinhole left keypoint
-    int search_lanes = 1;      // lanes cooperating on one map point (kWG-thread search; 1 = record-dealt)
-    bool search_wide = false;  // search in kSearchWG-thread tiles with the view staged in LDS
-    bool best_wide = false;    // stereo best match in kSearchWG-thread tiles (pinhole rows in LDS)
-    bool wide_misc = true;     // setup sorts and stereo resolve in kSearchWG-thread workgroups
+    int search_lanes = 1;      // lanes cooperating on one map point (1 = record-dealt search)
+    int aux_block = kAuxWG;    // threads per workgroup of the setup sorts and the stereo resolve
+    bool operator==(const Shapes &o) const
+    {
+        return best_lanes == o.best_lanes && search_lanes == o.search_lanes && aux_block == o.aux_block;
+    }
 };
-
-// Wide search: threads per workgroup and LDS staging bytes.
-constexpr int kSearchWG = 1024;
-constexpr int kSearchLds = 64 * 1024;
-// Wide pinhole best match: lanes per left keypoint and keypoints per workgroup.
-constexpr int kBestWideLanes = 8;
-constexpr int kBestWideQ = 1024 / kBestWideLanes;
 
 // Tiles of each phase for each job, as prefix sums: batch launches map a flat
 // block index to (job, tile) with a binary search over them.
@@ -167,37 +163,29 @@ struct TileMap {
     const FT_G int32_t *prefix;  // device [PH_COUNT][n_jobs + 1]
 };
 
+// Argument of every batch kernel: the device job table and its tile prefixes.
+struct BatchArgs {
+    const DevJob *p;
+    TileMap map;
+};
+
 // Per-job tile counts of each phase for the given shapes.
 void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search,
                int32_t out[PH_COUNT]);
 
-// Persistent batches: device state = [kPersistHdrInts header ints: task
-// ticket, abort flag] + done[n_jobs][PH_COUNT] completion counters.  The table
-// upload zeroes it before every launch.
-constexpr int kPersistHdrInts = 64;
-constexpr int kPersistSpinLimit = 1 << 22;   // sleeps of one dependency wait before aborting
-
-hipError_t launch_persistent(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
-                             int32_t *state, const Shapes &shapes, int blocks, int spin_limit,
-                             hipStream_t stream);
-// Lane groups the persistent kernel is built for nearest to `s`; a persistent
-// batch is planned and launched with these.
-Shapes persistent_shapes(const Shapes &s);
-// Workgroups of the persistent kernel that fit on the device at once.
-int persistent_blocks(const Shapes &shapes);
-
 // Optional per-phase event timing: when `ev` is non-null, ev[p] and ev[p+1]
 // bracket phase p on the launch stream (ev has kPhases + 1 events).
 constexpr int kPhases = FT_PHASES;
-constexpr int kPersistSlot = FT_PHASES - 1;   // timing slot of a whole persistent batch
-static_assert(kPersistSlot == PH_COUNT, "one timing slot per phase plus the persistent batch");
+static_assert(kPhases == PH_COUNT, "one timing slot per phase");
 
 // Launchers (ft_kernels.hip).  `table` == nullptr: one job passed by value;
 // otherwise a device job table whose flat tiles are described by `map`.
 // `totals` holds the number of workgroups of each phase.
 hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
-                           const DevJob &one, const Shapes &shapes, hipStream_t stream,
-                           bool do_stereo, bool do_search, hipEvent_t *ev);
+                           const DevJob &one, const Shapes &shapes, hipStream_t stream, hipEvent_t *ev);
+// Batch kernel of every phase for these shapes (JobTable argument), and its
+// workgroup size: the nodes of a lane's batch graph.
+void batch_kernels(const Shapes &shapes, void *fn[PH_COUNT], int block[PH_COUNT]);
 
 // Gather-list copy (ft_upload.hip): up to kUploadSegs segments per launch,
 // passed by value; each workgroup copies one kUploadChunk-byte chunk of one

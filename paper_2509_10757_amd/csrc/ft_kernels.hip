@@ -81,22 +81,6 @@ __host__ __device__ inline int div_up(int n, int d) { return (n + d - 1) / d; }
 __host__ __device__ inline bool refine_quarter(const DevJob &J) { return J.half_win == 5 && J.half_range == 5; }
 
 __host__ __device__ inline int view_kp(const DevJob &J, int v) { return J.view[v].side ? J.R.n : J.L.n; }
-// LDS staging of the wide search: cell offsets, then 16-byte records.
-__host__ __device__ inline int lds_rec_offset(int cells) { return ((cells + 1) * 4 + 15) / 16 * 16; }
-
-__host__ __device__ inline bool search_in_lds(int cells, int nK)
-{
-    return lds_rec_offset(cells) + 16 * nK <= kSearchLds;
-}
-
-// LDS staging of the wide best match: row offsets, then 16-byte row records.
-__host__ __device__ inline int rows_lds_offset(int entries) { return (entries * 4 + 15) / 16 * 16; }
-
-__host__ __device__ inline bool best_in_lds(int entries, int nR)
-{
-    return rows_lds_offset(entries) + 16 * nR <= kSearchLds;
-}
-
 // Entry l of a per-level table, selected from values loaded for every level
 // (the loads do not wait for l; a select chain instead of a dependent load).
 template <class T>
@@ -579,58 +563,6 @@ __device__ __forceinline__ void best_scan(const DevJob &J, const int *rs, const 
         done += n;
         if (done >= seen) break;
     }
-}
-
-// Pinhole best match in kSearchWG-thread tiles (kBestWideQ left keypoints,
-// kBestWideLanes lanes each).  The workgroup stages the frame's row offsets
-// and row records in LDS when they fit (best_in_lds), else scans global memory.
-__device__ __forceinline__ void ph_best_wide(const DevJob &J, int tile, unsigned char *smem)
-{
-    constexpr int G = kBestWideLanes;
-    const int sub = threadIdx.x % G;
-    const int i = tile * kBestWideQ + (int)threadIdx.x / G;
-    // the query's own loads first: they overlap the staging
-    bool q = false;
-    float x = 0.0f, y = 0.0f;
-    int oi = 0;
-    Desc di = {};
-    if (i < J.L.n) {
-        y = J.L.y[i];
-        x = J.L.x[i];
-        oi = J.L.oct[i];
-        di = load_desc(J.L.desc, i);
-    }
-    const float minU = x - J.maxD, maxU = x - 0.0f;
-    q = i < J.L.n && y > -1.0f && y < (float)J.rows && !(maxU < 0.0f);
-    const int row = q ? (int)y : 0;
-    uint32_t best = 0xFFFFFFFFu;   // Hamming << 16 | right index
-    float bx = 0.0f;               // x of that right keypoint (for the refinement)
-    const int n_rs = J.n_lb * (J.rows + 1);
-    if (best_in_lds(n_rs, J.R.n)) {
-        int *srs = reinterpret_cast<int *>(smem);
-        RowRec *srr = reinterpret_cast<RowRec *>(smem + rows_lds_offset(n_rs));
-        for (int r = threadIdx.x; r < n_rs; r += kSearchWG) srs[r] = J.row_start[r];
-        for (int p = threadIdx.x; p < J.R.n; p += kSearchWG) srr[p] = J.rrec[p];
-        __syncthreads();
-        if (q) best_scan<G>(J, srs, srr, row, oi, minU, maxU, di, sub, best, bx);
-    } else if (q) {
-        best_scan<G>(J, J.row_start, J.rrec, row, oi, minU, maxU, di, sub, best, bx);
-    }
-    for (int m = 1; m < G; m <<= 1) {
-        const uint32_t o = __shfl_xor(best, m);
-        const float ox = __shfl_xor(bx, m);
-        if (o < best) {
-            best = o;
-            bx = ox;
-        }
-    }
-    const int h = (int)(best >> 16);
-    const bool ok = best != 0xFFFFFFFFu && h < J.th_orb;
-    if (sub == 0 && i < J.L.n) {
-        J.best_j[i] = ok ? (int)(best & 0xFFFFu) : -1;
-        J.best_h[i] = ok ? h : -1;
-    }
-    append_match(J, sub == 0 && i < J.L.n && ok, match_rec(i, best, bx, x, y, oi));
 }
 
 // ----------------------------- stereo_a (fisheye): all-pairs top-2 on MFMA
@@ -1671,93 +1603,6 @@ __device__ __forceinline__ void ph_search(const DevJob &J, const DevView &V, int
     finish_query<G>(J, V, m, sub, top);
 }
 
-// Search by projection, kSearchWG-thread tiles of one view, one lane per map
-// point.  The workgroup first stages the view's cell offsets and records (with
-// the right coordinate of the stereo gate) in LDS, so that a map point reads
-// only its own record and its candidates' descriptors from global memory.
-// Views whose grid does not fit (search_in_lds) scan global memory instead.
-struct LRec {
-    float x, y;
-    uint32_t meta;   // octave | preassigned << 8 | index << 16
-    float ur;        // right coordinate of the keypoint (stereo gate), or 0
-};
-
-
-// The window is scanned in LDS and its candidates are collected first (the
-// first kCandBatch not yet handled, in registers); their descriptors are then
-// read together.  A lane's candidates turn up at different iterations of the
-// scan than its neighbours', so reading each one as it is found would cost the
-// whole wave a global round trip at almost every iteration.  A lane with more
-// candidates rescans the window (LDS only) for the next batch.
-__device__ __forceinline__ Top2<uint64_t> scan_lds(const DevView &V, const Query &q, const int *soff,
-                                                   const LRec *srec)
-{
-    Top2<uint64_t> top = {~0ull, ~0ull};
-    int done = 0;
-    for (;;) {
-        int n = 0, seen = 0;
-        int cp[kCandBatch];   // record positions (their meta is re-read from LDS)
-        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) cp[e] = 0;
-        for (int cy = q.cy0; cy <= q.cy1; ++cy) {
-            const int a = soff[q.cb + cy * V.cols + q.cx0], b = soff[q.cb + cy * V.cols + q.cx1 + 1];
-            for (int p = a; p < b; ++p) {
-                const LRec r = srec[p];
-                if (!in_window(q, r.x, r.y, r.meta) || gate_rejects(q, r.ur)) continue;
-                if (seen >= done && n < kCandBatch) {
-                    _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (n == e) cp[e] = p;
-                    ++n;
-                }
-                ++seen;
-            }
-        }
-        Desc d[kCandBatch];
-        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e) if (e < n) d[e] = load_desc(V.kdesc, (int)(srec[cp[e]].meta >> 16));
-        _Pragma("unroll") for (int e = 0; e < kCandBatch; ++e)
-        {
-            if (e < n) top = top2_insert(top, cand_key(hamming(q.dm, d[e]), srec[cp[e]].meta));
-        }
-        done += n;
-        if (done >= seen) break;
-    }
-    return top;
-}
-
-__device__ __forceinline__ void ph_search_wide(const DevJob &J, int tile, unsigned char *smem)
-{
-    const int tpv = div_up(J.nM, kSearchWG);
-    const int v = tile / tpv;
-    if (v >= J.n_views) return;
-    const DevView &V = J.view[v];
-    const int cells = V.n_pb * V.cols * V.rows;   // cell offsets of every level bin
-    const int rep = V.n_pb > 1 ? J.lv_lo + J.lv_hi + 1 : 1;
-    const int m = (tile - v * tpv) * kSearchWG + (int)threadIdx.x;
-    Top2<uint64_t> top = {~0ull, ~0ull};
-    if (search_in_lds(cells, rep * view_kp(J, v))) {
-        Query q;
-        q.vis = false;
-        if (m < J.nM) q = make_query(J, V, m);   // its loads overlap the staging below
-        int *soff = reinterpret_cast<int *>(smem);
-        LRec *srec = reinterpret_cast<LRec *>(smem + lds_rec_offset(cells));
-        for (int c = threadIdx.x; c <= cells; c += kSearchWG) soff[c] = V.cell_off[c];
-        const int nrec = V.cell_off[cells];
-        for (int p = threadIdx.x; p < nrec; p += kSearchWG) {
-            const CellRec r = V.crec[p];
-            LRec l;
-            l.x = r.x;
-            l.y = r.y;
-            l.meta = r.meta;
-            l.ur = V.u_right ? V.u_right[r.meta >> 16] : 0.0f;
-            srec[p] = l;
-        }
-        __syncthreads();
-        if (q.vis) top = scan_lds(V, q, soff, srec);
-    } else if (m < J.nM) {
-        const Query q = make_query(J, V, m);
-        if (q.vis) top = scan_global<1>(V, q, 0);
-    }
-    finish_query<1>(J, V, m, 0, top);
-}
-
 __device__ __forceinline__ void ph_search_final(const DevJob &J, const DevView &V, int nK, int tile)
 {
     const int idx = tile * kWG + threadIdx.x;
@@ -1800,16 +1645,16 @@ void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search,
     const int nv = do_search ? J.n_views : 0;
     out[PH_SETUP] = (pin || fish ? 1 : 0) + nv;
     if (pin) {
-        out[PH_STEREO_A] = s.best_wide ? div_up(nL, kBestWideQ) : div_up(nL, kWG / s.best_lanes);
+        out[PH_STEREO_A] = div_up(nL, kWG / s.best_lanes);
         out[PH_REFINE] = div_up(nL, refine_quarter(J) ? kRefineQPerWG : kRefinePerWG);
         out[PH_STEREO_C] = 1;
     } else if (fish) {
-        out[PH_STEREO_A] = div_up(nL, s.best_wide ? kKnnQueriesPerWG * (kSearchWG / kWG) : kKnnQueriesPerWG);
+        out[PH_STEREO_A] = div_up(nL, kKnnQueriesPerWG);
         out[PH_TRI] = div_up(nL, kWG);
-        out[PH_STEREO_C] = div_up(nL, s.wide_misc ? kSearchWG : kWG);
+        out[PH_STEREO_C] = div_up(nL, s.aux_block);
     }
     for (int v = 0; v < nv; ++v) {
-        out[PH_SEARCH] += s.search_wide ? div_up(J.nM, kSearchWG) : search_tiles_per_view(J, s.search_lanes);
+        out[PH_SEARCH] += search_tiles_per_view(J, s.search_lanes);
         out[PH_SEARCH_FIN] += final_tiles_view(J, v);
     }
 }
@@ -1835,9 +1680,7 @@ struct OneJob {
     }
 };
 
-struct JobTable {
-    const DevJob *p;
-    TileMap map;
+struct JobTable : BatchArgs {
     __device__ __forceinline__ const DevJob &operator()(int i) const { return p[i]; }
     __device__ __forceinline__ bool locate(int ph, int &job, int &tile) const
     {
@@ -1854,10 +1697,10 @@ struct JobTable {
         return tile < pre[lo + 1] - pre[lo];
     }
 };
+static_assert(sizeof(JobTable) == sizeof(BatchArgs), "graph nodes pass a BatchArgs as the JobTable argument");
 
 // ------------------------------------------------------------ phase tasks
 // One task = one tile of one phase of one frame, run by a whole workgroup.
-// The per-phase kernels and the persistent kernel call the same functions.
 // `smem` is the workgroup's LDS scratch (kTaskLds bytes, 16-byte aligned).
 constexpr int kTaskLds = (kMaxCells + 8 + kWG) * 4;
 
@@ -1884,19 +1727,6 @@ __device__ __forceinline__ void task_stereo_a(const DevJob &J, int tile, unsigne
     uint32_t *part = reinterpret_cast<uint32_t *>(smem + 256 * sizeof(uint64_t));
     if (J.flags & JOB_STEREO_PINHOLE) ph_best<G>(J, tile);
     else ph_knn<kWG>(J, tile, tab, part);
-}
-
-// Stereo best match in kSearchWG-thread tiles: pinhole frames take the wide
-// row-band scan, fisheye frames four kNN subgroups per workgroup.
-__device__ __forceinline__ void task_stereo_a_wide(const DevJob &J, int tile, unsigned char *smem)
-{
-    if (J.flags & JOB_STEREO_PINHOLE) {
-        ph_best_wide(J, tile, smem);
-    } else {
-        uint64_t *tab = reinterpret_cast<uint64_t *>(smem);
-        uint32_t *part = reinterpret_cast<uint32_t *>(smem + 256 * sizeof(uint64_t));
-        ph_knn<kSearchWG>(J, tile, tab, part);
-    }
 }
 
 template <int NT>
@@ -1929,7 +1759,6 @@ __device__ __forceinline__ void task_search_final(const DevJob &J, int tile)
 }
 
 static_assert(256 * 8 + 4 * kKnnQueriesPerWG * 2 * 4 <= kTaskLds, "stereo_a LDS");
-static_assert(256 * 8 + (kSearchWG / 256) * 4 * kKnnQueriesPerWG * 2 * 4 <= kSearchLds, "stereo_a LDS (wide)");
 static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
 static_assert(kRefineQPerWG * kRefineQLds <= kTaskLds, "refine LDS (quarter waves)");
 static_assert(4 * kDealLdsPerWave <= kTaskLds, "record-dealt search LDS");
@@ -1993,26 +1822,6 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     task_search<G>(src(job), tile, smem);
 }
 
-// Two workgroups per CU (LDS) need 8 waves per SIMD: at most 64 VGPRs.
-template <class Src>
-__global__ __launch_bounds__(kSearchWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_stereo_a_wide(Src src)
-{
-    __shared__ __align__(16) unsigned char smem[kSearchLds];
-    int job, tile;
-    if (!src.locate(PH_STEREO_A, job, tile)) return;
-    task_stereo_a_wide(src(job), tile, smem);
-}
-
-// Two workgroups per CU (LDS) need 8 waves per SIMD: at most 64 VGPRs.
-template <class Src>
-__global__ __launch_bounds__(kSearchWG) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_wide(Src src)
-{
-    __shared__ __align__(16) unsigned char smem[kSearchLds];
-    int job, tile;
-    if (!src.locate(PH_SEARCH, job, tile)) return;
-    ph_search_wide(src(job), tile, smem);
-}
-
 template <class Src>
 __global__ __launch_bounds__(kWG) void k_search_final(Src src)
 {
@@ -2021,264 +1830,72 @@ __global__ __launch_bounds__(kWG) void k_search_final(Src src)
     task_search_final(src(job), tile);
 }
 
-// ------------------------------------------------------- persistent kernel
-// One launch runs every task of a batch.  Tasks (phase, frame, tile) are
-// numbered phase by phase; a workgroup takes the next ticket, waits until the
-// frame's prerequisite phases have completed, runs the task and counts it as
-// done.  A task only ever waits for tasks with smaller tickets, which running
-// workgroups already hold, so the waits always end; a wait longer than
-// kPersistSpinLimit sleeps raises the abort flag and every workgroup leaves.
-struct PersistArgs {
-    const DevJob *jobs;
-    TileMap map;
-    int32_t task_off[PH_COUNT + 1];
-    int32_t *hdr;    // [0] next ticket, [1] abort
-    int32_t *done;   // [n_jobs][PH_COUNT]
-    int32_t spin_limit;
-};
-
-__device__ __forceinline__ int phase_tiles(const TileMap &m, int p, int j)
+// Kernel of phase p for these shapes, and its workgroup size.
+template <class Src>
+static void *phase_kernel(const Shapes &sh, int p, int *block)
 {
-    const int32_t *pre = m.prefix + p * (m.n_jobs + 1);
-    return pre[j + 1] - pre[j];
-}
-
-__device__ __forceinline__ bool phase_done(const PersistArgs &a, int j, int p)
-{
-    const int c = __hip_atomic_load(&a.done[j * PH_COUNT + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return c >= phase_tiles(a.map, p, j);
-}
-
-// A task of phase p waits for every earlier phase of its frame (refinement
-// and triangulation do not wait for each other).  Checking all of them, not
-// only the direct predecessors, keeps the order right when a phase has no
-// tiles for the frame.
-__device__ __forceinline__ bool deps_ready(const PersistArgs &a, int j, int p)
-{
-    for (int q = 0; q < p; ++q) {
-        if (p == PH_TRI && q == PH_REFINE) continue;
-        if (!phase_done(a, j, q)) return false;
-    }
-    return true;
-}
-
-// Every branch between two barriers of the task loop is wave-uniform and known
-// to be so (wave index and LDS values pass through readfirstlane; the atomics
-// are issued by all lanes of wave 0, lanes other than 0 adding nothing).  A
-// lane-divergent guard there (say, "thread 0 takes the ticket") lets the
-// compiler run the other lanes of wave 0 round the loop to the next barrier
-// with lane 0 parked, so the workgroup would pass the barrier before the next
-// task is published.
-template <int GB, int GS>
-__global__ __launch_bounds__(kWG) void k_persistent(PersistArgs a)
-{
-    __shared__ __align__(16) unsigned char smem[kTaskLds];
-    __shared__ int s_ctl[4];   // job, phase, tile, stop
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int one = (threadIdx.x & 63) == 0 ? 1 : 0;
-    const int total = a.task_off[PH_COUNT];
-    for (;;) {
-        if (wave == 0) {
-            const int t = __builtin_amdgcn_readfirstlane(atomicAdd(&a.hdr[0], one));
-            int stop = t >= total, job = 0, p = 0, tile = 0;
-            if (!stop) {
-                while (t >= a.task_off[p + 1]) ++p;
-                const int b = t - a.task_off[p];
-                const int32_t *pre = a.map.prefix + p * (a.map.n_jobs + 1);
-                int lo = 0, hi = a.map.n_jobs;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (__builtin_amdgcn_readfirstlane(pre[mid]) <= b) lo = mid;
-                    else hi = mid;
-                }
-                job = lo;
-                tile = b - __builtin_amdgcn_readfirstlane(pre[lo]);
-                int spins = 0;
-                while (!__builtin_amdgcn_readfirstlane((int)deps_ready(a, job, p))) {
-                    const int abort_now = __builtin_amdgcn_readfirstlane(
-                        __hip_atomic_load(&a.hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                    if (abort_now) {
-                        stop = 1;
-                        break;
-                    }
-                    if (++spins > a.spin_limit) {
-                        atomicExch(&a.hdr[1], 1);
-                        stop = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(8);
-                }
-            }
-            s_ctl[0] = job;   // every lane of wave 0 stores the same values
-            s_ctl[1] = p;
-            s_ctl[2] = tile;
-            s_ctl[3] = stop;
+    *block = kWG;
+    switch (p) {
+    case PH_SETUP:
+        if (sh.aux_block == kAuxWG) {
+            *block = kAuxWG;
+            return reinterpret_cast<void *>(&k_setup<Src, kAuxWG>);
         }
-        __syncthreads();
-        if (__builtin_amdgcn_readfirstlane(s_ctl[3])) break;
-        const int job = __builtin_amdgcn_readfirstlane(s_ctl[0]);
-        const int p = __builtin_amdgcn_readfirstlane(s_ctl[1]);
-        const int tile = __builtin_amdgcn_readfirstlane(s_ctl[2]);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the prerequisite phases' writes
-        const DevJob &J = a.jobs[job];
-        switch (p) {
-        case PH_SETUP: task_setup<kWG>(J, tile, smem); break;
-        case PH_STEREO_A: task_stereo_a<GB>(J, tile, smem); break;
-        case PH_REFINE: ph_refine(J, tile, smem); break;
-        case PH_TRI: ph_tri(J, tile); break;
-        case PH_STEREO_C: task_stereo_c<kWG>(J, tile, smem); break;
-        case PH_SEARCH: task_search<GS>(J, tile, smem); break;
-        default: task_search_final(J, tile); break;
+        return reinterpret_cast<void *>(&k_setup<Src, kWG>);
+    case PH_STEREO_A:
+        switch (sh.best_lanes) {
+        case 1: return reinterpret_cast<void *>(&k_stereo_a<Src, 1>);
+        case 2: return reinterpret_cast<void *>(&k_stereo_a<Src, 2>);
+        case 4: return reinterpret_cast<void *>(&k_stereo_a<Src, 4>);
+        case 16: return reinterpret_cast<void *>(&k_stereo_a<Src, 16>);
+        default: return reinterpret_cast<void *>(&k_stereo_a<Src, 8>);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // publish this task's writes
-        __syncthreads();
-        if (wave == 0)
-            __hip_atomic_fetch_add(&a.done[job * PH_COUNT + p], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    case PH_REFINE: return reinterpret_cast<void *>(&k_refine<Src>);
+    case PH_TRI: return reinterpret_cast<void *>(&k_tri<Src>);
+    case PH_STEREO_C:
+        if (sh.aux_block == kAuxWG) {
+            *block = kAuxWG;
+            return reinterpret_cast<void *>(&k_stereo_c<Src, kAuxWG>);
+        }
+        return reinterpret_cast<void *>(&k_stereo_c<Src, kWG>);
+    case PH_SEARCH:
+        switch (sh.search_lanes) {
+        case 1: return reinterpret_cast<void *>(&k_search<Src, 1>);
+        case 2: return reinterpret_cast<void *>(&k_search<Src, 2>);
+        case 8: return reinterpret_cast<void *>(&k_search<Src, 8>);
+        case 16: return reinterpret_cast<void *>(&k_search<Src, 16>);
+        default: return reinterpret_cast<void *>(&k_search<Src, 4>);
+        }
+    default: return reinterpret_cast<void *>(&k_search_final<Src>);
     }
 }
 
-template <int GB, int GS>
-static void *persistent_fn()
+void batch_kernels(const Shapes &shapes, void *fn[PH_COUNT], int block[PH_COUNT])
 {
-    return reinterpret_cast<void *>(&k_persistent<GB, GS>);
-}
-
-Shapes persistent_shapes(const Shapes &s)
-{
-    Shapes r = s;
-    r.search_wide = false;   // the persistent kernel's workgroups have kWG threads
-    r.best_wide = false;
-    r.wide_misc = false;
-    r.best_lanes = s.best_lanes <= 4 ? 4 : (s.best_lanes >= 16 ? 16 : 8);
-    r.search_lanes = s.search_lanes <= 1 ? 1 : (s.search_lanes >= 4 ? 4 : 2);
-    return r;
-}
-
-// The instantiation for exactly these lane groups, or null.
-static void *pick_persistent(const Shapes &s)
-{
-    const int gb = s.best_lanes, gs = s.search_lanes;
-    if (gb == 4 && gs == 1) return persistent_fn<4, 1>();
-    if (gb == 4 && gs == 2) return persistent_fn<4, 2>();
-    if (gb == 4 && gs == 4) return persistent_fn<4, 4>();
-    if (gb == 8 && gs == 1) return persistent_fn<8, 1>();
-    if (gb == 8 && gs == 2) return persistent_fn<8, 2>();
-    if (gb == 8 && gs == 4) return persistent_fn<8, 4>();
-    if (gb == 16 && gs == 1) return persistent_fn<16, 1>();
-    if (gb == 16 && gs == 2) return persistent_fn<16, 2>();
-    if (gb == 16 && gs == 4) return persistent_fn<16, 4>();
-    return nullptr;
-}
-
-int persistent_blocks(const Shapes &shapes)
-{
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    void *fn = pick_persistent(shapes);
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWG, 0) != hipSuccess) return 0;
-    return per_cu * prop.multiProcessorCount;
-}
-
-hipError_t launch_persistent(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
-                             int32_t *state, const Shapes &shapes, int blocks, int spin_limit,
-                             hipStream_t stream)
-{
-    PersistArgs a;
-    a.spin_limit = spin_limit;
-    a.jobs = table;
-    a.map = map;
-    a.task_off[0] = 0;
-    for (int p = 0; p < PH_COUNT; ++p) a.task_off[p + 1] = a.task_off[p] + totals[p];
-    a.hdr = state;
-    a.done = state + kPersistHdrInts;
-    void *args[] = {&a};
-    const int grid = std::max(1, std::min(blocks, a.task_off[PH_COUNT]));
-    void *fn = pick_persistent(shapes);
-    if (!fn) return hipErrorInvalidValue;   // tiles were planned for other lane groups
-    return hipLaunchKernel(fn, dim3(grid), dim3(kWG), args, 0, stream);
+    for (int p = 0; p < PH_COUNT; ++p) fn[p] = phase_kernel<JobTable>(shapes, p, &block[p]);
 }
 
 template <class Src>
-static void launch_best(Src src, int lanes, int blocks, hipStream_t s)
+static hipError_t run(Src src, const int32_t *tot, const Shapes &sh, hipStream_t s, hipEvent_t *ev)
 {
-    const dim3 blk(kWG);
-    switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_stereo_a<Src, 1>), dim3(blocks), blk, 0, s, src); break;
-    case 2: hipLaunchKernelGGL((k_stereo_a<Src, 2>), dim3(blocks), blk, 0, s, src); break;
-    case 4: hipLaunchKernelGGL((k_stereo_a<Src, 4>), dim3(blocks), blk, 0, s, src); break;
-    case 16: hipLaunchKernelGGL((k_stereo_a<Src, 16>), dim3(blocks), blk, 0, s, src); break;
-    default: hipLaunchKernelGGL((k_stereo_a<Src, 8>), dim3(blocks), blk, 0, s, src); break;
-    }
-}
-
-template <class Src>
-static void launch_search(Src src, int lanes, int blocks, hipStream_t s)
-{
-    const dim3 blk(kWG);
-    switch (lanes) {
-    case 1: hipLaunchKernelGGL((k_search<Src, 1>), dim3(blocks), blk, 0, s, src); break;
-    case 2: hipLaunchKernelGGL((k_search<Src, 2>), dim3(blocks), blk, 0, s, src); break;
-    case 8: hipLaunchKernelGGL((k_search<Src, 8>), dim3(blocks), blk, 0, s, src); break;
-    case 16: hipLaunchKernelGGL((k_search<Src, 16>), dim3(blocks), blk, 0, s, src); break;
-    default: hipLaunchKernelGGL((k_search<Src, 4>), dim3(blocks), blk, 0, s, src); break;
-    }
-}
-
-template <class Src>
-static hipError_t run(Src src, const int32_t *tot, const Shapes &sh, hipStream_t s, bool do_stereo,
-                      bool do_search, hipEvent_t *ev)
-{
-    const dim3 blk(kWG);
-    auto mark = [&](int p) {
+    void *args[] = {&src};
+    for (int p = 0; p < PH_COUNT; ++p) {
         if (ev) (void)hipEventRecord(ev[p], s);
-    };
-    mark(0);
-    if (tot[PH_SETUP] > 0) {
-        if (sh.wide_misc)
-            hipLaunchKernelGGL((k_setup<Src, kSearchWG>), dim3(tot[PH_SETUP]), dim3(kSearchWG), 0, s, src);
-        else
-            hipLaunchKernelGGL((k_setup<Src, kWG>), dim3(tot[PH_SETUP]), blk, 0, s, src);
+        if (tot[p] <= 0) continue;   // planned by job_tiles for the phases asked for
+        int block = kWG;
+        void *fn = phase_kernel<Src>(sh, p, &block);
+        const hipError_t e = hipLaunchKernel(fn, dim3(tot[p]), dim3(block), args, 0, s);
+        if (e != hipSuccess) return e;
     }
-    mark(1);
-    if (do_stereo && tot[PH_STEREO_A] > 0) {
-        if (sh.best_wide)
-            hipLaunchKernelGGL(k_stereo_a_wide<Src>, dim3(tot[PH_STEREO_A]), dim3(kSearchWG), 0, s, src);
-        else
-            launch_best(src, sh.best_lanes, tot[PH_STEREO_A], s);
-    }
-    mark(2);
-    if (do_stereo && tot[PH_REFINE] > 0)
-        hipLaunchKernelGGL(k_refine<Src>, dim3(tot[PH_REFINE]), blk, 0, s, src);
-    mark(3);
-    if (do_stereo && tot[PH_TRI] > 0) hipLaunchKernelGGL(k_tri<Src>, dim3(tot[PH_TRI]), blk, 0, s, src);
-    mark(4);
-    if (do_stereo && tot[PH_STEREO_C] > 0) {
-        if (sh.wide_misc)
-            hipLaunchKernelGGL((k_stereo_c<Src, kSearchWG>), dim3(tot[PH_STEREO_C]), dim3(kSearchWG), 0, s, src);
-        else
-            hipLaunchKernelGGL((k_stereo_c<Src, kWG>), dim3(tot[PH_STEREO_C]), blk, 0, s, src);
-    }
-    mark(5);
-    if (do_search && tot[PH_SEARCH] > 0) {
-        if (sh.search_wide)
-            hipLaunchKernelGGL(k_search_wide<Src>, dim3(tot[PH_SEARCH]), dim3(kSearchWG), 0, s, src);
-        else
-            launch_search(src, sh.search_lanes, tot[PH_SEARCH], s);
-    }
-    mark(6);
-    if (do_search && tot[PH_SEARCH_FIN] > 0)
-        hipLaunchKernelGGL(k_search_final<Src>, dim3(tot[PH_SEARCH_FIN]), blk, 0, s, src);
-    mark(7);
+    if (ev) (void)hipEventRecord(ev[PH_COUNT], s);
     return hipGetLastError();
 }
 
 hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
-                           const DevJob &one, const Shapes &shapes, hipStream_t stream,
-                           bool do_stereo, bool do_search, hipEvent_t *ev)
+                           const DevJob &one, const Shapes &shapes, hipStream_t stream, hipEvent_t *ev)
 {
-    if (table) return run(JobTable{table, map}, totals, shapes, stream, do_stereo, do_search, ev);
-    return run(OneJob{one}, totals, shapes, stream, do_stereo, do_search, ev);
+    if (table) return run(JobTable{{table, map}}, totals, shapes, stream, ev);
+    return run(OneJob{one}, totals, shapes, stream, ev);
 }
 
 }  // namespace ft

@@ -514,12 +514,7 @@ class DeviceExecutor:
         token = self.handles[h][0]
         if token[0] == "event":
             return token[1].query()
-        try:
-            return self.ctx.ft_batch_poll(token[1])
-        except self.ft.FtError as e:
-            if e.status == self.ft.FT_ERR_ABORTED:   # the batch ended, its outputs are invalid
-                raise BatchFailed(str(e)) from e
-            raise
+        return self.ctx.ft_batch_poll(token[1])
 
     def release(self, h):
         if self.on_release is not None:

@@ -42,7 +42,8 @@ def test_status_strings_without_device(lib):
     lib.ft_status_string.restype = ct.c_char_p
     assert lib.ft_status_string(0) == b"ok"
     assert lib.ft_status_string(2) == b"capacity exceeded"
-    assert lib.ft_status_string(5) == b"batch aborted"
+    assert lib.ft_status_string(4) == b"unsupported"
+    assert lib.ft_status_string(5) == b"unknown status"
     lib.ft_version.restype = ct.c_int32
     assert lib.ft_version() >= 100
 
@@ -83,7 +84,7 @@ def test_binding_constants_match_header():
     from paper_2509_10757_amd import binding
     defs = dict(re.findall(r"#define\s+(FT_[A-Z_0-9]+)\s+(-?\d+)", open(HEADER).read()))
     mirrored = [k for k in defs if hasattr(binding, k)]
-    assert {"FT_PHASES", "FT_ERR_ABORTED", "FT_EXEC_PERSISTENT"} <= set(mirrored)
+    assert {"FT_PHASES", "FT_EXEC_GRAPH", "FT_ERR_DEVICE"} <= set(mirrored)
     for k in mirrored:
         assert getattr(binding, k) == int(defs[k]), k
     assert len(binding.Context.PHASES) == int(defs["FT_PHASES"])

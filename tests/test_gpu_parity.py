@@ -230,8 +230,7 @@ def test_lane_groups_do_not_change_results(ft, ctx):
     jobs = [d.job() for d in dfs]
     ref = None
     try:
-        for shape in [(1, 1, 1024, 1024, 1024), (2, 16, 256, 256, 256), (4, 8, 256, 1024, 256),
-                      (8, 4, 1024, 256, 1024), (16, 2, 256, 256, 1024), (8, 1, 256, 1024, 256)]:
+        for shape in [(1, 1, 1024), (2, 16, 256), (4, 8, 256), (8, 4, 1024), (16, 2, 1024), (8, 1, 256)]:
             ctx.ft_set_shapes(*shape)
             say("shapes", shape)
             ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
@@ -245,7 +244,7 @@ def test_lane_groups_do_not_change_results(ft, ctx):
                 for a, b in zip(res, ref):
                     bit_equal(a, b)
     finally:
-        ctx.ft_set_shapes(8, 1, 256)
+        ctx.ft_set_shapes(8, 1)
 
 
 def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
@@ -256,10 +255,10 @@ def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
     try:
         chosen = ctx.ft_autotune(jobs, cache)
         assert chosen[0] in (1, 2, 4, 8, 16) and chosen[1] in (1, 2, 4, 8, 16)
-        assert all(b in (256, 1024) for b in chosen[2:])
+        assert chosen[2] in (256, 1024)
         text = open(cache).read()
         assert '"best_lanes": %d' % chosen[0] in text
-        ctx.ft_set_shapes(1, 1, 1024, 1024, 1024)
+        ctx.ft_set_shapes(1, 1, 1024 + 256 - chosen[2])
         assert ctx.ft_autotune(jobs, cache) == chosen        # served from the cache
         assert ctx.ft_get_shapes() == chosen
         assert open(cache).read() == text
@@ -268,7 +267,7 @@ def test_autotune_picks_valid_shapes_and_caches(ft, ctx, tmp_path):
         for f, d in zip(frames, dfs):
             compare_frame(d.results(), oracle.run_frame(f))
     finally:
-        ctx.ft_set_shapes(8, 1, 256)
+        ctx.ft_set_shapes(8, 1)
 
 
 def test_graph_replays_match_eager(ft, ctx):
@@ -312,108 +311,49 @@ def _clobber(dfs):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("n_frames,blocks", [(64, 0), (16, 1), (16, 37)])
-def test_persistent_matches_eager(ft, ctx, n_frames, blocks):
-    frames = synth.mixed_batch(n_frames=n_frames)
+def test_graph_nodes_follow_every_batch_shape(ft, ctx):
+    """The lane's one instantiated graph serves batches of every shape: each
+    submission sets the table size and every phase's grid in place.  Batches
+    with phases that have no tiles (pinhole only, fisheye only, search only),
+    of one frame and of all frames, and the same batches after a shape change
+    (which rebuilds the graphs) give the eager results; eager work runs
+    between the replays."""
+    frames = synth.mixed_batch(n_frames=12)
     dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
     jobs = [d.job() for d in dfs]
-    say("persistent", n_frames, "frames, blocks", blocks)
+    pin = [k for k, f in enumerate(frames) if f["kind"] == "pinhole"]
+    fish = [k for k, f in enumerate(frames) if f["kind"] == "fisheye"]
+    assert pin and fish
+    search_only = [dfs[k].job(stereo=False) for k in fish[:2]]
+    subsets = [list(range(12)), pin, fish, [0], list(range(12)), fish[:1], pin[:3]]
     try:
         ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
         ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
         torch.cuda.synchronize()
         ref = [d.results() for d in dfs]
-        ctx.ft_set_exec_mode(ft.FT_EXEC_PERSISTENT)
-        ctx.ft_set_persistent(blocks, 0)
-        for rep in range(3):
-            _clobber(dfs)
-            ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
-            torch.cuda.synchronize()
-            for d, w in zip(dfs, ref):
-                bit_equal(d.results(), w)
-    finally:
-        ctx.ft_set_persistent(0, 0)
+        ctx.ft_batch_wait(ctx.ft_batch_submit(search_only))
+        torch.cuda.synchronize()
+        ref_search = [dfs[k].results()["search"] for k in fish[:2]]
         ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
-    if n_frames == 64:
-        for d, f in list(zip(dfs, frames))[:6]:
-            compare_frame(d.results(), oracle.run_frame(f))
-
-
-def test_persistent_gives_up_cleanly_and_recovers(ft, ctx):
-    """A one-sleep spin limit makes dependency waits give up: the batch is then
-    reported as failed (or, if no task had to wait, is correct), and the next
-    batch with the default limit is correct again."""
-    frames = synth.mixed_batch(n_frames=32)
-    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
-    jobs = [d.job() for d in dfs]
-    with pytest.raises(ft.FtError):
-        ctx.ft_set_persistent(-1, 0)
-    try:
-        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
-        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
-        torch.cuda.synchronize()
-        ref = [d.results() for d in dfs]
-        ctx.ft_set_exec_mode(ft.FT_EXEC_PERSISTENT)
-        ctx.ft_set_persistent(0, 1)
-        _clobber(dfs)
-        t = ctx.ft_batch_submit(jobs)
-        try:
-            ctx.ft_batch_wait(t)
-            aborted = False
-        except ft.FtError as e:
-            assert e.status == ft.FT_ERR_ABORTED and "aborted" in str(e)
-            aborted = True
-        torch.cuda.synchronize()
-        say("gave up" if aborted else "finished without waiting")
-        if not aborted:
-            for d, w in zip(dfs, ref):
-                bit_equal(d.results(), w)
-        ctx.ft_set_persistent(0, 0)
-        _clobber(dfs)
-        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
-        torch.cuda.synchronize()
-        for d, w in zip(dfs, ref):
-            bit_equal(d.results(), w)
-    finally:
-        ctx.ft_set_persistent(0, 0)
-        ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
-
-
-def test_split_submissions_match_one_launch(ft, ctx):
-    """A submission split into 2-4 parts on the context's internal streams gives
-    the results of one launch, in eager and graph mode, also when there are
-    fewer frames than parts."""
-    frames = synth.mixed_batch(n_frames=24)
-    dfs = [ft.DeviceFrame(f, "cuda") for f in frames]
-    jobs = [d.job() for d in dfs]
-    for bad in (0, 5):
-        with pytest.raises(ft.FtError):
-            ctx.ft_set_batch_parts(bad)
-    try:
-        ctx.ft_set_batch_parts(1)
-        ctx.ft_set_exec_mode(ft.FT_EXEC_EAGER)
-        ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
-        torch.cuda.synchronize()
-        ref = [d.results() for d in dfs]
-        for mode in (ft.FT_EXEC_EAGER, ft.FT_EXEC_GRAPH):
-            ctx.ft_set_exec_mode(mode)
-            for parts in (2, 3, 4):
-                ctx.ft_set_batch_parts(parts)
-                assert ctx.ft_get_batch_parts() == parts
-                say("mode", mode, "parts", parts)
-                for rep in range(2):
-                    _clobber(dfs)
-                    ctx.ft_batch_wait(ctx.ft_batch_submit(jobs))
-                    torch.cuda.synchronize()
-                    for d, w in zip(dfs, ref):
-                        bit_equal(d.results(), w)
-                _clobber(dfs[:3])
-                ctx.ft_batch_wait(ctx.ft_batch_submit(jobs[:3]))
+        for shapes in ((8, 1), (4, 2, 256)):
+            ctx.ft_set_shapes(*shapes)
+            for sub in subsets:
+                say("shapes", shapes, "graph batch of frames", sub)
+                _clobber(dfs)
+                ctx.ft_batch_wait(ctx.ft_batch_submit([jobs[k] for k in sub]))
                 torch.cuda.synchronize()
-                for d, w in zip(dfs[:3], ref[:3]):
-                    bit_equal(d.results(), w)
+                for k in sub:
+                    bit_equal(dfs[k].results(), ref[k])
+            say("shapes", shapes, "graph batch of search-only jobs")
+            _clobber(dfs)
+            ctx.ft_batch_wait(ctx.ft_batch_submit(search_only))
+            torch.cuda.synchronize()
+            for k, w in zip(fish[:2], ref_search):
+                for a, b in zip(dfs[k].results()["search"], w):
+                    for key in a:
+                        assert np.array_equal(a[key], b[key]), key
     finally:
-        ctx.ft_set_batch_parts(1)
+        ctx.ft_set_shapes(8, 1)
         ctx.ft_set_exec_mode(ft.FT_EXEC_GRAPH)
 
 
@@ -440,11 +380,11 @@ def test_epipolar_band_widths(ft, ctx, band):
     want = oracle.run_frame(f)
     compare_frame(run_device(ft, ctx, f), want)
     try:
-        for blk in (256, 1024):
-            ctx.ft_set_shapes(4, 1, 256, blk, 1024)
+        for lanes in (4, 16):
+            ctx.ft_set_shapes(lanes, 1)
             compare_frame(run_device(ft, ctx, f, batch=True), want)
     finally:
-        ctx.ft_set_shapes(8, 1, 256)
+        ctx.ft_set_shapes(8, 1)
 
 
 def test_concurrent_batches_on_streams_match(ft):
