@@ -99,6 +99,30 @@ def triangulate(r1, r2, R_lr, t_lr):
     return X if ok else None
 
 
+def pyramid_layout(W: int, H: int, inv_sf) -> dict:
+    """Level sizes and packed offsets of the image pyramid (Section IV-B)."""
+    isf = _c(inv_sf, np.float32)
+    n = len(isf)
+    w = np.zeros(n, np.int32); h = np.zeros(n, np.int32); off = np.zeros(n, np.int64)
+    lib = _load()
+    lib.oracle_pyramid_layout.restype = ct.c_int64
+    total = lib.oracle_pyramid_layout(ct.c_int(W), ct.c_int(H), _p(isf), ct.c_int(n), _p(w), _p(h), _p(off))
+    return {"width": w, "height": h, "offset": off, "bytes": int(total)}
+
+
+def pyramid(img, inv_sf) -> dict:
+    """The image pyramid of a level-0 image (u8, H x W): every level computed
+    from level 0, packed row-major level after level."""
+    img = _c(img, np.uint8)
+    H, W = img.shape
+    lay = pyramid_layout(W, H, inv_sf)
+    isf = _c(inv_sf, np.float32)
+    out = np.zeros(lay["bytes"], np.uint8)
+    _load().oracle_pyramid(_p(img), ct.c_int(W), ct.c_int(H), ct.c_int(W), _p(isf), ct.c_int(len(isf)),
+                           _p(out))
+    return {"data": out, "offset": lay["offset"], "width": lay["width"], "height": lay["height"]}
+
+
 def stereo_pinhole(frame) -> dict:
     lib = _load()
     nL, xL, yL, oL, dL = _kp(frame["left"])

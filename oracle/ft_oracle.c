@@ -224,6 +224,75 @@ void oracle_stereo_pinhole(
 /* Kannala-Brandt fisheye model: theta_d = theta (1 + k1 t^2 + k2 t^4 +      */
 /* k3 t^6 + k4 t^8), image radius = f * theta_d.                            */
 /* ------------------------------------------------------------------------ */
+/* Level sizes and packed offsets of the image pyramid (see ft_oracle.h). */
+int64_t oracle_pyramid_layout(int W, int H, const float *inv_sf, int n_levels,
+                              int32_t *w, int32_t *h, int64_t *off)
+{
+    int64_t acc = 0;
+    for (int l = 0; l < n_levels; ++l) {
+        const float fw = (float)W * inv_sf[l];
+        const float fh = (float)H * inv_sf[l];
+        w[l] = (int32_t)floorf(fw + 0.5f);
+        h[l] = (int32_t)floorf(fh + 0.5f);
+        off[l] = acc;
+        acc += (int64_t)w[l] * h[l];
+    }
+    return acc;
+}
+
+/* Source pixel and 8-bit weight of output index x of a level n_out wide from a
+ * source n_in wide: s = ((2x + 1) * n_in - n_out) / (2 * n_out), i.e.
+ * (x + 1/2) * n_in / n_out - 1/2, as an exact fraction. */
+static void pyramid_tap(int x, int n_in, int n_out, int *i0, int *wt)
+{
+    const int64_t num = (int64_t)(2 * x + 1) * n_in - n_out;
+    const int64_t den = 2 * (int64_t)n_out;
+    if (num <= 0) {                         /* left of the first pixel centre */
+        *i0 = 0;
+        *wt = 0;
+        return;
+    }
+    int64_t q = num / den;
+    int64_t r = num % den;
+    int64_t wq = (256 * r) / den;           /* floor(256 * frac(s)) */
+    if (q >= n_in - 1) {                    /* right of the last pixel centre */
+        q = n_in - 1;
+        wq = 0;
+    }
+    *i0 = (int)q;
+    *wt = (int)wq;
+}
+
+void oracle_pyramid(const uint8_t *img, int W, int H, int pitch, const float *inv_sf, int n_levels,
+                    uint8_t *out)
+{
+    int32_t w[64], h[64];
+    int64_t off[64];
+    if (n_levels > 64) return;
+    oracle_pyramid_layout(W, H, inv_sf, n_levels, w, h, off);
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) out[(size_t)y * W + x] = img[(size_t)y * pitch + x];
+    for (int l = 1; l < n_levels; ++l) {
+        uint8_t *dst = out + off[l];
+        for (int y = 0; y < h[l]; ++y) {
+            int y0, b;
+            pyramid_tap(y, H, h[l], &y0, &b);
+            const int y1 = y0 + 1 < H ? y0 + 1 : H - 1;
+            for (int x = 0; x < w[l]; ++x) {
+                int x0, a;
+                pyramid_tap(x, W, w[l], &x0, &a);
+                const int x1 = x0 + 1 < W ? x0 + 1 : W - 1;
+                const int p00 = img[(size_t)y0 * pitch + x0], p01 = img[(size_t)y0 * pitch + x1];
+                const int p10 = img[(size_t)y1 * pitch + x0], p11 = img[(size_t)y1 * pitch + x1];
+                const int top = (256 - a) * p00 + a * p01;
+                const int bot = (256 - a) * p10 + a * p11;
+                const int v = (256 - b) * top + b * bot;
+                dst[(size_t)y * w[l] + x] = (uint8_t)((v + 32768) >> 16);
+            }
+        }
+    }
+}
+
 static double kb_distort(const float *kb, double th)
 {
     const double k1 = kb[4], k2 = kb[5], k3 = kb[6], k4 = kb[7];

@@ -88,6 +88,24 @@ int oracle_subpixel(const int *sad, int L, int *kbest, int *sad_best, float *del
 int oracle_median_keep(int n, const int32_t *sad, int num, int den, uint8_t *keep);
 int oracle_predict_level(float ratio, const float *sf, int n_levels);
 
+/* Image pyramid (Section IV-B: the pyramid is built on the device and kept
+ * there for stereo matching; the extractor it reuses computes every level at
+ * once).  Level l is round(W * inv_sf[l]) x round(H * inv_sf[l]) (binary32
+ * product, then floor(v + 0.5)); level 0 is the image; every other level is a
+ * bilinear resample of level 0 with pixel centres aligned, source coordinate
+ * s = (x + 1/2) * W / w - 1/2 taken exactly as a fraction, 8-bit weights
+ * floor(256 * frac(s)), clamp at the borders, and the result rounded as
+ * (v + 2^15) >> 16.  oracle_pyramid_layout fills the level sizes and packed
+ * offsets and returns the total byte count; oracle_pyramid writes the levels
+ * (img row-major with `pitch` bytes per row).  Pinned by closed forms:
+ * constant images, linear ramps (round-half-up of the exact source
+ * coordinate), exact 2x downscaling (rounded 2x2 box average), the level
+ * sizes of the paper's image shapes, and a numpy brute force. */
+int64_t oracle_pyramid_layout(int W, int H, const float *inv_sf, int n_levels,
+                              int32_t *w, int32_t *h, int64_t *off);
+void oracle_pyramid(const uint8_t *img, int W, int H, int pitch, const float *inv_sf, int n_levels,
+                    uint8_t *out);
+
 /* Kannala-Brandt helpers, exposed so tests can pin them (round trips). */
 int oracle_kb_unproject(const float *kb, float u, float v, int iters, double tol,
                         double max_theta, double *ray);

@@ -11,6 +11,7 @@ import pytest
 import oracle
 import synth
 from tests import test_oracle_pins as pins
+from tests import test_oracle_pyramid as pyr
 
 HERE = os.path.dirname(os.path.abspath(oracle.__file__))
 
@@ -59,6 +60,12 @@ MUTANTS = {
     "fish_left_reproj_right_level": ("chi2 * (double)sigma2[oL[i]]", "chi2 * (double)sigma2[oR[j1]]"),
     "fish_right_reproj_dropped": ("if (!(ex * ex + ey * ey <= chi2 * (double)sigma2[oR[j1]])) { ++n_rep; continue; }", ""),
     "fish_one_target_enough": ("if (nT < 2) continue;", "if (nT < 1) continue;"),
+    "pyramid_no_centre_alignment": ("(int64_t)(2 * x + 1) * n_in - n_out", "(int64_t)(2 * x) * n_in"),
+    "pyramid_weight_rounded": ("(256 * r) / den", "(256 * r + den / 2) / den"),
+    "pyramid_result_truncated": ("(v + 32768) >> 16", "v >> 16"),
+    "pyramid_size_truncated": ("w[l] = (int32_t)floorf(fw + 0.5f);", "w[l] = (int32_t)floorf(fw);"),
+    "pyramid_rows_from_width": ("pyramid_tap(y, H, h[l], &y0, &b);", "pyramid_tap(y, W, h[l], &y0, &b);"),
+    "pyramid_weights_swapped": ("const int top = (256 - a) * p00 + a * p01;", "const int top = a * p00 + (256 - a) * p01;"),
     "conflict_tie": ("int64_t key = ((int64_t)dist[i] << 32) | (int64_t)i;\n        if (key < best",
                      "int64_t key = ((int64_t)dist[i] << 32) | (int64_t)(nQ - i);\n        if (key < best"),
 }
@@ -101,6 +108,11 @@ def _pins(frames):
     tests.append(pins.test_fisheye_depth_gate_scene)
     tests.append(pins.test_fisheye_reprojection_gate_scene)
     tests.append(pins.test_fisheye_needs_two_targets)
+    tests.append(pyr.test_level_sizes_of_the_paper_shapes)
+    tests.append(lambda: pyr.test_horizontal_ramp_is_round_half_up_of_the_source_column(200, 37))
+    tests.append(lambda: pyr.test_vertical_ramp_is_round_half_up_of_the_source_row(40, 250))
+    tests.append(pyr.test_exact_halving_is_the_rounded_box_average)
+    tests.append(lambda: pyr.test_random_images_match_numpy_resampler(101, 67, 6))
 
     def with_frames():
         c1 = (frames[1], oracle.run_frame(frames[1]))
