@@ -99,6 +99,57 @@ def triangulate(r1, r2, R_lr, t_lr):
     return X if ok else None
 
 
+def _cam_array(c) -> np.ndarray:
+    return np.array([c["fx"], c["fy"], c["cx"], c["cy"], *list(c["k"]), c["bf"]], np.float32)
+
+
+def search_last_frame(case) -> dict:
+    """Search by projection of the last frame's matched map points into the
+    current frame (Section II-C, Initial Pose Estimation), for a case from
+    synth.last_frame_case."""
+    lib = _load()
+    last, kps, c, prm = case["last"], case["kps"], case["cam"], case["params"]
+    nL = len(last["octave"])
+    nK, kx, ky, ko, kd = _kp(kps)
+    lpos = _c(last["pos"], np.float32); ld = _c(last["desc"], np.uint8)
+    lo = _c(last["octave"], np.uint8); la = _c(last["angle"], np.float32)
+    ka = _c(kps["angle"], np.float32)
+    ur = None if case.get("u_right") is None else _c(case["u_right"], np.float32)
+    pre = None if case.get("preassigned") is None else _c(case["preassigned"], np.uint8)
+    cam = _cam_array(c)
+    R = _c(c["R"], np.float32).reshape(-1); t = _c(c["t"], np.float32)
+    bounds = _c(c["bounds"], np.float32)
+    sf = _c(case["scales"]["sf"], np.float32)
+    fp = np.array([prm["th"]], np.float32)
+    ip = np.array([prm["th_high"], prm["direction"], prm["check_orientation"], prm["bins"]], np.int32)
+    out = {"last_match": np.empty(nL, np.int32), "last_dist": np.empty(nL, np.int32),
+           "kp_match": np.empty(nK, np.int32)}
+    stats = np.zeros(8, np.int64)
+    lib.oracle_search_last_frame(
+        ct.c_int(nL), _p(lpos), _p(ld), _p(lo), _p(la),
+        ct.c_int(nK), _p(kx), _p(ky), _p(ko), _p(kd), _p(ka), _p(ur), _p(pre),
+        ct.c_int(int(c["model"])), _p(cam), _p(R), _p(t), _p(bounds), _p(sf), ct.c_int(len(sf)),
+        _p(fp), _p(ip), _p(out["last_match"]), _p(out["last_dist"]), _p(out["kp_match"]), _p(stats))
+    out["stats"] = dict(zip(["in_image", "candidates", "accepted", "after_conflict", "matches"],
+                            stats[:5].tolist()))
+    out["kept_bins"] = [int(b) for b in stats[5:8] if b >= 0]
+    out["n_matches"] = int(stats[4])
+    return out
+
+
+def rotation_bin(a_last: float, a_cur: float, bins: int = 30) -> int:
+    lib = _load()
+    lib.oracle_rotation_bin.restype = ct.c_int
+    return int(lib.oracle_rotation_bin(ct.c_float(a_last), ct.c_float(a_cur), ct.c_int(bins)))
+
+
+def three_fullest(count) -> np.ndarray:
+    cnt = _c(count, np.int32)
+    kept = np.zeros(len(cnt), np.int32)
+    _load().oracle_three_fullest(_p(cnt), ct.c_int(len(cnt)), _p(kept))
+    return kept.astype(bool)
+
+
 def pyramid_layout(W: int, H: int, inv_sf) -> dict:
     """Level sizes and packed offsets of the image pyramid (Section IV-B)."""
     isf = _c(inv_sf, np.float32)

@@ -579,3 +579,121 @@ void oracle_search_local_points(
     }
     free(cand_k); free(cand_h); free(alive);
 }
+
+/* Rotation bin of a match between a last-frame keypoint (orientation a_last)
+ * and a current keypoint (a_cur), degrees: the rotation taken into [0, 360)
+ * and rounded to one of `bins` equal bins; the bin past the last wraps to 0. */
+int oracle_rotation_bin(float a_last, float a_cur, int bins)
+{
+    float rot = a_last - a_cur;
+    if (rot < 0.0f) rot += 360.0f;
+    const float factor = (float)bins / 360.0f;
+    int bin = (int)roundf(rot * factor);
+    if (bin >= bins) bin = 0;
+    return bin;
+}
+
+/* The fullest bin, then the second and third fullest (ties to the lower bin),
+ * the latter two kept only while 10 * count >= the fullest count.  kept[b] is
+ * set to 1 for the kept bins and 0 for the others. */
+void oracle_three_fullest(const int32_t *count, int bins, int32_t *kept)
+{
+    int i1 = -1, i2 = -1, i3 = -1;
+    int m1 = 0, m2 = 0, m3 = 0;
+    for (int b = 0; b < bins; ++b) {
+        const int c = count[b];
+        if (c > m1) { m3 = m2; i3 = i2; m2 = m1; i2 = i1; m1 = c; i1 = b; }
+        else if (c > m2) { m3 = m2; i3 = i2; m2 = c; i2 = b; }
+        else if (c > m3) { m3 = c; i3 = b; }
+    }
+    if (10 * m2 < m1) { i2 = -1; i3 = -1; }
+    else if (10 * m3 < m1) i3 = -1;
+    for (int b = 0; b < bins; ++b) kept[b] = (b == i1 || b == i2 || b == i3) ? 1 : 0;
+}
+
+void oracle_search_last_frame(
+    int nL, const float *lpos, const uint8_t *ldesc, const uint8_t *lo, const float *la,
+    int nK, const float *kx, const float *ky, const uint8_t *ko, const uint8_t *kdesc,
+    const float *ka, const float *u_right, const uint8_t *preassigned,
+    int model, const float *cam, const float *R, const float *t, const float *bounds,
+    const float *sf, int n_levels, const float *fp, const int32_t *ip,
+    int32_t *l_match, int32_t *l_dist, int32_t *kp_match, int64_t *stats)
+{
+    const float th = fp[0];
+    const int th_high = ip[0], direction = ip[1], check_rot = ip[2], bins = ip[3];
+    const float fx = cam[0], fy = cam[1], cx = cam[2], cy = cam[3], bf = cam[8];
+    int64_t n_in = 0, n_cand = 0, n_acc = 0;
+    int32_t *cand_k = (int32_t *)malloc(sizeof(int32_t) * (nL > 0 ? nL : 1));
+    int32_t *cand_h = (int32_t *)malloc(sizeof(int32_t) * (nL > 0 ? nL : 1));
+    uint8_t *alive = (uint8_t *)calloc(nL > 0 ? nL : 1, 1);
+
+    for (int k = 0; k < nK; ++k) kp_match[k] = -1;
+    for (int i = 0; i < nL; ++i) {
+        l_match[i] = -1; l_dist[i] = -1;
+        const float X = lpos[3 * i], Y = lpos[3 * i + 1], Z = lpos[3 * i + 2];
+        const float xc = ((R[0] * X + R[1] * Y) + R[2] * Z) + t[0];
+        const float yc = ((R[3] * X + R[4] * Y) + R[5] * Z) + t[1];
+        const float zc = ((R[6] * X + R[7] * Y) + R[8] * Z) + t[2];
+        if (!(zc > 0.0f)) continue;
+        float u, v;
+        if (model == 0) {
+            u = ((fx * xc) / zc) + cx;
+            v = ((fy * yc) / zc) + cy;
+        } else {
+            double Pc[3] = {(double)xc, (double)yc, (double)zc}, uv[2];
+            oracle_kb_project(cam, Pc, uv);
+            u = (float)uv[0];
+            v = (float)uv[1];
+        }
+        if (!(u >= bounds[0] && u <= bounds[1] && v >= bounds[2] && v <= bounds[3])) continue;
+        ++n_in;
+        const int ol = lo[i];
+        const float r = th * sf[ol < n_levels ? ol : n_levels - 1];
+        int lv_min, lv_max;
+        if (direction > 0) { lv_min = ol; lv_max = n_levels - 1; }
+        else if (direction < 0) { lv_min = 0; lv_max = ol; }
+        else { lv_min = ol - 1; lv_max = ol + 1; }
+        float ur_proj = 0.0f;
+        if (u_right) ur_proj = u - bf * (1.0f / zc);
+        int best = 1000, kbest = -1;
+        for (int k = 0; k < nK; ++k) {
+            if (ko[k] < lv_min || ko[k] > lv_max) continue;
+            if (!(fabsf(kx[k] - u) < r && fabsf(ky[k] - v) < r)) continue;
+            if (preassigned && preassigned[k]) continue;
+            if (u_right && u_right[k] > 0.0f && !(fabsf(ur_proj - u_right[k]) <= r)) continue;
+            ++n_cand;
+            const int h = oracle_hamming(ldesc + 32 * (size_t)i, kdesc + 32 * (size_t)k);
+            if (h < best) { best = h; kbest = k; }
+        }
+        if (kbest < 0 || !(best <= th_high)) continue;
+        ++n_acc;
+        cand_k[i] = kbest; cand_h[i] = best; alive[i] = 1;
+    }
+    resolve_conflicts(nL, cand_k, cand_h, nK, alive);
+    int64_t n_conf = 0;
+    for (int i = 0; i < nL; ++i) n_conf += alive[i];
+    int32_t kept3[3] = {-1, -1, -1};
+    if (check_rot && bins > 0) {
+        int32_t *count = (int32_t *)calloc((size_t)bins, sizeof(int32_t));
+        int32_t *kept = (int32_t *)calloc((size_t)bins, sizeof(int32_t));
+        for (int i = 0; i < nL; ++i)
+            if (alive[i]) ++count[oracle_rotation_bin(la[i], ka[cand_k[i]], bins)];
+        oracle_three_fullest(count, bins, kept);
+        for (int i = 0; i < nL; ++i)
+            if (alive[i] && !kept[oracle_rotation_bin(la[i], ka[cand_k[i]], bins)]) alive[i] = 0;
+        for (int b = 0, n = 0; b < bins && n < 3; ++b)
+            if (kept[b]) kept3[n++] = b;
+        free(count); free(kept);
+    }
+    int64_t n_match = 0;
+    for (int i = 0; i < nL; ++i) {
+        if (!alive[i]) continue;
+        l_match[i] = cand_k[i]; l_dist[i] = cand_h[i]; kp_match[cand_k[i]] = i;
+        ++n_match;
+    }
+    if (stats) {
+        stats[0] = n_in; stats[1] = n_cand; stats[2] = n_acc; stats[3] = n_conf; stats[4] = n_match;
+        stats[5] = kept3[0]; stats[6] = kept3[1]; stats[7] = kept3[2];
+    }
+    free(cand_k); free(cand_h); free(alive);
+}

@@ -80,6 +80,40 @@ void oracle_search_local_points(
     const float *fp, const int32_t *ip,
     int32_t *mp_match, int32_t *mp_dist, int32_t *kp_match, int64_t *stats);
 
+/* Search by projection of the last frame's matched map points into the
+ * current frame (Section II-C, Initial Pose Estimation; Section IV-E: the same
+ * kernel serves both call sites).  Last-frame point i has world position
+ * lpos[i], descriptor ldesc[i], and the octave lo[i] and orientation la[i]
+ * (degrees) of the last-frame keypoint that observed it.  For each point:
+ * project with the current pose (as in the local-map search); keep it if
+ * Z_c > 0 and inside the image bounds; radius th * sf[lo[i]]; keypoint levels
+ * [lo - 1, lo + 1] (direction 0), [lo, n_levels - 1] (1, camera moving
+ * forward) or [0, lo] (-1, moving backward); candidates |x - u| < r,
+ * |y - v| < r, not preassigned, and within r of the projected right
+ * coordinate where u_right > 0; best (distance, keypoint) accepted when
+ * distance <= th_high.  Two points claiming one keypoint: the smaller
+ * (distance, point) key keeps it.  Then, when check_orientation is set, the
+ * rotation rot = la[i] - ka[k] (plus 360 when negative) of every surviving
+ * match falls in bin roundf(rot * bins / 360) (bin == bins counts as 0); the
+ * three fullest bins are kept (ties: the lower bin), the second and third
+ * only while 10 * count >= the fullest count; matches in other bins are
+ * dropped.  cam, model, R, t, bounds as for oracle_search_local_points.
+ * fp = {th}; ip = {th_high, direction, check_orientation, bins}.
+ * stats: projected inside the image, candidates, accepted, after the
+ * conflict rule, after the rotation check, then the three kept bins. */
+void oracle_search_last_frame(
+    int nL, const float *lpos, const uint8_t *ldesc, const uint8_t *lo, const float *la,
+    int nK, const float *kx, const float *ky, const uint8_t *ko, const uint8_t *kdesc,
+    const float *ka, const float *u_right, const uint8_t *preassigned,
+    int model, const float *cam, const float *R, const float *t, const float *bounds,
+    const float *sf, int n_levels, const float *fp, const int32_t *ip,
+    int32_t *l_match, int32_t *l_dist, int32_t *kp_match, int64_t *stats);
+
+/* Rotation bin of a match and the bins kept by the three-fullest rule, exposed
+ * so tests can pin them on their own. */
+int oracle_rotation_bin(float a_last, float a_cur, int bins);
+void oracle_three_fullest(const int32_t *count, int bins, int32_t *kept);
+
 /* Stage helpers of the pinhole refinement and of the level prediction,
  * exported so tests can pin each stage on its own. */
 int oracle_sad_window(const uint8_t *IL, const uint8_t *IR, int Wl, int Hl,

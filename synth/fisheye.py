@@ -146,6 +146,7 @@ def fisheye_frame(seed, n_kp: int = 1500, n_map: int = 5000, grid=(64, 48),
     mp = C.map_point_fields(r_map, P, np.zeros(3), o_ref, sc, mdesc)
     pm = r_map.permutation(n_map)
     mp = {k: np.ascontiguousarray(v[pm]) for k, v in mp.items()}
+    inv_m = np.argsort(pm)
 
     R_lw, t_lw, O_l = C.perturbed_pose(r_pose, np.eye(3), np.zeros(3))
     R_rw = R_rl @ R_lw
@@ -181,7 +182,8 @@ def fisheye_frame(seed, n_kp: int = 1500, n_map: int = 5000, grid=(64, 48),
              "use_u_right": False},
         ],
         "search_params": C.search_params(th),
-        "truth": {"stereo_pairs": true_pairs, "points": XL},
+        "truth": {"stereo_pairs": true_pairs, "points": XL,
+                  "map_kp": np.stack([inv_m[:n_from], inv_l[pick]], axis=1)},
         "size": {"W": W, "H": H},
     }
     return frame

@@ -215,3 +215,82 @@ def search_pinhole(frame, view=0, u_right=None):
                       "rej_frame": int((~in_frame).sum()), "rej_near": int((in_frame & ~near_ok).sum()),
                       "rej_far": int((in_frame & near_ok & ~far_ok).sum()),
                       "rej_angle": int((in_frame & near_ok & far_ok & ~angle_ok).sum())}}
+
+
+def rotation_bins(a_last, a_cur, bins):
+    """Rotation bin of every match, binary32 as in the definition."""
+    rot = (np.asarray(a_last, np.float32) - np.asarray(a_cur, np.float32)).astype(np.float32)
+    rot = np.where(rot < 0, (rot + f32(360.0)).astype(np.float32), rot)
+    b = round_half_away((rot * (f32(bins) / f32(360.0))).astype(np.float32))
+    return np.where(b >= bins, 0, b)
+
+
+def three_fullest(count):
+    """Kept bins: the fullest and, while 10 * count >= the fullest, the second
+    and third fullest; ties go to the lower bin (stable sort by -count)."""
+    count = np.asarray(count, np.int64)
+    order = np.argsort(-count, kind="stable")
+    kept = np.zeros(len(count), bool)
+    if len(count) == 0 or count[order[0]] == 0:
+        return kept
+    m1 = count[order[0]]
+    kept[order[0]] = True
+    for j in (1, 2):
+        if j < len(count) and count[order[j]] > 0 and 10 * count[order[j]] >= m1:
+            kept[order[j]] = True
+        else:
+            break
+    return kept
+
+
+def search_last_frame_pinhole(case):
+    """Last-frame search by projection (pinhole camera) over every (point,
+    keypoint) pair."""
+    last, kp, cam, prm = case["last"], case["kps"], case["cam"], case["params"]
+    sf = case["scales"]["sf"]
+    nL, nK = len(last["octave"]), len(kp["x"])
+    R, t = cam["R"], cam["t"]
+    P = last["pos"]
+    X, Y, Z = P[:, 0], P[:, 1], P[:, 2]
+    xc = ((R[0, 0] * X + R[0, 1] * Y) + R[0, 2] * Z) + t[0]
+    yc = ((R[1, 0] * X + R[1, 1] * Y) + R[1, 2] * Z) + t[1]
+    zc = ((R[2, 0] * X + R[2, 1] * Y) + R[2, 2] * Z) + t[2]
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        u = ((cam["fx"] * xc) / zc) + cam["cx"]
+        v = ((cam["fy"] * yc) / zc) + cam["cy"]
+    b = cam["bounds"]
+    inside = (zc > 0) & (u >= b[0]) & (u <= b[1]) & (v >= b[2]) & (v <= b[3])
+    lo = last["octave"].astype(np.int64)
+    r = (f32(prm["th"]) * sf[np.minimum(lo, len(sf) - 1)]).astype(np.float32)
+    d = prm["direction"]
+    lv_min = np.where(d > 0, lo, np.where(d < 0, 0, lo - 1))
+    lv_max = np.where(d > 0, len(sf) - 1, np.where(d < 0, lo, lo + 1))
+    ko = kp["octave"].astype(np.int64)
+    with np.errstate(invalid="ignore", over="ignore"):
+        C = (inside[:, None] & (ko[None, :] >= lv_min[:, None]) & (ko[None, :] <= lv_max[:, None]) &
+             (np.abs(kp["x"][None, :] - u[:, None]) < r[:, None]) &
+             (np.abs(kp["y"][None, :] - v[:, None]) < r[:, None]))
+        if case.get("preassigned") is not None:
+            C &= ~case["preassigned"].astype(bool)[None, :]
+        if case.get("u_right") is not None:
+            ur = case["u_right"]
+            uR = u - cam["bf"] * (f32(1.0) / zc)
+            C &= ~((ur[None, :] > 0) & ~(np.abs(uR[:, None] - ur[None, :]) <= r[:, None]))
+    Hm = hamming_matrix(last["desc"], kp["desc"])
+    H1, k1, _, _ = lexmin2(C, Hm)
+    acc = (k1 >= 0) & (H1 <= prm["th_high"])
+    alive = resolve(k1, H1, acc, nK)
+    kept_bins = []
+    if prm["check_orientation"]:
+        q = np.nonzero(alive)[0]
+        bins = rotation_bins(last["angle"][q], kp["angle"][k1[q]], prm["bins"])
+        kept = three_fullest(np.bincount(bins, minlength=prm["bins"]))
+        alive[q] = kept[bins]
+        kept_bins = [int(x) for x in np.nonzero(kept)[0]]
+    lm = np.where(alive, k1, -1)
+    kp_match = np.full(nK, -1)
+    kp_match[k1[alive]] = np.nonzero(alive)[0]
+    return {"last_match": lm, "last_dist": np.where(alive, H1, -1), "kp_match": kp_match,
+            "kept_bins": kept_bins,
+            "stats": {"in_image": int(inside.sum()), "candidates": int(C.sum()),
+                      "accepted": int(acc.sum()), "matches": int(alive.sum())}}

@@ -11,6 +11,7 @@ import pytest
 import oracle
 import synth
 from tests import test_oracle_pins as pins
+from tests import test_oracle_motion as motion
 from tests import test_oracle_pyramid as pyr
 
 HERE = os.path.dirname(os.path.abspath(oracle.__file__))
@@ -66,6 +67,19 @@ MUTANTS = {
     "pyramid_size_truncated": ("w[l] = (int32_t)floorf(fw + 0.5f);", "w[l] = (int32_t)floorf(fw);"),
     "pyramid_rows_from_width": ("pyramid_tap(y, H, h[l], &y0, &b);", "pyramid_tap(y, W, h[l], &y0, &b);"),
     "pyramid_weights_swapped": ("const int top = (256 - a) * p00 + a * p01;", "const int top = a * p00 + (256 - a) * p01;"),
+    "last_forward_window": ("if (direction > 0) { lv_min = ol; lv_max = n_levels - 1; }",
+                            "if (direction > 0) { lv_min = ol + 1; lv_max = n_levels - 1; }"),
+    "last_backward_window": ("else if (direction < 0) { lv_min = 0; lv_max = ol; }",
+                             "else if (direction < 0) { lv_min = 0; lv_max = ol - 1; }"),
+    "last_radius_level": ("const float r = th * sf[ol < n_levels ? ol : n_levels - 1];", "const float r = th * sf[0];"),
+    "last_threshold_strict": ("if (kbest < 0 || !(best <= th_high)) continue;", "if (kbest < 0 || !(best < th_high)) continue;"),
+    "last_stereo_gate_sign": ("if (u_right) ur_proj = u - bf * (1.0f / zc);", "if (u_right) ur_proj = u + bf * (1.0f / zc);"),
+    "last_conflict_skipped": ("    resolve_conflicts(nL, cand_k, cand_h, nK, alive);\n", ""),
+    "rotation_sign": ("float rot = a_last - a_cur;", "float rot = a_cur - a_last;"),
+    "rotation_wrap": ("if (bin >= bins) bin = 0;", "if (bin >= bins) bin = bins - 1;"),
+    "three_fullest_tenth": ("if (10 * m2 < m1) { i2 = -1; i3 = -1; }", "if (2 * m2 < m1) { i2 = -1; i3 = -1; }"),
+    "three_fullest_third_always": ("else if (10 * m3 < m1) i3 = -1;", ""),
+    "three_fullest_tie_to_later": ("if (c > m1) { m3 = m2;", "if (c >= m1) { m3 = m2;"),
     "conflict_tie": ("int64_t key = ((int64_t)dist[i] << 32) | (int64_t)i;\n        if (key < best",
                      "int64_t key = ((int64_t)dist[i] << 32) | (int64_t)(nQ - i);\n        if (key < best"),
 }
@@ -108,6 +122,19 @@ def _pins(frames):
     tests.append(pins.test_fisheye_depth_gate_scene)
     tests.append(pins.test_fisheye_reprojection_gate_scene)
     tests.append(pins.test_fisheye_needs_two_targets)
+    for kind in ("pinhole", "clustered"):
+        for d in (0, 1, -1):
+            tests.append(lambda k=kind, d=d: motion.test_last_frame_search_equals_bruteforce(k, d))
+    for a, c, w in [(10.0, 11.0, 0), (0.0, 174.0, 16), (342.0, 0.0, 29), (11.0, 0.0, 1)]:
+        tests.append(lambda a=a, c=c, w=w: motion.test_rotation_bin_closed_forms(a, c, w))
+    for cnt, kept in [([5, 9, 9, 1], [0, 1, 2]), ([100, 9, 10, 0], [0, 2]), ([100, 5, 5], [0]),
+                      ([3, 3, 3, 3], [0, 1, 2])]:
+        tests.append(lambda c=cnt, k=kept: motion.test_three_fullest_rule_closed_forms(c, k))
+    for args in [(2, 3, 1, False), (3, 3, 1, True), (4, 3, -1, False), (3, 3, -1, True), (2, 3, 0, True)]:
+        tests.append(lambda a=args: motion.test_level_window_follows_the_direction_of_motion(*a))
+    tests.append(motion.test_stereo_gate_and_preassigned_flag)
+    tests.append(lambda: motion.test_distance_threshold_is_inclusive(100, True))
+    tests.append(motion.test_two_points_claiming_one_keypoint)
     tests.append(pyr.test_level_sizes_of_the_paper_shapes)
     tests.append(lambda: pyr.test_horizontal_ramp_is_round_half_up_of_the_source_column(200, 37))
     tests.append(lambda: pyr.test_vertical_ramp_is_round_half_up_of_the_source_row(40, 250))
