@@ -268,6 +268,30 @@ ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_poi
                                  const ft_grid *grid, const ft_scales *scales,
                                  const ft_search_params *params, const ft_search_out *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid allocation): the search of
+ * ft_search_local_points, same kernels and bit-identical outputs, with no
+ * context.  Its workspace is a fixed device array that every GPU the library
+ * runs on holds for the life of the process (FT_NOALLOC_SCRATCH_BYTES, 1 MiB);
+ * the call allocates nothing and runs on the calling thread's current device.
+ * Limits: kps->n <= FT_NOALLOC_MAX_KP, map->n <= FT_NOALLOC_MAX_MAP, grid
+ * cols*rows <= 8192, else FT_ERR_CAPACITY with nothing enqueued; other errors
+ * as for ft_search_local_points (FT_ERR_UNSUPPORTED on a device that is not
+ * gfx950).  Every call on one GPU uses that GPU's one array, so two calls
+ * whose device work overlaps (different streams, or different threads) race
+ * and both outputs are undefined: order them on one stream.  The array holds
+ * whatever the last call left; the kernels initialise every part they read.
+ * The text of the last error of this entry point on the calling thread is
+ * ft_last_error(NULL). */
+#define FT_NOALLOC_MAX_KP 8192
+#define FT_NOALLOC_MAX_MAP 65536
+#define FT_NOALLOC_SCRATCH_BYTES 1048576
+ft_status ft_search_local_points_noalloc(void *stream, const ft_map_points *map,
+                                         const ft_search_camera *cam, const ft_keypoints *kps,
+                                         const float *u_right, const uint8_t *preassigned,
+                                         const ft_grid *grid, const ft_scales *scales,
+                                         const ft_search_params *params, const ft_search_out *out);
+
 /* ------------------------------------------------------------------------ */
 /* Batched frames: many frames of uneven size in one submission.             */
 /* ------------------------------------------------------------------------ */

@@ -148,6 +148,10 @@ EXPORTS = {
                                ct.POINTER(ft_keypoints), P, P, ct.POINTER(ft_grid),
                                ct.POINTER(ft_scales), ct.POINTER(ft_search_params),
                                ct.POINTER(ft_search_out)],
+    "ft_search_local_points_noalloc": [P, ct.POINTER(ft_map_points), ct.POINTER(ft_search_camera),
+                                       ct.POINTER(ft_keypoints), P, P, ct.POINTER(ft_grid),
+                                       ct.POINTER(ft_scales), ct.POINTER(ft_search_params),
+                                       ct.POINTER(ft_search_out)],
     "ft_batch_submit": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.POINTER(ct.c_uint64)],
     "ft_batch_poll": [P, ct.c_uint64, ct.POINTER(ct.c_int32)],
     "ft_batch_wait": [P, ct.c_uint64],
@@ -203,6 +207,23 @@ def default_limits(**kw) -> ft_limits:
              max_batch_map_total=0)
     v.update(kw)
     return ft_limits(**v)
+
+
+FT_NOALLOC_MAX_KP, FT_NOALLOC_MAX_MAP, FT_NOALLOC_SCRATCH_BYTES = 8192, 65536, 1 << 20
+
+
+def ft_search_local_points_noalloc(map_points, cam, kps, u_right, preassigned, grid, scales, params,
+                                   out, stream=None, check=True):
+    """The context-free, allocation-free search (same outputs as
+    Context.ft_search_local_points) on the current device."""
+    lib = load()
+    st = lib.ft_search_local_points_noalloc(_stream(stream), ct.byref(map_points), ct.byref(cam),
+                                            ct.byref(kps), P(u_right or None), P(preassigned or None),
+                                            ct.byref(grid), ct.byref(scales), ct.byref(params),
+                                            ct.byref(out))
+    if check and st != FT_OK:
+        raise FtError(st, f"ft_search_local_points_noalloc: {lib.ft_last_error(None).decode()}")
+    return st
 
 
 def _stream(stream) -> P:

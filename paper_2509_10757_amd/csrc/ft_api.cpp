@@ -170,6 +170,9 @@ void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
     for (int v = 0; v < 2; ++v) carve_view(s, v, base, b, kp, mp);
 }
 
+// Text of the last error of the context-free entry point on this thread.
+thread_local char g_noalloc_err[256] = "";
+
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 bool valid_lanes(int g) { return g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
@@ -817,7 +820,11 @@ const char *ft_status_string(ft_status s)
     }
 }
 
-const char *ft_last_error(const ft_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *ft_last_error(const ft_context *ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_noalloc_err[0] ? g_noalloc_err : "null context";
+}
 
 ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **out)
 {
@@ -1082,6 +1089,51 @@ ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_poi
     fill_search_common(J, map, params);
     if ((st = build_view(ctx, J, 0, 0, cam, kps, u_right, preassigned, grid, out, ctx->direct))) return st;
     return launch_one(ctx, J, (hipStream_t)stream, false, true);
+}
+
+ft_status ft_search_local_points_noalloc(void *stream, const ft_map_points *map,
+                                         const ft_search_camera *cam, const ft_keypoints *kps,
+                                         const float *u_right, const uint8_t *preassigned,
+                                         const ft_grid *grid, const ft_scales *scales,
+                                         const ft_search_params *params, const ft_search_out *out)
+{
+    g_noalloc_err[0] = 0;
+    // a context on the host stack carries the limits the validators check and
+    // the error text; it owns no device memory
+    ft_context tmp;
+    auto done = [&](ft_status st) {
+        if (st) snprintf(g_noalloc_err, sizeof g_noalloc_err, "%s", tmp.err.c_str());
+        return st;
+    };
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return done(fail(&tmp, FT_ERR_DEVICE, "noalloc: hipGetDevice failed"));
+    tmp.device = dev;
+    tmp.lim.max_kp_per_image = FT_NOALLOC_MAX_KP;
+    tmp.lim.max_map_points = FT_NOALLOC_MAX_MAP;
+    tmp.lim.max_rows = kMaxRows;
+    tmp.lim.max_grid_cells = kMaxCells;
+    tmp.lim.max_batch_frames = 1;
+    tmp.lim.max_inflight = 1;
+    tmp.lim.max_levels = kLevels;
+    ft_status st;
+    if ((st = check_scales(&tmp, scales)) || (st = check_search_common(&tmp, map, params))) return done(st);
+    bool gfx950 = false;
+    char *base = nullptr;
+    const hipError_t e = noalloc_scratch(dev, &base, &gfx950);
+    if (e != hipSuccess)
+        return done(fail(&tmp, FT_ERR_DEVICE, "noalloc: device scratch lookup failed: %s", hipGetErrorString(e)));
+    if (!gfx950) return done(fail(&tmp, FT_ERR_UNSUPPORTED, "noalloc: device %d is not gfx950", dev));
+    Slot slot{};
+    Bump b;
+    carve_view(slot, 0, base, b, FT_NOALLOC_MAX_KP, FT_NOALLOC_MAX_MAP);
+    if (b.off > kNoallocScratchBytes)
+        return done(fail(&tmp, FT_ERR_UNSUPPORTED, "noalloc: workspace %zu B exceeds the %zu B scratch", b.off,
+                         kNoallocScratchBytes));
+    DevJob J{};
+    fill_scales(J, scales);
+    fill_search_common(J, map, params);
+    if ((st = build_view(&tmp, J, 0, 0, cam, kps, u_right, preassigned, grid, out, slot))) return done(st);
+    return done(launch_one(&tmp, J, (hipStream_t)stream, false, true));
 }
 
 ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,

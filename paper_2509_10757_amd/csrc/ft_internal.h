@@ -187,6 +187,14 @@ hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_
 // workgroup size: the nodes of a lane's batch graph.
 void batch_kernels(const Shapes &shapes, void *fn[PH_COUNT], int block[PH_COUNT]);
 
+// Allocation-free search (ft_noalloc.hip): the workspace of one view in a
+// fixed device array of every GPU, kNoallocScratchBytes long, sized for
+// FT_NOALLOC_MAX_KP keypoints, FT_NOALLOC_MAX_MAP map points and kMaxCells
+// grid cells.  noalloc_scratch returns the current device's address of it
+// and whether the device is a gfx950 (both looked up once per device).
+constexpr size_t kNoallocScratchBytes = FT_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch(int device, char **out, bool *gfx950);
+
 // Gather-list copy (ft_upload.hip): up to kUploadSegs segments per launch,
 // passed by value; each workgroup copies one kUploadChunk-byte chunk of one
 // segment.  `first[s]` is the first workgroup of segment s, first[n] the grid.
