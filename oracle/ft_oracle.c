@@ -581,15 +581,16 @@ void oracle_search_local_points(
 }
 
 /* Rotation bin of a match between a last-frame keypoint (orientation a_last)
- * and a current keypoint (a_cur), degrees: the rotation taken into [0, 360)
- * and rounded to one of `bins` equal bins; the bin past the last wraps to 0. */
+ * and a current keypoint (a_cur), degrees: the rotation plus 360 when
+ * negative, rounded to one of `bins` equal bins and taken modulo `bins` (for
+ * angles in [0, 360) only the bin past the last wraps, to 0). */
 int oracle_rotation_bin(float a_last, float a_cur, int bins)
 {
     float rot = a_last - a_cur;
     if (rot < 0.0f) rot += 360.0f;
     const float factor = (float)bins / 360.0f;
-    int bin = (int)roundf(rot * factor);
-    if (bin >= bins) bin = 0;
+    int bin = (int)roundf(rot * factor) % bins;   /* the bin past the last is bin 0 */
+    if (bin < 0) bin += bins;
     return bin;
 }
 

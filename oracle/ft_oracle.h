@@ -94,7 +94,7 @@ void oracle_search_local_points(
  * distance <= th_high.  Two points claiming one keypoint: the smaller
  * (distance, point) key keeps it.  Then, when check_orientation is set, the
  * rotation rot = la[i] - ka[k] (plus 360 when negative) of every surviving
- * match falls in bin roundf(rot * bins / 360) (bin == bins counts as 0); the
+ * match falls in bin roundf(rot * bins / 360) mod bins; the
  * three fullest bins are kept (ties: the lower bin), the second and third
  * only while 10 * count >= the fullest count; matches in other bins are
  * dropped.  cam, model, R, t, bounds as for oracle_search_local_points.

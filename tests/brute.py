@@ -222,7 +222,7 @@ def rotation_bins(a_last, a_cur, bins):
     rot = (np.asarray(a_last, np.float32) - np.asarray(a_cur, np.float32)).astype(np.float32)
     rot = np.where(rot < 0, (rot + f32(360.0)).astype(np.float32), rot)
     b = round_half_away((rot * (f32(bins) / f32(360.0))).astype(np.float32))
-    return np.where(b >= bins, 0, b)
+    return np.mod(b, bins)
 
 
 def three_fullest(count):

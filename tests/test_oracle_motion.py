@@ -55,10 +55,11 @@ def test_last_frame_search_full_size_equals_bruteforce():
 @pytest.mark.parametrize("a_last,a_cur,want", [
     (0.0, 0.0, 0), (10.0, 10.0, 0), (10.0, 11.0, 0),     # -1 deg -> 359 -> 29.92 -> 30 -> wraps to 0
     (180.0, 0.0, 15), (11.0, 0.0, 1), (17.0, 0.0, 1), (19.0, 0.0, 2),
-    (0.0, 174.0, 16), (359.0, 0.0, 0), (353.0, 0.0, 29), (342.0, 0.0, 29)])
+    (0.0, 174.0, 16), (359.0, 0.0, 0), (353.0, 0.0, 29), (342.0, 0.0, 29),
+    (400.0, 0.0, 3), (0.0, 500.0, 18), (720.0, 0.0, 0)])   # angles outside [0, 360): bin modulo 30
 def test_rotation_bin_closed_forms(a_last, a_cur, want):
     """30 bins of 12 degrees centred on multiples of 12: a rotation r lands in
-    bin round(r / 12) of [0, 360), the bin past the last wrapping to 0."""
+    bin round(r / 12) mod 30 (after adding 360 to a negative rotation)."""
     assert oracle.rotation_bin(a_last, a_cur, 30) == want
     assert brute.rotation_bins([a_last], [a_cur], 30)[0] == want
 

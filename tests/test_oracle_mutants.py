@@ -76,7 +76,7 @@ MUTANTS = {
     "last_stereo_gate_sign": ("if (u_right) ur_proj = u - bf * (1.0f / zc);", "if (u_right) ur_proj = u + bf * (1.0f / zc);"),
     "last_conflict_skipped": ("    resolve_conflicts(nL, cand_k, cand_h, nK, alive);\n", ""),
     "rotation_sign": ("float rot = a_last - a_cur;", "float rot = a_cur - a_last;"),
-    "rotation_wrap": ("if (bin >= bins) bin = 0;", "if (bin >= bins) bin = bins - 1;"),
+    "rotation_wrap": ("int bin = (int)roundf(rot * factor) % bins;", "int bin = (int)roundf(rot * factor); if (bin >= bins) bin = bins - 1;"),
     "three_fullest_tenth": ("if (10 * m2 < m1) { i2 = -1; i3 = -1; }", "if (2 * m2 < m1) { i2 = -1; i3 = -1; }"),
     "three_fullest_third_always": ("else if (10 * m3 < m1) i3 = -1;", ""),
     "three_fullest_tie_to_later": ("if (c > m1) { m3 = m2;", "if (c >= m1) { m3 = m2;"),
