@@ -268,6 +268,83 @@ ft_status ft_search_local_points(ft_context *ctx, void *stream, const ft_map_poi
                                  const ft_grid *grid, const ft_scales *scales,
                                  const ft_search_params *params, const ft_search_out *out);
 
+/* ------------------------------------------------------------------------ */
+/* Image pyramid (Section IV-B: the ORB extractor the paper reuses builds the */
+/* pyramid on the device and stereo matching reads it there; 90% of stereo's  */
+/* input bytes).                                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct ft_image {
+    const uint8_t *data;       /* device, level-0 image, row-major */
+    int32_t width, height;     /* 2 <= width <= FT_PYRAMID_MAX_WIDTH, 2 <= height <= 4096 */
+    int32_t pitch;             /* bytes from one row to the next, >= width */
+} ft_image;
+
+#define FT_PYRAMID_MAX_WIDTH 1536
+
+/* Level sizes and packed offsets of the pyramid of a width x height image:
+ * level l is floor(width * inv_sf[l] + 0.5) x floor(height * inv_sf[l] + 0.5)
+ * (binary32 product), levels stored row-major one after another from offset
+ * 0.  Fills offset, width and height of *pyr (not data) and the total byte
+ * count in *bytes.  Host only, no context.  A level of size 0 or a size out of
+ * range: FT_ERR_INVALID_ARGUMENT. */
+ft_status ft_pyramid_layout(int32_t width, int32_t height, const ft_scales *scales, ft_pyramid *pyr,
+                            int64_t *bytes);
+
+/* Builds the pyramid of `image` into pyr->data (device, the layout's bytes;
+ * pyr's offsets and sizes must equal ft_pyramid_layout's): level 0 is a copy
+ * of the image and every other level a bilinear resample of level 0, all
+ * levels in one launch.  The source coordinate of output index x of a level n
+ * wide over a level-0 axis N long is (x + 1/2) * N / n - 1/2, taken exactly;
+ * the weights are floor(256 * fraction), the taps clamp at the borders, and
+ * the value (sum of weight products + 2^15) >> 16.  Errors as above. */
+ft_status ft_build_pyramid(ft_context *ctx, void *stream, const ft_image *image, const ft_scales *scales,
+                           const ft_pyramid *pyr);
+
+/* ------------------------------------------------------------------------ */
+/* Last-frame search by projection (Section II-C, Initial Pose Estimation:   */
+/* the previous frame's map points are projected into the current frame and */
+/* matched against its keypoints; Section IV-E: one kernel serves both call  */
+/* sites).                                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct ft_last_points {
+    int32_t n;
+    const float *pos;          /* [n][3] world position of each matched map point */
+    const uint8_t *desc;       /* [n][32] its descriptor, 16-byte aligned */
+    const uint8_t *octave;     /* [n] octave of the last-frame keypoint that observed it */
+    const float *angle;        /* [n] orientation of that keypoint, degrees (nullable when the
+                                  rotation check is off) */
+} ft_last_points;
+
+typedef struct ft_last_params {
+    float th;                  /* window half-size = th * sf[last octave] (7) */
+    int32_t th_high;           /* accept when distance <= th_high (100) */
+    int32_t direction;         /* keypoint levels searched: 0 = octave-1..octave+1, 1 = the camera
+                                  moves forward: octave..7, -1 = backward: 0..octave */
+    int32_t check_orientation; /* 1: keep only matches in the three fullest rotation bins */
+    int32_t bins;              /* rotation bins over 360 degrees (30), 1..64 */
+} ft_last_params;
+
+/* For every last-frame point: project with the current camera (pinhole or the
+ * left/right KB view, as in ft_search_local_points), keep it if in front of
+ * the camera and inside the image, and take the best keypoint (distance, then
+ * index) inside the window, at the allowed levels, not preassigned and, when
+ * `u_right` is given, within the window of the projected right coordinate
+ * where u_right > 0; accept at distance <= th_high.  Two points claiming one
+ * keypoint: the smaller (distance, point index) keeps it.  With the rotation
+ * check, the rotation last angle - current angle (kp_angle, device [kps->n],
+ * degrees) of each match falls in bin round(rot * bins / 360) mod bins; the
+ * three fullest bins are kept (ties to the lower bin), the second and third
+ * only while 10 * count >= the fullest count, and other matches are dropped.
+ * Outputs as for ft_search_local_points, indexed by last-frame point
+ * (mp_match / mp_dist) and by keypoint (kp_match holds the point index).
+ * Requirements: last->n <= max_map_points, kps->n <= max_kp_per_image, grid
+ * cols*rows <= max_grid_cells.  Errors as above. */
+ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_points *last,
+                               const ft_search_camera *cam, const ft_keypoints *kps, const float *kp_angle,
+                               const float *u_right, const uint8_t *preassigned, const ft_grid *grid,
+                               const ft_scales *scales, const ft_last_params *params,
+                               const ft_search_out *out);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops or harnesses that forbid allocation): the search of
  * ft_search_local_points, same kernels and bit-identical outputs, with no
@@ -310,6 +387,9 @@ typedef struct ft_frame_job {
     ft_pinhole_params pinhole_params;
     ft_pinhole_out pinhole_out;
     int32_t use_u_right;       /* pinhole: gate the left view with the stereo u_right */
+    int32_t build_pyramids;    /* pinhole: build pyr_left / pyr_right from image_left /
+                                  image_right first (as ft_build_pyramid) */
+    ft_image image_left, image_right;
     /* fisheye stereo */
     ft_fisheye_stereo fisheye;
     ft_fisheye_params fisheye_params;
@@ -423,14 +503,14 @@ const char *ft_status_string(ft_status status);
 const char *ft_last_error(const ft_context *ctx);
 /* Per-phase kernel timing (for measurement tools).  When enabled, every
  * submission records HIP events on its own stream around each phase kernel:
- * 0 setup (row index / overlap lists / grids), 1 stereo best match (pinhole
- * row band or fisheye all-pairs), 2 pinhole refinement, 3 fisheye
- * triangulation check, 4 stereo resolve + outputs, 5 search by projection,
- * 6 search resolve + outputs.
+ * 0 image pyramids (jobs that build them), 1 setup (row index / overlap
+ * lists / grids), 2 stereo best match (pinhole row band or fisheye
+ * all-pairs), 3 pinhole refinement, 4 fisheye triangulation check, 5 stereo
+ * resolve + outputs, 6 search by projection, 7 search resolve + outputs.
  * ft_context_read_timing waits for the recorded work, returns the summed
  * milliseconds and launch counts per phase (arrays of FT_PHASES), and resets
  * them.  Enabling timing adds event records between kernels. */
-#define FT_PHASES 7
+#define FT_PHASES 8
 ft_status ft_context_enable_timing(ft_context *ctx, int32_t enable);
 ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches);
 /* Library version as major*10000 + minor*100 + patch. */

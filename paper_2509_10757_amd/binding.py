@@ -18,7 +18,7 @@ from . import build as _build
 
 LEVELS = 8
 FT_OK, FT_ERR_INVALID_ARGUMENT, FT_ERR_CAPACITY, FT_ERR_DEVICE, FT_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
-FT_PHASES = 7
+FT_PHASES = 8
 FT_CAMERA_PINHOLE, FT_CAMERA_KB = 0, 1
 FT_JOB_PINHOLE, FT_JOB_FISHEYE, FT_JOB_SEARCH = 1, 2, 3
 FT_EXEC_EAGER, FT_EXEC_GRAPH = 0, 1
@@ -113,12 +113,26 @@ class ft_search_out(ct.Structure):
     _fields_ = [("mp_match", P), ("mp_dist", P), ("kp_match", P), ("n_matches", P)]
 
 
+class ft_image(ct.Structure):
+    _fields_ = [("data", P), ("width", ct.c_int32), ("height", ct.c_int32), ("pitch", ct.c_int32)]
+
+
+class ft_last_points(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("pos", P), ("desc", P), ("octave", P), ("angle", P)]
+
+
+class ft_last_params(ct.Structure):
+    _fields_ = [("th", ct.c_float), ("th_high", ct.c_int32), ("direction", ct.c_int32),
+                ("check_orientation", ct.c_int32), ("bins", ct.c_int32)]
+
+
 class ft_frame_job(ct.Structure):
     _fields_ = [("kind", ct.c_int32), ("n_views", ct.c_int32),
                 ("left", ft_keypoints), ("right", ft_keypoints), ("scales", ft_scales),
                 ("pyr_left", ft_pyramid), ("pyr_right", ft_pyramid),
                 ("pinhole", ft_pinhole_stereo), ("pinhole_params", ft_pinhole_params),
                 ("pinhole_out", ft_pinhole_out), ("use_u_right", ct.c_int32),
+                ("build_pyramids", ct.c_int32), ("image_left", ft_image), ("image_right", ft_image),
                 ("fisheye", ft_fisheye_stereo), ("fisheye_params", ft_fisheye_params),
                 ("fisheye_out", ft_fisheye_out), ("map", ft_map_points),
                 ("cam", ft_search_camera * 2), ("grid", ft_grid * 2), ("preassigned", P * 2),
@@ -152,6 +166,12 @@ EXPORTS = {
                                        ct.POINTER(ft_keypoints), P, P, ct.POINTER(ft_grid),
                                        ct.POINTER(ft_scales), ct.POINTER(ft_search_params),
                                        ct.POINTER(ft_search_out)],
+    "ft_pyramid_layout": [ct.c_int32, ct.c_int32, ct.POINTER(ft_scales), ct.POINTER(ft_pyramid),
+                          ct.POINTER(ct.c_int64)],
+    "ft_build_pyramid": [P, P, ct.POINTER(ft_image), ct.POINTER(ft_scales), ct.POINTER(ft_pyramid)],
+    "ft_search_last_frame": [P, P, ct.POINTER(ft_last_points), ct.POINTER(ft_search_camera),
+                             ct.POINTER(ft_keypoints), P, P, P, ct.POINTER(ft_grid), ct.POINTER(ft_scales),
+                             ct.POINTER(ft_last_params), ct.POINTER(ft_search_out)],
     "ft_batch_submit": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.POINTER(ct.c_uint64)],
     "ft_batch_poll": [P, ct.c_uint64, ct.POINTER(ct.c_int32)],
     "ft_batch_wait": [P, ct.c_uint64],
@@ -226,6 +246,18 @@ def ft_search_local_points_noalloc(map_points, cam, kps, u_right, preassigned, g
     return st
 
 
+def pyramid_layout(width: int, height: int, scales) -> tuple:
+    """(ft_pyramid with offsets and sizes, total bytes) of a width x height
+    image's pyramid, from the library."""
+    lib = load()
+    pyr = ft_pyramid()
+    nb = ct.c_int64()
+    st = lib.ft_pyramid_layout(width, height, ct.byref(scales), ct.byref(pyr), ct.byref(nb))
+    if st != FT_OK:
+        raise FtError(st, f"ft_pyramid_layout({width}, {height})")
+    return pyr, nb.value
+
+
 def _stream(stream) -> P:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -265,7 +297,7 @@ class Context:
         self._check(self.lib.ft_context_workspace_bytes(self.h, ct.byref(v)), "workspace_bytes")
         return v.value
 
-    PHASES = ("setup", "stereo_best", "pinhole_refine", "fisheye_triangulate", "stereo_resolve",
+    PHASES = ("pyramid", "setup", "stereo_best", "pinhole_refine", "fisheye_triangulate", "stereo_resolve",
               "search", "search_resolve")
 
     def ft_context_enable_timing(self, enable: bool = True):
@@ -302,6 +334,21 @@ class Context:
                                              ct.byref(params), ct.byref(out))
         if check:
             self._check(st, "ft_search_local_points")
+        return st
+
+    def ft_build_pyramid(self, image, scales, pyr, stream=None, check=True):
+        st = self.lib.ft_build_pyramid(self.h, _stream(stream), ct.byref(image), ct.byref(scales), ct.byref(pyr))
+        if check:
+            self._check(st, "ft_build_pyramid")
+        return st
+
+    def ft_search_last_frame(self, last, cam, kps, kp_angle, u_right, preassigned, grid, scales, params, out,
+                             stream=None, check=True):
+        st = self.lib.ft_search_last_frame(self.h, _stream(stream), ct.byref(last), ct.byref(cam), ct.byref(kps),
+                                           P(kp_angle or None), P(u_right or None), P(preassigned or None),
+                                           ct.byref(grid), ct.byref(scales), ct.byref(params), ct.byref(out))
+        if check:
+            self._check(st, "ft_search_last_frame")
         return st
 
     def ft_batch_submit(self, jobs, stream=None) -> int:
@@ -442,19 +489,36 @@ def search_params_struct(sp) -> ft_search_params:
 class DeviceFrame:
     """One synthetic frame resident in device memory, with output buffers."""
 
-    def __init__(self, frame: dict, device="cuda"):
+    def __init__(self, frame: dict, device="cuda", build_pyramids: bool = False):
+        """build_pyramids (pinhole): upload only level 0 of each image and let
+        the batch job build both pyramids on the device before stereo (the
+        pyramid buffers start filled with 0xA5)."""
         self.frame = frame
         self.kind = frame["kind"]
         self.device = device
         self.left = DeviceKeypoints(frame["left"], device)
         self.right = DeviceKeypoints(frame["right"], device) if "right" in frame else None
         self.scales = _scales(frame["scales"])
+        self.build_pyramids = bool(build_pyramids) and self.kind == "pinhole"
         nL = self.left.n
         i32 = dict(dtype=torch.int32, device=device)
         f32 = dict(dtype=torch.float32, device=device)
+        if self.kind == "pinhole" and self.build_pyramids:
+            self.images = {}
+            for side in ("left", "right"):
+                pyr = frame["pyr_" + side]
+                w, h = int(pyr["width"][0]), int(pyr["height"][0])
+                img_t = _dev(pyr["data"][:w * h], np.uint8, device)
+                lay, nbytes = pyramid_layout(w, h, self.scales)
+                out_t = torch.full((nbytes,), 0xA5, dtype=torch.uint8, device=device)
+                lay.data = _ptr(out_t)
+                self.images[side] = (img_t, ft_image(_ptr(img_t), w, h, w))
+                setattr(self, "pyr_%s_t" % side, out_t)
+                setattr(self, "pyr_" + side, lay)
         if self.kind == "pinhole":
-            self.pyr_left_t, self.pyr_left = _pyramid(frame["pyr_left"], device)
-            self.pyr_right_t, self.pyr_right = _pyramid(frame["pyr_right"], device)
+            if not self.build_pyramids:
+                self.pyr_left_t, self.pyr_left = _pyramid(frame["pyr_left"], device)
+                self.pyr_right_t, self.pyr_right = _pyramid(frame["pyr_right"], device)
             c, sp = frame["stereo_cam"], frame["stereo_params"]
             self.stereo_cam = ft_pinhole_stereo(float(c["fx"]), float(c["bf"]), float(c["b"]), int(c["rows"]))
             self.stereo_params = ft_pinhole_params(sp["th_orb"], sp["half_win"], sp["half_range"],
@@ -539,6 +603,9 @@ class DeviceFrame:
         j.scales = self.scales
         if kind == "pinhole":
             j.pyr_left, j.pyr_right = self.pyr_left, self.pyr_right
+            if self.build_pyramids:
+                j.build_pyramids = 1
+                j.image_left, j.image_right = self.images["left"][1], self.images["right"][1]
             j.pinhole, j.pinhole_params, j.pinhole_out = self.stereo_cam, self.stereo_params, self.stereo_out
             j.use_u_right = int(self.views[0]["use_u_right"]) if self.views else 0
         elif kind == "fisheye":
@@ -551,6 +618,10 @@ class DeviceFrame:
             j.search_out[i] = v["out"]
         j.search_params = self.search_params
         return j
+
+    def pyramids(self) -> dict:
+        """The pinhole pyramid buffers as host arrays (synchronises)."""
+        return {side: getattr(self, "pyr_%s_t" % side).cpu().numpy() for side in ("left", "right")}
 
     def results(self) -> dict:
         """Copy every output to host numpy arrays (synchronises)."""
@@ -565,3 +636,40 @@ class DeviceFrame:
             s["n_matches"] = int(s["n_matches"][0])
             res["search"].append(s)
         return res
+
+
+class DeviceLastFrame:
+    """A last-frame search case (synth.last_frame_case) resident in device
+    memory, with output buffers."""
+
+    def __init__(self, case: dict, device="cuda"):
+        last, kps, prm = case["last"], case["kps"], case["params"]
+        self.n = len(last["octave"])
+        self.t = {"pos": _dev(last["pos"], np.float32, device), "desc": _dev(last["desc"], np.uint8, device),
+                  "octave": _dev(last["octave"], np.uint8, device), "angle": _dev(last["angle"], np.float32, device),
+                  "kp_angle": _dev(kps["angle"], np.float32, device)}
+        self.kps = DeviceKeypoints(kps, device)
+        self.u_right = None if case.get("u_right") is None else _dev(case["u_right"], np.float32, device)
+        self.pre = None if case.get("preassigned") is None else _dev(case["preassigned"], np.uint8, device)
+        t = self.t
+        self.last = ft_last_points(self.n, _ptr(t["pos"]), _ptr(t["desc"]), _ptr(t["octave"]), _ptr(t["angle"]))
+        self.cam = search_camera_struct(case["cam"])
+        self.grid = ft_grid(*case["grid"])
+        self.scales = _scales(case["scales"])
+        self.params = ft_last_params(float(prm["th"]), int(prm["th_high"]), int(prm["direction"]),
+                                     int(prm["check_orientation"]), int(prm["bins"]))
+        i32 = dict(dtype=torch.int32, device=device)
+        self.o = {"mp_match": torch.full((self.n,), -7, **i32), "mp_dist": torch.full((self.n,), -7, **i32),
+                  "kp_match": torch.full((self.kps.n,), -7, **i32), "n_matches": torch.full((1,), -7, **i32)}
+        o = self.o
+        self.out = ft_search_out(_ptr(o["mp_match"]), _ptr(o["mp_dist"]), _ptr(o["kp_match"]), _ptr(o["n_matches"]))
+
+    def run(self, ctx: Context, stream=None, check=True):
+        return ctx.ft_search_last_frame(self.last, self.cam, self.kps.struct(), _ptr(self.t["kp_angle"]),
+                                        _ptr(self.u_right), _ptr(self.pre), self.grid, self.scales, self.params,
+                                        self.out, stream=stream, check=check)
+
+    def results(self) -> dict:
+        r = {k: v.cpu().numpy() for k, v in self.o.items()}
+        return {"last_match": r["mp_match"], "last_dist": r["mp_dist"], "kp_match": r["kp_match"],
+                "n_matches": int(r["n_matches"][0])}

@@ -27,7 +27,7 @@ struct Slot {  // workspace of one frame
     MatchRec *mrec;
     uint32_t *claimR;
     struct {
-        int32_t *cell_off, *mp_k, *mp_h;
+        int32_t *cell_off, *mp_k, *mp_h, *hist;
         CellRec *crec;
         uint32_t *claim;
     } view[2];
@@ -146,6 +146,7 @@ void carve_view(Slot &s, int v, char *base, Bump &b, size_t kp, size_t mp)
     s.view[v].mp_k = b.take<int32_t>(base, mp);
     s.view[v].mp_h = b.take<int32_t>(base, mp);
     s.view[v].claim = b.take<uint32_t>(base, kp);
+    s.view[v].hist = b.take<int32_t>(base, kRotBinsMax);
 }
 
 void carve_slot(Slot &s, char *base, Bump &b, const ft_limits &L)
@@ -245,6 +246,63 @@ void bind_stereo_ws(DevJob &J, const Slot &s)
     J.depth = s.depth;
     J.xyz = s.xyz;
     J.claimR = s.claimR;
+}
+
+// Level sizes and packed offsets of the pyramid of a width x height image.
+bool pyramid_layout(int W, int H, const ft_scales *sc, ft_pyramid *pyr, int64_t *bytes)
+{
+    int64_t acc = 0;
+    for (int l = 0; l < kLevels; ++l) {
+        const float fw = (float)W * sc->inv_sf[l];
+        const float fh = (float)H * sc->inv_sf[l];
+        const int w = (int)std::floor(fw + 0.5f), h = (int)std::floor(fh + 0.5f);
+        if (w < 1 || h < 1) return false;
+        pyr->offset[l] = acc;
+        pyr->width[l] = w;
+        pyr->height[l] = h;
+        acc += (int64_t)w * h;
+    }
+    *bytes = acc;
+    return true;
+}
+
+// A level-0 image and the pyramid it is built into: sizes in range and the
+// pyramid's levels exactly the packed layout.
+ft_status check_pyramid_build(ft_context *ctx, const ft_image *img, const ft_scales *sc, const ft_pyramid *pyr,
+                              const char *what)
+{
+    if (!img || !pyr) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: null image or pyramid", what);
+    if (!img->data || !pyr->data) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: null image or pyramid data", what);
+    if (img->width < 2 || img->height < 2 || img->pitch < img->width)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: image %dx%d pitch %d", what, img->width, img->height,
+                    img->pitch);
+    if (img->width > kMaxPyrW || img->height > kMaxRows)
+        return fail(ctx, FT_ERR_CAPACITY, "%s: image %dx%d exceeds %dx%d", what, img->width, img->height, kMaxPyrW,
+                    kMaxRows);
+    ft_pyramid want{};
+    int64_t bytes = 0;
+    if (!pyramid_layout(img->width, img->height, sc, &want, &bytes))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: a pyramid level of the image would be empty", what);
+    for (int l = 0; l < kLevels; ++l)
+        if (pyr->offset[l] != want.offset[l] || pyr->width[l] != want.width[l] || pyr->height[l] != want.height[l])
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: pyramid level %d is not the packed layout", what, l);
+    return FT_OK;
+}
+
+void bind_pyramid_build(DevJob &J, const ft_image *L, const ft_image *R, const ft_pyramid *pl, const ft_pyramid *pr)
+{
+    J.imgL = L->data;
+    J.imgR = R ? R->data : nullptr;
+    J.pyr_outL = const_cast<uint8_t *>(pl->data);
+    J.pyr_outR = pr ? const_cast<uint8_t *>(pr->data) : nullptr;
+    J.img_w = L->width;
+    J.img_h = L->height;
+    J.img_pitch = L->pitch;
+    for (int l = 0; l < kLevels; ++l) {
+        J.lv_off[l] = pl->offset[l];
+        J.lv_w[l] = pl->width[l];
+        J.lv_h[l] = pl->height[l];
+    }
 }
 
 ft_status build_pinhole(ft_context *ctx, DevJob &J, const ft_keypoints *L, const ft_keypoints *R,
@@ -478,6 +536,7 @@ ft_status build_view(ft_context *ctx, DevJob &J, int v, int side, const ft_searc
     V.mp_k = slot.view[v].mp_k;
     V.mp_h = slot.view[v].mp_h;
     V.claim = slot.view[v].claim;
+    V.hist = slot.view[v].hist;
     J.flags |= (JOB_SEARCH0 << v);
     J.n_views = std::max(J.n_views, v + 1);
     if (side) J.R = dev_kps(kps);
@@ -573,6 +632,15 @@ ft_status build_batch(ft_context *ctx, Lane &lane, const ft_frame_job *jobs, int
             if ((st = build_pinhole(ctx, J, &jb.left, &jb.right, &jb.pyr_left, &jb.pyr_right, &jb.scales,
                                     &jb.pinhole, &jb.pinhole_params, &jb.pinhole_out, slot)))
                 return st;
+            if (jb.build_pyramids) {
+                if ((st = check_pyramid_build(ctx, &jb.image_left, &jb.scales, &jb.pyr_left, "left image")) ||
+                    (st = check_pyramid_build(ctx, &jb.image_right, &jb.scales, &jb.pyr_right, "right image")))
+                    return st;
+                if (jb.image_left.width != jb.image_right.width || jb.image_left.height != jb.image_right.height ||
+                    jb.image_left.pitch != jb.image_right.pitch)
+                    return fail(ctx, FT_ERR_INVALID_ARGUMENT, "batch: job %d stereo images differ in size or pitch", f);
+                bind_pyramid_build(J, &jb.image_left, &jb.image_right, &jb.pyr_left, &jb.pyr_right);
+            }
         } else if (jb.kind == FT_JOB_FISHEYE) {
             if ((st = build_fisheye(ctx, J, &jb.left, &jb.right, &jb.scales, &jb.fisheye,
                                     &jb.fisheye_params, &jb.fisheye_out, slot)))
@@ -1134,6 +1202,84 @@ ft_status ft_search_local_points_noalloc(void *stream, const ft_map_points *map,
     fill_search_common(J, map, params);
     if ((st = build_view(&tmp, J, 0, 0, cam, kps, u_right, preassigned, grid, out, slot))) return done(st);
     return done(launch_one(&tmp, J, (hipStream_t)stream, false, true));
+}
+
+ft_status ft_pyramid_layout(int32_t width, int32_t height, const ft_scales *scales, ft_pyramid *pyr,
+                            int64_t *bytes)
+{
+    if (!scales || !pyr || !bytes || scales->n_levels != kLevels) return FT_ERR_INVALID_ARGUMENT;
+    if (width < 1 || height < 1 || width > 65536 || height > 65536) return FT_ERR_INVALID_ARGUMENT;
+    ft_pyramid p{};
+    int64_t b = 0;
+    if (!pyramid_layout(width, height, scales, &p, &b)) return FT_ERR_INVALID_ARGUMENT;
+    for (int l = 0; l < kLevels; ++l) {
+        pyr->offset[l] = p.offset[l];
+        pyr->width[l] = p.width[l];
+        pyr->height[l] = p.height[l];
+    }
+    *bytes = b;
+    return FT_OK;
+}
+
+ft_status ft_build_pyramid(ft_context *ctx, void *stream, const ft_image *image, const ft_scales *scales,
+                           const ft_pyramid *pyr)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if ((st = check_scales(ctx, scales)) || (st = check_pyramid_build(ctx, image, scales, pyr, "pyramid")))
+        return st;
+    DevJob J{};
+    fill_scales(J, scales);
+    bind_pyramid_build(J, image, nullptr, pyr, nullptr);
+    return launch_one(ctx, J, (hipStream_t)stream, true, false);
+}
+
+ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_points *last,
+                               const ft_search_camera *cam, const ft_keypoints *kps, const float *kp_angle,
+                               const float *u_right, const uint8_t *preassigned, const ft_grid *grid,
+                               const ft_scales *scales, const ft_last_params *params,
+                               const ft_search_out *out)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if ((st = check_scales(ctx, scales))) return st;
+    if (!last || !params || !kps) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "last frame: null argument");
+    if (last->n < 0) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "last frame: n < 0");
+    if (last->n > ctx->lim.max_map_points)
+        return fail(ctx, FT_ERR_CAPACITY, "last frame: %d points exceed max_map_points %d", last->n,
+                    ctx->lim.max_map_points);
+    const bool rot = params->check_orientation != 0;
+    if (!(params->th > 0.0f) || params->th_high < 0 || params->th_high > 256 || params->direction < -1 ||
+        params->direction > 1 || params->check_orientation < 0 || params->check_orientation > 1 ||
+        params->bins < 1 || params->bins > kRotBinsMax)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "last frame: bad parameters");
+    if (last->n > 0) {
+        if (!last->pos || !last->desc || !last->octave || (rot && !last->angle))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "last frame: null point array");
+        if (!aligned(last->pos, 4) || !aligned(last->desc, 16) || (last->angle && !aligned(last->angle, 4)))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "last frame: misaligned point array");
+    }
+    if (rot && kps->n > 0 && (!kp_angle || !aligned(kp_angle, 4)))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "last frame: null or misaligned keypoint angles");
+    DevJob J{};
+    fill_scales(J, scales);
+    J.nM = last->n;
+    J.pos = last->pos;
+    J.mdesc = last->desc;
+    J.l_oct = last->octave;
+    J.l_ang = last->angle;
+    J.k_ang = kp_angle;
+    J.th = params->th;
+    J.th_high = params->th_high;
+    J.direction = params->direction;
+    J.check_rot = rot ? 1 : 0;
+    J.rot_bins = params->bins;
+    // the window's levels are not centred on a predicted level: one-bin index
+    J.lv_lo = kLevels;
+    J.lv_hi = kLevels;
+    if ((st = build_view(ctx, J, 0, 0, cam, kps, u_right, preassigned, grid, out, ctx->direct))) return st;
+    HIP_TRY(ctx, launch_last_frame(J, 4, (hipStream_t)stream));
+    return FT_OK;
 }
 
 ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *jobs, int32_t n,

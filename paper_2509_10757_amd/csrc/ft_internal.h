@@ -22,9 +22,13 @@ constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
 constexpr int kRefineQPerWG = 16;     // ... 11x11 window, +-5 shifts: four matches per wave
 constexpr int kRefineQLds = 800;      // bytes of LDS per match (11 x 12 + 11 x 24 16-bit values)
+constexpr int kPyrRows = 8;           // image pyramid: level-0 rows per workgroup
+constexpr int kMaxPyrW = 1536;        // widest level-0 image the pyramid build stages in LDS
+constexpr int kRotBinsMax = 64;       // rotation histogram bins of the last-frame search
 
 enum Phase : int {
-    PH_SETUP = 0,    // row sort / overlap lists / cell sort
+    PH_PYRAMID = 0,  // image pyramids of the stereo images (when the job builds them)
+    PH_SETUP,        // row sort / overlap lists / cell sort
     PH_STEREO_A,     // pinhole best match | fisheye all-pairs top-2
     PH_REFINE,       // pinhole SAD refinement
     PH_TRI,          // fisheye ratio + triangulation check
@@ -102,6 +106,7 @@ struct DevView {
     FT_G CellRec *crec;              // records sorted by (level bin, cell)
     FT_G int32_t *mp_k, *mp_h;
     FT_G uint32_t *claim;
+    FT_G int32_t *hist;              // rotation histogram of the last-frame search [kRotBinsMax]
 };
 
 struct DevJob {
@@ -141,6 +146,14 @@ struct DevJob {
     float th, cos_lim, cos_narrow, r_narrow, r_wide, dist_lo, dist_hi;
     int32_t lv_lo, lv_hi, th_high, s_ratio_num, s_ratio_den, same_level_only;
     DevView view[2];
+    // image pyramids built on the device (pinhole stereo images)
+    const FT_G uint8_t *imgL, *imgR;  // level-0 images, row pitch img_pitch (null: no build)
+    FT_G uint8_t *pyr_outL, *pyr_outR;
+    int32_t img_w, img_h, img_pitch;
+    // last-frame search by projection (view 0; pos / mdesc / nM hold the points)
+    const FT_G uint8_t *l_oct;        // octave of the last-frame keypoint of each point
+    const FT_G float *l_ang, *k_ang;  // orientations (degrees): last-frame keypoints, current keypoints
+    int32_t direction, check_rot, rot_bins;
 };
 
 // Launch shapes of one submission (the autotuner chooses them).  Defaults:
@@ -183,6 +196,9 @@ static_assert(kPhases == PH_COUNT, "one timing slot per phase");
 // `totals` holds the number of workgroups of each phase.
 hipError_t launch_pipeline(const DevJob *table, const TileMap &map, const int32_t totals[PH_COUNT],
                            const DevJob &one, const Shapes &shapes, hipStream_t stream, hipEvent_t *ev);
+// Last-frame search of one job's view 0: setup, search (`lanes` per point),
+// claim resolution with the rotation histogram, rotation check and outputs.
+hipError_t launch_last_frame(const DevJob &J, int lanes, hipStream_t stream);
 // Batch kernel of every phase for these shapes (JobTable argument), and its
 // workgroup size: the nodes of a lane's batch graph.
 void batch_kernels(const Shapes &shapes, void *fn[PH_COUNT], int block[PH_COUNT]);

@@ -183,6 +183,178 @@ __device__ __forceinline__ int cell_coord(float v, float lo, float inv, int n)
     return (int)f;
 }
 
+// ------------------------------------------------------ image pyramid
+// Level l of a pyramid is a bilinear resample of level 0 (Section IV-B: the
+// pyramid is built on the device and kept for stereo; every level is computed
+// from the image at once, so one launch builds them all).  Output index x of a
+// level n_out wide samples s = ((2x + 1) * n_in - n_out) / (2 * n_out) of the
+// level-0 axis n_in long: source pixel floor(s) and weight floor(256 * frac(s)),
+// clamped to the first and last pixel.  Returns pixel | weight << 16.
+//
+// floor(num / den) by a reciprocal estimate and one correction step each way
+// (num < 2^28 and den < 2^15, so the estimate is off by at most one).
+__device__ __forceinline__ int div_floor_small(int num, int den, int &rem)
+{
+    int q = (int)floorf((float)num * __builtin_amdgcn_rcpf((float)den));
+    int r = num - q * den;
+    if (r < 0) {
+        --q;
+        r += den;
+    } else if (r >= den) {
+        ++q;
+        r -= den;
+    }
+    rem = r;
+    return q;
+}
+
+__device__ __forceinline__ uint32_t pyr_tap(int x, int n_in, int n_out)
+{
+    const int num = (2 * x + 1) * n_in - n_out;
+    if (num <= 0) return 0u;
+    const int den = 2 * n_out;
+    int r;
+    int q = div_floor_small(num, den, r);
+    int r2;
+    int wq = div_floor_small(256 * r, den, r2);
+    if (q >= n_in - 1) {
+        q = n_in - 1;
+        wq = 0;
+    }
+    return (uint32_t)q | ((uint32_t)wq << 16);
+}
+
+// LDS of one pyramid tile: kPyrRows + 1 staged level-0 rows, then the column
+// taps of levels 1..7, then per-level row ranges.
+constexpr int kPyrStage = (kPyrRows + 1) * kMaxPyrW;
+constexpr int kPyrTab = kPyrStage;                          // uint32 [kPyrTabN]
+constexpr int kPyrTabN = 4 * kMaxPyrW;                      // sum of w_l over l >= 1 is < 3.6 W
+constexpr int kPyrMeta = kPyrTab + 4 * kPyrTabN;            // int [3 * kLevels]
+constexpr int kPyrLds = kPyrMeta + 3 * kLevels * 4;
+
+// Output rows of level l whose top tap row lies in [Y0, Y1): the level's row
+// tap is monotone in the row, so the range is found by bisection.
+__device__ __forceinline__ int pyr_first_row(int Y, int H, int h)
+{
+    int lo = 0, hi = h;   // first y with tap(y) >= Y
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)(pyr_tap(mid, H, h) & 0xFFFFu) >= Y) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// One tile: image `side` (0 left, 1 right) of the frame, level-0 rows
+// [Y0, Y0 + kPyrRows).  Stages those rows and the next in LDS, copies them to
+// level 0 and writes every output row of levels 1..7 whose top tap row is
+// among them: each source row is read from memory once and each output byte
+// written once.  Waves take whole output rows; lanes stride the columns.
+__device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned char *smem)
+{
+    const int W = J.img_w, H = J.img_h, pitch = J.img_pitch;
+    const int per = div_up(H, kPyrRows);
+    const int side = tile / per;
+    const FT_G uint8_t *src = side ? J.imgR : J.imgL;
+    FT_G uint8_t *dst = side ? J.pyr_outR : J.pyr_outL;
+    if (!src) return;
+    const int Y0 = (tile - side * per) * kPyrRows;
+    const int Y1 = min(Y0 + kPyrRows, H);
+    const int ys = min(Y1 + 1, H);           // staged rows [Y0, ys)
+    const int stride = (W + 3) & ~3;
+    uint8_t *stage = smem;
+    uint32_t *tab = reinterpret_cast<uint32_t *>(smem + kPyrTab);
+    int *meta = reinterpret_cast<int *>(smem + kPyrMeta);   // row lo | row hi | table offset
+    const int tid = threadIdx.x;
+    if (tid < kLevels) {
+        const int l = tid;
+        int toff = 0;
+        for (int k = 1; k < l; ++k) toff += J.lv_w[k];
+        meta[3 * l + 2] = toff;
+        if (l >= 1) {
+            meta[3 * l] = pyr_first_row(Y0, H, J.lv_h[l]);
+            meta[3 * l + 1] = Y1 >= H ? J.lv_h[l] : pyr_first_row(Y1, H, J.lv_h[l]);
+        }
+    }
+    // stage the level-0 rows: 4-byte loads when rows and base are aligned
+    const bool al4 = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)pitch | (uintptr_t)W) & 3u) == 0;
+    if (al4) {
+        const int wq = W >> 2, n = (ys - Y0) * wq;
+        for (int e = tid; e < n; e += kWG) {
+            const int r = e / wq, c = e - r * wq;
+            const uint32_t v = *reinterpret_cast<const FT_G uint32_t *>(src + (size_t)(Y0 + r) * pitch + 4 * c);
+            *reinterpret_cast<uint32_t *>(stage + r * stride + 4 * c) = v;
+        }
+    } else {
+        const int n = (ys - Y0) * W;
+        for (int e = tid; e < n; e += kWG) {
+            const int r = e / W, c = e - r * W;
+            stage[r * stride + c] = src[(size_t)(Y0 + r) * pitch + c];
+        }
+    }
+    // column taps of levels 1..7
+    int ntab = 0;
+    for (int l = 1; l < kLevels; ++l) ntab += J.lv_w[l];
+    for (int e = tid; e < ntab; e += kWG) {
+        int l = 1, base = 0;
+        while (e >= base + J.lv_w[l]) {
+            base += J.lv_w[l];
+            ++l;
+        }
+        tab[e] = pyr_tap(e - base, W, J.lv_w[l]);
+    }
+    __syncthreads();
+    // level 0: the staged rows [Y0, Y1)
+    {
+        const int n = (Y1 - Y0) * W;
+        FT_G uint8_t *d0 = dst + (size_t)Y0 * W;
+        if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
+            const int wq = W >> 2;
+            for (int e = tid; e < (n >> 2); e += kWG) {
+                const int r = e / wq, c = e - r * wq;
+                *reinterpret_cast<FT_G uint32_t *>(d0 + 4 * e) =
+                    *reinterpret_cast<const uint32_t *>(stage + r * stride + 4 * c);
+            }
+        } else {
+            for (int e = tid; e < n; e += kWG) {
+                const int r = e / W, c = e - r * W;
+                d0[e] = stage[r * stride + c];
+            }
+        }
+    }
+    // levels 1..7: wave w takes output rows w, w + 4, ... of the tile's list
+    const int wave = tid >> 6, lane = tid & 63;
+    int row_base = 0;
+    for (int l = 1; l < kLevels; ++l) {
+        const int ylo = meta[3 * l], yhi = meta[3 * l + 1];
+        const int wl = J.lv_w[l], hl = J.lv_h[l];
+        const uint32_t *ct = tab + meta[3 * l + 2];
+        FT_G uint8_t *dl = dst + J.lv_off[l];
+        const int nrows = yhi - ylo;
+        // rows of this level taken by this wave, continuing the round robin
+        int k0 = (wave - row_base) & 3;
+        for (int k = k0; k < nrows; k += 4) {
+            const int y = ylo + k;
+            const uint32_t rt = pyr_tap(y, H, hl);
+            const int y0 = (int)(rt & 0xFFFFu), b = (int)(rt >> 16);
+            const uint8_t *r0 = stage + (y0 - Y0) * stride;
+            const uint8_t *r1 = stage + (min(y0 + 1, H - 1) - Y0) * stride;
+            FT_G uint8_t *drow = dl + (size_t)y * wl;
+            for (int x = lane; x < wl; x += 64) {
+                const uint32_t c = ct[x];
+                const int x0 = (int)(c & 0xFFFFu), a = (int)(c >> 16);
+                const int x1 = min(x0 + 1, W - 1);
+                const int p00 = r0[x0], p01 = r0[x1], p10 = r1[x0], p11 = r1[x1];
+                const int top = (256 - a) * p00 + a * p01;
+                const int bot = (256 - a) * p10 + a * p11;
+                const int v = (256 - b) * top + b * bot;
+                drow[x] = (uint8_t)((v + 32768) >> 16);
+            }
+        }
+        row_base += nrows;
+    }
+}
+
 // ------------------------------------------------ setup: rows (pinhole)
 // Row bin of a right keypoint (clamped; non-finite rows go to bin 0).
 __device__ __forceinline__ int row_bin(float y, int rows)
@@ -332,6 +504,7 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
     const int nb = V.n_pb * cells;
     for (int c = tid; c < nb; c += NT) cnt[c] = 0;
     for (int k = tid; k < K.n; k += NT) V.claim[k] = 0xFFFFFFFFu;
+    for (int b = tid; b < kRotBinsMax; b += NT) V.hist[b] = 0;
     if (tid == 0) *V.n_matches = 0;
     __syncthreads();
     for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
@@ -1622,6 +1795,234 @@ __device__ __forceinline__ void ph_search_final(const DevJob &J, const DevView &
     if ((threadIdx.x & 63) == 0 && mk) atomicAdd(V.n_matches, (int)__popcll(mk));
 }
 
+// --------------------------------- last-frame search by projection
+// Initial Pose Estimation projects the last frame's matched map points into
+// the current frame and searches its keypoints (Section II-C); the same
+// search by projection as the local-map search (Section IV-E), with the
+// window taken from the last-frame keypoint (radius th * sf[octave], levels
+// by the direction of motion) instead of the predicted level, no ratio test,
+// and a rotation-consistency check over the frame's matches.
+//
+// Camera projection of a world point into view V (pinhole binary32, KB
+// binary64 rounded to binary32); false when the point is behind the camera
+// or outside the image bounds.
+__device__ __forceinline__ bool project_point(const DevView &V, float X, float Y, float Z, float &u, float &v,
+                                              float &zc)
+{
+    const float xc = ((V.R[0] * X + V.R[1] * Y) + V.R[2] * Z) + V.t[0];
+    const float yc = ((V.R[3] * X + V.R[4] * Y) + V.R[5] * Z) + V.t[1];
+    zc = ((V.R[6] * X + V.R[7] * Y) + V.R[8] * Z) + V.t[2];
+    u = 0.0f;
+    v = 0.0f;
+    if (!(zc > 0.0f)) return false;
+    if (V.model == FT_CAMERA_PINHOLE) {
+        u = ((V.fx * xc) / zc) + V.cx;
+        v = ((V.fy * yc) / zc) + V.cy;
+    } else {
+        const float kb[8] = {V.fx, V.fy, V.cx, V.cy, V.k[0], V.k[1], V.k[2], V.k[3]};
+        const double Pc[3] = {(double)xc, (double)yc, (double)zc};
+        double uv[2];
+        kb_project(kb, Pc, uv);
+        u = (float)uv[0];
+        v = (float)uv[1];
+    }
+    return u >= V.min_x && u <= V.max_x && v >= V.min_y && v <= V.max_y;
+}
+
+struct LastQuery {
+    bool in;            // projected inside the image
+    bool gate;          // stereo right-coordinate gate applies
+    float u, v, r, uR;
+    int lmin, lmax;     // keypoint levels searched
+    int cx0, cx1, cy0, cy1;
+    Desc d;
+};
+
+__device__ __forceinline__ LastQuery make_last_query(const DevJob &J, const DevView &V, int i)
+{
+    LastQuery q;
+    const float X = J.pos[3 * i], Y = J.pos[3 * i + 1], Z = J.pos[3 * i + 2];
+    const int ol = lvl(J.l_oct[i]);
+    q.d = load_desc(J.mdesc, i);
+    float zc;
+    q.in = project_point(V, X, Y, Z, q.u, q.v, zc);
+    if (!q.in) return q;
+    q.r = J.th * J.sf[ol];
+    if (J.direction > 0) {
+        q.lmin = ol;
+        q.lmax = kLevels - 1;
+    } else if (J.direction < 0) {
+        q.lmin = 0;
+        q.lmax = ol;
+    } else {
+        q.lmin = ol - 1;
+        q.lmax = ol + 1;
+    }
+    q.gate = V.u_right != nullptr;
+    q.uR = q.gate ? q.u - V.bf * (1.0f / zc) : 0.0f;
+    // cells of u -+ (r + 0.01) bracket every candidate (as in the local search)
+    const float Rc = q.r + 0.01f;
+    q.cx0 = cell_coord(q.u - Rc, V.min_x, V.inv_cw, V.cols);
+    q.cx1 = cell_coord(q.u + Rc, V.min_x, V.inv_cw, V.cols);
+    q.cy0 = cell_coord(q.v - Rc, V.min_y, V.inv_ch, V.rows);
+    q.cy1 = cell_coord(q.v + Rc, V.min_y, V.inv_ch, V.rows);
+    return q;
+}
+
+// Best candidate key (distance << 40 | keypoint << 8 | level) of one point
+// over the window's cells of the one-bin index; lane `sub` of G takes every
+// G-th record of each window row.
+template <int G>
+__device__ __forceinline__ uint64_t scan_last(const DevView &V, const LastQuery &q, int sub)
+{
+    uint64_t best = ~0ull;
+    const FT_G int32_t *off = V.cell_off;
+    for (int cy = q.cy0; cy <= q.cy1; ++cy) {
+        const int c0 = off[cy * V.cols + q.cx0], c1 = off[cy * V.cols + q.cx1 + 1];
+        for (int p0 = c0 + sub; p0 < c1; p0 += kSearchUnroll * G) {
+            CellRec rec[kSearchUnroll];
+            bool cand[kSearchUnroll];
+            Desc d[kSearchUnroll];
+            float ur[kSearchUnroll];
+            _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e) rec[e] = V.crec[min(p0 + e * G, c1 - 1)];
+            _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
+            {
+                const int ok = (int)(rec[e].meta & 0xFFu);
+                cand[e] = p0 + e * G < c1 && ok >= q.lmin && ok <= q.lmax && fabsf(rec[e].x - q.u) < q.r &&
+                          fabsf(rec[e].y - q.v) < q.r && !(rec[e].meta & 0x100u);
+                ur[e] = 0.0f;
+                if (cand[e]) {
+                    d[e] = load_desc(V.kdesc, (int)(rec[e].meta >> 16));
+                    if (q.gate) ur[e] = V.u_right[rec[e].meta >> 16];
+                }
+            }
+            _Pragma("unroll") for (int e = 0; e < kSearchUnroll; ++e)
+            {
+                const bool rej = q.gate && ur[e] > 0.0f && !(fabsf(q.uR - ur[e]) <= q.r);
+                if (cand[e] && !rej) best = min(best, cand_key(hamming(q.d, d[e]), rec[e].meta));
+            }
+        }
+    }
+    return best;
+}
+
+// G lanes per last-frame point: best candidate, acceptance, claim.
+template <int G>
+__device__ __forceinline__ void ph_last_search(const DevJob &J, const DevView &V, int tile)
+{
+    const int sub = threadIdx.x % G;
+    const int i = tile * (kWG / G) + threadIdx.x / G;
+    uint64_t best = ~0ull;
+    if (i < J.nM) {
+        const LastQuery q = make_last_query(J, V, i);
+        if (q.in) best = scan_last<G>(V, q, sub);
+    }
+    for (int o = 1; o < G; o <<= 1) {
+        const uint64_t other = shfl_xor64(best, o);
+        best = other < best ? other : best;
+    }
+    if (sub != 0 || i >= J.nM) return;
+    int k = -1, h = -1;
+    if (best != ~0ull && (int)(best >> 40) <= J.th_high) {
+        h = (int)(best >> 40);
+        k = (int)((best >> 8) & 0xFFFFu);
+    }
+    V.mp_k[i] = k;
+    V.mp_h[i] = h;
+    if (k >= 0) atomicMin(&V.claim[k], ((uint32_t)h << 23) | (uint32_t)i);
+}
+
+// Rotation bin of a match: last minus current orientation, plus 360 when
+// negative, rounded to one of `bins` equal bins, taken modulo `bins` (the one
+// past the last is bin 0).
+__device__ __forceinline__ int rotation_bin(float a_last, float a_cur, int bins)
+{
+    float rot = a_last - a_cur;
+    if (rot < 0.0f) rot += 360.0f;
+    const float factor = (float)bins / 360.0f;
+    int bin = (int)roundf(rot * factor) % bins;   // the bin past the last is bin 0
+    if (bin < 0) bin += bins;                      // (angles outside [0, 360) stay in range)
+    return bin;
+}
+
+// Thread per point: the claim winners keep their keypoint (mp_k, distance |
+// bin << 16 in mp_h; losers get -1) and count their rotation bin.
+__device__ __forceinline__ void ph_last_resolve(const DevJob &J, const DevView &V, int tile)
+{
+    const int i = tile * kWG + threadIdx.x;
+    if (i >= J.nM) return;
+    const int k = V.mp_k[i];
+    const int h = V.mp_h[i];
+    const bool keep = k >= 0 && V.claim[k] == (((uint32_t)h << 23) | (uint32_t)i);
+    int bin = 0;
+    if (keep && J.check_rot) {
+        bin = rotation_bin(J.l_ang[i], J.k_ang[k], J.rot_bins);
+        atomicAdd(&V.hist[bin], 1);
+    }
+    V.mp_k[i] = keep ? k : -1;
+    V.mp_h[i] = keep ? (h | (bin << 16)) : -1;
+}
+
+// Bins kept by the rotation check (bit b set): the fullest bin and, while
+// holding a tenth of it, the second and third fullest; ties to the lower bin.
+__device__ __forceinline__ uint64_t kept_bins(const DevView &V, int bins)
+{
+    int i1 = -1, i2 = -1, i3 = -1, m1 = 0, m2 = 0, m3 = 0;
+    for (int b = 0; b < bins; ++b) {
+        const int c = V.hist[b];
+        if (c > m1) {
+            m3 = m2;
+            i3 = i2;
+            m2 = m1;
+            i2 = i1;
+            m1 = c;
+            i1 = b;
+        } else if (c > m2) {
+            m3 = m2;
+            i3 = i2;
+            m2 = c;
+            i2 = b;
+        } else if (c > m3) {
+            m3 = c;
+            i3 = b;
+        }
+    }
+    if (10 * m2 < m1) {
+        i2 = -1;
+        i3 = -1;
+    } else if (10 * m3 < m1) {
+        i3 = -1;
+    }
+    uint64_t kept = 0;
+    if (i1 >= 0) kept |= 1ull << i1;
+    if (i2 >= 0) kept |= 1ull << i2;
+    if (i3 >= 0) kept |= 1ull << i3;
+    return kept;
+}
+
+// Thread per point / keypoint: the rotation check and the outputs.
+__device__ __forceinline__ void ph_last_final(const DevJob &J, const DevView &V, int nK, int tile)
+{
+    const uint64_t kept = J.check_rot ? kept_bins(V, J.rot_bins) : ~0ull;
+    auto alive = [&](int i) {
+        return V.mp_k[i] >= 0 && ((kept >> ((V.mp_h[i] >> 16) & 63)) & 1ull);
+    };
+    const int idx = tile * kWG + threadIdx.x;
+    if (idx < J.nM) {
+        const bool a = alive(idx);
+        V.mp_match[idx] = a ? V.mp_k[idx] : -1;
+        V.mp_dist[idx] = a ? (V.mp_h[idx] & 0xFFFF) : -1;
+    }
+    bool has = false;
+    if (idx < nK) {
+        const uint32_t c = V.claim[idx];
+        has = c != 0xFFFFFFFFu && alive((int)(c & 0x7FFFFFu));
+        V.kp_match[idx] = has ? (int)(c & 0x7FFFFFu) : -1;
+    }
+    const unsigned long long mk = __ballot(has);
+    if ((threadIdx.x & 63) == 0 && mk) atomicAdd(V.n_matches, (int)__popcll(mk));
+}
+
 // ------------------------------------------------------- tile bookkeeping
 
 __host__ __device__ inline int search_tiles_per_view(const DevJob &J, int lanes)
@@ -1639,6 +2040,7 @@ __host__ __device__ inline int final_tiles_view(const DevJob &J, int v)
 void job_tiles(const DevJob &J, const Shapes &s, bool do_stereo, bool do_search, int32_t out[PH_COUNT])
 {
     for (int p = 0; p < PH_COUNT; ++p) out[p] = 0;
+    if (do_stereo && J.imgL) out[PH_PYRAMID] = (J.imgR ? 2 : 1) * div_up(J.img_h, kPyrRows);
     const int nL = J.L.n;
     const bool pin = do_stereo && (J.flags & JOB_STEREO_PINHOLE);
     const bool fish = do_stereo && (J.flags & JOB_STEREO_FISHEYE);
@@ -1765,6 +2167,15 @@ static_assert(4 * kDealLdsPerWave <= kTaskLds, "record-dealt search LDS");
 static_assert((256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4 <= kTaskLds, "median LDS");
 
 // ------------------------------------------------------- per-phase kernels
+template <class Src>
+__global__ __launch_bounds__(kWG) void k_pyramid(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[kPyrLds];
+    int job, tile;
+    if (!src.locate(PH_PYRAMID, job, tile)) return;
+    ph_pyramid(src(job), tile, smem);
+}
+
 template <class Src, int NT>
 __global__ __launch_bounds__(NT) void k_setup(Src src)
 {
@@ -1830,12 +2241,71 @@ __global__ __launch_bounds__(kWG) void k_search_final(Src src)
     task_search_final(src(job), tile);
 }
 
+// Last-frame search (one view of one job): search, claim resolution with the
+// rotation histogram, rotation check and outputs.
+template <class Src, int G>
+__global__ __launch_bounds__(kWG) void k_last_search(Src src)
+{
+    int job, tile;
+    if (!src.locate(PH_SEARCH, job, tile)) return;
+    const DevJob &J = src(job);
+    ph_last_search<G>(J, J.view[0], tile);
+}
+
+template <class Src>
+__global__ __launch_bounds__(kWG) void k_last_resolve(Src src)
+{
+    int job, tile;
+    if (!src.locate(PH_SEARCH_FIN, job, tile)) return;
+    const DevJob &J = src(job);
+    ph_last_resolve(J, J.view[0], tile);
+}
+
+template <class Src>
+__global__ __launch_bounds__(kWG) void k_last_final(Src src)
+{
+    int job, tile;
+    if (!src.locate(PH_SEARCH_FIN, job, tile)) return;
+    const DevJob &J = src(job);
+    ph_last_final(J, J.view[0], view_kp(J, 0), tile);
+}
+
+hipError_t launch_last_frame(const DevJob &J, int lanes, hipStream_t s)
+{
+    OneJob src{J};
+    void *args[] = {&src};
+    const int nK = view_kp(J, 0);
+    // setup: the view's one-bin cell index, claims cleared, histogram and
+    // match count zeroed
+    hipError_t e = hipLaunchKernel(reinterpret_cast<void *>(&k_setup<OneJob, kWG>), dim3(1), dim3(kWG), args, 0, s);
+    if (e != hipSuccess) return e;
+    if (J.nM > 0) {
+        void *fn;
+        switch (lanes) {
+        case 1: fn = reinterpret_cast<void *>(&k_last_search<OneJob, 1>); break;
+        case 2: fn = reinterpret_cast<void *>(&k_last_search<OneJob, 2>); break;
+        case 8: fn = reinterpret_cast<void *>(&k_last_search<OneJob, 8>); break;
+        default: fn = reinterpret_cast<void *>(&k_last_search<OneJob, 4>); lanes = 4; break;
+        }
+        if ((e = hipLaunchKernel(fn, dim3(div_up(J.nM, kWG / lanes)), dim3(kWG), args, 0, s)) != hipSuccess) return e;
+        if ((e = hipLaunchKernel(reinterpret_cast<void *>(&k_last_resolve<OneJob>), dim3(div_up(J.nM, kWG)),
+                                 dim3(kWG), args, 0, s)) != hipSuccess)
+            return e;
+    }
+    const int n = J.nM > nK ? J.nM : nK;
+    if (n > 0 && (e = hipLaunchKernel(reinterpret_cast<void *>(&k_last_final<OneJob>), dim3(div_up(n, kWG)),
+                                      dim3(kWG), args, 0, s)) != hipSuccess)
+        return e;
+    return hipGetLastError();
+}
+
 // Kernel of phase p for these shapes, and its workgroup size.
 template <class Src>
 static void *phase_kernel(const Shapes &sh, int p, int *block)
 {
     *block = kWG;
     switch (p) {
+    case PH_PYRAMID: return reinterpret_cast<void *>(&k_pyramid<Src>);
     case PH_SETUP:
         if (sh.aux_block == kAuxWG) {
             *block = kAuxWG;
