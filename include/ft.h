@@ -296,7 +296,9 @@ ft_status ft_pyramid_layout(int32_t width, int32_t height, const ft_scales *scal
  * levels in one launch.  The source coordinate of output index x of a level n
  * wide over a level-0 axis N long is (x + 1/2) * N / n - 1/2, taken exactly;
  * the weights are floor(256 * fraction), the taps clamp at the borders, and
- * the value (sum of weight products + 2^15) >> 16.  Errors as above. */
+ * the value (sum of weight products + 2^15) >> 16.  Every level must be no
+ * larger than the image (scale factors >= 1), else FT_ERR_INVALID_ARGUMENT.
+ * Errors as above. */
 ft_status ft_build_pyramid(ft_context *ctx, void *stream, const ft_image *image, const ft_scales *scales,
                            const ft_pyramid *pyr);
 

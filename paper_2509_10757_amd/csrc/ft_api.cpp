@@ -95,6 +95,7 @@ struct ft_context {
     bool timing = false;
     std::vector<std::vector<hipEvent_t>> ev_sets;
     std::vector<uint8_t> ev_pending;   // 0 free, 1 per-phase marks pending
+    std::vector<uint32_t> ev_mask;     // phases with a launched kernel, per event set
     size_t ev_next = 0;
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
@@ -283,6 +284,9 @@ ft_status check_pyramid_build(ft_context *ctx, const ft_image *img, const ft_sca
     int64_t bytes = 0;
     if (!pyramid_layout(img->width, img->height, sc, &want, &bytes))
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: a pyramid level of the image would be empty", what);
+    for (int l = 1; l < kLevels; ++l)   // levels shrink (the build stages at most kPyrRows + 1 rows per tile)
+        if (want.width[l] > img->width || want.height[l] > img->height)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: pyramid level %d is larger than the image", what, l);
     for (int l = 0; l < kLevels; ++l)
         if (pyr->offset[l] != want.offset[l] || pyr->width[l] != want.width[l] || pyr->height[l] != want.height[l])
             return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: pyramid level %d is not the packed layout", what, l);
@@ -553,6 +557,7 @@ void drain_set(ft_context *ctx, size_t k)
     auto &ev = ctx->ev_sets[k];
     hipEventSynchronize(ev[PH_COUNT]);
     for (int p = 0; p < PH_COUNT; ++p) {
+        if (!((ctx->ev_mask[k] >> p) & 1u)) continue;   // no kernel of this phase was launched
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev[p], ev[p + 1]) == hipSuccess && ms > 0.0f) {
             ctx->phase_ms[p] += ms;
@@ -562,14 +567,19 @@ void drain_set(ft_context *ctx, size_t k)
     ctx->ev_pending[k] = 0;
 }
 
-// Event set for the next launch (nullptr when timing is off).
-hipEvent_t *next_events(ft_context *ctx)
+// Event set for the next launch (nullptr when timing is off); only the phases
+// with tiles are timed.
+hipEvent_t *next_events(ft_context *ctx, const int32_t totals[PH_COUNT])
 {
     if (!ctx->timing) return nullptr;
     const size_t k = ctx->ev_next;
     ctx->ev_next = (k + 1) % kEventSets;
     drain_set(ctx, k);
     ctx->ev_pending[k] = 1;
+    uint32_t mask = 0;
+    for (int p = 0; p < PH_COUNT; ++p)
+        if (totals[p] > 0) mask |= 1u << p;
+    ctx->ev_mask[k] = mask;
     return ctx->ev_sets[k].data();
 }
 
@@ -578,6 +588,7 @@ ft_status set_timing(ft_context *ctx, bool enable)
     if (enable && ctx->ev_sets.empty()) {
         ctx->ev_sets.assign(kEventSets, std::vector<hipEvent_t>(kPhases + 1, nullptr));
         ctx->ev_pending.assign(kEventSets, 0);
+        ctx->ev_mask.assign(kEventSets, 0);
         for (auto &set : ctx->ev_sets)
             for (auto &e : set) HIP_TRY(ctx, hipEventCreate(&e));
     }
@@ -610,7 +621,7 @@ ft_status launch_one(ft_context *ctx, const DevJob &J, hipStream_t s, bool stere
     int32_t tot[PH_COUNT];
     job_tiles(J, ctx->shapes, stereo, search, tot);
     TileMap none{0, nullptr};
-    HIP_TRY(ctx, launch_pipeline(nullptr, none, tot, J, ctx->shapes, s, next_events(ctx)));
+    HIP_TRY(ctx, launch_pipeline(nullptr, none, tot, J, ctx->shapes, s, next_events(ctx, tot)));
     return FT_OK;
 }
 
@@ -1299,7 +1310,7 @@ ft_status ft_batch_submit(ft_context *ctx, void *stream, const ft_frame_job *job
     int32_t totals[PH_COUNT];
     plan_batch(ctx, *lane, n, ctx->shapes, totals);
     if (ctx->exec_mode == FT_EXEC_EAGER || ctx->timing)
-        st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx));
+        st = launch_batch(ctx, *lane, n, ctx->shapes, s, totals, next_events(ctx, totals));
     else
         st = launch_batch_graph(ctx, *lane, n, s, totals);
     if (st) return st;
@@ -1377,7 +1388,7 @@ ft_status ft_autotune(ft_context *ctx, void *stream, const ft_frame_job *jobs, i
             for (int r = 0; r < 4; ++r) {
                 int32_t totals[PH_COUNT];
                 plan_batch(ctx, *lane, n, sh, totals);
-                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx));
+                ft_status e = launch_batch(ctx, *lane, n, sh, s, totals, next_events(ctx, totals));
                 if (e) return e;
                 HIP_TRY(ctx, hipStreamSynchronize(s));
                 read_timing(ctx, ms, cnt);

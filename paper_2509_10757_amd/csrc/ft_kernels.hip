@@ -224,13 +224,13 @@ __device__ __forceinline__ uint32_t pyr_tap(int x, int n_in, int n_out)
     return (uint32_t)q | ((uint32_t)wq << 16);
 }
 
-// LDS of one pyramid tile: kPyrRows + 1 staged level-0 rows, then the column
-// taps of levels 1..7, then per-level row ranges.
+// LDS of one pyramid tile: kPyrRows + 1 staged level-0 rows, then per level
+// the first output row, the row count and the row taps of the tile's rows.
 constexpr int kPyrStage = (kPyrRows + 1) * kMaxPyrW;
-constexpr int kPyrTab = kPyrStage;                          // uint32 [kPyrTabN]
-constexpr int kPyrTabN = 4 * kMaxPyrW;                      // sum of w_l over l >= 1 is < 3.6 W
-constexpr int kPyrMeta = kPyrTab + 4 * kPyrTabN;            // int [3 * kLevels]
-constexpr int kPyrLds = kPyrMeta + 3 * kLevels * 4;
+constexpr int kPyrRowTaps = kPyrRows + 2;                   // output rows of one level in a tile (bound)
+constexpr int kPyrMeta = kPyrStage;                         // int [kLevels][2]: first row, count
+constexpr int kPyrRowTab = kPyrMeta + 2 * kLevels * 4;      // uint32 [kLevels][kPyrRowTaps]
+constexpr int kPyrLds = kPyrRowTab + kLevels * kPyrRowTaps * 4;
 
 // Output rows of level l whose top tap row lies in [Y0, Y1): the level's row
 // tap is monotone in the row, so the range is found by bisection.
@@ -249,7 +249,9 @@ __device__ __forceinline__ int pyr_first_row(int Y, int H, int h)
 // [Y0, Y0 + kPyrRows).  Stages those rows and the next in LDS, copies them to
 // level 0 and writes every output row of levels 1..7 whose top tap row is
 // among them: each source row is read from memory once and each output byte
-// written once.  Waves take whole output rows; lanes stride the columns.
+// written once.  A thread owns output columns (of all levels in turn), takes
+// the column's tap once and walks the tile's rows of that level; neighbouring
+// threads write neighbouring bytes of a row.
 __device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned char *smem)
 {
     const int W = J.img_w, H = J.img_h, pitch = J.img_pitch;
@@ -263,18 +265,17 @@ __device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned c
     const int ys = min(Y1 + 1, H);           // staged rows [Y0, ys)
     const int stride = (W + 3) & ~3;
     uint8_t *stage = smem;
-    uint32_t *tab = reinterpret_cast<uint32_t *>(smem + kPyrTab);
-    int *meta = reinterpret_cast<int *>(smem + kPyrMeta);   // row lo | row hi | table offset
+    int *meta = reinterpret_cast<int *>(smem + kPyrMeta);          // first row | row count per level
+    uint32_t *rtab = reinterpret_cast<uint32_t *>(smem + kPyrRowTab);
     const int tid = threadIdx.x;
-    if (tid < kLevels) {
-        const int l = tid;
-        int toff = 0;
-        for (int k = 1; k < l; ++k) toff += J.lv_w[k];
-        meta[3 * l + 2] = toff;
-        if (l >= 1) {
-            meta[3 * l] = pyr_first_row(Y0, H, J.lv_h[l]);
-            meta[3 * l + 1] = Y1 >= H ? J.lv_h[l] : pyr_first_row(Y1, H, J.lv_h[l]);
-        }
+    if (tid >= 1 && tid < kLevels) {
+        const int l = tid, hl = J.lv_h[l];
+        const int ylo = pyr_first_row(Y0, H, hl);
+        const int yhi = Y1 >= H ? hl : pyr_first_row(Y1, H, hl);
+        const int n = min(yhi - ylo, kPyrRowTaps);   // at most ceil(kPyrRows * hl / H) + 1 rows
+        meta[2 * l] = ylo;
+        meta[2 * l + 1] = n;
+        for (int r = 0; r < n; ++r) rtab[l * kPyrRowTaps + r] = pyr_tap(ylo + r, H, hl);
     }
     // stage the level-0 rows: 4-byte loads when rows and base are aligned
     const bool al4 = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)pitch | (uintptr_t)W) & 3u) == 0;
@@ -291,17 +292,6 @@ __device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned c
             const int r = e / W, c = e - r * W;
             stage[r * stride + c] = src[(size_t)(Y0 + r) * pitch + c];
         }
-    }
-    // column taps of levels 1..7
-    int ntab = 0;
-    for (int l = 1; l < kLevels; ++l) ntab += J.lv_w[l];
-    for (int e = tid; e < ntab; e += kWG) {
-        int l = 1, base = 0;
-        while (e >= base + J.lv_w[l]) {
-            base += J.lv_w[l];
-            ++l;
-        }
-        tab[e] = pyr_tap(e - base, W, J.lv_w[l]);
     }
     __syncthreads();
     // level 0: the staged rows [Y0, Y1)
@@ -322,36 +312,35 @@ __device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned c
             }
         }
     }
-    // levels 1..7: wave w takes output rows w, w + 4, ... of the tile's list
-    const int wave = tid >> 6, lane = tid & 63;
-    int row_base = 0;
-    for (int l = 1; l < kLevels; ++l) {
-        const int ylo = meta[3 * l], yhi = meta[3 * l + 1];
-        const int wl = J.lv_w[l], hl = J.lv_h[l];
-        const uint32_t *ct = tab + meta[3 * l + 2];
-        FT_G uint8_t *dl = dst + J.lv_off[l];
-        const int nrows = yhi - ylo;
-        // rows of this level taken by this wave, continuing the round robin
-        int k0 = (wave - row_base) & 3;
-        for (int k = k0; k < nrows; k += 4) {
-            const int y = ylo + k;
-            const uint32_t rt = pyr_tap(y, H, hl);
-            const int y0 = (int)(rt & 0xFFFFu), b = (int)(rt >> 16);
+    // levels 1..7: columns of the levels laid end to end, dealt over the threads
+    int wsum[kLevels];
+    int total = 0;
+    _Pragma("unroll") for (int l = 1; l < kLevels; ++l)
+    {
+        wsum[l] = total;
+        total += J.lv_w[l];
+    }
+    for (int e = tid; e < total; e += kWG) {
+        int l = 1;
+        _Pragma("unroll") for (int k = 2; k < kLevels; ++k) l = e >= wsum[k] ? k : l;
+        const int x = e - wsum[l];
+        const int wl = J.lv_w[l];
+        const uint32_t c = pyr_tap(x, W, wl);
+        const int x0 = (int)(c & 0xFFFFu), a = (int)(c >> 16);
+        const int x1 = min(x0 + 1, W - 1);
+        const int ylo = meta[2 * l], n = meta[2 * l + 1];
+        FT_G uint8_t *dcol = dst + J.lv_off[l] + (size_t)ylo * wl + x;
+        const uint32_t *rt = rtab + l * kPyrRowTaps;
+        for (int r = 0; r < n; ++r) {
+            const uint32_t t = rt[r];
+            const int y0 = (int)(t & 0xFFFFu), b = (int)(t >> 16);
             const uint8_t *r0 = stage + (y0 - Y0) * stride;
             const uint8_t *r1 = stage + (min(y0 + 1, H - 1) - Y0) * stride;
-            FT_G uint8_t *drow = dl + (size_t)y * wl;
-            for (int x = lane; x < wl; x += 64) {
-                const uint32_t c = ct[x];
-                const int x0 = (int)(c & 0xFFFFu), a = (int)(c >> 16);
-                const int x1 = min(x0 + 1, W - 1);
-                const int p00 = r0[x0], p01 = r0[x1], p10 = r1[x0], p11 = r1[x1];
-                const int top = (256 - a) * p00 + a * p01;
-                const int bot = (256 - a) * p10 + a * p11;
-                const int v = (256 - b) * top + b * bot;
-                drow[x] = (uint8_t)((v + 32768) >> 16);
-            }
+            const int top = (256 - a) * r0[x0] + a * r0[x1];
+            const int bot = (256 - a) * r1[x0] + a * r1[x1];
+            const int v = (256 - b) * top + b * bot;
+            dcol[(size_t)r * wl] = (uint8_t)((v + 32768) >> 16);
         }
-        row_base += nrows;
     }
 }
 
