@@ -150,6 +150,30 @@ def three_fullest(count) -> np.ndarray:
     return kept.astype(bool)
 
 
+def map_update(mp: dict, capacity: int, remove, insert: dict | None):
+    """Local-map maintenance in place (see ft_oracle.h): returns the edited
+    map (arrays of length new n) or None when the edit is rejected."""
+    n = len(mp["dmin"])
+    m = 0 if insert is None else len(insert["dmin"])
+    cap = max(capacity, 1)
+    work = {"pos": np.zeros((cap, 3), np.float32), "normal": np.zeros((cap, 3), np.float32),
+            "dmin": np.zeros(cap, np.float32), "dmax": np.zeros(cap, np.float32),
+            "desc": np.zeros((cap, 32), np.uint8)}
+    for k in work:
+        work[k][:n] = mp[k]
+    ins = insert if insert is not None else {k: v[:0] for k, v in work.items()}
+    ins = {k: _c(v, work[k].dtype) for k, v in ins.items()}
+    rem = _c(np.asarray(remove, np.int64), np.int32)
+    lib = _load()
+    new_n = lib.oracle_map_update(ct.c_int(n), ct.c_int(capacity), _p(work["pos"]), _p(work["normal"]),
+                                  _p(work["dmin"]), _p(work["dmax"]), _p(work["desc"]), ct.c_int(len(rem)), _p(rem),
+                                  ct.c_int(m), _p(ins["pos"]), _p(ins["normal"]), _p(ins["dmin"]), _p(ins["dmax"]),
+                                  _p(ins["desc"]))
+    if new_n < 0:
+        return None
+    return {k: np.ascontiguousarray(v[:new_n]) for k, v in work.items()}
+
+
 def pyramid_layout(W: int, H: int, inv_sf) -> dict:
     """Level sizes and packed offsets of the image pyramid (Section IV-B)."""
     isf = _c(inv_sf, np.float32)

@@ -698,3 +698,46 @@ void oracle_search_last_frame(
     }
     free(cand_k); free(cand_h); free(alive);
 }
+
+/* Copy map record `from` over record `to`. */
+static void map_copy(float *pos, float *normal, float *dmin, float *dmax, uint8_t *desc, int to,
+                     const float *spos, const float *snormal, const float *sdmin, const float *sdmax,
+                     const uint8_t *sdesc, int from)
+{
+    for (int c = 0; c < 3; ++c) {
+        pos[3 * to + c] = spos[3 * from + c];
+        normal[3 * to + c] = snormal[3 * from + c];
+    }
+    dmin[to] = sdmin[from];
+    dmax[to] = sdmax[from];
+    memcpy(desc + 32 * (size_t)to, sdesc + 32 * (size_t)from, 32);
+}
+
+int oracle_map_update(int n, int capacity, float *pos, float *normal, float *dmin, float *dmax, uint8_t *desc,
+                      int n_remove, const int32_t *remove, int n_insert, const float *ipos,
+                      const float *inormal, const float *idmin, const float *idmax, const uint8_t *idesc)
+{
+    if (n < 0 || n_remove < 0 || n_insert < 0 || n_remove > n) return -1;
+    uint8_t *gone = (uint8_t *)calloc(n > 0 ? n : 1, 1);
+    for (int i = 0; i < n_remove; ++i) {
+        const int r = remove[i];
+        if (r < 0 || r >= n || gone[r]) { free(gone); return -1; }
+        gone[r] = 1;
+    }
+    const int n1 = n - n_remove;
+    if ((int64_t)n1 + n_insert > capacity) { free(gone); return -1; }
+    /* the k-th removed slot below n1 takes the k-th surviving point at or above n1 */
+    int h = 0, src = n1;
+    for (;;) {
+        while (h < n1 && !gone[h]) ++h;
+        while (src < n && gone[src]) ++src;
+        if (h >= n1 || src >= n) break;
+        map_copy(pos, normal, dmin, dmax, desc, h, pos, normal, dmin, dmax, desc, src);
+        ++h;
+        ++src;
+    }
+    for (int j = 0; j < n_insert; ++j)
+        map_copy(pos, normal, dmin, dmax, desc, n1 + j, ipos, inormal, idmin, idmax, idesc, j);
+    free(gone);
+    return n1 + n_insert;
+}

@@ -109,6 +109,23 @@ void oracle_search_last_frame(
     const float *sf, int n_levels, const float *fp, const int32_t *ip,
     int32_t *l_match, int32_t *l_dist, int32_t *kp_match, int64_t *stats);
 
+/* Local-map maintenance in place (Update Local Map's output set kept where
+ * the search reads it; Section IV-D and IV-E).  The map is SoA (pos [n][3],
+ * normal [n][3], dmin, dmax, desc [n][32]) with room for `capacity` points.
+ * The n_remove indices in `remove` (distinct, each < n) leave the map; with
+ * n1 = n - n_remove, the removed slots below n1 ("holes", ascending) take the
+ * surviving points at or above n1 ("sources", ascending), the k-th hole the
+ * k-th source; then the n_insert new points are appended at n1, in order.
+ * Returns the new count n1 + n_insert, or -1 (map untouched) when an index is
+ * out of range or repeated or the result exceeds the capacity.  Pinned by
+ * invariants: the new map holds exactly the surviving and inserted records,
+ * survivors below n1 keep their slots, holes take the tail survivors in
+ * order, inserted points follow in order; edge cases (nothing, everything,
+ * only head or only tail points removed, exact capacity, invalid lists). */
+int oracle_map_update(int n, int capacity, float *pos, float *normal, float *dmin, float *dmax, uint8_t *desc,
+                      int n_remove, const int32_t *remove, int n_insert, const float *ipos,
+                      const float *inormal, const float *idmin, const float *idmax, const uint8_t *idesc);
+
 /* Rotation bin of a match and the bins kept by the three-fullest rule, exposed
  * so tests can pin them on their own. */
 int oracle_rotation_bin(float a_last, float a_cur, int bins);

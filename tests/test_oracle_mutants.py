@@ -11,6 +11,7 @@ import pytest
 import oracle
 import synth
 from tests import test_oracle_pins as pins
+from tests import test_oracle_map as mapt
 from tests import test_oracle_motion as motion
 from tests import test_oracle_pyramid as pyr
 
@@ -80,6 +81,11 @@ MUTANTS = {
     "three_fullest_tenth": ("if (10 * m2 < m1) { i2 = -1; i3 = -1; }", "if (2 * m2 < m1) { i2 = -1; i3 = -1; }"),
     "three_fullest_third_always": ("else if (10 * m3 < m1) i3 = -1;", ""),
     "three_fullest_tie_to_later": ("if (c > m1) { m3 = m2;", "if (c >= m1) { m3 = m2;"),
+    "map_pair_from_the_end": ("int h = 0, src = n1;", "int h = 0, src = n1 + 1;"),
+    "map_append_at_old_count": ("map_copy(pos, normal, dmin, dmax, desc, n1 + j, ipos", "map_copy(pos, normal, dmin, dmax, desc, n + j, ipos"),
+    "map_duplicates_accepted": ("if (r < 0 || r >= n || gone[r])", "if (r < 0 || r >= n)"),
+    "map_normal_not_moved": ("        normal[3 * to + c] = snormal[3 * from + c];\n", ""),
+    "map_capacity_strict": ("if ((int64_t)n1 + n_insert > capacity)", "if ((int64_t)n1 + n_insert >= capacity)"),
     "conflict_tie": ("int64_t key = ((int64_t)dist[i] << 32) | (int64_t)i;\n        if (key < best",
                      "int64_t key = ((int64_t)dist[i] << 32) | (int64_t)(nQ - i);\n        if (key < best"),
 }
@@ -135,6 +141,12 @@ def _pins(frames):
     tests.append(motion.test_stereo_gate_and_preassigned_flag)
     tests.append(lambda: motion.test_distance_threshold_is_inclusive(100, True))
     tests.append(motion.test_two_points_claiming_one_keypoint)
+    for case in mapt.CASES:
+        tests.append(lambda c=case: mapt.test_map_update_rule(*c))
+    tests.append(mapt.test_random_edit_sequences)
+    for args in [([3, 3], 0, 100), ([50], 0, 100)]:
+        tests.append(lambda a=args: mapt.test_invalid_edits_are_rejected(*a))
+    tests.append(mapt.test_exact_capacity_is_accepted)
     tests.append(pyr.test_level_sizes_of_the_paper_shapes)
     tests.append(lambda: pyr.test_horizontal_ramp_is_round_half_up_of_the_source_column(200, 37))
     tests.append(lambda: pyr.test_vertical_ramp_is_round_half_up_of_the_source_row(40, 250))
