@@ -22,6 +22,8 @@ Beside the headline the default run also reports:
     roofline warm and cold);
   * the last-frame search by projection (Initial Pose Estimation) on the
     pinhole frame and both fisheye views: per-call p50/p99;
+  * local-map maintenance on the device: a 20000-point map with 5% of its
+    points replaced per edit, against uploading the whole map again;
   * a bounded serving sweep (32 camera streams, resident maps of 2k-40k
     points): per-frame path and continuous batching over the same Poisson
     arrivals, frames/s at equal p99, and a sample of frames served inside
@@ -327,7 +329,7 @@ def main():
                     help="seconds per arrival rate of the serving sweep (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the single-frame workloads and the clustered batch")
-    ap.add_argument("--only", choices=["mixed", "clustered"], default=None,
+    ap.add_argument("--only", choices=["mixed", "clustered", "pyramids"], default=None,
                     help="profiling runs: only the timed region of one workload, no other legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration) and exit")
@@ -381,7 +383,9 @@ def main():
     # one private copy of the frames (inputs, workspace-independent outputs)
     # per submission stream, so batches in flight on different streams never
     # share a buffer
-    copies = [[ft.DeviceFrame(f, "cuda") for f in frames] for _ in range(1 if profiling else max_streams)]
+    build_pyr = args.only == "pyramids"   # profiling: the pinhole jobs build their pyramids first
+    copies = [[ft.DeviceFrame(f, "cuda", build_pyramids=build_pyr) for f in frames]
+              for _ in range(1 if profiling else max_streams)]
     dfs = copies[0]
     job_sets = [[d.job() for d in c] for c in copies]
     jobs = job_sets[0]
@@ -644,6 +648,55 @@ def main():
                                    "matches": dl.results()["n_matches"], "reps": reps}
                 log("last frame", key, last_frame[key])
 
+    # ---- local-map maintenance on the device: a 20000-point map edited per
+    # frame (5% of its points replaced: removal list and the new points'
+    # upload included) against uploading the whole map again
+    map_maint = None
+    if not args.no_extra:
+        mf = synth.clustered_search_20000()[0]["map"]
+        n_map, n_edit, cap = len(mf["dmin"]), 1000, 24000
+        dmap = ft.DeviceMap(mf, cap)
+        rng = np.random.default_rng(5)
+        newp = synth.clustered_search_20000(seed=synth.seed_of(77))[0]["map"]
+        pinned = {k: torch.from_numpy(np.ascontiguousarray(v[:n_edit])).pin_memory() for k, v in newp.items()}
+        dev_ins = {k: torch.empty(v.shape, dtype=v.dtype, device="cuda") for k, v in pinned.items()}
+        ins = ft.ft_map_points(n_edit, *(ft._ptr(dev_ins[k]) for k in ("pos", "normal", "dmin", "dmax", "desc")))
+        whole = {k: torch.from_numpy(np.ascontiguousarray(v)).pin_memory() for k, v in mf.items()}
+        whole_dev = {k: torch.empty(v.shape, dtype=v.dtype, device="cuda") for k, v in whole.items()}
+        reps = max(200, args.steps)
+
+        def edit_once():
+            with torch.cuda.stream(stream):
+                for k in dev_ins:
+                    dev_ins[k].copy_(pinned[k], non_blocking=True)
+            remove = rng.choice(dmap.n, n_edit, replace=False)
+            ctx.ft_map_update(dmap.struct, cap, remove, ins, stream=stream)
+
+        for _ in range(10):
+            edit_once()
+        torch.cuda.synchronize()
+        te = []
+        for _ in range(reps):
+            s0 = time.perf_counter()
+            edit_once()
+            stream.synchronize()
+            te.append((time.perf_counter() - s0) * 1e3)
+        tw = []
+        for _ in range(reps):
+            s0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                for k in whole_dev:
+                    whole_dev[k].copy_(whole[k], non_blocking=True)
+            stream.synchronize()
+            tw.append((time.perf_counter() - s0) * 1e3)
+        map_maint = {"workload": f"{n_map}-point local map, {n_edit} points removed and {n_edit} inserted per edit",
+                     "edit_ms": percentiles(te), "whole_map_upload_ms": percentiles(tw),
+                     "bytes_per_point": 64, "reps": reps,
+                     "timed": "host clock around each edit (upload of the inserted points, removal list, "
+                              "both kernels) and each whole-map upload, synchronized"}
+        log("map maintenance", map_maint)
+        del dmap, dev_ins, whole_dev
+
     serving = None
     if args.serving > 0:
         del copies, dfs
@@ -670,6 +723,7 @@ def main():
         "single_frame_workloads": configs,
         "clustered_batch64": clustered,
         "device_pyramids": pyramids,
+        "map_maintenance": map_maint,
         "last_frame_search": last_frame,
         "serving": serving,
     }

@@ -347,6 +347,31 @@ ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_poin
                                const ft_scales *scales, const ft_last_params *params,
                                const ft_search_out *out);
 
+/* ------------------------------------------------------------------------ */
+/* Local-map maintenance on the device (Update Local Map's output set kept  */
+/* where Search Local Points reads it: Section IV-D, IV-E).                  */
+/* ------------------------------------------------------------------------ */
+typedef struct ft_map_edit {
+    int32_t n_remove;
+    const int32_t *remove;     /* HOST [n_remove] indices into the current map: distinct, each < map->n */
+    ft_map_points insert;      /* DEVICE arrays of the insert.n points to append (a map's layout) */
+} ft_map_edit;
+
+/* Edits a device-resident map in place.  The listed points leave the map;
+ * with n1 = map->n - n_remove, the removed slots below n1 take the surviving
+ * points at or above n1 (the k-th slot in ascending order the k-th point in
+ * ascending order) and the inserted points are appended at n1 in order, so
+ * the call moves 64 B per removed slot below n1 plus 64 B per inserted point.
+ * `map` holds device arrays with room for `capacity` points; map->n (host) is
+ * set to n1 + insert.n when the call returns, while the moves run on `stream`
+ * (the map must not be read on another stream before they complete).
+ * Errors: a repeated or out-of-range index, null or misaligned arrays:
+ * FT_ERR_INVALID_ARGUMENT; a result above `capacity`, or n_remove or
+ * insert.n above max_map_points: FT_ERR_CAPACITY.  On error map->n is
+ * unchanged and nothing is enqueued. */
+ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,
+                        const ft_map_edit *edit);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops or harnesses that forbid allocation): the search of
  * ft_search_local_points, same kernels and bit-identical outputs, with no

@@ -113,6 +113,10 @@ class ft_search_out(ct.Structure):
     _fields_ = [("mp_match", P), ("mp_dist", P), ("kp_match", P), ("n_matches", P)]
 
 
+class ft_map_edit(ct.Structure):
+    _fields_ = [("n_remove", ct.c_int32), ("remove", P), ("insert", ft_map_points)]
+
+
 class ft_image(ct.Structure):
     _fields_ = [("data", P), ("width", ct.c_int32), ("height", ct.c_int32), ("pitch", ct.c_int32)]
 
@@ -172,6 +176,7 @@ EXPORTS = {
     "ft_search_last_frame": [P, P, ct.POINTER(ft_last_points), ct.POINTER(ft_search_camera),
                              ct.POINTER(ft_keypoints), P, P, P, ct.POINTER(ft_grid), ct.POINTER(ft_scales),
                              ct.POINTER(ft_last_params), ct.POINTER(ft_search_out)],
+    "ft_map_update": [P, P, ct.POINTER(ft_map_points), ct.c_int32, ct.POINTER(ft_map_edit)],
     "ft_batch_submit": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.POINTER(ct.c_uint64)],
     "ft_batch_poll": [P, ct.c_uint64, ct.POINTER(ct.c_int32)],
     "ft_batch_wait": [P, ct.c_uint64],
@@ -349,6 +354,18 @@ class Context:
                                            ct.byref(grid), ct.byref(scales), ct.byref(params), ct.byref(out))
         if check:
             self._check(st, "ft_search_last_frame")
+        return st
+
+    def ft_map_update(self, map_points, capacity: int, remove, insert, stream=None, check=True):
+        """Edit a device map in place; `map_points.n` is updated.  `remove`:
+        host indices (a sequence), `insert`: an ft_map_points of device arrays
+        (or None)."""
+        rem = np.ascontiguousarray(np.asarray(remove, dtype=np.int32).reshape(-1))
+        ed = ft_map_edit(len(rem), P(rem.ctypes.data if len(rem) else None),
+                         insert if insert is not None else ft_map_points())
+        st = self.lib.ft_map_update(self.h, _stream(stream), ct.byref(map_points), capacity, ct.byref(ed))
+        if check:
+            self._check(st, "ft_map_update")
         return st
 
     def ft_batch_submit(self, jobs, stream=None) -> int:
@@ -673,3 +690,43 @@ class DeviceLastFrame:
         r = {k: v.cpu().numpy() for k, v in self.o.items()}
         return {"last_match": r["mp_match"], "last_dist": r["mp_dist"], "kp_match": r["kp_match"],
                 "n_matches": int(r["n_matches"][0])}
+
+
+class DeviceMap:
+    """A local map in device memory with room for `capacity` points, edited in
+    place with ft_map_update."""
+
+    def __init__(self, mp: dict, capacity: int, device="cuda"):
+        n = len(mp["dmin"])
+        self.capacity = capacity
+        self.t = {"pos": torch.zeros((capacity, 3), dtype=torch.float32, device=device),
+                  "normal": torch.zeros((capacity, 3), dtype=torch.float32, device=device),
+                  "dmin": torch.zeros(capacity, dtype=torch.float32, device=device),
+                  "dmax": torch.zeros(capacity, dtype=torch.float32, device=device),
+                  "desc": torch.zeros((capacity, 32), dtype=torch.uint8, device=device)}
+        for k, v in self.t.items():
+            if n:
+                v[:n] = _dev(mp[k], v.cpu().numpy().dtype, device)
+        t = self.t
+        self.struct = ft_map_points(n, _ptr(t["pos"]), _ptr(t["normal"]), _ptr(t["dmin"]), _ptr(t["dmax"]),
+                                    _ptr(t["desc"]))
+
+    @property
+    def n(self) -> int:
+        return self.struct.n
+
+    def edit(self, ctx: Context, remove, insert: dict | None, stream=None, check=True):
+        """Remove host indices `remove` and append the points of host dict
+        `insert` (uploaded first)."""
+        ins = None
+        self._ins = None
+        if insert is not None and len(insert["dmin"]):
+            self._ins = {k: _dev(np.ascontiguousarray(v), None, self.t[k].device) for k, v in insert.items()}
+            i = self._ins
+            ins = ft_map_points(len(insert["dmin"]), _ptr(i["pos"]), _ptr(i["normal"]), _ptr(i["dmin"]),
+                                _ptr(i["dmax"]), _ptr(i["desc"]))
+        return ctx.ft_map_update(self.struct, self.capacity, remove, ins, stream=stream, check=check)
+
+    def host(self) -> dict:
+        n = self.n
+        return {k: v[:n].cpu().numpy() for k, v in self.t.items()}

@@ -61,8 +61,9 @@ struct BatchGraph {
     hipGraphNode_t kern[PH_COUNT] = {};
     void *fn[PH_COUNT] = {};
     int block[PH_COUNT] = {};
-    int32_t n = -1;                  // job count of the last submission (kernel argument)
-    int32_t grid[PH_COUNT] = {};     // grids of the last submission
+    int32_t n[PH_COUNT] = {};        // job count (kernel argument) each node was last set for
+    int32_t grid[PH_COUNT] = {};     // grid each node was last set for
+    bool off[PH_COUNT] = {};         // phase nodes disabled for the last submission (no tiles)
 };
 
 struct Lane {  // one batch in flight
@@ -100,6 +101,14 @@ struct ft_context {
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
     std::vector<std::pair<char *, size_t>> host_blocks;   // ft_host_alloc blocks (upload sources)
+    // map edits: (hole, source) pairs staged in pinned memory and copied to the
+    // device, one slot per edit in flight (a slot is reused after its event)
+    static constexpr int kEditSlots = 4;
+    int32_t *d_edit[kEditSlots] = {};
+    int32_t *h_edit[kEditSlots] = {};
+    hipEvent_t edit_ev[kEditSlots] = {};
+    bool edit_used[kEditSlots] = {};
+    int edit_next = 0;
 };
 
 namespace {
@@ -792,8 +801,9 @@ ft_status rebuild_graphs(ft_context *ctx)
 
 // Launches the lane's graph for this batch: the table upload size and, for
 // every phase whose grid or job count changed, the kernel node's grid and
-// argument are set in the instantiated graph first.  A phase without tiles
-// keeps its node with one workgroup, which finds no tile and returns.
+// argument are set in the instantiated graph first.  The node of a phase
+// without tiles is disabled for the launch (it then orders nothing and runs
+// nothing).
 ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, hipStream_t s,
                              const int32_t totals[PH_COUNT])
 {
@@ -804,8 +814,14 @@ ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, hipStream_t
     BatchArgs a = batch_args(ctx, lane, n);
     void *args[] = {&a};
     for (int p = 0; p < PH_COUNT; ++p) {
-        const int32_t grid = std::max<int32_t>(1, totals[p]);
-        if (grid == g.grid[p] && n == g.n) continue;
+        const bool off = totals[p] <= 0;
+        if (off != g.off[p]) {
+            HIP_TRY(ctx, hipGraphNodeSetEnabled(g.exec, g.kern[p], off ? 0u : 1u));
+            g.off[p] = off;
+        }
+        if (off) continue;
+        const int32_t grid = totals[p];
+        if (grid == g.grid[p] && n == g.n[p]) continue;
         hipKernelNodeParams kp{};
         kp.func = g.fn[p];
         kp.gridDim = dim3(grid);
@@ -815,8 +831,8 @@ ft_status launch_batch_graph(ft_context *ctx, Lane &lane, int32_t n, hipStream_t
         kp.extra = nullptr;
         HIP_TRY(ctx, hipGraphExecKernelNodeSetParams(g.exec, g.kern[p], &kp));
         g.grid[p] = grid;
+        g.n[p] = n;
     }
-    g.n = n;
     HIP_TRY(ctx, hipGraphLaunch(g.exec, s));
     return FT_OK;
 }
@@ -936,7 +952,8 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     carve_slot(tmp, nullptr, b, *lim);
     const size_t slot_bytes = align_up(b.off, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
-    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight;
+    const size_t edit_bytes = align_up(sizeof(int32_t) * 2 * (size_t)lim->max_map_points, 256);
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight + edit_bytes * ft_context::kEditSlots;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -948,6 +965,15 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         off += slot_bytes;
     };
     carve_at(ctx->direct);
+    for (int k = 0; k < ft_context::kEditSlots; ++k) {
+        ctx->d_edit[k] = reinterpret_cast<int32_t *>(ctx->base + off);
+        off += edit_bytes;
+        if (hipHostMalloc((void **)&ctx->h_edit[k], edit_bytes, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&ctx->edit_ev[k], hipEventDisableTiming) != hipSuccess) {
+            ft_context_destroy(ctx);
+            return FT_ERR_DEVICE;
+        }
+    }
     ctx->lanes.resize(lim->max_inflight);
     for (auto &ln : ctx->lanes) {
         ln.slots.resize(lim->max_batch_frames);
@@ -1000,6 +1026,13 @@ ft_status ft_context_destroy(ft_context *ctx)
         }
         release_graph(ln.g);
         if (ln.h_table) hipHostFree(ln.h_table);
+    }
+    for (int k = 0; k < ft_context::kEditSlots; ++k) {
+        if (ctx->edit_ev[k]) {
+            hipEventSynchronize(ctx->edit_ev[k]);
+            hipEventDestroy(ctx->edit_ev[k]);
+        }
+        if (ctx->h_edit[k]) hipHostFree(ctx->h_edit[k]);
     }
     if (ctx->base || !ctx->host_blocks.empty()) hipDeviceSynchronize();
     for (auto &hb : ctx->host_blocks) hipHostFree(hb.first);
@@ -1290,6 +1323,81 @@ ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_poin
     J.lv_hi = kLevels;
     if ((st = build_view(ctx, J, 0, 0, cam, kps, u_right, preassigned, grid, out, ctx->direct))) return st;
     HIP_TRY(ctx, launch_last_frame(J, 4, (hipStream_t)stream));
+    return FT_OK;
+}
+
+ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,
+                        const ft_map_edit *edit)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (!map || !edit) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null argument");
+    const int n = map->n, nr = edit->n_remove, m = edit->insert.n;
+    if (n < 0 || capacity < n || capacity > kMaxMap || nr < 0 || m < 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: n %d, capacity %d, %d removed, %d inserted", n,
+                    capacity, nr, m);
+    if (nr > ctx->lim.max_map_points || m > ctx->lim.max_map_points)
+        return fail(ctx, FT_ERR_CAPACITY, "map update: %d removed / %d inserted exceed max_map_points %d", nr, m,
+                    ctx->lim.max_map_points);
+    if (nr > 0 && !edit->remove) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null removal list");
+    auto arrays_ok = [](const ft_map_points &p) {
+        return p.pos && p.normal && p.dmin && p.dmax && p.desc && aligned(p.pos, 4) && aligned(p.normal, 4) &&
+               aligned(p.dmin, 4) && aligned(p.dmax, 4) && aligned(p.desc, 16);
+    };
+    if (capacity > 0 && !arrays_ok(*map))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null or misaligned map array");
+    if (m > 0 && !arrays_ok(edit->insert))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null or misaligned insert array");
+    std::vector<int32_t> rem(edit->remove, edit->remove + nr);
+    std::sort(rem.begin(), rem.end());
+    for (int i = 0; i < nr; ++i) {
+        if (rem[i] < 0 || rem[i] >= n)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: index %d outside [0, %d)", rem[i], n);
+        if (i > 0 && rem[i] == rem[i - 1])
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: index %d listed twice", rem[i]);
+    }
+    const int n1 = n - nr;
+    if ((int64_t)n1 + m > capacity)
+        return fail(ctx, FT_ERR_CAPACITY, "map update: %d points exceed the capacity %d", n1 + m, capacity);
+    // (hole, source) pairs: removed slots below n1 and surviving points from n1 up, both ascending
+    const int slot = ctx->edit_next;
+    ctx->edit_next = (slot + 1) % ft_context::kEditSlots;
+    if (ctx->edit_used[slot]) HIP_TRY(ctx, hipEventSynchronize(ctx->edit_ev[slot]));
+    int32_t *pairs = ctx->h_edit[slot];
+    const int n_holes = (int)(std::lower_bound(rem.begin(), rem.end(), n1) - rem.begin());
+    int src = n1;
+    size_t tail = (size_t)n_holes;   // removed indices at or above n1 (ascending)
+    for (int h = 0; h < n_holes; ++h) {
+        while (tail < rem.size() && rem[tail] == src) {
+            ++tail;
+            ++src;
+        }
+        pairs[2 * h] = rem[h];
+        pairs[2 * h + 1] = src++;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (n_holes > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_edit[slot], pairs, sizeof(int32_t) * 2 * (size_t)n_holes,
+                                    hipMemcpyHostToDevice, s));
+    MapEditArgs a{};
+    a.pos = const_cast<float *>(map->pos);
+    a.normal = const_cast<float *>(map->normal);
+    a.dmin = const_cast<float *>(map->dmin);
+    a.dmax = const_cast<float *>(map->dmax);
+    a.desc = const_cast<uint8_t *>(map->desc);
+    a.pairs = ctx->d_edit[slot];
+    a.n_pairs = n_holes;
+    a.ipos = edit->insert.pos;
+    a.inormal = edit->insert.normal;
+    a.idmin = edit->insert.dmin;
+    a.idmax = edit->insert.dmax;
+    a.idesc = edit->insert.desc;
+    a.n1 = n1;
+    a.n_insert = m;
+    HIP_TRY(ctx, launch_map_edit(a, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->edit_ev[slot], s));
+    ctx->edit_used[slot] = true;
+    map->n = n1 + m;
     return FT_OK;
 }
 

@@ -211,6 +211,20 @@ void batch_kernels(const Shapes &shapes, void *fn[PH_COUNT], int block[PH_COUNT]
 constexpr size_t kNoallocScratchBytes = FT_NOALLOC_SCRATCH_BYTES;
 hipError_t noalloc_scratch(int device, char **out, bool *gfx950);
 
+// Local-map edit (ft_kernels.hip): the (hole, source) pairs move first, then
+// the inserted points are appended at n1 (two launches: an append may land on
+// a source slot).
+struct MapEditArgs {
+    FT_G float *pos, *normal, *dmin, *dmax;
+    FT_G uint8_t *desc;
+    const FT_G int32_t *pairs;   // [n_pairs][2]: hole, source
+    int32_t n_pairs;
+    const FT_G float *ipos, *inormal, *idmin, *idmax;
+    const FT_G uint8_t *idesc;
+    int32_t n1, n_insert;
+};
+hipError_t launch_map_edit(const MapEditArgs &a, hipStream_t stream);
+
 // Gather-list copy (ft_upload.hip): up to kUploadSegs segments per launch,
 // passed by value; each workgroup copies one kUploadChunk-byte chunk of one
 // segment.  `first[s]` is the first workgroup of segment s, first[n] the grid.

@@ -2288,6 +2288,55 @@ hipError_t launch_last_frame(const DevJob &J, int lanes, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------- local-map edit
+// A thread per moved or appended point copies its 64-byte record (position,
+// normal, distance bounds, descriptor).
+__device__ __forceinline__ void map_copy_rec(const MapEditArgs &a, int to, const FT_G float *pos,
+                                             const FT_G float *normal, const FT_G float *dmin,
+                                             const FT_G float *dmax, const FT_G uint8_t *desc, int from)
+{
+    float p[3], nr[3];
+    _Pragma("unroll") for (int c = 0; c < 3; ++c)
+    {
+        p[c] = pos[3 * from + c];
+        nr[c] = normal[3 * from + c];
+    }
+    const float d0 = dmin[from], d1 = dmax[from];
+    const uint4 q0 = reinterpret_cast<const FT_G uint4 *>(desc + 32 * (size_t)from)[0];
+    const uint4 q1 = reinterpret_cast<const FT_G uint4 *>(desc + 32 * (size_t)from)[1];
+    _Pragma("unroll") for (int c = 0; c < 3; ++c)
+    {
+        a.pos[3 * to + c] = p[c];
+        a.normal[3 * to + c] = nr[c];
+    }
+    a.dmin[to] = d0;
+    a.dmax[to] = d1;
+    reinterpret_cast<FT_G uint4 *>(a.desc + 32 * (size_t)to)[0] = q0;
+    reinterpret_cast<FT_G uint4 *>(a.desc + 32 * (size_t)to)[1] = q1;
+}
+
+__global__ __launch_bounds__(kWG) void k_map_move(MapEditArgs a)
+{
+    const int i = blockIdx.x * kWG + threadIdx.x;
+    if (i >= a.n_pairs) return;
+    const int hole = a.pairs[2 * i], src = a.pairs[2 * i + 1];
+    map_copy_rec(a, hole, a.pos, a.normal, a.dmin, a.dmax, a.desc, src);
+}
+
+__global__ __launch_bounds__(kWG) void k_map_append(MapEditArgs a)
+{
+    const int j = blockIdx.x * kWG + threadIdx.x;
+    if (j >= a.n_insert) return;
+    map_copy_rec(a, a.n1 + j, a.ipos, a.inormal, a.idmin, a.idmax, a.idesc, j);
+}
+
+hipError_t launch_map_edit(const MapEditArgs &a, hipStream_t s)
+{
+    if (a.n_pairs > 0) hipLaunchKernelGGL(k_map_move, dim3(div_up(a.n_pairs, kWG)), dim3(kWG), 0, s, a);
+    if (a.n_insert > 0) hipLaunchKernelGGL(k_map_append, dim3(div_up(a.n_insert, kWG)), dim3(kWG), 0, s, a);
+    return hipGetLastError();
+}
+
 // Kernel of phase p for these shapes, and its workgroup size.
 template <class Src>
 static void *phase_kernel(const Shapes &sh, int p, int *block)
