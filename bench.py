@@ -219,6 +219,8 @@ def serving_sweep(duration_s, per_frame_rates, batched_rates, check_frames=24):
     batched run whose first `check_frames` served frames are copied as their
     batches end (while other batches are in flight) and compared bit for bit
     with the same frames served alone through the single-frame calls."""
+    import numpy as np
+
     from paper_2509_10757_amd import serve
     from synth.serving import make_streams
     log("generating the 32-stream serving workload")
@@ -227,22 +229,7 @@ def serving_sweep(duration_s, per_frame_rates, batched_rates, check_frames=24):
     for s in streams:
         ex.admit(s["id"])
     log("serving shapes", ex.autotune())
-    rows = []
-    for mode, rates in (("per_frame", per_frame_rates), ("batched", batched_rates)):
-        for a in rates:
-            r = serve.serve(streams, duration_s, speedup=a, mode=mode, executor=ex)
-            log(mode, a, {k: round(v, 3) if isinstance(v, float) else v for k, v in r.items()
-                          if k in ("frames_per_s", "p50_ms", "p99_ms", "offered_fps", "mean_batch", "max_overlap")})
-            rows.append({k: r[k] for k in ("mode", "speedup", "offered_fps", "frames_per_s",
-                                           "p50_ms", "p99_ms", "mean_batch", "max_overlap", "failed")})
-            if r["frames_per_s"] < 0.9 * r["offered_fps"]:
-                break
-    pf = [r for r in rows if r["mode"] == "per_frame" and r["frames_per_s"] >= 0.95 * r["offered_fps"]]
-    knee = max(pf, key=lambda r: r["offered_fps"]) if pf else min(
-        (r for r in rows if r["mode"] == "per_frame"), key=lambda r: r["offered_fps"])
-    bound = knee["p99_ms"]
-    ok = [r for r in rows if r["mode"] == "batched" and r["p99_ms"] <= bound]
-    best = max(ok, key=lambda r: r["frames_per_s"]) if ok else None
+    rows, bound, knee, best = _sweep_modes(serve, ex, streams, duration_s, per_frame_rates, batched_rates)
 
     # served results (copied before the slots are reused) against the same
     # frames served alone
@@ -273,13 +260,56 @@ def serving_sweep(duration_s, per_frame_rates, batched_rates, check_frames=24):
                            len(f["search"]), sync=False)
         ex.release(h)
         bad += not same_results(got, alone)
-    return {"streams": len(streams), "duration_s": duration_s, "runs": rows,
-            "p99_bound_ms": round(bound, 3), "per_frame_fps_at_bound": round(knee["frames_per_s"], 1),
+    out = {"streams": len(streams), "duration_s": duration_s, "runs": rows,
+           **_at_bound(bound, knee, best),
+           "served_frames_checked_against_alone": min(len(captured), check_frames),
+           "served_frames_mismatching": bad}
+    del ex
+
+    # the same streams with 5 % of every local map replaced before each frame
+    # (maps edited in place on the device, frames of a stream served in order)
+    log("generating the 32-stream serving workload with 5% map churn per frame")
+    cstreams = make_streams(map_churn=0.05)
+    cex = serve.DeviceExecutor(cstreams, max_batch=64, max_inflight=4)
+    for s in cstreams:
+        cex.admit(s["id"])
+    cex.autotune()
+    crows, cbound, cknee, cbest = _sweep_modes(serve, cex, cstreams, duration_s, per_frame_rates,
+                                               [4, 8, 12, 16, 24, 32, 48])
+    out["map_churn"] = {"fraction_per_frame": 0.05, "runs": crows, **_at_bound(cbound, cknee, cbest),
+                        "points_replaced_per_frame_mean": round(float(np.mean([len(s["edits"][1]["remove_ids"])
+                                                                               for s in cstreams])), 1)}
+    return out
+
+
+def _sweep_modes(serve, ex, streams, duration_s, per_frame_rates, batched_rates):
+    """Per-frame and batched runs over rising rates; each mode stops after the
+    first rate it cannot keep up with.  Returns (rows, p99 bound, per-frame
+    knee row, best batched row within the bound)."""
+    rows = []
+    for mode, rates in (("per_frame", per_frame_rates), ("batched", batched_rates)):
+        for a in rates:
+            r = serve.serve(streams, duration_s, speedup=a, mode=mode, executor=ex)
+            log(mode, a, {k: round(v, 3) if isinstance(v, float) else v for k, v in r.items()
+                          if k in ("frames_per_s", "p50_ms", "p99_ms", "offered_fps", "mean_batch", "max_overlap")})
+            rows.append({k: r[k] for k in ("mode", "speedup", "offered_fps", "frames_per_s",
+                                           "p50_ms", "p99_ms", "mean_batch", "max_overlap", "failed")})
+            if r["frames_per_s"] < 0.9 * r["offered_fps"]:
+                break
+    pf = [r for r in rows if r["mode"] == "per_frame" and r["frames_per_s"] >= 0.95 * r["offered_fps"]]
+    knee = max(pf, key=lambda r: r["offered_fps"]) if pf else min(
+        (r for r in rows if r["mode"] == "per_frame"), key=lambda r: r["offered_fps"])
+    bound = knee["p99_ms"]
+    ok = [r for r in rows if r["mode"] == "batched" and r["p99_ms"] <= bound]
+    best = max(ok, key=lambda r: r["frames_per_s"]) if ok else None
+    return rows, bound, knee, best
+
+
+def _at_bound(bound, knee, best):
+    return {"p99_bound_ms": round(bound, 3), "per_frame_fps_at_bound": round(knee["frames_per_s"], 1),
             "batched_fps_at_bound": round(best["frames_per_s"], 1) if best else None,
             "batched_over_per_frame_at_equal_p99": (round(best["frames_per_s"] / knee["frames_per_s"], 2)
-                                                    if best and knee["frames_per_s"] > 0 else None),
-            "served_frames_checked_against_alone": min(len(captured), check_frames),
-            "served_frames_mismatching": bad}
+                                                    if best and knee["frames_per_s"] > 0 else None)}
 
 
 # --------------------------------------------------------------- helpers ----
@@ -649,53 +679,64 @@ def main():
                 log("last frame", key, last_frame[key])
 
     # ---- local-map maintenance on the device: a 20000-point map edited per
-    # frame (5% of its points replaced: removal list and the new points'
-    # upload included) against uploading the whole map again
+    # frame (5% of its points replaced; the kernels read the removal pairs and
+    # the inserted points from pinned host memory) against uploading the whole
+    # map again (one gather copy of its five arrays from pinned memory)
     map_maint = None
     if not args.no_extra:
+        import ctypes as ct
         mf = synth.clustered_search_20000()[0]["map"]
         n_map, n_edit, cap = len(mf["dmin"]), 1000, 24000
         dmap = ft.DeviceMap(mf, cap)
         rng = np.random.default_rng(5)
         newp = synth.clustered_search_20000(seed=synth.seed_of(77))[0]["map"]
-        pinned = {k: torch.from_numpy(np.ascontiguousarray(v[:n_edit])).pin_memory() for k, v in newp.items()}
-        dev_ins = {k: torch.empty(v.shape, dtype=v.dtype, device="cuda") for k, v in pinned.items()}
-        ins = ft.ft_map_points(n_edit, *(ft._ptr(dev_ins[k]) for k in ("pos", "normal", "dmin", "dmax", "desc")))
-        whole = {k: torch.from_numpy(np.ascontiguousarray(v)).pin_memory() for k, v in mf.items()}
-        whole_dev = {k: torch.empty(v.shape, dtype=v.dtype, device="cuda") for k, v in whole.items()}
+        keys = ("pos", "normal", "dmin", "dmax", "desc")
+
+        def pinned_block(arrays):
+            sizes = [-(-a.nbytes // 256) * 256 for a in arrays]
+            base = ctx.ft_host_alloc(sum(sizes))
+            view = np.ctypeslib.as_array((ct.c_uint8 * sum(sizes)).from_address(base))
+            addrs, at = [], 0
+            for a, sz in zip(arrays, sizes):
+                view[at:at + a.nbytes] = np.ascontiguousarray(a).view(np.uint8).reshape(-1)
+                addrs.append(base + at)
+                at += sz
+            return base, addrs
+        ins_base, ins_addr = pinned_block([newp[k][:n_edit] for k in keys])
+        ins = ft.ft_map_points(n_edit, *ins_addr)
+        whole_base, whole_addr = pinned_block([mf[k] for k in keys])
+        whole_dev = {k: torch.empty(v.shape, dtype=torch.from_numpy(v[:1]).dtype, device="cuda") for k, v in mf.items()}
+        segs = np.array([(whole_addr[i], whole_dev[k].data_ptr(), mf[k].nbytes) for i, k in enumerate(keys)],
+                        dtype=np.int64)
         reps = max(200, args.steps)
+        # removal lists drawn beforehand (the map size stays n_map)
+        removals = [np.ascontiguousarray(rng.choice(n_map, n_edit, replace=False), dtype=np.int32)
+                    for _ in range(reps + 10)]
 
-        def edit_once():
-            with torch.cuda.stream(stream):
-                for k in dev_ins:
-                    dev_ins[k].copy_(pinned[k], non_blocking=True)
-            remove = rng.choice(dmap.n, n_edit, replace=False)
-            ctx.ft_map_update(dmap.struct, cap, remove, ins, stream=stream)
-
-        for _ in range(10):
-            edit_once()
+        for k in range(10):
+            ctx.ft_map_update(dmap.struct, cap, removals[reps + k], ins, stream=stream)
+            ctx.ft_upload(segs, stream)
         torch.cuda.synchronize()
-        te = []
-        for _ in range(reps):
+        te, tw = [], []
+        for k in range(reps):
             s0 = time.perf_counter()
-            edit_once()
+            ctx.ft_map_update(dmap.struct, cap, removals[k], ins, stream=stream)
             stream.synchronize()
             te.append((time.perf_counter() - s0) * 1e3)
-        tw = []
         for _ in range(reps):
             s0 = time.perf_counter()
-            with torch.cuda.stream(stream):
-                for k in whole_dev:
-                    whole_dev[k].copy_(whole[k], non_blocking=True)
+            ctx.ft_upload(segs, stream)
             stream.synchronize()
             tw.append((time.perf_counter() - s0) * 1e3)
         map_maint = {"workload": f"{n_map}-point local map, {n_edit} points removed and {n_edit} inserted per edit",
                      "edit_ms": percentiles(te), "whole_map_upload_ms": percentiles(tw),
                      "bytes_per_point": 64, "reps": reps,
-                     "timed": "host clock around each edit (upload of the inserted points, removal list, "
-                              "both kernels) and each whole-map upload, synchronized"}
+                     "timed": "host clock around each edit (removal list, both kernels, inserted points read "
+                              "from pinned memory) and each whole-map upload (one gather copy), synchronized"}
         log("map maintenance", map_maint)
-        del dmap, dev_ins, whole_dev
+        del dmap, whole_dev
+        ctx.ft_host_free(ins_base)
+        ctx.ft_host_free(whole_base)
 
     serving = None
     if args.serving > 0:

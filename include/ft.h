@@ -354,7 +354,9 @@ ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_poin
 typedef struct ft_map_edit {
     int32_t n_remove;
     const int32_t *remove;     /* HOST [n_remove] indices into the current map: distinct, each < map->n */
-    ft_map_points insert;      /* DEVICE arrays of the insert.n points to append (a map's layout) */
+    ft_map_points insert;      /* arrays of the insert.n points to append (a map's layout): DEVICE
+                                  memory, or HOST memory inside ft_host_alloc blocks (all five), which
+                                  the append kernel reads over the bus: no copy command */
 } ft_map_edit;
 
 /* Edits a device-resident map in place.  The listed points leave the map;
@@ -364,9 +366,12 @@ typedef struct ft_map_edit {
  * the call moves 64 B per removed slot below n1 plus 64 B per inserted point.
  * `map` holds device arrays with room for `capacity` points; map->n (host) is
  * set to n1 + insert.n when the call returns, while the moves run on `stream`
- * (the map must not be read on another stream before they complete).
- * Errors: a repeated or out-of-range index, null or misaligned arrays:
- * FT_ERR_INVALID_ARGUMENT; a result above `capacity`, or n_remove or
+ * (the map must not be read on another stream before they complete; host
+ * insert arrays must stay unchanged until then).  The (slot, source) pairs
+ * are read by the move kernel from the context's pinned staging, so an edit
+ * enqueues two kernels and no copy.
+ * Errors: a repeated or out-of-range index, null or misaligned arrays, host
+ * insert arrays partly outside the ft_host_alloc blocks: FT_ERR_INVALID_ARGUMENT; a result above `capacity`, or n_remove or
  * insert.n above max_map_points: FT_ERR_CAPACITY.  On error map->n is
  * unchanged and nothing is enqueued. */
 ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -101,14 +102,18 @@ struct ft_context {
     double phase_ms[kPhases] = {};
     int64_t phase_n[kPhases] = {};
     std::vector<std::pair<char *, size_t>> host_blocks;   // ft_host_alloc blocks (upload sources)
-    // map edits: (hole, source) pairs staged in pinned memory and copied to the
-    // device, one slot per edit in flight (a slot is reused after its event)
-    static constexpr int kEditSlots = 4;
-    int32_t *d_edit[kEditSlots] = {};
-    int32_t *h_edit[kEditSlots] = {};
-    hipEvent_t edit_ev[kEditSlots] = {};
-    bool edit_used[kEditSlots] = {};
-    int edit_next = 0;
+    // map edits: (hole, source) pairs written to a pinned ring that the move
+    // kernel reads over the bus; an edit's chunk is reclaimed once the event
+    // recorded after its kernels has completed (oldest first)
+    struct EditChunk {
+        size_t off, bytes;
+        hipEvent_t ev;
+    };
+    static constexpr int kEditEvents = 64;
+    char *edit_ring = nullptr;
+    size_t edit_ring_bytes = 0, edit_head = 0;
+    std::deque<EditChunk> edit_live;
+    std::vector<hipEvent_t> edit_free_ev, edit_all_ev;
 };
 
 namespace {
@@ -953,7 +958,7 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     const size_t slot_bytes = align_up(b.off, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
     const size_t edit_bytes = align_up(sizeof(int32_t) * 2 * (size_t)lim->max_map_points, 256);
-    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight + edit_bytes * ft_context::kEditSlots;
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -965,14 +970,19 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         off += slot_bytes;
     };
     carve_at(ctx->direct);
-    for (int k = 0; k < ft_context::kEditSlots; ++k) {
-        ctx->d_edit[k] = reinterpret_cast<int32_t *>(ctx->base + off);
-        off += edit_bytes;
-        if (hipHostMalloc((void **)&ctx->h_edit[k], edit_bytes, hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&ctx->edit_ev[k], hipEventDisableTiming) != hipSuccess) {
+    ctx->edit_ring_bytes = std::max<size_t>(2 * edit_bytes, (size_t)1 << 20);
+    if (hipHostMalloc((void **)&ctx->edit_ring, ctx->edit_ring_bytes, hipHostMallocDefault) != hipSuccess) {
+        ft_context_destroy(ctx);
+        return FT_ERR_DEVICE;
+    }
+    for (int k = 0; k < ft_context::kEditEvents; ++k) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
             ft_context_destroy(ctx);
             return FT_ERR_DEVICE;
         }
+        ctx->edit_all_ev.push_back(e);
+        ctx->edit_free_ev.push_back(e);
     }
     ctx->lanes.resize(lim->max_inflight);
     for (auto &ln : ctx->lanes) {
@@ -1027,13 +1037,9 @@ ft_status ft_context_destroy(ft_context *ctx)
         release_graph(ln.g);
         if (ln.h_table) hipHostFree(ln.h_table);
     }
-    for (int k = 0; k < ft_context::kEditSlots; ++k) {
-        if (ctx->edit_ev[k]) {
-            hipEventSynchronize(ctx->edit_ev[k]);
-            hipEventDestroy(ctx->edit_ev[k]);
-        }
-        if (ctx->h_edit[k]) hipHostFree(ctx->h_edit[k]);
-    }
+    for (auto &c : ctx->edit_live) hipEventSynchronize(c.ev);
+    for (hipEvent_t e : ctx->edit_all_ev) hipEventDestroy(e);
+    if (ctx->edit_ring) hipHostFree(ctx->edit_ring);
     if (ctx->base || !ctx->host_blocks.empty()) hipDeviceSynchronize();
     for (auto &hb : ctx->host_blocks) hipHostFree(hb.first);
     if (ctx->base) hipFree(ctx->base);
@@ -1348,6 +1354,27 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null or misaligned map array");
     if (m > 0 && !arrays_ok(edit->insert))
         return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null or misaligned insert array");
+    if (m > 0) {
+        // host insert arrays: every one wholly inside an ft_host_alloc block
+        const ft_map_points &q = edit->insert;
+        const void *ptr[5] = {q.pos, q.normal, q.dmin, q.dmax, q.desc};
+        const size_t len[5] = {12 * (size_t)m, 12 * (size_t)m, 4 * (size_t)m, 4 * (size_t)m, 32 * (size_t)m};
+        int in_host = 0, touches = 0;
+        for (int f = 0; f < 5; ++f) {
+            const uintptr_t p0 = (uintptr_t)ptr[f];
+            for (const auto &hb : ctx->host_blocks) {
+                const uintptr_t b0 = (uintptr_t)hb.first;
+                if (p0 >= b0 && p0 - b0 < hb.second) {
+                    ++touches;
+                    if (len[f] <= hb.second - (p0 - b0)) ++in_host;
+                    break;
+                }
+            }
+        }
+        if (touches != 0 && (touches != 5 || in_host != 5))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT,
+                        "map update: host insert arrays must all lie wholly inside ft_host_alloc blocks");
+    }
     std::vector<int32_t> rem(edit->remove, edit->remove + nr);
     std::sort(rem.begin(), rem.end());
     for (int i = 0; i < nr; ++i) {
@@ -1360,11 +1387,28 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
     if ((int64_t)n1 + m > capacity)
         return fail(ctx, FT_ERR_CAPACITY, "map update: %d points exceed the capacity %d", n1 + m, capacity);
     // (hole, source) pairs: removed slots below n1 and surviving points from n1 up, both ascending
-    const int slot = ctx->edit_next;
-    ctx->edit_next = (slot + 1) % ft_context::kEditSlots;
-    if (ctx->edit_used[slot]) HIP_TRY(ctx, hipEventSynchronize(ctx->edit_ev[slot]));
-    int32_t *pairs = ctx->h_edit[slot];
     const int n_holes = (int)(std::lower_bound(rem.begin(), rem.end(), n1) - rem.begin());
+    // a chunk of the pinned ring for the pairs: completed chunks are reclaimed
+    // first; a chunk the new one would overlap (or the oldest, when every
+    // event is in use) is waited for
+    auto &live = ctx->edit_live;
+    auto pop_front = [&](bool wait) -> hipError_t {
+        hipError_t e = wait ? hipEventSynchronize(live.front().ev) : hipSuccess;
+        ctx->edit_free_ev.push_back(live.front().ev);
+        live.pop_front();
+        return e;
+    };
+    while (!live.empty() && hipEventQuery(live.front().ev) == hipSuccess) pop_front(false);
+    const size_t need = align_up(sizeof(int32_t) * 2 * (size_t)std::max(n_holes, 1), 256);
+    size_t off = ctx->edit_head + need <= ctx->edit_ring_bytes ? ctx->edit_head : 0;
+    auto overlaps = [&]() {
+        for (const auto &c : live)
+            if (off < c.off + c.bytes && c.off < off + need) return true;
+        return false;
+    };
+    while (!live.empty() && (overlaps() || ctx->edit_free_ev.empty())) HIP_TRY(ctx, pop_front(true));
+    ctx->edit_head = off + need;
+    int32_t *pairs = reinterpret_cast<int32_t *>(ctx->edit_ring + off);
     int src = n1;
     size_t tail = (size_t)n_holes;   // removed indices at or above n1 (ascending)
     for (int h = 0; h < n_holes; ++h) {
@@ -1376,16 +1420,13 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
         pairs[2 * h + 1] = src++;
     }
     hipStream_t s = (hipStream_t)stream;
-    if (n_holes > 0)
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->d_edit[slot], pairs, sizeof(int32_t) * 2 * (size_t)n_holes,
-                                    hipMemcpyHostToDevice, s));
     MapEditArgs a{};
     a.pos = const_cast<float *>(map->pos);
     a.normal = const_cast<float *>(map->normal);
     a.dmin = const_cast<float *>(map->dmin);
     a.dmax = const_cast<float *>(map->dmax);
     a.desc = const_cast<uint8_t *>(map->desc);
-    a.pairs = ctx->d_edit[slot];
+    a.pairs = pairs;                  // pinned staging, read by the move kernel over the bus
     a.n_pairs = n_holes;
     a.ipos = edit->insert.pos;
     a.inormal = edit->insert.normal;
@@ -1395,8 +1436,10 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
     a.n1 = n1;
     a.n_insert = m;
     HIP_TRY(ctx, launch_map_edit(a, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->edit_ev[slot], s));
-    ctx->edit_used[slot] = true;
+    hipEvent_t ev = ctx->edit_free_ev.back();
+    HIP_TRY(ctx, hipEventRecord(ev, s));
+    ctx->edit_free_ev.pop_back();
+    live.push_back({off, need, ev});
     map->n = n1 + m;
     return FT_OK;
 }

@@ -28,6 +28,13 @@ stay withheld until the executor reports its work ended; if that does not
 happen within another `timeout_s`, the loop stops with an error rather than
 hand the slots to new frames.  A removed stream's map stays resident until
 its last in-flight batch has ended.
+
+Streams whose local map changes from frame to frame (Update Local Map's
+output, Section II-D) are served sequentially, as tracking runs: with
+`sequential=True` a batch takes, in FIFO order, at most one frame per stream
+and no frame of a stream that still has a frame in flight, so the executor
+can edit the stream's device map in place (ft_map_update, on the batch's HIP
+stream, before the batch) with no batch reading it meanwhile.
 """
 from __future__ import annotations
 
@@ -83,8 +90,10 @@ class Scheduler:
     """Stream registry, admission, FIFO coalescing and latency accounting."""
 
     def __init__(self, executor, hbm_budget: int, max_batch: int = 64, max_inflight: int = 4,
-                 mode: str = "batched", clock=time.perf_counter, timeout_s: float = 10.0):
+                 mode: str = "batched", clock=time.perf_counter, timeout_s: float = 10.0,
+                 sequential: bool = False):
         assert mode in ("batched", "per_frame")
+        self.sequential = sequential
         self.ex = executor
         self.budget = hbm_budget
         self.used = 0
@@ -193,7 +202,20 @@ class Scheduler:
         n = min(self.max_batch, len(self.pending), self.ex.free_slots())
         if n <= 0:
             return False
-        frames = [self.pending.popleft() for _ in range(n)]
+        if self.sequential:
+            busy = {f.stream for _, fr, _ in self.inflight + self.quarantine for f in fr}
+            frames, kept = [], collections.deque()
+            for f in self.pending:
+                if len(frames) < n and f.stream not in busy:
+                    frames.append(f)
+                    busy.add(f.stream)
+                else:
+                    kept.append(f)
+            if not frames:
+                return False
+            self.pending = kept
+        else:
+            frames = [self.pending.popleft() for _ in range(n)]
         try:
             h = self.ex.launch(frames, per_frame=self.mode == "per_frame")
         except Exception:
@@ -229,6 +251,25 @@ class Scheduler:
 # --------------------------------------------------------------------------
 # Device executor
 # --------------------------------------------------------------------------
+def follow_edit(ids, slot_of, rem, insert_ids):
+    """The host's record of which point each map slot holds, carried through
+    one ft_map_update: `ids[slot]` is a point id, `slot_of[id]` its slot (-1:
+    not in the map), `rem` the sorted removed slots.  Removed slots below the
+    new count take the surviving tail points in ascending order, inserted
+    points are appended.  Updates `slot_of` in place and returns the new ids."""
+    ids = np.asarray(ids, dtype=np.int64).copy()
+    rem = np.asarray(rem, dtype=np.int64)
+    n1 = len(ids) - len(rem)
+    holes = rem[rem < n1]
+    tail = np.ones(len(ids) - n1, dtype=bool)
+    tail[rem[rem >= n1] - n1] = False
+    src = n1 + np.nonzero(tail)[0]
+    slot_of[ids[rem]] = -1
+    ids[holes] = ids[src]
+    ids = np.concatenate([ids[:n1], np.asarray(insert_ids, dtype=np.int64)])
+    slot_of[ids] = np.arange(len(ids))
+    return ids
+
 def _carve(sizes):
     """Offsets of consecutive 256-byte aligned parts; returns (offsets, total)."""
     off, out = 0, {}
@@ -261,7 +302,18 @@ class DeviceExecutor:
     producer would write it.  A launch uploads its frames with one gather
     copy (ft_upload) and submits job descriptors patched from per-frame
     templates: a template is built once per pooled frame for slot 0, and the
-    words that hold slot addresses are shifted by the slot's offset."""
+    words that hold slot addresses are shifted by the slot's offset.
+
+    A stream with per-frame map edits ("edits", point ids) holds its map in
+    device arrays of its map size; before a frame of sequence number k is
+    launched, the edits of sequence numbers since the map's last frame up to
+    k are applied in order on the batch's HIP stream by ft_map_update, which
+    reads the inserted points from the stream's pinned host block (packed
+    once at admission, as a local-map producer would write them): no copy
+    command per edit.  Removed points are found by slot through
+    the executor's record of which point each slot holds, kept by the edit
+    rule ft.h states (removed slots below the new count take the surviving
+    tail points in ascending order; inserted points are appended)."""
 
     def __init__(self, streams, max_batch: int = 64, max_inflight: int = 4, max_kp: int = 4096,
                  device: str = "cuda"):
@@ -272,6 +324,8 @@ class DeviceExecutor:
         self.streams = {s["id"]: s for s in streams}
         self.max_batch, self.max_inflight = max_batch, max_inflight
         n_map = max(max(s["n_map"] for s in streams), 1)
+        self.slot_ids, self.slot_of, self.map_seq, self.map_struct, self.ins_block, self.ins_pts = \
+            {}, {}, {}, {}, {}, {}
         self.ctx = ft.Context(ft.default_limits(max_kp_per_image=max_kp, max_map_points=n_map,
                                                 max_batch_frames=max_batch, max_inflight=max_inflight))
         self.hip_streams = [torch.cuda.Stream(device=device) for _ in range(max_inflight)]
@@ -323,8 +377,21 @@ class DeviceExecutor:
             return
         torch = self.torch
         s = self.streams[sid]
-        mp = s["frames"][0]["map"]
+        if "edits" in s:
+            ids0 = np.asarray(s["map_ids0"], dtype=np.int64)
+            mp = {k: v[ids0] for k, v in s["points"].items()}
+            self.slot_ids[sid] = ids0.copy()
+            self.slot_of[sid] = np.full(len(s["points"]["dmin"]), -1, dtype=np.int64)
+            self.slot_of[sid][ids0] = np.arange(len(ids0))
+            self.map_seq[sid] = 0
+            self._pack_inserts(sid)
+        else:
+            mp = s["frames"][0]["map"]
         self.maps[sid] = {k: torch.from_numpy(np.ascontiguousarray(v)).to(self.device) for k, v in mp.items()}
+        m = self.maps[sid]
+        self.map_struct[sid] = self.ft.ft_map_points(len(mp["dmin"]), m["pos"].data_ptr(), m["normal"].data_ptr(),
+                                                     m["dmin"].data_ptr(), m["dmax"].data_ptr(),
+                                                     m["desc"].data_ptr())
         for key, p in self._pyramids(sid).items():
             self.pyr[key] = torch.from_numpy(p["data"]).to(self.device)
         for q, f in enumerate(s["frames"]):
@@ -336,6 +403,10 @@ class DeviceExecutor:
         """Frees what the stream holds on the device (exactly what footprint
         counts); the scheduler calls it once no batch in flight reads it."""
         self.maps.pop(sid, None)
+        for d in (self.slot_ids, self.slot_of, self.map_seq, self.map_struct, self.ins_pts):
+            d.pop(sid, None)
+        if sid in self.ins_block:
+            self.ctx.ft_host_free(self.ins_block.pop(sid))
         for k in [k for k in self.tmpl if k[0] == sid]:
             del self.tmpl[k]
         for k in [k for k in self.pyr if k[0] == sid]:
@@ -359,6 +430,63 @@ class DeviceExecutor:
         """Device bytes held for admitted streams (maps and pyramids)."""
         return (sum(t.numel() * t.element_size() for m in self.maps.values() for t in m.values()) +
                 sum(t.numel() for t in self.pyr.values()))
+
+    def _pack_inserts(self, sid):
+        """Every edit's inserted points, packed into one pinned host block of
+        the context (five 256-byte aligned arrays per edit)."""
+        s = self.streams[sid]
+        fields = (("pos", 12), ("normal", 12), ("dmin", 4), ("dmax", 4), ("desc", 32))
+        sizes = [sum(-(-w * len(e["insert_ids"]) // 256) * 256 for _, w in fields) if e is not None else 0
+                 for e in s["edits"]]
+        total = max(sum(sizes), 256)
+        base = self.ctx.ft_host_alloc(total)
+        self.ins_block[sid] = base
+        view = np.ctypeslib.as_array((ct.c_uint8 * total).from_address(base))
+        pts, at = [], 0
+        for e in s["edits"]:
+            m = 0 if e is None else len(e["insert_ids"])
+            if not m:
+                pts.append(None)
+                continue
+            addr = {}
+            for key, w in fields:
+                b = np.ascontiguousarray(s["points"][key][e["insert_ids"]]).view(np.uint8).reshape(-1)
+                view[at:at + b.size] = b
+                addr[key] = base + at
+                at += -(-w * m // 256) * 256
+            pts.append(self.ft.ft_map_points(m, addr["pos"], addr["normal"], addr["dmin"], addr["dmax"],
+                                             addr["desc"]))
+        self.ins_pts[sid] = pts
+
+    def reset_map(self, sid):
+        """Upload a stream's first map again (a new run's sequence numbers
+        start at 0); the device is synchronised first."""
+        s = self.streams[sid]
+        self.torch.cuda.synchronize()
+        ids0 = np.asarray(s["map_ids0"], dtype=np.int64)
+        for k, t in self.maps[sid].items():
+            t[:len(ids0)].copy_(self.torch.from_numpy(np.ascontiguousarray(s["points"][k][ids0])))
+        self.slot_ids[sid] = ids0.copy()
+        self.slot_of[sid][:] = -1
+        self.slot_of[sid][ids0] = np.arange(len(ids0))
+        self.map_struct[sid].n = len(ids0)
+        self.map_seq[sid] = 0
+
+    def _edit_map(self, sid, seq, hs):
+        """Bring the stream's device map from its last frame's map to frame
+        `seq`'s, on HIP stream `hs`."""
+        s = self.streams[sid]
+        n_pool = len(s["frames"])
+        for k in range(self.map_seq[sid] + 1, seq + 1):
+            q = k % n_pool
+            e = s["edits"][q]
+            ids, slot_of = self.slot_ids[sid], self.slot_of[sid]
+            rem = np.sort(slot_of[e["remove_ids"]])
+            assert len(rem) == 0 or rem[0] >= 0, "removed point not in the map"
+            self.ctx.ft_map_update(self.map_struct[sid], self.maps[sid]["dmin"].numel(), rem.astype(np.int32),
+                                   self.ins_pts[sid][q], stream=hs)
+            self.slot_ids[sid] = follow_edit(ids, slot_of, rem, e["insert_ids"])
+        self.map_seq[sid] = max(self.map_seq[sid], seq)
 
     def _pack(self, f, at):
         L, R = f["left"], f["right"]
@@ -434,9 +562,7 @@ class DeviceExecutor:
             j.fisheye_out = ft.ft_fisheye_out(o["right_idx"].data_ptr(), o["dist"].data_ptr(),
                                               o["depth"].data_ptr(), o["xyz"].data_ptr(),
                                               o["n_stereo"].data_ptr())
-        m = self.maps[sid]
-        j.map = ft.ft_map_points(len(f["map"]["dmin"]), m["pos"].data_ptr(), m["normal"].data_ptr(),
-                                 m["dmin"].data_ptr(), m["dmax"].data_ptr(), m["desc"].data_ptr())
+        j.map = ft.ft_map_points.from_buffer_copy(bytes(self.map_struct[sid]))
         j.search_params = ft.search_params_struct(f["search_params"])
         j.n_views = len(f["search"])
         for v, spec in enumerate(f["search"]):
@@ -474,11 +600,21 @@ class DeviceExecutor:
         lane = 0 if per_frame else self.next_h % self.max_inflight
         hs = self.hip_streams[lane]
         n = len(frames)
+        for fr in frames:
+            if fr.stream in self.map_seq:
+                assert fr.seq >= self.map_seq[fr.stream], "frames of an edited map arrive in order"
+                self._edit_map(fr.stream, fr.seq, hs)
         slots = [self.free.pop() for _ in range(n)]
         keys = [(fr.stream, fr.seq % len(self.streams[fr.stream]["frames"])) for fr in frames]
         t = [self.tmpl[k] for k in keys]
         shift = np.array(slots, dtype=np.uint64) * np.uint64(self.slot_bytes)
         jobs = np.stack([w for w, _, _ in t]) + np.stack([m for _, m, _ in t]) * shift[:, None]
+        if self.map_seq:
+            n_word = jobs.view(np.int32)
+            at = self.ft.ft_frame_job.map.offset // 4    # ft_map_points.n: the map's current size
+            for i, fr in enumerate(frames):
+                if fr.stream in self.map_struct and fr.stream in self.map_seq:
+                    n_word[i, at] = self.map_struct[fr.stream].n
         segs = np.empty((n, 3), dtype=np.int64)
         segs[:, 0] = [self.arena + self.arena_off[k] for k in keys]
         segs[:, 1] = self.dev_base + np.array(slots, dtype=np.int64) * self.slot_bytes
@@ -548,9 +684,11 @@ def serve(streams, duration_s: float, speedup: float = 1.0, mode: str = "batched
     """Serve Poisson arrivals of every stream for `duration_s` seconds."""
     from synth.serving import poisson_arrivals
     ex = executor or DeviceExecutor(streams, max_batch=max_batch, max_inflight=max_inflight)
-    sch = Scheduler(ex, hbm_budget, max_batch=max_batch, max_inflight=max_inflight, mode=mode)
+    sch = Scheduler(ex, hbm_budget, max_batch=max_batch, max_inflight=max_inflight, mode=mode,
+                    sequential=any("edits" in s for s in streams))
     for s in streams:
-        sch.register_stream(s["id"], ex.footprint(s["id"]))
+        if sch.register_stream(s["id"], ex.footprint(s["id"])) and s["id"] in getattr(ex, "map_seq", {}):
+            ex.reset_map(s["id"])
     arr = poisson_arrivals(np.random.default_rng(seed), streams, duration_s, speedup)
     arr = [a for a in arr if a[1] in sch.streams] + [a for a in arr if a[1] not in sch.streams]
     arr.sort()

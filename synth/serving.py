@@ -10,6 +10,14 @@ per-stream rate of 20-30 Hz.  Frames are pre-generated into a small pool per
 stream (keypoints are projections of visible map points plus 20% distractors)
 and cycled; pinhole image pyramids come from a shared pool, since image content
 does not change the amount of work.
+
+With `map_churn` > 0 a stream's local map changes from frame to frame, as
+Update Local Map's output does while the camera moves: before pooled frame q
+(q >= 1) a fraction `map_churn` of the map's points leave it and as many
+points, not yet in it, join; before the pool starts over, the map returns to
+the set it started from.  Edits are given as point ids of the stream's point
+table (which slot a point occupies is up to the consumer), and each frame's
+keypoints are generated from the points of its own map.
 """
 from __future__ import annotations
 
@@ -159,11 +167,32 @@ def _fisheye_frame_kps(rng, mp, P, camL, camR, R_rl, t_rl, R, t, O, n_kp, sc):
     return C.permute_keypoints(left, rng.permutation(n_kp)), C.permute_keypoints(right, rng.permutation(n_kp))
 
 
+def _churn(rng, n_map: int, n_frames: int, k: int):
+    """Point-id sets of a map that loses k random points and gains k new ones
+    before every frame after the first: (sets, edits), where edits[q] turns
+    set q-1 into set q and edits[0] turns the last set back into the first."""
+    sets = [np.arange(n_map)]
+    edits = [None]
+    nxt = n_map
+    for _ in range(1, n_frames):
+        rem = np.sort(rng.choice(sets[-1], k, replace=False))
+        ins = np.arange(nxt, nxt + k)
+        nxt += k
+        sets.append(np.sort(np.concatenate([np.setdiff1d(sets[-1], rem), ins])))
+        edits.append({"remove_ids": rem, "insert_ids": ins})
+    edits[0] = {"remove_ids": np.setdiff1d(sets[-1], sets[0]), "insert_ids": np.setdiff1d(sets[0], sets[-1])}
+    return sets, edits
+
+
 def make_streams(seed=None, n_streams: int = 32, frames_per_stream: int = 8,
                  world_points: int = 2_000_000, map_range=(2000, 40000), kp_range=(800, 2000),
-                 pyramid_pool: int = 4, rate_range=(20.0, 30.0)):
-    """Streams, each with a resident map and a pool of frames (synth frame dicts
-    that share the stream's map arrays)."""
+                 pyramid_pool: int = 4, rate_range=(20.0, 30.0), map_churn: float = 0.0):
+    """Streams, each with a resident map and a pool of frames (synth frame
+    dicts).  Without churn every frame shares the stream's map arrays; with
+    churn a stream also carries its point table ("points"), the ids of its
+    first map ("map_ids0", the order it is uploaded in) and the per-frame
+    edits ("edits"), and frame q's "map" holds the points of its map in id
+    order (the set, not a slot order)."""
     ss = seed if seed is not None else np.random.SeedSequence(C.MASTER_SEED + 5)
     ctl, wss, pss, *stream_ss = ss.spawn(3 + n_streams)
     rng = np.random.default_rng(ctl)
@@ -185,7 +214,12 @@ def make_streams(seed=None, n_streams: int = 32, frames_per_stream: int = 8,
         rate = r.uniform(*rate_range)
         n_map = int(r.integers(map_range[0], map_range[1] + 1))
         n_kp = int(r.integers(kp_range[0], kp_range[1] + 1))
-        mp, P, _ = _stream_map(r, world, traj.position(0.0), n_map, sc)
+        k_churn = int(round(map_churn * n_map)) if frames_per_stream > 1 else 0
+        table, P_all, _ = _stream_map(r, world, traj.position(0.0), n_map + k_churn * (frames_per_stream - 1), sc)
+        if k_churn:
+            id_sets, edits = _churn(r, n_map, frames_per_stream, k_churn)
+        else:
+            id_sets, edits = [np.arange(n_map)] * frames_per_stream, None
         frames = []
         if kinds[s] == "fisheye":
             camL, camR = kb_camera(r), kb_camera(r)
@@ -193,6 +227,11 @@ def make_streams(seed=None, n_streams: int = 32, frames_per_stream: int = 8,
             t_lr = np.array([0.10, 0.0, 0.0])
             R_rl, t_rl = R_lr.T, -R_lr.T @ t_lr
         for f in range(frames_per_stream):
+            if edits is None:
+                mp, P = table, P_all
+            else:
+                mp = {key: v[id_sets[f]] for key, v in table.items()}
+                P = P_all[id_sets[f]]
             tt = f / rate
             R, t, O = traj.pose(tt)
             Rs, ts, Os = C.perturbed_pose(r, R, t)
@@ -240,8 +279,11 @@ def make_streams(seed=None, n_streams: int = 32, frames_per_stream: int = 8,
                     "search_params": C.search_params(2.0),
                 }
             frames.append(frame)
-        streams.append({"id": s, "kind": str(kinds[s]), "rate_hz": rate, "n_map": n_map,
-                        "n_kp": n_kp, "frames": frames, "map_bytes": 64 * n_map})
+        st = {"id": s, "kind": str(kinds[s]), "rate_hz": rate, "n_map": n_map,
+              "n_kp": n_kp, "frames": frames, "map_bytes": 64 * n_map}
+        if edits is not None:
+            st.update(points=table, map_ids0=id_sets[0], edits=edits)
+        streams.append(st)
     return streams
 
 

@@ -123,3 +123,89 @@ def test_search_over_an_edited_map(ft, ctx, kind):
     got = d.results()
     for v, (gs, ws) in enumerate(zip(got["search"], want["search"])):
         compare_search(gs, ws, f"[{kind} view {v}]")
+
+
+def _host_points(ctx, pts):
+    """The five arrays of `pts` packed into one ft_host_alloc block."""
+    import ctypes as ct
+    keys = ("pos", "normal", "dmin", "dmax", "desc")
+    sizes = [-(-pts[k].nbytes // 256) * 256 for k in keys]
+    base = ctx.ft_host_alloc(max(sum(sizes), 256))
+    view = np.ctypeslib.as_array((ct.c_uint8 * max(sum(sizes), 256)).from_address(base))
+    addr, at = [], 0
+    for k, sz in zip(keys, sizes):
+        view[at:at + pts[k].nbytes] = np.ascontiguousarray(pts[k]).view(np.uint8).reshape(-1)
+        addr.append(base + at)
+        at += sz
+    return base, addr
+
+
+def test_inserts_read_from_pinned_host_memory(ft, ctx):
+    """Inserted points in an ft_host_alloc block (read by the append kernel
+    over the bus) give the same map as the oracle; arrays only partly in host
+    blocks are rejected with the map unchanged."""
+    mp = _points(3000, 41, 0)
+    cap = 4000
+    dm = ft.DeviceMap(mp, cap)
+    rng = np.random.default_rng(42)
+    tag = 50000
+    for step in range(6):
+        n = dm.n
+        remove = rng.choice(n, int(rng.integers(0, 300)), replace=False).tolist()
+        m = int(rng.integers(1, 300))
+        ins = _points(m, 300 + step, tag)
+        tag += m
+        base, addr = _host_points(ctx, ins)
+        want = oracle.map_update(mp, cap, remove, ins)
+        ctx.ft_map_update(dm.struct, cap, remove, ft.ft_map_points(m, *addr))
+        torch.cuda.synchronize()
+        ctx.ft_host_free(base)
+        _same(dm.host(), want, step)
+        mp = want
+    # one array on the device, the others in a host block: rejected
+    ins = _points(10, 77, tag)
+    base, addr = _host_points(ctx, ins)
+    dev_dmin = torch.from_numpy(ins["dmin"]).cuda()
+    bad = ft.ft_map_points(10, addr[0], addr[1], dev_dmin.data_ptr(), addr[3], addr[4])
+    n = dm.n
+    assert ctx.ft_map_update(dm.struct, cap, [], bad, check=False) == ft.FT_ERR_INVALID_ARGUMENT
+    # a host array running past the end of its block: rejected
+    short = ft.ft_map_points(10, addr[0], addr[1], addr[2], addr[3], addr[4] + 256 - 16)
+    assert ctx.ft_map_update(dm.struct, cap, [], short, check=False) == ft.FT_ERR_INVALID_ARGUMENT
+    torch.cuda.synchronize()
+    ctx.ft_host_free(base)
+    assert dm.n == n
+    _same(dm.host(), mp, "unchanged")
+
+
+def test_many_edits_in_flight_behind_a_busy_stream(ft, ctx):
+    """More edits enqueued back to back, behind other work on their stream,
+    than the pair staging has events for: staging is reused only after the
+    edit that held it has ended, so every edit lands as the oracle's."""
+    mp0 = _points(2000, 51, 0)
+    cap = 2600
+    dm = ft.DeviceMap(mp0, cap)
+    rng = np.random.default_rng(52)
+    edits, mp, tag, n = [], mp0, 70000, 2000
+    for step in range(150):
+        remove = rng.choice(n, int(rng.integers(0, 40)), replace=False).tolist()
+        m = min(int(rng.integers(0, 40)), cap - (n - len(remove)))
+        ins = _points(m, 400 + step, tag)
+        tag += m
+        mp = oracle.map_update(mp, cap, remove, ins)
+        n = len(mp["dmin"])
+        dev = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in ins.items()} if m else None
+        edits.append((remove, m, dev))
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = torch.randn(4096, 4096, device="cuda")
+        for _ in range(4):
+            a = a @ a * 1e-3              # work the edits queue behind
+    for remove, m, dev in edits:
+        pts = ft.ft_map_points(m, *(ft._ptr(dev[k]) for k in ("pos", "normal", "dmin", "dmax", "desc"))) \
+            if m else None
+        ctx.ft_map_update(dm.struct, cap, remove, pts, stream=s)
+    s.synchronize()
+    assert dm.n == n
+    _same(dm.host(), mp, "after 150 queued edits")

@@ -130,6 +130,45 @@ def test_inflight_limit_and_slots_respected():
     assert st.completed == 30
 
 
+def test_sequential_streams_keep_one_frame_in_flight():
+    """Streams with per-frame map edits: a batch holds at most one frame per
+    stream, a stream's next frame launches only after its previous frame's
+    batch has ended, each stream's frames launch in arrival order, and frames
+    of other streams still coalesce."""
+    clock = FakeClock()
+    ex = FakeExecutor(clock, delay=0.003)
+    sch = Scheduler(ex, hbm_budget=10, max_batch=8, max_inflight=3, clock=clock, sequential=True)
+    for sid in range(4):
+        sch.register_stream(sid, 1)
+    arrivals = sorted((0.0002 * k + 0.00001 * sid, sid, k) for sid in range(4) for k in range(6))
+    ended = {}
+    real_release = ex.release
+
+    def release(h):
+        for f in ex.h[h][1]:
+            ended[(f.stream, f.seq)] = clock()
+        real_release(h)
+    ex.release = release
+    launched_at = {}
+    real_launch = ex.launch
+
+    def launch(frames, per_frame=False):
+        for f in frames:
+            launched_at[(f.stream, f.seq)] = clock()
+        return real_launch(frames, per_frame)
+    ex.launch = launch
+    st = drive(sch, clock, arrivals, horizon=0.2)
+    assert st.completed == 24 and st.failed == 0
+    for b in ex.launched:
+        assert len({sid for sid, _ in b}) == len(b)
+    for sid in range(4):
+        seqs = [q for b in ex.launched for s_, q in b if s_ == sid]
+        assert seqs == list(range(6))
+        for q in range(1, 6):
+            assert launched_at[(sid, q)] >= ended[(sid, q - 1)]
+    assert max(len(b) for b in ex.launched) > 1
+
+
 def test_per_frame_mode_never_batches():
     clock = FakeClock()
     ex = FakeExecutor(clock)
@@ -228,3 +267,45 @@ def test_summary_fields(mode):
     st.wall_s = 0.1
     s = st.summary()
     assert s["frames"] == 10 and s["p99_ms"] >= s["p50_ms"] > 0 and s["frames_per_s"] == 100.0
+
+
+def test_slot_record_follows_the_oracle_edit_rule():
+    """The executor's host record of which point each device map slot holds
+    equals the slot contents of the oracle's edited map (a map whose dmin
+    holds the point ids), over random edit sequences: nothing, head-only,
+    tail-only, everything, and mixes."""
+    import numpy as np
+
+    import oracle
+    from paper_2509_10757_amd.serve import follow_edit
+    rng = np.random.default_rng(8)
+    n_pts, cap = 5000, 3000
+    table = {"pos": np.zeros((n_pts, 3), np.float32), "normal": np.zeros((n_pts, 3), np.float32),
+             "dmin": np.arange(n_pts, dtype=np.float32), "dmax": np.zeros(n_pts, np.float32),
+             "desc": np.zeros((n_pts, 32), np.uint8)}
+    ids = np.arange(1000)
+    slot_of = np.full(n_pts, -1, np.int64)
+    slot_of[ids] = np.arange(1000)
+    mp = {k: v[ids] for k, v in table.items()}
+    unused = list(range(1000, n_pts))
+    for step in range(60):
+        n = len(ids)
+        if step == 0:
+            rem = []
+        elif step == 1:
+            rem = list(range(min(5, n)))
+        elif step == 2:
+            rem = list(range(n - 7, n))
+        elif step == 3:
+            rem = list(range(n))
+        else:
+            rem = rng.choice(n, int(rng.integers(0, n + 1)), replace=False).tolist() if n else []
+        m = int(rng.integers(0, min(300, cap - (n - len(rem))) + 1))
+        ins_ids = np.array(unused[:m], np.int64)
+        del unused[:m]
+        mp = oracle.map_update(mp, cap, rem, {k: v[ins_ids] for k, v in table.items()})
+        ids = follow_edit(ids, slot_of, np.sort(np.asarray(rem, np.int64)), ins_ids)
+        assert np.array_equal(ids, mp["dmin"].astype(np.int64)), step
+        live = np.nonzero(slot_of >= 0)[0]
+        assert np.array_equal(np.sort(live), np.sort(ids))
+        assert np.array_equal(slot_of[ids], np.arange(len(ids)))
