@@ -198,6 +198,69 @@ def pyramid(img, inv_sf) -> dict:
     return {"data": out, "offset": lay["offset"], "width": lay["width"], "height": lay["height"]}
 
 
+def fast_score_map(img, t: int, edge: int) -> np.ndarray:
+    """FAST-9 scores of one image (u8, H x W): the score inside the detection
+    window where it reaches t, 0 elsewhere (ORB extraction, Section II-A)."""
+    img = _c(img, np.uint8)
+    H, W = img.shape
+    out = np.zeros((H, W), np.uint8)
+    _load().oracle_fast_score_map(_p(img), ct.c_int(W), ct.c_int(H), ct.c_int(t), ct.c_int(edge), _p(out))
+    return out
+
+
+def orb_detect(pyr: dict, sf, t: int = 20, edge: int = 19, cap: int | None = None) -> dict:
+    """Corners of every pyramid level after non-maximum suppression, in
+    (level, y, x) order; `count` is the number found (at most `cap` written)."""
+    lib = _load()
+    lib.oracle_orb_detect.restype = ct.c_int64
+    off = _c(pyr["offset"], np.int64); w = _c(pyr["width"], np.int32); h = _c(pyr["height"], np.int32)
+    data = _c(pyr["data"], np.uint8)
+    sff = _c(sf, np.float32)
+    if cap is None:
+        cap = int(np.sum(np.maximum(w.astype(np.int64) - 2 * edge, 0) * np.maximum(h.astype(np.int64) - 2 * edge, 0)))
+    cap = max(int(cap), 0)
+    out = {"lx": np.zeros(cap, np.int16), "ly": np.zeros(cap, np.int16), "octave": np.zeros(cap, np.uint8),
+           "score": np.zeros(cap, np.uint8), "x": np.zeros(cap, np.float32), "y": np.zeros(cap, np.float32)}
+    n = lib.oracle_orb_detect(_p(data), _p(off), _p(w), _p(h), ct.c_int(len(w)), _p(sff), ct.c_int(t),
+                              ct.c_int(edge), ct.c_int64(cap), _p(out["lx"]), _p(out["ly"]), _p(out["octave"]),
+                              _p(out["score"]), _p(out["x"]), _p(out["y"]))
+    k = min(int(n), cap)
+    res = {key: v[:k].copy() for key, v in out.items()}
+    res["count"] = int(n)
+    return res
+
+
+def orb_blur(img) -> np.ndarray:
+    """The descriptor's smoothing of one image (u8, H x W)."""
+    img = _c(img, np.uint8)
+    H, W = img.shape
+    out = np.zeros((H, W), np.uint8)
+    _load().oracle_orb_blur(_p(img), ct.c_int(W), ct.c_int(H), _p(out))
+    return out
+
+
+def orb_blur_pyramid(pyr: dict) -> np.ndarray:
+    """Every level of a pyramid smoothed, in the pyramid's packed layout."""
+    out = np.zeros_like(_c(pyr["data"], np.uint8))
+    for l in range(len(pyr["width"])):
+        w, h, o = int(pyr["width"][l]), int(pyr["height"][l]), int(pyr["offset"][l])
+        out[o:o + w * h] = orb_blur(pyr["data"][o:o + w * h].reshape(h, w)).reshape(-1)
+    return out
+
+
+def orb_describe(pyr: dict, blurred, kps: dict, pattern) -> dict:
+    """Orientation (degrees) and 256-bit descriptor of each keypoint (lx, ly,
+    octave on the pyramid levels) with the point-pair `pattern` (int8 [256, 4])."""
+    n = len(kps["lx"])
+    off = _c(pyr["offset"], np.int64); w = _c(pyr["width"], np.int32)
+    out = {"angle": np.zeros(n, np.float32), "desc": np.zeros((n, 32), np.uint8)}
+    _load().oracle_orb_describe(_p(_c(pyr["data"], np.uint8)), _p(_c(blurred, np.uint8)), _p(off), _p(w),
+                                ct.c_int(n), _p(_c(kps["lx"], np.int16)), _p(_c(kps["ly"], np.int16)),
+                                _p(_c(kps["octave"], np.uint8)), _p(_c(pattern, np.int8)), _p(out["angle"]),
+                                _p(out["desc"]))
+    return out
+
+
 def stereo_pinhole(frame) -> dict:
     lib = _load()
     nL, xL, yL, oL, dL = _kp(frame["left"])

@@ -741,3 +741,167 @@ int oracle_map_update(int n, int capacity, float *pos, float *normal, float *dmi
     free(gone);
     return n1 + n_insert;
 }
+
+/* ------------------------------------------------------------------------ */
+/* ORB extraction on the image pyramid (Section II-A: keypoints extracted    */
+/* on every scale and described; Section IV-B: done on the device next to    */
+/* the pyramid).  The readings are stated in ft_oracle.h.                    */
+
+/* The 16 pixels at distance 3 from a centre, in order round the circle
+ * (clockwise in image coordinates, starting straight above the centre). */
+static const int orb_ring_dx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+static const int orb_ring_dy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+
+/* Largest threshold at which nine consecutive ring pixels are all brighter,
+ * or all darker, than the centre by more than it: over the 16 arcs of nine
+ * and both signs, the largest smallest difference, minus one (-1 when no arc
+ * differs positively throughout). */
+static int orb_fast_score(const uint8_t *img, int w, int x, int y)
+{
+    const int c = img[(size_t)y * w + x];
+    int best = -1;
+    for (int a = 0; a < 16; ++a) {
+        int lo_bright = 256, lo_dark = 256;
+        for (int k = 0; k < 9; ++k) {
+            const int r = (a + k) % 16;
+            const int v = img[(size_t)(y + orb_ring_dy[r]) * w + (x + orb_ring_dx[r])];
+            if (v - c < lo_bright) lo_bright = v - c;
+            if (c - v < lo_dark) lo_dark = c - v;
+        }
+        if (lo_bright - 1 > best) best = lo_bright - 1;
+        if (lo_dark - 1 > best) best = lo_dark - 1;
+    }
+    return best;
+}
+
+void oracle_fast_score_map(const uint8_t *img, int w, int h, int t, int edge, uint8_t *out)
+{
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            int v = 0;
+            if (x >= edge && x < w - edge && y >= edge && y < h - edge) {
+                const int s = orb_fast_score(img, w, x, y);
+                if (s >= t) v = s;
+            }
+            out[(size_t)y * w + x] = (uint8_t)v;
+        }
+}
+
+int64_t oracle_orb_detect(const uint8_t *pyr, const int64_t *off, const int32_t *w, const int32_t *h,
+                          int n_levels, const float *sf, int t, int edge, int64_t cap, int16_t *lx,
+                          int16_t *ly, uint8_t *oct, uint8_t *score, float *x, float *y)
+{
+    int64_t n = 0;
+    for (int l = 0; l < n_levels; ++l) {
+        const int W = w[l], H = h[l];
+        uint8_t *s = (uint8_t *)calloc((size_t)W * H + 1, 1);
+        oracle_fast_score_map(pyr + off[l], W, H, t, edge, s);
+        for (int yy = 0; yy < H; ++yy)
+            for (int xx = 0; xx < W; ++xx) {
+                const int v = s[(size_t)yy * W + xx];
+                if (v == 0) continue;
+                int keep = 1;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (dx == 0 && dy == 0) continue;
+                        const int nx = xx + dx, ny = yy + dy;
+                        const int nb = (nx >= 0 && nx < W && ny >= 0 && ny < H) ? s[(size_t)ny * W + nx] : 0;
+                        if (v <= nb) keep = 0;
+                    }
+                if (!keep) continue;
+                if (n < cap) {
+                    lx[n] = (int16_t)xx;
+                    ly[n] = (int16_t)yy;
+                    oct[n] = (uint8_t)l;
+                    score[n] = (uint8_t)v;
+                    x[n] = (float)xx * sf[l];
+                    y[n] = (float)yy * sf[l];
+                }
+                ++n;
+            }
+        free(s);
+    }
+    return n;
+}
+
+/* 7-tap binomial weights of the descriptor's smoothing. */
+static const int orb_blur_k[7] = {1, 6, 15, 20, 15, 6, 1};
+
+void oracle_orb_blur(const uint8_t *img, int w, int h, uint8_t *out)
+{
+    int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * ((size_t)w * h + 1));
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            int32_t acc = 0;
+            for (int i = 0; i < 7; ++i) {
+                int xs = x + i - 3;
+                xs = xs < 0 ? 0 : (xs > w - 1 ? w - 1 : xs);
+                acc += orb_blur_k[i] * img[(size_t)y * w + xs];
+            }
+            rows[(size_t)y * w + x] = acc;
+        }
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            int32_t acc = 0;
+            for (int j = 0; j < 7; ++j) {
+                int ys = y + j - 3;
+                ys = ys < 0 ? 0 : (ys > h - 1 ? h - 1 : ys);
+                acc += orb_blur_k[j] * rows[(size_t)ys * w + x];
+            }
+            out[(size_t)y * w + x] = (uint8_t)((acc + 2048) >> 12);
+        }
+    free(rows);
+}
+
+/* The integer nearest to num / sqrt(m2), halves away from zero, decided
+ * exactly: the largest k >= 0 with k = 0 or (2k - 1)^2 m2 <= 4 num^2, given
+ * the sign of num. */
+static int orb_round_ratio(int64_t num, int64_t m2)
+{
+    const int64_t a = num < 0 ? -num : num;
+    int k = 0;
+    for (;;) {
+        const int64_t odd = 2 * (int64_t)(k + 1) - 1;
+        if (odd * odd * m2 > 4 * a * a) break;
+        ++k;
+    }
+    return num < 0 ? -k : k;
+}
+
+void oracle_orb_describe(const uint8_t *pyr, const uint8_t *blurred, const int64_t *off, const int32_t *w,
+                         int n, const int16_t *lx, const int16_t *ly, const uint8_t *oct,
+                         const int8_t *pattern, float *angle, uint8_t *desc)
+{
+    for (int i = 0; i < n; ++i) {
+        const int l = oct[i], W = w[l], u = lx[i], v = ly[i];
+        const uint8_t *img = pyr + off[l];
+        const uint8_t *B = blurred + off[l];
+        int64_t m10 = 0, m01 = 0;
+        for (int dy = -15; dy <= 15; ++dy)
+            for (int dx = -15; dx <= 15; ++dx) {
+                if (dx * dx + dy * dy > 225) continue;
+                const int I = img[(size_t)(v + dy) * W + (u + dx)];
+                m10 += (int64_t)dx * I;
+                m01 += (int64_t)dy * I;
+            }
+        double a = atan2((double)m01, (double)m10) * (180.0 / 3.14159265358979323846);
+        if (a < 0.0) a += 360.0;
+        angle[i] = (float)a;
+        const int64_t m2 = m10 * m10 + m01 * m01;
+        uint8_t *d = desc + 32 * (size_t)i;
+        memset(d, 0, 32);
+        for (int t = 0; t < 256; ++t) {
+            const int x1 = pattern[4 * t], y1 = pattern[4 * t + 1];
+            const int x2 = pattern[4 * t + 2], y2 = pattern[4 * t + 3];
+            int c1 = x1, r1 = y1, c2 = x2, r2 = y2;
+            if (m2 > 0) {   /* the pattern turned by the intensity-centroid angle */
+                c1 = orb_round_ratio((int64_t)x1 * m10 - (int64_t)y1 * m01, m2);
+                r1 = orb_round_ratio((int64_t)x1 * m01 + (int64_t)y1 * m10, m2);
+                c2 = orb_round_ratio((int64_t)x2 * m10 - (int64_t)y2 * m01, m2);
+                r2 = orb_round_ratio((int64_t)x2 * m01 + (int64_t)y2 * m10, m2);
+            }
+            if (B[(size_t)(v + r1) * W + (u + c1)] < B[(size_t)(v + r2) * W + (u + c2)])
+                d[t / 8] |= (uint8_t)(1u << (t % 8));
+        }
+    }
+}

@@ -157,6 +157,55 @@ int64_t oracle_pyramid_layout(int W, int H, const float *inv_sf, int n_levels,
 void oracle_pyramid(const uint8_t *img, int W, int H, int pitch, const float *inv_sf, int n_levels,
                     uint8_t *out);
 
+/* ORB extraction on the pyramid (Section II-A: keypoints are extracted on
+ * every scale of the image pyramid and each gets a descriptor; Section IV-B:
+ * the extraction runs on the device, next to the pyramid).  The paper gives
+ * no detector, score, orientation or descriptor details; the readings:
+ *   - FAST-9 score of a pixel: the ring of 16 pixels at distance 3, the
+ *     largest (over the 16 arcs of nine consecutive ring pixels and both
+ *     signs) smallest difference ring - centre (or centre - ring) minus one;
+ *     a corner when the score reaches the threshold t (1..254), i.e. nine
+ *     consecutive ring pixels all brighter than centre + t or all darker than
+ *     centre - t;
+ *   - detection window of level l: x in [edge, w_l - edge), y in
+ *     [edge, h_l - edge) with edge >= 19 (the orientation disc and the turned
+ *     pattern plus the smoothing stay inside the level);
+ *   - non-maximum suppression: a corner is kept when its score exceeds the
+ *     score of each of its 8 neighbours (non-corners count 0), so plateaus
+ *     of equal scores keep none;
+ *   - order: (level, y, x); coordinates lx, ly on the level and x = lx *
+ *     sf[l], y = ly * sf[l] in binary32; when more than `cap` corners exist
+ *     the first cap are written and the count is returned;
+ *   - orientation: intensity centroid over the disc dx^2 + dy^2 <= 225 of the
+ *     level image: m10 = sum dx I, m01 = sum dy I (exact integers); angle =
+ *     atan2(m01, m10) in degrees (binary64, times 180 / pi, plus 360 when
+ *     negative), stored in binary32;
+ *   - smoothing for the descriptor: per level, the separable binomial
+ *     [1 6 15 20 15 6 1] horizontally then vertically, borders clamped,
+ *     rounded once: (sum + 2^11) >> 12;
+ *   - descriptor: 256 tests of a caller-supplied pattern of point pairs
+ *     (x1, y1, x2, y2), each point within radius 13; each point is turned by
+ *     the centroid angle exactly: column = the integer nearest (x m10 -
+ *     y m01) / sqrt(m10^2 + m01^2), row = the integer nearest (x m01 +
+ *     y m10) / sqrt(...), halves away from zero, decided in integers (no
+ *     turn when m10 = m01 = 0); bit t (bit t % 8 of byte t / 8) is set when
+ *     the smoothed level is darker at the first turned point than at the
+ *     second.
+ * Pinned by closed forms (a lone bright pixel, straight edges, the strict
+ * threshold, invariance under an added constant, inversion, transposition
+ * and half turns; orientation of linear ramps in four directions, the disc's
+ * size; the blur of impulses, constants and ramps; descriptors of ramps, which
+ * equal the unturned pattern's x order in every direction), by an
+ * independent numpy brute force, and by planted mistakes. */
+void oracle_fast_score_map(const uint8_t *img, int w, int h, int t, int edge, uint8_t *out);
+int64_t oracle_orb_detect(const uint8_t *pyr, const int64_t *off, const int32_t *w, const int32_t *h,
+                          int n_levels, const float *sf, int t, int edge, int64_t cap, int16_t *lx,
+                          int16_t *ly, uint8_t *oct, uint8_t *score, float *x, float *y);
+void oracle_orb_blur(const uint8_t *img, int w, int h, uint8_t *out);
+void oracle_orb_describe(const uint8_t *pyr, const uint8_t *blurred, const int64_t *off, const int32_t *w,
+                         int n, const int16_t *lx, const int16_t *ly, const uint8_t *oct,
+                         const int8_t *pattern, float *angle, uint8_t *desc);
+
 /* Kannala-Brandt helpers, exposed so tests can pin them (round trips). */
 int oracle_kb_unproject(const float *kb, float u, float v, int iters, double tol,
                         double max_theta, double *ray);

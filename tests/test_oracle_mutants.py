@@ -13,6 +13,7 @@ import synth
 from tests import test_oracle_pins as pins
 from tests import test_oracle_map as mapt
 from tests import test_oracle_motion as motion
+from tests import test_oracle_orb as orb
 from tests import test_oracle_pyramid as pyr
 
 HERE = os.path.dirname(os.path.abspath(oracle.__file__))
@@ -86,6 +87,28 @@ MUTANTS = {
     "map_duplicates_accepted": ("if (r < 0 || r >= n || gone[r])", "if (r < 0 || r >= n)"),
     "map_normal_not_moved": ("        normal[3 * to + c] = snormal[3 * from + c];\n", ""),
     "map_capacity_strict": ("if ((int64_t)n1 + n_insert > capacity)", "if ((int64_t)n1 + n_insert >= capacity)"),
+    "orb_ring_offset": ("orb_ring_dx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1}",
+                        "orb_ring_dx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -2}"),
+    "orb_arc_of_eight": ("for (int k = 0; k < 9; ++k) {\n            const int r = (a + k) % 16;",
+                         "for (int k = 0; k < 8; ++k) {\n            const int r = (a + k) % 16;"),
+    "orb_score_not_minus_one": ("if (lo_dark - 1 > best) best = lo_dark - 1;", "if (lo_dark > best) best = lo_dark;"),
+    "orb_threshold_strict": ("if (s >= t) v = s;", "if (s > t) v = s;"),
+    "orb_window_right_edge": ("x < w - edge &&", "x <= w - edge &&"),
+    "orb_nms_keeps_ties": ("if (v <= nb) keep = 0;", "if (v < nb) keep = 0;"),
+    "orb_nms_four_neighbours": ("if (dx == 0 && dy == 0) continue;\n                        const int nx",
+                                "if (dx == dy || dx == -dy) continue;\n                        const int nx"),
+    "orb_coordinates_unscaled": ("x[n] = (float)xx * sf[l];", "x[n] = (float)xx * sf[0];"),
+    "orb_blur_unrounded": ("(uint8_t)((acc + 2048) >> 12)", "(uint8_t)(acc >> 12)"),
+    "orb_blur_weights": ("orb_blur_k[7] = {1, 6, 15, 20, 15, 6, 1}", "orb_blur_k[7] = {2, 6, 15, 18, 15, 6, 2}"),
+    "orb_disc_strict": ("if (dx * dx + dy * dy > 225) continue;", "if (dx * dx + dy * dy >= 225) continue;"),
+    "orb_m01_sign": ("m01 += (int64_t)dy * I;", "m01 -= (int64_t)dy * I;"),
+    "orb_turn_sign": ("c1 = orb_round_ratio((int64_t)x1 * m10 - (int64_t)y1 * m01, m2);",
+                      "c1 = orb_round_ratio((int64_t)x1 * m10 + (int64_t)y1 * m01, m2);"),
+    "orb_bit_order": ("d[t / 8] |= (uint8_t)(1u << (t % 8));", "d[t / 8] |= (uint8_t)(0x80u >> (t % 8));"),
+    "orb_test_reversed": ("if (B[(size_t)(v + r1) * W + (u + c1)] < B[", "if (B[(size_t)(v + r1) * W + (u + c1)] > B["),
+    "orb_descriptor_unsmoothed": ("const uint8_t *B = blurred + off[l];", "const uint8_t *B = pyr + off[l];"),
+    "orb_orientation_smoothed": ("const uint8_t *img = pyr + off[l];\n        const uint8_t *B",
+                                 "const uint8_t *img = blurred + off[l];\n        const uint8_t *B"),
     "conflict_tie": ("int64_t key = ((int64_t)dist[i] << 32) | (int64_t)i;\n        if (key < best",
                      "int64_t key = ((int64_t)dist[i] << 32) | (int64_t)(nQ - i);\n        if (key < best"),
 }
@@ -152,6 +175,23 @@ def _pins(frames):
     tests.append(lambda: pyr.test_vertical_ramp_is_round_half_up_of_the_source_row(40, 250))
     tests.append(pyr.test_exact_halving_is_the_rounded_box_average)
     tests.append(lambda: pyr.test_random_images_match_numpy_resampler(101, 67, 6))
+    for bg, fg in [(50, 200), (200, 50)]:
+        tests.append(lambda b=bg, f=fg: orb.test_lone_pixel_is_the_only_corner(b, f))
+    for t in (7, 20):
+        tests.append(lambda t=t: orb.test_threshold_is_strict(t))
+    tests.append(lambda: orb.test_scores_are_invariant_under_the_image_symmetries(1))
+    tests.append(lambda: orb.test_scores_equal_numpy_brute_force(4, 20, 19))
+    tests.append(orb.test_detection_equals_brute_force_on_a_pyramid)
+    tests.append(orb.test_plateaus_of_equal_scores_keep_nothing)
+    tests.append(orb.test_blur_of_an_impulse_is_the_rounded_binomial_product)
+    tests.append(orb.test_blur_keeps_constants_and_interior_ramps_and_clamps_borders)
+    for kind, deg in [("+x", 0.0), ("+y", 90.0), ("-x", 180.0), ("+x-y", 315.0)]:
+        tests.append(lambda k=kind, d=deg: orb.test_orientation_of_linear_ramps(k, d))
+    tests.append(orb.test_orientation_disc_has_radius_15_inclusive)
+    for kind in ("+x", "+y", "-x"):
+        tests.append(lambda k=kind: orb.test_ramp_descriptors_equal_the_pattern_x_order_in_every_direction(k))
+    tests.append(orb.test_diagonal_ramp_descriptor_uses_the_exactly_turned_pattern)
+    tests.append(orb.test_descriptors_equal_numpy_brute_force_on_textures)
 
     def with_frames():
         c1 = (frames[1], oracle.run_frame(frames[1]))
