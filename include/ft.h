@@ -377,6 +377,70 @@ typedef struct ft_map_edit {
 ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,
                         const ft_map_edit *edit);
 
+/* ------------------------------------------------------------------------ */
+/* ORB extraction on the device-resident pyramid (Section II-A: keypoints   */
+/* extracted on every scale of the pyramid and described; Section IV-B:    */
+/* the extraction runs on the device, next to the pyramid stereo reads).    */
+/* The paper gives no detector details; this library computes FAST-9        */
+/* corners with strict 3x3 suppression, intensity-centroid orientation and  */
+/* a descriptor over a caller-supplied pattern turned exactly by it.        */
+/* Filtering and distributing the corners is left to the caller.           */
+/* ------------------------------------------------------------------------ */
+#define FT_ORB_TESTS 256
+
+typedef struct ft_orb_params {
+    int32_t threshold;         /* FAST threshold t, 1..254: a corner has nine consecutive ring pixels
+                                  (distance 3) all brighter than centre + t or all darker than centre - t */
+    int32_t edge;              /* detection window of level l: x in [edge, w_l - edge), y in
+                                  [edge, h_l - edge); edge >= 19 */
+} ft_orb_params;
+
+typedef struct ft_orb_corners {
+    int32_t capacity;          /* entries of each output array */
+    int16_t *lx, *ly;          /* DEVICE [capacity]: column and row on the corner's level */
+    uint8_t *octave, *score;   /* DEVICE [capacity]: level; FAST score (the largest threshold it passes) */
+    float *x, *y;              /* DEVICE [capacity]: lx * sf[level], ly * sf[level] (binary32) */
+    int32_t *count;            /* DEVICE [1]: corners found; when above capacity, the first capacity
+                                  (in order) are written */
+} ft_orb_corners;
+
+/* Detects the corners of every level of `pyr` (device, the packed layout of
+ * ft_pyramid_layout or any per-level layout with widths <= FT_PYRAMID_MAX_WIDTH):
+ * a pixel of the window is a corner when its FAST-9 score (over the 16 arcs of
+ * nine ring pixels and both signs, the largest smallest difference from the
+ * centre, minus one) reaches the threshold, and it is kept when its score
+ * exceeds each of its 8 neighbours' (non-corners count 0).  Corners are
+ * written in (level, row, column) order.  When `blurred` (DEVICE, the
+ * pyramid's layout) is not null it receives every level smoothed for the
+ * descriptor: the separable binomial [1 6 15 20 15 6 1] / 64 per direction,
+ * borders clamped, rounded once ((sum + 2^11) >> 12).  Two kernels on
+ * `stream`; *count and the outputs are valid when they complete.  Errors:
+ * bad threshold, edge, pyramid or null / misaligned outputs (lx, ly 2-byte,
+ * x, y, count 4-byte aligned): FT_ERR_INVALID_ARGUMENT; a level above
+ * FT_PYRAMID_MAX_WIDTH x 4096: FT_ERR_CAPACITY.  Up to 8 detections may be
+ * in flight per context (a ninth waits for the first to complete). */
+ft_status ft_orb_detect(ft_context *ctx, void *stream, const ft_pyramid *pyr, const ft_scales *scales,
+                        const ft_orb_params *params, uint8_t *blurred, const ft_orb_corners *out);
+
+/* Orientation and descriptor of keypoints on the pyramid's levels (for
+ * example the output of ft_orb_detect, filtered or not): n = n_max, or
+ * min(n_max, *count) when `count` (DEVICE) is not null.  Orientation: the
+ * intensity centroid over the disc dx^2 + dy^2 <= 225 of the level image,
+ * angle[i] = atan2(m01, m10) in degrees, [0, 360].  Descriptor (32 bytes, bit
+ * t in bit t % 8 of byte t / 8): test t of `pattern` (HOST int8
+ * [FT_ORB_TESTS][4] = x1, y1, x2, y2, each point within radius 13) turns both
+ * points exactly by the centroid angle (each coordinate the integer nearest
+ * (x m10 - y m01) / |m| and (x m01 + y m10) / |m|, halves away from zero; no
+ * turn when m = 0) and sets the bit when `blurred` (DEVICE, from
+ * ft_orb_detect) is darker at the first point than at the second.  A keypoint
+ * closer than 15 pixels to its level's border, or of a level >= FT_LEVELS,
+ * gets angle -1 and a zero descriptor.  Errors: null or misaligned arrays
+ * (desc 8-byte aligned), a pattern point beyond radius 13:
+ * FT_ERR_INVALID_ARGUMENT. */
+ft_status ft_orb_describe(ft_context *ctx, void *stream, const ft_pyramid *pyr, const uint8_t *blurred,
+                          int32_t n_max, const int32_t *count, const int16_t *lx, const int16_t *ly,
+                          const uint8_t *octave, const int8_t *pattern, float *angle, uint8_t *desc);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops or harnesses that forbid allocation): the search of
  * ft_search_local_points, same kernels and bit-identical outputs, with no

@@ -22,6 +22,8 @@ FT_PHASES = 8
 FT_CAMERA_PINHOLE, FT_CAMERA_KB = 0, 1
 FT_JOB_PINHOLE, FT_JOB_FISHEYE, FT_JOB_SEARCH = 1, 2, 3
 FT_EXEC_EAGER, FT_EXEC_GRAPH = 0, 1
+FT_ORB_TESTS = 256
+FT_PYRAMID_MAX_WIDTH = 1536
 
 P = ct.c_void_p
 F8 = ct.c_float * LEVELS
@@ -113,6 +115,15 @@ class ft_search_out(ct.Structure):
     _fields_ = [("mp_match", P), ("mp_dist", P), ("kp_match", P), ("n_matches", P)]
 
 
+class ft_orb_params(ct.Structure):
+    _fields_ = [("threshold", ct.c_int32), ("edge", ct.c_int32)]
+
+
+class ft_orb_corners(ct.Structure):
+    _fields_ = [("capacity", ct.c_int32), ("lx", P), ("ly", P), ("octave", P), ("score", P), ("x", P), ("y", P),
+                ("count", P)]
+
+
 class ft_map_edit(ct.Structure):
     _fields_ = [("n_remove", ct.c_int32), ("remove", P), ("insert", ft_map_points)]
 
@@ -177,6 +188,9 @@ EXPORTS = {
                              ct.POINTER(ft_keypoints), P, P, P, ct.POINTER(ft_grid), ct.POINTER(ft_scales),
                              ct.POINTER(ft_last_params), ct.POINTER(ft_search_out)],
     "ft_map_update": [P, P, ct.POINTER(ft_map_points), ct.c_int32, ct.POINTER(ft_map_edit)],
+    "ft_orb_detect": [P, P, ct.POINTER(ft_pyramid), ct.POINTER(ft_scales), ct.POINTER(ft_orb_params), P,
+                      ct.POINTER(ft_orb_corners)],
+    "ft_orb_describe": [P, P, ct.POINTER(ft_pyramid), P, ct.c_int32, P, P, P, P, P, P, P],
     "ft_batch_submit": [P, P, ct.POINTER(ft_frame_job), ct.c_int32, ct.POINTER(ct.c_uint64)],
     "ft_batch_poll": [P, ct.c_uint64, ct.POINTER(ct.c_int32)],
     "ft_batch_wait": [P, ct.c_uint64],
@@ -366,6 +380,25 @@ class Context:
         st = self.lib.ft_map_update(self.h, _stream(stream), ct.byref(map_points), capacity, ct.byref(ed))
         if check:
             self._check(st, "ft_map_update")
+        return st
+
+    def ft_orb_detect(self, pyr, scales, params, blurred, corners, stream=None, check=True):
+        """`blurred`: device address or None; `corners`: ft_orb_corners."""
+        st = self.lib.ft_orb_detect(self.h, _stream(stream), ct.byref(pyr), ct.byref(scales), ct.byref(params),
+                                    P(blurred or None), ct.byref(corners))
+        if check:
+            self._check(st, "ft_orb_detect")
+        return st
+
+    def ft_orb_describe(self, pyr, blurred, n_max, count, lx, ly, octave, pattern, angle, desc, stream=None,
+                        check=True):
+        """Device addresses (count may be None); `pattern`: host int8 [256, 4]."""
+        pat = np.ascontiguousarray(np.asarray(pattern, dtype=np.int8).reshape(-1))
+        st = self.lib.ft_orb_describe(self.h, _stream(stream), ct.byref(pyr), P(blurred or None), int(n_max),
+                                      P(count or None), P(lx or None), P(ly or None), P(octave or None),
+                                      P(pat.ctypes.data), P(angle or None), P(desc or None))
+        if check:
+            self._check(st, "ft_orb_describe")
         return st
 
     def ft_batch_submit(self, jobs, stream=None) -> int:
@@ -690,6 +723,55 @@ class DeviceLastFrame:
         r = {k: v.cpu().numpy() for k, v in self.o.items()}
         return {"last_match": r["mp_match"], "last_dist": r["mp_dist"], "kp_match": r["kp_match"],
                 "n_matches": int(r["n_matches"][0])}
+
+
+class DeviceOrb:
+    """ORB extraction of one device pyramid: the smoothed pyramid and corner
+    outputs (capacity corners) allocated once; detect() then describe() run
+    on the device with no host round trip (describe reads the device count)."""
+
+    def __init__(self, pyr: dict, capacity: int = 65536, device="cuda"):
+        n = int(pyr["data"].size) if isinstance(pyr["data"], np.ndarray) else int(pyr["data"].numel())
+        self.pyr_t = pyr["data"] if isinstance(pyr["data"], torch.Tensor) else \
+            torch.from_numpy(np.ascontiguousarray(pyr["data"])).to(device)
+        self.pyr = ft_pyramid()
+        self.pyr.data = self.pyr_t.data_ptr()
+        self.pyr.offset[:] = [int(v) for v in pyr["offset"]]
+        self.pyr.width[:] = [int(v) for v in pyr["width"]]
+        self.pyr.height[:] = [int(v) for v in pyr["height"]]
+        self.blurred = torch.empty(n, dtype=torch.uint8, device=device)
+        self.capacity = capacity
+        c = capacity
+        self.t = {"lx": torch.empty(c, dtype=torch.int16, device=device),
+                  "ly": torch.empty(c, dtype=torch.int16, device=device),
+                  "octave": torch.empty(c, dtype=torch.uint8, device=device),
+                  "score": torch.empty(c, dtype=torch.uint8, device=device),
+                  "x": torch.empty(c, dtype=torch.float32, device=device),
+                  "y": torch.empty(c, dtype=torch.float32, device=device),
+                  "count": torch.zeros(1, dtype=torch.int32, device=device),
+                  "angle": torch.empty(c, dtype=torch.float32, device=device),
+                  "desc": torch.empty((c, 32), dtype=torch.uint8, device=device)}
+        t = self.t
+        self.corners = ft_orb_corners(c, _ptr(t["lx"]), _ptr(t["ly"]), _ptr(t["octave"]), _ptr(t["score"]),
+                                      _ptr(t["x"]), _ptr(t["y"]), _ptr(t["count"]))
+
+    def detect(self, ctx: Context, scales, threshold=20, edge=19, stream=None, check=True):
+        return ctx.ft_orb_detect(self.pyr, scales, ft_orb_params(threshold, edge), self.blurred.data_ptr(),
+                                 self.corners, stream=stream, check=check)
+
+    def describe(self, ctx: Context, pattern, stream=None, check=True):
+        t = self.t
+        return ctx.ft_orb_describe(self.pyr, self.blurred.data_ptr(), self.capacity, _ptr(t["count"]),
+                                   _ptr(t["lx"]), _ptr(t["ly"]), _ptr(t["octave"]), pattern, _ptr(t["angle"]),
+                                   _ptr(t["desc"]), stream=stream, check=check)
+
+    def results(self) -> dict:
+        n = int(self.t["count"][0])
+        k = min(n, self.capacity)
+        out = {key: self.t[key][:k].cpu().numpy() for key in ("lx", "ly", "octave", "score", "x", "y", "angle",
+                                                                "desc")}
+        out["count"] = n
+        return out
 
 
 class DeviceMap:

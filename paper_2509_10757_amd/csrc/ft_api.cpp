@@ -114,6 +114,13 @@ struct ft_context {
     size_t edit_ring_bytes = 0, edit_head = 0;
     std::deque<EditChunk> edit_live;
     std::vector<hipEvent_t> edit_free_ev, edit_all_ev;
+    // ORB detection: per-tile corner counts, one buffer per call in flight
+    // (round robin; a buffer is reused once the event after its kernels ran)
+    static constexpr int kOrbSlots = 8;
+    int32_t *orb_tiles[kOrbSlots] = {};
+    hipEvent_t orb_ev[kOrbSlots] = {};
+    bool orb_used[kOrbSlots] = {};
+    int orb_next = 0;
 };
 
 namespace {
@@ -958,7 +965,8 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     const size_t slot_bytes = align_up(b.off, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
     const size_t edit_bytes = align_up(sizeof(int32_t) * 2 * (size_t)lim->max_map_points, 256);
-    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight;
+    const size_t orb_bytes = align_up(sizeof(int32_t) * (size_t)kOrbMaxTiles, 256);
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight + orb_bytes * ft_context::kOrbSlots;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -970,6 +978,14 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
         off += slot_bytes;
     };
     carve_at(ctx->direct);
+    for (int k = 0; k < ft_context::kOrbSlots; ++k) {
+        ctx->orb_tiles[k] = reinterpret_cast<int32_t *>(ctx->base + off);
+        off += orb_bytes;
+        if (hipEventCreateWithFlags(&ctx->orb_ev[k], hipEventDisableTiming) != hipSuccess) {
+            ft_context_destroy(ctx);
+            return FT_ERR_DEVICE;
+        }
+    }
     ctx->edit_ring_bytes = std::max<size_t>(2 * edit_bytes, (size_t)1 << 20);
     if (hipHostMalloc((void **)&ctx->edit_ring, ctx->edit_ring_bytes, hipHostMallocDefault) != hipSuccess) {
         ft_context_destroy(ctx);
@@ -1037,6 +1053,11 @@ ft_status ft_context_destroy(ft_context *ctx)
         release_graph(ln.g);
         if (ln.h_table) hipHostFree(ln.h_table);
     }
+    for (int k = 0; k < ft_context::kOrbSlots; ++k)
+        if (ctx->orb_ev[k]) {
+            hipEventSynchronize(ctx->orb_ev[k]);
+            hipEventDestroy(ctx->orb_ev[k]);
+        }
     for (auto &c : ctx->edit_live) hipEventSynchronize(c.ev);
     for (hipEvent_t e : ctx->edit_all_ev) hipEventDestroy(e);
     if (ctx->edit_ring) hipHostFree(ctx->edit_ring);
@@ -1441,6 +1462,118 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
     ctx->edit_free_ev.pop_back();
     live.push_back({off, need, ev});
     map->n = n1 + m;
+    return FT_OK;
+}
+
+// ------------------------------------------------------------ ORB extraction
+namespace {
+
+ft_status check_orb_pyramid(ft_context *ctx, const ft_pyramid *pyr, const char *what)
+{
+    if (!pyr || !pyr->data) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: null pyramid", what);
+    for (int l = 0; l < kLevels; ++l) {
+        if (pyr->width[l] < 1 || pyr->height[l] < 1 || pyr->offset[l] < 0)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "%s: level %d is %dx%d at offset %lld", what, l, pyr->width[l],
+                        pyr->height[l], (long long)pyr->offset[l]);
+        if (pyr->width[l] > kMaxPyrW || pyr->height[l] > kMaxRows)
+            return fail(ctx, FT_ERR_CAPACITY, "%s: level %d is %dx%d, above %dx%d", what, l, pyr->width[l],
+                        pyr->height[l], kMaxPyrW, kMaxRows);
+    }
+    return FT_OK;
+}
+
+}  // namespace
+
+ft_status ft_orb_detect(ft_context *ctx, void *stream, const ft_pyramid *pyr, const ft_scales *scales,
+                        const ft_orb_params *params, uint8_t *blurred, const ft_orb_corners *out)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if ((st = check_scales(ctx, scales)) || (st = check_orb_pyramid(ctx, pyr, "orb detect"))) return st;
+    if (!params || !out) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb detect: null argument");
+    if (params->threshold < 1 || params->threshold > 254 || params->edge < 19 || params->edge > kMaxRows)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb detect: threshold %d (1..254), edge %d (>= 19)",
+                    params->threshold, params->edge);
+    if (out->capacity < 0 || !out->count || !aligned(out->count, 4))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb detect: capacity %d, count %p", out->capacity,
+                    (const void *)out->count);
+    if (out->capacity > 0 && (!out->lx || !out->ly || !out->octave || !out->score || !out->x || !out->y ||
+                              !aligned(out->lx, 2) || !aligned(out->ly, 2) || !aligned(out->x, 4) ||
+                              !aligned(out->y, 4)))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb detect: null or misaligned output array");
+    OrbDetectArgs a{};
+    a.pyr = pyr->data;
+    a.blurred = blurred;
+    int tiles = 0, wmax = 0;
+    for (int l = 0; l < kLevels; ++l) {
+        a.off[l] = pyr->offset[l];
+        a.w[l] = pyr->width[l];
+        a.h[l] = pyr->height[l];
+        a.sf[l] = scales->sf[l];
+        a.tile0[l] = tiles;
+        tiles += (pyr->height[l] + kOrbRows - 1) / kOrbRows;
+        wmax = std::max(wmax, (int)pyr->width[l]);
+    }
+    a.tile0[kLevels] = tiles;
+    a.t = params->threshold;
+    a.edge = params->edge;
+    a.capacity = out->capacity;
+    a.lds_w = (wmax + 3) & ~3;
+    a.lx = out->lx;
+    a.ly = out->ly;
+    a.oct = out->octave;
+    a.score = out->score;
+    a.x = out->x;
+    a.y = out->y;
+    a.count = out->count;
+    const int slot = ctx->orb_next;
+    ctx->orb_next = (slot + 1) % ft_context::kOrbSlots;
+    if (ctx->orb_used[slot]) HIP_TRY(ctx, hipEventSynchronize(ctx->orb_ev[slot]));
+    a.tile_count = ctx->orb_tiles[slot];
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(ctx, launch_orb_detect(a, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->orb_ev[slot], s));
+    ctx->orb_used[slot] = true;
+    return FT_OK;
+}
+
+ft_status ft_orb_describe(ft_context *ctx, void *stream, const ft_pyramid *pyr, const uint8_t *blurred,
+                          int32_t n_max, const int32_t *count, const int16_t *lx, const int16_t *ly,
+                          const uint8_t *octave, const int8_t *pattern, float *angle, uint8_t *desc)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if ((st = check_orb_pyramid(ctx, pyr, "orb describe"))) return st;
+    if (!blurred || !pattern || n_max < 0)
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb describe: null smoothed pyramid or pattern, or n %d", n_max);
+    if (n_max > 0 && (!lx || !ly || !octave || !angle || !desc || !aligned(lx, 2) || !aligned(ly, 2) ||
+                      !aligned(angle, 4) || !aligned(desc, 8) || (count && !aligned(count, 4))))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb describe: null or misaligned array");
+    OrbDescribeArgs a{};
+    for (int t = 0; t < kOrbTests; ++t)
+        for (int c = 0; c < 2; ++c) {
+            const int px = pattern[4 * t + 2 * c], py = pattern[4 * t + 2 * c + 1];
+            if (px * px + py * py > 169)
+                return fail(ctx, FT_ERR_INVALID_ARGUMENT, "orb describe: pattern point %d of test %d lies beyond radius 13",
+                            c, t);
+            a.pattern[t][2 * c] = (int8_t)px;
+            a.pattern[t][2 * c + 1] = (int8_t)py;
+        }
+    a.pyr = pyr->data;
+    a.blurred = blurred;
+    for (int l = 0; l < kLevels; ++l) {
+        a.off[l] = pyr->offset[l];
+        a.w[l] = pyr->width[l];
+        a.h[l] = pyr->height[l];
+    }
+    a.n_max = n_max;
+    a.count = count;
+    a.lx = lx;
+    a.ly = ly;
+    a.oct = octave;
+    a.angle = angle;
+    a.desc = desc;
+    HIP_TRY(ctx, launch_orb_describe(a, (hipStream_t)stream));
     return FT_OK;
 }
 

@@ -225,6 +225,44 @@ struct MapEditArgs {
 };
 hipError_t launch_map_edit(const MapEditArgs &a, hipStream_t stream);
 
+// ORB extraction (ft_orb.hip).  Detection runs over row tiles of every level
+// of one pyramid: kOrbRows output rows per 256-thread workgroup, the level
+// rows they need staged in LDS (kOrbHalo above and below: the FAST ring and
+// the suppression), so a pyramid has at most kOrbMaxTiles tiles.
+constexpr int kOrbRows = 8;
+constexpr int kOrbHalo = 4;
+constexpr int kOrbMaxTiles = kLevels * (kMaxRows / kOrbRows);
+constexpr int kOrbTests = 256;
+struct OrbDetectArgs {
+    const FT_G uint8_t *pyr;
+    FT_G uint8_t *blurred;            // null: no smoothing
+    int64_t off[kLevels];
+    int32_t w[kLevels], h[kLevels];
+    float sf[kLevels];
+    int32_t tile0[kLevels + 1];       // first tile of each level; tile0[kLevels] = tiles
+    int32_t t, edge, capacity, lds_w; // lds_w: LDS row stride (the widest level, rounded up to 4)
+    FT_G int32_t *tile_count;         // [tiles] corners kept per tile
+    FT_G int16_t *lx, *ly;
+    FT_G uint8_t *oct, *score;
+    FT_G float *x, *y;
+    FT_G int32_t *count;
+};
+struct OrbDescribeArgs {
+    const FT_G uint8_t *pyr, *blurred;
+    int64_t off[kLevels];
+    int32_t w[kLevels], h[kLevels];
+    int32_t n_max;
+    const FT_G int32_t *count;        // nullable: n = min(n_max, *count)
+    const FT_G int16_t *lx, *ly;
+    const FT_G uint8_t *oct;
+    FT_G float *angle;
+    FT_G uint8_t *desc;
+    int8_t pattern[kOrbTests][4];     // x1, y1, x2, y2 of each test
+};
+size_t orb_detect_lds(int lds_w);
+hipError_t launch_orb_detect(const OrbDetectArgs &a, hipStream_t stream);
+hipError_t launch_orb_describe(const OrbDescribeArgs &a, hipStream_t stream);
+
 // Gather-list copy (ft_upload.hip): up to kUploadSegs segments per launch,
 // passed by value; each workgroup copies one kUploadChunk-byte chunk of one
 // segment.  `first[s]` is the first workgroup of segment s, first[n] the grid.

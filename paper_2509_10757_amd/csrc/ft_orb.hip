@@ -1,0 +1,343 @@
+// ORB extraction on the device-resident image pyramid (Section II-A: keypoints
+// are extracted on every scale and described; Section IV-B: the extraction
+// runs next to the pyramid on the device).
+//
+//  * k_orb_detect: one 256-thread workgroup per tile of kOrbRows rows of one
+//    level.  The tile's level rows and kOrbHalo rows above and below are
+//    staged in LDS; FAST-9 scores (a compass-point quick test first) fill a
+//    score band one row larger on each side; strict 3x3 suppression counts
+//    the tile's corners; the descriptor's binomial smoothing of the tile's
+//    rows is written from the same staged rows.
+//  * k_orb_emit: the same staging, scores and suppression; the tile's first
+//    output index is the sum of the counts of the tiles before it (tiles are
+//    in (level, row) order), and corners are written in (row, x) order within
+//    the tile by wave ballots.
+//  * k_orb_describe: one wave per keypoint: the intensity-centroid moments
+//    over the radius-15 disc (lanes stride the disc, one wave reduction), then
+//    four tests per lane on the smoothed level with the pattern turned exactly
+//    by the moments (integer rounding decisions), and one ballot per 64 tests
+//    gives 8 descriptor bytes.
+#include <hip/hip_runtime.h>
+
+#define FT_KERNELS 1
+#include "ft_internal.h"
+
+namespace ft {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kStaged = kOrbRows + 2 * kOrbHalo;   // level rows staged per tile
+constexpr int kScoreRows = kOrbRows + 2;           // score rows: the tile and one row each side
+
+// The 16 ring pixels at distance 3 (clockwise from straight above).
+__constant__ int8_t kRingDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+__constant__ int8_t kRingDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+
+__device__ __forceinline__ int level_of_tile(const OrbDetectArgs &a, int tile)
+{
+    int l = 0;
+    while (l + 1 < kLevels && tile >= a.tile0[l + 1]) ++l;
+    return l;
+}
+
+// FAST-9 score of the staged pixel (x, staged row sr), 0 unless it reaches t.
+__device__ __forceinline__ int fast_score(const unsigned char *px, int S, int sr, int x, int t)
+{
+    const unsigned char *p = px + sr * S + x;
+    const int c = p[0];
+    const int hi = c + t, lo = c - t;
+    const int n0 = p[-3 * S], n4 = p[3], n8 = p[3 * S], n12 = p[-3];
+    // nine consecutive ring pixels always include two neighbouring compass points
+    const bool b0 = n0 > hi, b4 = n4 > hi, b8 = n8 > hi, b12 = n12 > hi;
+    const bool d0 = n0 < lo, d4 = n4 < lo, d8 = n8 < lo, d12 = n12 < lo;
+    const bool maybe = (b0 && b4) || (b4 && b8) || (b8 && b12) || (b12 && b0) || (d0 && d4) || (d4 && d8) ||
+                       (d8 && d12) || (d12 && d0);
+    if (!maybe) return 0;
+    int e[16];
+    _Pragma("unroll") for (int k = 0; k < 16; ++k) e[k] = (int)p[kRingDy[k] * S + kRingDx[k]] - c;
+    // sliding minimum / maximum over nine consecutive ring pixels by doubling
+    int mn2[16], mx2[16], mn4[16], mx4[16];
+    _Pragma("unroll") for (int k = 0; k < 16; ++k)
+    {
+        mn2[k] = min(e[k], e[(k + 1) & 15]);
+        mx2[k] = max(e[k], e[(k + 1) & 15]);
+    }
+    _Pragma("unroll") for (int k = 0; k < 16; ++k)
+    {
+        mn4[k] = min(mn2[k], mn2[(k + 2) & 15]);
+        mx4[k] = max(mx2[k], mx2[(k + 2) & 15]);
+    }
+    int bright = -256, dark = 256;   // best arc minimum; smallest arc maximum
+    _Pragma("unroll") for (int k = 0; k < 16; ++k)
+    {
+        const int mn9 = min(min(mn4[k], mn4[(k + 4) & 15]), e[(k + 8) & 15]);
+        const int mx9 = max(max(mx4[k], mx4[(k + 4) & 15]), e[(k + 8) & 15]);
+        bright = max(bright, mn9);
+        dark = min(dark, mx9);
+    }
+    const int s = max(bright, -dark) - 1;
+    return s >= t ? s : 0;
+}
+
+// Stage the tile's level rows (clamped at the level's borders) and fill the
+// score band; returns after a barrier.
+__device__ __forceinline__ void stage_and_score(const OrbDetectArgs &a, int l, int y0, int rows,
+                                                unsigned char *px, unsigned char *sc)
+{
+    const int W = a.w[l], H = a.h[l], S = a.lds_w;
+    const FT_G uint8_t *img = a.pyr + a.off[l];
+    for (int sr = 0; sr < rows + 2 * kOrbHalo; ++sr) {
+        int yy = y0 - kOrbHalo + sr;
+        yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
+        const FT_G uint8_t *src = img + (int64_t)yy * W;
+        for (int x = threadIdx.x; x < W; x += kThreads) px[sr * S + x] = src[x];
+    }
+    __syncthreads();
+    const int E = a.edge;
+    for (int r = 0; r < rows + 2; ++r) {
+        const int yy = y0 - 1 + r;
+        const bool row_in = yy >= E && yy < H - E;
+        for (int x = threadIdx.x; x < W; x += kThreads) {
+            int s = 0;
+            if (row_in && x >= E && x < W - E) s = fast_score(px, S, r + kOrbHalo - 1, x, a.t);
+            sc[r * S + x] = (unsigned char)s;
+        }
+    }
+    __syncthreads();
+}
+
+// Is the corner at output row r, column x kept by the suppression?
+__device__ __forceinline__ bool kept(const unsigned char *sc, int S, int r, int x, int W)
+{
+    if (x >= W) return false;
+    const unsigned char *q = sc + (r + 1) * S + x;
+    const int v = q[0];
+    if (v == 0) return false;
+    // window pixels are >= 19 from every border: the 8 neighbours exist
+    return v > q[-S - 1] && v > q[-S] && v > q[-S + 1] && v > q[-1] && v > q[1] && v > q[S - 1] && v > q[S] &&
+           v > q[S + 1];
+}
+
+__device__ __forceinline__ int block_sum(int v, int *red)
+{
+    _Pragma("unroll") for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    const int s = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_orb_detect(OrbDetectArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int red[4];
+    const int tile = blockIdx.x;
+    const int l = level_of_tile(a, tile);
+    const int W = a.w[l], H = a.h[l], S = a.lds_w;
+    const int y0 = (tile - a.tile0[l]) * kOrbRows;
+    const int rows = min(kOrbRows, H - y0);
+    unsigned char *px = lds;
+    unsigned char *sc = lds + kStaged * S;
+    stage_and_score(a, l, y0, rows, px, sc);
+    int cnt = 0;
+    for (int r = 0; r < rows; ++r)
+        for (int x = threadIdx.x; x < W; x += kThreads) cnt += kept(sc, S, r, x, W) ? 1 : 0;
+    cnt = block_sum(cnt, red);
+    if (threadIdx.x == 0) a.tile_count[tile] = cnt;
+    if (!a.blurred) return;
+    // smoothing: per column, horizontal sums of staged rows 1 .. rows + 6 (level
+    // rows y0 - 3 .. y0 + rows + 2, clamped), then the vertical taps
+    FT_G uint8_t *dst = a.blurred + a.off[l];
+    constexpr int kw[7] = {1, 6, 15, 20, 15, 6, 1};
+    for (int x = threadIdx.x; x < W; x += kThreads) {
+        int xs[7];
+        _Pragma("unroll") for (int i = 0; i < 7; ++i)
+        {
+            const int v = x + i - 3;
+            xs[i] = v < 0 ? 0 : (v > W - 1 ? W - 1 : v);
+        }
+        int hs[kOrbRows + 6];
+        _Pragma("unroll") for (int k = 0; k < kOrbRows + 6; ++k)
+        {
+            const unsigned char *row = px + (k + 1) * S;
+            int acc = 0;
+            _Pragma("unroll") for (int i = 0; i < 7; ++i) acc += kw[i] * row[xs[i]];
+            hs[k] = acc;
+        }
+        _Pragma("unroll") for (int r = 0; r < kOrbRows; ++r)
+        {
+            if (r < rows) {
+                int acc = 0;
+                _Pragma("unroll") for (int j = 0; j < 7; ++j) acc += kw[j] * hs[r + j];
+                dst[(int64_t)(y0 + r) * W + x] = (uint8_t)((acc + 2048) >> 12);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ int red[4];
+    __shared__ int wave_n[4];
+    const int tile = blockIdx.x;
+    const int l = level_of_tile(a, tile);
+    const int W = a.w[l], H = a.h[l], S = a.lds_w;
+    const int y0 = (tile - a.tile0[l]) * kOrbRows;
+    const int rows = min(kOrbRows, H - y0);
+    const int tiles = a.tile0[kLevels];
+    // first output index: the corners of every earlier tile
+    int before = 0, all = 0;
+    for (int k = threadIdx.x; k < tiles; k += kThreads) {
+        const int c = a.tile_count[k];
+        all += c;
+        before += k < tile ? c : 0;
+    }
+    before = block_sum(before, red);
+    if (tile == 0) {
+        all = block_sum(all, red);
+        if (threadIdx.x == 0) a.count[0] = all;
+    }
+    unsigned char *px = lds;
+    unsigned char *sc = lds + kStaged * S;
+    stage_and_score(a, l, y0, rows, px, sc);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int base = before;
+    const float sf = a.sf[l];
+    for (int r = 0; r < rows; ++r)
+        for (int x0 = 0; x0 < W; x0 += kThreads) {
+            const int x = x0 + (int)threadIdx.x;
+            const bool k = kept(sc, S, r, x, W);
+            const uint64_t m = __ballot(k);
+            if (lane == 0) wave_n[wave] = __popcll(m);
+            __syncthreads();
+            int off = base;
+            for (int w = 0; w < wave; ++w) off += wave_n[w];
+            const int chunk = wave_n[0] + wave_n[1] + wave_n[2] + wave_n[3];
+            __syncthreads();
+            if (k) {
+                const int i = off + __popcll(m & below);
+                if (i < a.capacity) {
+                    const int yy = y0 + r;
+                    a.lx[i] = (int16_t)x;
+                    a.ly[i] = (int16_t)yy;
+                    a.oct[i] = (uint8_t)l;
+                    a.score[i] = sc[(r + 1) * S + x];
+                    a.x[i] = (float)x * sf;
+                    a.y[i] = (float)yy * sf;
+                }
+            }
+            base += chunk;
+        }
+}
+
+// The integer nearest num / sqrt(m2), halves away from zero: an estimate in
+// binary64, then exact integer corrections to the largest k >= 0 with k = 0 or
+// (2k - 1)^2 m2 <= 4 num^2.
+__device__ __forceinline__ int round_ratio(int64_t num, int64_t m2)
+{
+    const int64_t a = num < 0 ? -num : num;
+    const int64_t a4 = 4 * a * a;
+    int k = (int)floor((double)a / sqrt((double)m2) + 0.5);
+    if (k < 0) k = 0;
+    while (k > 0 && (int64_t)(2 * k - 1) * (2 * k - 1) * m2 > a4) --k;
+    while ((int64_t)(2 * k + 1) * (2 * k + 1) * m2 <= a4) ++k;
+    return num < 0 ? -k : k;
+}
+
+__global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)((blockIdx.x * kThreads + threadIdx.x) >> 6);
+    const int waves = (int)(gridDim.x * (kThreads / 64));
+    int n = a.n_max;
+    if (a.count) {
+        const int c = a.count[0];
+        n = c < n ? c : n;
+    }
+    for (int i = wave; i < n; i += waves) {
+        const int l = a.oct[i];
+        const int u = a.lx[i], v = a.ly[i];
+        const bool ok = l < kLevels && u >= 15 && v >= 15 && u < a.w[l < kLevels ? l : 0] - 15 &&
+                        v < a.h[l < kLevels ? l : 0] - 15;
+        FT_G uint8_t *d = a.desc + 32 * (int64_t)i;
+        if (!ok) {   // outside the window the disc and the turned pattern need
+            if (lane < 8) reinterpret_cast<FT_G uint32_t *>(d)[lane] = 0u;
+            if (lane == 0) a.angle[i] = -1.0f;
+            continue;
+        }
+        const int W = a.w[l];
+        const FT_G uint8_t *img = a.pyr + a.off[l] + (int64_t)v * W + u;
+        const FT_G uint8_t *B = a.blurred + a.off[l] + (int64_t)v * W + u;
+        int m10 = 0, m01 = 0;
+        for (int k = lane; k < 31 * 32; k += 64) {
+            const int dy = (k >> 5) - 15, dx = (k & 31) - 15;
+            if (dx <= 15 && dx * dx + dy * dy <= 225) {
+                const int I = img[dy * W + dx];
+                m10 += dx * I;
+                m01 += dy * I;
+            }
+        }
+        _Pragma("unroll") for (int o = 32; o > 0; o >>= 1)
+        {
+            m10 += __shfl_xor(m10, o);
+            m01 += __shfl_xor(m01, o);
+        }
+        if (lane == 0) {
+            double ang = atan2((double)m01, (double)m10) * (180.0 / 3.14159265358979323846);
+            if (ang < 0.0) ang += 360.0;
+            a.angle[i] = (float)ang;
+        }
+        const int64_t M10 = m10, M01 = m01;
+        const int64_t m2 = M10 * M10 + M01 * M01;
+        uint64_t mask[4];
+        _Pragma("unroll") for (int q = 0; q < 4; ++q)
+        {
+            const int t = q * 64 + lane;
+            const int x1 = a.pattern[t][0], y1 = a.pattern[t][1], x2 = a.pattern[t][2], y2 = a.pattern[t][3];
+            int c1 = x1, r1 = y1, c2 = x2, r2 = y2;
+            if (m2 > 0) {
+                c1 = round_ratio(x1 * M10 - y1 * M01, m2);
+                r1 = round_ratio(x1 * M01 + y1 * M10, m2);
+                c2 = round_ratio(x2 * M10 - y2 * M01, m2);
+                r2 = round_ratio(x2 * M01 + y2 * M10, m2);
+            }
+            const bool bit = B[r1 * W + c1] < B[r2 * W + c2];
+            mask[q] = __ballot(bit);
+        }
+        if (lane < 4) {
+            const uint64_t mq = lane == 0 ? mask[0] : lane == 1 ? mask[1] : lane == 2 ? mask[2] : mask[3];
+            reinterpret_cast<FT_G uint64_t *>(d)[lane] = mq;
+        }
+    }
+}
+
+}  // namespace
+
+size_t orb_detect_lds(int lds_w) { return (size_t)(kStaged + kScoreRows) * (size_t)lds_w; }
+
+hipError_t launch_orb_detect(const OrbDetectArgs &a, hipStream_t s)
+{
+    const int tiles = a.tile0[kLevels];
+    if (tiles <= 0) return hipSuccess;
+    const size_t lds = orb_detect_lds(a.lds_w);
+    hipLaunchKernelGGL(k_orb_detect, dim3(tiles), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL(k_orb_emit, dim3(tiles), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_orb_describe(const OrbDescribeArgs &a, hipStream_t s)
+{
+    if (a.n_max <= 0) return hipSuccess;
+    const int per_block = kThreads / 64;
+    int blocks = (a.n_max + per_block - 1) / per_block;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_orb_describe, dim3(blocks), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ft
