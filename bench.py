@@ -22,12 +22,17 @@ Beside the headline the default run also reports:
     roofline warm and cold);
   * the last-frame search by projection (Initial Pose Estimation) on the
     pinhole frame and both fisheye views: per-call p50/p99;
+  * ORB extraction of the benchmark's 64 pinhole images (FAST-9 corners on
+    all eight levels, every corner described): images/s, corners per image,
+    detection and description times and the detection pair's roofline;
   * local-map maintenance on the device: a 20000-point map with 5% of its
     points replaced per edit, against uploading the whole map again;
   * a bounded serving sweep (32 camera streams, resident maps of 2k-40k
     points): per-frame path and continuous batching over the same Poisson
     arrivals, frames/s at equal p99, and a sample of frames served inside
     overlapping batches checked bit for bit against the same frames alone;
+    then the same streams with 5% of every local map replaced before each
+    frame (maps edited in place on the device, frames of a stream in order);
   * the CPU oracle on the same frames, one thread and on all host cores (the
     host's CPU model and core count recorded), and on each single-frame
     workload.
@@ -341,6 +346,78 @@ def search_roofline(nbytes, us, traffic, note):
             "timed": note}
 
 
+def orb_leg(ctx, ft, frames, streams, steps, timing=True, flush=None):
+    """ORB extraction of the benchmark's pinhole images (both images of each
+    pinhole frame, 752x480, eight levels): detection (two kernels) then
+    description of every detected corner, per image, images spread over the
+    submission streams; throughput, corners per image, and HIP-event times of
+    the detection pair and the description on one stream."""
+    import numpy as np
+    import torch
+
+    import synth
+    pat = synth.orb_pattern()
+    sc = ft._scales(synth.scale_tables())
+    imgs = [f[side] for f in frames if f["kind"] == "pinhole" for side in ("pyr_left", "pyr_right")]
+    orbs = [ft.DeviceOrb(p, capacity=65536) for p in imgs]
+
+    def run_all():
+        for k, d in enumerate(orbs):
+            st = streams[k % len(streams)]
+            d.detect(ctx, sc, stream=st)
+            d.describe(ctx, pat, stream=st)
+
+    for _ in range(3):
+        run_all()
+    torch.cuda.synchronize()
+    n = max(10, steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        run_all()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    counts = [int(d.t["count"][0]) for d in orbs]
+    out = {"workload": f"{len(imgs)} EuRoC-like 752x480 images (both images of the benchmark's pinhole frames), "
+                       "8-level pyramids resident on the device; FAST threshold 20, every corner described",
+           "images_per_s": round(len(imgs) * n / dt, 1), "rounds": n, "streams": len(streams),
+           "corners_per_image": {"mean": round(float(np.mean(counts)), 1), "min": int(min(counts)),
+                                 "max": int(max(counts))}}
+    if not timing:
+        return out
+
+    def per_image(flush_each):
+        st = streams[0]
+        det, des = [], []
+        for d in orbs:
+            if flush_each is not None:
+                flush_each()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(st)
+            d.detect(ctx, sc, stream=st)
+            e[1].record(st)
+            d.describe(ctx, pat, stream=st)
+            e[2].record(st)
+            st.synchronize()
+            det.append(e[0].elapsed_time(e[1]) * 1e3)
+            des.append(e[1].elapsed_time(e[2]) * 1e3)
+        return float(np.mean(det)), float(np.mean(des))
+    det_us, des_us = per_image(None)
+    cold = per_image(flush)
+    pyr_bytes = int(np.mean([d.pyr_t.numel() for d in orbs]))
+    # detection: the pyramid read once, the smoothed pyramid written once, 14 B per corner written
+    det_bytes = 2 * pyr_bytes + 14 * int(np.mean(counts))
+    achieved = det_bytes / (det_us * 1e-6) / 1e9
+    out["detect_us"] = round(det_us, 2)
+    out["describe_us"] = round(des_us, 2)
+    out["describe_ns_per_corner"] = round(des_us * 1e3 / max(np.mean(counts), 1), 2)
+    out["cold"] = {"detect_us": round(cold[0], 2), "describe_us": round(cold[1], 2)}
+    out["roofline"] = {"bound": "hbm", "kernel": "k_orb_detect + k_orb_emit (one image)", "achieved": round(achieved, 2),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                       "algorithmic_bytes_per_launch": det_bytes, "avg_launch_us": round(det_us, 3),
+                       "timed": "HIP events around the detection pair of each image on one stream, warm caches"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,7 +436,7 @@ def main():
                     help="seconds per arrival rate of the serving sweep (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the single-frame workloads and the clustered batch")
-    ap.add_argument("--only", choices=["mixed", "clustered", "pyramids"], default=None,
+    ap.add_argument("--only", choices=["mixed", "clustered", "pyramids", "orb"], default=None,
                     help="profiling runs: only the timed region of one workload, no other legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration) and exit")
@@ -418,6 +495,10 @@ def main():
               for _ in range(1 if profiling else max_streams)]
     dfs = copies[0]
     job_sets = [[d.job() for d in c] for c in copies]
+    if args.only == "orb":
+        r = orb_leg(ctx, ft, frames, [torch.cuda.current_stream()], args.steps, timing=False)
+        print(json.dumps({"workload": "orb", **r}))
+        return
     jobs = job_sets[0]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(len(copies) - 1)]
     stream = streams[0]
@@ -678,6 +759,13 @@ def main():
                                    "matches": dl.results()["n_matches"], "reps": reps}
                 log("last frame", key, last_frame[key])
 
+    # ---- ORB extraction on the device (Section II-A, IV-B)
+    orb = None
+    if not args.no_extra:
+        log("orb extraction")
+        orb = orb_leg(ctx, ft, frames, streams, args.steps, timing=not args.no_timing, flush=flush)
+        log("orb", {k: v for k, v in orb.items() if k != "workload"})
+
     # ---- local-map maintenance on the device: a 20000-point map edited per
     # frame (5% of its points replaced; the kernels read the removal pairs and
     # the inserted points from pinned host memory) against uploading the whole
@@ -765,6 +853,7 @@ def main():
         "clustered_batch64": clustered,
         "device_pyramids": pyramids,
         "map_maintenance": map_maint,
+        "orb_extraction": orb,
         "last_frame_search": last_frame,
         "serving": serving,
     }

@@ -80,20 +80,56 @@ __device__ __forceinline__ int fast_score(const unsigned char *px, int S, int sr
     return s >= t ? s : 0;
 }
 
-// Stage the tile's level rows (clamped at the level's borders) and fill the
-// score band; returns after a barrier.
-__device__ __forceinline__ void stage_and_score(const OrbDetectArgs &a, int l, int y0, int rows,
-                                                unsigned char *px, unsigned char *sc)
+// Stage the tile's level rows (clamped at the level's borders) into LDS with
+// row stride W, and fill the score band (stride W); returns after a barrier.
+// `lds` is 16-byte aligned; the staged rows start at the returned pointer.
+// Interior tiles copy one contiguous range: aligned dwords (every load issued
+// before the LDS stores), bytes at the two ragged ends; a tile whose halo
+// leaves the level copies row by row with clamped row indices.
+__device__ __forceinline__ unsigned char *stage_and_score(const OrbDetectArgs &a, int l, int y0, int rows,
+                                                          unsigned char *lds)
 {
-    const int W = a.w[l], H = a.h[l], S = a.lds_w;
+    const int W = a.w[l], H = a.h[l];
     const FT_G uint8_t *img = a.pyr + a.off[l];
-    for (int sr = 0; sr < rows + 2 * kOrbHalo; ++sr) {
-        int yy = y0 - kOrbHalo + sr;
-        yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
-        const FT_G uint8_t *src = img + (int64_t)yy * W;
-        for (int x = threadIdx.x; x < W; x += kThreads) px[sr * S + x] = src[x];
+    const int n_staged = rows + 2 * kOrbHalo;
+    unsigned char *px;
+    if (y0 - kOrbHalo >= 0 && y0 + rows + kOrbHalo <= H) {
+        const FT_G uint8_t *g0 = img + (int64_t)(y0 - kOrbHalo) * W;
+        const int len = n_staged * W;
+        const uintptr_t ga = reinterpret_cast<uintptr_t>(g0);
+        const int sh = (int)(ga & 3u);
+        px = lds + sh;                                   // px[i] = g0[i]; aligned dwords land aligned
+        const int head = sh ? 4 - sh : 0;                // bytes before the first aligned dword
+        const int nd = (len - head) >> 2;                // whole aligned dwords
+        const FT_G uint32_t *gd = reinterpret_cast<const FT_G uint32_t *>(g0 + head);
+        uint32_t *ld = reinterpret_cast<uint32_t *>(px + head);
+        constexpr int kMaxPer = (kStaged * kMaxPyrW / 4 + kThreads - 1) / kThreads;
+        uint32_t v[kMaxPer];
+        _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
+        {
+            const int j = (int)threadIdx.x + k * kThreads;
+            if (j < nd) v[k] = gd[j];
+        }
+        _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
+        {
+            const int j = (int)threadIdx.x + k * kThreads;
+            if (j < nd) ld[j] = v[k];
+        }
+        const int tail0 = head + 4 * nd;
+        if ((int)threadIdx.x < head) px[threadIdx.x] = g0[threadIdx.x];
+        if ((int)threadIdx.x < len - tail0) px[tail0 + threadIdx.x] = g0[tail0 + threadIdx.x];
+    } else {
+        px = lds;
+        for (int sr = 0; sr < n_staged; ++sr) {
+            int yy = y0 - kOrbHalo + sr;
+            yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
+            const FT_G uint8_t *src = img + (int64_t)yy * W;
+            for (int x = threadIdx.x; x < W; x += kThreads) px[sr * W + x] = src[x];
+        }
     }
     __syncthreads();
+    const int S = W;
+    unsigned char *sc = lds + 4 + kStaged * a.lds_w;    // after the staged rows and their slack
     const int E = a.edge;
     for (int r = 0; r < rows + 2; ++r) {
         const int yy = y0 - 1 + r;
@@ -105,6 +141,12 @@ __device__ __forceinline__ void stage_and_score(const OrbDetectArgs &a, int l, i
         }
     }
     __syncthreads();
+    return px;
+}
+
+__device__ __forceinline__ unsigned char *score_band(const OrbDetectArgs &a, unsigned char *lds)
+{
+    return lds + 4 + kStaged * a.lds_w;
 }
 
 // Is the corner at output row r, column x kept by the suppression?
@@ -136,12 +178,11 @@ __global__ __launch_bounds__(kThreads) void k_orb_detect(OrbDetectArgs a)
     __shared__ int red[4];
     const int tile = blockIdx.x;
     const int l = level_of_tile(a, tile);
-    const int W = a.w[l], H = a.h[l], S = a.lds_w;
+    const int W = a.w[l], H = a.h[l], S = W;
     const int y0 = (tile - a.tile0[l]) * kOrbRows;
     const int rows = min(kOrbRows, H - y0);
-    unsigned char *px = lds;
-    unsigned char *sc = lds + kStaged * S;
-    stage_and_score(a, l, y0, rows, px, sc);
+    const unsigned char *px = stage_and_score(a, l, y0, rows, lds);
+    const unsigned char *sc = score_band(a, lds);
     int cnt = 0;
     for (int r = 0; r < rows; ++r)
         for (int x = threadIdx.x; x < W; x += kThreads) cnt += kept(sc, S, r, x, W) ? 1 : 0;
@@ -185,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
     __shared__ int wave_n[4];
     const int tile = blockIdx.x;
     const int l = level_of_tile(a, tile);
-    const int W = a.w[l], H = a.h[l], S = a.lds_w;
+    const int W = a.w[l], H = a.h[l], S = W;
     const int y0 = (tile - a.tile0[l]) * kOrbRows;
     const int rows = min(kOrbRows, H - y0);
     const int tiles = a.tile0[kLevels];
@@ -201,9 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
         all = block_sum(all, red);
         if (threadIdx.x == 0) a.count[0] = all;
     }
-    unsigned char *px = lds;
-    unsigned char *sc = lds + kStaged * S;
-    stage_and_score(a, l, y0, rows, px, sc);
+    stage_and_score(a, l, y0, rows, lds);
+    const unsigned char *sc = score_band(a, lds);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     int base = before;
@@ -235,18 +275,39 @@ __global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
         }
 }
 
-// The integer nearest num / sqrt(m2), halves away from zero: an estimate in
-// binary64, then exact integer corrections to the largest k >= 0 with k = 0 or
-// (2k - 1)^2 m2 <= 4 num^2.
-__device__ __forceinline__ int round_ratio(int64_t num, int64_t m2)
+// The integer nearest num / sqrt(m2), halves away from zero, decided exactly:
+// the largest k >= 0 with k = 0 or (2k - 1)^2 m2 <= 4 num^2, with num's sign;
+// found from a binary64 estimate by exact integer corrections.
+__device__ __forceinline__ int round_ratio_exact(int num, int64_t m2)
 {
-    const int64_t a = num < 0 ? -num : num;
+    const int64_t a = num < 0 ? -(int64_t)num : (int64_t)num;
     const int64_t a4 = 4 * a * a;
     int k = (int)floor((double)a / sqrt((double)m2) + 0.5);
     if (k < 0) k = 0;
     while (k > 0 && (int64_t)(2 * k - 1) * (2 * k - 1) * m2 > a4) --k;
     while ((int64_t)(2 * k + 1) * (2 * k + 1) * m2 <= a4) ++k;
     return num < 0 ? -k : k;
+}
+
+// The same integer from a binary32 estimate |num| * (1 / sqrt(m2)): turned
+// pattern coordinates are at most 13, where the estimate is within 4e-6 of the
+// exact quotient, so unless it lies within 1e-4 of a half its rounding is the
+// exact one; `near` is set otherwise (the caller then decides exactly).
+__device__ __forceinline__ int turn_fast(int num, float inv_r, bool &near)
+{
+    const int a = num < 0 ? -num : num;
+    const float q = (float)a * inv_r;
+    const float fr = q - floorf(q);
+    near |= !(fabsf(fr - 0.5f) > 1e-4f);
+    const int k = (int)(q + 0.5f);
+    return num < 0 ? -k : k;
+}
+
+__device__ __forceinline__ float angle_deg(int m10, int m01)
+{
+    double ang = atan2((double)m01, (double)m10) * (180.0 / 3.14159265358979323846);
+    if (ang < 0.0) ang += 360.0;
+    return (float)ang;
 }
 
 __global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
@@ -259,66 +320,107 @@ __global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
         const int c = a.count[0];
         n = c < n ? c : n;
     }
-    for (int i = wave; i < n; i += waves) {
+    // this lane's four tests (t = 64 q + lane), held for the whole kernel
+    int tx1[4], ty1[4], tx2[4], ty2[4];
+    _Pragma("unroll") for (int q = 0; q < 4; ++q)
+    {
+        const int t = q * 64 + lane;
+        tx1[q] = a.pattern[t][0];
+        ty1[q] = a.pattern[t][1];
+        tx2[q] = a.pattern[t][2];
+        ty2[q] = a.pattern[t][3];
+    }
+    // disc geometry of this lane: column dx for all 16 positions, rows dy0 + 2j
+    const int dx = (lane & 31) - 15, dxl = dx < 15 ? dx : 15;
+    const int dy0 = (lane >> 5) - 15;
+    // angles: lane (slot % 64) keeps the moments of the wave's slot-th
+    // keypoint; every 64 slots (and at the end) each lane converts its own
+    int keep_i = -1, keep_m10 = 0, keep_m01 = 0;
+    int slot = 0;
+    for (int i = wave; i < n; i += waves, ++slot) {
         const int l = a.oct[i];
         const int u = a.lx[i], v = a.ly[i];
         const bool ok = l < kLevels && u >= 15 && v >= 15 && u < a.w[l < kLevels ? l : 0] - 15 &&
                         v < a.h[l < kLevels ? l : 0] - 15;
         FT_G uint8_t *d = a.desc + 32 * (int64_t)i;
+        int m10 = 0, m01 = 0;
         if (!ok) {   // outside the window the disc and the turned pattern need
             if (lane < 8) reinterpret_cast<FT_G uint32_t *>(d)[lane] = 0u;
-            if (lane == 0) a.angle[i] = -1.0f;
-            continue;
-        }
-        const int W = a.w[l];
-        const FT_G uint8_t *img = a.pyr + a.off[l] + (int64_t)v * W + u;
-        const FT_G uint8_t *B = a.blurred + a.off[l] + (int64_t)v * W + u;
-        int m10 = 0, m01 = 0;
-        for (int k = lane; k < 31 * 32; k += 64) {
-            const int dy = (k >> 5) - 15, dx = (k & 31) - 15;
-            if (dx <= 15 && dx * dx + dy * dy <= 225) {
-                const int I = img[dy * W + dx];
-                m10 += dx * I;
-                m01 += dy * I;
+        } else {
+            const int W = a.w[l];
+            const FT_G uint8_t *img = a.pyr + a.off[l] + (int64_t)v * W + u;
+            const FT_G uint8_t *B = a.blurred + a.off[l] + (int64_t)v * W + u;
+            // the 32 x 32 square from (-15, -15): 16 positions per lane, every
+            // load issued before any is used (row and column 16, outside the
+            // disc, load a pixel of row or column 15 and weigh 0)
+            int pix[16];
+            _Pragma("unroll") for (int j = 0; j < 16; ++j)
+            {
+                const int dy = dy0 + 2 * j;
+                pix[j] = img[(dy < 15 ? dy : 15) * W + dxl];
+            }
+            int sx = 0;
+            _Pragma("unroll") for (int j = 0; j < 16; ++j)
+            {
+                const int dy = dy0 + 2 * j;
+                const int w = (dx <= 15 && dx * dx + dy * dy <= 225) ? pix[j] : 0;
+                sx += w;
+                m01 += dy * w;
+            }
+            m10 = dx * sx;
+            _Pragma("unroll") for (int o = 32; o > 0; o >>= 1)
+            {
+                m10 += __shfl_xor(m10, o);
+                m01 += __shfl_xor(m01, o);
+            }
+            const int64_t m2 = (int64_t)m10 * m10 + (int64_t)m01 * m01;
+            const float inv_r = m2 > 0 ? rsqrtf((float)m2) : 0.0f;
+            // per test: the two turned points (binary32 estimates, the exact
+            // decision when one lies near a half), then their smoothed pixels
+            uint64_t mask[4];
+            _Pragma("unroll") for (int q = 0; q < 4; ++q)
+            {
+                const int n0 = tx1[q] * m10 - ty1[q] * m01, n1 = tx1[q] * m01 + ty1[q] * m10;
+                const int n2 = tx2[q] * m10 - ty2[q] * m01, n3 = tx2[q] * m01 + ty2[q] * m10;
+                int c1 = tx1[q], r1 = ty1[q], c2 = tx2[q], r2 = ty2[q];
+                if (m2 > 0) {
+                    bool near = false;
+                    c1 = turn_fast(n0, inv_r, near);
+                    r1 = turn_fast(n1, inv_r, near);
+                    c2 = turn_fast(n2, inv_r, near);
+                    r2 = turn_fast(n3, inv_r, near);
+                    if (near) {
+                        c1 = round_ratio_exact(n0, m2);
+                        r1 = round_ratio_exact(n1, m2);
+                        c2 = round_ratio_exact(n2, m2);
+                        r2 = round_ratio_exact(n3, m2);
+                    }
+                }
+                mask[q] = __ballot(B[r1 * W + c1] < B[r2 * W + c2]);
+            }
+            if (lane < 4) {
+                const uint64_t mq = lane == 0 ? mask[0] : lane == 1 ? mask[1] : lane == 2 ? mask[2] : mask[3];
+                reinterpret_cast<FT_G uint64_t *>(d)[lane] = mq;
             }
         }
-        _Pragma("unroll") for (int o = 32; o > 0; o >>= 1)
-        {
-            m10 += __shfl_xor(m10, o);
-            m01 += __shfl_xor(m01, o);
+        if (lane == (slot & 63)) {
+            keep_i = ok ? i : -2 - i;
+            keep_m10 = m10;
+            keep_m01 = m01;
         }
-        if (lane == 0) {
-            double ang = atan2((double)m01, (double)m10) * (180.0 / 3.14159265358979323846);
-            if (ang < 0.0) ang += 360.0;
-            a.angle[i] = (float)ang;
-        }
-        const int64_t M10 = m10, M01 = m01;
-        const int64_t m2 = M10 * M10 + M01 * M01;
-        uint64_t mask[4];
-        _Pragma("unroll") for (int q = 0; q < 4; ++q)
-        {
-            const int t = q * 64 + lane;
-            const int x1 = a.pattern[t][0], y1 = a.pattern[t][1], x2 = a.pattern[t][2], y2 = a.pattern[t][3];
-            int c1 = x1, r1 = y1, c2 = x2, r2 = y2;
-            if (m2 > 0) {
-                c1 = round_ratio(x1 * M10 - y1 * M01, m2);
-                r1 = round_ratio(x1 * M01 + y1 * M10, m2);
-                c2 = round_ratio(x2 * M10 - y2 * M01, m2);
-                r2 = round_ratio(x2 * M01 + y2 * M10, m2);
-            }
-            const bool bit = B[r1 * W + c1] < B[r2 * W + c2];
-            mask[q] = __ballot(bit);
-        }
-        if (lane < 4) {
-            const uint64_t mq = lane == 0 ? mask[0] : lane == 1 ? mask[1] : lane == 2 ? mask[2] : mask[3];
-            reinterpret_cast<FT_G uint64_t *>(d)[lane] = mq;
+        if ((slot & 63) == 63) {
+            if (keep_i >= 0) a.angle[keep_i] = angle_deg(keep_m10, keep_m01);
+            else if (keep_i < -1) a.angle[-2 - keep_i] = -1.0f;
+            keep_i = -1;
         }
     }
+    if (keep_i >= 0) a.angle[keep_i] = angle_deg(keep_m10, keep_m01);
+    else if (keep_i < -1) a.angle[-2 - keep_i] = -1.0f;
 }
 
 }  // namespace
 
-size_t orb_detect_lds(int lds_w) { return (size_t)(kStaged + kScoreRows) * (size_t)lds_w; }
+size_t orb_detect_lds(int lds_w) { return (size_t)(kStaged + kScoreRows) * (size_t)lds_w + 8; }
 
 hipError_t launch_orb_detect(const OrbDetectArgs &a, hipStream_t s)
 {
