@@ -2,7 +2,7 @@
 // are extracted on every scale and described; Section IV-B: the extraction
 // runs next to the pyramid on the device).
 //
-//  * k_orb_detect: one 256-thread workgroup per tile of kOrbRows rows of one
+//  * k_orb_detect: one 1024-thread workgroup per tile of kOrbRows rows of one
 //    level.  The tile's level rows and kOrbHalo rows above and below are
 //    staged in LDS; FAST-9 scores (a compass-point quick test first) fill a
 //    score band one row larger on each side; strict 3x3 suppression counts
@@ -26,7 +26,8 @@ namespace ft {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;      // description: one wave per keypoint, 4 waves per workgroup
+constexpr int kDetThreads = 1024;  // detection: one tile per workgroup, 4 waves per SIMD
 constexpr int kStaged = kOrbRows + 2 * kOrbHalo;   // level rows staged per tile
 constexpr int kScoreRows = kOrbRows + 2;           // score rows: the tile and one row each side
 
@@ -103,16 +104,16 @@ __device__ __forceinline__ unsigned char *stage_and_score(const OrbDetectArgs &a
         const int nd = (len - head) >> 2;                // whole aligned dwords
         const FT_G uint32_t *gd = reinterpret_cast<const FT_G uint32_t *>(g0 + head);
         uint32_t *ld = reinterpret_cast<uint32_t *>(px + head);
-        constexpr int kMaxPer = (kStaged * kMaxPyrW / 4 + kThreads - 1) / kThreads;
+        constexpr int kMaxPer = (kStaged * kMaxPyrW / 4 + kDetThreads - 1) / kDetThreads;
         uint32_t v[kMaxPer];
         _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
         {
-            const int j = (int)threadIdx.x + k * kThreads;
+            const int j = (int)threadIdx.x + k * kDetThreads;
             if (j < nd) v[k] = gd[j];
         }
         _Pragma("unroll") for (int k = 0; k < kMaxPer; ++k)
         {
-            const int j = (int)threadIdx.x + k * kThreads;
+            const int j = (int)threadIdx.x + k * kDetThreads;
             if (j < nd) ld[j] = v[k];
         }
         const int tail0 = head + 4 * nd;
@@ -124,7 +125,7 @@ __device__ __forceinline__ unsigned char *stage_and_score(const OrbDetectArgs &a
             int yy = y0 - kOrbHalo + sr;
             yy = yy < 0 ? 0 : (yy > H - 1 ? H - 1 : yy);
             const FT_G uint8_t *src = img + (int64_t)yy * W;
-            for (int x = threadIdx.x; x < W; x += kThreads) px[sr * W + x] = src[x];
+            for (int x = threadIdx.x; x < W; x += kDetThreads) px[sr * W + x] = src[x];
         }
     }
     __syncthreads();
@@ -134,7 +135,7 @@ __device__ __forceinline__ unsigned char *stage_and_score(const OrbDetectArgs &a
     for (int r = 0; r < rows + 2; ++r) {
         const int yy = y0 - 1 + r;
         const bool row_in = yy >= E && yy < H - E;
-        for (int x = threadIdx.x; x < W; x += kThreads) {
+        for (int x = threadIdx.x; x < W; x += kDetThreads) {
             int s = 0;
             if (row_in && x >= E && x < W - E) s = fast_score(px, S, r + kOrbHalo - 1, x, a.t);
             sc[r * S + x] = (unsigned char)s;
@@ -161,21 +162,24 @@ __device__ __forceinline__ bool kept(const unsigned char *sc, int S, int r, int 
            v > q[S + 1];
 }
 
+constexpr int kDetWaves = kDetThreads / 64;
+
 __device__ __forceinline__ int block_sum(int v, int *red)
 {
     _Pragma("unroll") for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    const int s = red[0] + red[1] + red[2] + red[3];
+    int s = 0;
+    _Pragma("unroll") for (int w = 0; w < kDetWaves; ++w) s += red[w];
     __syncthreads();
     return s;
 }
 
-__global__ __launch_bounds__(kThreads) void k_orb_detect(OrbDetectArgs a)
+__global__ __launch_bounds__(kDetThreads, 8) void k_orb_detect(OrbDetectArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int red[4];
+    __shared__ int red[kDetWaves];
     const int tile = blockIdx.x;
     const int l = level_of_tile(a, tile);
     const int W = a.w[l], H = a.h[l], S = W;
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void k_orb_detect(OrbDetectArgs a)
     const unsigned char *sc = score_band(a, lds);
     int cnt = 0;
     for (int r = 0; r < rows; ++r)
-        for (int x = threadIdx.x; x < W; x += kThreads) cnt += kept(sc, S, r, x, W) ? 1 : 0;
+        for (int x = threadIdx.x; x < W; x += kDetThreads) cnt += kept(sc, S, r, x, W) ? 1 : 0;
     cnt = block_sum(cnt, red);
     if (threadIdx.x == 0) a.tile_count[tile] = cnt;
     if (!a.blurred) return;
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_orb_detect(OrbDetectArgs a)
     // rows y0 - 3 .. y0 + rows + 2, clamped), then the vertical taps
     FT_G uint8_t *dst = a.blurred + a.off[l];
     constexpr int kw[7] = {1, 6, 15, 20, 15, 6, 1};
-    for (int x = threadIdx.x; x < W; x += kThreads) {
+    for (int x = threadIdx.x; x < W; x += kDetThreads) {
         int xs[7];
         _Pragma("unroll") for (int i = 0; i < 7; ++i)
         {
@@ -219,11 +223,11 @@ __global__ __launch_bounds__(kThreads) void k_orb_detect(OrbDetectArgs a)
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
+__global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int red[4];
-    __shared__ int wave_n[4];
+    __shared__ int red[kDetWaves];
+    __shared__ int wave_n[kDetWaves];
     const int tile = blockIdx.x;
     const int l = level_of_tile(a, tile);
     const int W = a.w[l], H = a.h[l], S = W;
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
     const int tiles = a.tile0[kLevels];
     // first output index: the corners of every earlier tile
     int before = 0, all = 0;
-    for (int k = threadIdx.x; k < tiles; k += kThreads) {
+    for (int k = threadIdx.x; k < tiles; k += kDetThreads) {
         const int c = a.tile_count[k];
         all += c;
         before += k < tile ? c : 0;
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
     int base = before;
     const float sf = a.sf[l];
     for (int r = 0; r < rows; ++r)
-        for (int x0 = 0; x0 < W; x0 += kThreads) {
+        for (int x0 = 0; x0 < W; x0 += kDetThreads) {
             const int x = x0 + (int)threadIdx.x;
             const bool k = kept(sc, S, r, x, W);
             const uint64_t m = __ballot(k);
@@ -257,7 +261,8 @@ __global__ __launch_bounds__(kThreads) void k_orb_emit(OrbDetectArgs a)
             __syncthreads();
             int off = base;
             for (int w = 0; w < wave; ++w) off += wave_n[w];
-            const int chunk = wave_n[0] + wave_n[1] + wave_n[2] + wave_n[3];
+            int chunk = 0;
+            _Pragma("unroll") for (int w = 0; w < kDetWaves; ++w) chunk += wave_n[w];
             __syncthreads();
             if (k) {
                 const int i = off + __popcll(m & below);
@@ -427,8 +432,8 @@ hipError_t launch_orb_detect(const OrbDetectArgs &a, hipStream_t s)
     const int tiles = a.tile0[kLevels];
     if (tiles <= 0) return hipSuccess;
     const size_t lds = orb_detect_lds(a.lds_w);
-    hipLaunchKernelGGL(k_orb_detect, dim3(tiles), dim3(kThreads), lds, s, a);
-    hipLaunchKernelGGL(k_orb_emit, dim3(tiles), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL(k_orb_detect, dim3(tiles), dim3(kDetThreads), lds, s, a);
+    hipLaunchKernelGGL(k_orb_emit, dim3(tiles), dim3(kDetThreads), lds, s, a);
     return hipGetLastError();
 }
 
