@@ -80,9 +80,10 @@ def algorithmic_search_bytes(frames):
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2509_10757_amd", "csrc", "ft_kernels.hip")
+ORB_SOURCE = os.path.join(ROOT, "paper_2509_10757_amd", "csrc", "ft_orb.hip")
 
 
-def measured_traffic(kernel_key, workload):
+def measured_traffic(kernel_key, workload, source=KERNEL_SOURCE):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each scaled by what
     the counter reads for a plain copy of known size), or None when there is no
@@ -90,7 +91,7 @@ def measured_traffic(kernel_key, workload):
     counters were taken."""
     import glob
     import re
-    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    digest = hashlib.sha256(open(source, "rb").read()).hexdigest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*pmc*.md"))):
         m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
         if not m:
@@ -413,6 +414,7 @@ def orb_leg(ctx, ft, frames, streams, steps, timing=True, flush=None):
     out["cold"] = {"detect_us": round(cold[0], 2), "describe_us": round(cold[1], 2)}
     out["roofline"] = {"bound": "hbm", "kernel": "k_orb_detect + k_orb_emit (one image)", "achieved": round(achieved, 2),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                       "traffic": measured_traffic("k_orb_detect+k_orb_emit", "orb_images64", ORB_SOURCE),
                        "algorithmic_bytes_per_launch": det_bytes, "avg_launch_us": round(det_us, 3),
                        "timed": "HIP events around the detection pair of each image on one stream, warm caches"}
     return out
@@ -436,7 +438,7 @@ def main():
                     help="seconds per arrival rate of the serving sweep (0: skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the single-frame workloads and the clustered batch")
-    ap.add_argument("--only", choices=["mixed", "clustered", "pyramids", "orb"], default=None,
+    ap.add_argument("--only", choices=["mixed", "clustered", "pyramids", "orb", "fisheye", "pinhole"], default=None,
                     help="profiling runs: only the timed region of one workload, no other legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (counter calibration) and exit")
@@ -468,6 +470,8 @@ def main():
     else:
         log("generating the 64-frame workload")
         frames = synth.mixed_batch()
+        if args.only in ("fisheye", "pinhole"):   # one kind's 32 frames of it (counter runs)
+            frames = [f for f in frames if f["kind"] == args.only]
     n_frames = len(frames)
 
     single = {} if args.no_extra or profiling else {name: synth.workload(name)[0]
@@ -722,7 +726,8 @@ def main():
             # per image: level 0 read once, every level (level 0 included) written once
             pbytes = sum(int(d.pyr_left_t.numel()) + int(d.pyr_right_t.numel()) +
                          2 * int(d.pyr_left.width[0]) * int(d.pyr_left.height[0]) for d in pdfs if d.build_pyramids)
-            proof = search_roofline(pbytes, pph["pyramid"]["avg_us"], None,
+            proof = search_roofline(pbytes, pph["pyramid"]["avg_us"],
+                                    measured_traffic("k_pyramid<JobTable>", "pyramids_batch64"),
                                     "HIP events around each phase kernel, eager per-phase pass, warm caches")
             proof["kernel"] = "k_pyramid (image pyramids)"
             cold = search_roofline(pbytes, pph_cold["pyramid"]["avg_us"], None,
