@@ -30,6 +30,7 @@ constexpr int kThreads = 256;      // description: one wave per keypoint, 4 wave
 constexpr int kDetThreads = 1024;  // detection: one tile per workgroup, 4 waves per SIMD
 constexpr int kStaged = kOrbRows + 2 * kOrbHalo;   // level rows staged per tile
 constexpr int kScoreRows = kOrbRows + 2;           // score rows: the tile and one row each side
+static_assert(kOrbRows % 2 == 0 && kOrbRows <= 8 && kMaxPyrW < 2048, "emitted corners pack column, row, score");
 
 // The 16 ring pixels at distance 3 (clockwise from straight above).
 __constant__ int8_t kRingDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
@@ -57,25 +58,23 @@ __device__ __forceinline__ int fast_score(const unsigned char *px, int S, int sr
     if (!maybe) return 0;
     int e[16];
     _Pragma("unroll") for (int k = 0; k < 16; ++k) e[k] = (int)p[kRingDy[k] * S + kRingDx[k]] - c;
-    // sliding minimum / maximum over nine consecutive ring pixels by doubling
-    int mn2[16], mx2[16], mn4[16], mx4[16];
-    _Pragma("unroll") for (int k = 0; k < 16; ++k)
-    {
-        mn2[k] = min(e[k], e[(k + 1) & 15]);
-        mx2[k] = max(e[k], e[(k + 1) & 15]);
-    }
-    _Pragma("unroll") for (int k = 0; k < 16; ++k)
-    {
-        mn4[k] = min(mn2[k], mn2[(k + 2) & 15]);
-        mx4[k] = max(mx2[k], mx2[(k + 2) & 15]);
-    }
+    // sliding minimum (bright side), then maximum (dark side), over nine
+    // consecutive ring pixels by doubling; one side at a time keeps the live
+    // set small
     int bright = -256, dark = 256;   // best arc minimum; smallest arc maximum
-    _Pragma("unroll") for (int k = 0; k < 16; ++k)
     {
-        const int mn9 = min(min(mn4[k], mn4[(k + 4) & 15]), e[(k + 8) & 15]);
-        const int mx9 = max(max(mx4[k], mx4[(k + 4) & 15]), e[(k + 8) & 15]);
-        bright = max(bright, mn9);
-        dark = min(dark, mx9);
+        int a2[16], a4[16];
+        _Pragma("unroll") for (int k = 0; k < 16; ++k) a2[k] = min(e[k], e[(k + 1) & 15]);
+        _Pragma("unroll") for (int k = 0; k < 16; ++k) a4[k] = min(a2[k], a2[(k + 2) & 15]);
+        _Pragma("unroll") for (int k = 0; k < 16; ++k)
+            bright = max(bright, min(min(a4[k], a4[(k + 4) & 15]), e[(k + 8) & 15]));
+    }
+    {
+        int a2[16], a4[16];
+        _Pragma("unroll") for (int k = 0; k < 16; ++k) a2[k] = max(e[k], e[(k + 1) & 15]);
+        _Pragma("unroll") for (int k = 0; k < 16; ++k) a4[k] = max(a2[k], a2[(k + 2) & 15]);
+        _Pragma("unroll") for (int k = 0; k < 16; ++k)
+            dark = min(dark, max(max(a4[k], a4[(k + 4) & 15]), e[(k + 8) & 15]));
     }
     const int s = max(bright, -dark) - 1;
     return s >= t ? s : 0;
@@ -150,6 +149,14 @@ __device__ __forceinline__ unsigned char *score_band(const OrbDetectArgs &a, uns
     return lds + 4 + kStaged * a.lds_w;
 }
 
+// A tile's kept corners (emission): strict suppression never keeps two
+// 8-neighbours, so a tile holds at most (kOrbRows / 2) x ceil(W / 2) corners;
+// lds_w is W rounded up to 4, so (kOrbRows / 2) x (lds_w / 2) entries suffice.
+__device__ __forceinline__ uint32_t *corner_list(const OrbDetectArgs &a, unsigned char *lds)
+{
+    return reinterpret_cast<uint32_t *>(lds + 8 + (kStaged + kScoreRows) * a.lds_w);
+}
+
 // Is the corner at output row r, column x kept by the suppression?
 __device__ __forceinline__ bool kept(const unsigned char *sc, int S, int r, int x, int W)
 {
@@ -164,14 +171,21 @@ __device__ __forceinline__ bool kept(const unsigned char *sc, int S, int r, int 
 
 constexpr int kDetWaves = kDetThreads / 64;
 
+// Sum over the workgroup; `red` holds kDetWaves + 1 ints.  The total is formed
+// once, behind a barrier, so no thread keeps the per-wave sums live.
 __device__ __forceinline__ int block_sum(int v, int *red)
 {
     _Pragma("unroll") for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    int s = 0;
-    _Pragma("unroll") for (int w = 0; w < kDetWaves; ++w) s += red[w];
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < kDetWaves; ++w) s += red[w];
+        red[kDetWaves] = s;
+    }
+    __syncthreads();
+    const int s = __builtin_amdgcn_readfirstlane(red[kDetWaves]);
     __syncthreads();
     return s;
 }
@@ -179,7 +193,7 @@ __device__ __forceinline__ int block_sum(int v, int *red)
 __global__ __launch_bounds__(kDetThreads, 8) void k_orb_detect(OrbDetectArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int red[kDetWaves];
+    __shared__ int red[kDetWaves + 1];
     const int tile = blockIdx.x;
     const int l = level_of_tile(a, tile);
     const int W = a.w[l], H = a.h[l], S = W;
@@ -226,7 +240,7 @@ __global__ __launch_bounds__(kDetThreads, 8) void k_orb_detect(OrbDetectArgs a)
 __global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int red[kDetWaves];
+    __shared__ int red[kDetWaves + 1];
     __shared__ int wave_n[kDetWaves];
     const int tile = blockIdx.x;
     const int l = level_of_tile(a, tile);
@@ -248,10 +262,12 @@ __global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
     }
     stage_and_score(a, l, y0, rows, lds);
     const unsigned char *sc = score_band(a, lds);
+    // the tile's corners in (row, column) order, packed column | row << 11 |
+    // score << 14, then written to the outputs contiguously
+    uint32_t *tc = corner_list(a, lds);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    int base = before;
-    const float sf = a.sf[l];
+    int n = 0;
     for (int r = 0; r < rows; ++r)
         for (int x0 = 0; x0 < W; x0 += kDetThreads) {
             const int x = x0 + (int)threadIdx.x;
@@ -259,25 +275,28 @@ __global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
             const uint64_t m = __ballot(k);
             if (lane == 0) wave_n[wave] = __popcll(m);
             __syncthreads();
-            int off = base;
+            int off = n;
             for (int w = 0; w < wave; ++w) off += wave_n[w];
             int chunk = 0;
             _Pragma("unroll") for (int w = 0; w < kDetWaves; ++w) chunk += wave_n[w];
             __syncthreads();
-            if (k) {
-                const int i = off + __popcll(m & below);
-                if (i < a.capacity) {
-                    const int yy = y0 + r;
-                    a.lx[i] = (int16_t)x;
-                    a.ly[i] = (int16_t)yy;
-                    a.oct[i] = (uint8_t)l;
-                    a.score[i] = sc[(r + 1) * S + x];
-                    a.x[i] = (float)x * sf;
-                    a.y[i] = (float)yy * sf;
-                }
-            }
-            base += chunk;
+            if (k) tc[off + __popcll(m & below)] = (uint32_t)x | ((uint32_t)r << 11) | ((uint32_t)sc[(r + 1) * S + x] << 14);
+            n += chunk;
         }
+    __syncthreads();
+    const float sf = a.sf[l];
+    for (int k = threadIdx.x; k < n; k += kDetThreads) {
+        const int i = before + k;
+        if (i >= a.capacity) break;
+        const uint32_t e = tc[k];
+        const int x = (int)(e & 2047u), yy = y0 + (int)((e >> 11) & 7u);
+        a.lx[i] = (int16_t)x;
+        a.ly[i] = (int16_t)yy;
+        a.oct[i] = (uint8_t)l;
+        a.score[i] = (uint8_t)(e >> 14);
+        a.x[i] = (float)x * sf;
+        a.y[i] = (float)yy * sf;
+    }
 }
 
 // The integer nearest num / sqrt(m2), halves away from zero, decided exactly:
@@ -425,7 +444,10 @@ __global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
 
 }  // namespace
 
-size_t orb_detect_lds(int lds_w) { return (size_t)(kStaged + kScoreRows) * (size_t)lds_w + 8; }
+size_t orb_detect_lds(int lds_w)
+{
+    return (size_t)(kStaged + kScoreRows) * (size_t)lds_w + 8 + 4 * (size_t)(kOrbRows / 2) * (size_t)(lds_w / 2);
+}
 
 hipError_t launch_orb_detect(const OrbDetectArgs &a, hipStream_t s)
 {
