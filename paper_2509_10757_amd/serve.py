@@ -251,24 +251,29 @@ class Scheduler:
 # --------------------------------------------------------------------------
 # Device executor
 # --------------------------------------------------------------------------
-def follow_edit(ids, slot_of, rem, insert_ids):
+def follow_edit(ids, n, slot_of, rem, insert_ids):
     """The host's record of which point each map slot holds, carried through
-    one ft_map_update: `ids[slot]` is a point id, `slot_of[id]` its slot (-1:
-    not in the map), `rem` the sorted removed slots.  Removed slots below the
-    new count take the surviving tail points in ascending order, inserted
-    points are appended.  Updates `slot_of` in place and returns the new ids."""
-    ids = np.asarray(ids, dtype=np.int64).copy()
+    one ft_map_update, in time proportional to the edit: `ids[:n]` (an array
+    with room for the map's capacity) holds the point id of each slot,
+    `slot_of[id]` its slot (-1: not in the map), `rem` the sorted removed
+    slots.  Removed slots below the new count take the surviving tail points
+    in ascending order, inserted points are appended.  Updates both arrays in
+    place and returns the new count."""
     rem = np.asarray(rem, dtype=np.int64)
-    n1 = len(ids) - len(rem)
+    insert_ids = np.asarray(insert_ids, dtype=np.int64)
+    n1 = n - len(rem)
     holes = rem[rem < n1]
-    tail = np.ones(len(ids) - n1, dtype=bool)
+    tail = np.ones(n - n1, dtype=bool)
     tail[rem[rem >= n1] - n1] = False
-    src = n1 + np.nonzero(tail)[0]
+    src = n1 + np.flatnonzero(tail)
     slot_of[ids[rem]] = -1
-    ids[holes] = ids[src]
-    ids = np.concatenate([ids[:n1], np.asarray(insert_ids, dtype=np.int64)])
-    slot_of[ids] = np.arange(len(ids))
-    return ids
+    moved = ids[src]
+    ids[holes] = moved
+    slot_of[moved] = holes
+    m = len(insert_ids)
+    ids[n1:n1 + m] = insert_ids
+    slot_of[insert_ids] = np.arange(n1, n1 + m)
+    return n1 + m
 
 def _carve(sizes):
     """Offsets of consecutive 256-byte aligned parts; returns (offsets, total)."""
@@ -326,6 +331,7 @@ class DeviceExecutor:
         n_map = max(max(s["n_map"] for s in streams), 1)
         self.slot_ids, self.slot_of, self.map_seq, self.map_struct, self.ins_block, self.ins_pts = \
             {}, {}, {}, {}, {}, {}
+        self.slot_n = {}
         self.ctx = ft.Context(ft.default_limits(max_kp_per_image=max_kp, max_map_points=n_map,
                                                 max_batch_frames=max_batch, max_inflight=max_inflight))
         self.hip_streams = [torch.cuda.Stream(device=device) for _ in range(max_inflight)]
@@ -380,7 +386,9 @@ class DeviceExecutor:
         if "edits" in s:
             ids0 = np.asarray(s["map_ids0"], dtype=np.int64)
             mp = {k: v[ids0] for k, v in s["points"].items()}
-            self.slot_ids[sid] = ids0.copy()
+            self.slot_ids[sid] = np.zeros(len(ids0), dtype=np.int64)    # the map's capacity
+            self.slot_ids[sid][:] = ids0
+            self.slot_n[sid] = len(ids0)
             self.slot_of[sid] = np.full(len(s["points"]["dmin"]), -1, dtype=np.int64)
             self.slot_of[sid][ids0] = np.arange(len(ids0))
             self.map_seq[sid] = 0
@@ -403,7 +411,7 @@ class DeviceExecutor:
         """Frees what the stream holds on the device (exactly what footprint
         counts); the scheduler calls it once no batch in flight reads it."""
         self.maps.pop(sid, None)
-        for d in (self.slot_ids, self.slot_of, self.map_seq, self.map_struct, self.ins_pts):
+        for d in (self.slot_ids, self.slot_n, self.slot_of, self.map_seq, self.map_struct, self.ins_pts):
             d.pop(sid, None)
         if sid in self.ins_block:
             self.ctx.ft_host_free(self.ins_block.pop(sid))
@@ -466,7 +474,8 @@ class DeviceExecutor:
         ids0 = np.asarray(s["map_ids0"], dtype=np.int64)
         for k, t in self.maps[sid].items():
             t[:len(ids0)].copy_(self.torch.from_numpy(np.ascontiguousarray(s["points"][k][ids0])))
-        self.slot_ids[sid] = ids0.copy()
+        self.slot_ids[sid][:len(ids0)] = ids0
+        self.slot_n[sid] = len(ids0)
         self.slot_of[sid][:] = -1
         self.slot_of[sid][ids0] = np.arange(len(ids0))
         self.map_struct[sid].n = len(ids0)
@@ -485,7 +494,7 @@ class DeviceExecutor:
             assert len(rem) == 0 or rem[0] >= 0, "removed point not in the map"
             self.ctx.ft_map_update(self.map_struct[sid], self.maps[sid]["dmin"].numel(), rem.astype(np.int32),
                                    self.ins_pts[sid][q], stream=hs)
-            self.slot_ids[sid] = follow_edit(ids, slot_of, rem, e["insert_ids"])
+            self.slot_n[sid] = follow_edit(ids, self.slot_n[sid], slot_of, rem, e["insert_ids"])
         self.map_seq[sid] = max(self.map_seq[sid], seq)
 
     def _pack(self, f, at):

@@ -283,13 +283,15 @@ def test_slot_record_follows_the_oracle_edit_rule():
     table = {"pos": np.zeros((n_pts, 3), np.float32), "normal": np.zeros((n_pts, 3), np.float32),
              "dmin": np.arange(n_pts, dtype=np.float32), "dmax": np.zeros(n_pts, np.float32),
              "desc": np.zeros((n_pts, 32), np.uint8)}
-    ids = np.arange(1000)
+    ids = np.zeros(cap, np.int64)
+    ids[:1000] = np.arange(1000)
+    n_live = 1000
     slot_of = np.full(n_pts, -1, np.int64)
-    slot_of[ids] = np.arange(1000)
-    mp = {k: v[ids] for k, v in table.items()}
+    slot_of[:1000] = np.arange(1000)
+    mp = {k: v[ids[:n_live]] for k, v in table.items()}
     unused = list(range(1000, n_pts))
     for step in range(60):
-        n = len(ids)
+        n = n_live
         if step == 0:
             rem = []
         elif step == 1:
@@ -304,8 +306,8 @@ def test_slot_record_follows_the_oracle_edit_rule():
         ins_ids = np.array(unused[:m], np.int64)
         del unused[:m]
         mp = oracle.map_update(mp, cap, rem, {k: v[ins_ids] for k, v in table.items()})
-        ids = follow_edit(ids, slot_of, np.sort(np.asarray(rem, np.int64)), ins_ids)
-        assert np.array_equal(ids, mp["dmin"].astype(np.int64)), step
+        n_live = follow_edit(ids, n_live, slot_of, np.sort(np.asarray(rem, np.int64)), ins_ids)
+        assert np.array_equal(ids[:n_live], mp["dmin"].astype(np.int64)), step
         live = np.nonzero(slot_of >= 0)[0]
-        assert np.array_equal(np.sort(live), np.sort(ids))
-        assert np.array_equal(slot_of[ids], np.arange(len(ids)))
+        assert np.array_equal(np.sort(live), np.sort(ids[:n_live]))
+        assert np.array_equal(slot_of[ids[:n_live]], np.arange(n_live))
