@@ -281,7 +281,7 @@ def serving_sweep(duration_s, per_frame_rates, batched_rates, check_frames=24):
         cex.admit(s["id"])
     cex.autotune()
     crows, cbound, cknee, cbest = _sweep_modes(serve, cex, cstreams, duration_s, per_frame_rates,
-                                               [4, 8, 12, 16, 24, 32, 48])
+                                               [4, 8, 16, 32, 48, 64, 96, 128, 192])
     out["map_churn"] = {"fraction_per_frame": 0.05, "runs": crows, **_at_bound(cbound, cknee, cbest),
                         "points_replaced_per_frame_mean": round(float(np.mean([len(s["edits"][1]["remove_ids"])
                                                                                for s in cstreams])), 1)}

@@ -351,12 +351,25 @@ ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_poin
 /* Local-map maintenance on the device (Update Local Map's output set kept  */
 /* where Search Local Points reads it: Section IV-D, IV-E).                  */
 /* ------------------------------------------------------------------------ */
+/* The caller's record of which point each slot of a device map holds, for
+ * callers that name map points by id (0 .. id_count - 1) rather than by slot:
+ * ft_map_update translates removals given as ids and keeps both arrays. */
+typedef struct ft_map_ids {
+    int32_t *slot_id;          /* HOST [capacity]: point id held by slot s, for s < map->n */
+    int32_t *slot_of;          /* HOST [id_count]: slot of point id i, -1 when i is not in the map */
+    int32_t id_count;
+} ft_map_ids;
+
 typedef struct ft_map_edit {
     int32_t n_remove;
-    const int32_t *remove;     /* HOST [n_remove] indices into the current map: distinct, each < map->n */
+    const int32_t *remove;     /* HOST [n_remove]: slots of the current map (distinct, each < map->n),
+                                  or, with `ids`, point ids in the map (distinct) */
     ft_map_points insert;      /* arrays of the insert.n points to append (a map's layout): DEVICE
                                   memory, or HOST memory inside ft_host_alloc blocks (all five), which
                                   the append kernel reads over the bus: no copy command */
+    const int32_t *insert_ids; /* with `ids`: HOST [insert.n] ids of the inserted points (distinct,
+                                  none in the map); otherwise ignored */
+    ft_map_ids *ids;           /* nullable: the slot record, translated and updated by the call */
 } ft_map_edit;
 
 /* Edits a device-resident map in place.  The listed points leave the map;
@@ -369,13 +382,31 @@ typedef struct ft_map_edit {
  * (the map must not be read on another stream before they complete; host
  * insert arrays must stay unchanged until then).  The (slot, source) pairs
  * are read by the move kernel from the context's pinned staging, so an edit
- * enqueues two kernels and no copy.
- * Errors: a repeated or out-of-range index, null or misaligned arrays, host
- * insert arrays partly outside the ft_host_alloc blocks: FT_ERR_INVALID_ARGUMENT; a result above `capacity`, or n_remove or
- * insert.n above max_map_points: FT_ERR_CAPACITY.  On error map->n is
- * unchanged and nothing is enqueued. */
+ * enqueues two kernels and no copy.  With `edit->ids` the removals are point
+ * ids, and slot_id / slot_of are updated on the host for the moved, removed
+ * and inserted points only (time proportional to the edit).
+ * Errors: a repeated or out-of-range index (or id: outside [0, id_count), not
+ * in the map when removed, already in the map when inserted), null or
+ * misaligned arrays, host insert arrays partly outside the ft_host_alloc
+ * blocks: FT_ERR_INVALID_ARGUMENT; a result above `capacity`, or n_remove or
+ * insert.n above max_map_points: FT_ERR_CAPACITY.  On error map->n and the
+ * id record are unchanged and nothing is enqueued. */
 ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,
                         const ft_map_edit *edit);
+
+/* n edits of n distinct maps in one call (Update Local Map for every frame of
+ * a batch): edits[i] is applied to *maps[i] (HOST array of pointers; each
+ * map's n is updated) within capacities[i], with ft_map_update's rule and
+ * checks.  Every edit is validated before anything is enqueued: on any error
+ * no map, no id record changes and nothing is enqueued.  The edits' pairs and
+ * appends are staged together in the context's pinned staging, copied to the
+ * device in one command, and applied by two kernels for all n maps.  Errors:
+ * as ft_map_update, two edits naming one map: FT_ERR_INVALID_ARGUMENT; more
+ * than 4096 edits, or staging above half the context's edit staging (which is
+ * max(16 x max_map_points, 8 MiB) bytes; a call stages 88 B per edit, 12 B per
+ * moved point and 8 B per inserted point): FT_ERR_CAPACITY. */
+ft_status ft_map_update_many(ft_context *ctx, void *stream, int32_t n, ft_map_points *const *maps,
+                             const int32_t *capacities, const ft_map_edit *edits);
 
 /* ------------------------------------------------------------------------ */
 /* ORB extraction on the device-resident pyramid (Section II-A: keypoints   */

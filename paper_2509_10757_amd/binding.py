@@ -124,8 +124,13 @@ class ft_orb_corners(ct.Structure):
                 ("count", P)]
 
 
+class ft_map_ids(ct.Structure):
+    _fields_ = [("slot_id", P), ("slot_of", P), ("id_count", ct.c_int32)]
+
+
 class ft_map_edit(ct.Structure):
-    _fields_ = [("n_remove", ct.c_int32), ("remove", P), ("insert", ft_map_points)]
+    _fields_ = [("n_remove", ct.c_int32), ("remove", P), ("insert", ft_map_points), ("insert_ids", P),
+                ("ids", ct.POINTER(ft_map_ids))]
 
 
 class ft_image(ct.Structure):
@@ -188,6 +193,7 @@ EXPORTS = {
                              ct.POINTER(ft_keypoints), P, P, P, ct.POINTER(ft_grid), ct.POINTER(ft_scales),
                              ct.POINTER(ft_last_params), ct.POINTER(ft_search_out)],
     "ft_map_update": [P, P, ct.POINTER(ft_map_points), ct.c_int32, ct.POINTER(ft_map_edit)],
+    "ft_map_update_many": [P, P, ct.c_int32, ct.POINTER(ct.POINTER(ft_map_points)), P, ct.POINTER(ft_map_edit)],
     "ft_orb_detect": [P, P, ct.POINTER(ft_pyramid), ct.POINTER(ft_scales), ct.POINTER(ft_orb_params), P,
                       ct.POINTER(ft_orb_corners)],
     "ft_orb_describe": [P, P, ct.POINTER(ft_pyramid), P, ct.c_int32, P, P, P, P, P, P, P],
@@ -370,17 +376,42 @@ class Context:
             self._check(st, "ft_search_last_frame")
         return st
 
-    def ft_map_update(self, map_points, capacity: int, remove, insert, stream=None, check=True):
+    def ft_map_update(self, map_points, capacity: int, remove, insert, stream=None, check=True, ids=None,
+                      insert_ids=None):
         """Edit a device map in place; `map_points.n` is updated.  `remove`:
-        host indices (a sequence), `insert`: an ft_map_points of device arrays
-        (or None)."""
+        host slot indices (a sequence), or point ids when `ids` (an
+        ft_map_ids record, kept by the call) is given; `insert`: an
+        ft_map_points of device or ft_host_alloc arrays (or None);
+        `insert_ids`: the inserted points' ids (with `ids`)."""
         rem = np.ascontiguousarray(np.asarray(remove, dtype=np.int32).reshape(-1))
+        iid = None if insert_ids is None else np.ascontiguousarray(np.asarray(insert_ids, dtype=np.int32))
         ed = ft_map_edit(len(rem), P(rem.ctypes.data if len(rem) else None),
-                         insert if insert is not None else ft_map_points())
+                         insert if insert is not None else ft_map_points(),
+                         P(iid.ctypes.data if iid is not None and len(iid) else None),
+                         ct.pointer(ids) if ids is not None else None)
         st = self.lib.ft_map_update(self.h, _stream(stream), ct.byref(map_points), capacity, ct.byref(ed))
         if check:
             self._check(st, "ft_map_update")
         return st
+
+    def ft_map_update_many(self, maps, capacities, edits, stream=None, check=True):
+        """Edits of several distinct maps in one call: `maps` a sequence of
+        ft_map_points (each one's n updated), `capacities` ints, `edits`
+        ft_map_edit structs (arrays they point to kept alive by the caller)."""
+        n = len(maps)
+        mp = (ct.POINTER(ft_map_points) * max(n, 1))(*[ct.pointer(m) for m in maps])
+        cap = np.ascontiguousarray(np.asarray(capacities, dtype=np.int32))
+        ed = (ft_map_edit * max(n, 1))(*edits)
+        st = self.lib.ft_map_update_many(self.h, _stream(stream), n, mp, P(cap.ctypes.data if n else None), ed)
+        if check:
+            self._check(st, "ft_map_update_many")
+        return st
+
+    def ft_map_update_raw(self, map_points, capacity: int, edit, stream):
+        """ft_map_update with a prepared ft_map_edit (arrays kept alive by
+        the caller): one call, no conversions."""
+        return self._check(self.lib.ft_map_update(self.h, P(stream.cuda_stream), ct.byref(map_points), capacity,
+                                                  ct.byref(edit)), "ft_map_update")
 
     def ft_orb_detect(self, pyr, scales, params, blurred, corners, stream=None, check=True):
         """`blurred`: device address or None; `corners`: ft_orb_corners."""

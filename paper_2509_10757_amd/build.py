@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfasttrack.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["ft_kernels.hip", "ft_upload.hip", "ft_noalloc.hip", "ft_orb.hip", "ft_api.cpp"]
+SOURCES = ["ft_kernels.hip", "ft_upload.hip", "ft_noalloc.hip", "ft_orb.hip", "ft_map.hip", "ft_api.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 DEVICE = ["--offload-arch=gfx950", "-fhip-fp32-correctly-rounded-divide-sqrt",

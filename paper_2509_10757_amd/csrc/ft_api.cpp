@@ -110,10 +110,12 @@ struct ft_context {
         hipEvent_t ev;
     };
     static constexpr int kEditEvents = 64;
-    char *edit_ring = nullptr;
+    char *edit_ring = nullptr;     // pinned
+    char *d_edit_ring = nullptr;   // device mirror (same offsets) for staged batches of edits
     size_t edit_ring_bytes = 0, edit_head = 0;
     std::deque<EditChunk> edit_live;
     std::vector<hipEvent_t> edit_free_ev, edit_all_ev;
+    std::vector<uint64_t> edit_marks;   // removed-slot bitmap of the edit being prepared (left all zero)
     // ORB detection: per-tile corner counts, one buffer per call in flight
     // (round robin; a buffer is reused once the event after its kernels ran)
     static constexpr int kOrbSlots = 8;
@@ -966,7 +968,9 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
     const size_t edit_bytes = align_up(sizeof(int32_t) * 2 * (size_t)lim->max_map_points, 256);
     const size_t orb_bytes = align_up(sizeof(int32_t) * (size_t)kOrbMaxTiles, 256);
-    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight + orb_bytes * ft_context::kOrbSlots;
+    ctx->edit_ring_bytes = std::max<size_t>(2 * edit_bytes, (size_t)8 << 20);
+    ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight + orb_bytes * ft_context::kOrbSlots +
+                 ctx->edit_ring_bytes;
     if (hipMalloc((void **)&ctx->base, ctx->bytes) != hipSuccess) {
         delete ctx;
         return FT_ERR_DEVICE;
@@ -986,7 +990,8 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
             return FT_ERR_DEVICE;
         }
     }
-    ctx->edit_ring_bytes = std::max<size_t>(2 * edit_bytes, (size_t)1 << 20);
+    ctx->d_edit_ring = ctx->base + off;
+    off += ctx->edit_ring_bytes;
     if (hipHostMalloc((void **)&ctx->edit_ring, ctx->edit_ring_bytes, hipHostMallocDefault) != hipSuccess) {
         ft_context_destroy(ctx);
         return FT_ERR_DEVICE;
@@ -1353,11 +1358,18 @@ ft_status ft_search_last_frame(ft_context *ctx, void *stream, const ft_last_poin
     return FT_OK;
 }
 
-ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,
-                        const ft_map_edit *edit)
+namespace {
+
+// One validated map edit: the removed slots (ascending), the (hole, source)
+// pairs, and the new count; nothing is changed until it is committed.
+struct PreparedEdit {
+    int n1 = 0, m = 0, n_holes = 0;
+    std::vector<int32_t> rem, pairs;
+};
+
+ft_status prepare_edit(ft_context *ctx, const ft_map_points *map, int32_t capacity, const ft_map_edit *edit,
+                       PreparedEdit &pe)
 {
-    ft_status st = enter(ctx);
-    if (st) return st;
     if (!map || !edit) return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: null argument");
     const int n = map->n, nr = edit->n_remove, m = edit->insert.n;
     if (n < 0 || capacity < n || capacity > kMaxMap || nr < 0 || m < 0)
@@ -1396,22 +1408,120 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
             return fail(ctx, FT_ERR_INVALID_ARGUMENT,
                         "map update: host insert arrays must all lie wholly inside ft_host_alloc blocks");
     }
-    std::vector<int32_t> rem(edit->remove, edit->remove + nr);
-    std::sort(rem.begin(), rem.end());
+    const ft_map_ids *rec = edit->ids;
+    std::vector<int32_t> &rem = pe.rem;
+    rem.assign(edit->remove, edit->remove + nr);
+    if (rec) {
+        // removals named by point id: their slots from the record
+        if (!rec->slot_id || !rec->slot_of || rec->id_count < 0 || (m > 0 && !edit->insert_ids))
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: incomplete id record");
+        for (int i = 0; i < nr; ++i) {
+            const int id = rem[i];
+            if (id < 0 || id >= rec->id_count)
+                return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: id %d outside [0, %d)", id, rec->id_count);
+            rem[i] = rec->slot_of[id];
+            if (rem[i] < 0 || rem[i] >= n || rec->slot_id[rem[i]] != id)
+                return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: id %d is not in the map", id);
+        }
+        // inserted ids: in range, not in the map, distinct (marked -2 in slot_of while checked, then restored)
+        int32_t *sof = rec->slot_of;
+        int bad = -1, j = 0;
+        for (; j < m; ++j) {
+            const int id = edit->insert_ids[j];
+            if (id < 0 || id >= rec->id_count || sof[id] != -1) {
+                bad = id;
+                break;
+            }
+            sof[id] = -2;
+        }
+        for (int k = 0; k < j; ++k) sof[edit->insert_ids[k]] = -1;
+        if (bad != -1 || j < m)
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: inserted id %d out of range, in the map or listed twice",
+                        bad);
+    }
+    // removed slots: range and duplicates through a bitmap over [0, n), which
+    // also yields the holes below n1 in ascending order without a sort
+    std::vector<uint64_t> &mk = ctx->edit_marks;
+    if (mk.size() < (size_t)(n + 63) / 64) mk.resize((size_t)(n + 63) / 64, 0);
+    auto unmark = [&](int upto) {
+        for (int i = 0; i < upto; ++i) mk[rem[i] >> 6] &= ~(1ull << (rem[i] & 63));
+    };
     for (int i = 0; i < nr; ++i) {
-        if (rem[i] < 0 || rem[i] >= n)
-            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: index %d outside [0, %d)", rem[i], n);
-        if (i > 0 && rem[i] == rem[i - 1])
-            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: index %d listed twice", rem[i]);
+        const int r = rem[i];
+        if (r < 0 || r >= n) {
+            unmark(i);
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: index %d outside [0, %d)", r, n);
+        }
+        const uint64_t bit = 1ull << (r & 63);
+        if (mk[r >> 6] & bit) {
+            unmark(i);
+            return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: index %d listed twice", r);
+        }
+        mk[r >> 6] |= bit;
     }
     const int n1 = n - nr;
-    if ((int64_t)n1 + m > capacity)
+    if ((int64_t)n1 + m > capacity) {
+        unmark(nr);
         return fail(ctx, FT_ERR_CAPACITY, "map update: %d points exceed the capacity %d", n1 + m, capacity);
+    }
     // (hole, source) pairs: removed slots below n1 and surviving points from n1 up, both ascending
-    const int n_holes = (int)(std::lower_bound(rem.begin(), rem.end(), n1) - rem.begin());
-    // a chunk of the pinned ring for the pairs: completed chunks are reclaimed
-    // first; a chunk the new one would overlap (or the oldest, when every
-    // event is in use) is waited for
+    std::vector<int32_t> holes;
+    holes.reserve(nr);
+    for (int w = 0; w < (n1 + 63) / 64; ++w) {
+        uint64_t bits = mk[w];
+        if (w == n1 / 64) bits &= (n1 % 64) ? ((1ull << (n1 % 64)) - 1) : 0ull;
+        while (bits) {
+            holes.push_back(w * 64 + __builtin_ctzll(bits));
+            bits &= bits - 1;
+        }
+    }
+    const int n_holes = (int)holes.size();
+    pe.pairs.resize(2 * (size_t)n_holes);
+    int src = n1;
+    for (int h = 0; h < n_holes; ++h) {
+        while (mk[src >> 6] & (1ull << (src & 63))) ++src;
+        pe.pairs[2 * h] = holes[h];
+        pe.pairs[2 * h + 1] = src++;
+    }
+    unmark(nr);
+    if (rec) {   // the moved points' record entries must be consistent before anything is enqueued
+        for (int h = 0; h < n_holes; ++h) {
+            const int id = rec->slot_id[pe.pairs[2 * h + 1]];
+            if (id < 0 || id >= rec->id_count || rec->slot_of[id] != pe.pairs[2 * h + 1])
+                return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update: id record inconsistent at slot %d",
+                            pe.pairs[2 * h + 1]);
+        }
+    }
+    pe.n1 = n1;
+    pe.m = m;
+    pe.n_holes = n_holes;
+    return FT_OK;
+}
+
+// The id record follows an enqueued edit (removed ids leave, moved ids take
+// their holes, inserted ids follow n1).
+void commit_record(const ft_map_edit *edit, const PreparedEdit &pe)
+{
+    ft_map_ids *rec = edit->ids;
+    if (!rec) return;
+    int32_t *sid = rec->slot_id, *sof = rec->slot_of;
+    for (int32_t r : pe.rem) sof[sid[r]] = -1;
+    for (int h = 0; h < pe.n_holes; ++h) {
+        const int id = sid[pe.pairs[2 * h + 1]];
+        sid[pe.pairs[2 * h]] = id;
+        sof[id] = pe.pairs[2 * h];
+    }
+    for (int j = 0; j < pe.m; ++j) {
+        sid[pe.n1 + j] = edit->insert_ids[j];
+        sof[edit->insert_ids[j]] = pe.n1 + j;
+    }
+}
+
+// A chunk of `need` bytes of the pinned edit ring (and of its device mirror
+// at the same offset): completed chunks are reclaimed first; a chunk the new
+// one would overlap (or the oldest, when every event is in use) is waited for.
+ft_status take_edit_chunk(ft_context *ctx, size_t need, size_t *off_out)
+{
     auto &live = ctx->edit_live;
     auto pop_front = [&](bool wait) -> hipError_t {
         hipError_t e = wait ? hipEventSynchronize(live.front().ev) : hipSuccess;
@@ -1420,7 +1530,6 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
         return e;
     };
     while (!live.empty() && hipEventQuery(live.front().ev) == hipSuccess) pop_front(false);
-    const size_t need = align_up(sizeof(int32_t) * 2 * (size_t)std::max(n_holes, 1), 256);
     size_t off = ctx->edit_head + need <= ctx->edit_ring_bytes ? ctx->edit_head : 0;
     auto overlaps = [&]() {
         for (const auto &c : live)
@@ -1429,17 +1538,33 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
     };
     while (!live.empty() && (overlaps() || ctx->edit_free_ev.empty())) HIP_TRY(ctx, pop_front(true));
     ctx->edit_head = off + need;
+    *off_out = off;
+    return FT_OK;
+}
+
+ft_status finish_edit_chunk(ft_context *ctx, size_t off, size_t need, hipStream_t s)
+{
+    hipEvent_t ev = ctx->edit_free_ev.back();
+    HIP_TRY(ctx, hipEventRecord(ev, s));
+    ctx->edit_free_ev.pop_back();
+    ctx->edit_live.push_back({off, need, ev});
+    return FT_OK;
+}
+
+}  // namespace
+
+ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32_t capacity,
+                        const ft_map_edit *edit)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    PreparedEdit pe;
+    if ((st = prepare_edit(ctx, map, capacity, edit, pe))) return st;
+    const size_t need = align_up(sizeof(int32_t) * 2 * (size_t)std::max(pe.n_holes, 1), 256);
+    size_t off = 0;
+    if ((st = take_edit_chunk(ctx, need, &off))) return st;
     int32_t *pairs = reinterpret_cast<int32_t *>(ctx->edit_ring + off);
-    int src = n1;
-    size_t tail = (size_t)n_holes;   // removed indices at or above n1 (ascending)
-    for (int h = 0; h < n_holes; ++h) {
-        while (tail < rem.size() && rem[tail] == src) {
-            ++tail;
-            ++src;
-        }
-        pairs[2 * h] = rem[h];
-        pairs[2 * h + 1] = src++;
-    }
+    if (pe.n_holes) memcpy(pairs, pe.pairs.data(), sizeof(int32_t) * pe.pairs.size());
     hipStream_t s = (hipStream_t)stream;
     MapEditArgs a{};
     a.pos = const_cast<float *>(map->pos);
@@ -1448,20 +1573,93 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
     a.dmax = const_cast<float *>(map->dmax);
     a.desc = const_cast<uint8_t *>(map->desc);
     a.pairs = pairs;                  // pinned staging, read by the move kernel over the bus
-    a.n_pairs = n_holes;
+    a.n_pairs = pe.n_holes;
     a.ipos = edit->insert.pos;
     a.inormal = edit->insert.normal;
     a.idmin = edit->insert.dmin;
     a.idmax = edit->insert.dmax;
     a.idesc = edit->insert.desc;
-    a.n1 = n1;
-    a.n_insert = m;
+    a.n1 = pe.n1;
+    a.n_insert = pe.m;
     HIP_TRY(ctx, launch_map_edit(a, s));
-    hipEvent_t ev = ctx->edit_free_ev.back();
-    HIP_TRY(ctx, hipEventRecord(ev, s));
-    ctx->edit_free_ev.pop_back();
-    live.push_back({off, need, ev});
-    map->n = n1 + m;
+    if ((st = finish_edit_chunk(ctx, off, need, s))) return st;
+    commit_record(edit, pe);
+    map->n = pe.n1 + pe.m;
+    return FT_OK;
+}
+
+ft_status ft_map_update_many(ft_context *ctx, void *stream, int32_t n, ft_map_points *const *maps,
+                             const int32_t *capacities, const ft_map_edit *edits)
+{
+    ft_status st = enter(ctx);
+    if (st) return st;
+    if (n < 0 || (n > 0 && (!maps || !capacities || !edits)))
+        return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update many: %d edits, null list", n);
+    if (n > kMaxManyEdits)
+        return fail(ctx, FT_ERR_CAPACITY, "map update many: %d edits exceed %d", n, kMaxManyEdits);
+    std::vector<PreparedEdit> pe(n);
+    int64_t moves = 0, apps = 0;
+    for (int i = 0; i < n; ++i) {
+        if ((st = prepare_edit(ctx, maps[i], capacities[i], &edits[i], pe[i]))) return st;
+        for (int k = 0; k < i; ++k)
+            if (maps[k]->pos == maps[i]->pos)
+                return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update many: edits %d and %d name one map", k, i);
+        moves += pe[i].n_holes;
+        apps += pe[i].m;
+    }
+    if (n == 0) return FT_OK;
+    // one chunk: the edits' descriptors, moves (edit, hole, source), appends (edit, j)
+    const size_t d_bytes = align_up(sizeof(MapEditDesc) * (size_t)n, 256);
+    const size_t m_bytes = align_up(sizeof(int32_t) * 3 * (size_t)std::max<int64_t>(moves, 1), 256);
+    const size_t a_bytes = align_up(sizeof(int32_t) * 2 * (size_t)std::max<int64_t>(apps, 1), 256);
+    const size_t need = d_bytes + m_bytes + a_bytes;
+    if (need > ctx->edit_ring_bytes / 2)
+        return fail(ctx, FT_ERR_CAPACITY, "map update many: %lld moves and %lld inserts exceed the staging",
+                    (long long)moves, (long long)apps);
+    size_t off = 0;
+    if ((st = take_edit_chunk(ctx, need, &off))) return st;
+    char *h = ctx->edit_ring + off;
+    MapEditDesc *desc = reinterpret_cast<MapEditDesc *>(h);
+    int32_t *mv = reinterpret_cast<int32_t *>(h + d_bytes);
+    int32_t *ap = reinterpret_cast<int32_t *>(h + d_bytes + m_bytes);
+    int64_t mk = 0, ak = 0;
+    for (int i = 0; i < n; ++i) {
+        const ft_map_points &mp = *maps[i];
+        const ft_map_points &ins = edits[i].insert;
+        MapEditDesc &d = desc[i];
+        d.pos = const_cast<float *>(mp.pos);
+        d.normal = const_cast<float *>(mp.normal);
+        d.dmin = const_cast<float *>(mp.dmin);
+        d.dmax = const_cast<float *>(mp.dmax);
+        d.desc = const_cast<uint8_t *>(mp.desc);
+        d.ipos = ins.pos;
+        d.inormal = ins.normal;
+        d.idmin = ins.dmin;
+        d.idmax = ins.dmax;
+        d.idesc = ins.desc;
+        d.n1 = pe[i].n1;
+        d.pad = 0;
+        for (int k = 0; k < pe[i].n_holes; ++k, ++mk) {
+            mv[3 * mk] = i;
+            mv[3 * mk + 1] = pe[i].pairs[2 * k];
+            mv[3 * mk + 2] = pe[i].pairs[2 * k + 1];
+        }
+        for (int j = 0; j < pe[i].m; ++j, ++ak) {
+            ap[2 * ak] = i;
+            ap[2 * ak + 1] = j;
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char *d = ctx->d_edit_ring + off;
+    HIP_TRY(ctx, hipMemcpyAsync(d, h, need, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_map_edit_many(reinterpret_cast<const MapEditDesc *>(d),
+                                      reinterpret_cast<const int32_t *>(d + d_bytes), (int)moves,
+                                      reinterpret_cast<const int32_t *>(d + d_bytes + m_bytes), (int)apps, s));
+    if ((st = finish_edit_chunk(ctx, off, need, s))) return st;
+    for (int i = 0; i < n; ++i) {
+        commit_record(&edits[i], pe[i]);
+        maps[i]->n = pe[i].n1 + pe[i].m;
+    }
     return FT_OK;
 }
 

@@ -224,6 +224,18 @@ struct MapEditArgs {
     int32_t n1, n_insert;
 };
 hipError_t launch_map_edit(const MapEditArgs &a, hipStream_t stream);
+// Several maps' edits in two launches (ft_map.hip): descriptors, moves (edit,
+// hole, source) and appends (edit, j), all in device memory.
+constexpr int kMaxManyEdits = 4096;
+struct MapEditDesc {
+    FT_G float *pos, *normal, *dmin, *dmax;
+    FT_G uint8_t *desc;
+    const FT_G float *ipos, *inormal, *idmin, *idmax;
+    const FT_G uint8_t *idesc;
+    int32_t n1, pad;
+};
+hipError_t launch_map_edit_many(const MapEditDesc *descs, const int32_t *moves, int n_moves, const int32_t *apps,
+                                int n_apps, hipStream_t stream);
 
 // ORB extraction (ft_orb.hip).  Detection runs over row tiles of every level
 // of one pyramid: kOrbRows output rows per 256-thread workgroup, the level

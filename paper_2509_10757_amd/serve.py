@@ -251,30 +251,6 @@ class Scheduler:
 # --------------------------------------------------------------------------
 # Device executor
 # --------------------------------------------------------------------------
-def follow_edit(ids, n, slot_of, rem, insert_ids):
-    """The host's record of which point each map slot holds, carried through
-    one ft_map_update, in time proportional to the edit: `ids[:n]` (an array
-    with room for the map's capacity) holds the point id of each slot,
-    `slot_of[id]` its slot (-1: not in the map), `rem` the sorted removed
-    slots.  Removed slots below the new count take the surviving tail points
-    in ascending order, inserted points are appended.  Updates both arrays in
-    place and returns the new count."""
-    rem = np.asarray(rem, dtype=np.int64)
-    insert_ids = np.asarray(insert_ids, dtype=np.int64)
-    n1 = n - len(rem)
-    holes = rem[rem < n1]
-    tail = np.ones(n - n1, dtype=bool)
-    tail[rem[rem >= n1] - n1] = False
-    src = n1 + np.flatnonzero(tail)
-    slot_of[ids[rem]] = -1
-    moved = ids[src]
-    ids[holes] = moved
-    slot_of[moved] = holes
-    m = len(insert_ids)
-    ids[n1:n1 + m] = insert_ids
-    slot_of[insert_ids] = np.arange(n1, n1 + m)
-    return n1 + m
-
 def _carve(sizes):
     """Offsets of consecutive 256-byte aligned parts; returns (offsets, total)."""
     off, out = 0, {}
@@ -315,10 +291,9 @@ class DeviceExecutor:
     k are applied in order on the batch's HIP stream by ft_map_update, which
     reads the inserted points from the stream's pinned host block (packed
     once at admission, as a local-map producer would write them): no copy
-    command per edit.  Removed points are found by slot through
-    the executor's record of which point each slot holds, kept by the edit
-    rule ft.h states (removed slots below the new count take the surviving
-    tail points in ascending order; inserted points are appended)."""
+    command per edit.  Removals are given as point ids with the stream's id
+    record (which point each slot holds), which the library translates and
+    keeps; each edit's call arguments are prepared at admission."""
 
     def __init__(self, streams, max_batch: int = 64, max_inflight: int = 4, max_kp: int = 4096,
                  device: str = "cuda"):
@@ -329,9 +304,9 @@ class DeviceExecutor:
         self.streams = {s["id"]: s for s in streams}
         self.max_batch, self.max_inflight = max_batch, max_inflight
         n_map = max(max(s["n_map"] for s in streams), 1)
-        self.slot_ids, self.slot_of, self.map_seq, self.map_struct, self.ins_block, self.ins_pts = \
-            {}, {}, {}, {}, {}, {}
-        self.slot_n = {}
+        # streams with per-frame map edits: id record, prepared edits
+        self.id_rec, self.id_struct, self.edit_structs, self.map_seq, self.map_struct = {}, {}, {}, {}, {}
+        self.ins_block, self.ins_pts = {}, {}
         self.ctx = ft.Context(ft.default_limits(max_kp_per_image=max_kp, max_map_points=n_map,
                                                 max_batch_frames=max_batch, max_inflight=max_inflight))
         self.hip_streams = [torch.cuda.Stream(device=device) for _ in range(max_inflight)]
@@ -386,12 +361,12 @@ class DeviceExecutor:
         if "edits" in s:
             ids0 = np.asarray(s["map_ids0"], dtype=np.int64)
             mp = {k: v[ids0] for k, v in s["points"].items()}
-            self.slot_ids[sid] = np.zeros(len(ids0), dtype=np.int64)    # the map's capacity
-            self.slot_ids[sid][:] = ids0
-            self.slot_n[sid] = len(ids0)
-            self.slot_of[sid] = np.full(len(s["points"]["dmin"]), -1, dtype=np.int64)
-            self.slot_of[sid][ids0] = np.arange(len(ids0))
-            self.map_seq[sid] = 0
+            rec = {"slot_id": np.zeros(len(ids0), dtype=np.int32),     # the map's capacity
+                   "slot_of": np.full(len(s["points"]["dmin"]), -1, dtype=np.int32)}
+            self.id_rec[sid] = rec
+            self.id_struct[sid] = self.ft.ft_map_ids(rec["slot_id"].ctypes.data, rec["slot_of"].ctypes.data,
+                                                     len(rec["slot_of"]))
+            self._reset_record(sid)
             self._pack_inserts(sid)
         else:
             mp = s["frames"][0]["map"]
@@ -400,6 +375,21 @@ class DeviceExecutor:
         self.map_struct[sid] = self.ft.ft_map_points(len(mp["dmin"]), m["pos"].data_ptr(), m["normal"].data_ptr(),
                                                      m["dmin"].data_ptr(), m["dmax"].data_ptr(),
                                                      m["desc"].data_ptr())
+        if "edits" in s:   # every edit's call arguments, prepared once (arrays kept alive here)
+            keep, structs = [], []
+            for q, e in enumerate(s["edits"]):
+                if e is None:
+                    structs.append(None)
+                    continue
+                rem = np.ascontiguousarray(e["remove_ids"], dtype=np.int32)
+                iid = np.ascontiguousarray(e["insert_ids"], dtype=np.int32)
+                keep += [rem, iid]
+                ins = self.ins_pts[sid][q]
+                structs.append(self.ft.ft_map_edit(len(rem), rem.ctypes.data if len(rem) else None,
+                                                   ins if ins is not None else self.ft.ft_map_points(),
+                                                   iid.ctypes.data if len(iid) else None,
+                                                   ct.pointer(self.id_struct[sid])))
+            self.edit_structs[sid] = (structs, keep)
         for key, p in self._pyramids(sid).items():
             self.pyr[key] = torch.from_numpy(p["data"]).to(self.device)
         for q, f in enumerate(s["frames"]):
@@ -411,7 +401,7 @@ class DeviceExecutor:
         """Frees what the stream holds on the device (exactly what footprint
         counts); the scheduler calls it once no batch in flight reads it."""
         self.maps.pop(sid, None)
-        for d in (self.slot_ids, self.slot_n, self.slot_of, self.map_seq, self.map_struct, self.ins_pts):
+        for d in (self.id_rec, self.id_struct, self.edit_structs, self.map_seq, self.map_struct, self.ins_pts):
             d.pop(sid, None)
         if sid in self.ins_block:
             self.ctx.ft_host_free(self.ins_block.pop(sid))
@@ -466,6 +456,14 @@ class DeviceExecutor:
                                              addr["desc"]))
         self.ins_pts[sid] = pts
 
+    def _reset_record(self, sid):
+        ids0 = np.asarray(self.streams[sid]["map_ids0"], dtype=np.int64)
+        rec = self.id_rec[sid]
+        rec["slot_id"][:len(ids0)] = ids0
+        rec["slot_of"][:] = -1
+        rec["slot_of"][ids0] = np.arange(len(ids0))
+        self.map_seq[sid] = 0
+
     def reset_map(self, sid):
         """Upload a stream's first map again (a new run's sequence numbers
         start at 0); the device is synchronised first."""
@@ -474,28 +472,33 @@ class DeviceExecutor:
         ids0 = np.asarray(s["map_ids0"], dtype=np.int64)
         for k, t in self.maps[sid].items():
             t[:len(ids0)].copy_(self.torch.from_numpy(np.ascontiguousarray(s["points"][k][ids0])))
-        self.slot_ids[sid][:len(ids0)] = ids0
-        self.slot_n[sid] = len(ids0)
-        self.slot_of[sid][:] = -1
-        self.slot_of[sid][ids0] = np.arange(len(ids0))
+        self._reset_record(sid)
         self.map_struct[sid].n = len(ids0)
-        self.map_seq[sid] = 0
 
-    def _edit_map(self, sid, seq, hs):
-        """Bring the stream's device map from its last frame's map to frame
-        `seq`'s, on HIP stream `hs`."""
-        s = self.streams[sid]
-        n_pool = len(s["frames"])
-        for k in range(self.map_seq[sid] + 1, seq + 1):
-            q = k % n_pool
-            e = s["edits"][q]
-            ids, slot_of = self.slot_ids[sid], self.slot_of[sid]
-            rem = np.sort(slot_of[e["remove_ids"]])
-            assert len(rem) == 0 or rem[0] >= 0, "removed point not in the map"
-            self.ctx.ft_map_update(self.map_struct[sid], self.maps[sid]["dmin"].numel(), rem.astype(np.int32),
-                                   self.ins_pts[sid][q], stream=hs)
-            self.slot_n[sid] = follow_edit(ids, self.slot_n[sid], slot_of, rem, e["insert_ids"])
-        self.map_seq[sid] = max(self.map_seq[sid], seq)
+    def _edit_maps(self, frames, hs):
+        """Bring each edited stream's device map from its last frame's map to
+        its frame's, on HIP stream `hs`: round r applies every stream's r-th
+        pending edit in one ft_map_update_many call (a stream is normally one
+        edit behind)."""
+        pending = []
+        for fr in frames:
+            sid = fr.stream
+            if sid in self.map_seq:
+                assert fr.seq >= self.map_seq[sid], "frames of an edited map arrive in order"
+                if fr.seq > self.map_seq[sid]:
+                    pending.append((sid, self.map_seq[sid] + 1, fr.seq))
+                    self.map_seq[sid] = fr.seq
+        while pending:
+            maps, caps, edits, rest = [], [], [], []
+            for sid, k, last in pending:
+                s = self.streams[sid]
+                maps.append(self.map_struct[sid])
+                caps.append(self.maps[sid]["dmin"].numel())
+                edits.append(self.edit_structs[sid][0][k % len(s["frames"])])
+                if k < last:
+                    rest.append((sid, k + 1, last))
+            self.ctx.ft_map_update_many(maps, caps, edits, stream=hs)
+            pending = rest
 
     def _pack(self, f, at):
         L, R = f["left"], f["right"]
@@ -609,10 +612,8 @@ class DeviceExecutor:
         lane = 0 if per_frame else self.next_h % self.max_inflight
         hs = self.hip_streams[lane]
         n = len(frames)
-        for fr in frames:
-            if fr.stream in self.map_seq:
-                assert fr.seq >= self.map_seq[fr.stream], "frames of an edited map arrive in order"
-                self._edit_map(fr.stream, fr.seq, hs)
+        if self.map_seq:
+            self._edit_maps(frames, hs)
         slots = [self.free.pop() for _ in range(n)]
         keys = [(fr.stream, fr.seq % len(self.streams[fr.stream]["frames"])) for fr in frames]
         t = [self.tmpl[k] for k in keys]

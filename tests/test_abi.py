@@ -52,7 +52,7 @@ STRUCTS = ["ft_limits", "ft_keypoints", "ft_pyramid", "ft_scales", "ft_pinhole_s
            "ft_pinhole_params", "ft_pinhole_out", "ft_kb_intrinsics", "ft_fisheye_stereo",
            "ft_fisheye_params", "ft_fisheye_out", "ft_map_points", "ft_search_camera", "ft_grid",
            "ft_search_params", "ft_search_out", "ft_frame_job", "ft_shapes", "ft_image", "ft_last_points",
-           "ft_last_params", "ft_map_edit", "ft_orb_params", "ft_orb_corners"]
+           "ft_last_params", "ft_map_edit", "ft_map_ids", "ft_orb_params", "ft_orb_corners"]
 
 
 def test_ctypes_layout_matches_c_compiler(tmp_path):

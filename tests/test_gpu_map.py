@@ -209,3 +209,140 @@ def test_many_edits_in_flight_behind_a_busy_stream(ft, ctx):
     s.synchronize()
     assert dm.n == n
     _same(dm.host(), mp, "after 150 queued edits")
+
+
+def test_edits_by_point_id_keep_the_slot_record(ft, ctx):
+    """Removals named by point id with the library-kept slot record: the map
+    equals the oracle's, and the record equals the slot contents of an
+    id-tagged map edited by the oracle alongside; invalid ids (out of range,
+    not in the map, inserted twice or already present) leave map and record
+    unchanged."""
+    n_ids, cap = 9000, 5000
+    rng = np.random.default_rng(61)
+    table = _points(n_ids, 62, 0)                       # dmin = point id: the oracle map is its own tag
+    ids0 = np.sort(rng.choice(n_ids, 4000, replace=False))
+    mp = {k: v[ids0] for k, v in table.items()}
+    dm = ft.DeviceMap(mp, cap)
+    slot_id = np.zeros(cap, np.int32)
+    slot_id[:len(ids0)] = ids0
+    slot_of = np.full(n_ids, -1, np.int32)
+    slot_of[ids0] = np.arange(len(ids0))
+    rec = ft.ft_map_ids(slot_id.ctypes.data, slot_of.ctypes.data, n_ids)
+    for step in range(40):
+        live = slot_id[:dm.n].copy()
+        rem_ids = rng.choice(live, int(rng.integers(0, min(400, len(live)) + 1)), replace=False)
+        free = np.setdiff1d(np.arange(n_ids), live)
+        m = min(int(rng.integers(0, 400)), cap - (len(live) - len(rem_ids)), len(free))
+        ins_ids = rng.choice(free, m, replace=False)
+        # the oracle takes slots: the removed ids' current slots in the oracle's own map
+        oracle_slot = {int(v): i for i, v in enumerate(mp["dmin"].astype(np.int64))}
+        want = oracle.map_update(mp, cap, [oracle_slot[int(i)] for i in rem_ids],
+                                 {k: v[ins_ids] for k, v in table.items()})
+        ins = {k: torch.from_numpy(np.ascontiguousarray(v[ins_ids])).cuda() for k, v in table.items()}
+        pts = ft.ft_map_points(m, *(ft._ptr(ins[k]) for k in ("pos", "normal", "dmin", "dmax", "desc")))
+        ctx.ft_map_update(dm.struct, cap, rem_ids, pts if m else None, ids=rec, insert_ids=ins_ids)
+        torch.cuda.synchronize()
+        _same(dm.host(), want, step)
+        n = dm.n
+        assert np.array_equal(slot_id[:n], want["dmin"].astype(np.int32)), step
+        assert np.array_equal(np.flatnonzero(slot_of >= 0), np.sort(slot_id[:n])), step
+        assert np.array_equal(slot_of[slot_id[:n]], np.arange(n)), step
+        mp = want
+    live = slot_id[:dm.n].copy()
+    free = np.setdiff1d(np.arange(n_ids), live)
+    snap = (slot_id.copy(), slot_of.copy(), dm.n)
+    one = {k: torch.from_numpy(np.ascontiguousarray(v[:2])).cuda() for k, v in table.items()}
+    two = ft.ft_map_points(2, *(ft._ptr(one[k]) for k in ("pos", "normal", "dmin", "dmax", "desc")))
+    for rem_ids, ins_ids, what in (([n_ids], [free[0], free[1]], "id out of range"),
+                                   ([free[0]], [free[1], free[2]], "removed id not in the map"),
+                                   ([], [free[0], free[0]], "inserted twice"),
+                                   ([], [live[0], free[0]], "inserted id already in the map"),
+                                   ([live[0], live[0]], [free[0], free[1]], "removed twice")):
+        st = ctx.ft_map_update(dm.struct, cap, rem_ids, two, ids=rec, insert_ids=ins_ids, check=False)
+        assert st == ft.FT_ERR_INVALID_ARGUMENT, what
+        assert dm.n == snap[2] and np.array_equal(slot_id, snap[0]) and np.array_equal(slot_of, snap[1]), what
+    torch.cuda.synchronize()
+    _same(dm.host(), mp, "unchanged")
+
+
+def test_many_maps_edited_in_one_call(ft, ctx):
+    """Rounds of edits of five maps in one ft_map_update_many call each (two
+    maps edited by slot, three by point id with their records): every map
+    equals the oracle's; an invalid edit among valid ones, or two edits of one
+    map, leave every map and record unchanged; an empty call does nothing."""
+    rng = np.random.default_rng(71)
+    n_ids = 6000
+    table = _points(n_ids, 72, 0)
+    maps, dms, caps, recs = [], [], [], []
+    for k, n0 in enumerate((300, 1200, 2500, 4000, 50)):
+        ids0 = np.sort(rng.choice(n_ids, n0, replace=False))
+        mp = {key: v[ids0] for key, v in table.items()}
+        cap = n0 + 700
+        maps.append(mp)
+        dms.append(ft.DeviceMap(mp, cap))
+        caps.append(cap)
+        if k >= 2:
+            sid = np.zeros(cap, np.int32)
+            sid[:n0] = ids0
+            sof = np.full(n_ids, -1, np.int32)
+            sof[ids0] = np.arange(n0)
+            recs.append((sid, sof, ft.ft_map_ids(sid.ctypes.data, sof.ctypes.data, n_ids)))
+        else:
+            recs.append(None)
+    keep = []
+
+    def edit_for(k):
+        dm, mp, cap = dms[k], maps[k], caps[k]
+        n = dm.n
+        used = set(mp["dmin"].astype(np.int64).tolist())
+        nr = int(rng.integers(0, min(300, n) + 1))
+        rem_slots = rng.choice(n, nr, replace=False)
+        free = np.array(sorted(set(range(n_ids)) - used))
+        m = min(int(rng.integers(0, 300)), cap - (n - nr), len(free))
+        ins_ids = rng.choice(free, m, replace=False).astype(np.int32)
+        want = oracle.map_update(mp, cap, rem_slots, {key: v[ins_ids] for key, v in table.items()})
+        dev = {key: torch.from_numpy(np.ascontiguousarray(v[ins_ids])).cuda() for key, v in table.items()}
+        pts = ft.ft_map_points(m, *(ft._ptr(dev[key]) for key in ("pos", "normal", "dmin", "dmax", "desc"))) \
+            if m else ft.ft_map_points()
+        if recs[k] is None:
+            rem = np.ascontiguousarray(rem_slots, dtype=np.int32)
+            ed = ft.ft_map_edit(nr, rem.ctypes.data if nr else None, pts, None, None)
+        else:
+            rem = np.ascontiguousarray(mp["dmin"][rem_slots].astype(np.int32))   # the removed points' ids
+            ed = ft.ft_map_edit(nr, rem.ctypes.data if nr else None, pts, ins_ids.ctypes.data if m else None,
+                                ct.pointer(recs[k][2]))
+        keep.extend([rem, ins_ids, dev])
+        return ed, want
+
+    import ctypes as ct
+    for rnd in range(12):
+        order = rng.permutation(5)[: int(rng.integers(1, 6))]
+        eds, wants = zip(*[edit_for(int(k)) for k in order])
+        torch.cuda.synchronize()
+        ctx.ft_map_update_many([dms[k].struct for k in order], [caps[k] for k in order], list(eds))
+        torch.cuda.synchronize()
+        for k, want in zip(order, wants):
+            _same(dms[k].host(), want, (rnd, int(k)))
+            maps[k] = want
+            if recs[k] is not None:
+                n = dms[k].n
+                assert np.array_equal(recs[k][0][:n], want["dmin"].astype(np.int32)), (rnd, int(k))
+                assert np.array_equal(np.sort(np.flatnonzero(recs[k][1] >= 0)), np.sort(recs[k][0][:n]))
+    snap = [(dm.n, None if r is None else (r[0].copy(), r[1].copy())) for dm, r in zip(dms, recs)]
+    good, _ = edit_for(0)
+    bad_rem = np.array([np.flatnonzero(recs[3][1] < 0)[0]], np.int32)  # an id not in map 3
+    bad = ft.ft_map_edit(1, bad_rem.ctypes.data, ft.ft_map_points(), None, ct.pointer(recs[3][2]))
+    keep.append(bad_rem)
+    assert ctx.ft_map_update_many([dms[0].struct, dms[3].struct], [caps[0], caps[3]], [good, bad],
+                                  check=False) == ft.FT_ERR_INVALID_ARGUMENT
+    good1, _ = edit_for(1)
+    good1b, _ = edit_for(1)
+    assert ctx.ft_map_update_many([dms[1].struct, dms[1].struct], [caps[1], caps[1]], [good1, good1b],
+                                  check=False) == ft.FT_ERR_INVALID_ARGUMENT
+    assert ctx.ft_map_update_many([], [], []) == ft.FT_OK
+    torch.cuda.synchronize()
+    for k, (n, r) in enumerate(snap):
+        assert dms[k].n == n
+        _same(dms[k].host(), maps[k], ("unchanged", k))
+        if r is not None:
+            assert np.array_equal(recs[k][0], r[0]) and np.array_equal(recs[k][1], r[1])

@@ -85,7 +85,8 @@ def test_served_frames_follow_their_edited_maps(ft):
         compare_frame(got, oracle.run_frame(f))
     torch.cuda.synchronize()
     for sid, (mlist, ids) in maps.items():
-        assert ex.slot_n[sid] == len(ids) and np.array_equal(ex.slot_ids[sid][:len(ids)], ids), sid
+        assert np.array_equal(ex.id_rec[sid]["slot_id"][:len(ids)], ids), sid
+        assert np.array_equal(np.sort(np.flatnonzero(ex.id_rec[sid]["slot_of"] >= 0)), np.sort(ids)), sid
         assert ex.map_struct[sid].n == len(ids)
         for k, v in ex.maps[sid].items():
             assert np.array_equal(v.cpu().numpy().view(np.uint8), mlist[-1][k].view(np.uint8)), (sid, k)

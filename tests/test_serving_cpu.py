@@ -268,46 +268,3 @@ def test_summary_fields(mode):
     s = st.summary()
     assert s["frames"] == 10 and s["p99_ms"] >= s["p50_ms"] > 0 and s["frames_per_s"] == 100.0
 
-
-def test_slot_record_follows_the_oracle_edit_rule():
-    """The executor's host record of which point each device map slot holds
-    equals the slot contents of the oracle's edited map (a map whose dmin
-    holds the point ids), over random edit sequences: nothing, head-only,
-    tail-only, everything, and mixes."""
-    import numpy as np
-
-    import oracle
-    from paper_2509_10757_amd.serve import follow_edit
-    rng = np.random.default_rng(8)
-    n_pts, cap = 5000, 3000
-    table = {"pos": np.zeros((n_pts, 3), np.float32), "normal": np.zeros((n_pts, 3), np.float32),
-             "dmin": np.arange(n_pts, dtype=np.float32), "dmax": np.zeros(n_pts, np.float32),
-             "desc": np.zeros((n_pts, 32), np.uint8)}
-    ids = np.zeros(cap, np.int64)
-    ids[:1000] = np.arange(1000)
-    n_live = 1000
-    slot_of = np.full(n_pts, -1, np.int64)
-    slot_of[:1000] = np.arange(1000)
-    mp = {k: v[ids[:n_live]] for k, v in table.items()}
-    unused = list(range(1000, n_pts))
-    for step in range(60):
-        n = n_live
-        if step == 0:
-            rem = []
-        elif step == 1:
-            rem = list(range(min(5, n)))
-        elif step == 2:
-            rem = list(range(n - 7, n))
-        elif step == 3:
-            rem = list(range(n))
-        else:
-            rem = rng.choice(n, int(rng.integers(0, n + 1)), replace=False).tolist() if n else []
-        m = int(rng.integers(0, min(300, cap - (n - len(rem))) + 1))
-        ins_ids = np.array(unused[:m], np.int64)
-        del unused[:m]
-        mp = oracle.map_update(mp, cap, rem, {k: v[ins_ids] for k, v in table.items()})
-        n_live = follow_edit(ids, n_live, slot_of, np.sort(np.asarray(rem, np.int64)), ins_ids)
-        assert np.array_equal(ids[:n_live], mp["dmin"].astype(np.int64)), step
-        live = np.nonzero(slot_of >= 0)[0]
-        assert np.array_equal(np.sort(live), np.sort(ids[:n_live]))
-        assert np.array_equal(slot_of[ids[:n_live]], np.arange(n_live))
