@@ -24,7 +24,7 @@ Beside the headline the default run also reports:
     pinhole frame and both fisheye views: per-call p50/p99;
   * ORB extraction of the benchmark's 64 pinhole images (FAST-9 corners on
     all eight levels, every corner described): images/s, corners per image,
-    detection and description times and the detection pair's roofline;
+    detection and description times and the detection kernel's roofline;
   * local-map maintenance on the device: a 20000-point map with 5% of its
     points replaced per edit, against uploading the whole map again;
   * a bounded serving sweep (32 camera streams, resident maps of 2k-40k
@@ -349,10 +349,10 @@ def search_roofline(nbytes, us, traffic, note):
 
 def orb_leg(ctx, ft, frames, streams, steps, timing=True, flush=None):
     """ORB extraction of the benchmark's pinhole images (both images of each
-    pinhole frame, 752x480, eight levels): detection (two kernels) then
+    pinhole frame, 752x480, eight levels): detection (one kernel) then
     description of every detected corner, per image, images spread over the
     submission streams; throughput, corners per image, and HIP-event times of
-    the detection pair and the description on one stream."""
+    the detection and the description on one stream."""
     import numpy as np
     import torch
 
@@ -412,11 +412,11 @@ def orb_leg(ctx, ft, frames, streams, steps, timing=True, flush=None):
     out["describe_us"] = round(des_us, 2)
     out["describe_ns_per_corner"] = round(des_us * 1e3 / max(np.mean(counts), 1), 2)
     out["cold"] = {"detect_us": round(cold[0], 2), "describe_us": round(cold[1], 2)}
-    out["roofline"] = {"bound": "hbm", "kernel": "k_orb_detect + k_orb_emit (one image)", "achieved": round(achieved, 2),
+    out["roofline"] = {"bound": "hbm", "kernel": "k_orb_detect (one image)", "achieved": round(achieved, 2),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                       "traffic": measured_traffic("k_orb_detect+k_orb_emit", "orb_images64", ORB_SOURCE),
+                       "traffic": measured_traffic("k_orb_detect", "orb_images64", ORB_SOURCE),
                        "algorithmic_bytes_per_launch": det_bytes, "avg_launch_us": round(det_us, 3),
-                       "timed": "HIP events around the detection pair of each image on one stream, warm caches"}
+                       "timed": "HIP events around the detection of each image on one stream, warm caches"}
     return out
 
 

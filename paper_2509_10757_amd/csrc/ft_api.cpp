@@ -116,10 +116,15 @@ struct ft_context {
     std::deque<EditChunk> edit_live;
     std::vector<hipEvent_t> edit_free_ev, edit_all_ev;
     std::vector<uint64_t> edit_marks;   // removed-slot bitmap of the edit being prepared (left all zero)
-    // ORB detection: per-tile corner counts, one buffer per call in flight
-    // (round robin; a buffer is reused once the event after its kernels ran)
+    // ORB detection: per-tile look-back state and a ticket counter, one set
+    // per call in flight (round robin; a set is reused once the event after
+    // its kernel ran).  The state is tagged with a per-set epoch and tickets
+    // count on from a per-set base, so nothing is cleared between calls.
     static constexpr int kOrbSlots = 8;
-    int32_t *orb_tiles[kOrbSlots] = {};
+    unsigned long long *orb_state[kOrbSlots] = {};
+    uint32_t *orb_ticket[kOrbSlots] = {};
+    uint32_t orb_epoch[kOrbSlots] = {};
+    uint32_t orb_base[kOrbSlots] = {};
     hipEvent_t orb_ev[kOrbSlots] = {};
     bool orb_used[kOrbSlots] = {};
     int orb_next = 0;
@@ -967,7 +972,7 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     const size_t slot_bytes = align_up(b.off, 256);
     const size_t n_slots = 1 + (size_t)lim->max_inflight * lim->max_batch_frames;
     const size_t edit_bytes = align_up(sizeof(int32_t) * 2 * (size_t)lim->max_map_points, 256);
-    const size_t orb_bytes = align_up(sizeof(int32_t) * (size_t)kOrbMaxTiles, 256);
+    const size_t orb_bytes = align_up(sizeof(unsigned long long) * (size_t)kOrbMaxTiles + 256, 256);
     ctx->edit_ring_bytes = std::max<size_t>(2 * edit_bytes, (size_t)8 << 20);
     ctx->bytes = slot_bytes * n_slots + ctx->layout.total * lim->max_inflight + orb_bytes * ft_context::kOrbSlots +
                  ctx->edit_ring_bytes;
@@ -983,12 +988,14 @@ ft_status ft_context_create(const ft_limits *lim, int32_t device, ft_context **o
     };
     carve_at(ctx->direct);
     for (int k = 0; k < ft_context::kOrbSlots; ++k) {
-        ctx->orb_tiles[k] = reinterpret_cast<int32_t *>(ctx->base + off);
-        off += orb_bytes;
-        if (hipEventCreateWithFlags(&ctx->orb_ev[k], hipEventDisableTiming) != hipSuccess) {
+        ctx->orb_state[k] = reinterpret_cast<unsigned long long *>(ctx->base + off);
+        ctx->orb_ticket[k] = reinterpret_cast<uint32_t *>(ctx->base + off + orb_bytes - 256);
+        if (hipMemset(ctx->base + off, 0, orb_bytes) != hipSuccess ||   // epoch 0 is never used
+            hipEventCreateWithFlags(&ctx->orb_ev[k], hipEventDisableTiming) != hipSuccess) {
             ft_context_destroy(ctx);
             return FT_ERR_DEVICE;
         }
+        off += orb_bytes;
     }
     ctx->d_edit_ring = ctx->base + off;
     off += ctx->edit_ring_bytes;
@@ -1727,9 +1734,14 @@ ft_status ft_orb_detect(ft_context *ctx, void *stream, const ft_pyramid *pyr, co
     const int slot = ctx->orb_next;
     ctx->orb_next = (slot + 1) % ft_context::kOrbSlots;
     if (ctx->orb_used[slot]) HIP_TRY(ctx, hipEventSynchronize(ctx->orb_ev[slot]));
-    a.tile_count = ctx->orb_tiles[slot];
+    a.tile_state = ctx->orb_state[slot];
+    a.ticket = ctx->orb_ticket[slot];
+    a.ticket_base = ctx->orb_base[slot];
+    a.epoch = ++ctx->orb_epoch[slot];
+    if (a.epoch == 0) a.epoch = ++ctx->orb_epoch[slot];   // 0 marks never-written state
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(ctx, launch_orb_detect(a, s));
+    ctx->orb_base[slot] += (uint32_t)tiles;   // the kernel takes exactly `tiles` tickets
     HIP_TRY(ctx, hipEventRecord(ctx->orb_ev[slot], s));
     ctx->orb_used[slot] = true;
     return FT_OK;

@@ -238,9 +238,9 @@ hipError_t launch_map_edit_many(const MapEditDesc *descs, const int32_t *moves, 
                                 int n_apps, hipStream_t stream);
 
 // ORB extraction (ft_orb.hip).  Detection runs over row tiles of every level
-// of one pyramid: kOrbRows output rows per 256-thread workgroup, the level
-// rows they need staged in LDS (kOrbHalo above and below: the FAST ring and
-// the suppression), so a pyramid has at most kOrbMaxTiles tiles.
+// of one pyramid: kOrbRows output rows per workgroup, the level rows they need
+// staged in LDS (kOrbHalo above and below: the FAST ring and the
+// suppression), so a pyramid has at most kOrbMaxTiles tiles.
 constexpr int kOrbRows = 8;
 constexpr int kOrbHalo = 4;
 constexpr int kOrbMaxTiles = kLevels * (kMaxRows / kOrbRows);
@@ -253,7 +253,11 @@ struct OrbDetectArgs {
     float sf[kLevels];
     int32_t tile0[kLevels + 1];       // first tile of each level; tile0[kLevels] = tiles
     int32_t t, edge, capacity, lds_w; // lds_w: LDS row stride (the widest level, rounded up to 4)
-    FT_G int32_t *tile_count;         // [tiles] corners kept per tile
+    // single-pass emission: tiles are taken by ticket (ticket counter - ticket_base), and each
+    // publishes its count and then its inclusive prefix in tile_state, tagged with this call's epoch
+    FT_G unsigned long long *tile_state;  // [kOrbMaxTiles]
+    FT_G uint32_t *ticket;
+    uint32_t ticket_base, epoch;
     FT_G int16_t *lx, *ly;
     FT_G uint8_t *oct, *score;
     FT_G float *x, *y;

@@ -5,13 +5,12 @@
 //  * k_orb_detect: one 1024-thread workgroup per tile of kOrbRows rows of one
 //    level.  The tile's level rows and kOrbHalo rows above and below are
 //    staged in LDS; FAST-9 scores (a compass-point quick test first) fill a
-//    score band one row larger on each side; strict 3x3 suppression counts
-//    the tile's corners; the descriptor's binomial smoothing of the tile's
-//    rows is written from the same staged rows.
-//  * k_orb_emit: the same staging, scores and suppression; the tile's first
-//    output index is the sum of the counts of the tiles before it (tiles are
-//    in (level, row) order), and corners are written in (row, x) order within
-//    the tile by wave ballots.
+//    score band one row larger on each side; strict 3x3 suppression collects
+//    the tile's corners in (row, column) order in LDS; the tile's first output
+//    index comes from a decoupled look-back over the counts of the tiles
+//    before it (tiles are in (level, row) order and taken by ticket), and the
+//    corners are written contiguously; the descriptor's binomial smoothing of
+//    the tile's rows is written from the same staged rows.
 //  * k_orb_describe: one wave per keypoint: the intensity-centroid moments
 //    over the radius-15 disc (lanes stride the disc, one wave reduction), then
 //    four tests per lane on the smoothed level with the pattern turned exactly
@@ -171,101 +170,34 @@ __device__ __forceinline__ bool kept(const unsigned char *sc, int S, int r, int 
 
 constexpr int kDetWaves = kDetThreads / 64;
 
-// Sum over the workgroup; `red` holds kDetWaves + 1 ints.  The total is formed
-// once, behind a barrier, so no thread keeps the per-wave sums live.
-__device__ __forceinline__ int block_sum(int v, int *red)
-{
-    _Pragma("unroll") for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int s = 0;
-        for (int w = 0; w < kDetWaves; ++w) s += red[w];
-        red[kDetWaves] = s;
-    }
-    __syncthreads();
-    const int s = __builtin_amdgcn_readfirstlane(red[kDetWaves]);
-    __syncthreads();
-    return s;
-}
+// Look-back state of a tile: epoch << 32 | flag << 30 | value (corners).
+constexpr unsigned long long kAggregate = 1ull << 30, kInclusive = 2ull << 30;
+constexpr uint32_t kValueMask = (1u << 30) - 1u;
+constexpr int kMaxSpins = 1 << 16;       // bounds every wait (a tile found stuck poisons the prefix)
+constexpr int kPoison = 1 << 29;         // prefix of a tile whose predecessors never published
 
 __global__ __launch_bounds__(kDetThreads, 8) void k_orb_detect(OrbDetectArgs a)
 {
     extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int red[kDetWaves + 1];
-    const int tile = blockIdx.x;
+    __shared__ int wave_n[kDetWaves];
+    __shared__ int shared_tile, shared_prefix;
+    // tiles by ticket: every lower tile has been taken by a running workgroup,
+    // and none waits on a higher one, so each wait below ends
+    if (threadIdx.x == 0) shared_tile = (int)(atomicAdd(a.ticket, 1u) - a.ticket_base);
+    __syncthreads();
+    const int tile = shared_tile;
+    const int tiles = a.tile0[kLevels];
     const int l = level_of_tile(a, tile);
     const int W = a.w[l], H = a.h[l], S = W;
     const int y0 = (tile - a.tile0[l]) * kOrbRows;
     const int rows = min(kOrbRows, H - y0);
     const unsigned char *px = stage_and_score(a, l, y0, rows, lds);
     const unsigned char *sc = score_band(a, lds);
-    int cnt = 0;
-    for (int r = 0; r < rows; ++r)
-        for (int x = threadIdx.x; x < W; x += kDetThreads) cnt += kept(sc, S, r, x, W) ? 1 : 0;
-    cnt = block_sum(cnt, red);
-    if (threadIdx.x == 0) a.tile_count[tile] = cnt;
-    if (!a.blurred) return;
-    // smoothing: per column, horizontal sums of staged rows 1 .. rows + 6 (level
-    // rows y0 - 3 .. y0 + rows + 2, clamped), then the vertical taps
-    FT_G uint8_t *dst = a.blurred + a.off[l];
-    constexpr int kw[7] = {1, 6, 15, 20, 15, 6, 1};
-    for (int x = threadIdx.x; x < W; x += kDetThreads) {
-        int xs[7];
-        _Pragma("unroll") for (int i = 0; i < 7; ++i)
-        {
-            const int v = x + i - 3;
-            xs[i] = v < 0 ? 0 : (v > W - 1 ? W - 1 : v);
-        }
-        int hs[kOrbRows + 6];
-        _Pragma("unroll") for (int k = 0; k < kOrbRows + 6; ++k)
-        {
-            const unsigned char *row = px + (k + 1) * S;
-            int acc = 0;
-            _Pragma("unroll") for (int i = 0; i < 7; ++i) acc += kw[i] * row[xs[i]];
-            hs[k] = acc;
-        }
-        _Pragma("unroll") for (int r = 0; r < kOrbRows; ++r)
-        {
-            if (r < rows) {
-                int acc = 0;
-                _Pragma("unroll") for (int j = 0; j < 7; ++j) acc += kw[j] * hs[r + j];
-                dst[(int64_t)(y0 + r) * W + x] = (uint8_t)((acc + 2048) >> 12);
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
-{
-    extern __shared__ __align__(16) unsigned char lds[];
-    __shared__ int red[kDetWaves + 1];
-    __shared__ int wave_n[kDetWaves];
-    const int tile = blockIdx.x;
-    const int l = level_of_tile(a, tile);
-    const int W = a.w[l], H = a.h[l], S = W;
-    const int y0 = (tile - a.tile0[l]) * kOrbRows;
-    const int rows = min(kOrbRows, H - y0);
-    const int tiles = a.tile0[kLevels];
-    // first output index: the corners of every earlier tile
-    int before = 0, all = 0;
-    for (int k = threadIdx.x; k < tiles; k += kDetThreads) {
-        const int c = a.tile_count[k];
-        all += c;
-        before += k < tile ? c : 0;
-    }
-    before = block_sum(before, red);
-    if (tile == 0) {
-        all = block_sum(all, red);
-        if (threadIdx.x == 0) a.count[0] = all;
-    }
-    stage_and_score(a, l, y0, rows, lds);
-    const unsigned char *sc = score_band(a, lds);
-    // the tile's corners in (row, column) order, packed column | row << 11 |
-    // score << 14, then written to the outputs contiguously
-    uint32_t *tc = corner_list(a, lds);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long ep = (unsigned long long)a.epoch << 32;
+    // the tile's corners in (row, column) order, packed column | row << 11 |
+    // score << 14
+    uint32_t *tc = corner_list(a, lds);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     int n = 0;
     for (int r = 0; r < rows; ++r)
@@ -283,7 +215,48 @@ __global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
             if (k) tc[off + __popcll(m & below)] = (uint32_t)x | ((uint32_t)r << 11) | ((uint32_t)sc[(r + 1) * S + x] << 14);
             n += chunk;
         }
+    // decoupled look-back: the tile publishes its count; wave 0 then reads 64
+    // predecessors' states at a time and adds the counts down to the nearest
+    // inclusive prefix (a window with an unpublished state before it is read
+    // again); the tile then publishes its own inclusive prefix
+    if (wave == 0) {
+        int prefix = 0;
+        if (lane == 0)
+            atomicExch(&a.tile_state[tile], ep | (tile == 0 ? kInclusive : kAggregate) | (unsigned long long)n);
+        if (tile > 0) {
+            int top = tile - 1, spins = 0;
+            for (;;) {
+                const int k = top - lane;
+                unsigned long long v = ep | kInclusive;          // before tile 0: an inclusive 0
+                if (k >= 0) v = atomicOr(&a.tile_state[k], 0ull);  // coherent read
+                const bool pub = (v >> 32) == a.epoch && (v & (3ull << 30));
+                const uint64_t inc = __ballot(pub && (v & kInclusive));
+                const uint64_t unpub = __ballot(!pub);
+                const int first = inc ? __ffsll((long long)inc) - 1 : 64;   // nearest inclusive lane
+                const uint64_t upto = first == 64 ? ~0ull : (~0ull >> (63 - first));
+                if (unpub & upto) {
+                    if (++spins > kMaxSpins) {
+                        prefix += kPoison;
+                        break;
+                    }
+                    continue;
+                }
+                int add = (lane <= first) ? (int)(v & kValueMask) : 0;
+                _Pragma("unroll") for (int o = 32; o > 0; o >>= 1) add += __shfl_xor(add, o);
+                prefix += add;
+                if (first < 64) break;
+                top -= 64;
+            }
+            if (lane == 0)
+                atomicExch(&a.tile_state[tile], ep | kInclusive | (unsigned long long)min(prefix + n, (int)kValueMask));
+        }
+        if (lane == 0) {
+            shared_prefix = prefix;
+            if (tile == tiles - 1) a.count[0] = prefix + n >= kPoison ? -1 : prefix + n;
+        }
+    }
     __syncthreads();
+    const int before = shared_prefix;
     const float sf = a.sf[l];
     for (int k = threadIdx.x; k < n; k += kDetThreads) {
         const int i = before + k;
@@ -296,6 +269,36 @@ __global__ __launch_bounds__(kDetThreads, 8) void k_orb_emit(OrbDetectArgs a)
         a.score[i] = (uint8_t)(e >> 14);
         a.x[i] = (float)x * sf;
         a.y[i] = (float)yy * sf;
+    }
+    if (a.blurred) {
+        // smoothing: per column, horizontal sums of staged rows 1 .. rows + 6
+        // (level rows y0 - 3 .. y0 + rows + 2, clamped), then the vertical taps
+        FT_G uint8_t *dst = a.blurred + a.off[l];
+        constexpr int kw[7] = {1, 6, 15, 20, 15, 6, 1};
+        for (int x = threadIdx.x; x < W; x += kDetThreads) {
+            int xs[7];
+            _Pragma("unroll") for (int i = 0; i < 7; ++i)
+            {
+                const int v = x + i - 3;
+                xs[i] = v < 0 ? 0 : (v > W - 1 ? W - 1 : v);
+            }
+            int hs[kOrbRows + 6];
+            _Pragma("unroll") for (int k = 0; k < kOrbRows + 6; ++k)
+            {
+                const unsigned char *row = px + (k + 1) * S;
+                int acc = 0;
+                _Pragma("unroll") for (int i = 0; i < 7; ++i) acc += kw[i] * row[xs[i]];
+                hs[k] = acc;
+            }
+            _Pragma("unroll") for (int r = 0; r < kOrbRows; ++r)
+            {
+                if (r < rows) {
+                    int acc = 0;
+                    _Pragma("unroll") for (int j = 0; j < 7; ++j) acc += kw[j] * hs[r + j];
+                    dst[(int64_t)(y0 + r) * W + x] = (uint8_t)((acc + 2048) >> 12);
+                }
+            }
+        }
     }
 }
 
@@ -455,7 +458,6 @@ hipError_t launch_orb_detect(const OrbDetectArgs &a, hipStream_t s)
     if (tiles <= 0) return hipSuccess;
     const size_t lds = orb_detect_lds(a.lds_w);
     hipLaunchKernelGGL(k_orb_detect, dim3(tiles), dim3(kDetThreads), lds, s, a);
-    hipLaunchKernelGGL(k_orb_emit, dim3(tiles), dim3(kDetThreads), lds, s, a);
     return hipGetLastError();
 }
 
