@@ -401,7 +401,8 @@ ft_status ft_map_update(ft_context *ctx, void *stream, ft_map_points *map, int32
  * no map, no id record changes and nothing is enqueued.  The edits' pairs and
  * appends are staged together in the context's pinned staging, copied to the
  * device in one command, and applied by two kernels for all n maps.  Errors:
- * as ft_map_update, two edits naming one map: FT_ERR_INVALID_ARGUMENT; more
+ * as ft_map_update, two edits naming one map or sharing an id record:
+ * FT_ERR_INVALID_ARGUMENT; more
  * than 4096 edits, or staging above half the context's edit staging (which is
  * max(16 x max_map_points, 8 MiB) bytes; a call stages 88 B per edit, 12 B per
  * moved point and 8 B per inserted point): FT_ERR_CAPACITY. */

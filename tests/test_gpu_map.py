@@ -339,6 +339,9 @@ def test_many_maps_edited_in_one_call(ft, ctx):
     good1b, _ = edit_for(1)
     assert ctx.ft_map_update_many([dms[1].struct, dms[1].struct], [caps[1], caps[1]], [good1, good1b],
                                   check=False) == ft.FT_ERR_INVALID_ARGUMENT
+    shared = ft.ft_map_edit(0, None, ft.ft_map_points(), None, ct.pointer(recs[2][2]))
+    assert ctx.ft_map_update_many([dms[2].struct, dms[3].struct], [caps[2], caps[3]], [shared, shared],
+                                  check=False) == ft.FT_ERR_INVALID_ARGUMENT
     assert ctx.ft_map_update_many([], [], []) == ft.FT_OK
     torch.cuda.synchronize()
     for k, (n, r) in enumerate(snap):
