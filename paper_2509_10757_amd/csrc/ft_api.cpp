@@ -1611,7 +1611,8 @@ ft_status ft_map_update_many(ft_context *ctx, void *stream, int32_t n, ft_map_po
         for (int k = 0; k < i; ++k) {
             if (maps[k]->pos == maps[i]->pos)
                 return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update many: edits %d and %d name one map", k, i);
-            if (edits[i].ids && (edits[k].ids == edits[i].ids || edits[k].ids->slot_of == edits[i].ids->slot_of))
+            if (edits[i].ids && edits[k].ids &&
+                (edits[k].ids == edits[i].ids || edits[k].ids->slot_of == edits[i].ids->slot_of))
                 return fail(ctx, FT_ERR_INVALID_ARGUMENT, "map update many: edits %d and %d share an id record", k, i);
         }
         moves += pe[i].n_holes;
