@@ -131,17 +131,32 @@ __device__ __forceinline__ Top2<T> top2_merge(Top2<T> t, T o1, T o2)
     return r;
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
-__device__ __forceinline__ int wave_inclusive_scan(int v)
+// Inclusive prefix across the 64 lanes of a wave (every lane active) with DPP
+// lane moves: shifts by 1, 2, 4 and 8 inside each row of 16 lanes (lanes whose
+// source lies in another row read 0), then lane 15 of rows 0 and 2 into rows
+// 1 and 3, then lane 31 into rows 2 and 3.  Six VALU steps, no LDS traffic;
+// 0 is the identity of both operations used (sum, and max of values >= 0).
+template <bool kMax>
+__device__ __forceinline__ int wave_inclusive_dpp(int v)
 {
-    const int lane = threadIdx.x & 63;
-    _Pragma("unroll") for (int o = 1; o < 64; o <<= 1)
-    {
-        const int t = __shfl_up(v, o, 64);
-        v += lane >= o ? t : 0;
-    }
+    auto op = [](int a, int b) { return kMax ? max(a, b) : a + b; };
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = op(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
     return v;
 }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_scan(int v) { return wave_inclusive_dpp<false>(v); }
+
+// Inclusive prefix maximum of non-negative values across the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_max(int v) { return wave_inclusive_dpp<true>(v); }
+
+// Value of lane 63 (the total of an inclusive scan), wave-uniform.
+__device__ __forceinline__ int wave_last(int v) { return __builtin_amdgcn_readlane(v, 63); }
 
 // Workgroup-wide exclusive scan of a[0..n) in LDS; returns the total.  Each
 // thread owns a contiguous run of a[], the runs' sums are scanned inside each
@@ -1578,20 +1593,25 @@ __device__ __forceinline__ void wave_lds_sync()
 // point and loads the record ranges of up to kDealRows window rows at once;
 // the wave then lays the records of all 64 windows end to end and deals them
 // in contiguous runs of at most kDealRecs per lane, so every lane issues all
-// its record loads together whatever the window sizes.  Records that pass the
+// its record loads together whatever the window sizes.  The map lane that owns
+// a run's first record is found without a search: each map lane marks the
+// first run that starts inside its records (LDS atomic maximum, stamped with
+// the round), and owners never decrease along the runs, so a prefix maximum
+// over the marks hands every run its owner.  Records that pass the
 // window test become candidates in one wave-wide list, which is again dealt
 // evenly for the descriptor reads; each map point's best two keys are kept in
 // LDS by 32-bit atomic minima.
 constexpr int kDealRows = 4;    // window rows per lane and chunk
 constexpr int kDealRecs = 4;    // records per lane and round
 constexpr int kDealFlush = 1;   // candidates per lane and descriptor batch
+static_assert(kDealRecs <= 4, "run owner marks: ceil(a / run) multipliers cover runs of 1..4 records");
 constexpr int kDealQp = 0;                                // float4 u, v, Rm, level window [64]
 constexpr int kDealUr = kDealQp + 64 * 16;                // float uR [64]
 constexpr int kDealQd = kDealUr + 64 * 4;                 // Desc [64]
 constexpr int kDealTb = kDealQd + 64 * 32;                // best [64], second [64]
 constexpr int kDealSeg = kDealTb + 128 * 4;               // row segments [64][kDealRows]: start | count << 16
-constexpr int kDealBase = kDealSeg + 64 * kDealRows * 4;  // record prefix per lane [65]
-constexpr int kDealCands = kDealBase + 80 * 4;            // candidate list [64 * kDealRecs]
+constexpr int kDealMark = kDealSeg + 64 * kDealRows * 4;  // run owner marks [64]: round << 7 | lane + 1
+constexpr int kDealCands = kDealMark + 64 * 4;            // candidate list [64 * kDealRecs]
 constexpr int kDealLdsPerWave = kDealCands + 64 * kDealRecs * 4;
 
 __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, int tile, unsigned char *smem)
@@ -1604,7 +1624,7 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
     Desc *qd = reinterpret_cast<Desc *>(base + kDealQd);
     uint32_t *tb = reinterpret_cast<uint32_t *>(base + kDealTb);
     uint32_t *seg = reinterpret_cast<uint32_t *>(base + kDealSeg);
-    int *lbase = reinterpret_cast<int *>(base + kDealBase);
+    uint32_t *mark = reinterpret_cast<uint32_t *>(base + kDealMark);
     uint32_t *cl = reinterpret_cast<uint32_t *>(base + kDealCands);
 
     Query q;
@@ -1619,9 +1639,10 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
     qd[lane] = q.dm;
     tb[lane] = 0xFFFFFFFFu;
     tb[64 + lane] = 0xFFFFFFFFu;
+    mark[lane] = 0u;
     const bool gate = V.u_right != nullptr;
-    int chunks = (cy1 - cy0 + kDealRows) / kDealRows;
-    for (int o = 32; o >= 1; o >>= 1) chunks = max(chunks, __shfl_xor(chunks, o));
+    const int chunks = wave_last(wave_inclusive_max((cy1 - cy0 + kDealRows) / kDealRows));
+    uint32_t rid = 0;   // round number, stamps the marks
     for (int ch = 0; ch < chunks; ++ch) {
         // record ranges of this lane's rows of the chunk: one round of loads
         const int r0 = cy0 + ch * kDealRows;
@@ -1638,30 +1659,35 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
             mine += n;
         }
         const int incl = wave_inclusive_scan(mine);
-        const int total = __shfl(incl, 63);
-        wave_lds_sync();   // the previous chunk's readers are done with seg / lbase
-        lbase[lane] = incl - mine;
-        if (lane == 63) lbase[64] = total;
+        const int excl = incl - mine;
+        const int total = wave_last(incl);
+        wave_lds_sync();   // the previous chunk's readers are done with seg
         _Pragma("unroll") for (int e = 0; e < kDealRows; ++e) seg[lane * kDealRows + e] = sg[e];
-        wave_lds_sync();
         for (int g_lo = 0; g_lo < total; g_lo += 64 * kDealRecs) {
             const int cnt = min(total - g_lo, 64 * kDealRecs);
-            const int run = (cnt + 63) >> 6;
+            const int run = (cnt + 63) >> 6;   // 1..kDealRecs, wave-uniform
             const int g0 = g_lo + min(lane * run, cnt), g1 = g_lo + min(lane * run + run, cnt);
-            // the run's first record: owning lane s (last lane whose prefix is
-            // <= g0), then its row segment
+            // Mark the first run (lane d, starting at record d * run of the
+            // round) that starts inside this lane's records [a, b) of the round:
+            // d = ceil(a / run), by a multiply that is exact for a + run - 1 <= 258.
+            ++rid;
+            const int a = excl - g_lo, b = min(incl - g_lo, cnt);
+            if (a < b && b > 0) {
+                const uint32_t mg = run == 1 ? 65536u : run == 2 ? 32768u : run == 3 ? 21846u : 16384u;
+                const int d = a <= 0 ? 0 : (int)(((uint32_t)(a + run - 1) * mg) >> 16);
+                if (d * run < b) atomicMax(&mark[d], (rid << 7) | (uint32_t)(lane + 1));
+            }
+            wave_lds_sync();
+            const uint32_t mv = mark[lane];
+            // the run's first record: owning lane s, then its row segment
+            const int s0 = wave_inclusive_max((mv >> 7) == rid ? (int)(mv & 127u) : 0) - 1;
+            const int ex_s = __shfl(excl, max(s0, 0));
             int s = 0;
             int e = 0, off = 0;
             uint32_t cur = 0;
             if (g0 < g1) {
-                int lo = 0, hi = 63;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (lbase[mid] <= g0) lo = mid;
-                    else hi = mid - 1;
-                }
-                s = lo;
-                off = g0 - lbase[s];
+                s = max(s0, 0);   // a run always has an owner; the clamp keeps a slip inside the arrays
+                off = g0 - ex_s;
                 cur = seg[s * kDealRows];
                 while (off >= (int)(cur >> 16)) {
                     off -= (int)(cur >> 16);
@@ -1712,7 +1738,7 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
                 }
             }
             const int cincl = wave_inclusive_scan(nc);
-            const int ctot = __shfl(cincl, 63);
+            const int ctot = wave_last(cincl);
             int cw = cincl - nc;
             _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k) if (cand[k] != 0xFFFFFFFFu) cl[cw++] = cand[k];
             wave_lds_sync();
