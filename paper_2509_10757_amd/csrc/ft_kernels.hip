@@ -1592,26 +1592,21 @@ __device__ __forceinline__ void wave_lds_sync()
 // Record-dealt search (one lane per map point).  Every lane projects its map
 // point and loads the record ranges of up to kDealRows window rows at once;
 // the wave then lays the records of all 64 windows end to end and deals them
-// in contiguous runs of at most kDealRecs per lane, so every lane issues all
-// its record loads together whatever the window sizes.  The map lane that owns
-// a run's first record is found without a search: each map lane marks the
-// first run that starts inside its records (LDS atomic maximum, stamped with
-// the round), and owners never decrease along the runs, so a prefix maximum
-// over the marks hands every run its owner.  Records that pass the
-// window test become candidates in one wave-wide list, which is again dealt
-// evenly for the descriptor reads; each map point's best two keys are kept in
-// LDS by 32-bit atomic minima.
+// out in rounds of 64 * kDealRecs positions, lane d taking positions d, d + 64,
+// d + 128, ..., so every lane issues all its record loads together whatever
+// the window sizes and each load instruction reads 64 consecutive positions.
+// Records that pass the window test become candidates in one wave-wide list,
+// which is again dealt evenly for the descriptor reads; each map point's best
+// two keys are kept in LDS by 32-bit atomic minima.
 constexpr int kDealRows = 4;    // window rows per lane and chunk
 constexpr int kDealRecs = 4;    // records per lane and round
 constexpr int kDealFlush = 1;   // candidates per lane and descriptor batch
-static_assert(kDealRecs <= 4, "run owner marks: ceil(a / run) multipliers cover runs of 1..4 records");
 constexpr int kDealQp = 0;                                // float4 u, v, Rm, level window [64]
 constexpr int kDealUr = kDealQp + 64 * 16;                // float uR [64]
 constexpr int kDealQd = kDealUr + 64 * 4;                 // Desc [64]
 constexpr int kDealTb = kDealQd + 64 * 32;                // best [64], second [64]
-constexpr int kDealSeg = kDealTb + 128 * 4;               // row segments [64][kDealRows]: start | count << 16
-constexpr int kDealMark = kDealSeg + 64 * kDealRows * 4;  // run owner marks [64]: round << 7 | lane + 1
-constexpr int kDealCands = kDealMark + 64 * 4;            // candidate list [64 * kDealRecs]
+constexpr int kDealSeg = kDealTb + 128 * 4;               // record offset of each segment [64][kDealRows]
+constexpr int kDealCands = kDealSeg + 64 * kDealRows * 4;  // candidate list [64 * kDealRecs], or the round's marks
 constexpr int kDealLdsPerWave = kDealCands + 64 * kDealRecs * 4;
 
 __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, int tile, unsigned char *smem)
@@ -1624,8 +1619,8 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
     Desc *qd = reinterpret_cast<Desc *>(base + kDealQd);
     uint32_t *tb = reinterpret_cast<uint32_t *>(base + kDealTb);
     uint32_t *seg = reinterpret_cast<uint32_t *>(base + kDealSeg);
-    uint32_t *mark = reinterpret_cast<uint32_t *>(base + kDealMark);
     uint32_t *cl = reinterpret_cast<uint32_t *>(base + kDealCands);
+    uint32_t *mark = cl;
 
     Query q;
     q.vis = false;
@@ -1639,90 +1634,70 @@ __device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V
     qd[lane] = q.dm;
     tb[lane] = 0xFFFFFFFFu;
     tb[64 + lane] = 0xFFFFFFFFu;
-    mark[lane] = 0u;
     const bool gate = V.u_right != nullptr;
     const int chunks = wave_last(wave_inclusive_max((cy1 - cy0 + kDealRows) / kDealRows));
-    uint32_t rid = 0;   // round number, stamps the marks
     for (int ch = 0; ch < chunks; ++ch) {
         // record ranges of this lane's rows of the chunk: one round of loads
         const int r0 = cy0 + ch * kDealRows;
-        uint32_t sg[kDealRows];
+        int sa[kDealRows], sn[kDealRows];
         int mine = 0;
         _Pragma("unroll") for (int e = 0; e < kDealRows; ++e)
         {
             const bool in = r0 + e <= cy1;
             const int row = in ? r0 + e : 0;
-            const int a = off[row * V.cols + cx0];
+            sa[e] = off[row * V.cols + cx0];
             const int b = off[row * V.cols + cx1 + 1];
-            const int n = in ? b - a : 0;
-            sg[e] = (uint32_t)a | ((uint32_t)n << 16);
-            mine += n;
+            sn[e] = in ? b - sa[e] : 0;
+            mine += sn[e];
         }
         const int incl = wave_inclusive_scan(mine);
-        const int excl = incl - mine;
         const int total = wave_last(incl);
+        // the records of all segments (lane, row) end to end: a segment's first
+        // position in the chunk, and the offset from a position to its record
+        int st[kDealRows];
+        st[0] = incl - mine;
+        _Pragma("unroll") for (int e = 1; e < kDealRows; ++e) st[e] = st[e - 1] + sn[e - 1];
         wave_lds_sync();   // the previous chunk's readers are done with seg
-        _Pragma("unroll") for (int e = 0; e < kDealRows; ++e) seg[lane * kDealRows + e] = sg[e];
+        _Pragma("unroll") for (int e = 0; e < kDealRows; ++e) seg[lane * kDealRows + e] = (uint32_t)(sa[e] - st[e]);
         for (int g_lo = 0; g_lo < total; g_lo += 64 * kDealRecs) {
             const int cnt = min(total - g_lo, 64 * kDealRecs);
-            const int run = (cnt + 63) >> 6;   // 1..kDealRecs, wave-uniform
-            const int g0 = g_lo + min(lane * run, cnt), g1 = g_lo + min(lane * run + run, cnt);
-            // Mark the first run (lane d, starting at record d * run of the
-            // round) that starts inside this lane's records [a, b) of the round:
-            // d = ceil(a / run), by a multiply that is exact for a + run - 1 <= 258.
-            ++rid;
-            const int a = excl - g_lo, b = min(incl - g_lo, cnt);
-            if (a < b && b > 0) {
-                const uint32_t mg = run == 1 ? 65536u : run == 2 ? 32768u : run == 3 ? 21846u : 16384u;
-                const int d = a <= 0 ? 0 : (int)(((uint32_t)(a + run - 1) * mg) >> 16);
-                if (d * run < b) atomicMax(&mark[d], (rid << 7) | (uint32_t)(lane + 1));
+            // Position g_lo + 64k + d of the chunk goes to lane d.  Each
+            // non-empty segment writes its id + 1 at its first position of the
+            // round (position 0 for the one begun in an earlier round); no two
+            // segments share a position and ids grow with positions, so the
+            // prefix maximum over positions names every position's segment.
+            // The marks use the candidate list's memory.
+            *reinterpret_cast<uint4 *>(mark + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+            wave_lds_sync();
+            _Pragma("unroll") for (int e = 0; e < kDealRows; ++e)
+            {
+                const int A = st[e] - g_lo;
+                if (sn[e] > 0 && A < cnt && A + sn[e] > 0) mark[max(A, 0)] = (uint32_t)(lane * kDealRows + e + 1);
             }
             wave_lds_sync();
-            const uint32_t mv = mark[lane];
-            // the run's first record: owning lane s, then its row segment
-            const int s0 = wave_inclusive_max((mv >> 7) == rid ? (int)(mv & 127u) : 0) - 1;
-            const int ex_s = __shfl(excl, max(s0, 0));
-            int s = 0;
-            int e = 0, off = 0;
-            uint32_t cur = 0;
-            if (g0 < g1) {
-                s = max(s0, 0);   // a run always has an owner; the clamp keeps a slip inside the arrays
-                off = g0 - ex_s;
-                cur = seg[s * kDealRows];
-                while (off >= (int)(cur >> 16)) {
-                    off -= (int)(cur >> 16);
-                    cur = seg[s * kDealRows + ++e];
-                }
-            }
-            // the run's records: record index | map lane << 16
-            uint32_t key[kDealRecs];
+            int own[kDealRecs];
+            int carry = 0;
             _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k)
             {
-                const bool v = g0 + k < g1;
-                key[k] = v ? (((cur & 0xFFFFu) + (uint32_t)off) | ((uint32_t)s << 16)) : 0u;
-                if (v && g0 + k + 1 < g1) {
-                    if (++off == (int)(cur >> 16)) {
-                        off = 0;
-                        do {
-                            if (++e == kDealRows) {
-                                e = 0;
-                                ++s;
-                            }
-                            cur = seg[s * kDealRows + e];
-                        } while ((cur >> 16) == 0u);
-                    }
-                }
+                own[k] = max(wave_inclusive_max((int)mark[k * 64 + lane]), carry) - 1;
+                carry = wave_last(own[k]) + 1;
             }
+            // the records: position + its segment's offset, 64 consecutive
+            // positions per load instruction
             CellRec rec[kDealRecs];
-            _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k) if (g0 + k < g1) rec[k] = V.crec[key[k] & 0xFFFFu];
+            _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k)
+            {
+                const int p = k * 64 + lane;
+                if (p < cnt) rec[k] = V.crec[g_lo + p + (int)seg[max(own[k], 0)]];
+            }
             // window test; candidates as keypoint | level << 16 | map lane << 20
             uint32_t cand[kDealRecs];
             int nc = 0;
             _Pragma("unroll") for (int k = 0; k < kDealRecs; ++k)
             {
                 cand[k] = 0xFFFFFFFFu;
-                if (g0 + k < g1) {
-                    const int ml = (int)(key[k] >> 16);
+                if (k * 64 + lane < cnt) {
+                    const int ml = max(own[k], 0) / kDealRows;
                     const float4 qq = qp[ml];
                     const int l = __float_as_int(qq.w);
                     Query iq;
