@@ -1609,11 +1609,11 @@ constexpr int kDealSeg = kDealTb + 128 * 4;               // record offset of ea
 constexpr int kDealCands = kDealSeg + 64 * kDealRows * 4;  // candidate list [64 * kDealRecs], or the round's marks
 constexpr int kDealLdsPerWave = kDealCands + 64 * kDealRecs * 4;
 
-__device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, int tile, unsigned char *smem)
+// The wave takes map points m0 .. m0 + 63 of the view; `base` is its LDS.
+__device__ __forceinline__ void ph_search_deal(const DevJob &J, const DevView &V, int m0, unsigned char *base)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m = tile * kWG + wave * 64 + lane;
-    unsigned char *base = smem + wave * kDealLdsPerWave;
+    const int lane = threadIdx.x & 63;
+    const int m = m0 + lane;
     float4 *qp = reinterpret_cast<float4 *>(base + kDealQp);
     float *quR = reinterpret_cast<float *>(base + kDealUr);
     Desc *qd = reinterpret_cast<Desc *>(base + kDealQd);
@@ -2015,9 +2015,11 @@ __device__ __forceinline__ void ph_last_final(const DevJob &J, const DevView &V,
 
 // ------------------------------------------------------- tile bookkeeping
 
+// Search tiles of a view: one wave of 64 map points for the record-dealt
+// search (one lane per map point), else kWG / lanes map points.
 __host__ __device__ inline int search_tiles_per_view(const DevJob &J, int lanes)
 {
-    return div_up(J.nM, kWG / lanes);
+    return div_up(J.nM, lanes == 1 ? 64 : kWG / lanes);
 }
 
 
@@ -2138,7 +2140,7 @@ __device__ __forceinline__ void task_search(const DevJob &J, int tile, unsigned 
     const int tpv = search_tiles_per_view(J, G);
     const int v = tile / tpv;
     if (v >= J.n_views) return;
-    if constexpr (G == 1) ph_search_deal(J, J.view[v], tile - v * tpv, smem);
+    if constexpr (G == 1) ph_search_deal(J, J.view[v], (tile - v * tpv) * 64, smem);
     else ph_search<G>(J, J.view[v], tile - v * tpv);
 }
 
@@ -2153,7 +2155,7 @@ __device__ __forceinline__ void task_search_final(const DevJob &J, int tile)
 static_assert(256 * 8 + 4 * kKnnQueriesPerWG * 2 * 4 <= kTaskLds, "stereo_a LDS");
 static_assert(kRefinePerWG * kRefineLds <= kTaskLds, "refine LDS");
 static_assert(kRefineQPerWG * kRefineQLds <= kTaskLds, "refine LDS (quarter waves)");
-static_assert(4 * kDealLdsPerWave <= kTaskLds, "record-dealt search LDS");
+static_assert(kDealLdsPerWave <= kTaskLds, "record-dealt search LDS");
 static_assert((256 + kWG + 8) * 4 + (kMaxKp + 32) / 32 * 4 <= kTaskLds, "median LDS");
 
 // ------------------------------------------------------- per-phase kernels
@@ -2213,14 +2215,24 @@ __global__ __launch_bounds__(NT) void k_stereo_c(Src src)
 }
 
 template <class Src, int G>
-// Six waves per SIMD: the record-dealt search's LDS allows six workgroups per
-// CU, and registers are capped to match.
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_search(Src src)
+__global__ __launch_bounds__(kWG) void k_search(Src src)
 {
-    __shared__ __align__(16) unsigned char smem[G == 1 ? 4 * kDealLdsPerWave : 16];
     int job, tile;
     if (!src.locate(PH_SEARCH, job, tile)) return;
-    task_search<G>(src(job), tile, smem);
+    task_search<G>(src(job), tile, nullptr);
+}
+
+// Record-dealt search in one-wave workgroups: a wave's LDS and registers are
+// released as soon as it ends (waves of one workgroup would hold theirs until
+// the slowest ends), and single-wave workgroups take no barrier slot, so LDS
+// alone bounds the waves per CU.  Registers are capped at seven waves per SIMD.
+template <class Src>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_search_deal(Src src)
+{
+    __shared__ __align__(16) unsigned char smem[kDealLdsPerWave];
+    int job, tile;
+    if (!src.locate(PH_SEARCH, job, tile)) return;
+    task_search<1>(src(job), tile, smem);
 }
 
 template <class Src>
@@ -2369,7 +2381,7 @@ static void *phase_kernel(const Shapes &sh, int p, int *block)
         return reinterpret_cast<void *>(&k_stereo_c<Src, kWG>);
     case PH_SEARCH:
         switch (sh.search_lanes) {
-        case 1: return reinterpret_cast<void *>(&k_search<Src, 1>);
+        case 1: *block = 64; return reinterpret_cast<void *>(&k_search_deal<Src>);
         case 2: return reinterpret_cast<void *>(&k_search<Src, 2>);
         case 8: return reinterpret_cast<void *>(&k_search<Src, 8>);
         case 16: return reinterpret_cast<void *>(&k_search<Src, 16>);
