@@ -341,7 +341,7 @@ def phase_times(ctx, ft, submit, n, flush=None):
 
 def search_roofline(nbytes, us, traffic, note):
     achieved = nbytes / (us * 1e-6) / 1e9
-    return {"bound": "hbm", "kernel": "k_search (search by projection)", "achieved": round(achieved, 2),
+    return {"bound": "hbm", "kernel": "k_search_deal (search by projection)", "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": traffic, "algorithmic_bytes_per_launch": nbytes, "avg_launch_us": round(us, 3),
             "timed": note}
