@@ -823,21 +823,24 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
         const uint2 w = wn;
         const int tn = ((t + 4) << 4) + c;
         if (t + 4 < n_tiles && tn < nT) wn = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)tn + 8 * g);
+        // (a target past the end has zero bytes loaded; its column's sums are
+        // computed and never pushed)
         v4i B[4];
-        _Pragma("unroll") for (int s = 0; s < 4; ++s)
-            B[s] = tv ? expand16(tab, s < 2 ? w.x : w.y, s & 1) : v4i{0, 0, 0, 0};
+        _Pragma("unroll") for (int s = 0; s < 4; ++s) B[s] = expand16(tab, s < 2 ? w.x : w.y, s & 1);
         // acc[r] = -dot(query row 4g + r of block qb, target column c); the key
         // (256 - dot) << 15 | index = Hamming << 16 | index (dot = 256 - 2 H) is
-        // kbase + (acc << 15), one shift-add
+        // kbase + (acc << 15), one shift-add.  The blocks' MFMA chains are
+        // interleaved so that each hides the other's latency.
         const uint32_t kbase = (256u << 15) | (uint32_t)tj;
-        _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
-        {
-            v4i acc = {0, 0, 0, 0};
-            _Pragma("unroll") for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qb][s], B[s], acc, 0, 0, 0);
-            if (tv) {
+        v4i acc[QB];
+        _Pragma("unroll") for (int qb = 0; qb < QB; ++qb) acc[qb] = v4i{0, 0, 0, 0};
+        _Pragma("unroll") for (int s = 0; s < 4; ++s)
+            _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
+                acc[qb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[qb][s], B[s], acc[qb], 0, 0, 0);
+        if (tv) {
+            _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
                 _Pragma("unroll") for (int r = 0; r < 4; ++r)
-                    top2_push(ta[qb][r], tb[qb][r], kbase + ((uint32_t)acc[r] << 15));
-            }
+                    top2_push(ta[qb][r], tb[qb][r], kbase + ((uint32_t)acc[qb][r] << 15));
         }
     }
     _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
