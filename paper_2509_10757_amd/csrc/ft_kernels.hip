@@ -984,7 +984,7 @@ __device__ __forceinline__ void ph_refine_wave(const DevJob &J, int tile, uint8_
 __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uint8_t *lds)
 {
     constexpr int w = 5, L = 5, side = 2 * w + 1, strip = 2 * (L + w) + 1, nS = 2 * L + 1;
-    constexpr int nP = side * side, nT = nP + side * strip;
+    static_assert(side == 11 && strip == 21, "the row staging reads 11-byte patch and 21-byte strip rows");
     static_assert((side * 12 + side * 24) * 2 <= kRefineQLds, "refine windows");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ql = lane & 15, slot = wave * 4 + (lane >> 4);
@@ -1024,17 +1024,44 @@ __device__ __forceinline__ void ph_refine_quarter(const DevJob &J, int tile, uin
     uint16_t *P = reinterpret_cast<uint16_t *>(lds + slot * kRefineQLds);
     uint16_t *S = P + side * pS;
     if (act) {
+        // 22 row jobs per match (the patch's 11 rows, then the strip's), two
+        // per lane: each row read whole (unaligned dword loads covering exactly
+        // its 11 or 21 bytes) and widened to 16-bit pairs by byte permutes
         const uint8_t *IL = J.pyrL + off;
         const uint8_t *IR = J.pyrR + off;
-        _Pragma("unroll") for (int e0 = 0; e0 < nT; e0 += 16)
+        constexpr uint32_t kLo = 0x0C010C00u, kHi = 0x0C030C02u;   // bytes 0,1 / 2,3 -> u16 pair
+        _Pragma("unroll") for (int h = 0; h < 2; ++h)
         {
-            const int e = e0 + ql;
-            if (e < nP) {
-                const int r = e / side, c = e - r * side;
-                P[r * pS + c] = (uint16_t)(IL[(size_t)(sv - w + r) * Wl + su - w + c] + 255);
-            } else if (e < nT) {
-                const int e2 = e - nP, r = e2 / strip, c = e2 - r * strip;
-                S[r * sS + c] = IR[(size_t)(sv - w + r) * Wl + su0 - L - w + c];
+            const int jb = ql + 16 * h;
+            if (jb < side) {
+                const uint8_t *src = IL + (size_t)(sv - w + jb) * Wl + su - w;
+                uint32_t d0, d1;
+                uint16_t d2;
+                __builtin_memcpy(&d0, src, 4);
+                __builtin_memcpy(&d1, src + 4, 4);
+                __builtin_memcpy(&d2, src + 8, 2);
+                const uint32_t d3 = src[10];
+                uint32_t *row = reinterpret_cast<uint32_t *>(P + jb * pS);
+                constexpr uint32_t k255 = 0x00FF00FFu;
+                row[0] = __builtin_amdgcn_perm(0u, d0, kLo) + k255;
+                row[1] = __builtin_amdgcn_perm(0u, d0, kHi) + k255;
+                row[2] = __builtin_amdgcn_perm(0u, d1, kLo) + k255;
+                row[3] = __builtin_amdgcn_perm(0u, d1, kHi) + k255;
+                row[4] = __builtin_amdgcn_perm(0u, (uint32_t)d2, kLo) + k255;
+                row[5] = d3 + 255u;   // column 11 is padding
+            } else if (jb < 2 * side) {
+                const int r = jb - side;
+                const uint8_t *src = IR + (size_t)(sv - w + r) * Wl + su0 - L - w;
+                uint32_t d[5];
+                _Pragma("unroll") for (int k = 0; k < 5; ++k) __builtin_memcpy(&d[k], src + 4 * k, 4);
+                const uint32_t d5 = src[20];
+                uint32_t *row = reinterpret_cast<uint32_t *>(S + r * sS);
+                _Pragma("unroll") for (int k = 0; k < 5; ++k)
+                {
+                    row[2 * k] = __builtin_amdgcn_perm(0u, d[k], kLo);
+                    row[2 * k + 1] = __builtin_amdgcn_perm(0u, d[k], kHi);
+                }
+                row[10] = d5;
             }
         }
     }
