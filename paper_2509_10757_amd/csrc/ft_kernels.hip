@@ -511,35 +511,11 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
     for (int b = tid; b < kRotBinsMax; b += NT) V.hist[b] = 0;
     if (tid == 0) *V.n_matches = 0;
     __syncthreads();
-    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
-        float x[kSortUnroll], y[kSortUnroll];
-        int o[kSortUnroll];
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-        {
-            const int k = min(k0 + e * NT, K.n - 1);
-            x[e] = K.x[k];
-            y[e] = K.y[k];
-            o[e] = K.oct[k];
-        }
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-        {
-            if (k0 + e * NT < K.n) {
-                const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
-                const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
-                int p0, p1;
-                cell_bins(V, o[e], lv_lo, lv_hi, p0, p1);
-                for (int p = p0; p <= p1; ++p) atomicAdd(&cnt[p * cells + cy * V.cols + cx], 1);
-            }
-        }
-    }
-    __syncthreads();
-    const int total = wg_exclusive_scan<NT>(cnt, nb, tmp);
-    for (int c = tid; c < nb; c += NT) V.cell_off[c] = cnt[c];
-    if (tid == 0) V.cell_off[nb] = total;
-    __syncthreads();
-    for (int k0 = tid; k0 < K.n; k0 += kSortUnroll * NT) {
-        float x[kSortUnroll], y[kSortUnroll];
-        uint32_t meta[kSortUnroll];
+    // A chunk of kSortUnroll keypoints per thread: the cell, position and
+    // record meta of each (load), its counts (count) and its records (scatter).
+    // The first chunk stays in registers from the counting pass to the scatter,
+    // so a view of up to kSortUnroll * NT keypoints is read once.
+    auto load = [&](int k0, int *cell, float *x, float *y, uint32_t *meta) {
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int k = min(k0 + e * NT, K.n - 1);
@@ -550,9 +526,25 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
         }
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
+            const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
+            const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
+            cell[e] = cy * V.cols + cx;
+        }
+    };
+    auto count = [&](int k0, const int *cell, const uint32_t *meta) {
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
             if (k0 + e * NT < K.n) {
-                const int cx = cell_coord(x[e], V.min_x, V.inv_cw, V.cols);
-                const int cy = cell_coord(y[e], V.min_y, V.inv_ch, V.rows);
+                int p0, p1;
+                cell_bins(V, (int)(meta[e] & 0xFFu), lv_lo, lv_hi, p0, p1);
+                for (int p = p0; p <= p1; ++p) atomicAdd(&cnt[p * cells + cell[e]], 1);
+            }
+        }
+    };
+    auto scatter = [&](int k0, const int *cell, const float *x, const float *y, const uint32_t *meta) {
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            if (k0 + e * NT < K.n) {
                 CellRec rec;
                 rec.x = x[e];
                 rec.y = y[e];
@@ -560,9 +552,36 @@ __device__ __forceinline__ void ph_cellsort(const DevView &V, const DevKps &K, i
                 rec.pad = 0;
                 int p0, p1;
                 cell_bins(V, (int)(meta[e] & 0xFFu), lv_lo, lv_hi, p0, p1);
-                for (int p = p0; p <= p1; ++p) V.crec[atomicAdd(&cnt[p * cells + cy * V.cols + cx], 1)] = rec;
+                for (int p = p0; p <= p1; ++p) V.crec[atomicAdd(&cnt[p * cells + cell[e]], 1)] = rec;
             }
         }
+    };
+    int cell0[kSortUnroll];
+    float x0[kSortUnroll], y0[kSortUnroll];
+    uint32_t meta0[kSortUnroll];
+    if (tid < K.n) {
+        load(tid, cell0, x0, y0, meta0);
+        count(tid, cell0, meta0);
+    }
+    for (int k0 = tid + kSortUnroll * NT; k0 < K.n; k0 += kSortUnroll * NT) {
+        int cell[kSortUnroll];
+        float x[kSortUnroll], y[kSortUnroll];
+        uint32_t meta[kSortUnroll];
+        load(k0, cell, x, y, meta);
+        count(k0, cell, meta);
+    }
+    __syncthreads();
+    const int total = wg_exclusive_scan<NT>(cnt, nb, tmp);
+    for (int c = tid; c < nb; c += NT) V.cell_off[c] = cnt[c];
+    if (tid == 0) V.cell_off[nb] = total;
+    __syncthreads();
+    if (tid < K.n) scatter(tid, cell0, x0, y0, meta0);
+    for (int k0 = tid + kSortUnroll * NT; k0 < K.n; k0 += kSortUnroll * NT) {
+        int cell[kSortUnroll];
+        float x[kSortUnroll], y[kSortUnroll];
+        uint32_t meta[kSortUnroll];
+        load(k0, cell, x, y, meta);
+        scatter(k0, cell, x, y, meta);
     }
 }
 
