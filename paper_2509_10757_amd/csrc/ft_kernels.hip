@@ -392,17 +392,48 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
     for (int i = tid; i < J.L.n; i += NT) J.flag[i] = 0;   // the refinement flags matches only
     if (tid == 0) J.counts[2] = 0;                          // length of the match list
     __syncthreads();
-    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
-        float y[kSortUnroll];
-        int oc[kSortUnroll];
+    // A chunk of kSortUnroll right keypoints per thread; the first chunk stays
+    // in registers from the counting pass to the scatter.
+    auto load = [&](int j0, float *x, float *y, int *oc) {
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
         {
             const int j = min(j0 + e * NT, nR - 1);
+            x[e] = J.R.x[j];
             y[e] = J.R.y[j];
             oc[e] = J.R.oct[j];
         }
+    };
+    auto bin_of = [&](float y, int oc) { return (per_level ? lvl(oc) * rows : 0) + row_bin(y, rows); };
+    auto count = [&](int j0, const float *y, const int *oc) {
         _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-            if (j0 + e * NT < nR) atomicAdd(&cnt[(per_level ? lvl(oc[e]) * rows : 0) + row_bin(y[e], rows)], 1);
+            if (j0 + e * NT < nR) atomicAdd(&cnt[bin_of(y[e], oc[e])], 1);
+    };
+    auto scatter = [&](int j0, const float *x, const float *y, const int *oc) {
+        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
+        {
+            const int j = j0 + e * NT;
+            if (j < nR) {
+                const int pos = atomicAdd(&cnt[bin_of(y[e], oc[e])], 1);
+                RowRec rec;
+                rec.x = x[e];
+                rec.band = band_rows(J, y[e], oc[e]);
+                rec.meta = (uint32_t)oc[e] | ((uint32_t)j << 16);
+                rec.pad = 0;
+                J.rrec[pos] = rec;
+            }
+        }
+    };
+    float x0[kSortUnroll], y0[kSortUnroll];
+    int oc0[kSortUnroll];
+    if (tid < nR) {
+        load(tid, x0, y0, oc0);
+        count(tid, y0, oc0);
+    }
+    for (int j0 = tid + kSortUnroll * NT; j0 < nR; j0 += kSortUnroll * NT) {
+        float x[kSortUnroll], y[kSortUnroll];
+        int oc[kSortUnroll];
+        load(j0, x, y, oc);
+        count(j0, y, oc);
     }
     __syncthreads();
     const int total = wg_exclusive_scan<NT>(cnt, nb, tmp);
@@ -413,29 +444,12 @@ __device__ __forceinline__ void ph_rowsort(const DevJob &J, int *cnt, int *tmp)
         J.row_start[e] = bin < nb ? cnt[bin] : total;
     }
     __syncthreads();
-    for (int j0 = tid; j0 < nR; j0 += kSortUnroll * NT) {
+    if (tid < nR) scatter(tid, x0, y0, oc0);
+    for (int j0 = tid + kSortUnroll * NT; j0 < nR; j0 += kSortUnroll * NT) {
         float x[kSortUnroll], y[kSortUnroll];
-        int oct[kSortUnroll];
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-        {
-            const int j = min(j0 + e * NT, nR - 1);
-            x[e] = J.R.x[j];
-            y[e] = J.R.y[j];
-            oct[e] = J.R.oct[j];
-        }
-        _Pragma("unroll") for (int e = 0; e < kSortUnroll; ++e)
-        {
-            const int j = j0 + e * NT;
-            if (j < nR) {
-                const int pos = atomicAdd(&cnt[(per_level ? lvl(oct[e]) * rows : 0) + row_bin(y[e], rows)], 1);
-                RowRec rec;
-                rec.x = x[e];
-                rec.band = band_rows(J, y[e], oct[e]);
-                rec.meta = (uint32_t)oct[e] | ((uint32_t)j << 16);
-                rec.pad = 0;
-                J.rrec[pos] = rec;
-            }
-        }
+        int oc[kSortUnroll];
+        load(j0, x, y, oc);
+        scatter(j0, x, y, oc);
     }
 }
 
