@@ -583,7 +583,7 @@ void drain_set(ft_context *ctx, size_t k)
 {
     if (!ctx->ev_pending[k]) return;
     auto &ev = ctx->ev_sets[k];
-    hipEventSynchronize(ev[PH_COUNT]);
+    (void)hipEventSynchronize(ev[PH_COUNT]);   // a failure shows as a failed elapsed-time read below
     for (int p = 0; p < PH_COUNT; ++p) {
         if (!((ctx->ev_mask[k] >> p) & 1u)) continue;   // no kernel of this phase was launched
         float ms = 0.0f;
@@ -770,8 +770,8 @@ ft_status launch_batch(ft_context *ctx, Lane &lane, int32_t n, const Shapes &sh,
 
 void release_graph(BatchGraph &g)
 {
-    if (g.exec) hipGraphExecDestroy(g.exec);
-    if (g.graph) hipGraphDestroy(g.graph);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
     g = BatchGraph{};
 }
 
@@ -1053,29 +1053,31 @@ ft_status ft_context_read_timing(ft_context *ctx, double *ms, int64_t *launches)
 ft_status ft_context_destroy(ft_context *ctx)
 {
     if (!ctx) return FT_ERR_INVALID_ARGUMENT;
-    hipSetDevice(ctx->device);
+    // Best effort: every resource is released whatever an earlier call
+    // returned, so the individual results are not checked.
+    (void)hipSetDevice(ctx->device);
     for (auto &set : ctx->ev_sets)
         for (auto &e : set)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     for (auto &ln : ctx->lanes) {
         if (ln.done) {
-            hipEventSynchronize(ln.done);
-            hipEventDestroy(ln.done);
+            (void)hipEventSynchronize(ln.done);
+            (void)hipEventDestroy(ln.done);
         }
         release_graph(ln.g);
-        if (ln.h_table) hipHostFree(ln.h_table);
+        if (ln.h_table) (void)hipHostFree(ln.h_table);
     }
     for (int k = 0; k < ft_context::kOrbSlots; ++k)
         if (ctx->orb_ev[k]) {
-            hipEventSynchronize(ctx->orb_ev[k]);
-            hipEventDestroy(ctx->orb_ev[k]);
+            (void)hipEventSynchronize(ctx->orb_ev[k]);
+            (void)hipEventDestroy(ctx->orb_ev[k]);
         }
-    for (auto &c : ctx->edit_live) hipEventSynchronize(c.ev);
-    for (hipEvent_t e : ctx->edit_all_ev) hipEventDestroy(e);
-    if (ctx->edit_ring) hipHostFree(ctx->edit_ring);
-    if (ctx->base || !ctx->host_blocks.empty()) hipDeviceSynchronize();
-    for (auto &hb : ctx->host_blocks) hipHostFree(hb.first);
-    if (ctx->base) hipFree(ctx->base);
+    for (auto &c : ctx->edit_live) (void)hipEventSynchronize(c.ev);
+    for (hipEvent_t e : ctx->edit_all_ev) (void)hipEventDestroy(e);
+    if (ctx->edit_ring) (void)hipHostFree(ctx->edit_ring);
+    if (ctx->base || !ctx->host_blocks.empty()) (void)hipDeviceSynchronize();
+    for (auto &hb : ctx->host_blocks) (void)hipHostFree(hb.first);
+    if (ctx->base) (void)hipFree(ctx->base);
     delete ctx;
     return FT_OK;
 }
@@ -1098,7 +1100,7 @@ ft_status ft_host_free(ft_context *ctx, void *ptr)
     if (!ctx) return FT_ERR_INVALID_ARGUMENT;
     for (size_t i = 0; i < ctx->host_blocks.size(); ++i) {
         if (ctx->host_blocks[i].first != ptr) continue;
-        hipSetDevice(ctx->device);
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
         HIP_TRY(ctx, hipHostFree(ptr));
         ctx->host_blocks.erase(ctx->host_blocks.begin() + (ptrdiff_t)i);
         return FT_OK;
@@ -1536,7 +1538,7 @@ ft_status take_edit_chunk(ft_context *ctx, size_t need, size_t *off_out)
         live.pop_front();
         return e;
     };
-    while (!live.empty() && hipEventQuery(live.front().ev) == hipSuccess) pop_front(false);
+    while (!live.empty() && hipEventQuery(live.front().ev) == hipSuccess) (void)pop_front(false);
     size_t off = ctx->edit_head + need <= ctx->edit_ring_bytes ? ctx->edit_head : 0;
     auto overlaps = [&]() {
         for (const auto &c : live)
