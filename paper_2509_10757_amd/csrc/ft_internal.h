@@ -22,7 +22,7 @@ constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
 constexpr int kRefineQPerWG = 16;     // ... 11x11 window, +-5 shifts: four matches per wave
 constexpr int kRefineQLds = 800;      // bytes of LDS per match (11 x 12 + 11 x 24 16-bit values)
-constexpr int kPyrRows = 8;           // image pyramid: level-0 rows per workgroup
+constexpr int kPyrRows = 16;          // image pyramid: level-0 rows per workgroup
 constexpr int kMaxPyrW = 1536;        // widest level-0 image the pyramid build stages in LDS
 constexpr int kRotBinsMax = 64;       // rotation histogram bins of the last-frame search
 

@@ -246,18 +246,17 @@ constexpr int kPyrRowTaps = kPyrRows + 2;                   // output rows of on
 constexpr int kPyrMeta = kPyrStage;                         // int [kLevels][2]: first row, count
 constexpr int kPyrRowTab = kPyrMeta + 2 * kLevels * 4;      // uint32 [kLevels][kPyrRowTaps]
 constexpr int kPyrLds = kPyrRowTab + kLevels * kPyrRowTaps * 4;
+static_assert((kLevels - 1) * kPyrRowTaps <= kWG, "one thread per row tap of levels 1..7");
 
-// Output rows of level l whose top tap row lies in [Y0, Y1): the level's row
-// tap is monotone in the row, so the range is found by bisection.
+// First output row y of a level h rows tall whose top tap row is at least Y
+// (0 <= Y < H): the tap is floor(((2y + 1) H - h) / (2h)), and its clamp to
+// H - 1 never takes it below Y, so y is the smallest with
+// (2y + 1) H - h >= 2hY: ceil((2hY + h - H) / (2H)), and at least 0.
 __device__ __forceinline__ int pyr_first_row(int Y, int H, int h)
 {
-    int lo = 0, hi = h;   // first y with tap(y) >= Y
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)(pyr_tap(mid, H, h) & 0xFFFFu) >= Y) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
+    const int num = 2 * h * Y + h - H;
+    if (num <= 0) return 0;
+    return (num + 2 * H - 1) / (2 * H);
 }
 
 // One tile: image `side` (0 left, 1 right) of the frame, level-0 rows
@@ -283,48 +282,65 @@ __device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned c
     int *meta = reinterpret_cast<int *>(smem + kPyrMeta);          // first row | row count per level
     uint32_t *rtab = reinterpret_cast<uint32_t *>(smem + kPyrRowTab);
     const int tid = threadIdx.x;
-    if (tid >= 1 && tid < kLevels) {
-        const int l = tid, hl = J.lv_h[l];
+    // one thread per (level, row) tap of the tile
+    if (tid < (kLevels - 1) * kPyrRowTaps) {
+        const int l = 1 + tid / kPyrRowTaps, r = tid - (l - 1) * kPyrRowTaps;
+        const int hl = J.lv_h[l];
         const int ylo = pyr_first_row(Y0, H, hl);
         const int yhi = Y1 >= H ? hl : pyr_first_row(Y1, H, hl);
         const int n = min(yhi - ylo, kPyrRowTaps);   // at most ceil(kPyrRows * hl / H) + 1 rows
-        meta[2 * l] = ylo;
-        meta[2 * l + 1] = n;
-        for (int r = 0; r < n; ++r) rtab[l * kPyrRowTaps + r] = pyr_tap(ylo + r, H, hl);
+        if (r == 0) {
+            meta[2 * l] = ylo;
+            meta[2 * l + 1] = n;
+        }
+        if (r < n) rtab[l * kPyrRowTaps + r] = pyr_tap(ylo + r, H, hl);
     }
-    // stage the level-0 rows: 4-byte loads when rows and base are aligned
+    // Stage the level-0 rows (4-byte loads when rows and base are aligned).
+    // Element e of a row-major walk is row e / w, column e % w: one division
+    // for the thread's first element, then steps of kWG elements.
+    auto walk = [&](int w, int &r, int &c, int &dr, int &dc) {
+        r = tid / w;
+        c = tid - r * w;
+        dr = kWG / w;
+        dc = kWG - dr * w;
+    };
+    auto step = [&](int w, int &r, int &c, int dr, int dc) {
+        r += dr;
+        c += dc;
+        if (c >= w) {
+            c -= w;
+            ++r;
+        }
+    };
     const bool al4 = ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)pitch | (uintptr_t)W) & 3u) == 0;
     if (al4) {
-        const int wq = W >> 2, n = (ys - Y0) * wq;
-        for (int e = tid; e < n; e += kWG) {
-            const int r = e / wq, c = e - r * wq;
+        const int wq = W >> 2;
+        int r, c, dr, dc;
+        walk(wq, r, c, dr, dc);
+        for (; r < ys - Y0; step(wq, r, c, dr, dc)) {
             const uint32_t v = *reinterpret_cast<const FT_G uint32_t *>(src + (size_t)(Y0 + r) * pitch + 4 * c);
             *reinterpret_cast<uint32_t *>(stage + r * stride + 4 * c) = v;
         }
     } else {
-        const int n = (ys - Y0) * W;
-        for (int e = tid; e < n; e += kWG) {
-            const int r = e / W, c = e - r * W;
-            stage[r * stride + c] = src[(size_t)(Y0 + r) * pitch + c];
-        }
+        int r, c, dr, dc;
+        walk(W, r, c, dr, dc);
+        for (; r < ys - Y0; step(W, r, c, dr, dc)) stage[r * stride + c] = src[(size_t)(Y0 + r) * pitch + c];
     }
     __syncthreads();
     // level 0: the staged rows [Y0, Y1)
     {
-        const int n = (Y1 - Y0) * W;
         FT_G uint8_t *d0 = dst + (size_t)Y0 * W;
         if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
             const int wq = W >> 2;
-            for (int e = tid; e < (n >> 2); e += kWG) {
-                const int r = e / wq, c = e - r * wq;
-                *reinterpret_cast<FT_G uint32_t *>(d0 + 4 * e) =
+            int r, c, dr, dc;
+            walk(wq, r, c, dr, dc);
+            for (; r < Y1 - Y0; step(wq, r, c, dr, dc))
+                *reinterpret_cast<FT_G uint32_t *>(d0 + (size_t)r * W + 4 * c) =
                     *reinterpret_cast<const uint32_t *>(stage + r * stride + 4 * c);
-            }
         } else {
-            for (int e = tid; e < n; e += kWG) {
-                const int r = e / W, c = e - r * W;
-                d0[e] = stage[r * stride + c];
-            }
+            int r, c, dr, dc;
+            walk(W, r, c, dr, dc);
+            for (; r < Y1 - Y0; step(W, r, c, dr, dc)) d0[(size_t)r * W + c] = stage[r * stride + c];
         }
     }
     // levels 1..7: columns of the levels laid end to end, dealt over the threads
@@ -341,19 +357,22 @@ __device__ __forceinline__ void ph_pyramid(const DevJob &J, int tile, unsigned c
         const int x = e - wsum[l];
         const int wl = J.lv_w[l];
         const uint32_t c = pyr_tap(x, W, wl);
+        // column x0 + 1 is read even where the tap is clamped to the last
+        // column: its weight a is 0 there, and the byte read lies in LDS
         const int x0 = (int)(c & 0xFFFFu), a = (int)(c >> 16);
-        const int x1 = min(x0 + 1, W - 1);
         const int ylo = meta[2 * l], n = meta[2 * l + 1];
         FT_G uint8_t *dcol = dst + J.lv_off[l] + (size_t)ylo * wl + x;
         const uint32_t *rt = rtab + l * kPyrRowTaps;
         for (int r = 0; r < n; ++r) {
             const uint32_t t = rt[r];
             const int y0 = (int)(t & 0xFFFFu), b = (int)(t >> 16);
-            const uint8_t *r0 = stage + (y0 - Y0) * stride;
-            const uint8_t *r1 = stage + (min(y0 + 1, H - 1) - Y0) * stride;
-            const int top = (256 - a) * r0[x0] + a * r0[x1];
-            const int bot = (256 - a) * r1[x0] + a * r1[x1];
-            const int v = (256 - b) * top + b * bot;
+            const uint8_t *r0 = stage + (y0 - Y0) * stride + x0;
+            const uint8_t *r1 = stage + (min(y0 + 1, H - 1) - Y0) * stride + x0;
+            // (256 - w) p + w q = 256 p + w (q - p), exactly
+            const int p00 = r0[0], p10 = r1[0];
+            const int top = (p00 << 8) + a * ((int)r0[1] - p00);
+            const int bot = (p10 << 8) + a * ((int)r1[1] - p10);
+            const int v = (top << 8) + b * (bot - top);
             dcol[(size_t)r * wl] = (uint8_t)((v + 32768) >> 16);
         }
     }
