@@ -316,10 +316,12 @@ __device__ __forceinline__ int round_ratio_exact(int num, int64_t m2)
     return num < 0 ? -k : k;
 }
 
-// The same integer from a binary32 estimate |num| * (1 / sqrt(m2)): turned
-// pattern coordinates are at most 13, where the estimate is within 4e-6 of the
-// exact quotient, so unless it lies within 1e-4 of a half its rounding is the
-// exact one; `near` is set otherwise (the caller then decides exactly).
+// The same integer from a binary32 estimate |num| * rsqrt(m10^2 + m01^2),
+// the squares summed in binary32: every step is within a few units in the
+// last place, and turned pattern coordinates are at most 13, so the estimate
+// is within 1e-5 of the exact quotient and, unless it lies within 1e-4 of a
+// half, rounds to the exact integer; `near` is set otherwise (the caller then
+// decides exactly).
 __device__ __forceinline__ int turn_fast(int num, float inv_r, bool &near)
 {
     const int a = num < 0 ? -num : num;
@@ -328,6 +330,20 @@ __device__ __forceinline__ int turn_fast(int num, float inv_r, bool &near)
     near |= !(fabsf(fr - 0.5f) > 1e-4f);
     const int k = (int)(q + 0.5f);
     return num < 0 ? -k : k;
+}
+
+// Sum over the 64 lanes of a wave (every lane active) by DPP moves: shifts
+// by 1, 2, 4 and 8 inside rows of 16 lanes, then lane 15 of rows 0 and 2 into
+// rows 1 and 3, then lane 31 into rows 2 and 3; lane 63 holds the total.
+__device__ __forceinline__ int wave_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ float angle_deg(int m10, int m01)
@@ -394,14 +410,11 @@ __global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
                 sx += w;
                 m01 += dy * w;
             }
-            m10 = dx * sx;
-            _Pragma("unroll") for (int o = 32; o > 0; o >>= 1)
-            {
-                m10 += __shfl_xor(m10, o);
-                m01 += __shfl_xor(m01, o);
-            }
-            const int64_t m2 = (int64_t)m10 * m10 + (int64_t)m01 * m01;
-            const float inv_r = m2 > 0 ? rsqrtf((float)m2) : 0.0f;
+            m10 = wave_sum(dx * sx);
+            m01 = wave_sum(m01);
+            const bool turned = (m10 | m01) != 0;   // the squared radius m10^2 + m01^2 is positive
+            const float f10 = (float)m10, f01 = (float)m01;   // exact: |m| < 2^24
+            const float inv_r = turned ? rsqrtf(f10 * f10 + f01 * f01) : 0.0f;
             // per test: the two turned points (binary32 estimates, the exact
             // decision when one lies near a half), then their smoothed pixels
             uint64_t mask[4];
@@ -410,13 +423,14 @@ __global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
                 const int n0 = tx1[q] * m10 - ty1[q] * m01, n1 = tx1[q] * m01 + ty1[q] * m10;
                 const int n2 = tx2[q] * m10 - ty2[q] * m01, n3 = tx2[q] * m01 + ty2[q] * m10;
                 int c1 = tx1[q], r1 = ty1[q], c2 = tx2[q], r2 = ty2[q];
-                if (m2 > 0) {
+                if (turned) {
                     bool near = false;
                     c1 = turn_fast(n0, inv_r, near);
                     r1 = turn_fast(n1, inv_r, near);
                     c2 = turn_fast(n2, inv_r, near);
                     r2 = turn_fast(n3, inv_r, near);
                     if (near) {
+                        const int64_t m2 = (int64_t)m10 * m10 + (int64_t)m01 * m01;
                         c1 = round_ratio_exact(n0, m2);
                         r1 = round_ratio_exact(n1, m2);
                         c2 = round_ratio_exact(n2, m2);
