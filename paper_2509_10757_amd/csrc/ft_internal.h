@@ -18,6 +18,7 @@ constexpr int kMaxKp = 65535;
 constexpr int kMaxCellRep = 3;       // copies of a keypoint in a level-binned cell index (level window <= 3 octaves)
 constexpr int kMaxMap = (1 << 23) - 1;
 constexpr int kKnnQueriesPerWG = 32;  // fisheye all-pairs: queries per 256-thread subgroup (16-row MFMA blocks)
+constexpr int kKnnTilesInFlight = 8;  // fisheye all-pairs: target tiles whose descriptor loads a wave keeps in flight
 constexpr int kRefinePerWG = 4;       // pinhole refinement: one wave per match
 constexpr int kRefineLds = 1024;      // bytes of LDS per refining wave (patch + strip)
 constexpr int kRefineQPerWG = 16;     // ... 11x11 window, +-5 shifts: four matches per wave

@@ -664,6 +664,16 @@ __device__ __forceinline__ MatchRec match_rec(int i, uint32_t best, float bx, fl
     return r;
 }
 
+// Records [s, s + n) of level bin lb whose integer rows lie within that bin's
+// reach of row.
+__device__ __forceinline__ void bin_range(const DevJob &J, int lb, int row, int &s, int &n)
+{
+    const int reach = pick_level(J.lv_reach, lb);
+    const FT_G int32_t *rs = J.row_start + lb * (J.rows + 1);
+    s = rs[max(row - reach, 0)];
+    n = rs[min(row + reach, J.rows - 1) + 1] - s;
+}
+
 template <int G>
 __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
 {
@@ -684,39 +694,73 @@ __device__ __forceinline__ void ph_best(const DevJob &J, int tile)
             const Desc di = load_desc(J.L.desc, i);
             int lb0, lb1;
             level_bins(J, oi, lb0, lb1);
-            for (int lb = lb0; lb <= lb1; ++lb) {
-            const int reach = pick_level(J.lv_reach, lb);
-            const FT_G int32_t *rs = J.row_start + lb * (J.rows + 1);
-            const int b0 = max(row - reach, 0);
-            const int b1 = min(row + reach, J.rows - 1);
-            const int p1 = rs[b1 + 1];
-            // kBestUnroll records per step are loaded together (indices
-            // clamped into the range, surplus entries masked); then the
-            // descriptors of the candidates among them.
-            for (int p0 = rs[b0] + sub; p0 < p1; p0 += kBestUnroll * G) {
-                RowRec rec[kBestUnroll];
-                bool cand[kBestUnroll];
-                Desc d[kBestUnroll];
-                _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) rec[u] = J.rrec[min(p0 + u * G, p1 - 1)];
-                _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
-                {
-                    const int lo = (int)(rec[u].band & 0xFFFFu), hi = (int)(rec[u].band >> 16);
-                    const int oj = (int)(rec[u].meta & 0xFFu);
-                    cand[u] = p0 + u * G < p1 && row >= lo && row <= hi && oj >= oi - J.level_window &&
-                              oj <= oi + J.level_window && rec[u].x >= minU && rec[u].x <= maxU;
-                    if (cand[u]) d[u] = load_desc(J.R.desc, (int)(rec[u].meta >> 16));
+            auto test = [&](const RowRec &rec) {
+                const int lo = (int)(rec.band & 0xFFFFu), hi = (int)(rec.band >> 16);
+                const int oj = (int)(rec.meta & 0xFFu);
+                return row >= lo && row <= hi && oj >= oi - J.level_window && oj <= oi + J.level_window &&
+                       rec.x >= minU && rec.x <= maxU;
+            };
+            auto push = [&](const RowRec &rec, const Desc &d) {
+                const uint32_t key = ((uint32_t)hamming(di, d) << 16) | (rec.meta >> 16);
+                if (key < best) {
+                    best = key;
+                    bx = rec.x;
                 }
-                _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
-                {
-                    if (cand[u]) {
-                        const uint32_t key = ((uint32_t)hamming(di, d[u]) << 16) | (rec[u].meta >> 16);
-                        if (key < best) {
-                            best = key;
-                            bx = rec[u].x;
+            };
+            if (lb1 - lb0 < 3) {
+                // Up to three bins: their ranges are read together, positions
+                // 0 .. total - 1 run over them in order, lane `sub` taking every
+                // G-th, kBestUnroll per step; a step's descriptors load together
+                // with the next step's records.  (The minimum over distinct
+                // keys does not depend on the order.)
+                int s0, n0, s1 = 0, n1 = 0, s2 = 0, n2 = 0;
+                bin_range(J, lb0, row, s0, n0);
+                if (lb0 + 1 <= lb1) bin_range(J, lb0 + 1, row, s1, n1);
+                if (lb0 + 2 <= lb1) bin_range(J, lb0 + 2, row, s2, n2);
+                const int n01 = n0 + n1, total = n01 + n2;
+                auto at = [&](int p) {
+                    p = min(p, total - 1);   // past the end: a record loaded and never used
+                    return J.rrec[p < n0 ? s0 + p : p < n01 ? s1 + (p - n0) : s2 + (p - n01)];
+                };
+                RowRec rec[kBestUnroll];
+                if (total > 0) {
+                    _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) rec[u] = at(sub + u * G);
+                }
+                for (int p0 = sub; p0 < total; p0 += kBestUnroll * G) {
+                    bool cand[kBestUnroll];
+                    Desc d[kBestUnroll];
+                    _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
+                    {
+                        cand[u] = p0 + u * G < total && test(rec[u]);
+                        if (cand[u]) d[u] = load_desc(J.R.desc, (int)(rec[u].meta >> 16));
+                    }
+                    RowRec nx[kBestUnroll];
+                    _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) nx[u] = at(p0 + (kBestUnroll + u) * G);
+                    _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) if (cand[u]) push(rec[u], d[u]);
+                    _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) rec[u] = nx[u];
+                }
+            } else {
+                // any number of bins, one after another
+                for (int lb = lb0; lb <= lb1; ++lb) {
+                    int s, n;
+                    bin_range(J, lb, row, s, n);
+                    const int p1 = s + n;
+                    // kBestUnroll records per step are loaded together (indices
+                    // clamped into the range, surplus entries masked); then the
+                    // descriptors of the candidates among them.
+                    for (int p0 = s + sub; p0 < p1; p0 += kBestUnroll * G) {
+                        RowRec rec[kBestUnroll];
+                        bool cand[kBestUnroll];
+                        Desc d[kBestUnroll];
+                        _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) rec[u] = J.rrec[min(p0 + u * G, p1 - 1)];
+                        _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u)
+                        {
+                            cand[u] = p0 + u * G < p1 && test(rec[u]);
+                            if (cand[u]) d[u] = load_desc(J.R.desc, (int)(rec[u].meta >> 16));
                         }
+                        _Pragma("unroll") for (int u = 0; u < kBestUnroll; ++u) if (cand[u]) push(rec[u], d[u]);
                     }
                 }
-            }
             }
         }
     }
@@ -864,21 +908,31 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
     uint32_t ta[QB][4], tb[QB][4];
     _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
         _Pragma("unroll") for (int r = 0; r < 4; ++r) ta[qb][r] = tb[qb][r] = 0xFFFFFFFFu;
-    const int n_tiles = (nT + 15) >> 4;
-    // the next tile's descriptor bytes are loaded while this tile is processed
-    uint2 wn = make_uint2(0, 0);
-    if (wave < n_tiles && (wave << 4) + c < nT)
-        wn = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)((wave << 4) + c) + 8 * g);
-    for (int t = wave; t < n_tiles; t += 4) {
+    // (wave-uniform, so that the loop below branches on scalars)
+    const int n_tiles = __builtin_amdgcn_readfirstlane((nT + 15) >> 4);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // A ring of kKnnTilesInFlight target tiles' descriptor bytes per wave: the
+    // loop is unrolled over the ring, and a slot is reloaded with the tile
+    // kKnnTilesInFlight steps ahead as soon as its bytes are expanded, so that
+    // several loads are in flight while the matrix cores work.
+    constexpr int D = kKnnTilesInFlight;
+    const uint8_t *tdesc = J.tdesc + 8 * g;
+    uint2 ring[D];
+    _Pragma("unroll") for (int d = 0; d < D; ++d)
+    {
+        const int tj = min(((wv + 4 * d) << 4) + c, nT - 1);
+        ring[d] = *reinterpret_cast<const uint2 *>(tdesc + 32 * (size_t)tj);
+    }
+    // one tile: expand its bytes from ring slot d (then refill the slot with
+    // the tile D steps ahead), run the MFMAs, push the column's keys
+    auto step = [&](uint2 &slot, int t, bool refill) {
         const int tj = (t << 4) + c;
         const bool tv = tj < nT;
-        const uint2 w = wn;
-        const int tn = ((t + 4) << 4) + c;
-        if (t + 4 < n_tiles && tn < nT) wn = *reinterpret_cast<const uint2 *>(J.tdesc + 32 * (size_t)tn + 8 * g);
-        // (a target past the end has zero bytes loaded; its column's sums are
+        // (a column past the end holds the last target's bytes: its sums are
         // computed and never pushed)
         v4i B[4];
-        _Pragma("unroll") for (int s = 0; s < 4; ++s) B[s] = expand16(tab, s < 2 ? w.x : w.y, s & 1);
+        _Pragma("unroll") for (int s = 0; s < 4; ++s) B[s] = expand16(tab, s < 2 ? slot.x : slot.y, s & 1);
+        if (refill) slot = *reinterpret_cast<const uint2 *>(tdesc + 32 * (size_t)min(tj + 64 * D, nT - 1));
         // acc[r] = -dot(query row 4g + r of block qb, target column c); the key
         // (256 - dot) << 15 | index = Hamming << 16 | index (dot = 256 - 2 H) is
         // kbase + (acc << 15), one shift-add.  The blocks' MFMA chains are
@@ -894,7 +948,14 @@ __device__ __forceinline__ void ph_knn(const DevJob &J, int tile, uint64_t *tab,
                 _Pragma("unroll") for (int r = 0; r < 4; ++r)
                     top2_push(ta[qb][r], tb[qb][r], kbase + ((uint32_t)acc[qb][r] << 15));
         }
-    }
+    };
+    // whole turns of the ring (no exit inside, so the loads' waits stay
+    // counted), then the last tiles with no refill
+    int t0 = wv;
+    for (; t0 + 4 * (D - 1) < n_tiles; t0 += 4 * D)
+        _Pragma("unroll") for (int d = 0; d < D; ++d) step(ring[d], t0 + 4 * d, true);
+    _Pragma("unroll") for (int d = 0; d < D - 1; ++d)
+        if (t0 + 4 * d < n_tiles) step(ring[d], t0 + 4 * d, false);
     _Pragma("unroll") for (int qb = 0; qb < QB; ++qb)
     {
         _Pragma("unroll") for (int r = 0; r < 4; ++r)
