@@ -91,3 +91,47 @@ def test_striped_deal_names_every_record_once():
         want_rec = [a[l, e] + i for l in range(64) for e in range(4) for i in range(n[l, e])]
         assert seg_of.tolist() == want_seg
         assert rec_of.tolist() == want_rec
+
+
+def _bins_walk(ranges, G=4, U=2):
+    """The pinhole scan's positions over (start, count) ranges of up to three
+    level bins: lane `sub` of G reads positions sub + G u + U G k, clamped to
+    total - 1; returns the records the in-range positions name and every
+    record a clamped read touches."""
+    (s0, n0), (s1, n1), (s2, n2) = (list(ranges) + [(0, 0)] * 3)[:3]
+    n01, total = n0 + n1, n0 + n1 + n2
+
+    def at(p):
+        p = min(p, total - 1)
+        return s0 + p if p < n0 else s1 + (p - n0) if p < n01 else s2 + (p - n01)
+
+    named, touched = {}, set()
+    for sub in range(G):
+        if total == 0:
+            continue
+        for u in range(U):
+            touched.add(at(sub + u * G))
+        p0 = sub
+        while p0 < total:
+            for u in range(U):
+                p = p0 + u * G
+                if p < total:
+                    named[p] = at(p)
+                touched.add(at(p0 + (U + u) * G))
+            p0 += U * G
+    return [named[p] for p in sorted(named)], touched
+
+
+def test_bins_walk_names_every_record_once_in_order():
+    rng = np.random.default_rng(5)
+    for trial in range(400):
+        k = 1 + trial % 3
+        counts = rng.integers(0, 40, k)
+        if trial % 7 == 0:
+            counts[rng.integers(0, k)] = 0
+        starts = np.cumsum(rng.integers(0, 500, k)) + np.concatenate([[0], np.cumsum(counts)[:-1]])
+        ranges = [(int(a), int(n)) for a, n in zip(starts, counts)]
+        want = [a + i for a, n in ranges for i in range(n)]
+        got, touched = _bins_walk(ranges, G=int(rng.choice([1, 2, 4, 8, 16])))
+        assert got == want, (ranges, got[:10])
+        assert touched <= set(want), (ranges, sorted(touched - set(want))[:5])
