@@ -353,7 +353,9 @@ __device__ __forceinline__ float angle_deg(int m10, int m01)
     return (float)ang;
 }
 
-__global__ __launch_bounds__(kThreads) void k_orb_describe(OrbDescribeArgs a)
+// Four waves per SIMD (at most 128 registers): a few values spill, but the
+// extra waves hide more of the pixel gathers than the spills cost.
+__global__ __launch_bounds__(kThreads, 4) void k_orb_describe(OrbDescribeArgs a)
 {
     const int lane = threadIdx.x & 63;
     const int wave = (int)((blockIdx.x * kThreads + threadIdx.x) >> 6);
