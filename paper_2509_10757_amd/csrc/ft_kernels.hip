@@ -2330,7 +2330,10 @@ __global__ __launch_bounds__(kWG) void k_stereo_a(Src src)
 }
 
 template <class Src>
-__global__ __launch_bounds__(kWG) void k_refine(Src src)
+// 7 waves per SIMD (at most 72 registers) instead of the 6 its 73 registers
+// would give: more window loads in flight.  The batch kernel fits without a
+// spill; the single-frame one spills two values.
+__global__ __launch_bounds__(kWG, 7) void k_refine(Src src)
 {
     __shared__ __align__(16) unsigned char smem[kRefineQPerWG * kRefineQLds > kRefinePerWG * kRefineLds
                                                     ? kRefineQPerWG * kRefineQLds
